@@ -1,0 +1,381 @@
+"""FP64 CPU oracle of the Contact-Field pipeline -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product path (the HIP library in
+``paper_2511_07418_amd``) never does, and the two share no code: the oracle
+is ``oracle.c`` (plain C11, double precision, OpenMP over independent work)
+plus thin ctypes marshalling here.
+
+Each function cites the passage of the paper it follows (arXiv 2511.07418):
+
+* ``philox``           Philox4x32-10 counter RNG (Salmon et al., SC'11)
+* ``joint_sample``     random joint configurations of Sec. 4.3
+* ``fk``               forward kinematics F of Sec. 3.1
+* ``build_field``      Sec. 4.3 Alg. 1 (grid cover + normals per box) with
+                       per-link (patch) tables of Sec. 4.4 and quantised normals
+* ``query``            object contact query of Sec. 4.3 and the merged
+                       per-dependency-group domains of Sec. 5.3
+* ``draw``             Sec. 5.3 random selection + reverse lookup of Sec. 5.5
+* ``verdicts``/``set_tstar``  Eq. 1-2 with a linearised friction cone (LP)
+* ``compact``          accepted sets in pose-major, draw-minor order
+* ``realize``          Sec. 5.5 Eq. 7-8 (DLS IK with Phase-II projection) and
+                       the penetration criterion of Sec. 3.2
+
+Readings where the paper is silent are listed in the design doc.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+BAND = 1e-6
+
+
+def build(force: bool = True) -> str:
+    """Compile ``liboracle.so`` with gcc (plain IEEE double, no contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-Wall", "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Hand(C.Structure):
+    _fields_ = [("n_fingers", C.c_int32), ("n_joints", C.c_int32),
+                ("joint_finger", C.c_void_p), ("joint_parent", C.c_void_p),
+                ("joint_origin", C.c_void_p), ("joint_axis", C.c_void_p),
+                ("capsule", C.c_void_p), ("limits", C.c_void_p),
+                ("n_surf", C.c_int32), ("surf", C.c_void_p)]
+
+
+class _FieldParams(C.Structure):
+    _fields_ = [("samples", C.c_int64), ("seed", C.c_uint64), ("grid", C.c_int32),
+                ("h", C.c_double), ("bins", C.c_int32), ("grid_frame", C.c_void_p)]
+
+
+class _IK(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("phase1", C.c_int32), ("lam", C.c_double), ("beta", C.c_double),
+                ("tol_pos", C.c_double), ("tol_ang", C.c_double), ("margin", C.c_double)]
+
+
+class _SDF(C.Structure):
+    _fields_ = [("origin", C.c_double * 3), ("h", C.c_double), ("dims", C.c_int32),
+                ("values", C.c_void_p)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        vp, i32, i64, u64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+        L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+        L.orc_joint_sample.argtypes = [vp, u64, C.c_int, i64, vp]
+        L.orc_fk.argtypes = [vp, vp, vp]
+        L.orc_fk_finger.argtypes = [vp, C.c_int, vp, vp]
+        L.orc_bin_centers.argtypes = [C.c_int, vp]
+        L.orc_bin.argtypes = [C.c_int, vp, vp, vp]
+        L.orc_bin.restype = C.c_int
+        L.orc_build_field.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_build_field.restype = C.c_int
+        L.orc_query.argtypes = [vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp]
+        L.orc_query.restype = C.c_int
+        L.orc_draw.argtypes = [vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, i32, i32, u64,
+                               C.c_uint32, i64, vp, vp]
+        L.orc_draw.restype = C.c_int
+        L.orc_tangent_basis.argtypes = [vp, vp, vp]
+        L.orc_wrench_matrix.argtypes = [C.c_int, vp, vp, dbl, C.c_int, dbl, vp]
+        L.orc_lp_solve.argtypes = [C.c_int, vp, C.c_int, vp, vp]
+        L.orc_lp_solve.restype = dbl
+        L.orc_set_tstar.argtypes = [C.c_int, vp, vp, dbl, C.c_int, dbl, C.c_int, vp, vp]
+        L.orc_set_tstar.restype = dbl
+        L.orc_verdicts.argtypes = [vp, vp, i32, i32, vp, dbl, i32, dbl, dbl, i32, vp, vp, vp, vp]
+        L.orc_verdicts.restype = C.c_int
+        L.orc_ik_finger.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_point_jacobian.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp]
+        L.orc_sdf_eval.argtypes = [vp, vp]
+        L.orc_sdf_eval.restype = dbl
+        L.orc_axis_samples.argtypes = [vp, C.c_int]
+        L.orc_axis_samples.restype = C.c_int
+        L.orc_penetration.argtypes = [vp, vp, vp, vp]
+        L.orc_penetration.restype = dbl
+        L.orc_realize.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, i32, vp,
+                                  vp, vp, vp, vp, vp, vp, vp]
+        L.orc_realize.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+class _Keep:
+    """Holds ctypes structures together with the arrays they point to."""
+
+    def __init__(self, struct, arrays):
+        self.struct, self.arrays = struct, arrays
+
+    @property
+    def ref(self):
+        return C.byref(self.struct)
+
+
+def _hand(h) -> _Keep:
+    arrs = [_c(h.joint_finger, np.int32), _c(h.joint_parent, np.int32),
+            _c(h.joint_origin, np.float32), _c(h.joint_axis, np.float32),
+            _c(h.capsule, np.float32), _c(h.limits, np.float32), _c(h.surf, np.float32)]
+    s = _Hand(h.n_fingers, h.n_joints, _p(arrs[0]), _p(arrs[1]), _p(arrs[2]), _p(arrs[3]),
+              _p(arrs[4]), _p(arrs[5]), int(h.surf.shape[1]), _p(arrs[6]))
+    return _Keep(s, arrs)
+
+
+def _field(fp) -> _Keep:
+    gf = _c(fp.grid_frame, np.float32)
+    s = _FieldParams(int(fp.samples), int(fp.seed) & 0xFFFFFFFFFFFFFFFF, int(fp.grid),
+                     float(np.float32(fp.h)), int(fp.bins), _p(gf))
+    return _Keep(s, [gf])
+
+
+def _sdf(sdf) -> _Keep:
+    v = _c(sdf.values, np.float32)
+    s = _SDF((C.c_double * 3)(*[float(x) for x in np.asarray(sdf.origin, np.float32)]),
+             float(np.float32(sdf.h)), int(sdf.dims), _p(v))
+    return _Keep(s, [v])
+
+
+def _ik(ik) -> _IK:
+    return _IK(int(ik.iters), int(ik.phase1), float(ik.lam), float(ik.beta), float(ik.tol_pos),
+               float(ik.tol_ang), float(ik.margin))
+
+
+# ---------------------------------------------------------------------------
+def philox(ctr, key) -> np.ndarray:
+    """Philox4x32-10 block for counter ``ctr`` (4 x uint32) and ``key`` (2 x uint32)."""
+    c, k = _c(ctr, np.uint32), _c(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def joint_sample(hand, seed: int, f: int, s: int) -> np.ndarray:
+    """Joint values of finger ``f`` for joint sample ``s`` (Sec. 4.3)."""
+    H = _hand(hand)
+    q = np.zeros(hand.dof[f], np.float64)
+    lib().orc_joint_sample(H.ref, int(seed) & 0xFFFFFFFFFFFFFFFF, f, int(s), _p(q))
+    return q
+
+
+def fk(hand, q) -> np.ndarray:
+    """Link frames [J,12] (3x4 [R|t], hand frame) for joint vector ``q`` [J]."""
+    H = _hand(hand)
+    qq = _c(q, np.float64)
+    T = np.zeros((hand.n_joints, 12), np.float64)
+    lib().orc_fk(H.ref, _p(qq), _p(T))
+    return T
+
+
+def bin_centers(B: int) -> np.ndarray:
+    c = np.zeros((B, 3), np.float64)
+    lib().orc_bin_centers(B, _p(c))
+    return c
+
+
+def bin_of(B: int, d) -> tuple[int, int, float]:
+    """(best bin, second bin, (theta2 - theta1)/2) of direction ``d``."""
+    dd = _c(d, np.float64)
+    b2 = C.c_int(0)
+    gap = C.c_double(0)
+    b = lib().orc_bin(B, _p(dd), C.byref(b2), C.byref(gap))
+    return b, b2.value, gap.value
+
+
+def build_field(hand, fp, witness: bool = False, flags: bool = True) -> dict:
+    """Per-link voxel x normal-bin bit tables (Alg. 1 as a dense grid cover).
+
+    Returns ``bits``/``sure``/``maybe`` uint32 [L, G^3, B/32] and, with
+    ``witness``, int32 [L, G^3, B] ``wit``/``wit_lo``/``wit_hi`` (-1 = none),
+    plus ``stats`` = (vectors, in-window, dropped, flagged)."""
+    G, B, L = fp.grid, fp.bins, hand.n_joints
+    shp = (L, G ** 3, B // 32)
+    bits = np.zeros(shp, np.uint32)
+    sure = np.zeros(shp, np.uint32) if flags else None
+    maybe = np.zeros(shp, np.uint32) if flags else None
+    wshp = (L, G ** 3, B)
+    wit = np.zeros(wshp, np.int32) if witness else None
+    wlo = np.zeros(wshp, np.int32) if (witness and flags) else None
+    whi = np.zeros(wshp, np.int32) if (witness and flags) else None
+    stats = np.zeros(4, np.int64)
+    H, Fp = _hand(hand), _field(fp)
+    rc = lib().orc_build_field(H.ref, Fp.ref, _p(bits), _p(sure), _p(maybe), _p(wit), _p(wlo),
+                               _p(whi), _p(stats))
+    if rc != 0:
+        raise ValueError(f"orc_build_field failed ({rc})")
+    return {"bits": bits, "sure": sure, "maybe": maybe, "wit": wit, "wit_lo": wlo,
+            "wit_hi": whi, "stats": stats}
+
+
+def query(hand, fp, bits, pts, nrm, poses, flags: bool = True) -> dict:
+    """Contact domains: ``dom_bits`` uint32 [P,F,ceil(N/32)], ``dom_count``
+    uint32 [P,F], ``dom_flag`` (same shape as bits) and the number of in-window
+    (pose, point, link) lookups."""
+    pts, nrm, poses = _c(pts, np.float32), _c(nrm, np.float32), _c(poses, np.float32)
+    P, N, F = poses.shape[0], pts.shape[0], hand.n_fingers
+    NW = (N + 31) // 32
+    db = np.zeros((P, F, NW), np.uint32)
+    dc = np.zeros((P, F), np.uint32)
+    df = np.zeros((P, F, NW), np.uint32) if flags else None
+    lk = C.c_int64(0)
+    H, Fp = _hand(hand), _field(fp)
+    bb = _c(bits, np.uint32)
+    rc = lib().orc_query(H.ref, Fp.ref, _p(bb), _p(pts), _p(nrm), N, _p(poses), P, _p(db), _p(dc),
+                         _p(df), C.byref(lk))
+    if rc != 0:
+        raise ValueError(f"orc_query failed ({rc})")
+    return {"dom_bits": db, "dom_count": dc, "dom_flag": df, "lookups": lk.value}
+
+
+def draw(hand, fp, bits, pts, nrm, poses, dom_bits, dom_count, sp) -> tuple[np.ndarray, np.ndarray]:
+    """Seeded contact-set draws: ``set_pt``, ``set_link`` int32 [P, D, k]."""
+    pts, nrm, poses = _c(pts, np.float32), _c(nrm, np.float32), _c(poses, np.float32)
+    P, N = poses.shape[0], pts.shape[0]
+    spt = np.zeros((P, sp.draws, sp.k), np.int32)
+    sln = np.zeros((P, sp.draws, sp.k), np.int32)
+    H, Fp = _hand(hand), _field(fp)
+    rc = lib().orc_draw(H.ref, Fp.ref, _p(_c(bits, np.uint32)), _p(pts), _p(nrm), N, _p(poses), P,
+                        _p(_c(dom_bits, np.uint32)), _p(_c(dom_count, np.uint32)), sp.draws, sp.k,
+                        int(sp.seed) & 0xFFFFFFFFFFFFFFFF, int(sp.request_id), int(sp.pose_offset),
+                        _p(spt), _p(sln))
+    if rc != 0:
+        raise ValueError(f"orc_draw failed ({rc})")
+    return spt, sln
+
+
+def tangent_basis(n) -> tuple[np.ndarray, np.ndarray]:
+    nn = _c(n, np.float64)
+    x, y = np.zeros(3), np.zeros(3)
+    lib().orc_tangent_basis(_p(nn), _p(x), _p(y))
+    return x, y
+
+
+def wrench_matrix(p, n, mu: float, m: int, rho: float) -> np.ndarray:
+    """Wrench columns [k*m, 6] of the linearised cones."""
+    p, n = _c(p, np.float64), _c(n, np.float64)
+    k = p.shape[0]
+    W = np.zeros((k * m, 6), np.float64)
+    lib().orc_wrench_matrix(k, _p(p), _p(n), float(mu), int(m), float(rho), _p(W))
+    return W
+
+
+def lp_solve(W, max_pivots: int = 1000) -> tuple[float, int, int]:
+    """t* = min ||W^T g||_1 over the simplex; returns (t*, status, pivots)."""
+    W = _c(W, np.float64)
+    st, pv = C.c_int(0), C.c_int(0)
+    t = lib().orc_lp_solve(W.shape[0], _p(W), int(max_pivots), C.byref(st), C.byref(pv))
+    return t, st.value, pv.value
+
+
+def set_tstar(p, n, mu: float, m: int, rho: float, max_pivots: int = 1000) -> tuple[float, int]:
+    p, n = _c(p, np.float64), _c(n, np.float64)
+    st, pv = C.c_int(0), C.c_int(0)
+    t = lib().orc_set_tstar(p.shape[0], _p(p), _p(n), float(mu), int(m), float(rho),
+                            int(max_pivots), C.byref(st), C.byref(pv))
+    return t, st.value
+
+
+def verdicts(pts, nrm, set_pt, sp, max_pivots: int = 1000) -> dict:
+    """Force-closure verdicts of drawn sets (object frame)."""
+    pts, nrm = _c(pts, np.float32), _c(nrm, np.float32)
+    sets = _c(set_pt, np.int32).reshape(-1, sp.k)
+    n = sets.shape[0]
+    v = np.zeros(n, np.uint8)
+    t = np.zeros(n, np.float64)
+    vf = np.zeros(n, np.uint8)
+    st = np.zeros(n, np.int32)
+    rc = lib().orc_verdicts(_p(pts), _p(nrm), n, sp.k, _p(sets), float(np.float32(sp.mu)),
+                            sp.m_edges, float(np.float32(sp.moment_scale)),
+                            float(np.float32(sp.eps)), int(max_pivots), _p(v), _p(t), _p(vf),
+                            _p(st))
+    if rc != 0:
+        raise ValueError(f"orc_verdicts failed ({rc})")
+    return {"verdict": v, "tstar": t, "vflag": vf, "status": st}
+
+
+def compact(verdict) -> np.ndarray:
+    """Accepted set ids (g*D + d) in pose-major, draw-minor order."""
+    return np.flatnonzero(np.asarray(verdict).reshape(-1)).astype(np.int32)
+
+
+def ik_finger(hand, f: int, link: int, p, n, q0, ik) -> dict:
+    H = _hand(hand)
+    q = _c(q0, np.float64).copy()
+    pp, nn = _c(p, np.float64), _c(n, np.float64)
+    err, ang = C.c_double(0), C.c_double(0)
+    pt, nt = np.zeros(3), np.zeros(3)
+    ikp = _ik(ik)
+    lib().orc_ik_finger(H.ref, f, link, _p(pp), _p(nn), C.byref(ikp), _p(q), C.byref(err),
+                        C.byref(ang), _p(pt), _p(nt))
+    return {"q": q, "err": err.value, "ang": ang.value, "pt": pt, "nt": nt}
+
+
+def point_jacobian(hand, f: int, link: int, q, x) -> np.ndarray:
+    """3 x d_f position Jacobian of point ``x`` fixed to ``link`` (Eq. 8)."""
+    H = _hand(hand)
+    T = fk(hand, q)
+    xx = _c(x, np.float64)
+    Jm = np.zeros((3, hand.dof[f]), np.float64)
+    lib().orc_point_jacobian(H.ref, f, link, _p(T), _p(xx), _p(Jm))
+    return Jm
+
+
+def sdf_eval(sdf, y) -> float:
+    S = _sdf(sdf)
+    yy = _c(y, np.float64)
+    return lib().orc_sdf_eval(S.ref, _p(yy))
+
+
+def axis_samples(hand, l: int) -> int:
+    return lib().orc_axis_samples(_hand(hand).ref, l)
+
+
+def penetration(hand, q, sdf, pose) -> float:
+    H, S = _hand(hand), _sdf(sdf)
+    T = fk(hand, q)
+    pp = _c(pose, np.float32)
+    return lib().orc_penetration(H.ref, _p(T), S.ref, _p(pp))
+
+
+def realize(hand, fp, wit, sdf, pts, nrm, poses, set_pt, set_link, sp, acc_list, ik) -> dict:
+    """IK + penetration + acceptance for accepted set ids ``acc_list``."""
+    pts, nrm, poses = _c(pts, np.float32), _c(nrm, np.float32), _c(poses, np.float32)
+    acc = _c(acc_list, np.int32)
+    n, J, k = acc.shape[0], hand.n_joints, sp.k
+    q = np.zeros((n, J)); q0 = np.zeros((n, J))
+    err = np.zeros((n, k)); ang = np.zeros((n, k)); dep = np.zeros(n)
+    val = np.zeros(n, np.uint8); fl = np.zeros(n, np.uint8)
+    H, Fp, S = _hand(hand), _field(fp), _sdf(sdf)
+    ikp = _ik(ik)
+    w = None if wit is None else _c(wit, np.int32)
+    rc = lib().orc_realize(H.ref, Fp.ref, _p(w), S.ref, _p(pts), _p(nrm), _p(poses),
+                           _p(_c(set_pt, np.int32)), _p(_c(set_link, np.int32)), k, sp.draws,
+                           _p(acc), n, C.byref(ikp), _p(q), _p(q0), _p(err), _p(ang), _p(dep),
+                           _p(val), _p(fl))
+    if rc != 0:
+        raise ValueError(f"orc_realize failed ({rc})")
+    return {"q": q, "q0": q0, "contact_err": err, "contact_ang": ang, "depth": dep,
+            "valid": val, "rflag": fl}

@@ -1,0 +1,1179 @@
+/*
+ * FP64 CPU oracle of the Contact-Field pipeline (Lightning Grasp,
+ * arXiv 2511.07418).  TEST INFRASTRUCTURE ONLY: it is loaded by the tests,
+ * by the smoke check and by the CPU-baseline leg of the benchmark, never by
+ * the product path.  It shares no code with the HIP library.
+ *
+ * Plain, slow, obviously-correct C11 in double precision.  Inputs arrive as
+ * float32 arrays (the library's formats) and are promoted exactly.  Every
+ * discrete decision (voxel, normal bin, LP verdict, acceptance thresholds) is
+ * also reported with a boundary flag so that a float32 implementation can be
+ * compared bit-exactly on everything that is not within the stated bands:
+ *   - voxel: a coordinate within 1e-6 m of a voxel face,
+ *   - bin:   a direction within 1e-6 rad of a bin (Voronoi) boundary,
+ *            measured as (theta2 - theta1)/2,
+ *   - verdict / thresholds: within 1e-6 of the threshold.
+ *
+ * Build: gcc -O2 -std=c11 -fopenmp -ffp-contract=off -shared -fPIC.
+ */
+#define _DEFAULT_SOURCE
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_EINVAL -1
+#define ORC_ENOMEM -2
+
+#define BAND_POS 1e-6   /* m   */
+#define BAND_ANG 1e-6   /* rad */
+#define BAND_VAL 1e-6   /* thresholds (t*, contact error, angle, depth) */
+
+#define PURPOSE_JOINT 1u
+#define PURPOSE_DRAW 3u
+
+/* ------------------------------------------------------------------------ */
+/* Hand description (host arrays, float32 as in the library ABI)             */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_fingers;
+    int32_t n_joints;
+    const int32_t *joint_finger;  /* [J] */
+    const int32_t *joint_parent;  /* [J] -1 = hand base */
+    const float *joint_origin;    /* [J][12] parent->joint 3x4 row-major */
+    const float *joint_axis;      /* [J][3] */
+    const float *capsule;         /* [J][7] a, b, r (link frame) */
+    const float *limits;          /* [J][2] */
+    int32_t n_surf;
+    const float *surf;            /* [J][n_surf][6] link-frame point, normal */
+} orc_hand;
+
+typedef struct {
+    int64_t samples;      /* S per finger */
+    uint64_t seed;        /* Philox key */
+    int32_t grid;         /* G */
+    double h;             /* voxel edge */
+    int32_t bins;         /* B: 32 or 64 */
+    const float *grid_frame; /* [F][12] [R | o]: u = R^T (x - o) / h */
+} orc_field_params;
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as    */
+/* easy as 1, 2, 3", SC'11).  Counter-based: four 32-bit counter words, two   */
+/* 32-bit key words, ten rounds of two 32x32->64 multiplies, the key bumped   */
+/* by the Weyl constants between rounds.                                      */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t m0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t m1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t y0 = (uint32_t)(m1 >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)m1;
+        uint32_t y2 = (uint32_t)(m0 >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)m0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+static double u01(uint32_t w) { return (double)(w >> 8) * (1.0 / 16777216.0); }
+
+static int finger_first_joint(const orc_hand *H, int f)
+{
+    for (int j = 0; j < H->n_joints; ++j)
+        if (H->joint_finger[j] == f) return j;
+    return -1;
+}
+
+static int finger_dof(const orc_hand *H, int f)
+{
+    int n = 0;
+    for (int j = 0; j < H->n_joints; ++j) n += (H->joint_finger[j] == f);
+    return n;
+}
+
+/* Joint sample s of finger f (Sec. 4.3: random joint configurations).
+ * Joint t of the finger uses word t%4 of the block with counter
+ * (s, 8f + t/4, JOINT, 0); q = lo + (hi - lo) * u01.                         */
+void orc_joint_sample(const orc_hand *H, uint64_t seed, int f, int64_t s, double *q_out)
+{
+    int j0 = finger_first_joint(H, f), d = finger_dof(H, f);
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int t = 0; t < d; ++t) {
+        uint32_t ctr[4] = {(uint32_t)s, (uint32_t)(8 * f + t / 4), PURPOSE_JOINT, 0u};
+        uint32_t w[4];
+        orc_philox4x32_10(ctr, key, w);
+        double lo = H->limits[2 * (j0 + t)], hi = H->limits[2 * (j0 + t) + 1];
+        q_out[t] = lo + (hi - lo) * u01(w[t % 4]);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rigid transforms: 3x4 row-major [R | t]                                   */
+/* ------------------------------------------------------------------------ */
+static void tf_load(const float *src, double *T)
+{
+    for (int i = 0; i < 12; ++i) T[i] = src[i];
+}
+
+static void tf_mul(const double *A, const double *B, double *C)
+{
+    double R[12];
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j)
+            R[4 * i + j] = A[4 * i] * B[j] + A[4 * i + 1] * B[4 + j] + A[4 * i + 2] * B[8 + j];
+        R[4 * i + 3] = A[4 * i] * B[3] + A[4 * i + 1] * B[7] + A[4 * i + 2] * B[11] + A[4 * i + 3];
+    }
+    memcpy(C, R, sizeof R);
+}
+
+static void tf_point(const double *T, const double *p, double *x)
+{
+    for (int i = 0; i < 3; ++i)
+        x[i] = T[4 * i] * p[0] + T[4 * i + 1] * p[1] + T[4 * i + 2] * p[2] + T[4 * i + 3];
+}
+
+static void tf_dir(const double *T, const double *p, double *x)
+{
+    for (int i = 0; i < 3; ++i)
+        x[i] = T[4 * i] * p[0] + T[4 * i + 1] * p[1] + T[4 * i + 2] * p[2];
+}
+
+/* Rotation by angle q about unit axis a (Rodrigues' formula). */
+static void tf_axis_angle(const double *a, double q, double *T)
+{
+    double c = cos(q), s = sin(q), v = 1.0 - c;
+    double x = a[0], y = a[1], z = a[2];
+    T[0] = c + x * x * v;     T[1] = x * y * v - z * s; T[2] = x * z * v + y * s;  T[3] = 0;
+    T[4] = y * x * v + z * s; T[5] = c + y * y * v;     T[6] = y * z * v - x * s;  T[7] = 0;
+    T[8] = z * x * v - y * s; T[9] = z * y * v + x * s; T[10] = c + z * z * v;     T[11] = 0;
+}
+
+/* Forward kinematics F of Sec. 3.1 for the joints of finger f:
+ * T_j = T_parent * origin_j * Rot(axis_j, q_j).  q_f holds the finger's
+ * joints in chain order; frames are written for those joints only (index by
+ * global joint id).                                                          */
+void orc_fk_finger(const orc_hand *H, int f, const double *q_f, double *T /*[J][12]*/)
+{
+    int t = 0;
+    for (int j = 0; j < H->n_joints; ++j) {
+        if (H->joint_finger[j] != f) continue;
+        double O[12], Rq[12], P[12];
+        tf_load(H->joint_origin + 12 * j, O);
+        if (H->joint_parent[j] >= 0)
+            tf_mul(T + 12 * H->joint_parent[j], O, P);
+        else
+            memcpy(P, O, sizeof P);
+        double ax[3] = {H->joint_axis[3 * j], H->joint_axis[3 * j + 1], H->joint_axis[3 * j + 2]};
+        tf_axis_angle(ax, q_f[t], Rq);
+        tf_mul(P, Rq, T + 12 * j);
+        ++t;
+    }
+}
+
+/* All fingers: q holds all J joints in joint order. */
+void orc_fk(const orc_hand *H, const double *q, double *T)
+{
+    for (int f = 0; f < H->n_fingers; ++f) {
+        int j0 = finger_first_joint(H, f);
+        orc_fk_finger(H, f, q + j0, T);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Normal bins: spherical Fibonacci lattice, nearest centre = argmax dot      */
+/* (the paper quantises normals onto a compact unit sphere, Sec. 4.4).        */
+/* ------------------------------------------------------------------------ */
+void orc_bin_centers(int B, double *c)
+{
+    const double golden = M_PI * (3.0 - sqrt(5.0));
+    for (int b = 0; b < B; ++b) {
+        double z = 1.0 - (2.0 * b + 1.0) / B;
+        double r = sqrt(1.0 - z * z);
+        double ph = b * golden;
+        c[3 * b] = r * cos(ph);
+        c[3 * b + 1] = r * sin(ph);
+        c[3 * b + 2] = z;
+    }
+}
+
+/* Best bin of direction d (not necessarily unit) with ties to the lowest
+ * index; second best bin; half the angular gap (theta2 - theta1)/2.          */
+static int bin_of(int B, const double *c, const double *d, int *second, double *half_gap)
+{
+    double nd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    int b1 = -1, b2 = -1;
+    double s1 = -1e300, s2 = -1e300;
+    for (int b = 0; b < B; ++b) {
+        double s = c[3 * b] * d[0] + c[3 * b + 1] * d[1] + c[3 * b + 2] * d[2];
+        if (s > s1) { s2 = s1; b2 = b1; s1 = s; b1 = b; }
+        else if (s > s2) { s2 = s; b2 = b; }
+    }
+    if (second) *second = b2;
+    if (half_gap) {
+        double c1 = s1 / nd, c2 = s2 / nd;
+        if (c1 > 1) c1 = 1;
+        if (c2 > 1) c2 = 1;
+        if (c1 < -1) c1 = -1;
+        if (c2 < -1) c2 = -1;
+        *half_gap = 0.5 * (acos(c2) - acos(c1));
+    }
+    return b1;
+}
+
+int orc_bin(int B, const double *d, int *second, double *half_gap)
+{
+    double c[3 * 256];
+    if (B <= 0 || B > 256) return -1;
+    orc_bin_centers(B, c);
+    return bin_of(B, c, d, second, half_gap);
+}
+
+/* Voxel coordinates of hand-frame point x in finger window f:
+ * u = R^T (x - o) / h.  Returns 1 if inside [0, G)^3.                        */
+static int voxel_coords(const orc_field_params *fp, int f, const double *x, double *u)
+{
+    const float *F = fp->grid_frame + 12 * f;
+    double d[3] = {x[0] - F[3], x[1] - F[7], x[2] - F[11]};
+    int in = 1;
+    for (int a = 0; a < 3; ++a) {
+        u[a] = (F[a] * d[0] + F[4 + a] * d[1] + F[8 + a] * d[2]) / fp->h;
+        if (!(u[a] >= 0.0 && u[a] < (double)fp->grid)) in = 0;
+    }
+    return in;
+}
+
+/* distance (m) of coordinate u (voxel units) to the nearest voxel face
+ * (integer), including the window faces 0 and G                             */
+static double face_dist(double u, double h)
+{
+    double r = u - floor(u);
+    double d = r < 0.5 ? r : 1.0 - r;
+    return d * h;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Field construction (Sec. 4.3, Algorithm 1, and Sec. 4.4):                  */
+/* for every finger f, joint sample s, link l of f and surface sample (p, n)  */
+/* of l: contact vector x = T_l(q_s) p, nu = R_l(q_s) n; the grid cover of    */
+/* width h assigns x to voxel floor(u) (dropped if outside the window) and    */
+/* the normal is quantised to bin argmax_b <nu, c_b>; the bit of (l, voxel,   */
+/* bin) is set and the smallest sample index s reaching it is kept as the     */
+/* witness used by the reverse lookup of Sec. 5.5.                             */
+/*                                                                            */
+/* Outputs (canonical layout, voxel v = (iz*G + iy)*G + ix, word = b/32,      */
+/* bit = b%32):                                                               */
+/*   bits  [L][G^3][B/32]   every vector at its float64 voxel/bin              */
+/*   sure  [L][G^3][B/32]   cells set by at least one unflagged vector         */
+/*   maybe [L][G^3][B/32]   cells a flagged vector may reach (its cell, the    */
+/*                          neighbour across each near face, the 2nd bin)     */
+/*   wit   [L][G^3][B]      min s over `bits` contributions (optional)         */
+/*   wit_lo[L][G^3][B]      min s over any possible contribution (optional)   */
+/*   wit_hi[L][G^3][B]      min s over unflagged contributions (optional)     */
+/*   stats [4]: vectors, in-window vectors, dropped, flagged                  */
+/* ------------------------------------------------------------------------ */
+static inline void set_bit(uint32_t *w, int64_t v, int nw, int b)
+{
+    w[v * nw + (b >> 5)] |= 1u << (b & 31);
+}
+
+static inline void wmin(int32_t *w, int64_t idx, int32_t s)
+{
+    if (w[idx] < 0 || s < w[idx]) w[idx] = s;
+}
+
+int orc_build_field(const orc_hand *H, const orc_field_params *fp,
+                    uint32_t *bits, uint32_t *sure, uint32_t *maybe,
+                    int32_t *wit, int32_t *wit_lo, int32_t *wit_hi, int64_t *stats)
+{
+    const int G = fp->grid, B = fp->bins, J = H->n_joints;
+    if (G <= 0 || (B != 32 && B != 64) || fp->h <= 0 || fp->samples <= 0) return ORC_EINVAL;
+    const int nw = B / 32;
+    const int64_t G3 = (int64_t)G * G * G;
+    const int64_t words = (int64_t)J * G3 * nw;
+    if (bits) memset(bits, 0, words * 4);
+    if (sure) memset(sure, 0, words * 4);
+    if (maybe) memset(maybe, 0, words * 4);
+    int32_t *wits[3] = {wit, wit_lo, wit_hi};
+    for (int i = 0; i < 3; ++i)
+        if (wits[i]) memset(wits[i], 0xff, (size_t)J * G3 * B * 4); /* -1 = none */
+    double cb[3 * 64];
+    orc_bin_centers(B, cb);
+    int64_t n_vec = 0, n_in = 0, n_flag = 0;
+
+    /* one link per task: each task owns its link's tables (no races) */
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : n_vec, n_in, n_flag)
+    for (int l = 0; l < J; ++l) {
+        const int f = H->joint_finger[l];
+        const int j0 = finger_first_joint(H, f);
+        double q[32], T[12 * 64];
+        const int64_t lbase = (int64_t)l * G3;
+        for (int64_t s = 0; s < fp->samples; ++s) {
+            orc_joint_sample(H, fp->seed, f, s, q);
+            orc_fk_finger(H, f, q, T);
+            (void)j0;
+            const double *Tl = T + 12 * l;
+            for (int i = 0; i < H->n_surf; ++i) {
+                const float *sp = H->surf + ((int64_t)l * H->n_surf + i) * 6;
+                double p[3] = {sp[0], sp[1], sp[2]}, n[3] = {sp[3], sp[4], sp[5]};
+                double x[3], nu[3], u[3];
+                tf_point(Tl, p, x);
+                tf_dir(Tl, n, nu);
+                ++n_vec;
+                int in = voxel_coords(fp, f, x, u);
+                int b2;
+                double gap;
+                int b = bin_of(B, cb, nu, &b2, &gap);
+                int near_face[3];
+                int flagged = gap < BAND_ANG;
+                for (int a = 0; a < 3; ++a) {
+                    near_face[a] = face_dist(u[a], fp->h) < BAND_POS;
+                    flagged |= near_face[a];
+                }
+                /* a vector just outside the window can be inside at float32 */
+                int ix[3];
+                for (int a = 0; a < 3; ++a) ix[a] = (int)floor(u[a]);
+                if (in) {
+                    ++n_in;
+                    int64_t v = lbase + ((int64_t)ix[2] * G + ix[1]) * G + ix[0];
+                    if (bits) set_bit(bits, v, nw, b);
+                    if (wit) wmin(wit, v * B + b, (int32_t)s);
+                    if (!flagged) {
+                        if (sure) set_bit(sure, v, nw, b);
+                        if (wit_hi) wmin(wit_hi, v * B + b, (int32_t)s);
+                    }
+                }
+                if (!flagged) {
+                    if (in && wit_lo) {
+                        int64_t v = lbase + ((int64_t)ix[2] * G + ix[1]) * G + ix[0];
+                        wmin(wit_lo, v * B + b, (int32_t)s);
+                    }
+                    continue;
+                }
+                ++n_flag;
+                /* enumerate alternative voxels (+-1 across near faces) and bins */
+                int lo3[3], hi3[3];
+                for (int a = 0; a < 3; ++a) {
+                    lo3[a] = hi3[a] = ix[a];
+                    if (near_face[a]) {
+                        double r = u[a] - floor(u[a]);
+                        if (r < 0.5) lo3[a] = ix[a] - 1; else hi3[a] = ix[a] + 1;
+                    }
+                }
+                int nb = gap < BAND_ANG ? 2 : 1;
+                int bb[2] = {b, b2};
+                for (int zz = lo3[2]; zz <= hi3[2]; ++zz)
+                    for (int yy = lo3[1]; yy <= hi3[1]; ++yy)
+                        for (int xx = lo3[0]; xx <= hi3[0]; ++xx) {
+                            if (xx < 0 || yy < 0 || zz < 0 || xx >= G || yy >= G || zz >= G) continue;
+                            int64_t v = lbase + ((int64_t)zz * G + yy) * G + xx;
+                            for (int k = 0; k < nb; ++k) {
+                                if (maybe) set_bit(maybe, v, nw, bb[k]);
+                                if (wit_lo) wmin(wit_lo, v * B + bb[k], (int32_t)s);
+                            }
+                        }
+            }
+        }
+    }
+    if (stats) {
+        stats[0] = n_vec;
+        stats[1] = n_in;
+        stats[2] = n_vec - n_in;
+        stats[3] = n_flag;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Object contact query (Sec. 4.2-4.3, Def. 4.3, Sec. 5.3).                  */
+/* For pose (R, t) and object point (p, n): x = R p + t, nu = R n; the query  */
+/* vector is (x, -nu) (the contact surface representation negates the         */
+/* normal).  Link l hits if bit bin(-nu) of its table at voxel(x) is set      */
+/* (0 outside the window); the domain of finger f (a dependency group) is the */
+/* OR over its links.  dom_bits[g][f][w] bit i%32 of word i/32 is point i.    */
+/* dom_flag marks (g, f, i) whose value could change under the float32        */
+/* rounding bands (some alternative voxel/bin gives a different OR).          */
+/* ------------------------------------------------------------------------ */
+static int link_hits_at(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits,
+                        int f, const int *vox, int in, int b, uint32_t *mask)
+{
+    const int G = fp->grid, nw = fp->bins / 32;
+    const int64_t G3 = (int64_t)G * G * G;
+    uint32_t m = 0;
+    int t = 0, any = 0;
+    for (int l = 0; l < H->n_joints; ++l) {
+        if (H->joint_finger[l] != f) continue;
+        if (in) {
+            int64_t v = (int64_t)l * G3 + ((int64_t)vox[2] * G + vox[1]) * G + vox[0];
+            if ((bits[v * nw + (b >> 5)] >> (b & 31)) & 1u) {
+                m |= 1u << t;
+                any = 1;
+            }
+        }
+        ++t;
+    }
+    if (mask) *mask = m;
+    return any;
+}
+
+/* transform + voxel + bin for one (pose, point, finger); returns in-window */
+static int query_lookup(const orc_field_params *fp, const double *cb, const float *pose,
+                        const float *pt, const float *nm, int f,
+                        double *x, double *u, int *vox, int *b, int *b2, double *gap)
+{
+    double p[3] = {pt[0], pt[1], pt[2]}, n[3] = {nm[0], nm[1], nm[2]};
+    double T[12];
+    tf_load(pose, T);
+    double nu[3], q[3];
+    tf_point(T, p, x);
+    tf_dir(T, n, nu);
+    q[0] = -nu[0]; q[1] = -nu[1]; q[2] = -nu[2];
+    *b = bin_of(fp->bins, cb, q, b2, gap);
+    int in = voxel_coords(fp, f, x, u);
+    for (int a = 0; a < 3; ++a) vox[a] = (int)floor(u[a]);
+    return in;
+}
+
+int orc_query(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits,
+              const float *pts /*[N][3]*/, const float *nrm /*[N][3]*/, int32_t n_points,
+              const float *poses /*[P][12]*/, int32_t n_poses,
+              uint32_t *dom_bits, uint32_t *dom_count, uint32_t *dom_flag, int64_t *lookups)
+{
+    const int F = H->n_fingers, G = fp->grid;
+    const int64_t NW = (n_points + 31) / 32;
+    if (n_points < 0 || n_poses < 0) return ORC_EINVAL;
+    double cb[3 * 64];
+    orc_bin_centers(fp->bins, cb);
+    int64_t n_lookup = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : n_lookup)
+    for (int g = 0; g < n_poses; ++g) {
+        for (int f = 0; f < F; ++f) {
+            uint32_t *db = dom_bits + ((int64_t)g * F + f) * NW;
+            uint32_t *df = dom_flag ? dom_flag + ((int64_t)g * F + f) * NW : NULL;
+            memset(db, 0, NW * 4);
+            if (df) memset(df, 0, NW * 4);
+            uint32_t cnt = 0;
+            for (int i = 0; i < n_points; ++i) {
+                double x[3], u[3];
+                int vox[3], b, b2;
+                double gap;
+                int in = query_lookup(fp, cb, poses + 12 * (int64_t)g, pts + 3 * (int64_t)i,
+                                      nrm + 3 * (int64_t)i, f, x, u, vox, &b, &b2, &gap);
+                if (in) n_lookup += finger_dof(H, f);
+                int hit = link_hits_at(H, fp, bits, f, vox, in, b, NULL);
+                if (hit) {
+                    db[i >> 5] |= 1u << (i & 31);
+                    ++cnt;
+                }
+                if (!df) continue;
+                /* boundary flag: does any alternative outcome differ? */
+                int near[3], any_near = 0;
+                for (int a = 0; a < 3; ++a) {
+                    near[a] = face_dist(u[a], fp->h) < BAND_POS;
+                    any_near |= near[a];
+                }
+                int bin_near = gap < BAND_ANG;
+                if (!any_near && !bin_near) continue;
+                int lo3[3], hi3[3];
+                for (int a = 0; a < 3; ++a) {
+                    lo3[a] = hi3[a] = vox[a];
+                    if (near[a]) {
+                        double r = u[a] - floor(u[a]);
+                        if (r < 0.5) lo3[a] = vox[a] - 1; else hi3[a] = vox[a] + 1;
+                    }
+                }
+                int bb[2] = {b, b2}, nb = bin_near ? 2 : 1, differs = 0;
+                for (int zz = lo3[2]; zz <= hi3[2] && !differs; ++zz)
+                    for (int yy = lo3[1]; yy <= hi3[1] && !differs; ++yy)
+                        for (int xx = lo3[0]; xx <= hi3[0] && !differs; ++xx) {
+                            int v3[3] = {xx, yy, zz};
+                            int in2 = xx >= 0 && yy >= 0 && zz >= 0 && xx < G && yy < G && zz < G;
+                            for (int k = 0; k < nb; ++k)
+                                if (link_hits_at(H, fp, bits, f, v3, in2, bb[k], NULL) != hit)
+                                    differs = 1;
+                        }
+                if (differs) df[i >> 5] |= 1u << (i & 31);
+            }
+            dom_count[(int64_t)g * F + f] = cnt;
+        }
+    }
+    if (lookups) *lookups = n_lookup;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Contact-set draws (Sec. 5.3: one domain per dependency group, then one     */
+/* point per domain, Alg. 2 initialisation) and the reverse lookup of the     */
+/* hand link (Sec. 5.5: pick one of the active patch fields at random).       */
+/* Contact i lies on finger i (k == F).  Philox block (g, 4d + blk, DRAW,     */
+/* request_id); words 0..k-1 pick points, words k..2k-1 pick links.  The      */
+/* j-th set bit is selected with j = floor(r * count / 2^32).                 */
+/* ------------------------------------------------------------------------ */
+static int64_t select1(const uint32_t *words, int64_t nw, uint32_t j)
+{
+    uint32_t seen = 0;
+    for (int64_t w = 0; w < nw; ++w) {
+        uint32_t x = words[w];
+        for (int b = 0; b < 32; ++b) {
+            if ((x >> b) & 1u) {
+                if (seen == j) return w * 32 + b;
+                ++seen;
+            }
+        }
+    }
+    return -1;
+}
+
+static uint32_t popcount32(uint32_t x)
+{
+    uint32_t c = 0;
+    for (int b = 0; b < 32; ++b) c += (x >> b) & 1u;
+    return c;
+}
+
+static void draw_words(uint64_t seed, uint32_t request_id, int64_t g, int d, int n, uint32_t *w)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int blk = 0; blk * 4 < n; ++blk) {
+        uint32_t ctr[4] = {(uint32_t)g, (uint32_t)(4 * d + blk), PURPOSE_DRAW, request_id};
+        orc_philox4x32_10(ctr, key, w + 4 * blk);
+    }
+}
+
+int orc_draw(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits,
+             const float *pts, const float *nrm, int32_t n_points,
+             const float *poses, int32_t n_poses,
+             const uint32_t *dom_bits, const uint32_t *dom_count,
+             int32_t draws, int32_t k, uint64_t seed, uint32_t request_id, int64_t pose_offset,
+             int32_t *set_pt /*[P][D][k]*/, int32_t *set_link /*[P][D][k]*/)
+{
+    const int F = H->n_fingers;
+    const int64_t NW = (n_points + 31) / 32;
+    if (k != F || k > 8 || draws <= 0) return ORC_EINVAL;
+    double cb[3 * 64];
+    orc_bin_centers(fp->bins, cb);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int g = 0; g < n_poses; ++g) {
+        for (int d = 0; d < draws; ++d) {
+            uint32_t w[16];
+            draw_words(seed, request_id, pose_offset + g, d, 2 * k, w);
+            int32_t *sp = set_pt + ((int64_t)g * draws + d) * k;
+            int32_t *sl = set_link + ((int64_t)g * draws + d) * k;
+            int ok = 1;
+            for (int i = 0; i < k; ++i)
+                if (dom_count[(int64_t)g * F + i] == 0) ok = 0;
+            for (int i = 0; i < k; ++i) { sp[i] = -1; sl[i] = -1; }
+            if (!ok) continue;
+            for (int i = 0; i < k; ++i) {
+                uint32_t cnt = dom_count[(int64_t)g * F + i];
+                uint32_t j = (uint32_t)(((uint64_t)w[i] * cnt) >> 32);
+                int64_t idx = select1(dom_bits + ((int64_t)g * F + i) * NW, NW, j);
+                double x[3], u[3], gap;
+                int vox[3], b, b2;
+                int in = query_lookup(fp, cb, poses + 12 * (int64_t)g, pts + 3 * idx, nrm + 3 * idx,
+                                      i, x, u, vox, &b, &b2, &gap);
+                uint32_t mask = 0;
+                link_hits_at(H, fp, bits, i, vox, in, b, &mask);
+                uint32_t pc = popcount32(mask);
+                int link = -1;
+                if (pc > 0) {
+                    uint32_t jj = (uint32_t)(((uint64_t)w[k + i] * pc) >> 32);
+                    uint32_t seen = 0;
+                    int t = 0;
+                    for (int l = 0; l < H->n_joints; ++l) {
+                        if (H->joint_finger[l] != i) continue;
+                        if ((mask >> t) & 1u) {
+                            if (seen == jj) { link = l; break; }
+                            ++seen;
+                        }
+                        ++t;
+                    }
+                }
+                sp[i] = (int32_t)idx;
+                sl[i] = link;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Contact-set criterion (Sec. 3.2, Eq. 1-2) as a linear program.             */
+/* Friction cones are linearised with m edges around the contact normal:     */
+/*   d_ie = -n_i + mu (cos(2 pi e/m) x_i + sin(2 pi e/m) y_i),                */
+/* with (x_i, y_i) the branchless orthonormal tangent basis of Duff et al.    */
+/* (JCGT 2017) and the moment rows scaled by 1/rho:                           */
+/*   w_ie = [d_ie ; (p_i x d_ie) / rho].                                       */
+/* t* = min sum_r |(W g)_r|  s.t. g >= 0, sum g = 1, solved exactly by a      */
+/* dense Phase-1 simplex with Bland's rule.  t* = 0 iff a non-trivial         */
+/* self-balancing combination of contact forces exists.                       */
+/* status: 0 optimal, 1 pivot cap reached (undecided).                         */
+/* ------------------------------------------------------------------------ */
+static void duff_basis(const double *n, double *x, double *y)
+{
+    double sign = copysign(1.0, n[2]);
+    double a = -1.0 / (sign + n[2]);
+    double b = n[0] * n[1] * a;
+    x[0] = 1.0 + sign * n[0] * n[0] * a;
+    x[1] = sign * b;
+    x[2] = -sign * n[0];
+    y[0] = b;
+    y[1] = sign + n[1] * n[1] * a;
+    y[2] = -n[1];
+}
+
+void orc_tangent_basis(const double *n, double *x, double *y) { duff_basis(n, x, y); }
+
+/* wrench columns, W[c][6] with c = i*m + e */
+void orc_wrench_matrix(int k, const double *p, const double *n, double mu, int m, double rho,
+                       double *W)
+{
+    for (int i = 0; i < k; ++i) {
+        double x[3], y[3];
+        duff_basis(n + 3 * i, x, y);
+        for (int e = 0; e < m; ++e) {
+            double th = 2.0 * M_PI * e / m;
+            double ce = cos(th), se = sin(th);
+            double d[3];
+            for (int a = 0; a < 3; ++a) d[a] = -n[3 * i + a] + mu * (ce * x[a] + se * y[a]);
+            const double *pi = p + 3 * i;
+            double *w = W + 6 * (i * m + e);
+            w[0] = d[0]; w[1] = d[1]; w[2] = d[2];
+            w[3] = (pi[1] * d[2] - pi[2] * d[1]) / rho;
+            w[4] = (pi[2] * d[0] - pi[0] * d[2]) / rho;
+            w[5] = (pi[0] * d[1] - pi[1] * d[0]) / rho;
+        }
+    }
+}
+
+#define LP_TOL 1e-12
+
+/* Phase-1 LP on n columns (6 numbers each).  Variables: g_0..g_{n-1},
+ * s+_0..s+_5, s-_0..s-_5 (column index order used by Bland's rule).          */
+double orc_lp_solve(int n, const double *W, int max_pivots, int *status, int *pivots)
+{
+    const int nv = n + 12, rows = 7;
+    double *T = (double *)calloc((size_t)rows * (nv + 1), sizeof(double));
+    double *red = (double *)calloc((size_t)nv, sizeof(double));
+    int basis[7];
+    if (!T || !red) {
+        free(T); free(red);
+        if (status) *status = -1;
+        return NAN;
+    }
+#define TA(r, c) T[(r) * (nv + 1) + (c)]
+    for (int r = 0; r < 6; ++r) {
+        for (int c = 0; c < n; ++c) TA(r, c) = W[6 * c + r];
+        TA(r, n + r) = -1.0;    /* s+ */
+        TA(r, n + 6 + r) = 1.0; /* s- */
+        TA(r, nv) = 0.0;
+    }
+    for (int c = 0; c < n; ++c) TA(6, c) = 1.0;
+    TA(6, nv) = 1.0;
+    /* initial basis: g_0 for the normalisation row, one slack per wrench row */
+    for (int r = 0; r < 6; ++r) {
+        double f = TA(r, 0);
+        for (int c = 0; c <= nv; ++c) TA(r, c) -= f * TA(6, c);
+        if (TA(r, nv) >= 0.0) {
+            basis[r] = n + 6 + r;
+        } else {
+            for (int c = 0; c <= nv; ++c) TA(r, c) = -TA(r, c);
+            basis[r] = n + r;
+        }
+    }
+    basis[6] = 0;
+    int piv = 0, st = 0;
+    for (;;) {
+        /* reduced costs d_j = c_j - c_B^T T_j */
+        for (int j = 0; j < nv; ++j) {
+            double z = 0.0;
+            for (int r = 0; r < rows; ++r)
+                if (basis[r] >= n) z += TA(r, j);
+            red[j] = (j >= n ? 1.0 : 0.0) - z;
+        }
+        int e = -1;
+        for (int j = 0; j < nv; ++j)
+            if (red[j] < -LP_TOL) { e = j; break; }
+        if (e < 0) break;
+        if (piv >= max_pivots) { st = 1; break; }
+        int lr = -1;
+        double best = 0.0;
+        for (int r = 0; r < rows; ++r) {
+            if (TA(r, e) > LP_TOL) {
+                double ratio = TA(r, nv) / TA(r, e);
+                if (lr < 0 || ratio < best - LP_TOL * (1.0 + fabs(best)) ||
+                    (fabs(ratio - best) <= LP_TOL * (1.0 + fabs(best)) && basis[r] < basis[lr])) {
+                    lr = r;
+                    best = ratio;
+                }
+            }
+        }
+        if (lr < 0) { st = 2; break; } /* unbounded: impossible for this LP */
+        double pv = TA(lr, e);
+        for (int c = 0; c <= nv; ++c) TA(lr, c) /= pv;
+        for (int r = 0; r < rows; ++r) {
+            if (r == lr) continue;
+            double f = TA(r, e);
+            if (f != 0.0)
+                for (int c = 0; c <= nv; ++c) TA(r, c) -= f * TA(lr, c);
+        }
+        basis[lr] = e;
+        ++piv;
+    }
+    double t = 0.0;
+    for (int r = 0; r < rows; ++r)
+        if (basis[r] >= n) t += TA(r, nv);
+#undef TA
+    free(T);
+    free(red);
+    if (status) *status = st;
+    if (pivots) *pivots = piv;
+    return t;
+}
+
+/* t* for one contact set given object-frame points/normals */
+double orc_set_tstar(int k, const double *p, const double *n, double mu, int m, double rho,
+                     int max_pivots, int *status, int *pivots)
+{
+    double *W = (double *)malloc(sizeof(double) * 6 * k * m);
+    orc_wrench_matrix(k, p, n, mu, m, rho, W);
+    double t = orc_lp_solve(k * m, W, max_pivots, status, pivots);
+    free(W);
+    return t;
+}
+
+/* Batch verdicts for drawn sets.  verdict = valid set and t* <= eps;
+ * vflag marks |t* - eps| <= 1e-6.                                           */
+int orc_verdicts(const float *pts, const float *nrm, int32_t n_sets, int32_t k,
+                 const int32_t *set_pt, double mu, int32_t m_edges, double rho, double eps,
+                 int32_t max_pivots, uint8_t *verdict, double *tstar, uint8_t *vflag, int32_t *status)
+{
+    if (k <= 0 || k * m_edges + 12 > 4096 || rho <= 0) return ORC_EINVAL;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t s = 0; s < n_sets; ++s) {
+        const int32_t *sp = set_pt + s * k;
+        int valid = 1;
+        for (int i = 0; i < k; ++i) valid &= sp[i] >= 0;
+        if (!valid) {
+            verdict[s] = 0;
+            if (tstar) tstar[s] = NAN;
+            if (vflag) vflag[s] = 0;
+            if (status) status[s] = 0;
+            continue;
+        }
+        double p[3 * 16], n[3 * 16];
+        for (int i = 0; i < k; ++i)
+            for (int a = 0; a < 3; ++a) {
+                p[3 * i + a] = pts[3 * (int64_t)sp[i] + a];
+                n[3 * i + a] = nrm[3 * (int64_t)sp[i] + a];
+            }
+        int st, pv;
+        double t = orc_set_tstar(k, p, n, mu, m_edges, rho, max_pivots, &st, &pv);
+        verdict[s] = (st == 0 && t <= eps);
+        if (tstar) tstar[s] = t;
+        if (vflag) vflag[s] = fabs(t - eps) <= BAND_VAL;
+        if (status) status[s] = st;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Kinematics optimisation (Sec. 5.5, Eq. 7-8, Phase I and Phase II).          */
+/* Contact i (object point p_i, contact-surface normal n_i = -R n_obj) is     */
+/* realised by link l_i of finger i.  The hand contact point (p~, n~) is the  */
+/* capsule surface point closest to (p, n) in the combined metric             */
+/*   |x - p|^2 + beta^2 |n~ - n|^2                                            */
+/* (the closest aligned contact vector of the reverse lookup, taken on the    */
+/* analytic capsule surface).  Phase I keeps the point chosen at q0 fixed to  */
+/* the link; Phase II re-selects it on the current link every iteration.      */
+/* Each iteration: forward kinematics; residuals of the two matched points    */
+/* p~ -> p and p~ + beta n~ -> p + beta n; point Jacobians z_j x (x - o_j) of */
+/* the joints on the chain up to l_i (Eq. 8 written in the base frame); the   */
+/* damped least-squares step dq = (J^T J + lambda I)^-1 J^T e (Eq. 7); clamp  */
+/* to the joint limits.  Final contact error and angle use the plain          */
+/* projection of p onto the capsule (nearest surface point and its normal).   */
+/* ------------------------------------------------------------------------ */
+static void capsule_world(const orc_hand *H, const double *T, int l, double *A, double *Bp, double *r)
+{
+    const float *c = H->capsule + 7 * l;
+    double a[3] = {c[0], c[1], c[2]}, b[3] = {c[3], c[4], c[5]};
+    tf_point(T + 12 * l, a, A);
+    tf_point(T + 12 * l, b, Bp);
+    *r = c[6];
+}
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static void normalize_or(double *v, const double *axis)
+{
+    double nv = sqrt(dot3(v, v));
+    if (nv > 1e-300) {
+        for (int a = 0; a < 3; ++a) v[a] /= nv;
+    } else {
+        double y[3];
+        duff_basis(axis, v, y); /* any direction perpendicular to the axis */
+    }
+}
+
+/* plain projection of p onto the capsule surface: point pt, outward normal nt */
+static void capsule_project(const double *A, const double *Bp, double r, const double *p,
+                            double *pt, double *nt)
+{
+    double ab[3] = {Bp[0] - A[0], Bp[1] - A[1], Bp[2] - A[2]};
+    double ap[3] = {p[0] - A[0], p[1] - A[1], p[2] - A[2]};
+    double L2 = dot3(ab, ab);
+    double t = L2 > 0 ? dot3(ap, ab) / L2 : 0.0;
+    if (t < 0) t = 0;
+    if (t > 1) t = 1;
+    double c[3] = {A[0] + t * ab[0], A[1] + t * ab[1], A[2] + t * ab[2]};
+    double ax[3] = {0, 0, 1};
+    if (L2 > 0) for (int a = 0; a < 3; ++a) ax[a] = ab[a] / sqrt(L2);
+    for (int a = 0; a < 3; ++a) nt[a] = p[a] - c[a];
+    normalize_or(nt, ax);
+    for (int a = 0; a < 3; ++a) pt[a] = c[a] + r * nt[a];
+}
+
+/* capsule surface point minimising |x - p|^2 + beta^2 |nt - n|^2.
+ * Cylinder: axis point c = clamped projection of p; nt = unit part of
+ * r (p - c) + beta^2 n perpendicular to the axis.  Caps (centres A, B):
+ * nt = unit r (p - centre) + beta^2 n when it points into the cap's half
+ * space.  The candidate of least cost wins (cylinder, then end cap, then
+ * start cap on exact ties).                                                 */
+static void capsule_aligned_point(const double *A, const double *Bp, double r, const double *p,
+                                  const double *n, double beta, double *pt, double *nt)
+{
+    double ab[3] = {Bp[0] - A[0], Bp[1] - A[1], Bp[2] - A[2]};
+    double L = sqrt(dot3(ab, ab));
+    double ax[3] = {0, 0, 1};
+    if (L > 0) for (int a = 0; a < 3; ++a) ax[a] = ab[a] / L;
+    double b2 = beta * beta;
+    double best = INFINITY;
+    /* cylinder */
+    {
+        double ap[3] = {p[0] - A[0], p[1] - A[1], p[2] - A[2]};
+        double s = dot3(ap, ax);
+        if (s < 0) s = 0;
+        if (s > L) s = L;
+        double c[3], v[3];
+        for (int a = 0; a < 3; ++a) c[a] = A[a] + s * ax[a];
+        for (int a = 0; a < 3; ++a) v[a] = r * (p[a] - c[a]) + b2 * n[a];
+        double va = dot3(v, ax);
+        for (int a = 0; a < 3; ++a) v[a] -= va * ax[a];
+        normalize_or(v, ax);
+        double x[3], cost = 0;
+        for (int a = 0; a < 3; ++a) {
+            x[a] = c[a] + r * v[a];
+            cost += (x[a] - p[a]) * (x[a] - p[a]) + b2 * (v[a] - n[a]) * (v[a] - n[a]);
+        }
+        best = cost;
+        memcpy(pt, x, sizeof x);
+        memcpy(nt, v, sizeof v);
+    }
+    /* end cap (centre B, half space ax . nt >= 0), then start cap (centre A) */
+    for (int cap = 0; cap < 2; ++cap) {
+        const double *c = cap == 0 ? Bp : A;
+        double sg = cap == 0 ? 1.0 : -1.0;
+        double v[3];
+        for (int a = 0; a < 3; ++a) v[a] = r * (p[a] - c[a]) + b2 * n[a];
+        double nv = sqrt(dot3(v, v));
+        if (!(nv > 1e-300)) continue;
+        for (int a = 0; a < 3; ++a) v[a] /= nv;
+        if (sg * dot3(v, ax) < 0) continue;
+        double x[3], cost = 0;
+        for (int a = 0; a < 3; ++a) {
+            x[a] = c[a] + r * v[a];
+            cost += (x[a] - p[a]) * (x[a] - p[a]) + b2 * (v[a] - n[a]) * (v[a] - n[a]);
+        }
+        if (cost < best) {
+            best = cost;
+            memcpy(pt, x, sizeof x);
+            memcpy(nt, v, sizeof v);
+        }
+    }
+}
+
+/* Position Jacobian (3 x d_f, row-major) of a point x fixed to link `link`
+ * of finger f (Eq. 8 in the base frame): column t is z_j x (x - o_j) for the
+ * finger's joint j = first + t on the chain up to `link`, else zero.  T holds
+ * the finger's link frames.                                                  */
+void orc_point_jacobian(const orc_hand *H, int f, int link, const double *T, const double *x,
+                        double *Jm)
+{
+    const int j0 = finger_first_joint(H, f), d = finger_dof(H, f);
+    for (int i = 0; i < 3 * d; ++i) Jm[i] = 0.0;
+    for (int t = 0; t < d; ++t) {
+        int j = j0 + t;
+        if (j > link) break;
+        const double *Tj = T + 12 * j;
+        double o[3] = {Tj[3], Tj[7], Tj[11]};
+        double al[3] = {H->joint_axis[3 * j], H->joint_axis[3 * j + 1], H->joint_axis[3 * j + 2]};
+        double z[3];
+        tf_dir(Tj, al, z);
+        double v[3] = {x[0] - o[0], x[1] - o[1], x[2] - o[2]};
+        Jm[0 * d + t] = z[1] * v[2] - z[2] * v[1];
+        Jm[1 * d + t] = z[2] * v[0] - z[0] * v[2];
+        Jm[2 * d + t] = z[0] * v[1] - z[1] * v[0];
+    }
+}
+
+static int cholesky_solve(int n, double *A, double *b)
+{
+    for (int j = 0; j < n; ++j) {
+        double s = A[j * n + j];
+        for (int k = 0; k < j; ++k) s -= A[j * n + k] * A[j * n + k];
+        if (s <= 0) return -1;
+        double d = sqrt(s);
+        A[j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            double t = A[i * n + j];
+            for (int k = 0; k < j; ++k) t -= A[i * n + k] * A[j * n + k];
+            A[i * n + j] = t / d;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        double t = b[i];
+        for (int k = 0; k < i; ++k) t -= A[i * n + k] * b[k];
+        b[i] = t / A[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double t = b[i];
+        for (int k = i + 1; k < n; ++k) t -= A[k * n + i] * b[k];
+        b[i] = t / A[i * n + i];
+    }
+    return 0;
+}
+
+typedef struct {
+    int32_t iters;     /* total DLS iterations */
+    int32_t phase1;    /* leading iterations with the contact point fixed to the link */
+    double lambda;
+    double beta;
+    double tol_pos;
+    double tol_ang;
+    double margin;
+} orc_ik_params;
+
+/* One finger's IK towards one contact.  q_f in/out (finger joints).       */
+void orc_ik_finger(const orc_hand *H, int f, int link, const double *p, const double *n,
+                   const orc_ik_params *ik, double *q_f, double *err, double *ang,
+                   double *pt_out, double *nt_out)
+{
+    const int J = H->n_joints, j0 = finger_first_joint(H, f), d = finger_dof(H, f);
+    double *T = (double *)malloc(sizeof(double) * 12 * J);
+    double pt[3], nt[3], loc_p[3] = {0, 0, 0}, loc_n[3] = {0, 0, 1};
+    for (int it = 0; it < ik->iters; ++it) {
+        orc_fk_finger(H, f, q_f, T);
+        const double *Tl = T + 12 * link;
+        double A[3], Bp[3], r;
+        capsule_world(H, T, link, A, Bp, &r);
+        if (it >= ik->phase1 || it == 0) {
+            capsule_aligned_point(A, Bp, r, p, n, ik->beta, pt, nt);
+            /* link-frame copy: R^T (x - t), R^T n */
+            double dx[3] = {pt[0] - Tl[3], pt[1] - Tl[7], pt[2] - Tl[11]};
+            for (int a = 0; a < 3; ++a) {
+                loc_p[a] = Tl[a] * dx[0] + Tl[4 + a] * dx[1] + Tl[8 + a] * dx[2];
+                loc_n[a] = Tl[a] * nt[0] + Tl[4 + a] * nt[1] + Tl[8 + a] * nt[2];
+            }
+        } else {
+            tf_point(Tl, loc_p, pt);
+            tf_dir(Tl, loc_n, nt);
+        }
+        double x2[3], e[6];
+        for (int a = 0; a < 3; ++a) {
+            x2[a] = pt[a] + ik->beta * nt[a];
+            e[a] = p[a] - pt[a];
+            e[3 + a] = (p[a] + ik->beta * n[a]) - x2[a];
+        }
+        double Jm[6 * 16];
+        orc_point_jacobian(H, f, link, T, pt, Jm);
+        orc_point_jacobian(H, f, link, T, x2, Jm + 3 * d);
+        double M[16 * 16], g[16];
+        for (int a = 0; a < d; ++a) {
+            g[a] = 0.0;
+            for (int rr = 0; rr < 6; ++rr) g[a] += Jm[rr * d + a] * e[rr];
+            for (int b = 0; b < d; ++b) {
+                double s = 0.0;
+                for (int rr = 0; rr < 6; ++rr) s += Jm[rr * d + a] * Jm[rr * d + b];
+                M[a * d + b] = s + (a == b ? ik->lambda : 0.0);
+            }
+        }
+        if (cholesky_solve(d, M, g) != 0) break;
+        for (int t = 0; t < d; ++t) {
+            double lo = H->limits[2 * (j0 + t)], hi = H->limits[2 * (j0 + t) + 1];
+            double v = q_f[t] + g[t];
+            q_f[t] = v < lo ? lo : (v > hi ? hi : v);
+        }
+    }
+    orc_fk_finger(H, f, q_f, T);
+    {
+        double A[3], Bp[3], r;
+        capsule_world(H, T, link, A, Bp, &r);
+        capsule_project(A, Bp, r, p, pt, nt);
+    }
+    double dx[3] = {p[0] - pt[0], p[1] - pt[1], p[2] - pt[2]};
+    *err = sqrt(dot3(dx, dx));
+    double c = dot3(nt, n);
+    if (c > 1) c = 1;
+    if (c < -1) c = -1;
+    *ang = acos(c);
+    if (pt_out) memcpy(pt_out, pt, sizeof pt);
+    if (nt_out) memcpy(nt_out, nt, sizeof nt);
+    free(T);
+}
+
+/* Object SDF on a G^3 node grid (object frame), trilinear interpolation,
+ * +inf outside the grid.                                                    */
+typedef struct {
+    double origin[3];
+    double h;
+    int32_t dims;
+    const float *values; /* [G][G][G] as [iz][iy][ix] */
+} orc_sdf;
+
+double orc_sdf_eval(const orc_sdf *S, const double *y)
+{
+    const int G = S->dims;
+    double u[3];
+    int i0[3];
+    for (int a = 0; a < 3; ++a) {
+        u[a] = (y[a] - S->origin[a]) / S->h;
+        if (!(u[a] >= 0.0 && u[a] <= (double)(G - 1))) return INFINITY;
+        int i = (int)floor(u[a]);
+        if (i > G - 2) i = G - 2;
+        if (i < 0) i = 0;
+        i0[a] = i;
+        u[a] -= i;
+    }
+    double acc = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                double w = (dx ? u[0] : 1 - u[0]) * (dy ? u[1] : 1 - u[1]) * (dz ? u[2] : 1 - u[2]);
+                int64_t idx = ((int64_t)(i0[2] + dz) * G + (i0[1] + dy)) * G + (i0[0] + dx);
+                acc += w * S->values[idx];
+            }
+    return acc;
+}
+
+/* number of axis samples of a capsule: one per millimetre of axis, ends included */
+int orc_axis_samples(const orc_hand *H, int l)
+{
+    const float *c = H->capsule + 7 * l;
+    double dx = (double)c[3] - c[0], dy = (double)c[4] - c[1], dz = (double)c[5] - c[2];
+    double L = sqrt((dx * dx + dy * dy) + dz * dz);
+    return (int)ceil(L / 1e-3) + 1;
+}
+
+/* Penetration of the hand's capsules into the object (Sec. 3.2 criterion 1
+ * with a margin; the capsule axis samples are tested against the object's
+ * SDF): depth = max over links and axis samples of (r - SDF(x)).            */
+double orc_penetration(const orc_hand *H, const double *T, const orc_sdf *S, const float *pose)
+{
+    double P[12];
+    tf_load(pose, P);
+    double depth = -INFINITY;
+    for (int l = 0; l < H->n_joints; ++l) {
+        double A[3], Bp[3], r;
+        capsule_world(H, T, l, A, Bp, &r);
+        int M = orc_axis_samples(H, l);
+        for (int s = 0; s < M; ++s) {
+            double t = (double)s / (double)(M - 1);
+            double x[3], d[3], y[3];
+            for (int a = 0; a < 3; ++a) {
+                x[a] = A[a] + t * (Bp[a] - A[a]);
+                d[a] = x[a] - P[4 * a + 3];
+            }
+            /* object frame: y = R^T (x - t) */
+            for (int a = 0; a < 3; ++a) y[a] = P[a] * d[0] + P[4 + a] * d[1] + P[8 + a] * d[2];
+            double v = r - orc_sdf_eval(S, y);
+            if (v > depth) depth = v;
+        }
+    }
+    return depth;
+}
+
+/* Realise accepted sets: witness seed, IK per finger, penetration, acceptance.
+ * wit [L][G^3][B] may be NULL (then q0 = mid-limits).                        */
+int orc_realize(const orc_hand *H, const orc_field_params *fp, const int32_t *wit,
+                const orc_sdf *S, const float *pts, const float *nrm, const float *poses,
+                const int32_t *set_pt, const int32_t *set_link, int32_t k, int32_t draws,
+                const int32_t *acc_list, int32_t n_acc, const orc_ik_params *ik,
+                double *q_out /*[n_acc][J]*/, double *q0_out /*[n_acc][J] opt*/,
+                double *contact_err /*[n_acc][k]*/, double *contact_ang /*[n_acc][k]*/,
+                double *depth, uint8_t *valid, uint8_t *rflag)
+{
+    const int J = H->n_joints, F = H->n_fingers, G = fp->grid, B = fp->bins;
+    const int64_t G3 = (int64_t)G * G * G;
+    if (k != F || draws <= 0) return ORC_EINVAL;
+    double cb[3 * 64];
+    orc_bin_centers(B, cb);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int a = 0; a < n_acc; ++a) {
+        const int64_t sid = acc_list[a]; /* set id g*D + d */
+        const int64_t g = sid / draws;
+        const float *pose = poses + 12 * g;
+        double Tp[12];
+        tf_load(pose, Tp);
+        double *q = q_out + (int64_t)a * J;
+        double q0[64];
+        int fl = 0;
+        double worst_err = 0, worst_ang = 0;
+        for (int i = 0; i < k; ++i) {
+            const int f = i, l = set_link[sid * k + i], idx = set_pt[sid * k + i];
+            const int j0 = finger_first_joint(H, f), d = finger_dof(H, f);
+            double pl[3] = {pts[3 * idx], pts[3 * idx + 1], pts[3 * idx + 2]};
+            double nl[3] = {nrm[3 * idx], nrm[3 * idx + 1], nrm[3 * idx + 2]};
+            double p[3], nu[3], n[3];
+            tf_point(Tp, pl, p);
+            tf_dir(Tp, nl, nu);
+            for (int c = 0; c < 3; ++c) n[c] = -nu[c];
+            /* reverse lookup: witness sample of (l, voxel(p), bin(n)) */
+            int32_t w = -1;
+            if (wit) {
+                double u[3];
+                int in = voxel_coords(fp, f, p, u);
+                int b = bin_of(B, cb, n, NULL, NULL);
+                if (in) {
+                    int64_t v = ((int64_t)(int)floor(u[2]) * G + (int)floor(u[1])) * G + (int)floor(u[0]);
+                    w = wit[((int64_t)l * G3 + v) * B + b];
+                }
+            }
+            if (w >= 0) {
+                orc_joint_sample(H, fp->seed, f, w, q + j0);
+            } else {
+                for (int t = 0; t < d; ++t)
+                    q[j0 + t] = 0.5 * ((double)H->limits[2 * (j0 + t)] + H->limits[2 * (j0 + t) + 1]);
+            }
+            for (int t = 0; t < d; ++t) q0[j0 + t] = q[j0 + t];
+            double err, ang;
+            orc_ik_finger(H, f, l, p, n, ik, q + j0, &err, &ang, NULL, NULL);
+            contact_err[(int64_t)a * k + i] = err;
+            contact_ang[(int64_t)a * k + i] = ang;
+            fl |= fabs(err - ik->tol_pos) <= BAND_VAL;
+            fl |= fabs(ang - ik->tol_ang) <= BAND_VAL;
+            if (err > worst_err) worst_err = err;
+            if (ang > worst_ang) worst_ang = ang;
+        }
+        if (q0_out) memcpy(q0_out + (int64_t)a * J, q0, sizeof(double) * J);
+        double *T = (double *)malloc(sizeof(double) * 12 * J);
+        orc_fk(H, q, T);
+        double dp = orc_penetration(H, T, S, pose);
+        free(T);
+        depth[a] = dp;
+        fl |= fabs(dp - ik->margin) <= BAND_VAL;
+        valid[a] = worst_err <= ik->tol_pos && worst_ang <= ik->tol_ang && dp <= ik->margin;
+        if (rflag) rflag[a] = (uint8_t)fl;
+    }
+    return ORC_OK;
+}
