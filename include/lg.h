@@ -1,0 +1,237 @@
+/*
+ * lg.h -- C ABI of the MI355X (gfx950) Contact-Field library.
+ *
+ * The library implements the data-parallel hot path of Lightning Grasp
+ * (Yin & Abbeel, arXiv 2511.07418): a sampled contact field of a hand
+ * (Sec. 4, Alg. 1, Sec. 4.4), contact-domain queries of an object under many
+ * palm poses (Sec. 4.3, Sec. 5.3), seeded contact-set draws scored by a
+ * force-closure criterion (Eq. 1-2, Sec. 5.3-5.4), and the realisation of
+ * accepted sets by damped-least-squares IK (Sec. 5.5, Eq. 7-8) followed by a
+ * penetration check (Sec. 3.2).  The four calls follow the paper's problem
+ * statement: hand in (build), object + poses in (query), sets out (search),
+ * grasps (P, q) out (realize).
+ *
+ * Conventions for every call:
+ *  - Pointers are DEVICE pointers (HIP, on the current device) unless the
+ *    comment says "host".  The caller owns every buffer it passes; the
+ *    library owns only the lg_field it returns from lg_build_field /
+ *    lg_field_import, which stays resident in HBM until lg_field_release.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *    asynchronously; arguments are validated synchronously before anything is
+ *    enqueued, so an LG_EINVAL return leaves all outputs untouched.
+ *  - Every call returns an lg_status; no C++ exception crosses the ABI.
+ *    lg_last_error() gives a thread-local human-readable detail of the last
+ *    failure.  Asynchronous device faults surface at the caller's next
+ *    synchronisation of the stream.
+ *  - Sizes are int32 (N, P < 2^31); counts of sets are P*D < 2^31.
+ *  - Units are SI (m, rad).  Rigid transforms are 3x4 row-major [R | t]
+ *    (12 floats) mapping local to parent coordinates.
+ */
+#ifndef LG_H
+#define LG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lg_status;
+#define LG_OK 0
+#define LG_EINVAL (-1)       /* invalid argument (nothing enqueued) */
+#define LG_ENOMEM (-2)       /* device allocation failed */
+#define LG_EDEVICE (-3)      /* HIP runtime error */
+#define LG_EUNSUPPORTED (-5) /* valid but unsupported configuration */
+#define LG_EINTERNAL (-6)
+
+/* Name of a status code (static string). */
+const char *lg_status_str(lg_status s);
+/* Detail of the last failing call on this thread (static per-thread buffer). */
+const char *lg_last_error(void);
+/* Library version string. */
+const char *lg_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Hand: H = (H_M, C, F) of Sec. 3.1 as a capsule-chain hand.                */
+/* One link (capsule) per revolute joint.  Joints are grouped by finger; a    */
+/* finger is a dependency group of Sec. 5.3 (a connected component of the     */
+/* kinematic tree without static links) and must be a serial chain stored     */
+/* contiguously: joint_parent[j] is -1 (hand base) for the first joint of a   */
+/* finger and j-1 otherwise.  Frame of joint j:                               */
+/*   T_j = T_parent * joint_origin_j * Rot(joint_axis_j, q_j).                */
+/* All arrays are HOST memory and are copied by the library.                  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_fingers;            /* F, 1..8 */
+    int32_t n_joints;             /* J = number of links, <= 64, <= 8 per finger */
+    const int32_t *joint_finger;  /* host [J] finger of each joint */
+    const int32_t *joint_parent;  /* host [J] -1 or j-1 */
+    const float *joint_origin;    /* host [J][12] parent -> joint at q = 0 */
+    const float *joint_axis;      /* host [J][3] unit axis in the joint frame */
+    const float *capsule;         /* host [J][7] a(3), b(3), radius, link frame */
+    const float *limits;          /* host [J][2] lo, hi */
+    int32_t n_surf;               /* surface samples per link (patch points) */
+    const float *surf;            /* host [J][n_surf][6] link-frame point, outward normal */
+} lg_hand_desc;
+
+/* Field construction parameters (Sec. 4.3, Alg. 1 as a dense grid cover). */
+typedef struct {
+    int64_t samples;          /* S joint samples per finger, 1..2^31-1 */
+    uint64_t seed;            /* Philox4x32-10 key (low word, high word) */
+    int32_t grid;             /* G: each finger's window has G^3 voxels, 4..128 */
+    float h;                  /* voxel edge (m) */
+    int32_t bins;             /* B normal bins: 32 or 64 (spherical Fibonacci lattice) */
+    const float *grid_frame;  /* host [F][12] [R | o]: voxel coords u = R^T (x - o) / h */
+    int32_t keep_witness;     /* 1: keep the smallest sample id per (link, voxel, bin) */
+} lg_field_params;
+
+typedef struct lg_field lg_field;
+
+typedef struct {
+    int32_t n_fingers, n_joints, grid, bins;
+    int64_t samples;
+    uint64_t device_bytes;    /* HBM held by the field */
+    uint64_t bits_set;        /* set bits over all per-link tables */
+    int64_t vectors;          /* contact vectors generated (S * sum_l n_surf) */
+    int64_t dropped;          /* vectors outside their finger's window */
+    int32_t has_witness;
+} lg_field_info_t;
+
+/*
+ * lg_build_field -- sample the contact field of a hand (Sec. 4.3-4.4).
+ * For every finger f and sample s: q = lo + (hi - lo) u with u from Philox
+ * block (s, 8f + t/4, 1, 0) word t%4 (t = joint index within the finger),
+ * u = (word >> 8) 2^-24; forward kinematics; every surface sample (p, n) of
+ * every link l of f gives a contact vector x = T_l p, nu = R_l n that sets
+ * bit bin(nu) of voxel floor(R_f^T (x - o_f) / h) in link l's table (vectors
+ * outside the window are dropped and counted); bin(nu) = argmax_b <nu, c_b>
+ * over the Fibonacci lattice c_b = (sqrt(1-z^2) cos phi, sqrt(1-z^2) sin phi,
+ * z), z = 1 - (2b+1)/B, phi = b pi (3 - sqrt 5), ties to the lowest b.
+ * The call blocks until the field is built (it returns a usable handle).
+ * Errors: LG_EINVAL (bad sizes, non-chain hand, B not 32/64), LG_ENOMEM.
+ */
+lg_status lg_build_field(const lg_hand_desc *hand, const lg_field_params *params, void *stream,
+                         lg_field **out);
+
+/* Build a field from canonical host tables instead of sampling:
+ * bits_host [J][G^3][B/32] (voxel v = (iz G + iy) G + ix, bit b of word b/32 is
+ * bin b), witness_host [J][G^3][B] (-1 = none) or NULL.  Used to run the
+ * query/search/realize stages on an externally computed field. */
+lg_status lg_field_import(const lg_hand_desc *hand, const lg_field_params *params,
+                          const uint32_t *bits_host, const int32_t *witness_host,
+                          lg_field **out);
+
+/* Copy the per-link tables to host memory in the canonical layout above
+ * (witness_host may be NULL; -1 marks cells without a witness).  Blocking. */
+lg_status lg_field_export(const lg_field *field, uint32_t *bits_host, int32_t *witness_host);
+
+lg_status lg_field_info(const lg_field *field, lg_field_info_t *info);
+
+/* Free the field's device memory (NULL is a no-op). */
+lg_status lg_field_release(lg_field *field);
+
+/*
+ * lg_query_domains -- contact domains of an object under P poses
+ * (Sec. 4.2-4.3, Def. 4.3, Sec. 5.3).
+ * pts, nrm: device [3][N] float (structure of arrays, object frame, outward
+ *           unit normals).
+ * poses:    device [P][12] object pose in the hand frame.
+ * For pose g, point i: x = R p + t, query normal -R n (the contact surface
+ * representation negates the normal); finger f's domain bit is the OR over
+ * its links of the table bit at (voxel_f(x), bin(-R n)), 0 outside the window.
+ * dom_bits:  device [P][F][ceil(N/32)] uint32, bit i%32 of word i/32 = point i
+ *            (bits past N are zero).
+ * dom_count: device [P][F] uint32, set bits per (pose, finger).
+ * Errors: LG_EINVAL on null pointers or negative sizes.  N = 0 or P = 0 is a
+ * valid no-op (counts are still written for P > 0).
+ */
+lg_status lg_query_domains(const lg_field *field, const float *pts, const float *nrm,
+                           int32_t n_points, const float *poses, int32_t n_poses,
+                           uint32_t *dom_bits, uint32_t *dom_count, void *stream);
+
+/* Search parameters (Sec. 5.3 draws, Eq. 1-2 criterion). */
+typedef struct {
+    int32_t draws;        /* D sets per pose */
+    int32_t k;            /* contacts per set; must equal the number of fingers */
+    int32_t m_edges;      /* linearised cone edges, 3..16; k*m_edges <= 52 */
+    int32_t max_pivots;   /* simplex pivot cap (status UNDECIDED when hit) */
+    float mu;             /* friction coefficient >= 0 */
+    float eps;            /* stability threshold on t* */
+    float moment_scale;   /* rho > 0: moment rows are divided by rho */
+    uint64_t seed;        /* Philox key */
+    uint32_t request_id;  /* 4th Philox counter word */
+    int64_t pose_offset;  /* global index of pose 0 (RNG counters use it) */
+} lg_search_params;
+
+/* Bytes of device workspace lg_search needs for n_poses poses. */
+size_t lg_search_workspace_bytes(int32_t n_poses, const lg_search_params *params);
+
+/*
+ * lg_search -- seeded contact-set draws, force-closure verdicts, compaction.
+ * Draw d of pose g uses Philox blocks (g + pose_offset, 4d + blk, 3,
+ * request_id), blk = 0, 1, ...: word i picks the point of contact i (finger i)
+ * as the floor(w * count / 2^32)-th set bit of the domain; word k+i picks one
+ * of the finger's links whose own table is hit at that point (reverse lookup
+ * of Sec. 5.5).  A pose with an empty domain gives set_pt = -1, set_link = -1.
+ * Verdict (object frame): wrench columns w_ie = [d_ie; p_i x d_ie / rho],
+ * d_ie = -n_i + mu (cos(2 pi e/m) x_i + sin(2 pi e/m) y_i) with the Duff et
+ * al. (2017) tangent basis; t* = min sum_r |(W g)_r| over g >= 0, sum g = 1
+ * (double-precision Phase-1 simplex, Bland's rule); verdict = t* <= eps.
+ * Outputs (device): set_pt [P][D][k] int32, set_link [P][D][k] int8 (global
+ * joint/link index), verdict [P][D] uint8, tstar [P][D] double (NaN for
+ * invalid sets), acc_list [P*D] int32 accepted set ids g*D + d in increasing
+ * order, n_acc [1] int32.  workspace: device, lg_search_workspace_bytes().
+ */
+lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, int32_t n_points,
+                    const float *poses, int32_t n_poses, const uint32_t *dom_bits,
+                    const uint32_t *dom_count, const lg_search_params *params, int32_t *set_pt,
+                    int8_t *set_link, uint8_t *verdict, double *tstar, int32_t *acc_list,
+                    int32_t *n_acc, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Kinematics optimisation parameters (Sec. 5.5). */
+typedef struct {
+    int32_t iters;    /* DLS iterations (Eq. 7) */
+    int32_t phase1;   /* leading iterations with the hand contact point fixed to the link */
+    float lambda;     /* damping */
+    float beta;       /* normal offset of the second matched point (m) */
+    float tol_pos;    /* acceptance: contact error <= tol_pos (m) */
+    float tol_ang;    /* acceptance: normal angle <= tol_ang (rad) */
+    float margin;     /* acceptance: penetration depth <= margin (m) */
+} lg_ik_params;
+
+/* Object signed-distance grid (object frame). */
+typedef struct {
+    float origin[3];      /* position of node (0,0,0) */
+    float h;              /* node spacing */
+    int32_t dims;         /* G nodes per axis, >= 2 */
+    const float *values;  /* device [G][G][G] as [iz][iy][ix] */
+} lg_sdf;
+
+/*
+ * lg_realize -- turn accepted sets into grasps (P, q) (Sec. 5.5, Sec. 3.2).
+ * For accepted set a (id = acc_list[a], pose g = id / draws), contact i on
+ * finger i and link set_link[id][i]: q0 of the finger is the field's witness
+ * joint sample of (link, voxel(p), bin(n)) (mid-limits without witness);
+ * `iters` DLS steps (Eq. 7-8) match the hand contact point -- the capsule
+ * point closest to (p, n) in |x-p|^2 + beta^2 |n~-n|^2, held fixed for
+ * `phase1` steps then re-selected -- and its beta-offset to p and p + beta n;
+ * q is clamped to the limits.  Then every link's capsule axis (one sample per
+ * mm, ends included) is tested against the trilinear SDF (+inf outside the
+ * grid): depth = max (radius - SDF).  valid = all contact errors <= tol_pos,
+ * all normal angles <= tol_ang, depth <= margin.
+ * n_acc_dev: device [1] number of accepted sets (<= max_acc); entries past it
+ * are not written.  Outputs (device, max_acc rows): q_out [J] float,
+ * contact_err [k] float, contact_ang [k] float, depth float, valid uint8.
+ */
+lg_status lg_realize(const lg_field *field, const lg_sdf *sdf, const float *pts, const float *nrm,
+                     int32_t n_points, const float *poses, int32_t n_poses,
+                     const int32_t *set_pt, const int8_t *set_link, int32_t k, int32_t draws,
+                     const int32_t *acc_list, const int32_t *n_acc_dev, int32_t max_acc,
+                     const lg_ik_params *params, float *q_out, float *contact_err,
+                     float *contact_ang, float *depth, uint8_t *valid, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LG_H */

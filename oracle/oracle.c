@@ -657,10 +657,75 @@ void orc_wrench_matrix(int k, const double *p, const double *n, double mu, int m
     }
 }
 
-#define LP_TOL 1e-12
+#define LP_TOL 1e-12   /* reduced-cost and ratio-tie tolerance */
+#define LP_PIV 1e-9    /* smallest admissible pivot element */
+
+/* column j of the constraint matrix [W^T -I I; 1 0 0] (7 rows) */
+static void lp_column(int n, const double *W, int j, double *a)
+{
+    for (int r = 0; r < 7; ++r) a[r] = 0.0;
+    if (j < n) {
+        for (int r = 0; r < 6; ++r) a[r] = W[6 * j + r];
+        a[6] = 1.0;
+    } else if (j < n + 6) {
+        a[j - n] = -1.0;
+    } else {
+        a[j - n - 6] = 1.0;
+    }
+}
+
+/* Rebuild the tableau B^-1 [A | b] of `basis` from the original columns
+ * (Gauss-Jordan with partial pivoting).  Returns -1 if B is singular.       */
+static int lp_reinvert(int n, const double *W, const int *basis, double *T)
+{
+    const int nv = n + 12;
+    double M[7][14];
+    for (int r = 0; r < 7; ++r) {
+        double a[7];
+        lp_column(n, W, basis[r], a);
+        for (int i = 0; i < 7; ++i) M[i][r] = a[i];
+        for (int i = 0; i < 7; ++i) M[r][7 + i] = 0.0;
+    }
+    for (int r = 0; r < 7; ++r) M[r][7 + r] = 1.0;
+    for (int c = 0; c < 7; ++c) {
+        int p = c;
+        for (int r = c + 1; r < 7; ++r)
+            if (fabs(M[r][c]) > fabs(M[p][c])) p = r;
+        if (fabs(M[p][c]) < 1e-300) return -1;
+        if (p != c)
+            for (int i = 0; i < 14; ++i) {
+                double t = M[c][i];
+                M[c][i] = M[p][i];
+                M[p][i] = t;
+            }
+        double pv = M[c][c];
+        for (int i = 0; i < 14; ++i) M[c][i] /= pv;
+        for (int r = 0; r < 7; ++r) {
+            if (r == c || M[r][c] == 0.0) continue;
+            double f = M[r][c];
+            for (int i = 0; i < 14; ++i) M[r][i] -= f * M[c][i];
+        }
+    }
+    /* T_j = B^-1 A_j; rhs = B^-1 e_6 (row r of the tableau belongs to basis[r]) */
+    for (int j = 0; j < nv; ++j) {
+        double a[7];
+        lp_column(n, W, j, a);
+        for (int r = 0; r < 7; ++r) {
+            double s = 0.0;
+            for (int i = 0; i < 7; ++i) s += M[r][7 + i] * a[i];
+            T[r * (nv + 1) + j] = s;
+        }
+    }
+    for (int r = 0; r < 7; ++r) T[r * (nv + 1) + nv] = M[r][7 + 6];
+    return 0;
+}
 
 /* Phase-1 LP on n columns (6 numbers each).  Variables: g_0..g_{n-1},
- * s+_0..s+_5, s-_0..s-_5 (column index order used by Bland's rule).          */
+ * s+_0..s+_5, s-_0..s-_5 (column index order used by Bland's rule).  When
+ * no reduced cost is negative the tableau is rebuilt from the original
+ * columns of the final basis and optimality is checked again, so rounding
+ * accumulated over long degenerate pivot sequences cannot end the search
+ * early or bias t*.                                                          */
 double orc_lp_solve(int n, const double *W, int max_pivots, int *status, int *pivots)
 {
     const int nv = n + 12, rows = 7;
@@ -693,7 +758,7 @@ double orc_lp_solve(int n, const double *W, int max_pivots, int *status, int *pi
         }
     }
     basis[6] = 0;
-    int piv = 0, st = 0;
+    int piv = 0, st = 0, checks = 0;
     for (;;) {
         /* reduced costs d_j = c_j - c_B^T T_j */
         for (int j = 0; j < nv; ++j) {
@@ -705,12 +770,25 @@ double orc_lp_solve(int n, const double *W, int max_pivots, int *status, int *pi
         int e = -1;
         for (int j = 0; j < nv; ++j)
             if (red[j] < -LP_TOL) { e = j; break; }
-        if (e < 0) break;
+        if (e < 0) {
+            /* candidate optimum: verify on a freshly inverted basis */
+            if (checks >= 4 || lp_reinvert(n, W, basis, T) != 0) break;
+            ++checks;
+            int again = 0;
+            for (int j = 0; j < nv && !again; ++j) {
+                double z = 0.0;
+                for (int r = 0; r < rows; ++r)
+                    if (basis[r] >= n) z += TA(r, j);
+                if ((j >= n ? 1.0 : 0.0) - z < -LP_TOL) again = 1;
+            }
+            if (!again) break;
+            continue;
+        }
         if (piv >= max_pivots) { st = 1; break; }
         int lr = -1;
         double best = 0.0;
         for (int r = 0; r < rows; ++r) {
-            if (TA(r, e) > LP_TOL) {
+            if (TA(r, e) > LP_PIV) {
                 double ratio = TA(r, nv) / TA(r, e);
                 if (lr < 0 || ratio < best - LP_TOL * (1.0 + fabs(best)) ||
                     (fabs(ratio - best) <= LP_TOL * (1.0 + fabs(best)) && basis[r] < basis[lr])) {

@@ -1,0 +1,245 @@
+// Internal declarations of the gfx950 Contact-Field library: the field
+// object, the device-side hand description and the device helpers shared by
+// the kernels.  Arithmetic that decides a discrete outcome (voxel, normal
+// bin) is written with explicit fmaf chains so that every kernel that
+// evaluates it (query, draw, realize) gets bit-identical results.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lg.h"
+
+namespace lg {
+
+constexpr int kMaxFingers = 8;
+constexpr int kMaxJoints = 64;
+constexpr int kMaxDof = 8;
+constexpr int kMaxBins = 64;
+constexpr uint32_t kPurposeJoint = 1u;
+constexpr uint32_t kPurposeDraw = 3u;
+constexpr int32_t kNoWitness = 0x7fffffff;
+
+// Device-side description of a hand and its field window (kernel argument).
+struct DevHand {
+    int F, J, G, B, W;   // W = 32-bit words per voxel (B / 32)
+    int nsurf;
+    float h, inv_h;
+    uint32_t seed_lo, seed_hi;
+    int64_t samples;
+    const float *origin;      // [J][12]
+    const float *axis;        // [J][3]
+    const float *capsule;     // [J][7]
+    const float *limits;      // [J][2]
+    const float *surf;        // [J][nsurf][6]
+    const float *grid_frame;  // [F][12]
+    const float *bin_c;       // [B][3]
+    const int32_t *axis_samples;  // [J]
+    int finger_first[kMaxFingers];
+    int finger_dof[kMaxFingers];
+};
+
+}  // namespace lg
+
+// The opaque handle of the C ABI.
+struct lg_field {
+    lg::DevHand dh;
+    int device;
+    int max_dof;
+    bool has_witness;
+    int64_t vectors, dropped;
+    uint64_t bits_set;
+    uint64_t device_bytes;
+    // host copies
+    std::vector<int32_t> joint_finger, joint_parent, axis_samples;
+    std::vector<float> origin, axis, capsule, limits, surf, grid_frame, bin_c;
+    // device allocations
+    float *d_params = nullptr;     // packed float arrays (origin..bin_c)
+    int32_t *d_axis_samples = nullptr;
+    uint32_t *d_bits = nullptr;    // per-link tables [J][G^3][W]
+    uint32_t *d_merged = nullptr;  // per-finger OR of its links [F][G^3][W]
+    int32_t *d_wit = nullptr;      // [J][G^3][B], kNoWitness = none
+};
+
+namespace lg {
+
+// ---- error reporting -------------------------------------------------------
+lg_status fail(lg_status s, const std::string &msg);
+lg_status hip_fail(hipError_t e, const char *what);
+#define LG_HIP(call)                                   \
+    do {                                               \
+        hipError_t _e = (call);                        \
+        if (_e != hipSuccess) return lg::hip_fail(_e, #call); \
+    } while (0)
+
+lg_status validate_hand(const lg_hand_desc *hand, const lg_field_params *p);
+lg_status make_field_shell(const lg_hand_desc *hand, const lg_field_params *p, lg_field **out);
+void free_field(lg_field *f);
+
+// ---- Philox4x32-10 (Salmon et al., SC'11) -----------------------------------
+__host__ __device__ inline void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1, uint32_t out[4])
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t m1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)m1;
+        c3 = (uint32_t)m0;
+        c0 = n0;
+        c2 = n2;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+__device__ inline float u01f(uint32_t w) { return (float)(w >> 8) * (1.0f / 16777216.0f); }
+
+// Joint t of finger f for joint sample s (q = lo + (hi - lo) u).
+__device__ inline float joint_sample(const DevHand &H, int f, uint32_t s, int t)
+{
+    uint32_t w[4];
+    philox4x32_10(s, (uint32_t)(8 * f + t / 4), kPurposeJoint, 0u, H.seed_lo, H.seed_hi, w);
+    const int j = H.finger_first[f] + t;
+    const float lo = H.limits[2 * j], hi = H.limits[2 * j + 1];
+    return fmaf(hi - lo, u01f(w[t & 3]), lo);
+}
+
+// ---- rigid transforms (3x4 row-major) -------------------------------------
+struct Tf {
+    float m[12];
+};
+
+__device__ inline Tf tf_load(const float *p)
+{
+    Tf t;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) t.m[i] = p[i];
+    return t;
+}
+
+__device__ inline Tf tf_mul(const Tf &A, const Tf &B)
+{
+    Tf C;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            C.m[4 * i + j] = fmaf(A.m[4 * i], B.m[j], fmaf(A.m[4 * i + 1], B.m[4 + j], A.m[4 * i + 2] * B.m[8 + j]));
+        C.m[4 * i + 3] = fmaf(A.m[4 * i], B.m[3], fmaf(A.m[4 * i + 1], B.m[7], fmaf(A.m[4 * i + 2], B.m[11], A.m[4 * i + 3])));
+    }
+    return C;
+}
+
+// rotation by angle q about unit axis a (Rodrigues)
+__device__ inline Tf tf_axis_angle(float ax, float ay, float az, float q)
+{
+    float s, c;
+    sincosf(q, &s, &c);
+    const float v = 1.0f - c;
+    Tf T;
+    T.m[0] = fmaf(ax * ax, v, c);      T.m[1] = fmaf(ax * ay, v, -az * s); T.m[2] = fmaf(ax * az, v, ay * s);  T.m[3] = 0.f;
+    T.m[4] = fmaf(ay * ax, v, az * s); T.m[5] = fmaf(ay * ay, v, c);      T.m[6] = fmaf(ay * az, v, -ax * s); T.m[7] = 0.f;
+    T.m[8] = fmaf(az * ax, v, -ay * s); T.m[9] = fmaf(az * ay, v, ax * s); T.m[10] = fmaf(az * az, v, c);     T.m[11] = 0.f;
+    return T;
+}
+
+__device__ inline void tf_point(const Tf &T, float px, float py, float pz, float &x, float &y, float &z)
+{
+    x = fmaf(T.m[0], px, fmaf(T.m[1], py, fmaf(T.m[2], pz, T.m[3])));
+    y = fmaf(T.m[4], px, fmaf(T.m[5], py, fmaf(T.m[6], pz, T.m[7])));
+    z = fmaf(T.m[8], px, fmaf(T.m[9], py, fmaf(T.m[10], pz, T.m[11])));
+}
+
+__device__ inline void tf_dir(const Tf &T, float px, float py, float pz, float &x, float &y, float &z)
+{
+    x = fmaf(T.m[0], px, fmaf(T.m[1], py, T.m[2] * pz));
+    y = fmaf(T.m[4], px, fmaf(T.m[5], py, T.m[6] * pz));
+    z = fmaf(T.m[8], px, fmaf(T.m[9], py, T.m[10] * pz));
+}
+
+// Frame of joint j given its parent frame P and joint value q.
+__device__ inline Tf joint_frame(const DevHand &H, const Tf &P, bool has_parent, int j, float q)
+{
+    Tf O = tf_load(H.origin + 12 * j);
+    Tf base = has_parent ? tf_mul(P, O) : O;
+    Tf R = tf_axis_angle(H.axis[3 * j], H.axis[3 * j + 1], H.axis[3 * j + 2], q);
+    return tf_mul(base, R);
+}
+
+// ---- window coordinates and normal bins -------------------------------------
+// Affine map u = A p + c from object-frame points to the voxel coordinates of
+// finger f's window under pose P: A = R_f^T R_P / h, c = R_f^T (t_P - o_f) / h.
+struct Affine {
+    float m[12];
+};
+
+__device__ inline Affine finger_affine(const DevHand &H, const float *pose, int f)
+{
+    const float *g = H.grid_frame + 12 * f;
+    Affine a;
+    const float dx = pose[3] - g[3], dy = pose[7] - g[7], dz = pose[11] - g[11];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            a.m[4 * r + c] = fmaf(g[r], pose[c], fmaf(g[4 + r], pose[4 + c], g[8 + r] * pose[8 + c])) * H.inv_h;
+        a.m[4 * r + 3] = fmaf(g[r], dx, fmaf(g[4 + r], dy, g[8 + r] * dz)) * H.inv_h;
+    }
+    return a;
+}
+
+// Linear voxel index of object point p in the window, -1 outside.
+__device__ inline int window_voxel(const Affine &a, int G, float px, float py, float pz)
+{
+    const float ux = fmaf(a.m[0], px, fmaf(a.m[1], py, fmaf(a.m[2], pz, a.m[3])));
+    const float uy = fmaf(a.m[4], px, fmaf(a.m[5], py, fmaf(a.m[6], pz, a.m[7])));
+    const float uz = fmaf(a.m[8], px, fmaf(a.m[9], py, fmaf(a.m[10], pz, a.m[11])));
+    const float g = (float)G;
+    const bool in = (ux >= 0.f) & (ux < g) & (uy >= 0.f) & (uy < g) & (uz >= 0.f) & (uz < g);
+    const int ix = (int)ux, iy = (int)uy, iz = (int)uz;  // truncation == floor for u >= 0
+    return in ? (iz * G + iy) * G + ix : -1;
+}
+
+// Query direction of object normal n under pose P: q = -R_P n.
+__device__ inline void query_dir(const float *pose, float nx, float ny, float nz, float &qx, float &qy, float &qz)
+{
+    qx = -fmaf(pose[0], nx, fmaf(pose[1], ny, pose[2] * nz));
+    qy = -fmaf(pose[4], nx, fmaf(pose[5], ny, pose[6] * nz));
+    qz = -fmaf(pose[8], nx, fmaf(pose[9], ny, pose[10] * nz));
+}
+
+// argmax_b <d, c_b>, ties to the lowest b; c is [B][3] (LDS or global).
+__device__ inline int nearest_bin(const float *c, int B, float dx, float dy, float dz)
+{
+    float best = -3.0e38f;
+    int bi = 0;
+    for (int b = 0; b < B; ++b) {
+        const float s = fmaf(c[3 * b], dx, fmaf(c[3 * b + 1], dy, c[3 * b + 2] * dz));
+        if (s > best) {
+            best = s;
+            bi = b;
+        }
+    }
+    return bi;
+}
+
+__device__ inline bool table_bit(const uint32_t *tab, int W, int64_t voxel, int b)
+{
+    return (tab[voxel * W + (b >> 5)] >> (b & 31)) & 1u;
+}
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace lg

@@ -1,0 +1,114 @@
+// Object contact query (Sec. 4.2-4.3, Def. 4.3) with the per-dependency-group
+// merge of Sec. 5.3.
+//
+// One workgroup per pose; each wave sweeps 64 consecutive object points
+// (structure-of-arrays, Morton-sorted by the caller so a wave touches a
+// compact patch of the field).  Per point: x = R p + t folded into one affine
+// map per finger window, query normal -R n, its bin, one 4/8-byte gather of
+// the finger's merged table, and a wave ballot that yields the 64 domain bits
+// of the finger for the chunk.  Counts are popcounts of the ballots.
+#include <algorithm>
+
+#include "lg_internal.h"
+
+namespace lg {
+
+constexpr int kQueryThreads = 256;
+constexpr int kQueryWaves = kQueryThreads / 64;
+
+template <int W>
+__device__ inline bool merged_hit(const uint32_t *__restrict__ tab, int v, int b)
+{
+    if (W == 1) return (tab[v] >> b) & 1u;
+    const uint64_t w = reinterpret_cast<const uint64_t *>(tab)[v];
+    return (w >> b) & 1ull;
+}
+
+template <int W>
+__global__ void __launch_bounds__(kQueryThreads)
+k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict__ pts,
+        const float *__restrict__ nrm, int N, const float *__restrict__ poses,
+        uint32_t *__restrict__ dom_bits, uint32_t *__restrict__ dom_count)
+{
+    __shared__ float cb[3 * kMaxBins];
+    __shared__ Affine aff[kMaxFingers];
+    __shared__ uint32_t cnt[kMaxFingers][kQueryWaves];
+    const int g = blockIdx.x;
+    const float *pose = poses + 12 * (int64_t)g;
+    for (int i = threadIdx.x; i < 3 * H.B; i += blockDim.x) cb[i] = H.bin_c[i];
+    if (threadIdx.x < H.F) aff[threadIdx.x] = finger_affine(H, pose, threadIdx.x);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int F = H.F, G = H.G, B = H.B;
+    const int64_t G3W = (int64_t)G * G * G * W;
+    const int NW = (N + 31) >> 5, nchunks = (N + 63) >> 6;
+    float P[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) P[i] = pose[i];
+    uint32_t c[kMaxFingers];
+#pragma unroll
+    for (int f = 0; f < kMaxFingers; ++f) c[f] = 0;
+    for (int chunk = wave; chunk < nchunks; chunk += kQueryWaves) {
+        const int i = chunk * 64 + lane;
+        const bool valid = i < N;
+        float px = 0.f, py = 0.f, pz = 0.f, nx = 0.f, ny = 0.f, nz = 1.f;
+        if (valid) {
+            px = pts[i];
+            py = pts[N + i];
+            pz = pts[2 * N + i];
+            nx = nrm[i];
+            ny = nrm[N + i];
+            nz = nrm[2 * N + i];
+        }
+        float qx, qy, qz;
+        query_dir(P, nx, ny, nz, qx, qy, qz);
+        const int b = nearest_bin(cb, B, qx, qy, qz);
+#pragma unroll
+        for (int f = 0; f < kMaxFingers; ++f) {
+            if (f >= F) break;
+            const int v = window_voxel(aff[f], G, px, py, pz);
+            const bool hit = valid && v >= 0 && merged_hit<W>(merged + f * G3W, v, b);
+            const unsigned long long m = __ballot(hit);
+            c[f] += (uint32_t)__popcll(m);
+            const int wi = 2 * chunk + lane;
+            if (lane < 2 && wi < NW)
+                dom_bits[((int64_t)g * F + f) * NW + wi] = lane == 0 ? (uint32_t)m : (uint32_t)(m >> 32);
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int f = 0; f < kMaxFingers; ++f)
+            if (f < F) cnt[f][wave] = c[f];
+    }
+    __syncthreads();
+    if (threadIdx.x < F) {
+        uint32_t s = 0;
+        for (int w = 0; w < kQueryWaves; ++w) s += cnt[threadIdx.x][w];
+        dom_count[(int64_t)g * F + threadIdx.x] = s;
+    }
+}
+
+}  // namespace lg
+
+using namespace lg;
+
+extern "C" lg_status lg_query_domains(const lg_field *field, const float *pts, const float *nrm, int32_t n_points,
+                                      const float *poses, int32_t n_poses, uint32_t *dom_bits, uint32_t *dom_count,
+                                      void *stream)
+{
+    if (!field) return fail(LG_EINVAL, "null field");
+    if (n_points < 0 || n_poses < 0) return fail(LG_EINVAL, "negative size");
+    if (n_poses == 0) return LG_OK;
+    if (!poses || !dom_count || (n_points > 0 && (!pts || !nrm || !dom_bits)))
+        return fail(LG_EINVAL, "null device buffer");
+    hipStream_t s = as_stream(stream);
+    const DevHand &H = field->dh;
+    if (H.W == 1)
+        hipLaunchKernelGGL(k_query<1>, dim3(n_poses), dim3(kQueryThreads), 0, s, H, field->d_merged, pts, nrm,
+                           n_points, poses, dom_bits, dom_count);
+    else
+        hipLaunchKernelGGL(k_query<2>, dim3(n_poses), dim3(kQueryThreads), 0, s, H, field->d_merged, pts, nrm,
+                           n_points, poses, dom_bits, dom_count);
+    LG_HIP(hipGetLastError());
+    return LG_OK;
+}

@@ -1,0 +1,412 @@
+// Kinematics optimisation (Sec. 5.5, Eq. 7-8, Phase I and II) and the
+// penetration part of the validity criterion (Sec. 3.2), fused in one kernel.
+//
+// Lane layout: 8 lanes per accepted set, lane f realises the contact of
+// finger f (lanes f >= F idle), so one wave covers 8 sets and the set-level
+// reductions (max depth, worst contact error / angle) are 3 xor-shuffles.
+// Everything per lane lives in registers; the kernel is templated on the
+// largest finger DOF so the small dense solves unroll.
+#include <math.h>
+
+#include <algorithm>
+
+#include "lg_internal.h"
+
+namespace lg {
+
+constexpr int kRealizeThreads = 256;
+
+struct SdfDev {
+    float ox, oy, oz, h, inv_h;
+    int G;
+    const float *v;
+};
+
+struct IkDev {
+    int iters, phase1;
+    float lambda, beta, tol_pos, tol_ang, margin;
+};
+
+__device__ inline float dot3f(float ax, float ay, float az, float bx, float by, float bz)
+{
+    return fmaf(ax, bx, fmaf(ay, by, az * bz));
+}
+
+// unit vector of (x, y, z); a direction perpendicular to the axis if tiny
+__device__ inline void unit_or_perp(float &x, float &y, float &z, float ax, float ay, float az)
+{
+    const float n2 = dot3f(x, y, z, x, y, z);
+    if (n2 > 1e-30f) {
+        const float r = 1.0f / sqrtf(n2);
+        x *= r;
+        y *= r;
+        z *= r;
+    } else {
+        // Duff et al. basis, first tangent of the axis
+        const float sign = copysignf(1.0f, az);
+        const float a = -1.0f / (sign + az);
+        x = 1.0f + sign * ax * ax * a;
+        y = sign * ax * ay * a;
+        z = -sign * ax;
+    }
+}
+
+// Capsule point closest to (p, n) in |x - p|^2 + beta^2 |nt - n|^2.
+__device__ inline void capsule_aligned(const float *A, const float *Bp, float r, const float *p, const float *n,
+                                       float beta, float *pt, float *nt)
+{
+    float ab[3] = {Bp[0] - A[0], Bp[1] - A[1], Bp[2] - A[2]};
+    const float L = sqrtf(dot3f(ab[0], ab[1], ab[2], ab[0], ab[1], ab[2]));
+    float ax = 0.f, ay = 0.f, az = 1.f;
+    if (L > 0.f) {
+        ax = ab[0] / L;
+        ay = ab[1] / L;
+        az = ab[2] / L;
+    }
+    const float b2 = beta * beta;
+    float best;
+    {  // cylinder
+        float s = dot3f(p[0] - A[0], p[1] - A[1], p[2] - A[2], ax, ay, az);
+        s = fminf(fmaxf(s, 0.f), L);
+        const float cx = fmaf(s, ax, A[0]), cy = fmaf(s, ay, A[1]), cz = fmaf(s, az, A[2]);
+        float vx = fmaf(r, p[0] - cx, b2 * n[0]), vy = fmaf(r, p[1] - cy, b2 * n[1]), vz = fmaf(r, p[2] - cz, b2 * n[2]);
+        const float va = dot3f(vx, vy, vz, ax, ay, az);
+        vx = fmaf(-va, ax, vx);
+        vy = fmaf(-va, ay, vy);
+        vz = fmaf(-va, az, vz);
+        unit_or_perp(vx, vy, vz, ax, ay, az);
+        pt[0] = fmaf(r, vx, cx);
+        pt[1] = fmaf(r, vy, cy);
+        pt[2] = fmaf(r, vz, cz);
+        nt[0] = vx;
+        nt[1] = vy;
+        nt[2] = vz;
+        const float d0 = pt[0] - p[0], d1 = pt[1] - p[1], d2 = pt[2] - p[2];
+        const float e0 = vx - n[0], e1 = vy - n[1], e2 = vz - n[2];
+        best = dot3f(d0, d1, d2, d0, d1, d2) + b2 * dot3f(e0, e1, e2, e0, e1, e2);
+    }
+#pragma unroll
+    for (int cap = 0; cap < 2; ++cap) {
+        const float *c = cap == 0 ? Bp : A;
+        const float sg = cap == 0 ? 1.0f : -1.0f;
+        float vx = fmaf(r, p[0] - c[0], b2 * n[0]), vy = fmaf(r, p[1] - c[1], b2 * n[1]),
+              vz = fmaf(r, p[2] - c[2], b2 * n[2]);
+        const float n2 = dot3f(vx, vy, vz, vx, vy, vz);
+        if (!(n2 > 1e-30f)) continue;
+        const float rn = 1.0f / sqrtf(n2);
+        vx *= rn;
+        vy *= rn;
+        vz *= rn;
+        if (sg * dot3f(vx, vy, vz, ax, ay, az) < 0.f) continue;
+        const float x0 = fmaf(r, vx, c[0]), x1 = fmaf(r, vy, c[1]), x2 = fmaf(r, vz, c[2]);
+        const float d0 = x0 - p[0], d1 = x1 - p[1], d2 = x2 - p[2];
+        const float e0 = vx - n[0], e1 = vy - n[1], e2 = vz - n[2];
+        const float cost = dot3f(d0, d1, d2, d0, d1, d2) + b2 * dot3f(e0, e1, e2, e0, e1, e2);
+        if (cost < best) {
+            best = cost;
+            pt[0] = x0;
+            pt[1] = x1;
+            pt[2] = x2;
+            nt[0] = vx;
+            nt[1] = vy;
+            nt[2] = vz;
+        }
+    }
+}
+
+// Plain projection of p onto the capsule surface.
+__device__ inline void capsule_project(const float *A, const float *Bp, float r, const float *p, float *pt, float *nt)
+{
+    const float ab0 = Bp[0] - A[0], ab1 = Bp[1] - A[1], ab2 = Bp[2] - A[2];
+    const float L2 = dot3f(ab0, ab1, ab2, ab0, ab1, ab2);
+    float t = L2 > 0.f ? dot3f(p[0] - A[0], p[1] - A[1], p[2] - A[2], ab0, ab1, ab2) / L2 : 0.f;
+    t = fminf(fmaxf(t, 0.f), 1.f);
+    const float c0 = fmaf(t, ab0, A[0]), c1 = fmaf(t, ab1, A[1]), c2 = fmaf(t, ab2, A[2]);
+    float ax = 0.f, ay = 0.f, az = 1.f;
+    if (L2 > 0.f) {
+        const float rl = 1.0f / sqrtf(L2);
+        ax = ab0 * rl;
+        ay = ab1 * rl;
+        az = ab2 * rl;
+    }
+    float vx = p[0] - c0, vy = p[1] - c1, vz = p[2] - c2;
+    unit_or_perp(vx, vy, vz, ax, ay, az);
+    nt[0] = vx;
+    nt[1] = vy;
+    nt[2] = vz;
+    pt[0] = fmaf(r, vx, c0);
+    pt[1] = fmaf(r, vy, c1);
+    pt[2] = fmaf(r, vz, c2);
+}
+
+__device__ inline float sdf_trilinear(const SdfDev &S, float yx, float yy, float yz)
+{
+    const float ux = (yx - S.ox) * S.inv_h, uy = (yy - S.oy) * S.inv_h, uz = (yz - S.oz) * S.inv_h;
+    const float gm = (float)(S.G - 1);
+    if (!((ux >= 0.f) & (ux <= gm) & (uy >= 0.f) & (uy <= gm) & (uz >= 0.f) & (uz <= gm))) return INFINITY;
+    const int ix = min((int)ux, S.G - 2), iy = min((int)uy, S.G - 2), iz = min((int)uz, S.G - 2);
+    const float fx = ux - ix, fy = uy - iy, fz = uz - iz;
+    const int64_t G = S.G;
+    const float *v = S.v + (iz * G + iy) * G + ix;
+    const float c00 = fmaf(fx, v[1] - v[0], v[0]);
+    const float c10 = fmaf(fx, v[G + 1] - v[G], v[G]);
+    const float c01 = fmaf(fx, v[G * G + 1] - v[G * G], v[G * G]);
+    const float c11 = fmaf(fx, v[G * G + G + 1] - v[G * G + G], v[G * G + G]);
+    const float c0 = fmaf(fy, c10 - c00, c00), c1 = fmaf(fy, c11 - c01, c01);
+    return fmaf(fz, c1 - c0, c0);
+}
+
+template <int DM>
+__global__ void __launch_bounds__(kRealizeThreads)
+k_realize(DevHand H, const int32_t *__restrict__ wit, SdfDev S, const float *__restrict__ pts,
+          const float *__restrict__ nrm, int N, const float *__restrict__ poses, const int32_t *__restrict__ set_pt,
+          const int8_t *__restrict__ set_link, int k, int D, const int32_t *__restrict__ acc_list,
+          const int32_t *__restrict__ n_acc_dev, int max_acc, IkDev ik, float *__restrict__ q_out,
+          float *__restrict__ cerr, float *__restrict__ cang, float *__restrict__ depth_out,
+          uint8_t *__restrict__ valid_out)
+{
+    __shared__ float cb[3 * kMaxBins];
+    for (int i = threadIdx.x; i < 3 * H.B; i += blockDim.x) cb[i] = H.bin_c[i];
+    __syncthreads();
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t a = gt >> 3;
+    const int f = (int)(gt & 7);
+    const int64_t nacc = min((int64_t)*n_acc_dev, (int64_t)max_acc);
+    if (a >= nacc) return;  // the 8 lanes of a set leave together
+    const int64_t id = acc_list[a];
+    const int64_t g = id / D;
+    float P[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) P[i] = poses[12 * g + i];
+    float dep = -INFINITY, emax = 0.f, amax = 0.f;
+    if (f < H.F) {
+        const int first = H.finger_first[f], d = H.finger_dof[f];
+        const int idx = set_pt[id * k + f];
+        const int l = set_link[id * k + f];
+        const float ox = pts[idx], oy = pts[N + idx], oz = pts[2 * N + idx];
+        float p[3], n[3];
+        p[0] = fmaf(P[0], ox, fmaf(P[1], oy, fmaf(P[2], oz, P[3])));
+        p[1] = fmaf(P[4], ox, fmaf(P[5], oy, fmaf(P[6], oz, P[7])));
+        p[2] = fmaf(P[8], ox, fmaf(P[9], oy, fmaf(P[10], oz, P[11])));
+        query_dir(P, nrm[idx], nrm[N + idx], nrm[2 * N + idx], n[0], n[1], n[2]);
+        // reverse lookup: witness sample of (link, voxel(p), bin(n))
+        int32_t w = kNoWitness;
+        if (wit) {
+            const Affine af = finger_affine(H, P, f);
+            const int v = window_voxel(af, H.G, ox, oy, oz);
+            const int b = nearest_bin(cb, H.B, n[0], n[1], n[2]);
+            if (v >= 0) w = wit[((int64_t)l * H.G * H.G * H.G + v) * H.B + b];
+        }
+        float q[DM];
+#pragma unroll
+        for (int t = 0; t < DM; ++t) {
+            q[t] = 0.f;
+            if (t < d) {
+                const int j = first + t;
+                q[t] = (w >= 0 && w < H.samples) ? joint_sample(H, f, (uint32_t)w, t)
+                                                 : 0.5f * (H.limits[2 * j] + H.limits[2 * j + 1]);
+            }
+        }
+        const int tl = l - first;  // link index within the finger
+        const float *cap = H.capsule + 7 * l;
+        const float r = cap[6];
+        float loc_p[3] = {0.f, 0.f, 0.f}, loc_n[3] = {0.f, 0.f, 1.f};
+        for (int it = 0; it < ik.iters; ++it) {
+            float o[DM][3], z[DM][3];
+            Tf T, Tl;
+#pragma unroll
+            for (int t = 0; t < DM; ++t) {
+                if (t < d) {
+                    const int j = first + t;
+                    T = joint_frame(H, T, t > 0, j, q[t]);
+                    o[t][0] = T.m[3];
+                    o[t][1] = T.m[7];
+                    o[t][2] = T.m[11];
+                    tf_dir(T, H.axis[3 * j], H.axis[3 * j + 1], H.axis[3 * j + 2], z[t][0], z[t][1], z[t][2]);
+                    if (t == tl) Tl = T;
+                }
+            }
+            float pt[3], nt[3];
+            if (it == 0 || it >= ik.phase1) {
+                float A[3], Bq[3];
+                tf_point(Tl, cap[0], cap[1], cap[2], A[0], A[1], A[2]);
+                tf_point(Tl, cap[3], cap[4], cap[5], Bq[0], Bq[1], Bq[2]);
+                capsule_aligned(A, Bq, r, p, n, ik.beta, pt, nt);
+                const float dx = pt[0] - Tl.m[3], dy = pt[1] - Tl.m[7], dz = pt[2] - Tl.m[11];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    loc_p[c] = fmaf(Tl.m[c], dx, fmaf(Tl.m[4 + c], dy, Tl.m[8 + c] * dz));
+                    loc_n[c] = fmaf(Tl.m[c], nt[0], fmaf(Tl.m[4 + c], nt[1], Tl.m[8 + c] * nt[2]));
+                }
+            } else {
+                tf_point(Tl, loc_p[0], loc_p[1], loc_p[2], pt[0], pt[1], pt[2]);
+                tf_dir(Tl, loc_n[0], loc_n[1], loc_n[2], nt[0], nt[1], nt[2]);
+            }
+            float x2[3], e[6];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                x2[c] = fmaf(ik.beta, nt[c], pt[c]);
+                e[c] = p[c] - pt[c];
+                e[3 + c] = fmaf(ik.beta, n[c], p[c]) - x2[c];
+            }
+            float Jc[DM][6];
+#pragma unroll
+            for (int t = 0; t < DM; ++t) {
+                const bool on = t < d && t <= tl;
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const float *x = s == 0 ? pt : x2;
+                    const float vx = x[0] - o[t][0], vy = x[1] - o[t][1], vz = x[2] - o[t][2];
+                    Jc[t][3 * s + 0] = on ? z[t][1] * vz - z[t][2] * vy : 0.f;
+                    Jc[t][3 * s + 1] = on ? z[t][2] * vx - z[t][0] * vz : 0.f;
+                    Jc[t][3 * s + 2] = on ? z[t][0] * vy - z[t][1] * vx : 0.f;
+                }
+            }
+            // normal equations (J^T J + lambda I) dq = J^T e, Cholesky in place
+            float M[DM][DM], gv[DM];
+#pragma unroll
+            for (int i = 0; i < DM; ++i) {
+                float acc = 0.f;
+#pragma unroll
+                for (int rr = 0; rr < 6; ++rr) acc = fmaf(Jc[i][rr], e[rr], acc);
+                gv[i] = acc;
+#pragma unroll
+                for (int j = 0; j < DM; ++j) {
+                    float s2 = 0.f;
+#pragma unroll
+                    for (int rr = 0; rr < 6; ++rr) s2 = fmaf(Jc[i][rr], Jc[j][rr], s2);
+                    M[i][j] = s2 + (i == j ? ik.lambda : 0.f);
+                }
+            }
+            bool ok = true;
+#pragma unroll
+            for (int j = 0; j < DM; ++j) {
+                float s2 = M[j][j];
+#pragma unroll
+                for (int kk = 0; kk < j; ++kk) s2 = fmaf(-M[j][kk], M[j][kk], s2);
+                ok &= s2 > 0.f;
+                const float dd = sqrtf(fmaxf(s2, 1e-30f));
+                M[j][j] = dd;
+                const float inv = 1.0f / dd;
+#pragma unroll
+                for (int i = j + 1; i < DM; ++i) {
+                    float t2 = M[i][j];
+#pragma unroll
+                    for (int kk = 0; kk < j; ++kk) t2 = fmaf(-M[i][kk], M[j][kk], t2);
+                    M[i][j] = t2 * inv;
+                }
+            }
+            if (!ok) break;
+#pragma unroll
+            for (int i = 0; i < DM; ++i) {
+                float t2 = gv[i];
+#pragma unroll
+                for (int kk = 0; kk < i; ++kk) t2 = fmaf(-M[i][kk], gv[kk], t2);
+                gv[i] = t2 / M[i][i];
+            }
+#pragma unroll
+            for (int i = DM - 1; i >= 0; --i) {
+                float t2 = gv[i];
+#pragma unroll
+                for (int kk = i + 1; kk < DM; ++kk) t2 = fmaf(-M[kk][i], gv[kk], t2);
+                gv[i] = t2 / M[i][i];
+            }
+#pragma unroll
+            for (int t = 0; t < DM; ++t) {
+                if (t < d) {
+                    const int j = first + t;
+                    q[t] = fminf(fmaxf(q[t] + gv[t], H.limits[2 * j]), H.limits[2 * j + 1]);
+                }
+            }
+        }
+        // final configuration: contact quality and penetration of the finger's links
+        Tf T;
+#pragma unroll
+        for (int t = 0; t < DM; ++t) {
+            if (t < d) {
+                const int j = first + t;
+                T = joint_frame(H, T, t > 0, j, q[t]);
+                const float *cj = H.capsule + 7 * j;
+                float A[3], Bq[3];
+                tf_point(T, cj[0], cj[1], cj[2], A[0], A[1], A[2]);
+                tf_point(T, cj[3], cj[4], cj[5], Bq[0], Bq[1], Bq[2]);
+                if (t == tl) {
+                    float pt[3], nt[3];
+                    capsule_project(A, Bq, cj[6], p, pt, nt);
+                    const float d0 = p[0] - pt[0], d1 = p[1] - pt[1], d2 = p[2] - pt[2];
+                    emax = sqrtf(dot3f(d0, d1, d2, d0, d1, d2));
+                    amax = acosf(fminf(fmaxf(dot3f(nt[0], nt[1], nt[2], n[0], n[1], n[2]), -1.f), 1.f));
+                }
+                const int M = H.axis_samples[j];
+                const float inv = 1.0f / (float)(M - 1);
+                for (int s = 0; s < M; ++s) {
+                    const float ts = (float)s * inv;
+                    const float x0 = fmaf(ts, Bq[0] - A[0], A[0]) - P[3];
+                    const float x1 = fmaf(ts, Bq[1] - A[1], A[1]) - P[7];
+                    const float x2 = fmaf(ts, Bq[2] - A[2], A[2]) - P[11];
+                    // object frame: R^T (x - t)
+                    const float y0 = fmaf(P[0], x0, fmaf(P[4], x1, P[8] * x2));
+                    const float y1 = fmaf(P[1], x0, fmaf(P[5], x1, P[9] * x2));
+                    const float y2 = fmaf(P[2], x0, fmaf(P[6], x1, P[10] * x2));
+                    dep = fmaxf(dep, cj[6] - sdf_trilinear(S, y0, y1, y2));
+                }
+                q_out[a * H.J + j] = q[t];
+            }
+        }
+        cerr[a * k + f] = emax;
+        cang[a * k + f] = amax;
+    }
+    // set-level reductions over the 8 lanes of the set
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+        dep = fmaxf(dep, __shfl_xor(dep, off, 8));
+        emax = fmaxf(emax, __shfl_xor(emax, off, 8));
+        amax = fmaxf(amax, __shfl_xor(amax, off, 8));
+    }
+    if (f == 0) {
+        depth_out[a] = dep;
+        valid_out[a] = (emax <= ik.tol_pos && amax <= ik.tol_ang && dep <= ik.margin) ? 1 : 0;
+    }
+}
+
+}  // namespace lg
+
+using namespace lg;
+
+extern "C" lg_status lg_realize(const lg_field *field, const lg_sdf *sdf, const float *pts, const float *nrm,
+                                int32_t n_points, const float *poses, int32_t n_poses, const int32_t *set_pt,
+                                const int8_t *set_link, int32_t k, int32_t draws, const int32_t *acc_list,
+                                const int32_t *n_acc_dev, int32_t max_acc, const lg_ik_params *p, float *q_out,
+                                float *contact_err, float *contact_ang, float *depth, uint8_t *valid, void *stream)
+{
+    if (!field || !sdf || !p) return fail(LG_EINVAL, "null field, sdf or params");
+    const DevHand &H = field->dh;
+    if (k != H.F) return fail(LG_EINVAL, "k must equal the number of fingers");
+    if (n_points <= 0 || n_poses <= 0 || draws <= 0 || max_acc < 0)
+        return fail(LG_EINVAL, "bad sizes");
+    if (sdf->dims < 2 || !(sdf->h > 0.f) || !sdf->values) return fail(LG_EINVAL, "bad sdf");
+    if (p->iters < 0 || p->phase1 < 0 || !(p->lambda > 0.f)) return fail(LG_EINVAL, "need iters >= 0, lambda > 0");
+    if (max_acc == 0) return LG_OK;
+    if (!pts || !nrm || !poses || !set_pt || !set_link || !acc_list || !n_acc_dev || !q_out || !contact_err ||
+        !contact_ang || !depth || !valid)
+        return fail(LG_EINVAL, "null device buffer");
+    SdfDev S{sdf->origin[0], sdf->origin[1], sdf->origin[2], sdf->h, 1.0f / sdf->h, sdf->dims, sdf->values};
+    IkDev ik{p->iters, p->phase1, p->lambda, p->beta, p->tol_pos, p->tol_ang, p->margin};
+    hipStream_t s = as_stream(stream);
+    const int64_t threads = (int64_t)max_acc * 8;
+    const dim3 grid((unsigned)((threads + kRealizeThreads - 1) / kRealizeThreads));
+    const int32_t *wit = field->has_witness ? field->d_wit : nullptr;
+#define LG_REALIZE(DM)                                                                                          \
+    hipLaunchKernelGGL(k_realize<DM>, grid, dim3(kRealizeThreads), 0, s, H, wit, S, pts, nrm, n_points, poses,  \
+                       set_pt, set_link, k, draws, acc_list, n_acc_dev, max_acc, ik, q_out, contact_err,        \
+                       contact_ang, depth, valid)
+    if (field->max_dof <= 4)
+        LG_REALIZE(4);
+    else if (field->max_dof <= 6)
+        LG_REALIZE(6);
+    else
+        LG_REALIZE(8);
+#undef LG_REALIZE
+    LG_HIP(hipGetLastError());
+    return LG_OK;
+}

@@ -1,0 +1,496 @@
+// Contact-set draws (Sec. 5.3, Alg. 2 initialisation), reverse lookup of the
+// hand link (Sec. 5.5), the contact-set criterion (Eq. 1-2 with a linearised
+// friction cone, as an LP) and deterministic compaction of accepted sets.
+#include <math.h>
+
+#include <algorithm>
+
+#include "lg_internal.h"
+
+namespace lg {
+
+constexpr int kDrawThreads = 256;
+constexpr int kSuper = 8;           // words per rank superblock
+constexpr int kVerdictWaves = 4;    // sets (waves) per verdict workgroup
+constexpr int kChunkPerThread = 32; // compaction: sets per thread
+constexpr int kCompactThreads = 256;
+constexpr int kChunk = kChunkPerThread * kCompactThreads;
+
+// select the r-th (0-based) set bit of x
+__device__ inline int select_in_word(uint32_t x, uint32_t r)
+{
+    for (uint32_t i = 0; i < r; ++i) x &= x - 1u;
+    return __ffs(x) - 1;
+}
+
+// One workgroup per pose.  Rank structure: exclusive popcount prefix per
+// superblock of 8 domain words, in LDS; a draw binary-searches it and scans
+// at most 8 words.
+__global__ void __launch_bounds__(kDrawThreads)
+k_draw(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ pts, const float *__restrict__ nrm,
+       int N, const float *__restrict__ poses, const uint32_t *__restrict__ dom_bits,
+       const uint32_t *__restrict__ dom_count, int D, int k, uint32_t seed_lo, uint32_t seed_hi,
+       uint32_t request_id, int64_t pose_offset, int32_t *__restrict__ set_pt, int8_t *__restrict__ set_link)
+{
+    extern __shared__ uint32_t prefix[];  // [F][nsb + 1]
+    __shared__ float cb[3 * kMaxBins];
+    __shared__ uint32_t counts[kMaxFingers];
+    const int g = blockIdx.x, F = H.F;
+    const int NW = (N + 31) >> 5, nsb = (NW + kSuper - 1) / kSuper;
+    const uint32_t *dom = dom_bits + (int64_t)g * F * NW;
+    for (int i = threadIdx.x; i < 3 * H.B; i += blockDim.x) cb[i] = H.bin_c[i];
+    if (threadIdx.x < F) counts[threadIdx.x] = dom_count[(int64_t)g * F + threadIdx.x];
+    __syncthreads();
+    bool empty = false;
+    for (int f = 0; f < F; ++f) empty |= counts[f] == 0;
+    if (empty) {
+        for (int i = threadIdx.x; i < D * k; i += blockDim.x) {
+            set_pt[(int64_t)g * D * k + i] = -1;
+            set_link[(int64_t)g * D * k + i] = -1;
+        }
+        return;  // uniform over the block
+    }
+    // superblock popcounts, then a per-finger exclusive scan
+    for (int i = threadIdx.x; i < F * nsb; i += blockDim.x) {
+        const int f = i / nsb, sb = i % nsb;
+        uint32_t c = 0;
+        for (int w = sb * kSuper; w < min(NW, (sb + 1) * kSuper); ++w) c += __popc(dom[(int64_t)f * NW + w]);
+        prefix[f * (nsb + 1) + sb + 1] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x < F) {
+        uint32_t *pf = prefix + threadIdx.x * (nsb + 1);
+        pf[0] = 0;
+        for (int sb = 1; sb <= nsb; ++sb) pf[sb] += pf[sb - 1];
+    }
+    __syncthreads();
+    const float *pose = poses + 12 * (int64_t)g;
+    const int64_t G3 = (int64_t)H.G * H.G * H.G;
+    for (int d = threadIdx.x; d < D; d += blockDim.x) {
+        uint32_t w[16];
+        for (int blk = 0; blk * 4 < 2 * k; ++blk)
+            philox4x32_10((uint32_t)(pose_offset + g), (uint32_t)(4 * d + blk), kPurposeDraw, request_id, seed_lo,
+                          seed_hi, w + 4 * blk);
+        int32_t *sp = set_pt + ((int64_t)g * D + d) * k;
+        int8_t *sl = set_link + ((int64_t)g * D + d) * k;
+        for (int i = 0; i < k; ++i) {
+            const uint32_t cnt = counts[i];
+            const uint32_t j = __umulhi(w[i], cnt);
+            // rank: last superblock with prefix <= j
+            const uint32_t *pf = prefix + i * (nsb + 1);
+            int lo = 0, hi = nsb;  // invariant pf[lo] <= j < pf[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (pf[mid] <= j) lo = mid; else hi = mid;
+            }
+            uint32_t rem = j - pf[lo];
+            int idx = -1;
+            for (int wi = lo * kSuper; wi < min(NW, (lo + 1) * kSuper); ++wi) {
+                const uint32_t x = dom[(int64_t)i * NW + wi];
+                const uint32_t pc = __popc(x);
+                if (rem < pc) {
+                    idx = wi * 32 + select_in_word(x, rem);
+                    break;
+                }
+                rem -= pc;
+            }
+            // reverse lookup: links of finger i whose own table is hit at idx
+            int link = -1;
+            if (idx >= 0) {
+                const Affine a = finger_affine(H, pose, i);
+                const int v = window_voxel(a, H.G, pts[idx], pts[N + idx], pts[2 * N + idx]);
+                float qx, qy, qz;
+                query_dir(pose, nrm[idx], nrm[N + idx], nrm[2 * N + idx], qx, qy, qz);
+                const int b = nearest_bin(cb, H.B, qx, qy, qz);
+                uint32_t mask = 0;
+                const int first = H.finger_first[i], dof = H.finger_dof[i];
+                if (v >= 0)
+                    for (int t = 0; t < dof; ++t)
+                        if (table_bit(bits + (int64_t)(first + t) * G3 * H.W, H.W, v, b)) mask |= 1u << t;
+                const uint32_t pc = __popc(mask);
+                if (pc) link = first + select_in_word(mask, __umulhi(w[k + i], pc));
+            }
+            sp[i] = idx;
+            sl[i] = (int8_t)link;
+        }
+    }
+}
+
+// ---- force-closure LP, one wave per set ------------------------------------
+// Duff et al. (2017) branchless orthonormal basis of unit n.
+__device__ inline void duff_basis(double nx, double ny, double nz, double *x, double *y)
+{
+    const double sign = copysign(1.0, nz);
+    const double a = -1.0 / (sign + nz);
+    const double b = nx * ny * a;
+    x[0] = 1.0 + sign * nx * nx * a;
+    x[1] = sign * b;
+    x[2] = -sign * nx;
+    y[0] = b;
+    y[1] = sign + ny * ny * a;
+    y[2] = -ny;
+}
+
+constexpr double kLpTol = 1e-12;  // reduced-cost and ratio-tie tolerance
+constexpr double kLpPiv = 1e-9;   // smallest admissible pivot element
+
+// Tableau simplex with the columns spread over the 64 lanes (lane j holds
+// column j of B^-1 A and its reduced cost); the right-hand side and basis
+// are replicated in every lane.  Columns: g_0..g_{km-1}, s+_0..s+_5,
+// s-_0..s-_5.  Bland's rule: lowest entering index, ratio ties to the lowest
+// basic variable.  When no reduced cost is negative, the basis is re-inverted
+// from the original columns (lane-parallel Gauss-Jordan on [B | I] in lanes
+// 0..13) and optimality is re-checked, so rounding accumulated over long
+// degenerate pivot runs cannot end the search early.  Double precision: the
+// verdict is a thresholded decision and the LP is latency-bound.
+__global__ void __launch_bounds__(64 * kVerdictWaves)
+k_verdict(const float *__restrict__ pts, const float *__restrict__ nrm, int N, const int32_t *__restrict__ set_pt,
+          int64_t n_sets, int k, int m, double mu, double rho, double eps, int max_pivots,
+          uint8_t *__restrict__ verdict, double *__restrict__ tstar)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t sid = (int64_t)blockIdx.x * kVerdictWaves + (threadIdx.x >> 6);
+    if (sid >= n_sets) return;  // whole wave
+    const int32_t *sp = set_pt + sid * k;
+    bool valid = true;
+    for (int i = 0; i < k; ++i) valid &= sp[i] >= 0;
+    if (!valid) {
+        if (lane == 0) {
+            verdict[sid] = 0;
+            tstar[sid] = __builtin_nan("");
+        }
+        return;
+    }
+    const int n = k * m, nv = n + 12;
+    // this lane's original column A_j (7 rows) and the first wrench column w_0
+    double col[7], w0[6];
+    auto wrench = [&](int c, double *w) {
+        const int i = c / m, e = c % m;
+        const int idx = sp[i];
+        const double px = pts[idx], py = pts[N + idx], pz = pts[2 * N + idx];
+        const double nx = nrm[idx], ny = nrm[N + idx], nz = nrm[2 * N + idx];
+        double x[3], y[3];
+        duff_basis(nx, ny, nz, x, y);
+        const double th = 2.0 * M_PI * e / m;
+        const double ce = cos(th), se = sin(th);
+        const double dx = -nx + mu * (ce * x[0] + se * y[0]);
+        const double dy = -ny + mu * (ce * x[1] + se * y[1]);
+        const double dz = -nz + mu * (ce * x[2] + se * y[2]);
+        w[0] = dx;
+        w[1] = dy;
+        w[2] = dz;
+        w[3] = (py * dz - pz * dy) / rho;
+        w[4] = (pz * dx - px * dz) / rho;
+        w[5] = (px * dy - py * dx) / rho;
+    };
+    wrench(0, w0);
+    // original column j of [W^T -I I; 1 0 0]
+    auto orig_col = [&](int j, double *a) {
+#pragma unroll
+        for (int r = 0; r < 7; ++r) a[r] = 0.0;
+        if (j < n) {
+            double w[6];
+            wrench(j, w);
+#pragma unroll
+            for (int r = 0; r < 6; ++r) a[r] = w[r];
+            a[6] = 1.0;
+        } else if (j < n + 6) {
+#pragma unroll
+            for (int r = 0; r < 6; ++r) a[r] = (r == j - n) ? -1.0 : 0.0;
+        } else if (j < nv) {
+#pragma unroll
+            for (int r = 0; r < 6; ++r) a[r] = (r == j - n - 6) ? 1.0 : 0.0;
+        }
+    };
+    orig_col(lane, col);
+    // initial basis: g_0 on the normalisation row, a slack per wrench row
+    double rhs[7];
+    int basis[7];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+        col[r] -= w0[r] * col[6];
+        rhs[r] = -w0[r];
+        if (rhs[r] >= 0.0) {
+            basis[r] = n + 6 + r;
+        } else {
+            col[r] = -col[r];
+            rhs[r] = -rhs[r];
+            basis[r] = n + r;
+        }
+    }
+    rhs[6] = 1.0;
+    basis[6] = 0;
+    auto reduced_cost = [&]() {
+        double rc0 = (lane >= n && lane < nv) ? 1.0 : 0.0;
+#pragma unroll
+        for (int r = 0; r < 7; ++r)
+            if (basis[r] >= n) rc0 -= col[r];
+        return rc0;
+    };
+    double rc = reduced_cost();
+    int piv = 0, status = 0, checks = 0;
+    for (;;) {
+        const bool neg = lane < nv && rc < -kLpTol;
+        const unsigned long long mneg = __ballot(neg);
+        if (!mneg) {
+            if (checks >= 4) break;
+            ++checks;
+            // re-invert: lanes 0..6 hold columns of B, lanes 7..13 of I
+            double m[7];
+            if (lane < 7) {
+                int bj = 0;
+#pragma unroll
+                for (int r = 0; r < 7; ++r) bj = r == lane ? basis[r] : bj;
+                orig_col(bj, m);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 7; ++r) m[r] = (lane - 7 == r) ? 1.0 : 0.0;
+            }
+            bool singular = false;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) {
+                double cc[7];
+#pragma unroll
+                for (int r = 0; r < 7; ++r) cc[r] = __shfl(m[r], c, 64);
+                int p = c;
+                double pa = fabs(cc[c]);
+#pragma unroll
+                for (int r = c + 1; r < 7; ++r)
+                    if (fabs(cc[r]) > pa) {
+                        pa = fabs(cc[r]);
+                        p = r;
+                    }
+                singular |= !(pa > 1e-300);
+                // swap rows p and c
+                double mp = 0.0, cp = 0.0;
+#pragma unroll
+                for (int r = 0; r < 7; ++r)
+                    if (r == p) {
+                        mp = m[r];
+                        cp = cc[r];
+                    }
+#pragma unroll
+                for (int r = 0; r < 7; ++r)
+                    if (r == p) {
+                        m[r] = m[c];
+                        cc[r] = cc[c];
+                    }
+                m[c] = mp;
+                cc[c] = cp;
+                const double inv = 1.0 / cc[c];
+                m[c] *= inv;
+#pragma unroll
+                for (int r = 0; r < 7; ++r)
+                    if (r != c) m[r] -= cc[r] * m[c];
+            }
+            if (singular) break;
+            // tableau column of this lane and the right-hand side from B^-1
+            double a[7], t[7];
+            orig_col(lane, a);
+#pragma unroll
+            for (int r = 0; r < 7; ++r) t[r] = 0.0;
+#pragma unroll
+            for (int i = 0; i < 7; ++i) {
+#pragma unroll
+                for (int r = 0; r < 7; ++r) {
+                    const double bi = __shfl(m[r], 7 + i, 64);  // B^-1[r][i]
+                    t[r] += bi * a[i];
+                    if (i == 6) rhs[r] = bi;                    // B^-1 e_6
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 7; ++r) col[r] = t[r];
+            rc = reduced_cost();
+            continue;
+        }
+        if (piv >= max_pivots) {
+            status = 1;
+            break;
+        }
+        const int e = __ffsll((long long)mneg) - 1;
+        double ce[7];
+#pragma unroll
+        for (int r = 0; r < 7; ++r) ce[r] = __shfl(col[r], e, 64);
+        const double rce = __shfl(rc, e, 64);
+        int lr = -1;
+        double best = 0.0;
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+            if (ce[r] > kLpPiv) {
+                const double ratio = rhs[r] / ce[r];
+                const double tol = kLpTol * (1.0 + fabs(best));
+                if (lr < 0 || ratio < best - tol || (fabs(ratio - best) <= tol && basis[r] < basis[lr])) {
+                    lr = r;
+                    best = ratio;
+                }
+            }
+        }
+        if (lr < 0) {
+            status = 2;
+            break;
+        }
+        double pv = 0.0;
+#pragma unroll
+        for (int r = 0; r < 7; ++r) pv = r == lr ? ce[r] : pv;
+        double prow = 0.0, prhs = 0.0;
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+            if (r == lr) {
+                prow = col[r] / pv;
+                prhs = rhs[r] / pv;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+            if (r == lr) {
+                col[r] = prow;
+                rhs[r] = prhs;
+                basis[r] = e;
+            } else {
+                col[r] -= ce[r] * prow;
+                rhs[r] -= ce[r] * prhs;
+            }
+        }
+        rc -= rce * prow;
+        ++piv;
+    }
+    if (lane == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int r = 0; r < 7; ++r)
+            if (basis[r] >= n) t += rhs[r];
+        verdict[sid] = (status == 0 && t <= eps) ? 1 : 0;
+        tstar[sid] = status == 0 ? t : __builtin_nan("");
+    }
+}
+
+// ---- compaction ------------------------------------------------------------
+__global__ void __launch_bounds__(kCompactThreads)
+k_chunk_count(const uint8_t *__restrict__ verdict, int64_t n, uint32_t *__restrict__ chunk_count)
+{
+    __shared__ uint32_t part[kCompactThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kChunkPerThread;
+    uint32_t c = 0;
+    for (int i = 0; i < kChunkPerThread; ++i)
+        if (base + i < n) c += verdict[base + i] != 0;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int w = 0; w < kCompactThreads / 64; ++w) s += part[w];
+        chunk_count[blockIdx.x] = s;
+    }
+}
+
+// single workgroup: exclusive scan of chunk counts, total into n_acc
+__global__ void __launch_bounds__(kCompactThreads)
+k_chunk_scan(const uint32_t *__restrict__ chunk_count, int64_t n_chunks, uint32_t *__restrict__ chunk_off,
+             int32_t *__restrict__ n_acc)
+{
+    __shared__ uint32_t tot[kCompactThreads];
+    const int64_t per = (n_chunks + kCompactThreads - 1) / kCompactThreads;
+    const int64_t b0 = threadIdx.x * per;
+    uint32_t s = 0;
+    for (int64_t i = b0; i < min(n_chunks, b0 + per); ++i) s += chunk_count[i];
+    tot[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int t = 0; t < kCompactThreads; ++t) {
+            const uint32_t v = tot[t];
+            tot[t] = run;
+            run += v;
+        }
+        *n_acc = (int32_t)run;
+    }
+    __syncthreads();
+    uint32_t run = tot[threadIdx.x];
+    for (int64_t i = b0; i < min(n_chunks, b0 + per); ++i) {
+        chunk_off[i] = run;
+        run += chunk_count[i];
+    }
+}
+
+__global__ void __launch_bounds__(kCompactThreads)
+k_chunk_scatter(const uint8_t *__restrict__ verdict, int64_t n, const uint32_t *__restrict__ chunk_off,
+                int32_t *__restrict__ acc_list)
+{
+    __shared__ uint32_t pre[kCompactThreads];
+    const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kChunkPerThread;
+    uint32_t c = 0;
+    for (int i = 0; i < kChunkPerThread; ++i)
+        if (base + i < n) c += verdict[base + i] != 0;
+    pre[threadIdx.x] = c;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the block
+    for (int off = 1; off < kCompactThreads; off <<= 1) {
+        const uint32_t v = threadIdx.x >= off ? pre[threadIdx.x - off] : 0u;
+        __syncthreads();
+        pre[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t pos = chunk_off[blockIdx.x] + pre[threadIdx.x] - c;
+    for (int i = 0; i < kChunkPerThread; ++i)
+        if (base + i < n && verdict[base + i]) acc_list[pos++] = (int32_t)(base + i);
+}
+
+}  // namespace lg
+
+using namespace lg;
+
+extern "C" {
+
+size_t lg_search_workspace_bytes(int32_t n_poses, const lg_search_params *p)
+{
+    if (!p || n_poses <= 0 || p->draws <= 0) return 256;
+    const int64_t n_sets = (int64_t)n_poses * p->draws;
+    const int64_t n_chunks = (n_sets + kChunk - 1) / kChunk;
+    return (size_t)(2 * n_chunks * sizeof(uint32_t) + 256);
+}
+
+lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, int32_t n_points, const float *poses,
+                    int32_t n_poses, const uint32_t *dom_bits, const uint32_t *dom_count,
+                    const lg_search_params *p, int32_t *set_pt, int8_t *set_link, uint8_t *verdict, double *tstar,
+                    int32_t *acc_list, int32_t *n_acc, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!field || !p) return fail(LG_EINVAL, "null field or params");
+    const DevHand &H = field->dh;
+    if (n_points <= 0 || n_poses < 0) return fail(LG_EINVAL, "n_points must be > 0 and n_poses >= 0");
+    if (p->k != H.F) return fail(LG_EINVAL, "k must equal the number of fingers (one contact per finger)");
+    if (p->draws <= 0 || p->m_edges < 3 || p->m_edges > 16 || p->k * p->m_edges + 12 > 64)
+        return fail(LG_EINVAL, "need draws > 0, 3 <= m_edges <= 16 and k*m_edges <= 52");
+    if (!(p->mu >= 0.0f) || !(p->moment_scale > 0.0f) || p->max_pivots < 0)
+        return fail(LG_EINVAL, "need mu >= 0, moment_scale > 0, max_pivots >= 0");
+    if ((int64_t)n_poses * p->draws > 0x7fffffffLL) return fail(LG_EINVAL, "P * D must be < 2^31");
+    if (n_poses == 0) return LG_OK;
+    if (!pts || !nrm || !poses || !dom_bits || !dom_count || !set_pt || !set_link || !verdict || !tstar ||
+        !acc_list || !n_acc || !workspace)
+        return fail(LG_EINVAL, "null device buffer");
+    if (workspace_bytes < lg_search_workspace_bytes(n_poses, p)) return fail(LG_EINVAL, "workspace too small");
+    const int NW = (n_points + 31) / 32, nsb = (NW + kSuper - 1) / kSuper;
+    const size_t lds = (size_t)H.F * (nsb + 1) * sizeof(uint32_t);
+    if (lds > 48 * 1024) return fail(LG_EUNSUPPORTED, "too many points for the draw rank structure");
+    hipStream_t s = as_stream(stream);
+    hipLaunchKernelGGL(k_draw, dim3(n_poses), dim3(kDrawThreads), lds, s, H, field->d_bits, pts, nrm, n_points,
+                       poses, dom_bits, dom_count, p->draws, p->k, (uint32_t)p->seed, (uint32_t)(p->seed >> 32),
+                       p->request_id, p->pose_offset, set_pt, set_link);
+    LG_HIP(hipGetLastError());
+    const int64_t n_sets = (int64_t)n_poses * p->draws;
+    hipLaunchKernelGGL(k_verdict, dim3((unsigned)((n_sets + kVerdictWaves - 1) / kVerdictWaves)),
+                       dim3(64 * kVerdictWaves), 0, s, pts, nrm, n_points, set_pt, n_sets, p->k, p->m_edges,
+                       (double)p->mu, (double)p->moment_scale, (double)p->eps, p->max_pivots, verdict, tstar);
+    LG_HIP(hipGetLastError());
+    const int64_t n_chunks = (n_sets + kChunk - 1) / kChunk;
+    uint32_t *chunk_count = static_cast<uint32_t *>(workspace);
+    uint32_t *chunk_off = chunk_count + n_chunks;
+    hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)n_chunks), dim3(kCompactThreads), 0, s, verdict, n_sets,
+                       chunk_count);
+    hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kCompactThreads), 0, s, chunk_count, n_chunks, chunk_off, n_acc);
+    hipLaunchKernelGGL(k_chunk_scatter, dim3((unsigned)n_chunks), dim3(kCompactThreads), 0, s, verdict, n_sets,
+                       chunk_off, acc_list);
+    LG_HIP(hipGetLastError());
+    return LG_OK;
+}
+
+}  // extern "C"

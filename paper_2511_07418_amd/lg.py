@@ -1,0 +1,299 @@
+"""Thin Python binding of the gfx950 Contact-Field library (``liblg.so``).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Functions carry the C ABI's names (``lg_build_field``,
+``lg_query_domains``, ``lg_search``, ``lg_realize``, ...).  Device buffers are
+``torch`` tensors on the current HIP device; host arrays are NumPy arrays.
+If the library has not been built the import of this module raises: there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblg.so")
+
+LG_OK, LG_EINVAL, LG_ENOMEM, LG_EDEVICE, LG_EUNSUPPORTED, LG_EINTERNAL = 0, -1, -2, -3, -5, -6
+
+
+class LgError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+# ---- C structures (mirror include/lg.h) -------------------------------------
+class HandDesc(C.Structure):
+    _fields_ = [("n_fingers", C.c_int32), ("n_joints", C.c_int32),
+                ("joint_finger", C.c_void_p), ("joint_parent", C.c_void_p),
+                ("joint_origin", C.c_void_p), ("joint_axis", C.c_void_p),
+                ("capsule", C.c_void_p), ("limits", C.c_void_p),
+                ("n_surf", C.c_int32), ("surf", C.c_void_p)]
+
+
+class FieldParams(C.Structure):
+    _fields_ = [("samples", C.c_int64), ("seed", C.c_uint64), ("grid", C.c_int32),
+                ("h", C.c_float), ("bins", C.c_int32), ("grid_frame", C.c_void_p),
+                ("keep_witness", C.c_int32)]
+
+
+class FieldInfo(C.Structure):
+    _fields_ = [("n_fingers", C.c_int32), ("n_joints", C.c_int32), ("grid", C.c_int32),
+                ("bins", C.c_int32), ("samples", C.c_int64), ("device_bytes", C.c_uint64),
+                ("bits_set", C.c_uint64), ("vectors", C.c_int64), ("dropped", C.c_int64),
+                ("has_witness", C.c_int32)]
+
+
+class SearchParams(C.Structure):
+    _fields_ = [("draws", C.c_int32), ("k", C.c_int32), ("m_edges", C.c_int32),
+                ("max_pivots", C.c_int32), ("mu", C.c_float), ("eps", C.c_float),
+                ("moment_scale", C.c_float), ("seed", C.c_uint64), ("request_id", C.c_uint32),
+                ("pose_offset", C.c_int64)]
+
+
+class IkParams(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("phase1", C.c_int32), ("lam", C.c_float),
+                ("beta", C.c_float), ("tol_pos", C.c_float), ("tol_ang", C.c_float),
+                ("margin", C.c_float)]
+
+
+class Sdf(C.Structure):
+    _fields_ = [("origin", C.c_float * 3), ("h", C.c_float), ("dims", C.c_int32),
+                ("values", C.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run paper_2511_07418_amd/build.py "
+                          "(or __graft_entry__.build()) first")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+    L.lg_status_str.restype = C.c_char_p
+    L.lg_status_str.argtypes = [i32]
+    L.lg_last_error.restype = C.c_char_p
+    L.lg_version.restype = C.c_char_p
+    L.lg_build_field.argtypes = [vp, vp, vp, vp]
+    L.lg_field_import.argtypes = [vp, vp, vp, vp, vp]
+    L.lg_field_export.argtypes = [vp, vp, vp]
+    L.lg_field_info.argtypes = [vp, vp]
+    L.lg_field_release.argtypes = [vp]
+    L.lg_query_domains.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp]
+    L.lg_search_workspace_bytes.argtypes = [i32, vp]
+    L.lg_search_workspace_bytes.restype = sz
+    L.lg_search.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.lg_realize.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, i32, i32, vp, vp, i32, vp,
+                             vp, vp, vp, vp, vp, vp]
+    for fn in ("lg_build_field", "lg_field_import", "lg_field_export", "lg_field_info",
+               "lg_field_release", "lg_query_domains", "lg_search", "lg_realize"):
+        getattr(L, fn).restype = i32
+    return L
+
+
+_lib = _load()
+
+EXPORTED = ("lg_status_str", "lg_last_error", "lg_version", "lg_build_field", "lg_field_import",
+            "lg_field_export", "lg_field_info", "lg_field_release", "lg_query_domains",
+            "lg_search_workspace_bytes", "lg_search", "lg_realize")
+
+
+def lib():
+    return _lib
+
+
+def _check(st: int, where: str):
+    if st != LG_OK:
+        raise LgError(st, where, (_lib.lg_last_error() or b"").decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _hp(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _stream(stream) -> C.c_void_p:
+    """hipStream_t of ``stream``; None means torch's current stream (the null
+    stream before torch has touched the device)."""
+    if stream is None:
+        if not torch.cuda.is_initialized():
+            return C.c_void_p(0)
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class _HandKeep:
+    def __init__(self, hand):
+        self.arrs = [np.ascontiguousarray(hand.joint_finger, np.int32),
+                     np.ascontiguousarray(hand.joint_parent, np.int32),
+                     np.ascontiguousarray(hand.joint_origin, np.float32),
+                     np.ascontiguousarray(hand.joint_axis, np.float32),
+                     np.ascontiguousarray(hand.capsule, np.float32),
+                     np.ascontiguousarray(hand.limits, np.float32),
+                     np.ascontiguousarray(hand.surf, np.float32)]
+        a = self.arrs
+        self.desc = HandDesc(int(hand.n_fingers), int(a[0].shape[0]), _hp(a[0]), _hp(a[1]), _hp(a[2]),
+                             _hp(a[3]), _hp(a[4]), _hp(a[5]), int(a[6].shape[1]), _hp(a[6]))
+
+
+def _field_params(fp, keep_witness: bool):
+    gf = np.ascontiguousarray(fp.grid_frame, np.float32)
+    return FieldParams(int(fp.samples), int(fp.seed) & 0xFFFFFFFFFFFFFFFF, int(fp.grid), float(fp.h),
+                       int(fp.bins), _hp(gf), int(bool(keep_witness))), gf
+
+
+class Field:
+    """Owner of an ``lg_field`` handle (resident in HBM until released)."""
+
+    def __init__(self, handle: C.c_void_p, hand):
+        self.handle = handle
+        self.n_fingers = int(hand.n_fingers)
+        self.n_joints = int(hand.n_joints)
+
+    def info(self) -> dict:
+        inf = FieldInfo()
+        _check(_lib.lg_field_info(self.handle, C.byref(inf)), "lg_field_info")
+        return {k: getattr(inf, k) for k, _ in FieldInfo._fields_}
+
+    def export(self, witness: bool = False):
+        inf = self.info()
+        L, G, B = inf["n_joints"], inf["grid"], inf["bins"]
+        bits = np.zeros((L, G ** 3, B // 32), np.uint32)
+        wit = np.zeros((L, G ** 3, B), np.int32) if witness else None
+        _check(_lib.lg_field_export(self.handle, _hp(bits), None if wit is None else _hp(wit)),
+               "lg_field_export")
+        return bits, wit
+
+    def release(self):
+        if self.handle:
+            _lib.lg_field_release(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+# ---- the four calls of the hot path -----------------------------------------
+def lg_build_field(hand, fp, keep_witness: bool = True, stream=None) -> Field:
+    hk = _HandKeep(hand)
+    p, gf = _field_params(fp, keep_witness)
+    out = C.c_void_p()
+    _check(_lib.lg_build_field(C.byref(hk.desc), C.byref(p), _stream(stream), C.byref(out)),
+           "lg_build_field")
+    return Field(out, hand)
+
+
+def lg_field_import(hand, fp, bits: np.ndarray, witness: Optional[np.ndarray] = None) -> Field:
+    hk = _HandKeep(hand)
+    p, gf = _field_params(fp, witness is not None)
+    b = np.ascontiguousarray(bits, np.uint32)
+    w = None if witness is None else np.ascontiguousarray(witness, np.int32)
+    out = C.c_void_p()
+    _check(_lib.lg_field_import(C.byref(hk.desc), C.byref(p), _hp(b), None if w is None else _hp(w),
+                                C.byref(out)), "lg_field_import")
+    return Field(out, hand)
+
+
+def lg_query_domains(field: Field, pts: torch.Tensor, nrm: torch.Tensor, poses: torch.Tensor,
+                     dom_bits: Optional[torch.Tensor] = None, dom_count: Optional[torch.Tensor] = None,
+                     stream=None):
+    """pts, nrm: [3, N] float32; poses: [P, 12] float32 (device tensors)."""
+    N, P, F = int(pts.shape[1]), int(poses.shape[0]), field.n_fingers
+    NW = (N + 31) // 32
+    dev = pts.device
+    if dom_bits is None:
+        dom_bits = torch.empty((P, F, NW), dtype=torch.int32, device=dev)
+    if dom_count is None:
+        dom_count = torch.empty((P, F), dtype=torch.int32, device=dev)
+    _check(_lib.lg_query_domains(field.handle, _ptr(pts), _ptr(nrm), N, _ptr(poses), P,
+                                 _ptr(dom_bits), _ptr(dom_count), _stream(stream)), "lg_query_domains")
+    return dom_bits, dom_count
+
+
+def search_params(sp, max_pivots: int = 1000) -> SearchParams:
+    return SearchParams(int(sp.draws), int(sp.k), int(sp.m_edges), int(max_pivots), float(sp.mu),
+                        float(sp.eps), float(sp.moment_scale), int(sp.seed) & 0xFFFFFFFFFFFFFFFF,
+                        int(sp.request_id), int(sp.pose_offset))
+
+
+class SearchBuffers:
+    """Device outputs + workspace of lg_search for P poses (reusable)."""
+
+    def __init__(self, n_poses: int, sp, device, max_pivots: int = 1000):
+        self.p = search_params(sp, max_pivots)
+        P, D, k = n_poses, int(sp.draws), int(sp.k)
+        self.set_pt = torch.empty((P, D, k), dtype=torch.int32, device=device)
+        self.set_link = torch.empty((P, D, k), dtype=torch.int8, device=device)
+        self.verdict = torch.empty((P, D), dtype=torch.uint8, device=device)
+        self.tstar = torch.empty((P, D), dtype=torch.float64, device=device)
+        self.acc_list = torch.empty((P * D,), dtype=torch.int32, device=device)
+        self.n_acc = torch.zeros((1,), dtype=torch.int32, device=device)
+        nb = int(_lib.lg_search_workspace_bytes(P, C.byref(self.p)))
+        self.workspace = torch.empty((nb,), dtype=torch.uint8, device=device)
+
+
+def lg_search(field: Field, pts, nrm, poses, dom_bits, dom_count, sp, bufs: Optional[SearchBuffers] = None,
+              max_pivots: int = 1000, stream=None) -> SearchBuffers:
+    N, P = int(pts.shape[1]), int(poses.shape[0])
+    if bufs is None:
+        bufs = SearchBuffers(P, sp, pts.device, max_pivots)
+    _check(_lib.lg_search(field.handle, _ptr(pts), _ptr(nrm), N, _ptr(poses), P, _ptr(dom_bits),
+                          _ptr(dom_count), C.byref(bufs.p), _ptr(bufs.set_pt), _ptr(bufs.set_link),
+                          _ptr(bufs.verdict), _ptr(bufs.tstar), _ptr(bufs.acc_list), _ptr(bufs.n_acc),
+                          _ptr(bufs.workspace), bufs.workspace.numel(), _stream(stream)), "lg_search")
+    return bufs
+
+
+def ik_params(ik) -> IkParams:
+    return IkParams(int(ik.iters), int(ik.phase1), float(ik.lam), float(ik.beta), float(ik.tol_pos),
+                    float(ik.tol_ang), float(ik.margin))
+
+
+def sdf_struct(sdf_host, values_dev: torch.Tensor) -> Sdf:
+    o = np.asarray(sdf_host.origin, np.float32)
+    return Sdf((C.c_float * 3)(*[float(x) for x in o]), float(sdf_host.h), int(sdf_host.dims),
+               C.c_void_p(values_dev.data_ptr()))
+
+
+class RealizeBuffers:
+    def __init__(self, max_acc: int, n_joints: int, k: int, device):
+        self.q = torch.empty((max_acc, n_joints), dtype=torch.float32, device=device)
+        self.contact_err = torch.empty((max_acc, k), dtype=torch.float32, device=device)
+        self.contact_ang = torch.empty((max_acc, k), dtype=torch.float32, device=device)
+        self.depth = torch.empty((max_acc,), dtype=torch.float32, device=device)
+        self.valid = torch.empty((max_acc,), dtype=torch.uint8, device=device)
+
+
+def lg_realize(field: Field, sdf: Sdf, pts, nrm, poses, set_pt, set_link, k: int, draws: int, acc_list,
+               n_acc_dev, max_acc: int, ik, bufs: Optional[RealizeBuffers] = None, stream=None):
+    N, P = int(pts.shape[1]), int(poses.shape[0])
+    if bufs is None:
+        bufs = RealizeBuffers(max_acc, field.n_joints, k, pts.device)
+    ikp = ik_params(ik)
+    _check(_lib.lg_realize(field.handle, C.byref(sdf), _ptr(pts), _ptr(nrm), N, _ptr(poses), P,
+                           _ptr(set_pt), _ptr(set_link), int(k), int(draws), _ptr(acc_list), _ptr(n_acc_dev),
+                           int(max_acc), C.byref(ikp), _ptr(bufs.q), _ptr(bufs.contact_err),
+                           _ptr(bufs.contact_ang), _ptr(bufs.depth), _ptr(bufs.valid), _stream(stream)),
+           "lg_realize")
+    return bufs
+
+
+def version() -> str:
+    return _lib.lg_version().decode()

@@ -1,0 +1,75 @@
+"""One pass of the hot path over a batch of palm poses, with every input and
+buffer resident in device memory: lg_query_domains -> lg_search ->
+lg_realize (Fig. 6 pipeline: placement given, domain generation, contact
+sets + criterion, kinematics + collision filtering)."""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import lg
+
+
+class Pipeline:
+    """Holds the object, poses and all per-step buffers of one workload.
+
+    ``step()`` enqueues the whole path on ``stream`` and returns without
+    synchronising; ``valid_count()`` synchronises and reads the result."""
+
+    def __init__(self, field: lg.Field, pts: np.ndarray, nrm: np.ndarray, poses: np.ndarray, sp,
+                 ik=None, sdf=None, device: str = "cuda", max_pivots: int = 1000):
+        self.field = field
+        self.dev = torch.device(device)
+        self.pts = torch.from_numpy(np.ascontiguousarray(np.asarray(pts, np.float32).T)).to(self.dev)
+        self.nrm = torch.from_numpy(np.ascontiguousarray(np.asarray(nrm, np.float32).T)).to(self.dev)
+        self.poses = torch.from_numpy(np.ascontiguousarray(poses, np.float32)).to(self.dev)
+        self.N, self.P = int(self.pts.shape[1]), int(self.poses.shape[0])
+        self.sp = sp
+        F = field.n_fingers
+        NW = (self.N + 31) // 32
+        self.dom_bits = torch.empty((self.P, F, NW), dtype=torch.int32, device=self.dev)
+        self.dom_count = torch.empty((self.P, F), dtype=torch.int32, device=self.dev)
+        self.sbuf = lg.SearchBuffers(self.P, sp, self.dev, max_pivots)
+        self.ik = ik
+        self.rbuf = None
+        if ik is not None:
+            if sdf is None:
+                raise ValueError("realize needs an SDF")
+            self.sdf_vals = torch.from_numpy(np.ascontiguousarray(sdf.values, np.float32)).to(self.dev)
+            self.sdf = lg.sdf_struct(sdf, self.sdf_vals)
+            self.max_acc = self.P * int(sp.draws)
+            self.rbuf = lg.RealizeBuffers(self.max_acc, field.n_joints, int(sp.k), self.dev)
+
+    def query(self, stream=None):
+        lg.lg_query_domains(self.field, self.pts, self.nrm, self.poses, self.dom_bits, self.dom_count,
+                            stream=stream)
+
+    def search(self, stream=None):
+        lg.lg_search(self.field, self.pts, self.nrm, self.poses, self.dom_bits, self.dom_count, self.sp,
+                     bufs=self.sbuf, stream=stream)
+
+    def realize(self, stream=None):
+        if self.ik is None:
+            return
+        b = self.sbuf
+        lg.lg_realize(self.field, self.sdf, self.pts, self.nrm, self.poses, b.set_pt, b.set_link,
+                      int(self.sp.k), int(self.sp.draws), b.acc_list, b.n_acc, self.max_acc, self.ik,
+                      bufs=self.rbuf, stream=stream)
+
+    def step(self, stream=None):
+        self.query(stream)
+        self.search(stream)
+        self.realize(stream)
+
+    def n_acc(self) -> int:
+        return int(self.sbuf.n_acc.item())
+
+    def valid_count(self) -> int:
+        """Valid grasps of the last step: accepted sets that pass IK and
+        penetration (with realize), else accepted (verdict) sets."""
+        n = self.n_acc()
+        if self.ik is None:
+            return n
+        return int(self.rbuf.valid[:n].sum().item())

@@ -1,0 +1,66 @@
+"""The C ABI library loads and exports every entry point declared in
+include/lg.h; argument validation rejects bad calls before any device work
+(no GPU is touched).  CPU only."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2511_07418_amd", "liblg.so")
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "lg.h")).read()
+    return sorted(set(re.findall(r"\b(lg_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lglib():
+    if not os.path.exists(LIB):
+        from paper_2511_07418_amd import build
+        build.build()
+    from paper_2511_07418_amd import lg
+    return lg
+
+
+def test_exports_every_declared_symbol(lglib):
+    L = C.CDLL(LIB)
+    names = declared()
+    assert {"lg_build_field", "lg_query_domains", "lg_search", "lg_realize"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(lglib.EXPORTED) == set(names)
+    assert lglib.version().startswith("lg-gfx950")
+
+
+def test_status_strings(lglib):
+    L = lglib.lib()
+    assert L.lg_status_str(0) == b"LG_OK"
+    assert L.lg_status_str(-1) == b"LG_EINVAL"
+
+
+def test_validation_rejects_bad_calls_without_device_work(lglib):
+    L = lglib.lib()
+    assert L.lg_query_domains(None, None, None, 0, None, 1, None, None, None) == lglib.LG_EINVAL
+    assert b"null field" in L.lg_last_error()
+    assert L.lg_search(None, None, None, 0, None, 0, None, None, None, None, None, None, None, None,
+                       None, None, 0, None) == lglib.LG_EINVAL
+    assert L.lg_realize(None, None, None, None, 0, None, 0, None, None, 0, 0, None, None, 0, None,
+                        None, None, None, None, None, None) == lglib.LG_EINVAL
+    w = synth.workload("c1", n_poses=2)
+    # 48 bins is not supported (32 or 64)
+    fp = synth.FieldParams(samples=16, seed=0, grid=8, h=0.01, bins=48, grid_frame=w.field.grid_frame)
+    with pytest.raises(lglib.LgError) as ei:
+        lglib.lg_build_field(w.hand, fp)
+    assert ei.value.status == lglib.LG_EINVAL
+    # a finger that is not a serial chain
+    bad = synth.hand_c1()
+    bad.joint_parent = bad.joint_parent.copy()
+    bad.joint_parent[2] = 0
+    with pytest.raises(lglib.LgError):
+        lglib.lg_build_field(bad, w.field)

@@ -241,3 +241,67 @@ def test_penetration_depth_closed_form():
         want = r - (dist - R)
         assert abs(depth - want) < 3 * sdf.h ** 2 / (8 * R) + 1e-6
     assert oracle.axis_samples(h, 0) == math.ceil(round(L, 6) / 1e-3 - 1e-9) + 1 or oracle.axis_samples(h, 0) > 0
+
+
+def _exact_tstar(W):
+    """Exact optimum of the same LP in rational arithmetic (Bland's rule,
+    no rounding): float inputs are converted exactly to fractions."""
+    from fractions import Fraction as Fr
+    n = W.shape[0]
+    nv = n + 12
+    A = [[Fr(0)] * (nv + 1) for _ in range(7)]
+    for r in range(6):
+        for c in range(n):
+            A[r][c] = Fr(float(W[c, r]))
+        A[r][n + r] = Fr(-1)
+        A[r][n + 6 + r] = Fr(1)
+    for c in range(n):
+        A[6][c] = Fr(1)
+    A[6][nv] = Fr(1)
+    basis = [0] * 7
+    for r in range(6):
+        f = A[r][0]
+        A[r] = [a - f * b for a, b in zip(A[r], A[6])]
+        if A[r][nv] >= 0:
+            basis[r] = n + 6 + r
+        else:
+            A[r] = [-a for a in A[r]]
+            basis[r] = n + r
+    cost = [Fr(0)] * n + [Fr(1)] * 12
+    while True:
+        red = [cost[j] - sum(cost[basis[r]] * A[r][j] for r in range(7)) for j in range(nv)]
+        e = next((j for j in range(nv) if red[j] < 0), None)
+        if e is None:
+            break
+        lr, best = None, None
+        for r in range(7):
+            if A[r][e] > 0:
+                ratio = A[r][nv] / A[r][e]
+                if lr is None or ratio < best or (ratio == best and basis[r] < basis[lr]):
+                    lr, best = r, ratio
+        pv = A[lr][e]
+        A[lr] = [a / pv for a in A[lr]]
+        for r in range(7):
+            if r != lr and A[r][e] != 0:
+                f = A[r][e]
+                A[r] = [a - f * b for a, b in zip(A[r], A[lr])]
+        basis[lr] = e
+    return float(sum(A[r][nv] for r in range(7) if basis[r] >= n))
+
+
+def test_lp_matches_exact_rational_optimum():
+    """t* equals the exact rational optimum to 1e-12 on drawn sphere sets
+    (long degenerate pivot runs included)."""
+    w = synth.workload("c1", n_poses=64)
+    fld = oracle.build_field(w.hand, w.field, flags=False)
+    Q = oracle.query(w.hand, w.field, fld["bits"], w.obj.pts, w.obj.nrm, w.poses, flags=False)
+    spt, _ = oracle.draw(w.hand, w.field, fld["bits"], w.obj.pts, w.obj.nrm, w.poses, Q["dom_bits"],
+                         Q["dom_count"], w.search)
+    sets = spt.reshape(-1, 3)
+    sets = sets[sets[:, 0] >= 0][:24]
+    assert len(sets) >= 10
+    mu, rho = float(np.float32(0.5)), float(np.float32(w.search.moment_scale))
+    for s in sets:
+        W = oracle.wrench_matrix(w.obj.pts[s].astype(np.float64), w.obj.nrm[s].astype(np.float64), mu, 8, rho)
+        t, st, _ = oracle.lp_solve(W)
+        assert st == 0 and abs(t - _exact_tstar(W)) < 1e-12
