@@ -1,0 +1,190 @@
+"""Benchmark of the Contact-Field hot path on one MI355X.
+
+A step is one pass of the whole path over one batch of palm poses with the
+field prebuilt and resident (Fig. 6: the field is built once per hand and
+cached): contact-domain query -> draws + force-closure verdicts + compaction
+-> DLS IK + penetration.  Inputs are seeded synthetic workloads (see
+``synth``), resident in HBM before the timed region.
+
+Prints ONE JSON line: valid grasps per second (whole job), the query kernel's
+roofline (algorithmic bytes / measured kernel time vs 8 TB/s HBM), per-stage
+times, and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "valid grasps/sec per object (1 GPU); field-query HBM GB/s; p50/p99 latency"
+HBM_PEAK_GBPS = 8000.0
+
+DESCR = {
+    "c1": "3-finger 9-DOF hand, sphere R=40mm N=2048, P=256, D=16, k=3, field 32^3@4mm B=32 S=8192",
+    "c2": "4-finger 16-DOF hand, superquadric N=16384, P=16384, D=32, k=4, field 64^3@3mm B=64 S=262144",
+    "c3": "5-finger 22-DOF hand, tool union N=65536, P=65536, D=64, k=5, field 64^3@3mm B=64 S=262144, "
+          "IK 10 it lambda=1e-2, SDF 64^3",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-poses", type=int, default=0, help="poses of the CPU-oracle sample (0 = auto)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def in_window_lookups(torch, pipe, w) -> int:
+    """Exact number of (pose, point, finger) triples whose point lies inside
+    the finger's window (each needs one W-byte table word), counted on the
+    device in float32 (the query's precision)."""
+    gf = torch.from_numpy(np.asarray(w.field.grid_frame, np.float32).reshape(-1, 3, 4)).cuda()
+    Rg, og = gf[:, :, :3], gf[:, :, 3]
+    G, h = w.field.grid, float(np.float32(w.field.h))
+    pts = pipe.pts  # [3, N]
+    total = 0
+    chunk = max(1, int(2 ** 26 // (pts.shape[1] * gf.shape[0])))
+    for g0 in range(0, pipe.P, chunk):
+        P = pipe.poses[g0:g0 + chunk].reshape(-1, 3, 4)
+        x = P[:, :, :3] @ pts + P[:, :, 3:4]                                # [p, 3, N]
+        u = torch.einsum("fab,pan->pfbn", Rg, x) - torch.einsum("fab,fa->fb", Rg, og)[None, :, :, None]
+        u = u / h
+        inside = ((u >= 0) & (u < G)).all(dim=2)
+        total += int(inside.sum().item())
+    return total
+
+
+def cpu_baseline(w, n_poses: int, samples: int) -> dict:
+    """The FP64 oracle, as it stands, on the first ``n_poses`` poses: query,
+    draws, verdicts, compaction and (with an SDF) IK + penetration.  Its field
+    is the oracle's own, built untimed with ``samples`` joint samples per
+    finger (the step itself does not depend on S, only the field density)."""
+    import dataclasses
+
+    import oracle
+    import synth
+
+    fp = dataclasses.replace(w.field, samples=min(samples, w.field.samples))
+    sub = synth.Workload(name=w.name, hand=w.hand, field=fp, obj=w.obj, poses=w.poses[:n_poses],
+                         search=w.search, ik=w.ik, sdf=w.sdf)
+    fld = oracle.build_field(sub.hand, sub.field, witness=sub.ik is not None, flags=False)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    Q = oracle.query(sub.hand, sub.field, fld["bits"], sub.obj.pts, sub.obj.nrm, sub.poses, flags=False)
+    spt, sln = oracle.draw(sub.hand, sub.field, fld["bits"], sub.obj.pts, sub.obj.nrm, sub.poses,
+                           Q["dom_bits"], Q["dom_count"], sub.search)
+    V = oracle.verdicts(sub.obj.pts, sub.obj.nrm, spt, sub.search)
+    acc = oracle.compact(V["verdict"])
+    n_valid = len(acc)
+    if sub.ik is not None and len(acc):
+        k = sub.search.k
+        R = oracle.realize(sub.hand, sub.field, fld["wit"], sub.sdf, sub.obj.pts, sub.obj.nrm, sub.poses,
+                           spt.reshape(-1, k), sln.reshape(-1, k), sub.search, acc, sub.ik)
+        n_valid = int(R["valid"].sum())
+    dt = time.perf_counter() - t0
+    return {"value": n_valid / dt, "unit": "valid grasps/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n_poses} of {w.poses.shape[0]} poses of the same workload, full N and D; "
+                      f"oracle-built field with S={fp.samples} (untimed); {n_valid} valid grasps in {dt:.2f} s",
+            "seconds": dt, "poses_per_s": n_poses / dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import synth
+    from paper_2511_07418_amd import lg
+    from paper_2511_07418_amd.pipeline import Pipeline
+
+    torch.cuda.set_device(0)
+    w = synth.workload(args.workload, seed=args.seed, with_sdf=(args.workload == "c3"))
+    t_build = time.perf_counter()
+    field = lg.lg_build_field(w.hand, w.field, keep_witness=w.ik is not None)
+    t_build = time.perf_counter() - t_build
+    pipe = Pipeline(field, w.obj.pts, w.obj.nrm, w.poses, w.search, ik=w.ik, sdf=w.sdf)
+    print(f"[bench] {args.workload}: field built in {t_build:.2f}s ({field.info()['bits_set']} bits), "
+          f"P={pipe.P} N={pipe.N}", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        pipe.step()
+    torch.cuda.synchronize()
+
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    valid = []
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        e = ev[s]
+        e[0].record()
+        pipe.query()
+        e[1].record()
+        pipe.search()
+        e[2].record()
+        pipe.realize()
+        e[3].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n_valid = pipe.valid_count()
+    n_acc = pipe.n_acc()
+    st = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in ev])  # ms
+    ms_per_step = wall * 1000.0 / args.steps
+    value = n_valid / (ms_per_step / 1000.0)
+
+    # query roofline: algorithmic bytes per launch / measured query time
+    W = w.field.bins // 8
+    lookups = in_window_lookups(torch, pipe, w)
+    F = w.hand.n_fingers
+    NW = (pipe.N + 31) // 32
+    alg_bytes = lookups * W + pipe.P * F * NW * 4 + pipe.P * 48 + pipe.N * 24
+    q_ms = float(st[:, 0].mean())
+    achieved = alg_bytes / (q_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "valid grasps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {DESCR[args.workload]}", "poses_per_step": pipe.P,
+                   "points": pipe.N, "draws": int(w.search.draws), "seed": args.seed},
+        "valid_per_step": n_valid,
+        "accepted_sets_per_step": n_acc,
+        "stage_ms": {"query": q_ms, "search": float(st[:, 1].mean()), "realize": float(st[:, 2].mean())},
+        "query_gbps": achieved,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "k_query", "alg_bytes_per_launch": alg_bytes,
+                     "in_window_lookups": lookups},
+    }
+    if not args.no_cpu_baseline:
+        n = args.cpu_poses or {"c1": 256, "c2": 2048, "c3": 1024}[args.workload]
+        out["cpu_baseline"] = cpu_baseline(w, n, samples=16384)
+    out["poses_per_s"] = pipe.P / (ms_per_step / 1000.0)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
