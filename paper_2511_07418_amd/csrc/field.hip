@@ -88,6 +88,55 @@ __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
+// Candidate table of the normal bins over a cube map of directions: a
+// direction d is mapped to face (major axis, sign) and cell (iu, iv) of a
+// kLutRes x kLutRes grid over (d_b, d_c) / |d_a|.  A cell lists, in increasing
+// order, every bin whose dot product can come within kLutMargin of the best
+// one anywhere in the cell (checked on a dense sub-grid of the cell; the
+// margin exceeds the dot-product variation between sub-grid points), so the
+// argmax over the candidates equals the argmax over all bins.  Cells with
+// more than four candidates are marked for the full search (0xffffffff).
+static void build_bin_lut(const std::vector<float> &bc, int B, std::vector<uint32_t> &lut)
+{
+    const int R = kLutRes, SUB = 9;
+    lut.assign(6 * R * R, 0xffffffffu);
+    const double sub_step = 2.0 / R / (SUB - 1);           // in face coordinates
+    const double margin = 2.0 * sub_step + 1e-4;            // angular spacing <= coordinate spacing
+    for (int face = 0; face < 6; ++face) {
+        const int a = face >> 1, bax = (a + 1) % 3, cax = (a + 2) % 3;
+        const double sg = (face & 1) ? -1.0 : 1.0;
+        for (int iv = 0; iv < R; ++iv)
+            for (int iu = 0; iu < R; ++iu) {
+                std::vector<int> cand;
+                for (int sv = 0; sv < SUB; ++sv)
+                    for (int su = 0; su < SUB; ++su) {
+                        const double u = -1.0 + 2.0 * (iu + (double)su / (SUB - 1)) / R;
+                        const double v = -1.0 + 2.0 * (iv + (double)sv / (SUB - 1)) / R;
+                        double d[3];
+                        d[a] = sg;
+                        d[bax] = u;
+                        d[cax] = v;
+                        const double nd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                        double best = -1e300, dots[kMaxBins];
+                        for (int b = 0; b < B; ++b) {
+                            dots[b] = (bc[3 * b] * d[0] + bc[3 * b + 1] * d[1] + bc[3 * b + 2] * d[2]) / nd;
+                            best = std::max(best, dots[b]);
+                        }
+                        for (int b = 0; b < B; ++b)
+                            if (dots[b] >= best - margin && std::find(cand.begin(), cand.end(), b) == cand.end())
+                                cand.push_back(b);
+                    }
+                std::sort(cand.begin(), cand.end());
+                if (cand.size() <= 4) {
+                    uint32_t e = 0xffffffffu;
+                    for (size_t i = 0; i < cand.size(); ++i)
+                        e = (e & ~(0xffu << (8 * i))) | ((uint32_t)cand[i] << (8 * i));
+                    lut[(face * R + iv) * R + iu] = e;
+                }
+            }
+    }
+}
+
 // Copy the hand, compute bin centres and axis sample counts on the host,
 // upload them and allocate the (zeroed) tables.
 lg_status make_field_shell(const lg_hand_desc *hand, const lg_field_params *p, lg_field **out)
@@ -115,6 +164,8 @@ lg_status make_field_shell(const lg_hand_desc *hand, const lg_field_params *p, l
         f->bin_c[3 * b + 1] = (float)(r * sin(ph));
         f->bin_c[3 * b + 2] = (float)z;
     }
+    std::vector<uint32_t> lut;
+    build_bin_lut(f->bin_c, B, lut);
     // capsule axis samples for the penetration test: one per mm, ends included
     f->axis_samples.resize(J);
     for (int j = 0; j < J; ++j) {
@@ -153,11 +204,14 @@ lg_status make_field_shell(const lg_hand_desc *hand, const lg_field_params *p, l
     const size_t n_origin = f->origin.size(), n_axis = f->axis.size(), n_cap = f->capsule.size(),
                  n_lim = f->limits.size(), n_surf = f->surf.size(), n_gf = f->grid_frame.size(),
                  n_bc = f->bin_c.size();
-    const size_t n_all = n_origin + n_axis + n_cap + n_lim + n_surf + n_gf + n_bc;
+    const size_t n_lut = lut.size();
+    const size_t n_all = n_origin + n_axis + n_cap + n_lim + n_surf + n_gf + n_bc + n_lut;
     std::vector<float> packed;
     packed.reserve(n_all);
     for (auto *v : {&f->origin, &f->axis, &f->capsule, &f->limits, &f->surf, &f->grid_frame, &f->bin_c})
         packed.insert(packed.end(), v->begin(), v->end());
+    packed.resize(n_all);
+    memcpy(packed.data() + (n_all - n_lut), lut.data(), n_lut * sizeof(uint32_t));
     const int64_t G3 = (int64_t)G * G * G;
     hipError_t e = hipMalloc(&f->d_params, n_all * sizeof(float));
     if (e == hipSuccess) e = hipMemcpy(f->d_params, packed.data(), n_all * sizeof(float), hipMemcpyHostToDevice);
@@ -200,6 +254,8 @@ lg_status make_field_shell(const lg_hand_desc *hand, const lg_field_params *p, l
     H.grid_frame = base;
     base += n_gf;
     H.bin_c = base;
+    base += n_bc;
+    H.bin_lut = reinterpret_cast<const uint32_t *>(base);
     H.axis_samples = f->d_axis_samples;
     *out = f;
     return LG_OK;

@@ -22,6 +22,7 @@ constexpr int kMaxBins = 64;
 constexpr uint32_t kPurposeJoint = 1u;
 constexpr uint32_t kPurposeDraw = 3u;
 constexpr int32_t kNoWitness = 0x7fffffff;
+constexpr int kLutRes = 32;  // cube-map cells per face edge of the bin table
 
 // Device-side description of a hand and its field window (kernel argument).
 struct DevHand {
@@ -37,6 +38,7 @@ struct DevHand {
     const float *surf;        // [J][nsurf][6]
     const float *grid_frame;  // [F][12]
     const float *bin_c;       // [B][3]
+    const uint32_t *bin_lut;  // [6][kLutRes][kLutRes] candidate bins (4 x 8 bit), 0xffffffff = all
     const int32_t *axis_samples;  // [J]
     int finger_first[kMaxFingers];
     int finger_dof[kMaxFingers];
@@ -230,6 +232,49 @@ __device__ inline int nearest_bin(const float *c, int B, float dx, float dy, flo
         if (s > best) {
             best = s;
             bi = b;
+        }
+    }
+    return bi;
+}
+
+// Same result as nearest_bin, through the cube-map candidate table.
+__device__ inline int nearest_bin_lut(const uint32_t *lut, const float *c, int B, float dx, float dy, float dz)
+{
+    const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+    int face;
+    float m, u, v;
+    if (ax >= ay && ax >= az) {
+        face = dx < 0.f ? 1 : 0;
+        m = ax;
+        u = dy;
+        v = dz;
+    } else if (ay >= az) {
+        face = dy < 0.f ? 3 : 2;
+        m = ay;
+        u = dz;
+        v = dx;
+    } else {
+        face = dz < 0.f ? 5 : 4;
+        m = az;
+        u = dx;
+        v = dy;
+    }
+    const float s = (0.5f * kLutRes) / m;
+    const int iu = min(max((int)fmaf(u, s, 0.5f * kLutRes), 0), kLutRes - 1);
+    const int iv = min(max((int)fmaf(v, s, 0.5f * kLutRes), 0), kLutRes - 1);
+    const uint32_t e = lut[(face * kLutRes + iv) * kLutRes + iu];
+    if (e == 0xffffffffu) return nearest_bin(c, B, dx, dy, dz);
+    float best = -3.0e38f;
+    int bi = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t b = (e >> (8 * i)) & 0xffu;
+        if (b != 0xffu) {
+            const float sc = fmaf(c[3 * b], dx, fmaf(c[3 * b + 1], dy, c[3 * b + 2] * dz));
+            if (sc > best) {
+                best = sc;
+                bi = (int)b;
+            }
         }
     }
     return bi;

@@ -16,26 +16,20 @@ namespace lg {
 constexpr int kQueryThreads = 256;
 constexpr int kQueryWaves = kQueryThreads / 64;
 
-template <int W>
-__device__ inline bool merged_hit(const uint32_t *__restrict__ tab, int v, int b)
-{
-    if (W == 1) return (tab[v] >> b) & 1u;
-    const uint64_t w = reinterpret_cast<const uint64_t *>(tab)[v];
-    return (w >> b) & 1ull;
-}
-
-template <int W>
+template <int W, int FM>
 __global__ void __launch_bounds__(kQueryThreads)
 k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict__ pts,
         const float *__restrict__ nrm, int N, const float *__restrict__ poses,
         uint32_t *__restrict__ dom_bits, uint32_t *__restrict__ dom_count)
 {
     __shared__ float cb[3 * kMaxBins];
-    __shared__ Affine aff[kMaxFingers];
-    __shared__ uint32_t cnt[kMaxFingers][kQueryWaves];
+    __shared__ uint32_t lut[6 * kLutRes * kLutRes];
+    __shared__ Affine aff[FM];
+    __shared__ uint32_t cnt[FM][kQueryWaves];
     const int g = blockIdx.x;
     const float *pose = poses + 12 * (int64_t)g;
     for (int i = threadIdx.x; i < 3 * H.B; i += blockDim.x) cb[i] = H.bin_c[i];
+    for (int i = threadIdx.x; i < 6 * kLutRes * kLutRes; i += blockDim.x) lut[i] = H.bin_lut[i];
     if (threadIdx.x < H.F) aff[threadIdx.x] = finger_affine(H, pose, threadIdx.x);
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -45,9 +39,9 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
     float P[12];
 #pragma unroll
     for (int i = 0; i < 12; ++i) P[i] = pose[i];
-    uint32_t c[kMaxFingers];
+    uint32_t c[FM];
 #pragma unroll
-    for (int f = 0; f < kMaxFingers; ++f) c[f] = 0;
+    for (int f = 0; f < FM; ++f) c[f] = 0;
     for (int chunk = wave; chunk < nchunks; chunk += kQueryWaves) {
         const int i = chunk * 64 + lane;
         const bool valid = i < N;
@@ -60,14 +54,28 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
             ny = nrm[N + i];
             nz = nrm[2 * N + i];
         }
+        // all finger gathers are issued before any is consumed
+        uint64_t word[FM];
+#pragma unroll
+        for (int f = 0; f < FM; ++f) {
+            word[f] = 0;
+            if (f < F) {
+                const int v = window_voxel(aff[f], G, px, py, pz);
+                if (valid && v >= 0) {
+                    if (W == 1)
+                        word[f] = merged[f * G3W + v];
+                    else
+                        word[f] = reinterpret_cast<const uint64_t *>(merged + f * G3W)[v];
+                }
+            }
+        }
         float qx, qy, qz;
         query_dir(P, nx, ny, nz, qx, qy, qz);
-        const int b = nearest_bin(cb, B, qx, qy, qz);
+        const int b = nearest_bin_lut(lut, cb, B, qx, qy, qz);
 #pragma unroll
-        for (int f = 0; f < kMaxFingers; ++f) {
+        for (int f = 0; f < FM; ++f) {
             if (f >= F) break;
-            const int v = window_voxel(aff[f], G, px, py, pz);
-            const bool hit = valid && v >= 0 && merged_hit<W>(merged + f * G3W, v, b);
+            const bool hit = (word[f] >> b) & 1ull;
             const unsigned long long m = __ballot(hit);
             c[f] += (uint32_t)__popcll(m);
             const int wi = 2 * chunk + lane;
@@ -77,7 +85,7 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
     }
     if (lane == 0) {
 #pragma unroll
-        for (int f = 0; f < kMaxFingers; ++f)
+        for (int f = 0; f < FM; ++f)
             if (f < F) cnt[f][wave] = c[f];
     }
     __syncthreads();
@@ -103,12 +111,15 @@ extern "C" lg_status lg_query_domains(const lg_field *field, const float *pts, c
         return fail(LG_EINVAL, "null device buffer");
     hipStream_t s = as_stream(stream);
     const DevHand &H = field->dh;
-    if (H.W == 1)
-        hipLaunchKernelGGL(k_query<1>, dim3(n_poses), dim3(kQueryThreads), 0, s, H, field->d_merged, pts, nrm,
-                           n_points, poses, dom_bits, dom_count);
-    else
-        hipLaunchKernelGGL(k_query<2>, dim3(n_poses), dim3(kQueryThreads), 0, s, H, field->d_merged, pts, nrm,
-                           n_points, poses, dom_bits, dom_count);
+#define LG_QUERY(W, FM)                                                                                     \
+    hipLaunchKernelGGL((k_query<W, FM>), dim3(n_poses), dim3(kQueryThreads), 0, s, H, field->d_merged, pts, nrm, \
+                       n_points, poses, dom_bits, dom_count)
+    if (H.W == 1) {
+        if (H.F <= 3) LG_QUERY(1, 3); else if (H.F <= 4) LG_QUERY(1, 4); else if (H.F <= 5) LG_QUERY(1, 5); else LG_QUERY(1, 8);
+    } else {
+        if (H.F <= 3) LG_QUERY(2, 3); else if (H.F <= 4) LG_QUERY(2, 4); else if (H.F <= 5) LG_QUERY(2, 5); else LG_QUERY(2, 8);
+    }
+#undef LG_QUERY
     LG_HIP(hipGetLastError());
     return LG_OK;
 }

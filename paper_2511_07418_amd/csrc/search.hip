@@ -11,7 +11,6 @@ namespace lg {
 
 constexpr int kDrawThreads = 256;
 constexpr int kSuper = 8;           // words per rank superblock
-constexpr int kVerdictWaves = 4;    // sets (waves) per verdict workgroup
 constexpr int kChunkPerThread = 32; // compaction: sets per thread
 constexpr int kCompactThreads = 256;
 constexpr int kChunk = kChunkPerThread * kCompactThreads;
@@ -116,7 +115,7 @@ k_draw(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ p
     }
 }
 
-// ---- force-closure LP, one wave per set ------------------------------------
+// ---- force-closure LP ---------------------------------------------------------
 // Duff et al. (2017) branchless orthonormal basis of unit n.
 __device__ inline void duff_basis(double nx, double ny, double nz, double *x, double *y)
 {
@@ -134,190 +133,215 @@ __device__ inline void duff_basis(double nx, double ny, double nz, double *x, do
 constexpr double kLpTol = 1e-12;  // reduced-cost and ratio-tie tolerance
 constexpr double kLpPiv = 1e-9;   // smallest admissible pivot element
 
-// Tableau simplex with the columns spread over the 64 lanes (lane j holds
-// column j of B^-1 A and its reduced cost); the right-hand side and basis
-// are replicated in every lane.  Columns: g_0..g_{km-1}, s+_0..s+_5,
-// s-_0..s-_5.  Bland's rule: lowest entering index, ratio ties to the lowest
-// basic variable.  When no reduced cost is negative, the basis is re-inverted
-// from the original columns (lane-parallel Gauss-Jordan on [B | I] in lanes
-// 0..13) and optimality is re-checked, so rounding accumulated over long
-// degenerate pivot runs cannot end the search early.  Double precision: the
+// ---- force-closure LP, one set per lane -------------------------------------
+// Revised simplex with an explicit 7x7 basis inverse per lane.  Reduced
+// costs are priced through the duals y = c_B^T B^-1: for wrench column
+// (contact i, edge e),
+//   y^T a_ie = u_i . d_ie + y_6,  u_i = y_f + (y_m x p_i) / rho,
+//   u_i . d_ie = -u_i.n_i + mu (cos_e u_i.x_i + sin_e u_i.y_i),
+// so pricing all k*m columns costs O(k) dot products plus 2 FMAs per edge.
+// Bland's rule: lowest entering index, ratio ties to the lowest basic
+// variable; pivots below kLpPiv are not admissible.  Double precision: the
 // verdict is a thresholded decision and the LP is latency-bound.
-__global__ void __launch_bounds__(64 * kVerdictWaves)
-k_verdict(const float *__restrict__ pts, const float *__restrict__ nrm, int N, const int32_t *__restrict__ set_pt,
-          int64_t n_sets, int k, int m, double mu, double rho, double eps, int max_pivots,
-          uint8_t *__restrict__ verdict, double *__restrict__ tstar)
+// At a candidate optimum x_B and y are refined twice against the original
+// columns (residual correction through the current B^-1) and the pricing is
+// repeated, so drift in B^-1 cannot end the search early or bias t*.
+struct LpConst {
+    double ce[16], se[16];  // cos, sin of 2 pi e / m
+};
+
+template <int KM>
+__global__ void __launch_bounds__(256)
+k_verdict_lane(const float *__restrict__ pts, const float *__restrict__ nrm, int N, const int32_t *__restrict__ set_pt,
+               int64_t n_sets, int k, int m, double mu, double rho, double eps, int max_pivots, LpConst cs,
+               uint8_t *__restrict__ verdict, double *__restrict__ tstar)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t sid = (int64_t)blockIdx.x * kVerdictWaves + (threadIdx.x >> 6);
-    if (sid >= n_sets) return;  // whole wave
+    // contact data of this lane's set in LDS, lane-contiguous: cd[6*i + c][tid]
+    __shared__ float cd[KM * 6][256];
+    const int tid = threadIdx.x;
+    const int64_t sid = (int64_t)blockIdx.x * blockDim.x + tid;
+    if (sid >= n_sets) return;  // no block-level synchronisation below
     const int32_t *sp = set_pt + sid * k;
     bool valid = true;
-    for (int i = 0; i < k; ++i) valid &= sp[i] >= 0;
+    for (int i = 0; i < k; ++i) {
+        const int idx = sp[i];
+        valid &= idx >= 0;
+        const int ii = idx >= 0 ? idx : 0;
+        cd[6 * i + 0][tid] = pts[ii];
+        cd[6 * i + 1][tid] = pts[N + ii];
+        cd[6 * i + 2][tid] = pts[2 * N + ii];
+        cd[6 * i + 3][tid] = nrm[ii];
+        cd[6 * i + 4][tid] = nrm[N + ii];
+        cd[6 * i + 5][tid] = nrm[2 * N + ii];
+    }
     if (!valid) {
-        if (lane == 0) {
-            verdict[sid] = 0;
-            tstar[sid] = __builtin_nan("");
-        }
+        verdict[sid] = 0;
+        tstar[sid] = __builtin_nan("");
         return;
     }
-    const int n = k * m, nv = n + 12;
-    // this lane's original column A_j (7 rows) and the first wrench column w_0
-    double col[7], w0[6];
-    auto wrench = [&](int c, double *w) {
-        const int i = c / m, e = c % m;
-        const int idx = sp[i];
-        const double px = pts[idx], py = pts[N + idx], pz = pts[2 * N + idx];
-        const double nx = nrm[idx], ny = nrm[N + idx], nz = nrm[2 * N + idx];
-        double x[3], y[3];
-        duff_basis(nx, ny, nz, x, y);
-        const double th = 2.0 * M_PI * e / m;
-        const double ce = cos(th), se = sin(th);
-        const double dx = -nx + mu * (ce * x[0] + se * y[0]);
-        const double dy = -ny + mu * (ce * x[1] + se * y[1]);
-        const double dz = -nz + mu * (ce * x[2] + se * y[2]);
-        w[0] = dx;
-        w[1] = dy;
-        w[2] = dz;
-        w[3] = (py * dz - pz * dy) / rho;
-        w[4] = (pz * dx - px * dz) / rho;
-        w[5] = (px * dy - py * dx) / rho;
+    const int n = k * m;
+    // contact i's point and normal (each lane reads only its own column)
+    auto contact = [&](int ci, double &px, double &py, double &pz, double &nx, double &ny, double &nz) {
+        px = cd[6 * ci + 0][tid];
+        py = cd[6 * ci + 1][tid];
+        pz = cd[6 * ci + 2][tid];
+        nx = cd[6 * ci + 3][tid];
+        ny = cd[6 * ci + 4][tid];
+        nz = cd[6 * ci + 5][tid];
     };
-    wrench(0, w0);
     // original column j of [W^T -I I; 1 0 0]
-    auto orig_col = [&](int j, double *a) {
+    auto column = [&](int j, double *a) {
 #pragma unroll
         for (int r = 0; r < 7; ++r) a[r] = 0.0;
         if (j < n) {
-            double w[6];
-            wrench(j, w);
-#pragma unroll
-            for (int r = 0; r < 6; ++r) a[r] = w[r];
+            const int ci = j / m, e = j - ci * m;
+            double px, py, pz, nx, ny, nz;
+            contact(ci, px, py, pz, nx, ny, nz);
+            double x[3], y[3];
+            duff_basis(nx, ny, nz, x, y);
+            const double c = cs.ce[e], s = cs.se[e];
+            const double dx = -nx + mu * (c * x[0] + s * y[0]);
+            const double dy = -ny + mu * (c * x[1] + s * y[1]);
+            const double dz = -nz + mu * (c * x[2] + s * y[2]);
+            a[0] = dx;
+            a[1] = dy;
+            a[2] = dz;
+            a[3] = (py * dz - pz * dy) / rho;
+            a[4] = (pz * dx - px * dz) / rho;
+            a[5] = (px * dy - py * dx) / rho;
             a[6] = 1.0;
         } else if (j < n + 6) {
 #pragma unroll
             for (int r = 0; r < 6; ++r) a[r] = (r == j - n) ? -1.0 : 0.0;
-        } else if (j < nv) {
+        } else {
 #pragma unroll
             for (int r = 0; r < 6; ++r) a[r] = (r == j - n - 6) ? 1.0 : 0.0;
         }
     };
-    orig_col(lane, col);
-    // initial basis: g_0 on the normalisation row, a slack per wrench row
-    double rhs[7];
+    // initial basis: g_0 on the normalisation row, s-_r (w0_r <= 0) or s+_r
+    double Bi[7][7], xB[7];
     int basis[7];
-#pragma unroll
-    for (int r = 0; r < 6; ++r) {
-        col[r] -= w0[r] * col[6];
-        rhs[r] = -w0[r];
-        if (rhs[r] >= 0.0) {
-            basis[r] = n + 6 + r;
-        } else {
-            col[r] = -col[r];
-            rhs[r] = -rhs[r];
-            basis[r] = n + r;
-        }
-    }
-    rhs[6] = 1.0;
-    basis[6] = 0;
-    auto reduced_cost = [&]() {
-        double rc0 = (lane >= n && lane < nv) ? 1.0 : 0.0;
+    {
+        double w0[7];
+        column(0, w0);
 #pragma unroll
         for (int r = 0; r < 7; ++r)
-            if (basis[r] >= n) rc0 -= col[r];
-        return rc0;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) Bi[r][c] = 0.0;
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            const double sg = w0[r] <= 0.0 ? 1.0 : -1.0;
+            basis[r] = w0[r] <= 0.0 ? n + 6 + r : n + r;
+            Bi[r][r] = sg;
+            Bi[r][6] = -sg * w0[r];
+            xB[r] = -sg * w0[r];
+        }
+        Bi[6][6] = 1.0;
+        basis[6] = 0;
+        xB[6] = 1.0;
+    }
+    auto cost = [&](int j) { return j >= n ? 1.0 : 0.0; };
+    auto duals = [&](double *y) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < 7; ++r) s += cost(basis[r]) * Bi[r][c];
+            y[c] = s;
+        }
     };
-    double rc = reduced_cost();
-    int piv = 0, status = 0, checks = 0;
-    for (;;) {
-        const bool neg = lane < nv && rc < -kLpTol;
-        const unsigned long long mneg = __ballot(neg);
-        if (!mneg) {
-            if (checks >= 4) break;
-            ++checks;
-            // re-invert: lanes 0..6 hold columns of B, lanes 7..13 of I
-            double m[7];
-            if (lane < 7) {
-                int bj = 0;
-#pragma unroll
-                for (int r = 0; r < 7; ++r) bj = r == lane ? basis[r] : bj;
-                orig_col(bj, m);
-            } else {
-#pragma unroll
-                for (int r = 0; r < 7; ++r) m[r] = (lane - 7 == r) ? 1.0 : 0.0;
-            }
-            bool singular = false;
-#pragma unroll
-            for (int c = 0; c < 7; ++c) {
-                double cc[7];
-#pragma unroll
-                for (int r = 0; r < 7; ++r) cc[r] = __shfl(m[r], c, 64);
-                int p = c;
-                double pa = fabs(cc[c]);
-#pragma unroll
-                for (int r = c + 1; r < 7; ++r)
-                    if (fabs(cc[r]) > pa) {
-                        pa = fabs(cc[r]);
-                        p = r;
-                    }
-                singular |= !(pa > 1e-300);
-                // swap rows p and c
-                double mp = 0.0, cp = 0.0;
-#pragma unroll
-                for (int r = 0; r < 7; ++r)
-                    if (r == p) {
-                        mp = m[r];
-                        cp = cc[r];
-                    }
-#pragma unroll
-                for (int r = 0; r < 7; ++r)
-                    if (r == p) {
-                        m[r] = m[c];
-                        cc[r] = cc[c];
-                    }
-                m[c] = mp;
-                cc[c] = cp;
-                const double inv = 1.0 / cc[c];
-                m[c] *= inv;
-#pragma unroll
-                for (int r = 0; r < 7; ++r)
-                    if (r != c) m[r] -= cc[r] * m[c];
-            }
-            if (singular) break;
-            // tableau column of this lane and the right-hand side from B^-1
-            double a[7], t[7];
-            orig_col(lane, a);
-#pragma unroll
-            for (int r = 0; r < 7; ++r) t[r] = 0.0;
-#pragma unroll
-            for (int i = 0; i < 7; ++i) {
-#pragma unroll
-                for (int r = 0; r < 7; ++r) {
-                    const double bi = __shfl(m[r], 7 + i, 64);  // B^-1[r][i]
-                    t[r] += bi * a[i];
-                    if (i == 6) rhs[r] = bi;                    // B^-1 e_6
+    // Bland pricing: first column with a negative reduced cost, -1 if none
+    auto price = [&](const double *y) {
+        int e = -1;
+        for (int i = 0; i < k && e < 0; ++i) {
+            double px, py, pz, nx, ny, nz;
+            contact(i, px, py, pz, nx, ny, nz);
+            // u = y_f + (y_m x p) / rho
+            const double ux = y[0] + (y[4] * pz - y[5] * py) / rho;
+            const double uy = y[1] + (y[5] * px - y[3] * pz) / rho;
+            const double uz = y[2] + (y[3] * py - y[4] * px) / rho;
+            double x[3], yy[3];
+            duff_basis(nx, ny, nz, x, yy);
+            const double an = ux * nx + uy * ny + uz * nz;
+            const double bx = ux * x[0] + uy * x[1] + uz * x[2];
+            const double by = ux * yy[0] + uy * yy[1] + uz * yy[2];
+            for (int ee = 0; ee < m; ++ee) {
+                const double d = -(-an + mu * (cs.ce[ee] * bx + cs.se[ee] * by)) - y[6];
+                if (d < -kLpTol) {
+                    e = i * m + ee;
+                    break;
                 }
             }
+        }
+        for (int r = 0; r < 6 && e < 0; ++r)
+            if (1.0 + y[r] < -kLpTol) e = n + r;
+        for (int r = 0; r < 6 && e < 0; ++r)
+            if (1.0 - y[r] < -kLpTol) e = n + 6 + r;
+        return e;
+    };
+    // residual corrections of x_B (B x = e_6) and y (B^T y = c_B)
+    auto refine = [&](double *y) {
+        for (int pass = 0; pass < 2; ++pass) {
+            double rx[7] = {0, 0, 0, 0, 0, 0, 1.0}, ry[7];
+#pragma unroll 1
+            for (int q = 0; q < 7; ++q) {
+                double a[7];
+                column(basis[q], a);
+                double dot = 0.0;
 #pragma unroll
-            for (int r = 0; r < 7; ++r) col[r] = t[r];
-            rc = reduced_cost();
-            continue;
+                for (int r = 0; r < 7; ++r) {
+                    rx[r] -= a[r] * xB[q];
+                    dot += a[r] * y[r];
+                }
+                ry[q] = cost(basis[q]) - dot;
+            }
+#pragma unroll
+            for (int r = 0; r < 7; ++r) {
+                double s = 0.0;
+#pragma unroll
+                for (int c = 0; c < 7; ++c) s += Bi[r][c] * rx[c];
+                xB[r] += s;
+            }
+#pragma unroll
+            for (int c = 0; c < 7; ++c) {
+                double s = 0.0;
+#pragma unroll
+                for (int r = 0; r < 7; ++r) s += ry[r] * Bi[r][c];
+                y[c] += s;
+            }
+        }
+    };
+    int piv = 0, status = 0, checks = 0;
+    for (;;) {
+        double y[7];
+        duals(y);
+        int e = price(y);
+        if (e < 0) {
+            if (checks >= 4) break;
+            ++checks;
+            refine(y);
+            e = price(y);
+            if (e < 0) break;
         }
         if (piv >= max_pivots) {
             status = 1;
             break;
         }
-        const int e = __ffsll((long long)mneg) - 1;
-        double ce[7];
+        double a[7], al[7];
+        column(e, a);
 #pragma unroll
-        for (int r = 0; r < 7; ++r) ce[r] = __shfl(col[r], e, 64);
-        const double rce = __shfl(rc, e, 64);
+        for (int r = 0; r < 7; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) s += Bi[r][c] * a[c];
+            al[r] = s;
+        }
         int lr = -1;
         double best = 0.0;
 #pragma unroll
         for (int r = 0; r < 7; ++r) {
-            if (ce[r] > kLpPiv) {
-                const double ratio = rhs[r] / ce[r];
+            if (al[r] > kLpPiv) {
+                const double ratio = xB[r] / al[r];
                 const double tol = kLpTol * (1.0 + fabs(best));
                 if (lr < 0 || ratio < best - tol || (fabs(ratio - best) <= tol && basis[r] < basis[lr])) {
                     lr = r;
@@ -329,39 +353,42 @@ k_verdict(const float *__restrict__ pts, const float *__restrict__ nrm, int N, c
             status = 2;
             break;
         }
-        double pv = 0.0;
+        double pv = 1.0, prow[7], px = 0.0;
 #pragma unroll
-        for (int r = 0; r < 7; ++r) pv = r == lr ? ce[r] : pv;
-        double prow = 0.0, prhs = 0.0;
-#pragma unroll
-        for (int r = 0; r < 7; ++r) {
-            if (r == lr) {
-                prow = col[r] / pv;
-                prhs = rhs[r] / pv;
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < 7; ++r) {
-            if (r == lr) {
-                col[r] = prow;
-                rhs[r] = prhs;
-                basis[r] = e;
-            } else {
-                col[r] -= ce[r] * prow;
-                rhs[r] -= ce[r] * prhs;
-            }
-        }
-        rc -= rce * prow;
-        ++piv;
-    }
-    if (lane == 0) {
-        double t = 0.0;
+        for (int c = 0; c < 7; ++c) prow[c] = 0.0;
 #pragma unroll
         for (int r = 0; r < 7; ++r)
-            if (basis[r] >= n) t += rhs[r];
-        verdict[sid] = (status == 0 && t <= eps) ? 1 : 0;
-        tstar[sid] = status == 0 ? t : __builtin_nan("");
+            if (r == lr) {
+                pv = al[r];
+                px = xB[r];
+#pragma unroll
+                for (int c = 0; c < 7; ++c) prow[c] = Bi[r][c];
+            }
+        const double inv = 1.0 / pv;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) prow[c] *= inv;
+        px *= inv;
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+            if (r == lr) {
+#pragma unroll
+                for (int c = 0; c < 7; ++c) Bi[r][c] = prow[c];
+                xB[r] = px;
+                basis[r] = e;
+            } else {
+#pragma unroll
+                for (int c = 0; c < 7; ++c) Bi[r][c] -= al[r] * prow[c];
+                xB[r] -= al[r] * px;
+            }
+        }
+        ++piv;
     }
+    double t = 0.0;
+#pragma unroll
+    for (int r = 0; r < 7; ++r)
+        if (basis[r] >= n) t += xB[r];
+    verdict[sid] = (status == 0 && t <= eps) ? 1 : 0;
+    tstar[sid] = status == 0 ? t : __builtin_nan("");
 }
 
 // ---- compaction ------------------------------------------------------------
@@ -458,8 +485,8 @@ lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, i
     const DevHand &H = field->dh;
     if (n_points <= 0 || n_poses < 0) return fail(LG_EINVAL, "n_points must be > 0 and n_poses >= 0");
     if (p->k != H.F) return fail(LG_EINVAL, "k must equal the number of fingers (one contact per finger)");
-    if (p->draws <= 0 || p->m_edges < 3 || p->m_edges > 16 || p->k * p->m_edges + 12 > 64)
-        return fail(LG_EINVAL, "need draws > 0, 3 <= m_edges <= 16 and k*m_edges <= 52");
+    if (p->draws <= 0 || p->m_edges < 3 || p->m_edges > 16 || p->k > 8)
+        return fail(LG_EINVAL, "need draws > 0, 3 <= m_edges <= 16, k <= 8");
     if (!(p->mu >= 0.0f) || !(p->moment_scale > 0.0f) || p->max_pivots < 0)
         return fail(LG_EINVAL, "need mu >= 0, moment_scale > 0, max_pivots >= 0");
     if ((int64_t)n_poses * p->draws > 0x7fffffffLL) return fail(LG_EINVAL, "P * D must be < 2^31");
@@ -477,9 +504,21 @@ lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, i
                        p->request_id, p->pose_offset, set_pt, set_link);
     LG_HIP(hipGetLastError());
     const int64_t n_sets = (int64_t)n_poses * p->draws;
-    hipLaunchKernelGGL(k_verdict, dim3((unsigned)((n_sets + kVerdictWaves - 1) / kVerdictWaves)),
-                       dim3(64 * kVerdictWaves), 0, s, pts, nrm, n_points, set_pt, n_sets, p->k, p->m_edges,
-                       (double)p->mu, (double)p->moment_scale, (double)p->eps, p->max_pivots, verdict, tstar);
+    LpConst cs;
+    for (int e = 0; e < 16; ++e) {
+        const double th = 2.0 * M_PI * e / p->m_edges;
+        cs.ce[e] = e < p->m_edges ? cos(th) : 0.0;
+        cs.se[e] = e < p->m_edges ? sin(th) : 0.0;
+    }
+    const dim3 lgrid((unsigned)((n_sets + 255) / 256));
+    if (p->k <= 4)
+        hipLaunchKernelGGL(k_verdict_lane<4>, lgrid, dim3(256), 0, s, pts, nrm, n_points, set_pt, n_sets, p->k,
+                           p->m_edges, (double)p->mu, (double)p->moment_scale, (double)p->eps, p->max_pivots, cs,
+                           verdict, tstar);
+    else
+        hipLaunchKernelGGL(k_verdict_lane<8>, lgrid, dim3(256), 0, s, pts, nrm, n_points, set_pt, n_sets, p->k,
+                           p->m_edges, (double)p->mu, (double)p->moment_scale, (double)p->eps, p->max_pivots, cs,
+                           verdict, tstar);
     LG_HIP(hipGetLastError());
     const int64_t n_chunks = (n_sets + kChunk - 1) / kChunk;
     uint32_t *chunk_count = static_cast<uint32_t *>(workspace);
