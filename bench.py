@@ -45,27 +45,50 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-poses", type=int, default=0, help="poses of the CPU-oracle sample (0 = auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="full", choices=["full", "query", "search"],
+                    help="query / search: only the field build and --steps launches of that stage "
+                         "(query mode adds a 1 GiB device copy); for hardware-counter runs, no JSON")
     return ap.parse_args()
 
 
-def in_window_lookups(torch, pipe, w) -> int:
-    """Exact number of (pose, point, finger) triples whose point lies inside
-    the finger's window (each needs one W-byte table word), counted on the
-    device in float32 (the query's precision)."""
+def in_window_lookups(torch, pipe, w) -> list:
+    """Exact number, per finger, of (pose, point) pairs whose point lies
+    inside the finger's window (the links of a finger share it), counted on
+    the device in float32 (the query's precision)."""
     gf = torch.from_numpy(np.asarray(w.field.grid_frame, np.float32).reshape(-1, 3, 4)).cuda()
     Rg, og = gf[:, :, :3], gf[:, :, 3]
     G, h = w.field.grid, float(np.float32(w.field.h))
     pts = pipe.pts  # [3, N]
-    total = 0
+    total = torch.zeros(gf.shape[0], dtype=torch.int64, device="cuda")
     chunk = max(1, int(2 ** 26 // (pts.shape[1] * gf.shape[0])))
     for g0 in range(0, pipe.P, chunk):
         P = pipe.poses[g0:g0 + chunk].reshape(-1, 3, 4)
         x = P[:, :, :3] @ pts + P[:, :, 3:4]                                # [p, 3, N]
         u = torch.einsum("fab,pan->pfbn", Rg, x) - torch.einsum("fab,fa->fb", Rg, og)[None, :, :, None]
-        u = u / h
-        inside = ((u >= 0) & (u < G)).all(dim=2)
-        total += int(inside.sum().item())
-    return total
+        u = torch.floor(u / h)
+        inside = ((u >= 0) & (u < G)).all(dim=2)                          # [p, f, N]
+        total += inside.sum(dim=(0, 2))
+    return [int(x) for x in total.cpu()]
+
+
+def query_traffic():
+    """HBM bytes per query launch from the committed counter summary
+    (FETCH_SIZE, WRITE_SIZE scaled by a plain 1 GiB copy), or None when the
+    query kernel's sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_query_c3_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    h = hashlib.sha256()
+    for f in ("query.hip", "lg_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2511_07418_amd", "csrc", f), "rb").read())
+    import re
+    m = re.search(r"source sha256: ([0-9a-f]{64})", txt)
+    t = re.search(r"HBM traffic per launch \(bytes\): ([0-9]+)", txt)
+    if not m or not t or m.group(1) != h.hexdigest():
+        return None
+    return int(t.group(1))
 
 
 def cpu_baseline(w, n_poses: int, samples: int) -> dict:
@@ -123,6 +146,26 @@ def main():
     print(f"[bench] {args.workload}: field built in {t_build:.2f}s ({field.info()['bits_set']} bits), "
           f"P={pipe.P} N={pipe.N}", file=sys.stderr, flush=True)
 
+    if args.mode == "search":
+        pipe.query()
+        for _ in range(args.steps):
+            pipe.search()
+        torch.cuda.synchronize()
+        print(f"[bench] search-only run done: {args.steps} launches", file=sys.stderr, flush=True)
+        return
+    if args.mode == "query":
+        # counter runs: the query kernel alone, then a plain copy of known size
+        # (1 GiB read + 1 GiB written) whose FETCH_SIZE / WRITE_SIZE calibrate
+        # the counters' units
+        for _ in range(args.steps):
+            pipe.query()
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] query-only run done: {args.steps} launches", file=sys.stderr, flush=True)
+        return
+
     for _ in range(args.warmup):
         pipe.step()
     torch.cuda.synchronize()
@@ -147,12 +190,22 @@ def main():
     ms_per_step = wall * 1000.0 / args.steps
     value = n_valid / (ms_per_step / 1000.0)
 
-    # query roofline: algorithmic bytes per launch / measured query time
+    # query roofline.  Algorithmic bytes per launch (per-unit figures of the
+    # method): one W-byte field word (W = B/8) per in-window (pose, point,
+    # link) lookup, the domain bits written (P*F*ceil(N/32)*4), 48 B per pose
+    # and 24 B per point.  The kernel itself reads one 4-byte word per
+    # in-window (pose, point, finger) from the merged finger tables; those
+    # bytes are reported as impl_bytes_per_launch.
     W = w.field.bins // 8
-    lookups = in_window_lookups(torch, pipe, w)
+    per_finger = in_window_lookups(torch, pipe, w)
+    dof = w.hand.dof
+    link_lookups = sum(c * d for c, d in zip(per_finger, dof))
+    finger_lookups = sum(per_finger)
     F = w.hand.n_fingers
     NW = (pipe.N + 31) // 32
-    alg_bytes = lookups * W + pipe.P * F * NW * 4 + pipe.P * 48 + pipe.N * 24
+    out_bytes = pipe.P * F * NW * 4 + pipe.P * F * 4 + pipe.P * 48 + pipe.N * 24
+    alg_bytes = link_lookups * W + out_bytes
+    impl_bytes = finger_lookups * 4 + out_bytes
     q_ms = float(st[:, 0].mean())
     achieved = alg_bytes / (q_ms * 1e-3) / 1e9
     out = {
@@ -175,9 +228,11 @@ def main():
         "stage_ms": {"query": q_ms, "search": float(st[:, 1].mean()), "realize": float(st[:, 2].mean())},
         "query_gbps": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": query_traffic(),
                      "kernel": "k_query", "alg_bytes_per_launch": alg_bytes,
-                     "in_window_lookups": lookups},
+                     "in_window_link_lookups": link_lookups, "in_window_finger_lookups": finger_lookups,
+                     "impl_bytes_per_launch": impl_bytes,
+                     "impl_gbps": impl_bytes / (q_ms * 1e-3) / 1e9},
     }
     if not args.no_cpu_baseline:
         n = args.cpu_poses or {"c1": 256, "c2": 2048, "c3": 1024}[args.workload]

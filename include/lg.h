@@ -42,6 +42,7 @@ typedef int32_t lg_status;
 #define LG_EINVAL (-1)       /* invalid argument (nothing enqueued) */
 #define LG_ENOMEM (-2)       /* device allocation failed */
 #define LG_EDEVICE (-3)      /* HIP runtime error */
+#define LG_EBUDGET (-4)      /* request can never fit the server's HBM budget */
 #define LG_EUNSUPPORTED (-5) /* valid but unsupported configuration */
 #define LG_EINTERNAL (-6)
 
@@ -230,6 +231,84 @@ lg_status lg_realize(const lg_field *field, const lg_sdf *sdf, const float *pts,
                      const int32_t *acc_list, const int32_t *n_acc_dev, int32_t max_acc,
                      const lg_ik_params *params, float *q_out, float *contact_err,
                      float *contact_ang, float *depth, uint8_t *valid, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of grasp requests over resident fields.       */
+/* The paper caches each stage's output for reuse across forward passes       */
+/* (Fig. 6) and reuses search results (Sec. 5.7); a server keeps the fields   */
+/* resident and interleaves many requests on one GPU.  A request (object +    */
+/* palm poses + search parameters) is admitted when its device memory fits   */
+/* the HBM budget (FIFO); its poses are processed in chunks of `chunk_poses`, */
+/* chunks of different requests run concurrently on up to `max_active`        */
+/* streams, and a request's RNG counters depend only on (request_id, pose     */
+/* index within the request, draw), so its result is the same alone and in    */
+/* any mix.  Host API, thread-safe; work runs on a server thread.             */
+/* ------------------------------------------------------------------------ */
+typedef struct lg_server lg_server;
+
+typedef struct {
+    uint64_t budget_bytes;  /* device memory reserved for admitted requests */
+    int32_t max_active;     /* requests in flight at once (one stream each), 1..64 */
+    int32_t chunk_poses;    /* poses per scheduling quantum, >= 1 */
+} lg_server_params;
+
+typedef struct {
+    const lg_field *field;    /* resident field of the hand; must outlive the request */
+    const float *pts;         /* host [N][3] object points (object frame); copied at submit */
+    const float *nrm;         /* host [N][3] outward unit normals */
+    int32_t n_points;
+    const float *poses;       /* host [P][12] palm poses */
+    int32_t n_poses;
+    lg_search_params search;  /* request_id and pose_offset are ignored (set per chunk) */
+    uint32_t request_id;      /* RNG stream of the request */
+    int32_t realize;          /* 1: run IK + penetration (needs ik and sdf) */
+    lg_ik_params ik;
+    const float *sdf_values;  /* host [G][G][G], used when realize = 1 */
+    float sdf_origin[3];
+    float sdf_h;
+    int32_t sdf_dims;
+} lg_request;
+
+#define LG_REQ_QUEUED 0
+#define LG_REQ_RUNNING 1
+#define LG_REQ_DONE 2
+#define LG_REQ_CANCELLED 3
+#define LG_REQ_FAILED 4
+
+typedef struct {
+    int32_t state;          /* LG_REQ_* */
+    int32_t status;         /* lg_status of a failed request */
+    int64_t n_acc;          /* accepted sets (verdict true) */
+    int64_t n_valid;        /* valid grasps (= n_acc without realize) */
+    uint64_t acc_hash;      /* order-independent hash of the accepted (pose, draw) ids */
+    double t_submit, t_admit, t_done;  /* seconds on the server's clock */
+    uint64_t bytes;         /* device memory reserved for the request */
+} lg_result;
+
+typedef struct {
+    int64_t submitted, admitted, completed, cancelled, rejected, failed;
+    uint64_t budget_bytes, bytes_in_use, peak_bytes;
+    int32_t queued, active;
+} lg_server_stats;
+
+/* Device bytes a request reserves while admitted (inputs + one chunk of
+ * working buffers).  Requests larger than the budget are rejected. */
+uint64_t lg_serve_request_bytes(const lg_server_params *params, const lg_request *req);
+/* Create a server on the current device (allocates the budget slab). */
+lg_status lg_serve_create(const lg_server_params *params, lg_server **out);
+/* Copy the request's host data and queue it; LG_EBUDGET if it can never fit. */
+lg_status lg_serve_submit(lg_server *srv, const lg_request *req, uint64_t *ticket);
+/* Current state / result of a ticket (LG_EINVAL for an unknown ticket). */
+lg_status lg_serve_poll(lg_server *srv, uint64_t ticket, lg_result *out);
+/* Block until the ticket is DONE/CANCELLED/FAILED or timeout_s elapses. */
+lg_status lg_serve_wait(lg_server *srv, uint64_t ticket, double timeout_s, lg_result *out);
+/* Cancel: a queued request is dropped; a running one stops after its chunk. */
+lg_status lg_serve_cancel(lg_server *srv, uint64_t ticket);
+lg_status lg_serve_stats(lg_server *srv, lg_server_stats *out);
+/* Seconds on the server's clock (the clock of t_submit/t_admit/t_done). */
+double lg_serve_clock(lg_server *srv);
+/* Finish in-flight chunks, cancel the rest, free everything. */
+lg_status lg_serve_destroy(lg_server *srv);
 
 #ifdef __cplusplus
 }

@@ -486,7 +486,7 @@ lg_status lg_field_export(const lg_field *f, uint32_t *bits_host, int32_t *witne
         } else {
             LG_HIP(hipMemcpy(witness_host, f->d_wit, n * 4, hipMemcpyDeviceToHost));
             for (size_t i = 0; i < n; ++i)
-                if (witness_host[i] >= (int32_t)H.samples) witness_host[i] = -1;
+                if (witness_host[i] < 0 || witness_host[i] >= (int32_t)H.samples) witness_host[i] = -1;
         }
     }
     return LG_OK;

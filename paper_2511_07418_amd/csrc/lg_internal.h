@@ -202,15 +202,15 @@ __device__ inline Affine finger_affine(const DevHand &H, const float *pose, int 
     return a;
 }
 
-// Linear voxel index of object point p in the window, -1 outside.
+// Linear voxel index (iz G + iy) G + ix of object point p in the window, -1
+// outside.  floor + one unsigned compare per axis.
 __device__ inline int window_voxel(const Affine &a, int G, float px, float py, float pz)
 {
     const float ux = fmaf(a.m[0], px, fmaf(a.m[1], py, fmaf(a.m[2], pz, a.m[3])));
     const float uy = fmaf(a.m[4], px, fmaf(a.m[5], py, fmaf(a.m[6], pz, a.m[7])));
     const float uz = fmaf(a.m[8], px, fmaf(a.m[9], py, fmaf(a.m[10], pz, a.m[11])));
-    const float g = (float)G;
-    const bool in = (ux >= 0.f) & (ux < g) & (uy >= 0.f) & (uy < g) & (uz >= 0.f) & (uz < g);
-    const int ix = (int)ux, iy = (int)uy, iz = (int)uz;  // truncation == floor for u >= 0
+    const int ix = (int)floorf(ux), iy = (int)floorf(uy), iz = (int)floorf(uz);
+    const bool in = ((unsigned)ix < (unsigned)G) & ((unsigned)iy < (unsigned)G) & ((unsigned)iz < (unsigned)G);
     return in ? (iz * G + iy) * G + ix : -1;
 }
 
@@ -263,18 +263,16 @@ __device__ inline int nearest_bin_lut(const uint32_t *lut, const float *c, int B
     const int iu = min(max((int)fmaf(u, s, 0.5f * kLutRes), 0), kLutRes - 1);
     const int iv = min(max((int)fmaf(v, s, 0.5f * kLutRes), 0), kLutRes - 1);
     const uint32_t e = lut[(face * kLutRes + iv) * kLutRes + iu];
+    if ((e >> 8 & 0xffu) == 0xffu) return (int)(e & 0xffu);  // single candidate
     if (e == 0xffffffffu) return nearest_bin(c, B, dx, dy, dz);
     float best = -3.0e38f;
     int bi = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t b = (e >> (8 * i)) & 0xffu;
-        if (b != 0xffu) {
-            const float sc = fmaf(c[3 * b], dx, fmaf(c[3 * b + 1], dy, c[3 * b + 2] * dz));
-            if (sc > best) {
-                best = sc;
-                bi = (int)b;
-            }
+    for (uint32_t r = e; (r & 0xffu) != 0xffu; r = (r >> 8) | 0xff000000u) {
+        const uint32_t b = r & 0xffu;
+        const float sc = fmaf(c[3 * b], dx, fmaf(c[3 * b + 1], dy, c[3 * b + 2] * dz));
+        if (sc > best) {
+            best = sc;
+            bi = (int)b;
         }
     }
     return bi;

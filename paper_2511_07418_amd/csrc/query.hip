@@ -54,28 +54,24 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
             ny = nrm[N + i];
             nz = nrm[2 * N + i];
         }
+        float qx, qy, qz;
+        query_dir(P, nx, ny, nz, qx, qy, qz);
+        const int b = nearest_bin_lut(lut, cb, B, qx, qy, qz);
+        // one 32-bit word per finger: the word of the table that holds bit b;
         // all finger gathers are issued before any is consumed
-        uint64_t word[FM];
+        uint32_t word[FM];
 #pragma unroll
         for (int f = 0; f < FM; ++f) {
             word[f] = 0;
             if (f < F) {
                 const int v = window_voxel(aff[f], G, px, py, pz);
-                if (valid && v >= 0) {
-                    if (W == 1)
-                        word[f] = merged[f * G3W + v];
-                    else
-                        word[f] = reinterpret_cast<const uint64_t *>(merged + f * G3W)[v];
-                }
+                if (valid && v >= 0) word[f] = merged[f * G3W + (int64_t)v * W + (b >> 5)];
             }
         }
-        float qx, qy, qz;
-        query_dir(P, nx, ny, nz, qx, qy, qz);
-        const int b = nearest_bin_lut(lut, cb, B, qx, qy, qz);
 #pragma unroll
         for (int f = 0; f < FM; ++f) {
             if (f >= F) break;
-            const bool hit = (word[f] >> b) & 1ull;
+            const bool hit = (word[f] >> (b & 31)) & 1u;
             const unsigned long long m = __ballot(hit);
             c[f] += (uint32_t)__popcll(m);
             const int wi = 2 * chunk + lane;

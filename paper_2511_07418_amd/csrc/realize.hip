@@ -169,203 +169,205 @@ k_realize(DevHand H, const int32_t *__restrict__ wit, SdfDev S, const float *__r
     for (int i = threadIdx.x; i < 3 * H.B; i += blockDim.x) cb[i] = H.bin_c[i];
     __syncthreads();
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t a = gt >> 3;
     const int f = (int)(gt & 7);
     const int64_t nacc = min((int64_t)*n_acc_dev, (int64_t)max_acc);
-    if (a >= nacc) return;  // the 8 lanes of a set leave together
-    const int64_t id = acc_list[a];
-    const int64_t g = id / D;
-    float P[12];
+    const int64_t stride = ((int64_t)gridDim.x * blockDim.x) >> 3;
+    // grid-stride over accepted sets; the 8 lanes of a set move together
+    for (int64_t a = gt >> 3; a < nacc; a += stride) {
+        const int64_t id = acc_list[a];
+        const int64_t g = id / D;
+        float P[12];
 #pragma unroll
-    for (int i = 0; i < 12; ++i) P[i] = poses[12 * g + i];
-    float dep = -INFINITY, emax = 0.f, amax = 0.f;
-    if (f < H.F) {
-        const int first = H.finger_first[f], d = H.finger_dof[f];
-        const int idx = set_pt[id * k + f];
-        const int l = set_link[id * k + f];
-        const float ox = pts[idx], oy = pts[N + idx], oz = pts[2 * N + idx];
-        float p[3], n[3];
-        p[0] = fmaf(P[0], ox, fmaf(P[1], oy, fmaf(P[2], oz, P[3])));
-        p[1] = fmaf(P[4], ox, fmaf(P[5], oy, fmaf(P[6], oz, P[7])));
-        p[2] = fmaf(P[8], ox, fmaf(P[9], oy, fmaf(P[10], oz, P[11])));
-        query_dir(P, nrm[idx], nrm[N + idx], nrm[2 * N + idx], n[0], n[1], n[2]);
-        // reverse lookup: witness sample of (link, voxel(p), bin(n))
-        int32_t w = kNoWitness;
-        if (wit) {
-            const Affine af = finger_affine(H, P, f);
-            const int v = window_voxel(af, H.G, ox, oy, oz);
-            const int b = nearest_bin(cb, H.B, n[0], n[1], n[2]);
-            if (v >= 0) w = wit[((int64_t)l * H.G * H.G * H.G + v) * H.B + b];
-        }
-        float q[DM];
-#pragma unroll
-        for (int t = 0; t < DM; ++t) {
-            q[t] = 0.f;
-            if (t < d) {
-                const int j = first + t;
-                q[t] = (w >= 0 && w < H.samples) ? joint_sample(H, f, (uint32_t)w, t)
-                                                 : 0.5f * (H.limits[2 * j] + H.limits[2 * j + 1]);
+        for (int i = 0; i < 12; ++i) P[i] = poses[12 * g + i];
+        float dep = -INFINITY, emax = 0.f, amax = 0.f;
+        if (f < H.F) {
+            const int first = H.finger_first[f], d = H.finger_dof[f];
+            const int idx = set_pt[id * k + f];
+            const int l = set_link[id * k + f];
+            const float ox = pts[idx], oy = pts[N + idx], oz = pts[2 * N + idx];
+            float p[3], n[3];
+            p[0] = fmaf(P[0], ox, fmaf(P[1], oy, fmaf(P[2], oz, P[3])));
+            p[1] = fmaf(P[4], ox, fmaf(P[5], oy, fmaf(P[6], oz, P[7])));
+            p[2] = fmaf(P[8], ox, fmaf(P[9], oy, fmaf(P[10], oz, P[11])));
+            query_dir(P, nrm[idx], nrm[N + idx], nrm[2 * N + idx], n[0], n[1], n[2]);
+            // reverse lookup: witness sample of (link, voxel(p), bin(n))
+            int32_t w = kNoWitness;
+            if (wit) {
+                const Affine af = finger_affine(H, P, f);
+                const int v = window_voxel(af, H.G, ox, oy, oz);
+                const int b = nearest_bin(cb, H.B, n[0], n[1], n[2]);
+                if (v >= 0) w = wit[((int64_t)l * H.G * H.G * H.G + v) * H.B + b];
             }
-        }
-        const int tl = l - first;  // link index within the finger
-        const float *cap = H.capsule + 7 * l;
-        const float r = cap[6];
-        float loc_p[3] = {0.f, 0.f, 0.f}, loc_n[3] = {0.f, 0.f, 1.f};
-        for (int it = 0; it < ik.iters; ++it) {
-            float o[DM][3], z[DM][3];
-            Tf T, Tl;
+            float q[DM];
+#pragma unroll
+            for (int t = 0; t < DM; ++t) {
+                q[t] = 0.f;
+                if (t < d) {
+                    const int j = first + t;
+                    q[t] = (w >= 0 && w < H.samples) ? joint_sample(H, f, (uint32_t)w, t)
+                                                     : 0.5f * (H.limits[2 * j] + H.limits[2 * j + 1]);
+                }
+            }
+            const int tl = l - first;  // link index within the finger
+            const float *cap = H.capsule + 7 * l;
+            const float r = cap[6];
+            float loc_p[3] = {0.f, 0.f, 0.f}, loc_n[3] = {0.f, 0.f, 1.f};
+            for (int it = 0; it < ik.iters; ++it) {
+                float o[DM][3], z[DM][3];
+                Tf T, Tl;
+#pragma unroll
+                for (int t = 0; t < DM; ++t) {
+                    if (t < d) {
+                        const int j = first + t;
+                        T = joint_frame(H, T, t > 0, j, q[t]);
+                        o[t][0] = T.m[3];
+                        o[t][1] = T.m[7];
+                        o[t][2] = T.m[11];
+                        tf_dir(T, H.axis[3 * j], H.axis[3 * j + 1], H.axis[3 * j + 2], z[t][0], z[t][1], z[t][2]);
+                        if (t == tl) Tl = T;
+                    }
+                }
+                float pt[3], nt[3];
+                if (it == 0 || it >= ik.phase1) {
+                    float A[3], Bq[3];
+                    tf_point(Tl, cap[0], cap[1], cap[2], A[0], A[1], A[2]);
+                    tf_point(Tl, cap[3], cap[4], cap[5], Bq[0], Bq[1], Bq[2]);
+                    capsule_aligned(A, Bq, r, p, n, ik.beta, pt, nt);
+                    const float dx = pt[0] - Tl.m[3], dy = pt[1] - Tl.m[7], dz = pt[2] - Tl.m[11];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        loc_p[c] = fmaf(Tl.m[c], dx, fmaf(Tl.m[4 + c], dy, Tl.m[8 + c] * dz));
+                        loc_n[c] = fmaf(Tl.m[c], nt[0], fmaf(Tl.m[4 + c], nt[1], Tl.m[8 + c] * nt[2]));
+                    }
+                } else {
+                    tf_point(Tl, loc_p[0], loc_p[1], loc_p[2], pt[0], pt[1], pt[2]);
+                    tf_dir(Tl, loc_n[0], loc_n[1], loc_n[2], nt[0], nt[1], nt[2]);
+                }
+                float x2[3], e[6];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    x2[c] = fmaf(ik.beta, nt[c], pt[c]);
+                    e[c] = p[c] - pt[c];
+                    e[3 + c] = fmaf(ik.beta, n[c], p[c]) - x2[c];
+                }
+                float Jc[DM][6];
+#pragma unroll
+                for (int t = 0; t < DM; ++t) {
+                    const bool on = t < d && t <= tl;
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        const float *x = s == 0 ? pt : x2;
+                        const float vx = x[0] - o[t][0], vy = x[1] - o[t][1], vz = x[2] - o[t][2];
+                        Jc[t][3 * s + 0] = on ? z[t][1] * vz - z[t][2] * vy : 0.f;
+                        Jc[t][3 * s + 1] = on ? z[t][2] * vx - z[t][0] * vz : 0.f;
+                        Jc[t][3 * s + 2] = on ? z[t][0] * vy - z[t][1] * vx : 0.f;
+                    }
+                }
+                // normal equations (J^T J + lambda I) dq = J^T e, Cholesky in place
+                float M[DM][DM], gv[DM];
+#pragma unroll
+                for (int i = 0; i < DM; ++i) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int rr = 0; rr < 6; ++rr) acc = fmaf(Jc[i][rr], e[rr], acc);
+                    gv[i] = acc;
+#pragma unroll
+                    for (int j = 0; j < DM; ++j) {
+                        float s2 = 0.f;
+#pragma unroll
+                        for (int rr = 0; rr < 6; ++rr) s2 = fmaf(Jc[i][rr], Jc[j][rr], s2);
+                        M[i][j] = s2 + (i == j ? ik.lambda : 0.f);
+                    }
+                }
+                bool ok = true;
+#pragma unroll
+                for (int j = 0; j < DM; ++j) {
+                    float s2 = M[j][j];
+#pragma unroll
+                    for (int kk = 0; kk < j; ++kk) s2 = fmaf(-M[j][kk], M[j][kk], s2);
+                    ok &= s2 > 0.f;
+                    const float dd = sqrtf(fmaxf(s2, 1e-30f));
+                    M[j][j] = dd;
+                    const float inv = 1.0f / dd;
+#pragma unroll
+                    for (int i = j + 1; i < DM; ++i) {
+                        float t2 = M[i][j];
+#pragma unroll
+                        for (int kk = 0; kk < j; ++kk) t2 = fmaf(-M[i][kk], M[j][kk], t2);
+                        M[i][j] = t2 * inv;
+                    }
+                }
+                if (!ok) break;
+#pragma unroll
+                for (int i = 0; i < DM; ++i) {
+                    float t2 = gv[i];
+#pragma unroll
+                    for (int kk = 0; kk < i; ++kk) t2 = fmaf(-M[i][kk], gv[kk], t2);
+                    gv[i] = t2 / M[i][i];
+                }
+#pragma unroll
+                for (int i = DM - 1; i >= 0; --i) {
+                    float t2 = gv[i];
+#pragma unroll
+                    for (int kk = i + 1; kk < DM; ++kk) t2 = fmaf(-M[kk][i], gv[kk], t2);
+                    gv[i] = t2 / M[i][i];
+                }
+#pragma unroll
+                for (int t = 0; t < DM; ++t) {
+                    if (t < d) {
+                        const int j = first + t;
+                        q[t] = fminf(fmaxf(q[t] + gv[t], H.limits[2 * j]), H.limits[2 * j + 1]);
+                    }
+                }
+            }
+            // final configuration: contact quality and penetration of the finger's links
+            Tf T;
 #pragma unroll
             for (int t = 0; t < DM; ++t) {
                 if (t < d) {
                     const int j = first + t;
                     T = joint_frame(H, T, t > 0, j, q[t]);
-                    o[t][0] = T.m[3];
-                    o[t][1] = T.m[7];
-                    o[t][2] = T.m[11];
-                    tf_dir(T, H.axis[3 * j], H.axis[3 * j + 1], H.axis[3 * j + 2], z[t][0], z[t][1], z[t][2]);
-                    if (t == tl) Tl = T;
+                    const float *cj = H.capsule + 7 * j;
+                    float A[3], Bq[3];
+                    tf_point(T, cj[0], cj[1], cj[2], A[0], A[1], A[2]);
+                    tf_point(T, cj[3], cj[4], cj[5], Bq[0], Bq[1], Bq[2]);
+                    if (t == tl) {
+                        float pt[3], nt[3];
+                        capsule_project(A, Bq, cj[6], p, pt, nt);
+                        const float d0 = p[0] - pt[0], d1 = p[1] - pt[1], d2 = p[2] - pt[2];
+                        emax = sqrtf(dot3f(d0, d1, d2, d0, d1, d2));
+                        amax = acosf(fminf(fmaxf(dot3f(nt[0], nt[1], nt[2], n[0], n[1], n[2]), -1.f), 1.f));
+                    }
+                    const int M = H.axis_samples[j];
+                    const float inv = 1.0f / (float)(M - 1);
+                    for (int s = 0; s < M; ++s) {
+                        const float ts = (float)s * inv;
+                        const float x0 = fmaf(ts, Bq[0] - A[0], A[0]) - P[3];
+                        const float x1 = fmaf(ts, Bq[1] - A[1], A[1]) - P[7];
+                        const float x2 = fmaf(ts, Bq[2] - A[2], A[2]) - P[11];
+                        // object frame: R^T (x - t)
+                        const float y0 = fmaf(P[0], x0, fmaf(P[4], x1, P[8] * x2));
+                        const float y1 = fmaf(P[1], x0, fmaf(P[5], x1, P[9] * x2));
+                        const float y2 = fmaf(P[2], x0, fmaf(P[6], x1, P[10] * x2));
+                        dep = fmaxf(dep, cj[6] - sdf_trilinear(S, y0, y1, y2));
+                    }
+                    q_out[a * H.J + j] = q[t];
                 }
             }
-            float pt[3], nt[3];
-            if (it == 0 || it >= ik.phase1) {
-                float A[3], Bq[3];
-                tf_point(Tl, cap[0], cap[1], cap[2], A[0], A[1], A[2]);
-                tf_point(Tl, cap[3], cap[4], cap[5], Bq[0], Bq[1], Bq[2]);
-                capsule_aligned(A, Bq, r, p, n, ik.beta, pt, nt);
-                const float dx = pt[0] - Tl.m[3], dy = pt[1] - Tl.m[7], dz = pt[2] - Tl.m[11];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    loc_p[c] = fmaf(Tl.m[c], dx, fmaf(Tl.m[4 + c], dy, Tl.m[8 + c] * dz));
-                    loc_n[c] = fmaf(Tl.m[c], nt[0], fmaf(Tl.m[4 + c], nt[1], Tl.m[8 + c] * nt[2]));
-                }
-            } else {
-                tf_point(Tl, loc_p[0], loc_p[1], loc_p[2], pt[0], pt[1], pt[2]);
-                tf_dir(Tl, loc_n[0], loc_n[1], loc_n[2], nt[0], nt[1], nt[2]);
-            }
-            float x2[3], e[6];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                x2[c] = fmaf(ik.beta, nt[c], pt[c]);
-                e[c] = p[c] - pt[c];
-                e[3 + c] = fmaf(ik.beta, n[c], p[c]) - x2[c];
-            }
-            float Jc[DM][6];
-#pragma unroll
-            for (int t = 0; t < DM; ++t) {
-                const bool on = t < d && t <= tl;
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    const float *x = s == 0 ? pt : x2;
-                    const float vx = x[0] - o[t][0], vy = x[1] - o[t][1], vz = x[2] - o[t][2];
-                    Jc[t][3 * s + 0] = on ? z[t][1] * vz - z[t][2] * vy : 0.f;
-                    Jc[t][3 * s + 1] = on ? z[t][2] * vx - z[t][0] * vz : 0.f;
-                    Jc[t][3 * s + 2] = on ? z[t][0] * vy - z[t][1] * vx : 0.f;
-                }
-            }
-            // normal equations (J^T J + lambda I) dq = J^T e, Cholesky in place
-            float M[DM][DM], gv[DM];
-#pragma unroll
-            for (int i = 0; i < DM; ++i) {
-                float acc = 0.f;
-#pragma unroll
-                for (int rr = 0; rr < 6; ++rr) acc = fmaf(Jc[i][rr], e[rr], acc);
-                gv[i] = acc;
-#pragma unroll
-                for (int j = 0; j < DM; ++j) {
-                    float s2 = 0.f;
-#pragma unroll
-                    for (int rr = 0; rr < 6; ++rr) s2 = fmaf(Jc[i][rr], Jc[j][rr], s2);
-                    M[i][j] = s2 + (i == j ? ik.lambda : 0.f);
-                }
-            }
-            bool ok = true;
-#pragma unroll
-            for (int j = 0; j < DM; ++j) {
-                float s2 = M[j][j];
-#pragma unroll
-                for (int kk = 0; kk < j; ++kk) s2 = fmaf(-M[j][kk], M[j][kk], s2);
-                ok &= s2 > 0.f;
-                const float dd = sqrtf(fmaxf(s2, 1e-30f));
-                M[j][j] = dd;
-                const float inv = 1.0f / dd;
-#pragma unroll
-                for (int i = j + 1; i < DM; ++i) {
-                    float t2 = M[i][j];
-#pragma unroll
-                    for (int kk = 0; kk < j; ++kk) t2 = fmaf(-M[i][kk], M[j][kk], t2);
-                    M[i][j] = t2 * inv;
-                }
-            }
-            if (!ok) break;
-#pragma unroll
-            for (int i = 0; i < DM; ++i) {
-                float t2 = gv[i];
-#pragma unroll
-                for (int kk = 0; kk < i; ++kk) t2 = fmaf(-M[i][kk], gv[kk], t2);
-                gv[i] = t2 / M[i][i];
-            }
-#pragma unroll
-            for (int i = DM - 1; i >= 0; --i) {
-                float t2 = gv[i];
-#pragma unroll
-                for (int kk = i + 1; kk < DM; ++kk) t2 = fmaf(-M[kk][i], gv[kk], t2);
-                gv[i] = t2 / M[i][i];
-            }
-#pragma unroll
-            for (int t = 0; t < DM; ++t) {
-                if (t < d) {
-                    const int j = first + t;
-                    q[t] = fminf(fmaxf(q[t] + gv[t], H.limits[2 * j]), H.limits[2 * j + 1]);
-                }
-            }
+            cerr[a * k + f] = emax;
+            cang[a * k + f] = amax;
         }
-        // final configuration: contact quality and penetration of the finger's links
-        Tf T;
+        // set-level reductions over the 8 lanes of the set
 #pragma unroll
-        for (int t = 0; t < DM; ++t) {
-            if (t < d) {
-                const int j = first + t;
-                T = joint_frame(H, T, t > 0, j, q[t]);
-                const float *cj = H.capsule + 7 * j;
-                float A[3], Bq[3];
-                tf_point(T, cj[0], cj[1], cj[2], A[0], A[1], A[2]);
-                tf_point(T, cj[3], cj[4], cj[5], Bq[0], Bq[1], Bq[2]);
-                if (t == tl) {
-                    float pt[3], nt[3];
-                    capsule_project(A, Bq, cj[6], p, pt, nt);
-                    const float d0 = p[0] - pt[0], d1 = p[1] - pt[1], d2 = p[2] - pt[2];
-                    emax = sqrtf(dot3f(d0, d1, d2, d0, d1, d2));
-                    amax = acosf(fminf(fmaxf(dot3f(nt[0], nt[1], nt[2], n[0], n[1], n[2]), -1.f), 1.f));
-                }
-                const int M = H.axis_samples[j];
-                const float inv = 1.0f / (float)(M - 1);
-                for (int s = 0; s < M; ++s) {
-                    const float ts = (float)s * inv;
-                    const float x0 = fmaf(ts, Bq[0] - A[0], A[0]) - P[3];
-                    const float x1 = fmaf(ts, Bq[1] - A[1], A[1]) - P[7];
-                    const float x2 = fmaf(ts, Bq[2] - A[2], A[2]) - P[11];
-                    // object frame: R^T (x - t)
-                    const float y0 = fmaf(P[0], x0, fmaf(P[4], x1, P[8] * x2));
-                    const float y1 = fmaf(P[1], x0, fmaf(P[5], x1, P[9] * x2));
-                    const float y2 = fmaf(P[2], x0, fmaf(P[6], x1, P[10] * x2));
-                    dep = fmaxf(dep, cj[6] - sdf_trilinear(S, y0, y1, y2));
-                }
-                q_out[a * H.J + j] = q[t];
-            }
+        for (int off = 1; off < 8; off <<= 1) {
+            dep = fmaxf(dep, __shfl_xor(dep, off, 8));
+            emax = fmaxf(emax, __shfl_xor(emax, off, 8));
+            amax = fmaxf(amax, __shfl_xor(amax, off, 8));
         }
-        cerr[a * k + f] = emax;
-        cang[a * k + f] = amax;
-    }
-    // set-level reductions over the 8 lanes of the set
-#pragma unroll
-    for (int off = 1; off < 8; off <<= 1) {
-        dep = fmaxf(dep, __shfl_xor(dep, off, 8));
-        emax = fmaxf(emax, __shfl_xor(emax, off, 8));
-        amax = fmaxf(amax, __shfl_xor(amax, off, 8));
-    }
-    if (f == 0) {
-        depth_out[a] = dep;
-        valid_out[a] = (emax <= ik.tol_pos && amax <= ik.tol_ang && dep <= ik.margin) ? 1 : 0;
+        if (f == 0) {
+            depth_out[a] = dep;
+            valid_out[a] = (emax <= ik.tol_pos && amax <= ik.tol_ang && dep <= ik.margin) ? 1 : 0;
+        }
     }
 }
 
@@ -393,8 +395,12 @@ extern "C" lg_status lg_realize(const lg_field *field, const lg_sdf *sdf, const 
     SdfDev S{sdf->origin[0], sdf->origin[1], sdf->origin[2], sdf->h, 1.0f / sdf->h, sdf->dims, sdf->values};
     IkDev ik{p->iters, p->phase1, p->lambda, p->beta, p->tol_pos, p->tol_ang, p->margin};
     hipStream_t s = as_stream(stream);
-    const int64_t threads = (int64_t)max_acc * 8;
-    const dim3 grid((unsigned)((threads + kRealizeThreads - 1) / kRealizeThreads));
+    // grid-stride launch sized to the device, not to the max_acc upper bound
+    int dev = 0, n_cu = 0;
+    LG_HIP(hipGetDevice(&dev));
+    LG_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int64_t threads = std::min<int64_t>((int64_t)max_acc * 8, (int64_t)n_cu * 16 * kRealizeThreads);
+    const dim3 grid((unsigned)std::max<int64_t>(1, (threads + kRealizeThreads - 1) / kRealizeThreads));
     const int32_t *wit = field->has_witness ? field->d_wit : nullptr;
 #define LG_REALIZE(DM)                                                                                          \
     hipLaunchKernelGGL(k_realize<DM>, grid, dim3(kRealizeThreads), 0, s, H, wit, S, pts, nrm, n_points, poses,  \

@@ -180,6 +180,7 @@ k_verdict_lane(const float *__restrict__ pts, const float *__restrict__ nrm, int
         return;
     }
     const int n = k * m;
+    const double inv_rho = 1.0 / rho;
     // contact i's point and normal (each lane reads only its own column)
     auto contact = [&](int ci, double &px, double &py, double &pz, double &nx, double &ny, double &nz) {
         px = cd[6 * ci + 0][tid];
@@ -257,9 +258,9 @@ k_verdict_lane(const float *__restrict__ pts, const float *__restrict__ nrm, int
             double px, py, pz, nx, ny, nz;
             contact(i, px, py, pz, nx, ny, nz);
             // u = y_f + (y_m x p) / rho
-            const double ux = y[0] + (y[4] * pz - y[5] * py) / rho;
-            const double uy = y[1] + (y[5] * px - y[3] * pz) / rho;
-            const double uz = y[2] + (y[3] * py - y[4] * px) / rho;
+            const double ux = y[0] + (y[4] * pz - y[5] * py) * inv_rho;
+            const double uy = y[1] + (y[5] * px - y[3] * pz) * inv_rho;
+            const double uz = y[2] + (y[3] * py - y[4] * px) * inv_rho;
             double x[3], yy[3];
             duff_basis(nx, ny, nz, x, yy);
             const double an = ux * nx + uy * ny + uz * nz;
@@ -336,16 +337,20 @@ k_verdict_lane(const float *__restrict__ pts, const float *__restrict__ nrm, int
             for (int c = 0; c < 7; ++c) s += Bi[r][c] * a[c];
             al[r] = s;
         }
+        // ratio test min x_B[r] / al[r] without divisions: the current best is
+        // kept as the fraction bx / ba (ba > 0) and ratios are compared by
+        // cross-multiplication; the tie band is kLpTol (1 + |best|).
         int lr = -1;
-        double best = 0.0;
+        double bx = 0.0, ba = 1.0;
 #pragma unroll
         for (int r = 0; r < 7; ++r) {
             if (al[r] > kLpPiv) {
-                const double ratio = xB[r] / al[r];
-                const double tol = kLpTol * (1.0 + fabs(best));
-                if (lr < 0 || ratio < best - tol || (fabs(ratio - best) <= tol && basis[r] < basis[lr])) {
+                const double lhs = xB[r] * ba, rhs = bx * al[r];
+                const double band = kLpTol * (ba + fabs(bx)) * al[r];
+                if (lr < 0 || lhs < rhs - band || (fabs(lhs - rhs) <= band && basis[r] < basis[lr])) {
                     lr = r;
-                    best = ratio;
+                    bx = xB[r];
+                    ba = al[r];
                 }
             }
         }

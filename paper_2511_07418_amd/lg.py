@@ -20,7 +20,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblg.so")
 
-LG_OK, LG_EINVAL, LG_ENOMEM, LG_EDEVICE, LG_EUNSUPPORTED, LG_EINTERNAL = 0, -1, -2, -3, -5, -6
+LG_OK, LG_EINVAL, LG_ENOMEM, LG_EDEVICE, LG_EBUDGET, LG_EUNSUPPORTED, LG_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+LG_REQ_QUEUED, LG_REQ_RUNNING, LG_REQ_DONE, LG_REQ_CANCELLED, LG_REQ_FAILED = 0, 1, 2, 3, 4
 
 
 class LgError(RuntimeError):
@@ -69,6 +70,31 @@ class Sdf(C.Structure):
                 ("values", C.c_void_p)]
 
 
+class ServerParams(C.Structure):
+    _fields_ = [("budget_bytes", C.c_uint64), ("max_active", C.c_int32), ("chunk_poses", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("field", C.c_void_p), ("pts", C.c_void_p), ("nrm", C.c_void_p), ("n_points", C.c_int32),
+                ("poses", C.c_void_p), ("n_poses", C.c_int32), ("search", SearchParams),
+                ("request_id", C.c_uint32), ("realize", C.c_int32), ("ik", IkParams),
+                ("sdf_values", C.c_void_p), ("sdf_origin", C.c_float * 3), ("sdf_h", C.c_float),
+                ("sdf_dims", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("n_acc", C.c_int64), ("n_valid", C.c_int64),
+                ("acc_hash", C.c_uint64), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double), ("bytes", C.c_uint64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("cancelled", C.c_int64), ("rejected", C.c_int64), ("failed", C.c_int64),
+                ("budget_bytes", C.c_uint64), ("bytes_in_use", C.c_uint64), ("peak_bytes", C.c_uint64),
+                ("queued", C.c_int32), ("active", C.c_int32)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: run paper_2511_07418_amd/build.py "
@@ -90,8 +116,21 @@ def _load():
     L.lg_search.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.lg_realize.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, i32, i32, vp, vp, i32, vp,
                              vp, vp, vp, vp, vp, vp]
+    L.lg_serve_request_bytes.argtypes = [vp, vp]
+    L.lg_serve_request_bytes.restype = C.c_uint64
+    L.lg_serve_create.argtypes = [vp, vp]
+    L.lg_serve_submit.argtypes = [vp, vp, vp]
+    L.lg_serve_poll.argtypes = [vp, C.c_uint64, vp]
+    L.lg_serve_wait.argtypes = [vp, C.c_uint64, C.c_double, vp]
+    L.lg_serve_cancel.argtypes = [vp, C.c_uint64]
+    L.lg_serve_stats.argtypes = [vp, vp]
+    L.lg_serve_clock.argtypes = [vp]
+    L.lg_serve_clock.restype = C.c_double
+    L.lg_serve_destroy.argtypes = [vp]
     for fn in ("lg_build_field", "lg_field_import", "lg_field_export", "lg_field_info",
-               "lg_field_release", "lg_query_domains", "lg_search", "lg_realize"):
+               "lg_field_release", "lg_query_domains", "lg_search", "lg_realize", "lg_serve_create",
+               "lg_serve_submit", "lg_serve_poll", "lg_serve_wait", "lg_serve_cancel", "lg_serve_stats",
+               "lg_serve_destroy"):
         getattr(L, fn).restype = i32
     return L
 
@@ -100,7 +139,9 @@ _lib = _load()
 
 EXPORTED = ("lg_status_str", "lg_last_error", "lg_version", "lg_build_field", "lg_field_import",
             "lg_field_export", "lg_field_info", "lg_field_release", "lg_query_domains",
-            "lg_search_workspace_bytes", "lg_search", "lg_realize")
+            "lg_search_workspace_bytes", "lg_search", "lg_realize", "lg_serve_request_bytes",
+            "lg_serve_create", "lg_serve_submit", "lg_serve_poll", "lg_serve_wait", "lg_serve_cancel",
+            "lg_serve_stats", "lg_serve_clock", "lg_serve_destroy")
 
 
 def lib():
@@ -297,3 +338,99 @@ def lg_realize(field: Field, sdf: Sdf, pts, nrm, poses, set_pt, set_link, k: int
 
 def version() -> str:
     return _lib.lg_version().decode()
+
+
+# ---- serving -----------------------------------------------------------------
+def result_dict(r: Result) -> dict:
+    return {k: getattr(r, k) for k, _ in Result._fields_}
+
+
+class Server:
+    """Continuous-batching server over resident fields (see ``lg_serve_*``)."""
+
+    def __init__(self, budget_bytes: int, max_active: int = 8, chunk_poses: int = 4096):
+        self.params = ServerParams(int(budget_bytes), int(max_active), int(chunk_poses))
+        h = C.c_void_p()
+        _check(_lib.lg_serve_create(C.byref(self.params), C.byref(h)), "lg_serve_create")
+        self.handle = h
+        self._keep = {}
+
+    def make_request(self, field: Field, pts: np.ndarray, nrm: np.ndarray, poses: np.ndarray, sp,
+                     request_id: int, ik=None, sdf=None, max_pivots: int = 1000):
+        pts = np.ascontiguousarray(pts, np.float32)
+        nrm = np.ascontiguousarray(nrm, np.float32)
+        poses = np.ascontiguousarray(poses, np.float32)
+        keep = [pts, nrm, poses]
+        req = Request()
+        req.field = field.handle
+        req.pts, req.nrm, req.poses = _hp(pts), _hp(nrm), _hp(poses)
+        req.n_points, req.n_poses = int(pts.shape[0]), int(poses.shape[0])
+        req.search = search_params(sp, max_pivots)
+        req.request_id = int(request_id)
+        if ik is not None:
+            vals = np.ascontiguousarray(sdf.values, np.float32)
+            keep.append(vals)
+            req.realize = 1
+            req.ik = ik_params(ik)
+            req.sdf_values = _hp(vals)
+            req.sdf_origin = (C.c_float * 3)(*[float(x) for x in np.asarray(sdf.origin, np.float32)])
+            req.sdf_h = float(sdf.h)
+            req.sdf_dims = int(sdf.dims)
+        return req, keep
+
+    def request_bytes(self, req: Request) -> int:
+        return int(_lib.lg_serve_request_bytes(C.byref(self.params), C.byref(req)))
+
+    def submit(self, req: Request) -> int:
+        t = C.c_uint64()
+        _check(_lib.lg_serve_submit(self.handle, C.byref(req), C.byref(t)), "lg_serve_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int) -> dict:
+        r = Result()
+        _check(_lib.lg_serve_poll(self.handle, int(ticket), C.byref(r)), "lg_serve_poll")
+        return result_dict(r)
+
+    def wait(self, ticket: int, timeout_s: float = 60.0) -> dict:
+        r = Result()
+        _check(_lib.lg_serve_wait(self.handle, int(ticket), float(timeout_s), C.byref(r)), "lg_serve_wait")
+        return result_dict(r)
+
+    def cancel(self, ticket: int):
+        _check(_lib.lg_serve_cancel(self.handle, int(ticket)), "lg_serve_cancel")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(_lib.lg_serve_stats(self.handle, C.byref(st)), "lg_serve_stats")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def clock(self) -> float:
+        return float(_lib.lg_serve_clock(self.handle))
+
+    def destroy(self):
+        if self.handle:
+            _lib.lg_serve_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def mix64(z: int) -> int:
+    """splitmix64 finaliser used for the order-independent accepted-set hash."""
+    m = (1 << 64) - 1
+    z = (z + 0x9E3779B97F4A7C15) & m
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31)
+
+
+def accepted_hash(request_id: int, acc_ids) -> int:
+    """Hash the server reports for accepted set ids (pose * D + draw)."""
+    h = 0
+    for i in acc_ids:
+        h = (h + mix64(((int(request_id) << 40) ^ int(i)) & ((1 << 64) - 1))) & ((1 << 64) - 1)
+    return h

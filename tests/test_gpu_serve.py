@@ -1,0 +1,132 @@
+"""Serving (continuous batching over resident fields) through the C ABI.
+
+* a request's result (accepted count, valid count, hash of the accepted
+  (pose, draw) ids) is identical alone and mixed with other requests;
+* it equals the direct lg_query_domains / lg_search pipeline on the same
+  request id;
+* admission by the HBM budget: a request larger than the budget is rejected
+  with LG_EBUDGET; with room for one request at a time, requests are admitted
+  in order as memory frees up;
+* cancellation of a queued request.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    from paper_2511_07418_amd import lg
+    w1 = synth.workload("c1", n_poses=600)
+    w2 = synth.workload("c2", n_poses=300, n_points=3000, samples=16384)
+    f1 = lg.lg_build_field(w1.hand, w1.field, keep_witness=False)
+    f2 = lg.lg_build_field(w2.hand, w2.field, keep_witness=False)
+    return lg, w1, w2, f1, f2
+
+
+def _direct(lg, field, w, rid):
+    from paper_2511_07418_amd.pipeline import Pipeline
+    sp = synth.SearchParams(**{**w.search.__dict__, "request_id": rid, "pose_offset": 0})
+    pipe = Pipeline(field, w.obj.pts, w.obj.nrm, w.poses, sp)
+    pipe.query()
+    pipe.search()
+    torch.cuda.synchronize()
+    n = pipe.n_acc()
+    acc = pipe.sbuf.acc_list[:n].cpu().numpy()
+    return n, lg.accepted_hash(rid, acc)
+
+
+def test_serve_alone_equals_mix_equals_direct(env):
+    lg, w1, w2, f1, f2 = env
+    srv = lg.Server(budget_bytes=1 << 30, max_active=4, chunk_poses=128)
+    reqA, keepA = srv.make_request(f1, w1.obj.pts, w1.obj.nrm, w1.poses, w1.search, request_id=7)
+    ta = srv.submit(reqA)
+    alone = srv.wait(ta, 60.0)
+    assert alone["state"] == lg.LG_REQ_DONE and alone["n_acc"] > 0
+    # the same request mixed with two others of different sizes and hands
+    reqB, keepB = srv.make_request(f2, w2.obj.pts, w2.obj.nrm, w2.poses, w2.search, request_id=8)
+    reqC, keepC = srv.make_request(f1, w1.obj.pts[:777], w1.obj.nrm[:777], w1.poses[:300], w1.search,
+                                   request_id=9)
+    tb = srv.submit(reqB)
+    ta2 = srv.submit(reqA)
+    tc = srv.submit(reqC)
+    rb, ra2, rc = srv.wait(tb, 120.0), srv.wait(ta2, 120.0), srv.wait(tc, 120.0)
+    assert rb["state"] == rc["state"] == ra2["state"] == lg.LG_REQ_DONE
+    assert (ra2["n_acc"], ra2["n_valid"], ra2["acc_hash"]) == (alone["n_acc"], alone["n_valid"], alone["acc_hash"])
+    # the mix really overlapped: A2 was admitted before B finished
+    assert ra2["t_admit"] < rb["t_done"]
+    # equal to the direct (unchunked) pipeline on the same request id
+    n, h = _direct(lg, f1, w1, 7)
+    assert (alone["n_acc"], alone["acc_hash"]) == (n, h)
+    n, h = _direct(lg, f2, w2, 8)
+    assert (rb["n_acc"], rb["acc_hash"]) == (n, h)
+    st = srv.stats()
+    assert st["completed"] == 4 and st["bytes_in_use"] == 0
+    srv.destroy()
+
+
+def test_serve_admission_by_budget_and_rejection(env):
+    lg, w1, w2, f1, f2 = env
+    probe = lg.Server(budget_bytes=1 << 20, max_active=2, chunk_poses=64)
+    req, keep = probe.make_request(f1, w1.obj.pts, w1.obj.nrm, w1.poses, w1.search, request_id=1)
+    need = probe.request_bytes(req)
+    # too large for a 1 MiB budget
+    if need > (1 << 20):
+        with pytest.raises(lg.LgError) as ei:
+            probe.submit(req)
+        assert ei.value.status == lg.LG_EBUDGET
+        assert probe.stats()["rejected"] == 1
+    probe.destroy()
+    # room for exactly one such request: the second waits for the first
+    srv = lg.Server(budget_bytes=need + 4096, max_active=4, chunk_poses=64)
+    t1 = srv.submit(req)
+    req2, keep2 = srv.make_request(f1, w1.obj.pts, w1.obj.nrm, w1.poses, w1.search, request_id=2)
+    t2 = srv.submit(req2)
+    r1, r2 = srv.wait(t1, 60.0), srv.wait(t2, 60.0)
+    assert r1["state"] == r2["state"] == lg.LG_REQ_DONE
+    assert r2["t_admit"] >= r1["t_done"]
+    assert srv.stats()["peak_bytes"] <= need + 4096
+    srv.destroy()
+
+
+def test_serve_cancel_queued(env):
+    lg, w1, w2, f1, f2 = env
+    probe = lg.Server(budget_bytes=1 << 30, max_active=1, chunk_poses=32)
+    req, keep = probe.make_request(f2, w2.obj.pts, w2.obj.nrm, w2.poses, w2.search, request_id=3)
+    t1 = probe.submit(req)
+    t2 = probe.submit(req)  # queued behind t1 (one active slot)
+    probe.cancel(t2)
+    r2 = probe.poll(t2)
+    assert r2["state"] in (lg.LG_REQ_CANCELLED, lg.LG_REQ_DONE)
+    r1 = probe.wait(t1, 120.0)
+    assert r1["state"] == lg.LG_REQ_DONE
+    r2 = probe.wait(t2, 120.0)
+    assert r2["state"] == lg.LG_REQ_CANCELLED
+    assert probe.stats()["cancelled"] == 1
+    probe.destroy()
+
+
+def test_serve_with_realize(env):
+    """Requests that run IK + penetration report valid <= accepted, and the
+    valid count equals the direct pipeline's."""
+    lg, _, _, _, _ = env
+    from paper_2511_07418_amd.pipeline import Pipeline
+    w = synth.workload("c1", n_poses=200, with_sdf=True)
+    field = lg.lg_build_field(w.hand, w.field, keep_witness=True)
+    srv = lg.Server(budget_bytes=1 << 30, max_active=2, chunk_poses=64)
+    req, keep = srv.make_request(field, w.obj.pts, w.obj.nrm, w.poses, w.search, request_id=5, ik=w.ik, sdf=w.sdf)
+    r = srv.wait(srv.submit(req), 60.0)
+    assert r["state"] == lg.LG_REQ_DONE and r["n_valid"] <= r["n_acc"]
+    sp = synth.SearchParams(**{**w.search.__dict__, "request_id": 5})
+    pipe = Pipeline(field, w.obj.pts, w.obj.nrm, w.poses, sp, ik=w.ik, sdf=w.sdf)
+    pipe.step()
+    torch.cuda.synchronize()
+    assert (r["n_acc"], r["n_valid"]) == (pipe.n_acc(), pipe.valid_count())
+    srv.destroy()
