@@ -29,7 +29,8 @@ __global__ void __launch_bounds__(kDrawThreads)
 k_draw(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ pts, const float *__restrict__ nrm,
        int N, const float *__restrict__ poses, const uint32_t *__restrict__ dom_bits,
        const uint32_t *__restrict__ dom_count, int D, int k, uint32_t seed_lo, uint32_t seed_hi,
-       uint32_t request_id, int64_t pose_offset, int32_t *__restrict__ set_pt, int8_t *__restrict__ set_link)
+       uint32_t request_id, int64_t pose_offset, int32_t *__restrict__ set_pt, int8_t *__restrict__ set_link,
+       uint8_t *__restrict__ pose_valid, uint8_t *__restrict__ verdict, double *__restrict__ tstar)
 {
     extern __shared__ uint32_t prefix[];  // [F][nsb + 1]
     __shared__ float cb[3 * kMaxBins];
@@ -42,10 +43,15 @@ k_draw(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ p
     __syncthreads();
     bool empty = false;
     for (int f = 0; f < F; ++f) empty |= counts[f] == 0;
+    if (threadIdx.x == 0) pose_valid[g] = empty ? 0 : 1;
     if (empty) {
         for (int i = threadIdx.x; i < D * k; i += blockDim.x) {
             set_pt[(int64_t)g * D * k + i] = -1;
             set_link[(int64_t)g * D * k + i] = -1;
+        }
+        for (int d = threadIdx.x; d < D; d += blockDim.x) {  // no LP for these sets
+            verdict[(int64_t)g * D + d] = 0;
+            tstar[(int64_t)g * D + d] = __builtin_nan("");
         }
         return;  // uniform over the block
     }
@@ -132,6 +138,7 @@ __device__ inline void duff_basis(double nx, double ny, double nz, double *x, do
 
 constexpr double kLpTol = 1e-12;  // reduced-cost and ratio-tie tolerance
 constexpr double kLpPiv = 1e-9;   // smallest admissible pivot element
+constexpr int kBlandAfter = 48;   // pivots priced by Dantzig's rule before Bland's
 
 // ---- force-closure LP, one set per lane -------------------------------------
 // Revised simplex with an explicit 7x7 basis inverse per lane.  Reduced
@@ -153,247 +160,263 @@ struct LpConst {
 template <int KM>
 __global__ void __launch_bounds__(256)
 k_verdict_lane(const float *__restrict__ pts, const float *__restrict__ nrm, int N, const int32_t *__restrict__ set_pt,
-               int64_t n_sets, int k, int m, double mu, double rho, double eps, int max_pivots, LpConst cs,
-               uint8_t *__restrict__ verdict, double *__restrict__ tstar)
+               const int32_t *__restrict__ valid_poses, const int32_t *__restrict__ n_valid_poses, int D, int k,
+               int m, double mu, double rho, double eps, int max_pivots, LpConst cs, uint8_t *__restrict__ verdict,
+               double *__restrict__ tstar)
 {
     // contact data of this lane's set in LDS, lane-contiguous: cd[6*i + c][tid]
     __shared__ float cd[KM * 6][256];
     const int tid = threadIdx.x;
-    const int64_t sid = (int64_t)blockIdx.x * blockDim.x + tid;
-    if (sid >= n_sets) return;  // no block-level synchronisation below
-    const int32_t *sp = set_pt + sid * k;
-    bool valid = true;
-    for (int i = 0; i < k; ++i) {
-        const int idx = sp[i];
-        valid &= idx >= 0;
-        const int ii = idx >= 0 ? idx : 0;
-        cd[6 * i + 0][tid] = pts[ii];
-        cd[6 * i + 1][tid] = pts[N + ii];
-        cd[6 * i + 2][tid] = pts[2 * N + ii];
-        cd[6 * i + 3][tid] = nrm[ii];
-        cd[6 * i + 4][tid] = nrm[N + ii];
-        cd[6 * i + 5][tid] = nrm[2 * N + ii];
-    }
-    if (!valid) {
-        verdict[sid] = 0;
-        tstar[sid] = __builtin_nan("");
-        return;
-    }
-    const int n = k * m;
-    const double inv_rho = 1.0 / rho;
-    // contact i's point and normal (each lane reads only its own column)
-    auto contact = [&](int ci, double &px, double &py, double &pz, double &nx, double &ny, double &nz) {
-        px = cd[6 * ci + 0][tid];
-        py = cd[6 * ci + 1][tid];
-        pz = cd[6 * ci + 2][tid];
-        nx = cd[6 * ci + 3][tid];
-        ny = cd[6 * ci + 4][tid];
-        nz = cd[6 * ci + 5][tid];
-    };
-    // original column j of [W^T -I I; 1 0 0]
-    auto column = [&](int j, double *a) {
-#pragma unroll
-        for (int r = 0; r < 7; ++r) a[r] = 0.0;
-        if (j < n) {
-            const int ci = j / m, e = j - ci * m;
-            double px, py, pz, nx, ny, nz;
-            contact(ci, px, py, pz, nx, ny, nz);
-            double x[3], y[3];
-            duff_basis(nx, ny, nz, x, y);
-            const double c = cs.ce[e], s = cs.se[e];
-            const double dx = -nx + mu * (c * x[0] + s * y[0]);
-            const double dy = -ny + mu * (c * x[1] + s * y[1]);
-            const double dz = -nz + mu * (c * x[2] + s * y[2]);
-            a[0] = dx;
-            a[1] = dy;
-            a[2] = dz;
-            a[3] = (py * dz - pz * dy) / rho;
-            a[4] = (pz * dx - px * dz) / rho;
-            a[5] = (px * dy - py * dx) / rho;
-            a[6] = 1.0;
-        } else if (j < n + 6) {
-#pragma unroll
-            for (int r = 0; r < 6; ++r) a[r] = (r == j - n) ? -1.0 : 0.0;
-        } else {
-#pragma unroll
-            for (int r = 0; r < 6; ++r) a[r] = (r == j - n - 6) ? 1.0 : 0.0;
+    const int64_t n_work = (int64_t)(*n_valid_poses) * D;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // grid-stride over the sets of poses whose domains are all non-empty
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + tid; t < n_work; t += stride) {
+        const int64_t sid = (int64_t)valid_poses[t / D] * D + (t % D);
+        const int32_t *sp = set_pt + sid * k;
+        bool valid = true;
+        for (int i = 0; i < k; ++i) {
+            const int idx = sp[i];
+            valid &= idx >= 0;
+            const int ii = idx >= 0 ? idx : 0;
+            cd[6 * i + 0][tid] = pts[ii];
+            cd[6 * i + 1][tid] = pts[N + ii];
+            cd[6 * i + 2][tid] = pts[2 * N + ii];
+            cd[6 * i + 3][tid] = nrm[ii];
+            cd[6 * i + 4][tid] = nrm[N + ii];
+            cd[6 * i + 5][tid] = nrm[2 * N + ii];
         }
-    };
-    // initial basis: g_0 on the normalisation row, s-_r (w0_r <= 0) or s+_r
-    double Bi[7][7], xB[7];
-    int basis[7];
-    {
-        double w0[7];
-        column(0, w0);
-#pragma unroll
-        for (int r = 0; r < 7; ++r)
-#pragma unroll
-            for (int c = 0; c < 7; ++c) Bi[r][c] = 0.0;
-#pragma unroll
-        for (int r = 0; r < 6; ++r) {
-            const double sg = w0[r] <= 0.0 ? 1.0 : -1.0;
-            basis[r] = w0[r] <= 0.0 ? n + 6 + r : n + r;
-            Bi[r][r] = sg;
-            Bi[r][6] = -sg * w0[r];
-            xB[r] = -sg * w0[r];
+        if (!valid) {
+            verdict[sid] = 0;
+            tstar[sid] = __builtin_nan("");
+            continue;
         }
-        Bi[6][6] = 1.0;
-        basis[6] = 0;
-        xB[6] = 1.0;
-    }
-    auto cost = [&](int j) { return j >= n ? 1.0 : 0.0; };
-    auto duals = [&](double *y) {
+        const int n = k * m;
+        const double inv_rho = 1.0 / rho;
+        // contact i's point and normal (each lane reads only its own column)
+        auto contact = [&](int ci, double &px, double &py, double &pz, double &nx, double &ny, double &nz) {
+            px = cd[6 * ci + 0][tid];
+            py = cd[6 * ci + 1][tid];
+            pz = cd[6 * ci + 2][tid];
+            nx = cd[6 * ci + 3][tid];
+            ny = cd[6 * ci + 4][tid];
+            nz = cd[6 * ci + 5][tid];
+        };
+        // original column j of [W^T -I I; 1 0 0]
+        auto column = [&](int j, double *a) {
 #pragma unroll
-        for (int c = 0; c < 7; ++c) {
-            double s = 0.0;
+            for (int r = 0; r < 7; ++r) a[r] = 0.0;
+            if (j < n) {
+                const int ci = j / m, e = j - ci * m;
+                double px, py, pz, nx, ny, nz;
+                contact(ci, px, py, pz, nx, ny, nz);
+                double x[3], y[3];
+                duff_basis(nx, ny, nz, x, y);
+                const double c = cs.ce[e], s = cs.se[e];
+                const double dx = -nx + mu * (c * x[0] + s * y[0]);
+                const double dy = -ny + mu * (c * x[1] + s * y[1]);
+                const double dz = -nz + mu * (c * x[2] + s * y[2]);
+                a[0] = dx;
+                a[1] = dy;
+                a[2] = dz;
+                a[3] = (py * dz - pz * dy) / rho;
+                a[4] = (pz * dx - px * dz) / rho;
+                a[5] = (px * dy - py * dx) / rho;
+                a[6] = 1.0;
+            } else if (j < n + 6) {
 #pragma unroll
-            for (int r = 0; r < 7; ++r) s += cost(basis[r]) * Bi[r][c];
-            y[c] = s;
-        }
-    };
-    // Bland pricing: first column with a negative reduced cost, -1 if none
-    auto price = [&](const double *y) {
-        int e = -1;
-        for (int i = 0; i < k && e < 0; ++i) {
-            double px, py, pz, nx, ny, nz;
-            contact(i, px, py, pz, nx, ny, nz);
-            // u = y_f + (y_m x p) / rho
-            const double ux = y[0] + (y[4] * pz - y[5] * py) * inv_rho;
-            const double uy = y[1] + (y[5] * px - y[3] * pz) * inv_rho;
-            const double uz = y[2] + (y[3] * py - y[4] * px) * inv_rho;
-            double x[3], yy[3];
-            duff_basis(nx, ny, nz, x, yy);
-            const double an = ux * nx + uy * ny + uz * nz;
-            const double bx = ux * x[0] + uy * x[1] + uz * x[2];
-            const double by = ux * yy[0] + uy * yy[1] + uz * yy[2];
-            for (int ee = 0; ee < m; ++ee) {
-                const double d = -(-an + mu * (cs.ce[ee] * bx + cs.se[ee] * by)) - y[6];
-                if (d < -kLpTol) {
-                    e = i * m + ee;
-                    break;
-                }
+                for (int r = 0; r < 6; ++r) a[r] = (r == j - n) ? -1.0 : 0.0;
+            } else {
+#pragma unroll
+                for (int r = 0; r < 6; ++r) a[r] = (r == j - n - 6) ? 1.0 : 0.0;
             }
+        };
+        // initial basis: g_0 on the normalisation row, s-_r (w0_r <= 0) or s+_r
+        double Bi[7][7], xB[7];
+        int basis[7];
+        {
+            double w0[7];
+            column(0, w0);
+#pragma unroll
+            for (int r = 0; r < 7; ++r)
+#pragma unroll
+                for (int c = 0; c < 7; ++c) Bi[r][c] = 0.0;
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                const double sg = w0[r] <= 0.0 ? 1.0 : -1.0;
+                basis[r] = w0[r] <= 0.0 ? n + 6 + r : n + r;
+                Bi[r][r] = sg;
+                Bi[r][6] = -sg * w0[r];
+                xB[r] = -sg * w0[r];
+            }
+            Bi[6][6] = 1.0;
+            basis[6] = 0;
+            xB[6] = 1.0;
         }
-        for (int r = 0; r < 6 && e < 0; ++r)
-            if (1.0 + y[r] < -kLpTol) e = n + r;
-        for (int r = 0; r < 6 && e < 0; ++r)
-            if (1.0 - y[r] < -kLpTol) e = n + 6 + r;
-        return e;
-    };
-    // residual corrections of x_B (B x = e_6) and y (B^T y = c_B)
-    auto refine = [&](double *y) {
-        for (int pass = 0; pass < 2; ++pass) {
-            double rx[7] = {0, 0, 0, 0, 0, 0, 1.0}, ry[7];
-#pragma unroll 1
-            for (int q = 0; q < 7; ++q) {
-                double a[7];
-                column(basis[q], a);
-                double dot = 0.0;
-#pragma unroll
-                for (int r = 0; r < 7; ++r) {
-                    rx[r] -= a[r] * xB[q];
-                    dot += a[r] * y[r];
-                }
-                ry[q] = cost(basis[q]) - dot;
-            }
-#pragma unroll
-            for (int r = 0; r < 7; ++r) {
-                double s = 0.0;
-#pragma unroll
-                for (int c = 0; c < 7; ++c) s += Bi[r][c] * rx[c];
-                xB[r] += s;
-            }
+        auto cost = [&](int j) { return j >= n ? 1.0 : 0.0; };
+        auto duals = [&](double *y) {
 #pragma unroll
             for (int c = 0; c < 7; ++c) {
                 double s = 0.0;
 #pragma unroll
-                for (int r = 0; r < 7; ++r) s += ry[r] * Bi[r][c];
-                y[c] += s;
+                for (int r = 0; r < 7; ++r) s += cost(basis[r]) * Bi[r][c];
+                y[c] = s;
             }
-        }
-    };
-    int piv = 0, status = 0, checks = 0;
-    for (;;) {
-        double y[7];
-        duals(y);
-        int e = price(y);
-        if (e < 0) {
-            if (checks >= 4) break;
-            ++checks;
-            refine(y);
-            e = price(y);
-            if (e < 0) break;
-        }
-        if (piv >= max_pivots) {
-            status = 1;
-            break;
-        }
-        double a[7], al[7];
-        column(e, a);
-#pragma unroll
-        for (int r = 0; r < 7; ++r) {
-            double s = 0.0;
-#pragma unroll
-            for (int c = 0; c < 7; ++c) s += Bi[r][c] * a[c];
-            al[r] = s;
-        }
-        // ratio test min x_B[r] / al[r] without divisions: the current best is
-        // kept as the fraction bx / ba (ba > 0) and ratios are compared by
-        // cross-multiplication; the tie band is kLpTol (1 + |best|).
-        int lr = -1;
-        double bx = 0.0, ba = 1.0;
-#pragma unroll
-        for (int r = 0; r < 7; ++r) {
-            if (al[r] > kLpPiv) {
-                const double lhs = xB[r] * ba, rhs = bx * al[r];
-                const double band = kLpTol * (ba + fabs(bx)) * al[r];
-                if (lr < 0 || lhs < rhs - band || (fabs(lhs - rhs) <= band && basis[r] < basis[lr])) {
-                    lr = r;
-                    bx = xB[r];
-                    ba = al[r];
+        };
+        // Pricing.  Dantzig (most negative reduced cost, ties to the lowest index)
+        // for the first kBlandAfter pivots; Bland (first negative) afterwards,
+        // which rules out cycling.  -1 when no reduced cost is below -kLpTol.
+        auto price = [&](const double *y, bool bland) {
+            int e = -1;
+            double best = -kLpTol;
+            for (int i = 0; i < k && !(bland && e >= 0); ++i) {
+                double px, py, pz, nx, ny, nz;
+                contact(i, px, py, pz, nx, ny, nz);
+                // u = y_f + (y_m x p) / rho
+                const double ux = y[0] + (y[4] * pz - y[5] * py) * inv_rho;
+                const double uy = y[1] + (y[5] * px - y[3] * pz) * inv_rho;
+                const double uz = y[2] + (y[3] * py - y[4] * px) * inv_rho;
+                double x[3], yy[3];
+                duff_basis(nx, ny, nz, x, yy);
+                const double an = ux * nx + uy * ny + uz * nz;
+                const double bx = ux * x[0] + uy * x[1] + uz * x[2];
+                const double by = ux * yy[0] + uy * yy[1] + uz * yy[2];
+                for (int ee = 0; ee < m; ++ee) {
+                    const double d = -(-an + mu * (cs.ce[ee] * bx + cs.se[ee] * by)) - y[6];
+                    if (d < best) {
+                        best = d;
+                        e = i * m + ee;
+                        if (bland) break;
+                    }
                 }
             }
-        }
-        if (lr < 0) {
-            status = 2;
-            break;
-        }
-        double pv = 1.0, prow[7], px = 0.0;
+            for (int r = 0; r < 6 && !(bland && e >= 0); ++r)
+                if (1.0 + y[r] < best) {
+                    best = 1.0 + y[r];
+                    e = n + r;
+                }
+            for (int r = 0; r < 6 && !(bland && e >= 0); ++r)
+                if (1.0 - y[r] < best) {
+                    best = 1.0 - y[r];
+                    e = n + 6 + r;
+                }
+            return e;
+        };
+        // residual corrections of x_B (B x = e_6) and y (B^T y = c_B)
+        auto refine = [&](double *y) {
+            for (int pass = 0; pass < 2; ++pass) {
+                double rx[7] = {0, 0, 0, 0, 0, 0, 1.0}, ry[7];
+#pragma unroll 1
+                for (int q = 0; q < 7; ++q) {
+                    double a[7];
+                    column(basis[q], a);
+                    double dot = 0.0;
 #pragma unroll
-        for (int c = 0; c < 7; ++c) prow[c] = 0.0;
+                    for (int r = 0; r < 7; ++r) {
+                        rx[r] -= a[r] * xB[q];
+                        dot += a[r] * y[r];
+                    }
+                    ry[q] = cost(basis[q]) - dot;
+                }
+#pragma unroll
+                for (int r = 0; r < 7; ++r) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int c = 0; c < 7; ++c) s += Bi[r][c] * rx[c];
+                    xB[r] += s;
+                }
+#pragma unroll
+                for (int c = 0; c < 7; ++c) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int r = 0; r < 7; ++r) s += ry[r] * Bi[r][c];
+                    y[c] += s;
+                }
+            }
+        };
+        int piv = 0, status = 0, checks = 0;
+        for (;;) {
+            double y[7];
+            duals(y);
+            const bool bland = piv >= kBlandAfter;
+            int e = price(y, bland);
+            if (e < 0) {
+                if (checks >= 4) break;
+                ++checks;
+                refine(y);
+                e = price(y, bland);
+                if (e < 0) break;
+            }
+            if (piv >= max_pivots) {
+                status = 1;
+                break;
+            }
+            double a[7], al[7];
+            column(e, a);
+#pragma unroll
+            for (int r = 0; r < 7; ++r) {
+                double s = 0.0;
+#pragma unroll
+                for (int c = 0; c < 7; ++c) s += Bi[r][c] * a[c];
+                al[r] = s;
+            }
+            // ratio test min x_B[r] / al[r] without divisions: the current best is
+            // kept as the fraction bx / ba (ba > 0) and ratios are compared by
+            // cross-multiplication; the tie band is kLpTol (1 + |best|).
+            int lr = -1;
+            double bx = 0.0, ba = 1.0;
+#pragma unroll
+            for (int r = 0; r < 7; ++r) {
+                if (al[r] > kLpPiv) {
+                    const double lhs = xB[r] * ba, rhs = bx * al[r];
+                    const double band = kLpTol * (ba + fabs(bx)) * al[r];
+                    if (lr < 0 || lhs < rhs - band || (fabs(lhs - rhs) <= band && basis[r] < basis[lr])) {
+                        lr = r;
+                        bx = xB[r];
+                        ba = al[r];
+                    }
+                }
+            }
+            if (lr < 0) {
+                status = 2;
+                break;
+            }
+            double pv = 1.0, prow[7], px = 0.0;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) prow[c] = 0.0;
+#pragma unroll
+            for (int r = 0; r < 7; ++r)
+                if (r == lr) {
+                    pv = al[r];
+                    px = xB[r];
+#pragma unroll
+                    for (int c = 0; c < 7; ++c) prow[c] = Bi[r][c];
+                }
+            const double inv = 1.0 / pv;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) prow[c] *= inv;
+            px *= inv;
+#pragma unroll
+            for (int r = 0; r < 7; ++r) {
+                if (r == lr) {
+#pragma unroll
+                    for (int c = 0; c < 7; ++c) Bi[r][c] = prow[c];
+                    xB[r] = px;
+                    basis[r] = e;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 7; ++c) Bi[r][c] -= al[r] * prow[c];
+                    xB[r] -= al[r] * px;
+                }
+            }
+            ++piv;
+        }
+        double ts = 0.0;
 #pragma unroll
         for (int r = 0; r < 7; ++r)
-            if (r == lr) {
-                pv = al[r];
-                px = xB[r];
-#pragma unroll
-                for (int c = 0; c < 7; ++c) prow[c] = Bi[r][c];
-            }
-        const double inv = 1.0 / pv;
-#pragma unroll
-        for (int c = 0; c < 7; ++c) prow[c] *= inv;
-        px *= inv;
-#pragma unroll
-        for (int r = 0; r < 7; ++r) {
-            if (r == lr) {
-#pragma unroll
-                for (int c = 0; c < 7; ++c) Bi[r][c] = prow[c];
-                xB[r] = px;
-                basis[r] = e;
-            } else {
-#pragma unroll
-                for (int c = 0; c < 7; ++c) Bi[r][c] -= al[r] * prow[c];
-                xB[r] -= al[r] * px;
-            }
-        }
-        ++piv;
+            if (basis[r] >= n) ts += xB[r];
+        verdict[sid] = (status == 0 && ts <= eps) ? 1 : 0;
+        tstar[sid] = status == 0 ? ts : __builtin_nan("");
     }
-    double t = 0.0;
-#pragma unroll
-    for (int r = 0; r < 7; ++r)
-        if (basis[r] >= n) t += xB[r];
-    verdict[sid] = (status == 0 && t <= eps) ? 1 : 0;
-    tstar[sid] = status == 0 ? t : __builtin_nan("");
 }
 
 // ---- compaction ------------------------------------------------------------
@@ -473,12 +496,36 @@ using namespace lg;
 
 extern "C" {
 
+// workspace: [set chunks: count, offset] [pose chunks: count, offset]
+//            [valid pose list P] [n_valid_poses] [pose_valid P bytes]
+struct SearchWs {
+    uint32_t *chunk_count, *chunk_off, *pchunk_count, *pchunk_off;
+    int32_t *valid_poses, *n_valid_poses;
+    uint8_t *pose_valid;
+    size_t bytes;
+};
+
+static SearchWs search_ws(void *base, int64_t n_poses, int64_t draws)
+{
+    const int64_t n_sets = n_poses * draws;
+    const int64_t nc = (n_sets + kChunk - 1) / kChunk, npc = (n_poses + kChunk - 1) / kChunk;
+    SearchWs w;
+    uint32_t *u = static_cast<uint32_t *>(base);
+    w.chunk_count = u;
+    w.chunk_off = u + nc;
+    w.pchunk_count = u + 2 * nc;
+    w.pchunk_off = u + 2 * nc + npc;
+    w.valid_poses = reinterpret_cast<int32_t *>(u + 2 * nc + 2 * npc);
+    w.n_valid_poses = w.valid_poses + n_poses;
+    w.pose_valid = reinterpret_cast<uint8_t *>(w.n_valid_poses + 1);
+    w.bytes = (size_t)(2 * nc + 2 * npc + n_poses + 1) * 4 + (size_t)n_poses + 256;
+    return w;
+}
+
 size_t lg_search_workspace_bytes(int32_t n_poses, const lg_search_params *p)
 {
     if (!p || n_poses <= 0 || p->draws <= 0) return 256;
-    const int64_t n_sets = (int64_t)n_poses * p->draws;
-    const int64_t n_chunks = (n_sets + kChunk - 1) / kChunk;
-    return (size_t)(2 * n_chunks * sizeof(uint32_t) + 256);
+    return search_ws(nullptr, n_poses, p->draws).bytes;
 }
 
 lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, int32_t n_points, const float *poses,
@@ -504,9 +551,19 @@ lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, i
     const size_t lds = (size_t)H.F * (nsb + 1) * sizeof(uint32_t);
     if (lds > 48 * 1024) return fail(LG_EUNSUPPORTED, "too many points for the draw rank structure");
     hipStream_t s = as_stream(stream);
+    const SearchWs ws = search_ws(workspace, n_poses, p->draws);
     hipLaunchKernelGGL(k_draw, dim3(n_poses), dim3(kDrawThreads), lds, s, H, field->d_bits, pts, nrm, n_points,
                        poses, dom_bits, dom_count, p->draws, p->k, (uint32_t)p->seed, (uint32_t)(p->seed >> 32),
-                       p->request_id, p->pose_offset, set_pt, set_link);
+                       p->request_id, p->pose_offset, set_pt, set_link, ws.pose_valid, verdict, tstar);
+    LG_HIP(hipGetLastError());
+    // list of poses whose domains are all non-empty (ordered)
+    const int64_t npc = (n_poses + kChunk - 1) / kChunk;
+    hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)npc), dim3(kCompactThreads), 0, s, ws.pose_valid,
+                       (int64_t)n_poses, ws.pchunk_count);
+    hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kCompactThreads), 0, s, ws.pchunk_count, npc, ws.pchunk_off,
+                       ws.n_valid_poses);
+    hipLaunchKernelGGL(k_chunk_scatter, dim3((unsigned)npc), dim3(kCompactThreads), 0, s, ws.pose_valid,
+                       (int64_t)n_poses, ws.pchunk_off, ws.valid_poses);
     LG_HIP(hipGetLastError());
     const int64_t n_sets = (int64_t)n_poses * p->draws;
     LpConst cs;
@@ -515,19 +572,22 @@ lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, i
         cs.ce[e] = e < p->m_edges ? cos(th) : 0.0;
         cs.se[e] = e < p->m_edges ? sin(th) : 0.0;
     }
-    const dim3 lgrid((unsigned)((n_sets + 255) / 256));
-    if (p->k <= 4)
-        hipLaunchKernelGGL(k_verdict_lane<4>, lgrid, dim3(256), 0, s, pts, nrm, n_points, set_pt, n_sets, p->k,
-                           p->m_edges, (double)p->mu, (double)p->moment_scale, (double)p->eps, p->max_pivots, cs,
-                           verdict, tstar);
-    else
-        hipLaunchKernelGGL(k_verdict_lane<8>, lgrid, dim3(256), 0, s, pts, nrm, n_points, set_pt, n_sets, p->k,
-                           p->m_edges, (double)p->mu, (double)p->moment_scale, (double)p->eps, p->max_pivots, cs,
-                           verdict, tstar);
+    // grid-stride LP launch sized to the device (the valid count is on the device)
+    int dev = 0, n_cu = 0;
+    LG_HIP(hipGetDevice(&dev));
+    LG_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    const dim3 lgrid((unsigned)std::max<int64_t>(1, std::min<int64_t>((n_sets + 255) / 256, (int64_t)n_cu * 8)));
+#define LG_VERDICT(KM)                                                                                          \
+    hipLaunchKernelGGL(k_verdict_lane<KM>, lgrid, dim3(256), 0, s, pts, nrm, n_points, set_pt, ws.valid_poses,   \
+                       ws.n_valid_poses, p->draws, p->k, p->m_edges, (double)p->mu, (double)p->moment_scale,     \
+                       (double)p->eps, p->max_pivots, cs, verdict, tstar)
+    if (p->k <= 3) LG_VERDICT(3); else if (p->k <= 4) LG_VERDICT(4); else if (p->k <= 5) LG_VERDICT(5);
+    else if (p->k <= 6) LG_VERDICT(6); else LG_VERDICT(8);
+#undef LG_VERDICT
     LG_HIP(hipGetLastError());
     const int64_t n_chunks = (n_sets + kChunk - 1) / kChunk;
-    uint32_t *chunk_count = static_cast<uint32_t *>(workspace);
-    uint32_t *chunk_off = chunk_count + n_chunks;
+    uint32_t *chunk_count = ws.chunk_count;
+    uint32_t *chunk_off = ws.chunk_off;
     hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)n_chunks), dim3(kCompactThreads), 0, s, verdict, n_sets,
                        chunk_count);
     hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kCompactThreads), 0, s, chunk_count, n_chunks, chunk_off, n_acc);
