@@ -45,7 +45,10 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-poses", type=int, default=0, help="poses of the CPU-oracle sample (0 = auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="full", choices=["full", "query", "search"],
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving run (req/s)")
+    ap.add_argument("--serve-seconds", type=float, default=6.0, help="arrival window of the serving run (s)")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--mode", default="full", choices=["full", "query", "search", "serve"],
                     help="query / search: only the field build and --steps launches of that stage "
                          "(query mode adds a 1 GiB device copy); for hardware-counter runs, no JSON")
     return ap.parse_args()
@@ -89,6 +92,92 @@ def query_traffic():
     if not m or not t or m.group(1) != h.hexdigest():
         return None
     return int(t.group(1))
+
+
+def serve_bench(torch, lg, rate: float, seconds: float, seed: int = 0, alone_sample: int = 40) -> dict:
+    """Serving stream: Poisson arrivals at ``rate`` req/s for ``seconds``.
+
+    Each request is a sphere (R = 40 mm) or a superquadric (axes U[30,80] mm,
+    exponents U[0.3,2]) with N log-uniform in [2k, 64k] points, a pose budget
+    log-uniform in [1k, 64k] and either the 16-DOF or the 22-DOF hand, whose
+    fields (64^3 @ 3 mm, 64 bins, S = 262,144, with witnesses) are both
+    resident.  D = 32 draws per pose, k = number of fingers, mu = 0.5, 8-edge
+    cones; accepted sets run IK + penetration against the object's 64^3 SDF.
+    Latency = completion - submission on the server clock.  A sample of the
+    same requests is then run one at a time ("alone")."""
+    import synth
+    rng = np.random.default_rng(seed + 4242)
+    hands = {16: synth.hand_c2(seed), 22: synth.hand_c3(seed)}
+    fields = {}
+    for dof, hnd in hands.items():
+        fp = synth.FieldParams(samples=262144, seed=seed, grid=64, h=0.003, bins=64,
+                               grid_frame=synth.grid_frames(hnd, 64, 0.003))
+        fields[dof] = lg.lg_build_field(hnd, fp, keep_witness=True)
+    sph = synth.sphere_object(0.04, 65536)
+    pool = [(sph, synth.sdf_sphere(0.04))]
+    for i in range(2):
+        o = synth.superquadric_object(seed + i, 65536)
+        pool.append((o, synth.sdf_superquadric(o)))
+    ik = synth.IKParams()
+    n_req = max(1, int(rng.poisson(rate * seconds)))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    reqs = []
+    for r in range(n_req):
+        obj, sdf = pool[0] if rng.uniform() < 0.5 else pool[1 + int(rng.integers(0, len(pool) - 1))]
+        n = int(np.exp(rng.uniform(np.log(2048), np.log(65536))))
+        P = int(np.exp(rng.uniform(np.log(1024), np.log(65536))))
+        sel = np.sort(rng.choice(obj.n, size=n, replace=False))  # keeps the Morton order
+        dof = 16 if rng.uniform() < 0.5 else 22
+        sp = synth.SearchParams(draws=32, k=hands[dof].n_fingers, mu=0.5, m_edges=8, eps=1e-3, seed=seed,
+                                moment_scale=obj.rho)
+        reqs.append((arrivals[r], (fields[dof], obj.pts[sel], obj.nrm[sel], synth.palm_poses(P, seed + 1000 + r),
+                                   sp, 1 + r, ik, sdf)))
+
+    def make(srv, a):
+        f, p, nm, po, sp, rid, ik_, sdf_ = a
+        return srv.make_request(f, p, nm, po, sp, rid, ik=ik_, sdf=sdf_)
+
+    srv = lg.Server(budget_bytes=48 << 30, max_active=8, chunk_poses=4096)
+    built = [make(srv, a) for _, a in reqs]
+    t0 = time.perf_counter()
+    tickets = []
+    for (arr, _), (req, keep) in zip(reqs, built):
+        dt = arr - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(req))
+    res = [srv.wait(t, 600.0) for t in tickets]
+    assert all(r["state"] == lg.LG_REQ_DONE for r in res), "serving request did not complete"
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res]) * 1e3
+    span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+    n_valid = sum(r["n_valid"] for r in res)
+    st = srv.stats()
+    srv.destroy()
+    # a sample of the same requests, one at a time
+    srv = lg.Server(budget_bytes=48 << 30, max_active=8, chunk_poses=4096)
+    idx = np.linspace(0, n_req - 1, min(alone_sample, n_req)).astype(int)
+    alone, alone_valid, same = [], 0, True
+    for i in idx:
+        req, keep = make(srv, reqs[i][1])
+        r = srv.wait(srv.submit(req), 600.0)
+        alone.append(r["t_done"] - r["t_submit"])
+        alone_valid += r["n_valid"]
+        same &= (r["n_acc"], r["n_valid"], r["acc_hash"]) == (res[i]["n_acc"], res[i]["n_valid"],
+                                                              res[i]["acc_hash"])
+    srv.destroy()
+    for f in fields.values():
+        f.release()
+    alone = np.array(alone)
+    return {"rate_rps": rate, "requests": n_req, "poses": int(sum(len(a[3]) for _, a in reqs)),
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "valid_grasps": int(n_valid), "valid_grasps_per_s": n_valid / span,
+            "peak_bytes": int(st["peak_bytes"]),
+            "alone_sample": len(idx), "alone_p50_ms": float(np.percentile(alone, 50) * 1e3),
+            "alone_p99_ms": float(np.percentile(alone, 99) * 1e3),
+            "alone_valid_grasps_per_s": alone_valid / float(alone.sum()),
+            "alone_equals_mix": bool(same),
+            "mix": "sphere / superquadric 50/50, N log-U[2k,64k], poses log-U[1k,64k], "
+                   "16/22-DOF hands 50/50, D=32, IK + SDF penetration"}
 
 
 def cpu_baseline(w, n_poses: int, samples: int) -> dict:
@@ -138,6 +227,9 @@ def main():
     from paper_2511_07418_amd.pipeline import Pipeline
 
     torch.cuda.set_device(0)
+    if args.mode == "serve":
+        print(json.dumps({"serving": serve_bench(torch, lg, args.serve_rate, args.serve_seconds, args.seed)}))
+        return
     w = synth.workload(args.workload, seed=args.seed, with_sdf=(args.workload == "c3"))
     t_build = time.perf_counter()
     field = lg.lg_build_field(w.hand, w.field, keep_witness=w.ik is not None)
@@ -234,10 +326,17 @@ def main():
                      "impl_bytes_per_launch": impl_bytes,
                      "impl_gbps": impl_bytes / (q_ms * 1e-3) / 1e9},
     }
+    out["poses_per_s"] = pipe.P / (ms_per_step / 1000.0)
+    if not args.no_serve:
+        pipe = None
+        field.release()
+        torch.cuda.empty_cache()
+        out["serving"] = serve_bench(torch, lg, args.serve_rate, args.serve_seconds, args.seed)
+        out["p50_ms"] = out["serving"]["p50_ms"]
+        out["p99_ms"] = out["serving"]["p99_ms"]
     if not args.no_cpu_baseline:
         n = args.cpu_poses or {"c1": 256, "c2": 2048, "c3": 1024}[args.workload]
         out["cpu_baseline"] = cpu_baseline(w, n, samples=16384)
-    out["poses_per_s"] = pipe.P / (ms_per_step / 1000.0)
     print(json.dumps(out))
 
 

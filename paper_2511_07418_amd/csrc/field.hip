@@ -290,7 +290,7 @@ k_field_build(DevHand H, uint32_t *__restrict__ bits, int32_t *__restrict__ wit,
         const int j = first + t;
         const float q = active ? joint_sample(H, f, (uint32_t)s, t) : 0.0f;
         T = joint_frame(H, T, t > 0, j, q);
-        // composite link -> window map: u = R_f^T (T x - o_f) / h
+        // composite link -> window map: u = R_f^T (T x - o_f) / h + G (biased, see window_voxel)
         Affine a;
         {
             const float dx = T.m[3] - gf[3], dy = T.m[7] - gf[7], dz = T.m[11] - gf[11];
@@ -299,7 +299,7 @@ k_field_build(DevHand H, uint32_t *__restrict__ bits, int32_t *__restrict__ wit,
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
                     a.m[4 * r + c] = fmaf(gf[r], T.m[c], fmaf(gf[4 + r], T.m[4 + c], gf[8 + r] * T.m[8 + c])) * H.inv_h;
-                a.m[4 * r + 3] = fmaf(gf[r], dx, fmaf(gf[4 + r], dy, gf[8 + r] * dz)) * H.inv_h;
+                a.m[4 * r + 3] = fmaf(fmaf(gf[r], dx, fmaf(gf[4 + r], dy, gf[8 + r] * dz)), H.inv_h, (float)G);
             }
         }
         if (!active) continue;

@@ -182,7 +182,9 @@ __device__ inline Tf joint_frame(const DevHand &H, const Tf &P, bool has_parent,
 
 // ---- window coordinates and normal bins -------------------------------------
 // Affine map u = A p + c from object-frame points to the voxel coordinates of
-// finger f's window under pose P: A = R_f^T R_P / h, c = R_f^T (t_P - o_f) / h.
+// finger f's window under pose P: A = R_f^T R_P / h, c = R_f^T (t_P - o_f) / h
+// + G.  The +G bias makes every coordinate of interest positive, so a plain
+// truncation is the floor (see window_voxel).
 struct Affine {
     float m[12];
 };
@@ -197,21 +199,23 @@ __device__ inline Affine finger_affine(const DevHand &H, const float *pose, int 
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             a.m[4 * r + c] = fmaf(g[r], pose[c], fmaf(g[4 + r], pose[4 + c], g[8 + r] * pose[8 + c])) * H.inv_h;
-        a.m[4 * r + 3] = fmaf(g[r], dx, fmaf(g[4 + r], dy, g[8 + r] * dz)) * H.inv_h;
+        a.m[4 * r + 3] = fmaf(fmaf(g[r], dx, fmaf(g[4 + r], dy, g[8 + r] * dz)), H.inv_h, (float)H.G);
     }
     return a;
 }
 
 // Linear voxel index (iz G + iy) G + ix of object point p in the window, -1
-// outside.  floor + one unsigned compare per axis.
+// outside.  The affine map carries a +G bias (u' = u + G): for u' >= 0 the
+// truncation equals floor, and u' < 0 (u < -G) truncates to a value <= 0,
+// which the unsigned range test rejects like any other outside point.
 __device__ inline int window_voxel(const Affine &a, int G, float px, float py, float pz)
 {
     const float ux = fmaf(a.m[0], px, fmaf(a.m[1], py, fmaf(a.m[2], pz, a.m[3])));
     const float uy = fmaf(a.m[4], px, fmaf(a.m[5], py, fmaf(a.m[6], pz, a.m[7])));
     const float uz = fmaf(a.m[8], px, fmaf(a.m[9], py, fmaf(a.m[10], pz, a.m[11])));
-    const int ix = (int)floorf(ux), iy = (int)floorf(uy), iz = (int)floorf(uz);
-    const bool in = ((unsigned)ix < (unsigned)G) & ((unsigned)iy < (unsigned)G) & ((unsigned)iz < (unsigned)G);
-    return in ? (iz * G + iy) * G + ix : -1;
+    const unsigned ix = (unsigned)((int)ux - G), iy = (unsigned)((int)uy - G), iz = (unsigned)((int)uz - G);
+    const bool in = max(ix, max(iy, iz)) < (unsigned)G;
+    return in ? (int)__umul24(__umul24(iz, G) + iy, G) + (int)ix : -1;
 }
 
 // Query direction of object normal n under pose P: q = -R_P n.
@@ -241,25 +245,16 @@ __device__ inline int nearest_bin(const float *c, int B, float dx, float dy, flo
 __device__ inline int nearest_bin_lut(const uint32_t *lut, const float *c, int B, float dx, float dy, float dz)
 {
     const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
-    int face;
-    float m, u, v;
-    if (ax >= ay && ax >= az) {
-        face = dx < 0.f ? 1 : 0;
-        m = ax;
-        u = dy;
-        v = dz;
-    } else if (ay >= az) {
-        face = dy < 0.f ? 3 : 2;
-        m = ay;
-        u = dz;
-        v = dx;
-    } else {
-        face = dz < 0.f ? 5 : 4;
-        m = az;
-        u = dx;
-        v = dy;
-    }
-    const float s = (0.5f * kLutRes) / m;
+    // major axis (ties to the lower axis), branch-free
+    const bool xm = (ax >= ay) & (ax >= az);
+    const bool ym = !xm & (ay >= az);
+    const float m = xm ? ax : (ym ? ay : az);
+    const float u = xm ? dy : (ym ? dz : dx);
+    const float v = xm ? dz : (ym ? dx : dy);
+    const float dm = xm ? dx : (ym ? dy : dz);
+    const int face = (xm ? 0 : (ym ? 2 : 4)) + (dm < 0.f ? 1 : 0);
+    // the table is conservative, so an approximate reciprocal is enough
+    const float s = (0.5f * kLutRes) * __builtin_amdgcn_rcpf(m);
     const int iu = min(max((int)fmaf(u, s, 0.5f * kLutRes), 0), kLutRes - 1);
     const int iv = min(max((int)fmaf(v, s, 0.5f * kLutRes), 0), kLutRes - 1);
     const uint32_t e = lut[(face * kLutRes + iv) * kLutRes + iu];
