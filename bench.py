@@ -48,7 +48,10 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving run (req/s)")
     ap.add_argument("--serve-seconds", type=float, default=6.0, help="arrival window of the serving run (s)")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--mode", default="full", choices=["full", "query", "search", "serve"],
+    ap.add_argument("--train-objects", type=int, default=2000, help="proposer: training objects (seeds 0..n-1)")
+    ap.add_argument("--eval-objects", type=int, default=200, help="proposer: held-out objects (seeds 100000..)")
+    ap.add_argument("--epochs", type=int, default=30, help="proposer: training epochs")
+    ap.add_argument("--mode", default="full", choices=["full", "query", "search", "serve", "proposer"],
                     help="query / search: only the field build and --steps launches of that stage "
                          "(query mode adds a 1 GiB device copy); for hardware-counter runs, no JSON")
     return ap.parse_args()
@@ -180,6 +183,134 @@ def serve_bench(torch, lg, rate: float, seconds: float, seed: int = 0, alone_sam
                    "16/22-DOF hands 50/50, D=32, IK + SDF penetration"}
 
 
+PROP_POINTS = 2048      # proposer input: seeded subsample of the object's points
+PROP_POSES = 4096       # pose budget per object, learned and uniform alike
+PROP_TARGETS = 64       # training targets kept per object (valid-grasp poses)
+
+
+def _c2_object(seed: int):
+    """A C2 superquadric (N = 16,384) and its 64^3 SDF; runs in a CPU worker."""
+    import synth
+    o = synth.superquadric_object(seed, 16384)
+    return seed, o, synth.sdf_superquadric(o, workers=1)
+
+
+def _prop_input(torch, obj, seed: int):
+    rng = np.random.default_rng(seed + 77)
+    sel = np.sort(rng.choice(obj.n, size=PROP_POINTS, replace=False))
+    x = np.concatenate([obj.pts[sel], obj.nrm[sel]], axis=1).astype(np.float32)
+    return torch.from_numpy(x).cuda()
+
+
+def _diversity(torch, pipe, ids) -> int:
+    """Distinct sorted point-index k-tuples among the valid grasps."""
+    if ids.numel() == 0:
+        return 0
+    sets = pipe.sbuf.set_pt.view(-1, pipe.sbuf.set_pt.shape[-1])[ids.long()]
+    return int(torch.unique(torch.sort(sets, dim=1).values, dim=0).shape[0])
+
+
+def proposer_bench(torch, lg, pool, n_train: int, n_eval: int, epochs: int, seed: int = 0) -> dict:
+    """C5: train the proposer on the valid grasps of uniform search over
+    n_train C2 objects, then compare learned and uniform proposals on n_eval
+    held-out objects at an equal pose budget under the unchanged checks."""
+    import synth
+    from paper_2511_07418_amd.pipeline import Pipeline
+    hand = synth.hand_c2(seed)
+    fp = synth.FieldParams(samples=262144, seed=seed, grid=64, h=0.003, bins=64,
+                           grid_frame=synth.grid_frames(hand, 64, 0.003))
+    field = lg.lg_build_field(hand, fp, keep_witness=True)
+    ik = synth.IKParams()
+
+    def run(obj, sdf, poses):
+        sp = synth.SearchParams(draws=32, k=hand.n_fingers, mu=0.5, m_edges=8, eps=1e-3, seed=seed,
+                                moment_scale=obj.rho)
+        pipe = Pipeline(field, obj.pts, obj.nrm, poses, sp, ik=ik, sdf=sdf)
+        return pipe
+
+    # ---- training data: valid grasps of uniform search ----------------------------
+    t0 = time.perf_counter()
+    xs, ys = [], []
+    n_valid_train = 0
+    for i, (s_, obj, sdf) in enumerate(pool.imap(_c2_object, range(n_train), chunksize=4)):
+        pipe = run(obj, sdf, synth.palm_poses(PROP_POSES, s_ + 1))
+        pipe.step()
+        ids = pipe.valid_sets()
+        n_valid_train += int(ids.numel())
+        if ids.numel():
+            g = (ids // 32).long()
+            rng = np.random.default_rng(s_ + 5)
+            pick = torch.from_numpy(rng.choice(int(g.numel()), size=min(PROP_TARGETS, int(g.numel())),
+                                               replace=False)).cuda()
+            P = pipe.poses[g[pick]]
+            y = torch.cat([P[:, [0, 4, 8]], P[:, [1, 5, 9]], P[:, [3, 7, 11]] / 0.1], dim=1)
+            xs.append(_prop_input(torch, obj, s_))
+            ys.append(y)
+        if (i + 1) % 100 == 0:
+            print(f"[proposer] data {i + 1}/{n_train} objects, {len(xs)} with valid grasps, "
+                  f"{time.perf_counter() - t0:.0f}s", file=sys.stderr, flush=True)
+    t_data = time.perf_counter() - t0
+    # ---- training -------------------------------------------------------------------
+    Bt = 32
+    prop = lg.Proposer(max_batch=Bt, max_points=PROP_POINTS, max_targets=Bt * PROP_TARGETS, seed=seed)
+    X = torch.stack(xs)
+    rng = np.random.default_rng(seed + 99)
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        order = rng.permutation(len(xs))
+        ep_loss = []
+        for j in range(0, len(order) - Bt + 1, Bt):
+            idx = order[j:j + Bt]
+            tg = torch.cat([ys[k] for k in idx]).contiguous()
+            off = torch.from_numpy(np.concatenate([[0], np.cumsum([len(ys[k]) for k in idx])]).astype(np.int32)).cuda()
+            ep_loss.append(prop.train_step(X[torch.from_numpy(idx).cuda()].contiguous(), tg, off, 1e-3))
+        losses.append(float(torch.stack(ep_loss).mean().cpu()))
+        print(f"[proposer] epoch {ep + 1}/{epochs} loss {losses[-1]:.3f}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    # ---- evaluation on held-out objects ---------------------------------------------------
+    res = {"uniform": {"valid": 0, "diversity": 0, "s": 0.0, "per_obj": []},
+           "learned": {"valid": 0, "diversity": 0, "s": 0.0, "per_obj": []}}
+    ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for i, (s_, obj, sdf) in enumerate(pool.imap(_c2_object, range(100000, 100000 + n_eval), chunksize=2)):
+        x = _prop_input(torch, obj, s_)
+        for kind in ("uniform", "learned"):
+            if kind == "uniform":
+                poses = torch.from_numpy(synth.palm_poses(PROP_POSES, s_ + 1)).cuda()
+            else:
+                poses = torch.empty((PROP_POSES, 12), dtype=torch.float32, device="cuda")
+            pipe = run(obj, sdf, poses)
+            torch.cuda.synchronize()
+            ev[0].record()
+            if kind == "learned":
+                prop.sample(x, PROP_POSES, seed=s_, uniform_frac=0.1, out=pipe.poses)
+            pipe.step()
+            ev[1].record()
+            torch.cuda.synchronize()
+            ids = pipe.valid_sets()
+            r = res[kind]
+            r["valid"] += int(ids.numel())
+            r["diversity"] += _diversity(torch, pipe, ids)
+            r["s"] += ev[0].elapsed_time(ev[1]) * 1e-3
+            r["per_obj"].append(int(ids.numel()))
+    out = {"train_objects": n_train, "train_objects_with_valid": len(xs), "train_valid_grasps": n_valid_train,
+           "targets": int(sum(len(y) for y in ys)), "epochs": epochs, "loss_first_epoch": losses[0],
+           "loss_last_epoch": losses[-1], "data_s": t_data, "train_s": t_train, "eval_objects": n_eval,
+           "pose_budget": PROP_POSES, "uniform_frac": 0.1}
+    for kind, r in res.items():
+        out[kind] = {"valid_grasps": r["valid"], "valid_per_object": r["valid"] / n_eval,
+                     "valid_grasps_per_s": r["valid"] / r["s"], "distinct_contact_sets": r["diversity"],
+                     "seconds": r["s"]}
+    pu, pl = np.array(res["uniform"]["per_obj"]), np.array(res["learned"]["per_obj"])
+    out["objects_learned_ge_uniform"] = int((pl >= pu).sum())
+    out["valid_per_s_ratio"] = out["learned"]["valid_grasps_per_s"] / max(out["uniform"]["valid_grasps_per_s"], 1e-9)
+    prop.release()
+    field.release()
+    return out
+
+
 def cpu_baseline(w, n_poses: int, samples: int) -> dict:
     """The FP64 oracle, as it stands, on the first ``n_poses`` poses: query,
     draws, verdicts, compaction and (with an SDF) IK + penetration.  Its field
@@ -220,6 +351,11 @@ def main():
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    pool = None
+    if args.mode == "proposer":
+        # CPU workers for the object and SDF generators, forked before the GPU is touched
+        import multiprocessing as mp
+        pool = mp.get_context("fork").Pool(min(16, os.cpu_count() or 1))
     import torch
 
     import synth
@@ -227,6 +363,11 @@ def main():
     from paper_2511_07418_amd.pipeline import Pipeline
 
     torch.cuda.set_device(0)
+    if args.mode == "proposer":
+        out = proposer_bench(torch, lg, pool, args.train_objects, args.eval_objects, args.epochs, args.seed)
+        pool.close()
+        print(json.dumps({"proposer": out}))
+        return
     if args.mode == "serve":
         print(json.dumps({"serving": serve_bench(torch, lg, args.serve_rate, args.serve_seconds, args.seed)}))
         return

@@ -310,6 +310,86 @@ double lg_serve_clock(lg_server *srv);
 /* Finish in-flight chunks, cancel the rest, free everything. */
 lg_status lg_serve_destroy(lg_server *srv);
 
+/* ---- learned palm-pose proposer ------------------------------------------------
+ * Data-driven search (Sec. 5.7) names learning where to search as a way to skip
+ * unproductive regions of the pose space; the paper leaves it unimplemented.
+ * This is the project's proposer: a PointNet-style encoder (shared MLP 6 -> 128
+ * -> 256 with ReLU, max-pool over the points) and a head 256 -> 256 -> 256
+ * (ReLU) -> 152 = 8 x (logit, 9 means, 9 log-sigmas) of a diagonal Gaussian
+ * mixture over y = (R[:,0], R[:,1], t / 0.1 m) of a palm pose [R | t]; the
+ * rotation is recovered by Gram-Schmidt.  Matrix products run on BF16 MFMA
+ * with FP32 accumulation; training keeps FP32 master weights and Adam state.
+ * Proposed poses go through lg_query_domains / lg_search / lg_realize
+ * unchanged; uniform poses remain the fallback (uniform_frac below).
+ *
+ * Inputs x are DEVICE [B][Np][6] float32 rows (p in m, unit outward normal n),
+ * typically a seeded subsample of the object's points; the network scales p
+ * by 1 / 0.1 m.  The library owns each lg_prop: its weights, Adam state and the
+ * activations of one batch of at most max_batch objects x max_points points
+ * and max_targets targets.  Calls on one lg_prop must not overlap: they share
+ * its activation buffers.
+ */
+typedef struct lg_prop lg_prop;
+
+typedef struct {
+    int32_t max_batch;    /* objects per forward / training call, [1, 4096] */
+    int32_t max_points;   /* points per object, [1, 2^24] */
+    int32_t max_targets;  /* target poses per training call, [1, 2^26] */
+    uint64_t seed;        /* Philox key of the He-uniform initialisation */
+} lg_prop_params;
+
+/* Number of FP32 parameters (204,568); the flat layout is, per layer
+ * W1 [6][128], b1, W2 [128][256], b2, Wa [256][256], ba, Wb [256][256], bb,
+ * Wc [256][152], bc, each weight row-major [in][out]. */
+int64_t lg_prop_num_params(void);
+
+/* Allocates and initialises a proposer on the current device (synchronises
+ * `stream`).  LG_EINVAL on limits outside the ranges above, LG_ENOMEM. */
+lg_status lg_prop_create(const lg_prop_params *params, void *stream, lg_prop **out);
+lg_status lg_prop_release(lg_prop *p);
+
+/* Host copies of the FP32 master weights [lg_prop_num_params()] (checkpoints).
+ * set also refreshes the BF16 copies and resets the Adam state; both calls
+ * synchronise the device. */
+lg_status lg_prop_get_params(const lg_prop *p, float *host_out);
+lg_status lg_prop_set_params(lg_prop *p, const float *host_in);
+
+/* Forward pass of B objects with Np points each.  Optional outputs (NULL =
+ * skip): out [B][152] mixture parameters, feat [B][256] pooled features,
+ * arg [B][256] the point index of each channel's maximum (lowest index among
+ * equal maxima).  LG_EINVAL if B or Np is outside the proposer's limits. */
+lg_status lg_prop_forward(lg_prop *p, const float *x, int32_t B, int32_t Np, float *out, float *feat,
+                          int32_t *arg, void *stream);
+
+/* Mean mixture negative log-likelihood over T targets and its gradient.
+ * targets [T][9] are y vectors; object b owns targets offsets[b] ..
+ * offsets[b+1]-1 (offsets [B+1], offsets[0] = 0, offsets[B] = T, both DEVICE).
+ * Writes loss [1] and grad [lg_prop_num_params()] when non-NULL; the gradient
+ * also stays in the proposer for lg_prop_adam. */
+lg_status lg_prop_backward(lg_prop *p, const float *x, int32_t B, int32_t Np, const float *targets,
+                           const int32_t *offsets, int32_t T, float *loss, float *grad, void *stream);
+
+/* One Adam step (Kingma & Ba 2015, bias-corrected step size) with the last
+ * gradient; refreshes the BF16 weight copies. */
+lg_status lg_prop_adam(lg_prop *p, float lr, float beta1, float beta2, float eps, void *stream);
+
+/* lg_prop_backward followed by lg_prop_adam(lr, 0.9, 0.999, 1e-8). */
+lg_status lg_prop_train_step(lg_prop *p, const float *x, int32_t B, int32_t Np, const float *targets,
+                             const int32_t *offsets, int32_t T, float lr, float *loss, void *stream);
+
+/* n_poses palm poses [n_poses][12] from one mixture row mix [152].  Pose i
+ * uses Philox4x32-10 blocks (i, j, 7, 0), j = 0..2, key (seed lo, seed hi):
+ * with probability uniform_frac a uniform pose (Shoemake rotation, object
+ * origin at distance U[d_lo, d_hi] along a direction uniform on the +z
+ * hemisphere), else a draw of the mixture (component by inversion of the
+ * cumulative softmax, Box-Muller normals, log-sigma clamped to [-5, 2]). */
+lg_status lg_prop_sample_mixture(const float *mix, int32_t n_poses, uint64_t seed, float uniform_frac, float d_lo,
+                                 float d_hi, float *poses, void *stream);
+
+/* Forward pass of one object (x [Np][6]) and n_poses samples of its mixture. */
+lg_status lg_prop_sample(lg_prop *p, const float *x, int32_t Np, int32_t n_poses, uint64_t seed, float uniform_frac,
+                         float d_lo, float d_hi, float *poses, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

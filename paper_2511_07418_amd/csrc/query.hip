@@ -42,71 +42,42 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
     uint32_t c[FM];
 #pragma unroll
     for (int f = 0; f < FM; ++f) c[f] = 0;
-    // Each wave handles UNR chunks of 64 points per iteration, and the points
-    // of its next iteration are loaded before the current ones are used
-    // (software pipelining), so point loads, the LDS table read and the
-    // table gathers of different chunks overlap.
-    constexpr int UNR = 2;
-    constexpr int STEP = UNR * kQueryWaves;
-    float np[UNR][6];
-    auto load_pts = [&](int chunk0, float (*dst)[6]) {
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const int i = (chunk0 + u * kQueryWaves) * 64 + lane;
-            const bool ok = i < N;
-            dst[u][0] = ok ? pts[i] : 0.f;
-            dst[u][1] = ok ? pts[N + i] : 0.f;
-            dst[u][2] = ok ? pts[2 * N + i] : 0.f;
-            dst[u][3] = ok ? nrm[i] : 0.f;
-            dst[u][4] = ok ? nrm[N + i] : 0.f;
-            dst[u][5] = ok ? nrm[2 * N + i] : 1.f;
+    for (int chunk = wave; chunk < nchunks; chunk += kQueryWaves) {
+        const int i = chunk * 64 + lane;
+        const bool valid = i < N;
+        float px = 0.f, py = 0.f, pz = 0.f, nx = 0.f, ny = 0.f, nz = 1.f;
+        if (valid) {
+            px = pts[i];
+            py = pts[N + i];
+            pz = pts[2 * N + i];
+            nx = nrm[i];
+            ny = nrm[N + i];
+            nz = nrm[2 * N + i];
         }
-    };
-    load_pts(wave, np);
-    for (int chunk0 = wave; chunk0 < nchunks; chunk0 += STEP) {
-        float cp[UNR][6];
+        float qx, qy, qz;
+        query_dir(P, nx, ny, nz, qx, qy, qz);
+        const int b = nearest_bin_lut(lut, cb, B, qx, qy, qz);
+        // one 32-bit word per finger: the word of the table that holds bit b;
+        // all finger gathers are issued before any is consumed
+        uint32_t word[FM];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u)
-#pragma unroll
-            for (int q = 0; q < 6; ++q) cp[u][q] = np[u][q];
-        if (chunk0 + STEP < nchunks) load_pts(chunk0 + STEP, np);
-        int b[UNR];
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            float qx, qy, qz;
-            query_dir(P, cp[u][3], cp[u][4], cp[u][5], qx, qy, qz);
-            b[u] = nearest_bin_lut(lut, cb, B, qx, qy, qz);
-        }
-        // one 32-bit word per (chunk, finger): the word holding bit b; all
-        // gathers are issued before any is consumed
-        uint32_t word[UNR][FM];
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const bool valid = (chunk0 + u * kQueryWaves) * 64 + lane < N;
-#pragma unroll
-            for (int f = 0; f < FM; ++f) {
-                word[u][f] = 0;
-                if (f < F) {
-                    const int v = window_voxel(aff[f], G, cp[u][0], cp[u][1], cp[u][2]);
-                    const uint32_t *tab = merged + f * G3W;  // uniform base, 32-bit lane offsets
-                    if (valid && v >= 0) word[u][f] = tab[(uint32_t)v * W + (uint32_t)(b[u] >> 5)];
-                }
+        for (int f = 0; f < FM; ++f) {
+            word[f] = 0;
+            if (f < F) {
+                const int v = window_voxel(aff[f], G, px, py, pz);
+                const uint32_t *tab = merged + f * G3W;  // uniform base, 32-bit lane offsets
+                if (valid && v >= 0) word[f] = tab[(uint32_t)v * W + (uint32_t)(b >> 5)];
             }
         }
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const int chunk = chunk0 + u * kQueryWaves;
-            if (chunk >= nchunks) break;
-#pragma unroll
-            for (int f = 0; f < FM; ++f) {
-                if (f >= F) break;
-                const bool hit = (word[u][f] >> (b[u] & 31)) & 1u;
-                const unsigned long long m = __ballot(hit);
-                c[f] += (uint32_t)__popcll(m);
-                const int wi = 2 * chunk + lane;
-                if (lane < 2 && wi < NW)
-                    dom_bits[((int64_t)g * F + f) * NW + wi] = lane == 0 ? (uint32_t)m : (uint32_t)(m >> 32);
-            }
+        for (int f = 0; f < FM; ++f) {
+            if (f >= F) break;
+            const bool hit = (word[f] >> (b & 31)) & 1u;
+            const unsigned long long m = __ballot(hit);
+            c[f] += (uint32_t)__popcll(m);
+            const int wi = 2 * chunk + lane;
+            if (lane < 2 && wi < NW)
+                dom_bits[((int64_t)g * F + f) * NW + wi] = lane == 0 ? (uint32_t)m : (uint32_t)(m >> 32);
         }
     }
     if (lane == 0) {

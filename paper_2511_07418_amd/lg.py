@@ -127,10 +127,23 @@ def _load():
     L.lg_serve_clock.argtypes = [vp]
     L.lg_serve_clock.restype = C.c_double
     L.lg_serve_destroy.argtypes = [vp]
+    L.lg_prop_num_params.restype = i64
+    L.lg_prop_create.argtypes = [vp, vp, vp]
+    L.lg_prop_release.argtypes = [vp]
+    L.lg_prop_get_params.argtypes = [vp, vp]
+    L.lg_prop_set_params.argtypes = [vp, vp]
+    L.lg_prop_forward.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp]
+    L.lg_prop_backward.argtypes = [vp, vp, i32, i32, vp, vp, i32, vp, vp, vp]
+    L.lg_prop_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+    L.lg_prop_train_step.argtypes = [vp, vp, i32, i32, vp, vp, i32, C.c_float, vp, vp]
+    L.lg_prop_sample_mixture.argtypes = [vp, i32, C.c_uint64, C.c_float, C.c_float, C.c_float, vp, vp]
+    L.lg_prop_sample.argtypes = [vp, vp, i32, i32, C.c_uint64, C.c_float, C.c_float, C.c_float, vp, vp]
     for fn in ("lg_build_field", "lg_field_import", "lg_field_export", "lg_field_info",
                "lg_field_release", "lg_query_domains", "lg_search", "lg_realize", "lg_serve_create",
                "lg_serve_submit", "lg_serve_poll", "lg_serve_wait", "lg_serve_cancel", "lg_serve_stats",
-               "lg_serve_destroy"):
+               "lg_serve_destroy", "lg_prop_create", "lg_prop_release", "lg_prop_get_params",
+               "lg_prop_set_params", "lg_prop_forward", "lg_prop_backward", "lg_prop_adam",
+               "lg_prop_train_step", "lg_prop_sample_mixture", "lg_prop_sample"):
         getattr(L, fn).restype = i32
     return L
 
@@ -141,7 +154,10 @@ EXPORTED = ("lg_status_str", "lg_last_error", "lg_version", "lg_build_field", "l
             "lg_field_export", "lg_field_info", "lg_field_release", "lg_query_domains",
             "lg_search_workspace_bytes", "lg_search", "lg_realize", "lg_serve_request_bytes",
             "lg_serve_create", "lg_serve_submit", "lg_serve_poll", "lg_serve_wait", "lg_serve_cancel",
-            "lg_serve_stats", "lg_serve_clock", "lg_serve_destroy")
+            "lg_serve_stats", "lg_serve_clock", "lg_serve_destroy", "lg_prop_num_params",
+            "lg_prop_create", "lg_prop_release", "lg_prop_get_params", "lg_prop_set_params",
+            "lg_prop_forward", "lg_prop_backward", "lg_prop_adam", "lg_prop_train_step",
+            "lg_prop_sample_mixture", "lg_prop_sample")
 
 
 def lib():
@@ -434,3 +450,103 @@ def accepted_hash(request_id: int, acc_ids) -> int:
     for i in acc_ids:
         h = (h + mix64(((int(request_id) << 40) ^ int(i)) & ((1 << 64) - 1))) & ((1 << 64) - 1)
     return h
+
+
+# ---- learned palm-pose proposer ---------------------------------------------
+PROP_OUT = 152
+PROP_FEAT = 256
+
+
+class PropParams(C.Structure):
+    _fields_ = [("max_batch", C.c_int32), ("max_points", C.c_int32), ("max_targets", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+def lg_prop_num_params() -> int:
+    return int(_lib.lg_prop_num_params())
+
+
+class Proposer:
+    """A proposer owned by the library (see ``lg_prop_*``).  Inputs ``x`` are
+    device float32 tensors [B][Np][6] of (p in m, unit normal)."""
+
+    def __init__(self, max_batch: int = 64, max_points: int = 2048, max_targets: int = 1 << 16,
+                 seed: int = 0, stream=None):
+        self.params = PropParams(int(max_batch), int(max_points), int(max_targets), int(seed))
+        h = C.c_void_p()
+        _check(_lib.lg_prop_create(C.byref(self.params), _stream(stream), C.byref(h)), "lg_prop_create")
+        self.handle = h
+        self.n_params = lg_prop_num_params()
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, np.float32)
+        _check(_lib.lg_prop_get_params(self.handle, _hp(out)), "lg_prop_get_params")
+        return out
+
+    def set_params(self, flat) -> None:
+        a = np.ascontiguousarray(flat, np.float32)
+        if a.size != self.n_params:
+            raise ValueError("parameter vector has the wrong length")
+        _check(_lib.lg_prop_set_params(self.handle, _hp(a)), "lg_prop_set_params")
+
+    def forward(self, x: torch.Tensor, stream=None) -> dict:
+        B, Np = int(x.shape[0]), int(x.shape[1])
+        dev = x.device
+        out = torch.empty((B, PROP_OUT), dtype=torch.float32, device=dev)
+        feat = torch.empty((B, PROP_FEAT), dtype=torch.float32, device=dev)
+        arg = torch.empty((B, PROP_FEAT), dtype=torch.int32, device=dev)
+        _check(_lib.lg_prop_forward(self.handle, _ptr(x), B, Np, _ptr(out), _ptr(feat), _ptr(arg),
+                                    _stream(stream)), "lg_prop_forward")
+        return {"out": out, "feat": feat, "arg": arg}
+
+    def backward(self, x: torch.Tensor, targets: torch.Tensor, offsets: torch.Tensor, stream=None):
+        B, Np = int(x.shape[0]), int(x.shape[1])
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        _check(_lib.lg_prop_backward(self.handle, _ptr(x), B, Np, _ptr(targets), _ptr(offsets),
+                                     int(targets.shape[0]), _ptr(loss), _ptr(grad), _stream(stream)),
+               "lg_prop_backward")
+        return loss, grad
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None):
+        _check(_lib.lg_prop_adam(self.handle, float(lr), float(beta1), float(beta2), float(eps),
+                                 _stream(stream)), "lg_prop_adam")
+
+    def train_step(self, x: torch.Tensor, targets: torch.Tensor, offsets: torch.Tensor, lr: float,
+                   loss: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        B, Np = int(x.shape[0]), int(x.shape[1])
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        _check(_lib.lg_prop_train_step(self.handle, _ptr(x), B, Np, _ptr(targets), _ptr(offsets),
+                                       int(targets.shape[0]), float(lr), _ptr(loss), _stream(stream)),
+               "lg_prop_train_step")
+        return loss
+
+    def sample(self, x: torch.Tensor, n_poses: int, seed: int, uniform_frac: float,
+               d_lo: float = 0.08, d_hi: float = 0.12, out: Optional[torch.Tensor] = None,
+               stream=None) -> torch.Tensor:
+        Np = int(x.shape[-2])
+        if out is None:
+            out = torch.empty((n_poses, 12), dtype=torch.float32, device=x.device)
+        _check(_lib.lg_prop_sample(self.handle, _ptr(x), Np, int(n_poses), int(seed), float(uniform_frac),
+                                   float(d_lo), float(d_hi), _ptr(out), _stream(stream)), "lg_prop_sample")
+        return out
+
+    def release(self):
+        if self.handle:
+            _lib.lg_prop_release(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def lg_prop_sample_mixture(mix: torch.Tensor, n_poses: int, seed: int, uniform_frac: float,
+                           d_lo: float = 0.08, d_hi: float = 0.12, stream=None) -> torch.Tensor:
+    out = torch.empty((n_poses, 12), dtype=torch.float32, device=mix.device)
+    _check(_lib.lg_prop_sample_mixture(_ptr(mix), int(n_poses), int(seed), float(uniform_frac), float(d_lo),
+                                       float(d_hi), _ptr(out), _stream(stream)), "lg_prop_sample_mixture")
+    return out

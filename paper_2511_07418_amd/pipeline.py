@@ -24,7 +24,10 @@ class Pipeline:
         self.dev = torch.device(device)
         self.pts = torch.from_numpy(np.ascontiguousarray(np.asarray(pts, np.float32).T)).to(self.dev)
         self.nrm = torch.from_numpy(np.ascontiguousarray(np.asarray(nrm, np.float32).T)).to(self.dev)
-        self.poses = torch.from_numpy(np.ascontiguousarray(poses, np.float32)).to(self.dev)
+        if isinstance(poses, torch.Tensor):       # already on the device (e.g. proposer output)
+            self.poses = poses.to(self.dev, torch.float32).contiguous()
+        else:
+            self.poses = torch.from_numpy(np.ascontiguousarray(poses, np.float32)).to(self.dev)
         self.N, self.P = int(self.pts.shape[1]), int(self.poses.shape[0])
         self.sp = sp
         F = field.n_fingers
@@ -65,6 +68,14 @@ class Pipeline:
 
     def n_acc(self) -> int:
         return int(self.sbuf.n_acc.item())
+
+    def valid_sets(self) -> torch.Tensor:
+        """Global set ids (g * D + d) of the valid grasps of the last step."""
+        n = self.n_acc()
+        ids = self.sbuf.acc_list[:n]
+        if self.ik is None:
+            return ids
+        return ids[self.rbuf.valid[:n] != 0]
 
     def valid_count(self) -> int:
         """Valid grasps of the last step: accepted sets that pass IK and
