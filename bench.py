@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--train-objects", type=int, default=2000, help="proposer: training objects (seeds 0..n-1)")
     ap.add_argument("--eval-objects", type=int, default=200, help="proposer: held-out objects (seeds 100000..)")
-    ap.add_argument("--epochs", type=int, default=30, help="proposer: training epochs")
+    ap.add_argument("--epochs", type=int, default=60, help="proposer: training epochs")
     ap.add_argument("--mode", default="full", choices=["full", "query", "search", "serve", "proposer"],
                     help="query / search: only the field build and --steps launches of that stage "
                          "(query mode adds a 1 GiB device copy); for hardware-counter runs, no JSON")
@@ -305,6 +305,23 @@ def proposer_bench(torch, lg, pool, n_train: int, n_eval: int, epochs: int, seed
                      "seconds": r["s"]}
     pu, pl = np.array(res["uniform"]["per_obj"]), np.array(res["learned"]["per_obj"])
     out["objects_learned_ge_uniform"] = int((pl >= pu).sum())
+    # encoder throughput: one forward of 512 objects x 2048 points (dense MFMA work)
+    big = lg.Proposer(max_batch=512, max_points=PROP_POINTS, max_targets=1, seed=seed)
+    xb = X[torch.arange(512, device="cuda") % X.shape[0]].contiguous()
+    for _ in range(3):
+        big.forward(xb)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(10):
+        big.forward(xb)
+    ev[1].record()
+    torch.cuda.synchronize()
+    f_ms = ev[0].elapsed_time(ev[1]) / 10
+    flops = 2.0 * 512 * PROP_POINTS * (6 * 128 + 128 * 256)
+    out["encoder_forward"] = {"objects": 512, "points": PROP_POINTS, "ms": f_ms,
+                              "tflops": flops / (f_ms * 1e-3) / 1e12, "peak_tflops": 2500.0,
+                              "frac": flops / (f_ms * 1e-3) / 1e12 / 2500.0}
+    big.release()
     out["valid_per_s_ratio"] = out["learned"]["valid_grasps_per_s"] / max(out["uniform"]["valid_grasps_per_s"], 1e-9)
     prop.release()
     field.release()

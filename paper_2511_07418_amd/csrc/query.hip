@@ -43,6 +43,9 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
 #pragma unroll
     for (int f = 0; f < FM; ++f) c[f] = 0;
     for (int chunk = wave; chunk < nchunks; chunk += kQueryWaves) {
+        // re-read the per-finger maps from LDS every chunk instead of pinning
+        // 12 x F registers for them: halves the register footprint
+        asm volatile("" ::: "memory");
         const int i = chunk * 64 + lane;
         const bool valid = i < N;
         float px = 0.f, py = 0.f, pz = 0.f, nx = 0.f, ny = 0.f, nz = 1.f;

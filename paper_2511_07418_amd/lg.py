@@ -18,7 +18,8 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblg.so")
+# LG_LIBRARY names another build of the same library (e.g. a kernel variant under test)
+LIB_PATH = os.environ.get("LG_LIBRARY") or os.path.join(_HERE, "liblg.so")
 
 LG_OK, LG_EINVAL, LG_ENOMEM, LG_EDEVICE, LG_EBUDGET, LG_EUNSUPPORTED, LG_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 LG_REQ_QUEUED, LG_REQ_RUNNING, LG_REQ_DONE, LG_REQ_CANCELLED, LG_REQ_FAILED = 0, 1, 2, 3, 4
