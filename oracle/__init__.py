@@ -17,6 +17,9 @@ Each function cites the passage of the paper it follows (arXiv 2511.07418):
                        per-dependency-group domains of Sec. 5.3
 * ``draw``             Sec. 5.3 random selection + reverse lookup of Sec. 5.5
 * ``verdicts``/``set_tstar``  Eq. 1-2 with a linearised friction cone (LP)
+* ``optimize``         Sec. 5.4 Alg. 2 (blockwise zeroth-order contact-point
+                       optimisation), with ``project_domain`` and ``opt_noise``
+* ``relink``           the reverse lookup of Sec. 5.5 for optimised sets
 * ``compact``          accepted sets in pose-major, draw-minor order
 * ``realize``          Sec. 5.5 Eq. 7-8 (DLS IK with Phase-II projection) and
                        the penetration criterion of Sec. 3.2
@@ -102,6 +105,14 @@ def lib():
         L.orc_set_tstar.restype = dbl
         L.orc_verdicts.argtypes = [vp, vp, i32, i32, vp, dbl, i32, dbl, dbl, i32, vp, vp, vp, vp]
         L.orc_verdicts.restype = C.c_int
+        L.orc_opt_noise.argtypes = [u64, C.c_uint32, i64, C.c_int, C.c_uint32, dbl, vp]
+        L.orc_project_domain.argtypes = [vp, i32, vp, vp, vp]
+        L.orc_project_domain.restype = i64
+        L.orc_optimize.argtypes = [vp, vp, i32, vp, i32, i32, i32, i32, vp, dbl, i32, dbl, i32, i32, dbl,
+                                   u64, C.c_uint32, i64, i32, vp, vp]
+        L.orc_optimize.restype = C.c_int
+        L.orc_relink.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, i32, vp, u64, C.c_uint32, i64, vp]
+        L.orc_relink.restype = C.c_int
         L.orc_ik_finger.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_point_jacobian.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp]
         L.orc_sdf_eval.argtypes = [vp, vp]
@@ -314,6 +325,58 @@ def verdicts(pts, nrm, set_pt, sp, max_pivots: int = 1000) -> dict:
     if rc != 0:
         raise ValueError(f"orc_verdicts failed ({rc})")
     return {"verdict": v, "tstar": t, "vflag": vf, "status": st}
+
+
+def opt_noise(seed: int, request_id: int, g: int, d: int, step: int, sigma: float) -> np.ndarray:
+    """Tangent-plane offsets (dx, dy) of one candidate of Sec. 5.4 Alg. 2."""
+    out = np.zeros(2, np.float64)
+    lib().orc_opt_noise(int(seed) & 0xFFFFFFFFFFFFFFFF, int(request_id), int(g), int(d), int(step),
+                        float(sigma), _p(out))
+    return out
+
+
+def project_domain(pts, dom_words, y) -> tuple[int, bool]:
+    """Nearest point of a contact domain (bitset over points) to y; (index, near-tie flag)."""
+    pts = _c(pts, np.float32)
+    yy = _c(y, np.float64)
+    fl = C.c_int(0)
+    i = lib().orc_project_domain(_p(pts), pts.shape[0], _p(_c(dom_words, np.uint32)), _p(yy), C.byref(fl))
+    return int(i), bool(fl.value)
+
+
+def optimize(pts, nrm, dom_bits, set_pt, sp, F: int, max_pivots: int = 1000) -> dict:
+    """Sec. 5.4 Alg. 2 on drawn sets: optimised set_pt [P, D, k], t* of the final
+    sets (NaN for invalid draws) and the band flag of each set."""
+    pts, nrm = _c(pts, np.float32), _c(nrm, np.float32)
+    spt = _c(set_pt, np.int32).copy()
+    P, D, k = spt.shape
+    t = np.zeros(P * D, np.float64)
+    fl = np.zeros(P * D, np.uint8)
+    rc = lib().orc_optimize(_p(pts), _p(nrm), pts.shape[0], _p(_c(dom_bits, np.uint32)), P, int(F), D, k,
+                            _p(spt), float(np.float32(sp.mu)), sp.m_edges, float(np.float32(sp.moment_scale)),
+                            int(sp.opt_outer), int(sp.opt_inner), float(np.float32(sp.opt_sigma)),
+                            int(sp.seed) & 0xFFFFFFFFFFFFFFFF, int(sp.request_id), int(sp.pose_offset),
+                            int(max_pivots), _p(t), _p(fl))
+    if rc != 0:
+        raise ValueError(f"orc_optimize failed ({rc})")
+    eps = float(np.float32(sp.eps))
+    return {"set_pt": spt, "tstar": t, "oflag": fl, "verdict": (t <= eps).astype(np.uint8),
+            "vflag": (np.abs(t - eps) <= BAND).astype(np.uint8)}
+
+
+def relink(hand, fp, bits, pts, nrm, poses, set_pt, sp) -> np.ndarray:
+    """Links of (optimised) sets, picked with each set's draw words."""
+    pts, nrm, poses = _c(pts, np.float32), _c(nrm, np.float32), _c(poses, np.float32)
+    spt = _c(set_pt, np.int32)
+    P, D, k = spt.shape
+    sln = np.zeros((P, D, k), np.int32)
+    H, Fp = _hand(hand), _field(fp)
+    rc = lib().orc_relink(H.ref, Fp.ref, _p(_c(bits, np.uint32)), _p(pts), _p(nrm), _p(poses), P, D, k,
+                          _p(spt), int(sp.seed) & 0xFFFFFFFFFFFFFFFF, int(sp.request_id), int(sp.pose_offset),
+                          _p(sln))
+    if rc != 0:
+        raise ValueError(f"orc_relink failed ({rc})")
+    return sln
 
 
 def compact(verdict) -> np.ndarray:

@@ -35,6 +35,9 @@
 
 #define PURPOSE_JOINT 1u
 #define PURPOSE_DRAW 3u
+#define PURPOSE_OPT 5u
+#define OPT_TAU 1e-9    /* candidates within OPT_TAU of the best criterion value tie */
+#define OPT_BAND 1e-7   /* m: projection near-tie band (FP32 candidate positions err by ~1e-8 m) */
 
 /* ------------------------------------------------------------------------ */
 /* Hand description (host arrays, float32 as in the library ABI)             */
@@ -551,6 +554,33 @@ static void draw_words(uint64_t seed, uint32_t request_id, int64_t g, int d, int
     }
 }
 
+/* Reverse lookup of the link (Sec. 5.5): among the links of finger f whose
+ * table bit is set at point idx under the pose, the floor(r * count / 2^32)-th;
+ * -1 if none. */
+static int pick_link(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits, const double *cb,
+                     const float *pts, const float *nrm, const float *pose, int f, int64_t idx, uint32_t r)
+{
+    double x[3], u[3], gap;
+    int vox[3], b, b2;
+    int in = query_lookup(fp, cb, pose, pts + 3 * idx, nrm + 3 * idx, f, x, u, vox, &b, &b2, &gap);
+    uint32_t mask = 0;
+    link_hits_at(H, fp, bits, f, vox, in, b, &mask);
+    uint32_t pc = popcount32(mask);
+    if (pc == 0) return -1;
+    uint32_t jj = (uint32_t)(((uint64_t)r * pc) >> 32);
+    uint32_t seen = 0;
+    int t = 0;
+    for (int l = 0; l < H->n_joints; ++l) {
+        if (H->joint_finger[l] != f) continue;
+        if ((mask >> t) & 1u) {
+            if (seen == jj) return l;
+            ++seen;
+        }
+        ++t;
+    }
+    return -1;
+}
+
 int orc_draw(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits,
              const float *pts, const float *nrm, int32_t n_points,
              const float *poses, int32_t n_poses,
@@ -579,29 +609,8 @@ int orc_draw(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits
                 uint32_t cnt = dom_count[(int64_t)g * F + i];
                 uint32_t j = (uint32_t)(((uint64_t)w[i] * cnt) >> 32);
                 int64_t idx = select1(dom_bits + ((int64_t)g * F + i) * NW, NW, j);
-                double x[3], u[3], gap;
-                int vox[3], b, b2;
-                int in = query_lookup(fp, cb, poses + 12 * (int64_t)g, pts + 3 * idx, nrm + 3 * idx,
-                                      i, x, u, vox, &b, &b2, &gap);
-                uint32_t mask = 0;
-                link_hits_at(H, fp, bits, i, vox, in, b, &mask);
-                uint32_t pc = popcount32(mask);
-                int link = -1;
-                if (pc > 0) {
-                    uint32_t jj = (uint32_t)(((uint64_t)w[k + i] * pc) >> 32);
-                    uint32_t seen = 0;
-                    int t = 0;
-                    for (int l = 0; l < H->n_joints; ++l) {
-                        if (H->joint_finger[l] != i) continue;
-                        if ((mask >> t) & 1u) {
-                            if (seen == jj) { link = l; break; }
-                            ++seen;
-                        }
-                        ++t;
-                    }
-                }
                 sp[i] = (int32_t)idx;
-                sl[i] = link;
+                sl[i] = pick_link(H, fp, bits, cb, pts, nrm, poses + 12 * (int64_t)g, i, idx, w[k + i]);
             }
         }
     }
@@ -862,6 +871,173 @@ int orc_verdicts(const float *pts, const float *nrm, int32_t n_sets, int32_t k,
         if (tstar) tstar[s] = t;
         if (vflag) vflag[s] = fabs(t - eps) <= BAND_VAL;
         if (status) status[s] = st;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Blockwise zeroth-order contact-point optimisation (Sec. 5.4, Alg. 2).       */
+/* A drawn set (Alg. 2's random start) is refined in n_outer rounds; in each   */
+/* round every contact i in turn gets n_inner candidates: its point moved in   */
+/* the tangent plane of its object normal (Duff basis x_i, y_i) by            */
+/* (dx, dy) ~ N(0, sigma^2) each, then projected onto its contact domain D_i  */
+/* (the nearest domain point, lowest index on ties).  Each candidate set      */
+/* (contact i replaced, the others fixed) is scored by the criterion J = t*   */
+/* (the LP above) and contact i moves to the best candidate: the first whose  */
+/* J is within OPT_TAU of the minimum over the candidates.                     */
+/* Noise of candidate j of step s = (round * k + i) * n_inner + j: Philox     */
+/* block (g, d, PURPOSE_OPT | s << 8, request_id), key = seed; Box-Muller of  */
+/* u1 = ((w0 >> 8) + 1) / 2^24 and u2 = (w1 >> 8) / 2^24.                     */
+/* oflag marks sets with a decision inside a band: a runner-up domain point   */
+/* within OPT_BAND of the nearest, or a candidate J within 1e-10 of the tie  */
+/* threshold.  tstar receives J of the final set (its verdict: J <= eps).     */
+/* ------------------------------------------------------------------------ */
+static void opt_noise(uint64_t seed, uint32_t request_id, int64_t g, int d, uint32_t step, double sigma,
+                      double *dx, double *dy)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {(uint32_t)g, (uint32_t)d, PURPOSE_OPT | (step << 8), request_id};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    double u1 = ((double)(w[0] >> 8) + 1.0) * (1.0 / 16777216.0);
+    double u2 = (double)(w[1] >> 8) * (1.0 / 16777216.0);
+    double r = sqrt(-2.0 * log(u1));
+    *dx = sigma * r * cos(2.0 * M_PI * u2);
+    *dy = sigma * r * sin(2.0 * M_PI * u2);
+}
+
+void orc_opt_noise(uint64_t seed, uint32_t request_id, int64_t g, int d, uint32_t step, double sigma,
+                   double *dxdy)
+{
+    opt_noise(seed, request_id, g, d, step, sigma, dxdy, dxdy + 1);
+}
+
+/* nearest point of the domain (bitset over the N points) to y */
+int64_t orc_project_domain(const float *pts, int32_t n_points, const uint32_t *dom, const double *y, int *flag)
+{
+    const int64_t NW = (n_points + 31) / 32;
+    int64_t best = -1;
+    double bd = INFINITY, second = INFINITY;
+    for (int64_t w = 0; w < NW; ++w) {
+        for (int b = 0; b < 32; ++b) {
+            if (!((dom[w] >> b) & 1u)) continue;
+            int64_t i = w * 32 + b;
+            if (i >= n_points) break;
+            double dd = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                double e = (double)pts[3 * i + a] - y[a];
+                dd += e * e;
+            }
+            double dist = sqrt(dd);
+            if (dist < bd) {
+                second = bd;
+                bd = dist;
+                best = i;
+            } else if (dist < second) {
+                second = dist;
+            }
+        }
+    }
+    if (flag) *flag = (second - bd) <= OPT_BAND;
+    return best;
+}
+
+int orc_optimize(const float *pts, const float *nrm, int32_t n_points, const uint32_t *dom_bits /*[P][F][NW]*/,
+                 int32_t n_poses, int32_t F, int32_t draws, int32_t k, int32_t *set_pt /*[P][D][k] in/out*/,
+                 double mu, int32_t m_edges, double rho, int32_t n_outer, int32_t n_inner, double sigma,
+                 uint64_t seed, uint32_t request_id, int64_t pose_offset, int32_t max_pivots,
+                 double *tstar /*[P][D]*/, uint8_t *oflag /*[P][D]*/)
+{
+    const int64_t NW = (n_points + 31) / 32;
+    if (k <= 0 || k > 16 || k > F || n_outer < 0 || n_inner < 1 || n_inner > 64 || !(sigma >= 0.0))
+        return ORC_EINVAL;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t s = 0; s < (int64_t)n_poses * draws; ++s) {
+        const int64_t g = s / draws;
+        const int d = (int)(s % draws);
+        int32_t *sp = set_pt + s * k;
+        int valid = 1;
+        for (int i = 0; i < k; ++i) valid &= sp[i] >= 0;
+        if (!valid) {
+            tstar[s] = NAN;
+            oflag[s] = 0;
+            continue;
+        }
+        double p[3 * 16], n[3 * 16];
+        for (int i = 0; i < k; ++i)
+            for (int a = 0; a < 3; ++a) {
+                p[3 * i + a] = pts[3 * (int64_t)sp[i] + a];
+                n[3 * i + a] = nrm[3 * (int64_t)sp[i] + a];
+            }
+        int st, pv, fl = 0;
+        double J = orc_set_tstar(k, p, n, mu, m_edges, rho, max_pivots, &st, &pv);
+        if (st != 0) J = INFINITY;
+        for (int r = 0; r < n_outer; ++r) {
+            for (int i = 0; i < k; ++i) {
+                double tx[3], ty[3];
+                duff_basis(n + 3 * i, tx, ty);
+                double Jc[64] = {0};
+                int64_t idx[64];
+                const uint32_t *dom = dom_bits + (g * F + i) * NW;
+                for (int j = 0; j < n_inner; ++j) {
+                    double dx, dy, y[3];
+                    opt_noise(seed, request_id, pose_offset + g, d, (uint32_t)((r * k + i) * n_inner + j), sigma,
+                              &dx, &dy);
+                    for (int a = 0; a < 3; ++a) y[a] = p[3 * i + a] + dx * tx[a] + dy * ty[a];
+                    int pf = 0;
+                    idx[j] = orc_project_domain(pts, n_points, dom, y, &pf);
+                    fl |= pf;
+                    double pc[3 * 16], nc[3 * 16];
+                    memcpy(pc, p, sizeof(double) * 3 * k);
+                    memcpy(nc, n, sizeof(double) * 3 * k);
+                    for (int a = 0; a < 3; ++a) {
+                        pc[3 * i + a] = pts[3 * idx[j] + a];
+                        nc[3 * i + a] = nrm[3 * idx[j] + a];
+                    }
+                    Jc[j] = orc_set_tstar(k, pc, nc, mu, m_edges, rho, max_pivots, &st, &pv);
+                    if (st != 0) Jc[j] = INFINITY;
+                }
+                double mn = INFINITY;
+                for (int j = 0; j < n_inner; ++j) mn = fmin(mn, Jc[j]);
+                int js = 0;
+                for (int j = 0; j < n_inner; ++j)
+                    if (Jc[j] <= mn + OPT_TAU) { js = j; break; }
+                for (int j = 0; j < n_inner; ++j)
+                    if (isfinite(mn) && fabs(Jc[j] - (mn + OPT_TAU)) <= 1e-10) fl = 1;
+                sp[i] = (int32_t)idx[js];
+                for (int a = 0; a < 3; ++a) {
+                    p[3 * i + a] = pts[3 * idx[js] + a];
+                    n[3 * i + a] = nrm[3 * idx[js] + a];
+                }
+                J = Jc[js];
+            }
+        }
+        tstar[s] = J;
+        oflag[s] = (uint8_t)fl;
+    }
+    return ORC_OK;
+}
+
+/* Link of every contact of every valid set, picked as in orc_draw with the  */
+/* set's draw words (for sets whose points the optimisation moved).           */
+int orc_relink(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits, const float *pts,
+               const float *nrm, const float *poses, int32_t n_poses, int32_t draws, int32_t k,
+               const int32_t *set_pt, uint64_t seed, uint32_t request_id, int64_t pose_offset,
+               int32_t *set_link)
+{
+    if (k != H->n_fingers || k > 8 || draws <= 0) return ORC_EINVAL;
+    double cb[3 * 64];
+    orc_bin_centers(fp->bins, cb);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int g = 0; g < n_poses; ++g) {
+        for (int d = 0; d < draws; ++d) {
+            uint32_t w[16];
+            draw_words(seed, request_id, pose_offset + g, d, 2 * k, w);
+            const int32_t *sp = set_pt + ((int64_t)g * draws + d) * k;
+            int32_t *sl = set_link + ((int64_t)g * draws + d) * k;
+            for (int i = 0; i < k; ++i)
+                sl[i] = sp[i] < 0 ? -1 : pick_link(H, fp, bits, cb, pts, nrm, poses + 12 * (int64_t)g, i, sp[i], w[k + i]);
+        }
     }
     return ORC_OK;
 }

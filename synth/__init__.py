@@ -646,6 +646,9 @@ class SearchParams:
     request_id: int = 0
     pose_offset: int = 0
     moment_scale: float = 1.0
+    opt_outer: int = 0       # rounds of contact-point optimisation (0 = score the draws as drawn)
+    opt_inner: int = 8       # candidates per contact and round
+    opt_sigma: float = 0.004  # m, std of the tangent-plane mutations
 
 
 @dataclass
