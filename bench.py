@@ -46,8 +46,13 @@ def parse():
     ap.add_argument("--cpu-poses", type=int, default=0, help="poses of the CPU-oracle sample (0 = auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving run (req/s)")
+    ap.add_argument("--serve-rates", default="5,20,50,100", help="serve mode: comma-separated arrival rates")
     ap.add_argument("--serve-seconds", type=float, default=6.0, help="arrival window of the serving run (s)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--opt-outer", type=int, default=0,
+                    help="rounds of contact-point optimisation (Alg. 2) before the verdicts; 0 = the plain method")
+    ap.add_argument("--opt-inner", type=int, default=8)
+    ap.add_argument("--opt-sigma", type=float, default=0.004)
     ap.add_argument("--train-objects", type=int, default=2000, help="proposer: training objects (seeds 0..n-1)")
     ap.add_argument("--eval-objects", type=int, default=200, help="proposer: held-out objects (seeds 100000..)")
     ap.add_argument("--epochs", type=int, default=60, help="proposer: training epochs")
@@ -386,9 +391,14 @@ def main():
         print(json.dumps({"proposer": out}))
         return
     if args.mode == "serve":
-        print(json.dumps({"serving": serve_bench(torch, lg, args.serve_rate, args.serve_seconds, args.seed)}))
+        for rate in [float(r) for r in args.serve_rates.split(",")]:
+            print(json.dumps({"serving": serve_bench(torch, lg, rate, args.serve_seconds, args.seed)}), flush=True)
         return
     w = synth.workload(args.workload, seed=args.seed, with_sdf=(args.workload == "c3"))
+    if args.opt_outer > 0:
+        import dataclasses
+        w.search = dataclasses.replace(w.search, opt_outer=args.opt_outer, opt_inner=args.opt_inner,
+                                       opt_sigma=args.opt_sigma)
     t_build = time.perf_counter()
     field = lg.lg_build_field(w.hand, w.field, keep_witness=w.ik is not None)
     t_build = time.perf_counter() - t_build
@@ -472,7 +482,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {DESCR[args.workload]}", "poses_per_step": pipe.P,
-                   "points": pipe.N, "draws": int(w.search.draws), "seed": args.seed},
+                   "points": pipe.N, "draws": int(w.search.draws), "seed": args.seed,
+                   "contact_opt": ({"rounds": args.opt_outer, "candidates": args.opt_inner,
+                                    "sigma_m": args.opt_sigma} if args.opt_outer > 0 else None)},
         "valid_per_step": n_valid,
         "accepted_sets_per_step": n_acc,
         "stage_ms": {"query": q_ms, "search": float(st[:, 1].mean()), "realize": float(st[:, 2].mean())},

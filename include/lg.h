@@ -163,10 +163,13 @@ typedef struct {
     uint64_t seed;        /* Philox key */
     uint32_t request_id;  /* 4th Philox counter word */
     int64_t pose_offset;  /* global index of pose 0 (RNG counters use it) */
+    int32_t opt_outer;    /* rounds of contact-point optimisation (Sec. 5.4, Alg. 2); 0 = none */
+    int32_t opt_inner;    /* candidates per contact and round, 1..16 */
+    float opt_sigma;      /* std of the tangent-plane mutations (m) */
 } lg_search_params;
 
-/* Bytes of device workspace lg_search needs for n_poses poses. */
-size_t lg_search_workspace_bytes(int32_t n_poses, const lg_search_params *params);
+/* Bytes of device workspace lg_search needs for n_points points and n_poses poses. */
+size_t lg_search_workspace_bytes(int32_t n_points, int32_t n_poses, const lg_search_params *params);
 
 /*
  * lg_search -- seeded contact-set draws, force-closure verdicts, compaction.
@@ -179,6 +182,16 @@ size_t lg_search_workspace_bytes(int32_t n_poses, const lg_search_params *params
  * d_ie = -n_i + mu (cos(2 pi e/m) x_i + sin(2 pi e/m) y_i) with the Duff et
  * al. (2017) tangent basis; t* = min sum_r |(W g)_r| over g >= 0, sum g = 1
  * (double-precision Phase-1 simplex, Bland's rule); verdict = t* <= eps.
+ * With opt_outer > 0 the drawn sets of poses whose domains are all non-empty
+ * are first refined by Alg. 2 of Sec. 5.4: for opt_outer rounds, each contact
+ * i in turn gets opt_inner candidates, its point moved in the tangent plane of
+ * its object normal (Duff basis x_i, y_i) by (dx, dy) ~ N(0, opt_sigma^2) and
+ * projected onto its domain (nearest domain point, lowest index on ties);
+ * contact i moves to the first candidate whose t* is within 1e-9 of the
+ * candidates' minimum.  Candidate j of step s = (round * k + i) * opt_inner + j
+ * uses Philox block (g + pose_offset, d, 5 | s << 8, request_id): Box-Muller of
+ * u1 = ((w0 >> 8) + 1) / 2^24, u2 = (w1 >> 8) / 2^24.  tstar and verdict are
+ * those of the final set; its links are picked again with the draw's words.
  * Outputs (device): set_pt [P][D][k] int32, set_link [P][D][k] int8 (global
  * joint/link index), verdict [P][D] uint8, tstar [P][D] double (NaN for
  * invalid sets), acc_list [P*D] int32 accepted set ids g*D + d in increasing

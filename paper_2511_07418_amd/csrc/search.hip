@@ -22,6 +22,27 @@ __device__ inline int select_in_word(uint32_t x, uint32_t r)
     return __ffs(x) - 1;
 }
 
+// Reverse lookup (Sec. 5.5): among the links of finger i whose own table is
+// hit at point idx under the pose, the floor(r * count / 2^32)-th; -1 if none.
+__device__ inline int pick_link(const DevHand &H, const uint32_t *__restrict__ bits, const float *cb,
+                                const float *__restrict__ pts, const float *__restrict__ nrm, int N,
+                                const float *pose, int i, int idx, uint32_t r)
+{
+    const int64_t G3 = (int64_t)H.G * H.G * H.G;
+    const Affine a = finger_affine(H, pose, i);
+    const int v = window_voxel(a, H.G, pts[idx], pts[N + idx], pts[2 * N + idx]);
+    float qx, qy, qz;
+    query_dir(pose, nrm[idx], nrm[N + idx], nrm[2 * N + idx], qx, qy, qz);
+    const int b = nearest_bin(cb, H.B, qx, qy, qz);
+    uint32_t mask = 0;
+    const int first = H.finger_first[i], dof = H.finger_dof[i];
+    if (v >= 0)
+        for (int t = 0; t < dof; ++t)
+            if (table_bit(bits + (int64_t)(first + t) * G3 * H.W, H.W, v, b)) mask |= 1u << t;
+    const uint32_t pc = __popc(mask);
+    return pc ? first + select_in_word(mask, __umulhi(r, pc)) : -1;
+}
+
 // One workgroup per pose.  Rank structure: exclusive popcount prefix per
 // superblock of 8 domain words, in LDS; a draw binary-searches it and scans
 // at most 8 words.
@@ -70,7 +91,6 @@ k_draw(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ p
     }
     __syncthreads();
     const float *pose = poses + 12 * (int64_t)g;
-    const int64_t G3 = (int64_t)H.G * H.G * H.G;
     for (int d = threadIdx.x; d < D; d += blockDim.x) {
         uint32_t w[16];
         for (int blk = 0; blk * 4 < 2 * k; ++blk)
@@ -99,24 +119,8 @@ k_draw(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ p
                 }
                 rem -= pc;
             }
-            // reverse lookup: links of finger i whose own table is hit at idx
-            int link = -1;
-            if (idx >= 0) {
-                const Affine a = finger_affine(H, pose, i);
-                const int v = window_voxel(a, H.G, pts[idx], pts[N + idx], pts[2 * N + idx]);
-                float qx, qy, qz;
-                query_dir(pose, nrm[idx], nrm[N + idx], nrm[2 * N + idx], qx, qy, qz);
-                const int b = nearest_bin(cb, H.B, qx, qy, qz);
-                uint32_t mask = 0;
-                const int first = H.finger_first[i], dof = H.finger_dof[i];
-                if (v >= 0)
-                    for (int t = 0; t < dof; ++t)
-                        if (table_bit(bits + (int64_t)(first + t) * G3 * H.W, H.W, v, b)) mask |= 1u << t;
-                const uint32_t pc = __popc(mask);
-                if (pc) link = first + select_in_word(mask, __umulhi(w[k + i], pc));
-            }
             sp[i] = idx;
-            sl[i] = (int8_t)link;
+            sl[i] = (int8_t)(idx >= 0 ? pick_link(H, bits, cb, pts, nrm, N, pose, i, idx, w[k + i]) : -1);
         }
     }
 }
@@ -157,6 +161,240 @@ struct LpConst {
     double ce[16], se[16];  // cos, sin of 2 pi e / m
 };
 
+// t* of the set held in this lane's LDS column (cd[6 i + c][tid]); status
+// 0 = optimal, 1 = pivot cap, 2 = unbounded ratio test (not expected).
+template <int KM>
+__device__ inline double lp_lane(float (&cd)[KM * 6][256], int tid, int k, int m, double mu, double rho,
+                                 int max_pivots, const LpConst &cs, int &status_out)
+{
+    const int n = k * m;
+    const double inv_rho = 1.0 / rho;
+    // contact i's point and normal (each lane reads only its own column)
+    auto contact = [&](int ci, double &px, double &py, double &pz, double &nx, double &ny, double &nz) {
+        px = cd[6 * ci + 0][tid];
+        py = cd[6 * ci + 1][tid];
+        pz = cd[6 * ci + 2][tid];
+        nx = cd[6 * ci + 3][tid];
+        ny = cd[6 * ci + 4][tid];
+        nz = cd[6 * ci + 5][tid];
+    };
+    // original column j of [W^T -I I; 1 0 0]
+    auto column = [&](int j, double *a) {
+#pragma unroll
+        for (int r = 0; r < 7; ++r) a[r] = 0.0;
+        if (j < n) {
+            const int ci = j / m, e = j - ci * m;
+            double px, py, pz, nx, ny, nz;
+            contact(ci, px, py, pz, nx, ny, nz);
+            double x[3], y[3];
+            duff_basis(nx, ny, nz, x, y);
+            const double c = cs.ce[e], s = cs.se[e];
+            const double dx = -nx + mu * (c * x[0] + s * y[0]);
+            const double dy = -ny + mu * (c * x[1] + s * y[1]);
+            const double dz = -nz + mu * (c * x[2] + s * y[2]);
+            a[0] = dx;
+            a[1] = dy;
+            a[2] = dz;
+            a[3] = (py * dz - pz * dy) / rho;
+            a[4] = (pz * dx - px * dz) / rho;
+            a[5] = (px * dy - py * dx) / rho;
+            a[6] = 1.0;
+        } else if (j < n + 6) {
+#pragma unroll
+            for (int r = 0; r < 6; ++r) a[r] = (r == j - n) ? -1.0 : 0.0;
+        } else {
+#pragma unroll
+            for (int r = 0; r < 6; ++r) a[r] = (r == j - n - 6) ? 1.0 : 0.0;
+        }
+    };
+    // initial basis: g_0 on the normalisation row, s-_r (w0_r <= 0) or s+_r
+    double Bi[7][7], xB[7];
+    int basis[7];
+    {
+        double w0[7];
+        column(0, w0);
+#pragma unroll
+        for (int r = 0; r < 7; ++r)
+#pragma unroll
+            for (int c = 0; c < 7; ++c) Bi[r][c] = 0.0;
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            const double sg = w0[r] <= 0.0 ? 1.0 : -1.0;
+            basis[r] = w0[r] <= 0.0 ? n + 6 + r : n + r;
+            Bi[r][r] = sg;
+            Bi[r][6] = -sg * w0[r];
+            xB[r] = -sg * w0[r];
+        }
+        Bi[6][6] = 1.0;
+        basis[6] = 0;
+        xB[6] = 1.0;
+    }
+    auto cost = [&](int j) { return j >= n ? 1.0 : 0.0; };
+    auto duals = [&](double *y) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < 7; ++r) s += cost(basis[r]) * Bi[r][c];
+            y[c] = s;
+        }
+    };
+    // Pricing.  Dantzig (most negative reduced cost, ties to the lowest index)
+    // for the first kBlandAfter pivots; Bland (first negative) afterwards,
+    // which rules out cycling.  -1 when no reduced cost is below -kLpTol.
+    auto price = [&](const double *y, bool bland) {
+        int e = -1;
+        double best = -kLpTol;
+        for (int i = 0; i < k && !(bland && e >= 0); ++i) {
+            double px, py, pz, nx, ny, nz;
+            contact(i, px, py, pz, nx, ny, nz);
+            // u = y_f + (y_m x p) / rho
+            const double ux = y[0] + (y[4] * pz - y[5] * py) * inv_rho;
+            const double uy = y[1] + (y[5] * px - y[3] * pz) * inv_rho;
+            const double uz = y[2] + (y[3] * py - y[4] * px) * inv_rho;
+            double x[3], yy[3];
+            duff_basis(nx, ny, nz, x, yy);
+            const double an = ux * nx + uy * ny + uz * nz;
+            const double bx = ux * x[0] + uy * x[1] + uz * x[2];
+            const double by = ux * yy[0] + uy * yy[1] + uz * yy[2];
+            for (int ee = 0; ee < m; ++ee) {
+                const double d = -(-an + mu * (cs.ce[ee] * bx + cs.se[ee] * by)) - y[6];
+                if (d < best) {
+                    best = d;
+                    e = i * m + ee;
+                    if (bland) break;
+                }
+            }
+        }
+        for (int r = 0; r < 6 && !(bland && e >= 0); ++r)
+            if (1.0 + y[r] < best) {
+                best = 1.0 + y[r];
+                e = n + r;
+            }
+        for (int r = 0; r < 6 && !(bland && e >= 0); ++r)
+            if (1.0 - y[r] < best) {
+                best = 1.0 - y[r];
+                e = n + 6 + r;
+            }
+        return e;
+    };
+    // residual corrections of x_B (B x = e_6) and y (B^T y = c_B)
+    auto refine = [&](double *y) {
+        for (int pass = 0; pass < 2; ++pass) {
+            double rx[7] = {0, 0, 0, 0, 0, 0, 1.0}, ry[7];
+#pragma unroll 1
+            for (int q = 0; q < 7; ++q) {
+                double a[7];
+                column(basis[q], a);
+                double dot = 0.0;
+#pragma unroll
+                for (int r = 0; r < 7; ++r) {
+                    rx[r] -= a[r] * xB[q];
+                    dot += a[r] * y[r];
+                }
+                ry[q] = cost(basis[q]) - dot;
+            }
+#pragma unroll
+            for (int r = 0; r < 7; ++r) {
+                double s = 0.0;
+#pragma unroll
+                for (int c = 0; c < 7; ++c) s += Bi[r][c] * rx[c];
+                xB[r] += s;
+            }
+#pragma unroll
+            for (int c = 0; c < 7; ++c) {
+                double s = 0.0;
+#pragma unroll
+                for (int r = 0; r < 7; ++r) s += ry[r] * Bi[r][c];
+                y[c] += s;
+            }
+        }
+    };
+    int piv = 0, status = 0, checks = 0;
+    for (;;) {
+        double y[7];
+        duals(y);
+        const bool bland = piv >= kBlandAfter;
+        int e = price(y, bland);
+        if (e < 0) {
+            if (checks >= 4) break;
+            ++checks;
+            refine(y);
+            e = price(y, bland);
+            if (e < 0) break;
+        }
+        if (piv >= max_pivots) {
+            status = 1;
+            break;
+        }
+        double a[7], al[7];
+        column(e, a);
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) s += Bi[r][c] * a[c];
+            al[r] = s;
+        }
+        // ratio test min x_B[r] / al[r] without divisions: the current best is
+        // kept as the fraction bx / ba (ba > 0) and ratios are compared by
+        // cross-multiplication; the tie band is kLpTol (1 + |best|).
+        int lr = -1;
+        double bx = 0.0, ba = 1.0;
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+            if (al[r] > kLpPiv) {
+                const double lhs = xB[r] * ba, rhs = bx * al[r];
+                const double band = kLpTol * (ba + fabs(bx)) * al[r];
+                if (lr < 0 || lhs < rhs - band || (fabs(lhs - rhs) <= band && basis[r] < basis[lr])) {
+                    lr = r;
+                    bx = xB[r];
+                    ba = al[r];
+                }
+            }
+        }
+        if (lr < 0) {
+            status = 2;
+            break;
+        }
+        double pv = 1.0, prow[7], px = 0.0;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) prow[c] = 0.0;
+#pragma unroll
+        for (int r = 0; r < 7; ++r)
+            if (r == lr) {
+                pv = al[r];
+                px = xB[r];
+#pragma unroll
+                for (int c = 0; c < 7; ++c) prow[c] = Bi[r][c];
+            }
+        const double inv = 1.0 / pv;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) prow[c] *= inv;
+        px *= inv;
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+            if (r == lr) {
+#pragma unroll
+                for (int c = 0; c < 7; ++c) Bi[r][c] = prow[c];
+                xB[r] = px;
+                basis[r] = e;
+            } else {
+#pragma unroll
+                for (int c = 0; c < 7; ++c) Bi[r][c] -= al[r] * prow[c];
+                xB[r] -= al[r] * px;
+            }
+        }
+        ++piv;
+    }
+    double ts = 0.0;
+#pragma unroll
+    for (int r = 0; r < 7; ++r)
+        if (basis[r] >= n) ts += xB[r];
+    status_out = status;
+    return ts;
+}
+
 template <int KM>
 __global__ void __launch_bounds__(256)
 k_verdict_lane(const float *__restrict__ pts, const float *__restrict__ nrm, int N, const int32_t *__restrict__ set_pt,
@@ -190,232 +428,288 @@ k_verdict_lane(const float *__restrict__ pts, const float *__restrict__ nrm, int
             tstar[sid] = __builtin_nan("");
             continue;
         }
-        const int n = k * m;
-        const double inv_rho = 1.0 / rho;
-        // contact i's point and normal (each lane reads only its own column)
-        auto contact = [&](int ci, double &px, double &py, double &pz, double &nx, double &ny, double &nz) {
-            px = cd[6 * ci + 0][tid];
-            py = cd[6 * ci + 1][tid];
-            pz = cd[6 * ci + 2][tid];
-            nx = cd[6 * ci + 3][tid];
-            ny = cd[6 * ci + 4][tid];
-            nz = cd[6 * ci + 5][tid];
-        };
-        // original column j of [W^T -I I; 1 0 0]
-        auto column = [&](int j, double *a) {
-#pragma unroll
-            for (int r = 0; r < 7; ++r) a[r] = 0.0;
-            if (j < n) {
-                const int ci = j / m, e = j - ci * m;
-                double px, py, pz, nx, ny, nz;
-                contact(ci, px, py, pz, nx, ny, nz);
-                double x[3], y[3];
-                duff_basis(nx, ny, nz, x, y);
-                const double c = cs.ce[e], s = cs.se[e];
-                const double dx = -nx + mu * (c * x[0] + s * y[0]);
-                const double dy = -ny + mu * (c * x[1] + s * y[1]);
-                const double dz = -nz + mu * (c * x[2] + s * y[2]);
-                a[0] = dx;
-                a[1] = dy;
-                a[2] = dz;
-                a[3] = (py * dz - pz * dy) / rho;
-                a[4] = (pz * dx - px * dz) / rho;
-                a[5] = (px * dy - py * dx) / rho;
-                a[6] = 1.0;
-            } else if (j < n + 6) {
-#pragma unroll
-                for (int r = 0; r < 6; ++r) a[r] = (r == j - n) ? -1.0 : 0.0;
-            } else {
-#pragma unroll
-                for (int r = 0; r < 6; ++r) a[r] = (r == j - n - 6) ? 1.0 : 0.0;
-            }
-        };
-        // initial basis: g_0 on the normalisation row, s-_r (w0_r <= 0) or s+_r
-        double Bi[7][7], xB[7];
-        int basis[7];
-        {
-            double w0[7];
-            column(0, w0);
-#pragma unroll
-            for (int r = 0; r < 7; ++r)
-#pragma unroll
-                for (int c = 0; c < 7; ++c) Bi[r][c] = 0.0;
-#pragma unroll
-            for (int r = 0; r < 6; ++r) {
-                const double sg = w0[r] <= 0.0 ? 1.0 : -1.0;
-                basis[r] = w0[r] <= 0.0 ? n + 6 + r : n + r;
-                Bi[r][r] = sg;
-                Bi[r][6] = -sg * w0[r];
-                xB[r] = -sg * w0[r];
-            }
-            Bi[6][6] = 1.0;
-            basis[6] = 0;
-            xB[6] = 1.0;
-        }
-        auto cost = [&](int j) { return j >= n ? 1.0 : 0.0; };
-        auto duals = [&](double *y) {
-#pragma unroll
-            for (int c = 0; c < 7; ++c) {
-                double s = 0.0;
-#pragma unroll
-                for (int r = 0; r < 7; ++r) s += cost(basis[r]) * Bi[r][c];
-                y[c] = s;
-            }
-        };
-        // Pricing.  Dantzig (most negative reduced cost, ties to the lowest index)
-        // for the first kBlandAfter pivots; Bland (first negative) afterwards,
-        // which rules out cycling.  -1 when no reduced cost is below -kLpTol.
-        auto price = [&](const double *y, bool bland) {
-            int e = -1;
-            double best = -kLpTol;
-            for (int i = 0; i < k && !(bland && e >= 0); ++i) {
-                double px, py, pz, nx, ny, nz;
-                contact(i, px, py, pz, nx, ny, nz);
-                // u = y_f + (y_m x p) / rho
-                const double ux = y[0] + (y[4] * pz - y[5] * py) * inv_rho;
-                const double uy = y[1] + (y[5] * px - y[3] * pz) * inv_rho;
-                const double uz = y[2] + (y[3] * py - y[4] * px) * inv_rho;
-                double x[3], yy[3];
-                duff_basis(nx, ny, nz, x, yy);
-                const double an = ux * nx + uy * ny + uz * nz;
-                const double bx = ux * x[0] + uy * x[1] + uz * x[2];
-                const double by = ux * yy[0] + uy * yy[1] + uz * yy[2];
-                for (int ee = 0; ee < m; ++ee) {
-                    const double d = -(-an + mu * (cs.ce[ee] * bx + cs.se[ee] * by)) - y[6];
-                    if (d < best) {
-                        best = d;
-                        e = i * m + ee;
-                        if (bland) break;
-                    }
-                }
-            }
-            for (int r = 0; r < 6 && !(bland && e >= 0); ++r)
-                if (1.0 + y[r] < best) {
-                    best = 1.0 + y[r];
-                    e = n + r;
-                }
-            for (int r = 0; r < 6 && !(bland && e >= 0); ++r)
-                if (1.0 - y[r] < best) {
-                    best = 1.0 - y[r];
-                    e = n + 6 + r;
-                }
-            return e;
-        };
-        // residual corrections of x_B (B x = e_6) and y (B^T y = c_B)
-        auto refine = [&](double *y) {
-            for (int pass = 0; pass < 2; ++pass) {
-                double rx[7] = {0, 0, 0, 0, 0, 0, 1.0}, ry[7];
-#pragma unroll 1
-                for (int q = 0; q < 7; ++q) {
-                    double a[7];
-                    column(basis[q], a);
-                    double dot = 0.0;
-#pragma unroll
-                    for (int r = 0; r < 7; ++r) {
-                        rx[r] -= a[r] * xB[q];
-                        dot += a[r] * y[r];
-                    }
-                    ry[q] = cost(basis[q]) - dot;
-                }
-#pragma unroll
-                for (int r = 0; r < 7; ++r) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int c = 0; c < 7; ++c) s += Bi[r][c] * rx[c];
-                    xB[r] += s;
-                }
-#pragma unroll
-                for (int c = 0; c < 7; ++c) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int r = 0; r < 7; ++r) s += ry[r] * Bi[r][c];
-                    y[c] += s;
-                }
-            }
-        };
-        int piv = 0, status = 0, checks = 0;
-        for (;;) {
-            double y[7];
-            duals(y);
-            const bool bland = piv >= kBlandAfter;
-            int e = price(y, bland);
-            if (e < 0) {
-                if (checks >= 4) break;
-                ++checks;
-                refine(y);
-                e = price(y, bland);
-                if (e < 0) break;
-            }
-            if (piv >= max_pivots) {
-                status = 1;
-                break;
-            }
-            double a[7], al[7];
-            column(e, a);
-#pragma unroll
-            for (int r = 0; r < 7; ++r) {
-                double s = 0.0;
-#pragma unroll
-                for (int c = 0; c < 7; ++c) s += Bi[r][c] * a[c];
-                al[r] = s;
-            }
-            // ratio test min x_B[r] / al[r] without divisions: the current best is
-            // kept as the fraction bx / ba (ba > 0) and ratios are compared by
-            // cross-multiplication; the tie band is kLpTol (1 + |best|).
-            int lr = -1;
-            double bx = 0.0, ba = 1.0;
-#pragma unroll
-            for (int r = 0; r < 7; ++r) {
-                if (al[r] > kLpPiv) {
-                    const double lhs = xB[r] * ba, rhs = bx * al[r];
-                    const double band = kLpTol * (ba + fabs(bx)) * al[r];
-                    if (lr < 0 || lhs < rhs - band || (fabs(lhs - rhs) <= band && basis[r] < basis[lr])) {
-                        lr = r;
-                        bx = xB[r];
-                        ba = al[r];
-                    }
-                }
-            }
-            if (lr < 0) {
-                status = 2;
-                break;
-            }
-            double pv = 1.0, prow[7], px = 0.0;
-#pragma unroll
-            for (int c = 0; c < 7; ++c) prow[c] = 0.0;
-#pragma unroll
-            for (int r = 0; r < 7; ++r)
-                if (r == lr) {
-                    pv = al[r];
-                    px = xB[r];
-#pragma unroll
-                    for (int c = 0; c < 7; ++c) prow[c] = Bi[r][c];
-                }
-            const double inv = 1.0 / pv;
-#pragma unroll
-            for (int c = 0; c < 7; ++c) prow[c] *= inv;
-            px *= inv;
-#pragma unroll
-            for (int r = 0; r < 7; ++r) {
-                if (r == lr) {
-#pragma unroll
-                    for (int c = 0; c < 7; ++c) Bi[r][c] = prow[c];
-                    xB[r] = px;
-                    basis[r] = e;
-                } else {
-#pragma unroll
-                    for (int c = 0; c < 7; ++c) Bi[r][c] -= al[r] * prow[c];
-                    xB[r] -= al[r] * px;
-                }
-            }
-            ++piv;
-        }
-        double ts = 0.0;
-#pragma unroll
-        for (int r = 0; r < 7; ++r)
-            if (basis[r] >= n) ts += xB[r];
+        int status = 0;
+        const double ts = lp_lane<KM>(cd, tid, k, m, mu, rho, max_pivots, cs, status);
         verdict[sid] = (status == 0 && ts <= eps) ? 1 : 0;
         tstar[sid] = status == 0 ? ts : __builtin_nan("");
+    }
+}
+
+// ---- contact-point optimisation (Sec. 5.4, Alg. 2) ---------------------------
+// A uniform cell grid over the object's points serves the projection of a
+// candidate onto a contact domain (nearest domain point).  Cells are cubes of
+// edge c = max(sigma, extent / kGridMax); points are bucketed by a counting
+// sort.  The search scans shells of cells at Chebyshev distance R = 0, 1, ...
+// around the candidate's cell; points in unscanned cells are at least R c away,
+// so once the best distance is below R c (less a rounding margin) it is exact.
+// Beyond kProjShells the whole domain bitset is scanned.  Distances are FP64,
+// ties go to the lowest point index.
+constexpr int kGridMax = 64;
+constexpr int kProjShells = 4;
+constexpr uint32_t kPurposeOpt = 5u;
+constexpr double kOptTau = 1e-9;  // candidates within kOptTau of the best criterion value tie
+
+struct GridDev {
+    float lo[3];
+    float cell, inv_cell;
+    int dims[3];
+};
+
+__global__ void __launch_bounds__(1024)
+k_grid_setup(const float *__restrict__ pts, int N, float sigma, GridDev *__restrict__ gd)
+{
+    __shared__ float red[6][1024];
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = threadIdx.x; i < N; i += blockDim.x)
+        for (int a = 0; a < 3; ++a) {
+            mn[a] = fminf(mn[a], pts[a * N + i]);
+            mx[a] = fmaxf(mx[a], pts[a * N + i]);
+        }
+    for (int a = 0; a < 3; ++a) {
+        red[a][threadIdx.x] = mn[a];
+        red[3 + a][threadIdx.x] = mx[a];
+    }
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int a = 0; a < 3; ++a) {
+                red[a][threadIdx.x] = fminf(red[a][threadIdx.x], red[a][threadIdx.x + w]);
+                red[3 + a][threadIdx.x] = fmaxf(red[3 + a][threadIdx.x], red[3 + a][threadIdx.x + w]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        float ext = 0.0f;
+        for (int a = 0; a < 3; ++a) ext = fmaxf(ext, red[3 + a][0] - red[a][0]);
+        const float c = fmaxf(fmaxf(sigma, ext / (float)kGridMax), 1e-4f);
+        GridDev g;
+        g.cell = c;
+        g.inv_cell = 1.0f / c;
+        for (int a = 0; a < 3; ++a) {
+            g.lo[a] = red[a][0];
+            g.dims[a] = min(kGridMax + 1, (int)((red[3 + a][0] - red[a][0]) * g.inv_cell) + 1);
+        }
+        *gd = g;
+    }
+}
+
+__device__ inline int grid_coord(const GridDev &g, int a, float x)
+{
+    return (int)floorf((x - g.lo[a]) * g.inv_cell);
+}
+
+__device__ inline int point_cell(const GridDev &g, const float *pts, int N, int i)
+{
+    int c[3];
+    for (int a = 0; a < 3; ++a) c[a] = min(max(grid_coord(g, a, pts[a * N + i]), 0), g.dims[a] - 1);
+    return (c[2] * g.dims[1] + c[1]) * g.dims[0] + c[0];
+}
+
+__global__ void k_grid_count(const float *__restrict__ pts, int N, const GridDev *__restrict__ gd,
+                             uint32_t *__restrict__ cell_count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) atomicAdd(&cell_count[point_cell(*gd, pts, N, i)], 1u);
+}
+
+// single workgroup: exclusive scan of the cell counts (cell_start[n_cells] = N)
+__global__ void __launch_bounds__(1024)
+k_grid_scan(uint32_t *__restrict__ cell_count, const GridDev *__restrict__ gd, uint32_t *__restrict__ cell_start)
+{
+    __shared__ uint32_t tot[1024];
+    const int nc = gd->dims[0] * gd->dims[1] * gd->dims[2];
+    const int per = (nc + 1023) / 1024, b0 = threadIdx.x * per;
+    uint32_t s = 0;
+    for (int i = b0; i < min(nc, b0 + per); ++i) s += cell_count[i];
+    tot[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int t = 0; t < 1024; ++t) {
+            const uint32_t v = tot[t];
+            tot[t] = run;
+            run += v;
+        }
+        cell_start[nc] = run;
+    }
+    __syncthreads();
+    uint32_t run = tot[threadIdx.x];
+    for (int i = b0; i < min(nc, b0 + per); ++i) {
+        const uint32_t v = cell_count[i];
+        cell_start[i] = run;
+        cell_count[i] = run;  // becomes the scatter cursor
+        run += v;
+    }
+}
+
+__global__ void k_grid_scatter(const float *__restrict__ pts, int N, const GridDev *__restrict__ gd,
+                               uint32_t *__restrict__ cursor, int32_t *__restrict__ cell_pts)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) cell_pts[atomicAdd(&cursor[point_cell(*gd, pts, N, i)], 1u)] = i;
+}
+
+__device__ inline bool dom_has(const uint32_t *dom, int i) { return (dom[i >> 5] >> (i & 31)) & 1u; }
+
+// nearest point of the domain to y (FP64 distances, lowest index on ties)
+__device__ int project_domain(const GridDev &g, const uint32_t *__restrict__ cell_start,
+                              const int32_t *__restrict__ cell_pts, const float *__restrict__ pts, int N,
+                              const uint32_t *__restrict__ dom, double yx, double yy, double yz)
+{
+    const int cx = (int)floor((yx - g.lo[0]) * (double)g.inv_cell);
+    const int cy = (int)floor((yy - g.lo[1]) * (double)g.inv_cell);
+    const int cz = (int)floor((yz - g.lo[2]) * (double)g.inv_cell);
+    double best = INFINITY;
+    int bi = -1;
+    auto consider = [&](int i) {
+        const double ex = (double)pts[i] - yx, ey = (double)pts[N + i] - yy, ez = (double)pts[2 * N + i] - yz;
+        const double d2 = ex * ex + ey * ey + ez * ez;
+        if (d2 < best || (d2 == best && i < bi)) {
+            best = d2;
+            bi = i;
+        }
+    };
+    for (int R = 0; R <= kProjShells; ++R) {
+        for (int dz = -R; dz <= R; ++dz) {
+            const int z = cz + dz;
+            if (z < 0 || z >= g.dims[2]) continue;
+            for (int dy = -R; dy <= R; ++dy) {
+                const int yv = cy + dy;
+                if (yv < 0 || yv >= g.dims[1]) continue;
+                const bool edge = (dz == -R || dz == R || dy == -R || dy == R);
+                for (int dx = -R; dx <= R; dx += (edge ? 1 : 2 * R)) {
+                    const int x = cx + dx;
+                    if (x >= 0 && x < g.dims[0]) {
+                        const int c = (z * g.dims[1] + yv) * g.dims[0] + x;
+                        for (uint32_t q = cell_start[c]; q < cell_start[c + 1]; ++q) {
+                            const int i = cell_pts[q];
+                            if (dom_has(dom, i)) consider(i);
+                        }
+                    }
+                    if (R == 0) break;
+                }
+            }
+        }
+        if (bi >= 0 && sqrt(best) < (double)R * (double)g.cell - 1e-6) return bi;
+    }
+    // far from every scanned cell: the whole domain
+    const int NW = (N + 31) >> 5;
+    for (int w = 0; w < NW; ++w) {
+        uint32_t x = dom[w];
+        while (x) {
+            const int b = __ffs(x) - 1;
+            x &= x - 1u;
+            consider(w * 32 + b);
+        }
+    }
+    return bi;
+}
+
+// GS lanes per set (GS >= n_inner, a power of two): lane j evaluates candidate
+// j of every step; the group agrees on the pick by shuffles and one ballot.
+template <int KM, int GS>
+__global__ void __launch_bounds__(256)
+k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, const int32_t *__restrict__ valid_poses,
+           const int32_t *__restrict__ n_valid_poses, const uint32_t *__restrict__ dom_bits, int F, int D, int k, int m,
+           double mu, double rho, double eps, int max_pivots, LpConst cs, int n_outer, int n_inner, double sigma,
+           uint32_t seed_lo, uint32_t seed_hi, uint32_t request_id, int64_t pose_offset,
+           const GridDev *__restrict__ gdp, const uint32_t *__restrict__ cell_start,
+           const int32_t *__restrict__ cell_pts, int32_t *__restrict__ set_pt, uint8_t *__restrict__ verdict,
+           double *__restrict__ tstar)
+{
+    __shared__ float cd[KM * 6][256];
+    const int tid = threadIdx.x, lane = tid & 63, j = tid % GS, gbase = lane - j;
+    const GridDev g = *gdp;
+    const int NW = (N + 31) >> 5;
+    const int64_t n_work = (int64_t)(*n_valid_poses) * D;
+    const int64_t groups = ((int64_t)gridDim.x * blockDim.x) / GS;
+    auto load = [&](int ci, int idx) {
+        cd[6 * ci + 0][tid] = pts[idx];
+        cd[6 * ci + 1][tid] = pts[N + idx];
+        cd[6 * ci + 2][tid] = pts[2 * N + idx];
+        cd[6 * ci + 3][tid] = nrm[idx];
+        cd[6 * ci + 4][tid] = nrm[N + idx];
+        cd[6 * ci + 5][tid] = nrm[2 * N + idx];
+    };
+    for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + tid) / GS; t < n_work; t += groups) {
+        const int64_t pg = valid_poses[t / D];
+        const int d = (int)(t % D);
+        const int64_t sid = pg * D + d;
+        int32_t *sp = set_pt + sid * k;
+        int cur[KM];
+        for (int i = 0; i < k; ++i) {
+            cur[i] = sp[i];
+            load(i, cur[i]);
+        }
+        double J = INFINITY;
+        for (int r = 0; r < n_outer; ++r) {
+            for (int i = 0; i < k; ++i) {
+                int cand = -1;
+                double Jc = INFINITY;
+                if (j < n_inner) {
+                    const double px = cd[6 * i + 0][tid], py = cd[6 * i + 1][tid], pz = cd[6 * i + 2][tid];
+                    double tx[3], ty[3];
+                    duff_basis(cd[6 * i + 3][tid], cd[6 * i + 4][tid], cd[6 * i + 5][tid], tx, ty);
+                    uint32_t w[4];
+                    const uint32_t step = (uint32_t)((r * k + i) * n_inner + j);
+                    philox4x32_10((uint32_t)(pose_offset + pg), (uint32_t)d, kPurposeOpt | (step << 8), request_id,
+                                  seed_lo, seed_hi, w);
+                    const double u1 = ((double)(w[0] >> 8) + 1.0) * (1.0 / 16777216.0);
+                    const double u2 = (double)(w[1] >> 8) * (1.0 / 16777216.0);
+                    const double rr = sqrt(-2.0 * log(u1));
+                    const double dx = sigma * rr * cos(2.0 * M_PI * u2), dy = sigma * rr * sin(2.0 * M_PI * u2);
+                    cand = project_domain(g, cell_start, cell_pts, pts, N, dom_bits + (pg * F + i) * NW,
+                                          px + dx * tx[0] + dy * ty[0], py + dx * tx[1] + dy * ty[1],
+                                          pz + dx * tx[2] + dy * ty[2]);
+                    if (cand >= 0) {  // always, for a pose whose domains are all non-empty
+                        load(i, cand);
+                        int st = 0;
+                        Jc = lp_lane<KM>(cd, tid, k, m, mu, rho, max_pivots, cs, st);
+                        if (st != 0) Jc = INFINITY;
+                    }
+                }
+                double mn = Jc;
+                for (int off = GS >> 1; off > 0; off >>= 1) mn = fmin(mn, __shfl_xor(mn, off, GS));
+                const unsigned long long ok = __ballot(Jc <= mn + kOptTau);
+                const int js = __ffsll((long long)((ok >> gbase) & ((GS == 64) ? ~0ull : ((1ull << GS) - 1)))) - 1;
+                const int pick = __shfl(cand, gbase + js, 64);
+                const double Jp = __shfl(Jc, gbase + js, 64);
+                if (pick >= 0) {
+                    J = Jp;
+                    cur[i] = pick;
+                }
+                load(i, cur[i]);
+            }
+        }
+        if (j == 0) {
+            for (int i = 0; i < k; ++i) sp[i] = cur[i];
+            verdict[sid] = J <= eps ? 1 : 0;
+            tstar[sid] = isinf(J) ? __builtin_nan("") : J;
+        }
+    }
+}
+
+// links of the (moved) contacts of every set of a pose with non-empty domains,
+// picked with the set's draw words exactly as k_draw does
+__global__ void k_relink(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ pts,
+                         const float *__restrict__ nrm, int N, const float *__restrict__ poses,
+                         const int32_t *__restrict__ valid_poses, const int32_t *__restrict__ n_valid_poses, int D,
+                         int k, uint32_t seed_lo, uint32_t seed_hi, uint32_t request_id, int64_t pose_offset,
+                         const int32_t *__restrict__ set_pt, int8_t *__restrict__ set_link)
+{
+    const int64_t n_work = (int64_t)(*n_valid_poses) * D;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_work;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = valid_poses[t / D];
+        const int d = (int)(t % D);
+        uint32_t w[16];
+        for (int blk = 0; blk * 4 < 2 * k; ++blk)
+            philox4x32_10((uint32_t)(pose_offset + g), (uint32_t)(4 * d + blk), kPurposeDraw, request_id, seed_lo,
+                          seed_hi, w + 4 * blk);
+        const int32_t *sp = set_pt + (g * D + d) * k;
+        int8_t *sl = set_link + (g * D + d) * k;
+        for (int i = 0; i < k; ++i)
+            sl[i] = (int8_t)pick_link(H, bits, H.bin_c, pts, nrm, N, poses + 12 * g, i, sp[i], w[k + i]);
     }
 }
 
@@ -498,14 +792,19 @@ extern "C" {
 
 // workspace: [set chunks: count, offset] [pose chunks: count, offset]
 //            [valid pose list P] [n_valid_poses] [pose_valid P bytes]
+//            and, for the contact-point optimisation, [grid params]
+//            [cell counts/cursor (kGridMax+1)^3] [cell starts +1] [cell points N]
 struct SearchWs {
     uint32_t *chunk_count, *chunk_off, *pchunk_count, *pchunk_off;
     int32_t *valid_poses, *n_valid_poses;
     uint8_t *pose_valid;
+    GridDev *grid;
+    uint32_t *cell_count, *cell_start;
+    int32_t *cell_pts;
     size_t bytes;
 };
 
-static SearchWs search_ws(void *base, int64_t n_poses, int64_t draws)
+static SearchWs search_ws(void *base, int64_t n_points, int64_t n_poses, int64_t draws, bool opt)
 {
     const int64_t n_sets = n_poses * draws;
     const int64_t nc = (n_sets + kChunk - 1) / kChunk, npc = (n_poses + kChunk - 1) / kChunk;
@@ -518,14 +817,30 @@ static SearchWs search_ws(void *base, int64_t n_poses, int64_t draws)
     w.valid_poses = reinterpret_cast<int32_t *>(u + 2 * nc + 2 * npc);
     w.n_valid_poses = w.valid_poses + n_poses;
     w.pose_valid = reinterpret_cast<uint8_t *>(w.n_valid_poses + 1);
-    w.bytes = (size_t)(2 * nc + 2 * npc + n_poses + 1) * 4 + (size_t)n_poses + 256;
+    size_t off = ((size_t)(2 * nc + 2 * npc + n_poses + 1) * 4 + (size_t)n_poses + 255) & ~(size_t)255;
+    w.grid = nullptr;
+    w.cell_count = w.cell_start = nullptr;
+    w.cell_pts = nullptr;
+    if (opt) {
+        const int64_t ncell = (int64_t)(kGridMax + 1) * (kGridMax + 1) * (kGridMax + 1);
+        char *b = static_cast<char *>(base);
+        w.grid = reinterpret_cast<GridDev *>(b + off);
+        off += 256;
+        w.cell_count = reinterpret_cast<uint32_t *>(b + off);
+        off += (size_t)ncell * 4;
+        w.cell_start = reinterpret_cast<uint32_t *>(b + off);
+        off += (size_t)(ncell + 1) * 4;
+        w.cell_pts = reinterpret_cast<int32_t *>(b + off);
+        off += (size_t)n_points * 4;
+    }
+    w.bytes = off + 256;
     return w;
 }
 
-size_t lg_search_workspace_bytes(int32_t n_poses, const lg_search_params *p)
+size_t lg_search_workspace_bytes(int32_t n_points, int32_t n_poses, const lg_search_params *p)
 {
     if (!p || n_poses <= 0 || p->draws <= 0) return 256;
-    return search_ws(nullptr, n_poses, p->draws).bytes;
+    return search_ws(nullptr, std::max(n_points, 0), n_poses, p->draws, p->opt_outer > 0).bytes;
 }
 
 lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, int32_t n_points, const float *poses,
@@ -546,12 +861,16 @@ lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, i
     if (!pts || !nrm || !poses || !dom_bits || !dom_count || !set_pt || !set_link || !verdict || !tstar ||
         !acc_list || !n_acc || !workspace)
         return fail(LG_EINVAL, "null device buffer");
-    if (workspace_bytes < lg_search_workspace_bytes(n_poses, p)) return fail(LG_EINVAL, "workspace too small");
+    if (p->opt_outer < 0 || p->opt_outer > 64 || (p->opt_outer > 0 && (p->opt_inner < 1 || p->opt_inner > 16)) ||
+        !(p->opt_sigma >= 0.0f) || (int64_t)p->opt_outer * p->k * p->opt_inner >= (1 << 24))
+        return fail(LG_EINVAL, "need 0 <= opt_outer <= 64, 1 <= opt_inner <= 16, opt_sigma >= 0");
+    if (workspace_bytes < lg_search_workspace_bytes(n_points, n_poses, p)) return fail(LG_EINVAL, "workspace too small");
     const int NW = (n_points + 31) / 32, nsb = (NW + kSuper - 1) / kSuper;
     const size_t lds = (size_t)H.F * (nsb + 1) * sizeof(uint32_t);
     if (lds > 48 * 1024) return fail(LG_EUNSUPPORTED, "too many points for the draw rank structure");
     hipStream_t s = as_stream(stream);
-    const SearchWs ws = search_ws(workspace, n_poses, p->draws);
+    const bool opt = p->opt_outer > 0;
+    const SearchWs ws = search_ws(workspace, n_points, n_poses, p->draws, opt);
     hipLaunchKernelGGL(k_draw, dim3(n_poses), dim3(kDrawThreads), lds, s, H, field->d_bits, pts, nrm, n_points,
                        poses, dom_bits, dom_count, p->draws, p->k, (uint32_t)p->seed, (uint32_t)(p->seed >> 32),
                        p->request_id, p->pose_offset, set_pt, set_link, ws.pose_valid, verdict, tstar);
@@ -581,8 +900,40 @@ lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, i
     hipLaunchKernelGGL(k_verdict_lane<KM>, lgrid, dim3(256), 0, s, pts, nrm, n_points, set_pt, ws.valid_poses,   \
                        ws.n_valid_poses, p->draws, p->k, p->m_edges, (double)p->mu, (double)p->moment_scale,     \
                        (double)p->eps, p->max_pivots, cs, verdict, tstar)
-    if (p->k <= 3) LG_VERDICT(3); else if (p->k <= 4) LG_VERDICT(4); else if (p->k <= 5) LG_VERDICT(5);
-    else if (p->k <= 6) LG_VERDICT(6); else LG_VERDICT(8);
+    if (!opt) {
+        if (p->k <= 3) LG_VERDICT(3); else if (p->k <= 4) LG_VERDICT(4); else if (p->k <= 5) LG_VERDICT(5);
+        else if (p->k <= 6) LG_VERDICT(6); else LG_VERDICT(8);
+    } else {
+        // cell grid of the object, then Alg. 2 on the drawn sets, then the links of the moved contacts
+        const int64_t ncell = (int64_t)(kGridMax + 1) * (kGridMax + 1) * (kGridMax + 1);
+        hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(1024), 0, s, pts, n_points, p->opt_sigma, ws.grid);
+        LG_HIP(hipMemsetAsync(ws.cell_count, 0, (size_t)ncell * 4, s));
+        const unsigned pb = (unsigned)((n_points + 255) / 256);
+        hipLaunchKernelGGL(k_grid_count, dim3(pb), dim3(256), 0, s, pts, n_points, ws.grid, ws.cell_count);
+        hipLaunchKernelGGL(k_grid_scan, dim3(1), dim3(1024), 0, s, ws.cell_count, ws.grid, ws.cell_start);
+        hipLaunchKernelGGL(k_grid_scatter, dim3(pb), dim3(256), 0, s, pts, n_points, ws.grid, ws.cell_count,
+                           ws.cell_pts);
+        const int gs = p->opt_inner <= 1 ? 1 : p->opt_inner <= 2 ? 2 : p->opt_inner <= 4 ? 4 : p->opt_inner <= 8 ? 8 : 16;
+        const dim3 ogrid((unsigned)std::max<int64_t>(
+            1, std::min<int64_t>((n_sets * gs + 255) / 256, (int64_t)n_cu * 8)));
+#define LG_OPT(KM, GS)                                                                                           \
+    hipLaunchKernelGGL((k_optimize<KM, GS>), ogrid, dim3(256), 0, s, pts, nrm, n_points, ws.valid_poses,           \
+                       ws.n_valid_poses, dom_bits, H.F, p->draws, p->k, p->m_edges, (double)p->mu,                \
+                       (double)p->moment_scale, (double)p->eps, p->max_pivots, cs, p->opt_outer, p->opt_inner,    \
+                       (double)p->opt_sigma, (uint32_t)p->seed, (uint32_t)(p->seed >> 32), p->request_id,         \
+                       p->pose_offset, ws.grid, ws.cell_start, ws.cell_pts, set_pt, verdict, tstar)
+#define LG_OPT_K(GS)                                                                                             \
+    if (p->k <= 3) LG_OPT(3, GS); else if (p->k <= 4) LG_OPT(4, GS); else if (p->k <= 5) LG_OPT(5, GS);        \
+    else if (p->k <= 6) LG_OPT(6, GS); else LG_OPT(8, GS)
+        if (gs == 1) { LG_OPT_K(1); } else if (gs == 2) { LG_OPT_K(2); } else if (gs == 4) { LG_OPT_K(4); }
+        else if (gs == 8) { LG_OPT_K(8); } else { LG_OPT_K(16); }
+#undef LG_OPT_K
+#undef LG_OPT
+        LG_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_relink, lgrid, dim3(256), 0, s, H, field->d_bits, pts, nrm, n_points, poses,
+                           ws.valid_poses, ws.n_valid_poses, p->draws, p->k, (uint32_t)p->seed,
+                           (uint32_t)(p->seed >> 32), p->request_id, p->pose_offset, set_pt, set_link);
+    }
 #undef LG_VERDICT
     LG_HIP(hipGetLastError());
     const int64_t n_chunks = (n_sets + kChunk - 1) / kChunk;

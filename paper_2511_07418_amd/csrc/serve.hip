@@ -156,7 +156,7 @@ static ReqLayout layout_of(const lg_server_params &sp, const lg_request &r)
     L.acc = take(4 * (uint64_t)sets);
     L.n_acc = take(4);
     lg_search_params p = r.search;
-    L.ws = take(lg_search_workspace_bytes((int32_t)chunk, &p));
+    L.ws = take(lg_search_workspace_bytes((int32_t)N, (int32_t)chunk, &p));
     const int64_t ra = r.realize ? sets : 0;
     L.q = take(4 * (uint64_t)(ra * J));
     L.err = take(4 * (uint64_t)(ra * k));

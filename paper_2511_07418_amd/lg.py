@@ -57,7 +57,8 @@ class SearchParams(C.Structure):
     _fields_ = [("draws", C.c_int32), ("k", C.c_int32), ("m_edges", C.c_int32),
                 ("max_pivots", C.c_int32), ("mu", C.c_float), ("eps", C.c_float),
                 ("moment_scale", C.c_float), ("seed", C.c_uint64), ("request_id", C.c_uint32),
-                ("pose_offset", C.c_int64)]
+                ("pose_offset", C.c_int64), ("opt_outer", C.c_int32), ("opt_inner", C.c_int32),
+                ("opt_sigma", C.c_float)]
 
 
 class IkParams(C.Structure):
@@ -112,7 +113,7 @@ def _load():
     L.lg_field_info.argtypes = [vp, vp]
     L.lg_field_release.argtypes = [vp]
     L.lg_query_domains.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp]
-    L.lg_search_workspace_bytes.argtypes = [i32, vp]
+    L.lg_search_workspace_bytes.argtypes = [i32, i32, vp]
     L.lg_search_workspace_bytes.restype = sz
     L.lg_search.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.lg_realize.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, i32, i32, vp, vp, i32, vp,
@@ -288,13 +289,14 @@ def lg_query_domains(field: Field, pts: torch.Tensor, nrm: torch.Tensor, poses: 
 def search_params(sp, max_pivots: int = 1000) -> SearchParams:
     return SearchParams(int(sp.draws), int(sp.k), int(sp.m_edges), int(max_pivots), float(sp.mu),
                         float(sp.eps), float(sp.moment_scale), int(sp.seed) & 0xFFFFFFFFFFFFFFFF,
-                        int(sp.request_id), int(sp.pose_offset))
+                        int(sp.request_id), int(sp.pose_offset), int(getattr(sp, "opt_outer", 0)),
+                        int(getattr(sp, "opt_inner", 8)), float(getattr(sp, "opt_sigma", 0.004)))
 
 
 class SearchBuffers:
     """Device outputs + workspace of lg_search for P poses (reusable)."""
 
-    def __init__(self, n_poses: int, sp, device, max_pivots: int = 1000):
+    def __init__(self, n_poses: int, sp, device, max_pivots: int = 1000, n_points: int = 0):
         self.p = search_params(sp, max_pivots)
         P, D, k = n_poses, int(sp.draws), int(sp.k)
         self.set_pt = torch.empty((P, D, k), dtype=torch.int32, device=device)
@@ -303,7 +305,7 @@ class SearchBuffers:
         self.tstar = torch.empty((P, D), dtype=torch.float64, device=device)
         self.acc_list = torch.empty((P * D,), dtype=torch.int32, device=device)
         self.n_acc = torch.zeros((1,), dtype=torch.int32, device=device)
-        nb = int(_lib.lg_search_workspace_bytes(P, C.byref(self.p)))
+        nb = int(_lib.lg_search_workspace_bytes(int(n_points), P, C.byref(self.p)))
         self.workspace = torch.empty((nb,), dtype=torch.uint8, device=device)
 
 
@@ -311,7 +313,7 @@ def lg_search(field: Field, pts, nrm, poses, dom_bits, dom_count, sp, bufs: Opti
               max_pivots: int = 1000, stream=None) -> SearchBuffers:
     N, P = int(pts.shape[1]), int(poses.shape[0])
     if bufs is None:
-        bufs = SearchBuffers(P, sp, pts.device, max_pivots)
+        bufs = SearchBuffers(P, sp, pts.device, max_pivots, n_points=N)
     _check(_lib.lg_search(field.handle, _ptr(pts), _ptr(nrm), N, _ptr(poses), P, _ptr(dom_bits),
                           _ptr(dom_count), C.byref(bufs.p), _ptr(bufs.set_pt), _ptr(bufs.set_link),
                           _ptr(bufs.verdict), _ptr(bufs.tstar), _ptr(bufs.acc_list), _ptr(bufs.n_acc),

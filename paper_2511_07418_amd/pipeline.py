@@ -34,7 +34,7 @@ class Pipeline:
         NW = (self.N + 31) // 32
         self.dom_bits = torch.empty((self.P, F, NW), dtype=torch.int32, device=self.dev)
         self.dom_count = torch.empty((self.P, F), dtype=torch.int32, device=self.dev)
-        self.sbuf = lg.SearchBuffers(self.P, sp, self.dev, max_pivots)
+        self.sbuf = lg.SearchBuffers(self.P, sp, self.dev, max_pivots, n_points=self.N)
         self.ik = ik
         self.rbuf = None
         if ik is not None:

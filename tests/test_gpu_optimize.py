@@ -1,0 +1,101 @@
+"""GPU parity of the contact-point optimisation (Sec. 5.4, Alg. 2) inside
+lg_search against the oracle's ``optimize`` + ``relink``, through the C ABI.
+
+Stage-isolated like the other search tests: the oracle's field and domains
+are fed to the GPU.  Bars: for every set the oracle does not flag (a
+projection whose runner-up domain point is within 1e-7 m, or a candidate
+criterion value within 1e-10 of the tie threshold), the optimised point
+indices are identical and t* agrees to 1e-9; verdicts are identical outside
+|t* - eps| <= 1e-6; links follow the draw bar (<= 1e-4 of entries, from
+voxel/bin rounding bands).  Flagged sets are counted (a decision chain of
+n_outer * k * n_inner projections per set makes them a few percent).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.test_gpu_parity import dev, lgmod, soa
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _opt_check(w, sp, max_flag_frac=0.08):
+    lg = lgmod()
+    ref = oracle.build_field(w.hand, w.field, flags=False)
+    Q = oracle.query(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses, flags=False)
+    field = lg.lg_field_import(w.hand, w.field, ref["bits"])
+    bufs = lg.lg_search(field, soa(w.obj.pts), soa(w.obj.nrm), dev(w.poses), dev(Q["dom_bits"].view(np.int32)),
+                        dev(Q["dom_count"].view(np.int32)), sp)
+    torch.cuda.synchronize()
+    spt = bufs.set_pt.cpu().numpy()
+    sln = bufs.set_link.cpu().numpy().astype(np.int32)
+    ver = bufs.verdict.cpu().numpy().reshape(-1)
+    tst = bufs.tstar.cpu().numpy().reshape(-1)
+    acc = bufs.acc_list[:int(bufs.n_acc.item())].cpu().numpy()
+    d_spt, _ = oracle.draw(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses, Q["dom_bits"],
+                           Q["dom_count"], sp)
+    O = oracle.optimize(w.obj.pts, w.obj.nrm, Q["dom_bits"], d_spt, sp, w.hand.n_fingers)
+    o_sln = oracle.relink(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses, O["set_pt"], sp)
+    P, D, k = spt.shape
+    valid = (d_spt >= 0).all(-1).reshape(-1)
+    flag = O["oflag"].astype(bool)
+    assert flag.sum() <= max_flag_frac * max(1, valid.sum()), (flag.sum(), valid.sum())
+    ok = valid & ~flag
+    assert ok.sum() > 0
+    same = (spt.reshape(-1, k) == O["set_pt"].reshape(-1, k)).all(-1)
+    assert same[ok].all(), f"{(~same[ok]).sum()} unflagged sets differ"
+    assert np.allclose(tst[ok], O["tstar"][ok], atol=1e-9, rtol=0)
+    vf = O["vflag"].astype(bool)
+    assert ((ver != O["verdict"]) & ok & ~vf).sum() == 0
+    assert (spt.reshape(-1, k)[~valid] == -1).all() and np.isnan(tst[~valid]).all()
+    mis = (sln.reshape(-1, k) != o_sln.reshape(-1, k))[ok]
+    assert mis.sum() <= max(1, 1e-4 * mis.size)
+    assert (acc == np.flatnonzero(ver)).all()
+    return O, ver, d_spt
+
+
+def test_optimize_c1_full():
+    w = synth.workload("c1")
+    sp = dataclasses.replace(w.search, opt_outer=2, opt_inner=8, opt_sigma=0.004)
+    O, ver, d_spt = _opt_check(w, sp)
+    V0 = oracle.verdicts(w.obj.pts, w.obj.nrm, d_spt, w.search)
+    assert ver.sum() > V0["verdict"].sum()          # the optimisation raises acceptance
+
+
+@pytest.mark.parametrize("inner", [1, 3, 16])
+def test_optimize_group_sizes(inner):
+    w = synth.workload("c1", n_poses=96)
+    sp = dataclasses.replace(w.search, opt_outer=1, opt_inner=inner, opt_sigma=0.006, request_id=inner)
+    _opt_check(w, sp)
+
+
+def test_optimize_c2_shape():
+    w = synth.workload("c2", samples=4096, n_poses=48, n_points=4096)
+    sp = dataclasses.replace(w.search, opt_outer=1, opt_inner=8, opt_sigma=0.004)
+    _opt_check(w, sp)
+
+
+def test_vanishing_step_gives_the_draws():
+    lg = lgmod()
+    w = synth.workload("c1", n_poses=64)
+    ref = oracle.build_field(w.hand, w.field, flags=False)
+    Q = oracle.query(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses, flags=False)
+    field = lg.lg_field_import(w.hand, w.field, ref["bits"])
+    args = (field, soa(w.obj.pts), soa(w.obj.nrm), dev(w.poses), dev(Q["dom_bits"].view(np.int32)),
+            dev(Q["dom_count"].view(np.int32)))
+    a = lg.lg_search(*args, w.search)
+    b = lg.lg_search(*args, dataclasses.replace(w.search, opt_outer=2, opt_sigma=1e-9))
+    torch.cuda.synchronize()
+    assert torch.equal(a.set_pt, b.set_pt) and torch.equal(a.set_link, b.set_link)
+    assert torch.equal(a.verdict, b.verdict)
