@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--cpu-poses", type=int, default=0, help="poses of the CPU-oracle sample (0 = auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving run (req/s)")
-    ap.add_argument("--serve-rates", default="5,20,50,100", help="serve mode: comma-separated arrival rates")
+    ap.add_argument("--serve-rates", default="5,20,50,100,400", help="serve mode: comma-separated arrival rates")
     ap.add_argument("--serve-seconds", type=float, default=6.0, help="arrival window of the serving run (s)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--opt-outer", type=int, default=0,

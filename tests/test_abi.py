@@ -64,3 +64,39 @@ def test_validation_rejects_bad_calls_without_device_work(lglib):
     bad.joint_parent[2] = 0
     with pytest.raises(lglib.LgError):
         lglib.lg_build_field(bad, w.field)
+
+
+def test_proposer_validation_rejects_bad_calls_without_device_work(lglib):
+    L = lglib.lib()
+    EINVAL = lglib.LG_EINVAL
+    assert L.lg_prop_num_params() == 204568
+    bad = lglib.PropParams(0, 2048, 16, 0)          # max_batch < 1
+    out = C.c_void_p()
+    assert L.lg_prop_create(C.byref(bad), None, C.byref(out)) == EINVAL and not out.value
+    assert L.lg_prop_create(None, None, C.byref(out)) == EINVAL
+    assert L.lg_prop_forward(None, None, 1, 1, None, None, None, None) == EINVAL
+    assert L.lg_prop_backward(None, None, 1, 1, None, None, 1, None, None, None) == EINVAL
+    assert L.lg_prop_adam(None, 1e-3, 0.9, 0.999, 1e-8, None) == EINVAL
+    assert L.lg_prop_train_step(None, None, 1, 1, None, None, 1, 1e-3, None, None) == EINVAL
+    assert L.lg_prop_sample(None, None, 1, 1, 0, 0.5, 0.08, 0.12, None, None) == EINVAL
+    assert L.lg_prop_get_params(None, None) == EINVAL and L.lg_prop_set_params(None, None) == EINVAL
+    # sampler arguments: negative count, fraction outside [0, 1], d_lo > d_hi, null buffers
+    assert L.lg_prop_sample_mixture(None, -1, 0, 0.5, 0.08, 0.12, None, None) == EINVAL
+    assert L.lg_prop_sample_mixture(None, 0, 0, 0.5, 0.08, 0.12, None, None) == lglib.LG_OK
+    assert L.lg_prop_sample_mixture(None, 4, 0, 0.5, 0.08, 0.12, None, None) == EINVAL
+    dummy = C.c_void_p(1)
+    assert L.lg_prop_sample_mixture(dummy, 4, 0, 1.5, 0.08, 0.12, dummy, None) == EINVAL
+    assert L.lg_prop_sample_mixture(dummy, 4, 0, 0.5, 0.12, 0.08, dummy, None) == EINVAL
+    assert b"d_lo" in L.lg_last_error()
+    assert L.lg_prop_release(None) == lglib.LG_OK
+
+
+def test_search_workspace_grows_with_the_optimisation(lglib):
+    w = synth.workload("c1", n_poses=4)
+    p0 = lglib.search_params(w.search)
+    import dataclasses
+    p1 = lglib.search_params(dataclasses.replace(w.search, opt_outer=1))
+    L = lglib.lib()
+    b0 = L.lg_search_workspace_bytes(2048, 256, C.byref(p0))
+    b1 = L.lg_search_workspace_bytes(2048, 256, C.byref(p1))
+    assert b1 >= b0 + 2048 * 4 and L.lg_search_workspace_bytes(2048, 0, C.byref(p1)) == 256

@@ -99,3 +99,17 @@ def test_vanishing_step_gives_the_draws():
     torch.cuda.synchronize()
     assert torch.equal(a.set_pt, b.set_pt) and torch.equal(a.set_link, b.set_link)
     assert torch.equal(a.verdict, b.verdict)
+
+
+@pytest.mark.parametrize("bad", [{"opt_outer": -1}, {"opt_outer": 1, "opt_inner": 0}, {"opt_outer": 1, "opt_inner": 17},
+                                 {"opt_outer": 1, "opt_sigma": -1.0}])
+def test_invalid_optimisation_parameters(bad):
+    lg = lgmod()
+    w = synth.workload("c1", n_poses=8)
+    ref = oracle.build_field(w.hand, w.field, flags=False)
+    Q = oracle.query(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses, flags=False)
+    field = lg.lg_field_import(w.hand, w.field, ref["bits"])
+    with pytest.raises(lg.LgError) as ei:
+        lg.lg_search(field, soa(w.obj.pts), soa(w.obj.nrm), dev(w.poses), dev(Q["dom_bits"].view(np.int32)),
+                     dev(Q["dom_count"].view(np.int32)), dataclasses.replace(w.search, **bad))
+    assert ei.value.status == lg.LG_EINVAL
