@@ -42,45 +42,61 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
     uint32_t c[FM];
 #pragma unroll
     for (int f = 0; f < FM; ++f) c[f] = 0;
-    for (int chunk = wave; chunk < nchunks; chunk += kQueryWaves) {
-        // re-read the per-finger maps from LDS every chunk instead of pinning
-        // 12 x F registers for them: halves the register footprint
-        asm volatile("" ::: "memory");
-        const int i = chunk * 64 + lane;
-        const bool valid = i < N;
-        float px = 0.f, py = 0.f, pz = 0.f, nx = 0.f, ny = 0.f, nz = 1.f;
-        if (valid) {
-            px = pts[i];
-            py = pts[N + i];
-            pz = pts[2 * N + i];
-            nx = nrm[i];
-            ny = nrm[N + i];
-            nz = nrm[2 * N + i];
-        }
-        float qx, qy, qz;
-        query_dir(P, nx, ny, nz, qx, qy, qz);
-        const int b = nearest_bin_lut(lut, cb, B, qx, qy, qz);
-        // one 32-bit word per finger: the word of the table that holds bit b;
-        // all finger gathers are issued before any is consumed
-        uint32_t word[FM];
+    // Waves take blocks of 32 consecutive chunks (2,048 points, a compact
+    // patch of the Morton-ordered object) in turn.  The 64 ballot words of a
+    // block stay in registers, lane 2j / 2j+1 holding chunk j's halves, and
+    // leave as one coalesced 256-byte store per finger.
+    const int nblk = (nchunks + 31) >> 5;
+    for (int blk = wave; blk < nblk; blk += kQueryWaves) {
+        uint32_t acc[FM];
 #pragma unroll
-        for (int f = 0; f < FM; ++f) {
-            word[f] = 0;
-            if (f < F) {
-                const int v = window_voxel(aff[f], G, px, py, pz);
-                const uint32_t *tab = merged + f * G3W;  // uniform base, 32-bit lane offsets
-                if (valid && v >= 0) word[f] = tab[(uint32_t)v * W + (uint32_t)(b >> 5)];
+        for (int f = 0; f < FM; ++f) acc[f] = 0;
+        const int c_end = min(nchunks, (blk + 1) * 32);
+        for (int chunk = blk * 32; chunk < c_end; ++chunk) {
+            // re-read the per-finger maps from LDS every chunk instead of pinning
+            // 12 x F registers for them: halves the register footprint
+            asm volatile("" ::: "memory");
+            const int i = chunk * 64 + lane;
+            const bool valid = i < N;
+            float px = 0.f, py = 0.f, pz = 0.f, nx = 0.f, ny = 0.f, nz = 1.f;
+            if (valid) {
+                px = pts[i];
+                py = pts[N + i];
+                pz = pts[2 * N + i];
+                nx = nrm[i];
+                ny = nrm[N + i];
+                nz = nrm[2 * N + i];
+            }
+            float qx, qy, qz;
+            query_dir(P, nx, ny, nz, qx, qy, qz);
+            const int b = nearest_bin_lut(lut, cb, B, qx, qy, qz);
+            // one 32-bit word per finger: the word of the table that holds bit b;
+            // all finger gathers are issued before any is consumed
+            uint32_t word[FM];
+#pragma unroll
+            for (int f = 0; f < FM; ++f) {
+                word[f] = 0;
+                if (f < F) {
+                    const int v = window_voxel(aff[f], G, px, py, pz);
+                    const uint32_t *tab = merged + f * G3W;  // uniform base, 32-bit lane offsets
+                    if (valid && v >= 0) word[f] = tab[(uint32_t)v * W + (uint32_t)(b >> 5)];
+                }
+            }
+            const int j2 = 2 * (chunk - blk * 32);
+#pragma unroll
+            for (int f = 0; f < FM; ++f) {
+                if (f >= F) break;
+                const bool hit = (word[f] >> (b & 31)) & 1u;
+                const unsigned long long m = __ballot(hit);
+                c[f] += (uint32_t)__popcll(m);
+                acc[f] = lane == j2 ? (uint32_t)m : lane == j2 + 1 ? (uint32_t)(m >> 32) : acc[f];
             }
         }
+        const int wi = blk * 64 + lane;
+        if (wi < NW) {
 #pragma unroll
-        for (int f = 0; f < FM; ++f) {
-            if (f >= F) break;
-            const bool hit = (word[f] >> (b & 31)) & 1u;
-            const unsigned long long m = __ballot(hit);
-            c[f] += (uint32_t)__popcll(m);
-            const int wi = 2 * chunk + lane;
-            if (lane < 2 && wi < NW)
-                dom_bits[((int64_t)g * F + f) * NW + wi] = lane == 0 ? (uint32_t)m : (uint32_t)(m >> 32);
+            for (int f = 0; f < FM; ++f)
+                if (f < F) dom_bits[((int64_t)g * F + f) * NW + wi] = acc[f];
         }
     }
     if (lane == 0) {
