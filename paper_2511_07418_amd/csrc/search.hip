@@ -608,7 +608,7 @@ __device__ int project_domain(const GridDev &g, const uint32_t *__restrict__ cel
 // GS lanes per set (GS >= n_inner, a power of two): lane j evaluates candidate
 // j of every step; the group agrees on the pick by shuffles and one ballot.
 template <int KM, int GS>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, const int32_t *__restrict__ valid_poses,
            const int32_t *__restrict__ n_valid_poses, const uint32_t *__restrict__ dom_bits, int F, int D, int k, int m,
            double mu, double rho, double eps, int max_pivots, LpConst cs, int n_outer, int n_inner, double sigma,
@@ -618,6 +618,7 @@ k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, 
            double *__restrict__ tstar)
 {
     __shared__ float cd[KM * 6][256];
+    __shared__ int cur[KM][256];  // the set's current point indices (every lane of a group holds them)
     const int tid = threadIdx.x, lane = tid & 63, j = tid % GS, gbase = lane - j;
     const GridDev g = *gdp;
     const int NW = (N + 31) >> 5;
@@ -636,10 +637,9 @@ k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, 
         const int d = (int)(t % D);
         const int64_t sid = pg * D + d;
         int32_t *sp = set_pt + sid * k;
-        int cur[KM];
         for (int i = 0; i < k; ++i) {
-            cur[i] = sp[i];
-            load(i, cur[i]);
+            cur[i][tid] = sp[i];
+            load(i, sp[i]);
         }
         double J = INFINITY;
         for (int r = 0; r < n_outer; ++r) {
@@ -676,13 +676,13 @@ k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, 
                 const double Jp = __shfl(Jc, gbase + js, 64);
                 if (pick >= 0) {
                     J = Jp;
-                    cur[i] = pick;
+                    cur[i][tid] = pick;
                 }
-                load(i, cur[i]);
+                load(i, cur[i][tid]);
             }
         }
         if (j == 0) {
-            for (int i = 0; i < k; ++i) sp[i] = cur[i];
+            for (int i = 0; i < k; ++i) sp[i] = cur[i][tid];
             verdict[sid] = J <= eps ? 1 : 0;
             tstar[sid] = isinf(J) ? __builtin_nan("") : J;
         }
