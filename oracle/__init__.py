@@ -22,7 +22,8 @@ Each function cites the passage of the paper it follows (arXiv 2511.07418):
 * ``relink``           the reverse lookup of Sec. 5.5 for optimised sets
 * ``compact``          accepted sets in pose-major, draw-minor order
 * ``realize``          Sec. 5.5 Eq. 7-8 (DLS IK with Phase-II projection) and
-                       the penetration criterion of Sec. 3.2
+                       the penetration criterion of Sec. 3.2, optionally with the
+                       hand self-collision filter of Sec. 5.6 (``self_penetration``)
 
 Readings where the paper is silent are listed in the design doc.
 """
@@ -68,7 +69,8 @@ class _FieldParams(C.Structure):
 
 class _IK(C.Structure):
     _fields_ = [("iters", C.c_int32), ("phase1", C.c_int32), ("lam", C.c_double), ("beta", C.c_double),
-                ("tol_pos", C.c_double), ("tol_ang", C.c_double), ("margin", C.c_double)]
+                ("tol_pos", C.c_double), ("tol_ang", C.c_double), ("margin", C.c_double),
+                ("self_collision", C.c_int32)]
 
 
 class _SDF(C.Structure):
@@ -113,6 +115,10 @@ def lib():
         L.orc_optimize.restype = C.c_int
         L.orc_relink.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, i32, vp, u64, C.c_uint32, i64, vp]
         L.orc_relink.restype = C.c_int
+        L.orc_segment_distance.argtypes = [vp, vp, vp, vp]
+        L.orc_segment_distance.restype = dbl
+        L.orc_self_penetration.argtypes = [vp, vp]
+        L.orc_self_penetration.restype = dbl
         L.orc_ik_finger.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_point_jacobian.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp]
         L.orc_sdf_eval.argtypes = [vp, vp]
@@ -172,7 +178,7 @@ def _sdf(sdf) -> _Keep:
 
 def _ik(ik) -> _IK:
     return _IK(int(ik.iters), int(ik.phase1), float(ik.lam), float(ik.beta), float(ik.tol_pos),
-               float(ik.tol_ang), float(ik.margin))
+               float(ik.tol_ang), float(ik.margin), int(getattr(ik, "self_collision", 0)))
 
 
 # ---------------------------------------------------------------------------
@@ -404,6 +410,19 @@ def point_jacobian(hand, f: int, link: int, q, x) -> np.ndarray:
     Jm = np.zeros((3, hand.dof[f]), np.float64)
     lib().orc_point_jacobian(H.ref, f, link, _p(T), _p(xx), _p(Jm))
     return Jm
+
+
+def segment_distance(p1, q1, p2, q2) -> float:
+    """Distance between segments [p1, q1] and [p2, q2] (closed form)."""
+    a = [_c(v, np.float64) for v in (p1, q1, p2, q2)]
+    return float(lib().orc_segment_distance(*[_p(v) for v in a]))
+
+
+def self_penetration(hand, q) -> float:
+    """Deepest penetration between capsules of different fingers at joint vector q (Sec. 5.6)."""
+    T = fk(hand, q)
+    H = _hand(hand)
+    return float(lib().orc_self_penetration(H.ref, _p(_c(T, np.float64))))
 
 
 def sdf_eval(sdf, y) -> float:

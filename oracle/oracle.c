@@ -1216,6 +1216,7 @@ typedef struct {
     double tol_pos;
     double tol_ang;
     double margin;
+    int32_t self_collision; /* also require no hand self-penetration deeper than margin */
 } orc_ik_params;
 
 /* One finger's IK towards one contact.  q_f in/out (finger joints).       */
@@ -1359,6 +1360,70 @@ double orc_penetration(const orc_hand *H, const double *T, const orc_sdf *S, con
 
 /* Realise accepted sets: witness seed, IK per finger, penetration, acceptance.
  * wit [L][G^3][B] may be NULL (then q0 = mid-limits).                        */
+/* ------------------------------------------------------------------------ */
+/* Hand self-collision (Sec. 5.6 postprocessing: hand-to-hand collisions),    */
+/* for capsule links in closed form: the distance between two axis segments   */
+/* is minimised over (s, t) in [0,1]^2 (Ericson, Real-Time Collision          */
+/* Detection, Sec. 5.1.9); two capsules of different fingers penetrate by     */
+/* r1 + r2 - dist.  Links of one finger are excluded (consecutive links meet  */
+/* at their joints).                                                          */
+/* ------------------------------------------------------------------------ */
+double orc_segment_distance(const double *p1, const double *q1, const double *p2, const double *q2)
+{
+    double d1[3], d2[3], r[3];
+    for (int c = 0; c < 3; ++c) {
+        d1[c] = q1[c] - p1[c];
+        d2[c] = q2[c] - p2[c];
+        r[c] = p1[c] - p2[c];
+    }
+    const double a = dot3(d1, d1), e = dot3(d2, d2), f = dot3(d2, r);
+    double s, t;
+    if (a <= 1e-30 && e <= 1e-30) {
+        s = t = 0.0;
+    } else if (a <= 1e-30) {
+        s = 0.0;
+        t = fmin(fmax(f / e, 0.0), 1.0);
+    } else {
+        const double c = dot3(d1, r);
+        if (e <= 1e-30) {
+            t = 0.0;
+            s = fmin(fmax(-c / a, 0.0), 1.0);
+        } else {
+            const double b = dot3(d1, d2), den = a * e - b * b;
+            s = den > 0.0 ? fmin(fmax((b * f - c * e) / den, 0.0), 1.0) : 0.0;
+            t = (b * s + f) / e;
+            if (t < 0.0) {
+                t = 0.0;
+                s = fmin(fmax(-c / a, 0.0), 1.0);
+            } else if (t > 1.0) {
+                t = 1.0;
+                s = fmin(fmax((b - c) / a, 0.0), 1.0);
+            }
+        }
+    }
+    double dd = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        const double x = p1[c] + s * d1[c] - (p2[c] + t * d2[c]);
+        dd += x * x;
+    }
+    return sqrt(dd);
+}
+
+/* deepest penetration between capsules of different fingers (-inf if none) */
+double orc_self_penetration(const orc_hand *H, const double *T /*[J][12]*/)
+{
+    double worst = -INFINITY;
+    for (int l1 = 0; l1 < H->n_joints; ++l1)
+        for (int l2 = l1 + 1; l2 < H->n_joints; ++l2) {
+            if (H->joint_finger[l1] == H->joint_finger[l2]) continue;
+            double A1[3], B1[3], r1, A2[3], B2[3], r2;
+            capsule_world(H, T, l1, A1, B1, &r1);
+            capsule_world(H, T, l2, A2, B2, &r2);
+            worst = fmax(worst, r1 + r2 - orc_segment_distance(A1, B1, A2, B2));
+        }
+    return worst;
+}
+
 int orc_realize(const orc_hand *H, const orc_field_params *fp, const int32_t *wit,
                 const orc_sdf *S, const float *pts, const float *nrm, const float *poses,
                 const int32_t *set_pt, const int32_t *set_link, int32_t k, int32_t draws,
@@ -1423,6 +1488,7 @@ int orc_realize(const orc_hand *H, const orc_field_params *fp, const int32_t *wi
         double *T = (double *)malloc(sizeof(double) * 12 * J);
         orc_fk(H, q, T);
         double dp = orc_penetration(H, T, S, pose);
+        if (ik->self_collision) dp = fmax(dp, orc_self_penetration(H, T));
         free(T);
         depth[a] = dp;
         fl |= fabs(dp - ik->margin) <= BAND_VAL;

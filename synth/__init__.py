@@ -660,6 +660,7 @@ class IKParams:
     tol_pos: float = 0.002
     tol_ang: float = 0.35
     margin: float = 0.002
+    self_collision: int = 0   # also reject grasps whose links of different fingers penetrate
 
 
 @dataclass
