@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--opt-outer", type=int, default=0,
                     help="rounds of contact-point optimisation (Alg. 2) before the verdicts; 0 = the plain method")
     ap.add_argument("--opt-inner", type=int, default=8)
+    ap.add_argument("--self-collision", action="store_true",
+                    help="also reject grasps whose links of different fingers penetrate")
     ap.add_argument("--opt-sigma", type=float, default=0.004)
     ap.add_argument("--train-objects", type=int, default=2000, help="proposer: training objects (seeds 0..n-1)")
     ap.add_argument("--eval-objects", type=int, default=200, help="proposer: held-out objects (seeds 100000..)")
@@ -395,6 +397,9 @@ def main():
             print(json.dumps({"serving": serve_bench(torch, lg, rate, args.serve_seconds, args.seed)}), flush=True)
         return
     w = synth.workload(args.workload, seed=args.seed, with_sdf=(args.workload == "c3"))
+    if args.self_collision and w.ik is not None:
+        import dataclasses
+        w.ik = dataclasses.replace(w.ik, self_collision=1)
     if args.opt_outer > 0:
         import dataclasses
         w.search = dataclasses.replace(w.search, opt_outer=args.opt_outer, opt_inner=args.opt_inner,
@@ -484,7 +489,8 @@ def main():
         "config": {"workload": f"{args.workload}: {DESCR[args.workload]}", "poses_per_step": pipe.P,
                    "points": pipe.N, "draws": int(w.search.draws), "seed": args.seed,
                    "contact_opt": ({"rounds": args.opt_outer, "candidates": args.opt_inner,
-                                    "sigma_m": args.opt_sigma} if args.opt_outer > 0 else None)},
+                                    "sigma_m": args.opt_sigma} if args.opt_outer > 0 else None),
+                   "self_collision": bool(args.self_collision)},
         "valid_per_step": n_valid,
         "accepted_sets_per_step": n_acc,
         "stage_ms": {"query": q_ms, "search": float(st[:, 1].mean()), "realize": float(st[:, 2].mean())},

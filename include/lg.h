@@ -212,6 +212,8 @@ typedef struct {
     float tol_pos;    /* acceptance: contact error <= tol_pos (m) */
     float tol_ang;    /* acceptance: normal angle <= tol_ang (rad) */
     float margin;     /* acceptance: penetration depth <= margin (m) */
+    int32_t self_collision; /* 1: depth also covers capsules of different fingers (Sec. 5.6
+                               hand-to-hand check, closed-form segment distance); 0: object only */
 } lg_ik_params;
 
 /* Object signed-distance grid (object frame). */

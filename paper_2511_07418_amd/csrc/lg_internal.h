@@ -22,7 +22,7 @@ constexpr int kMaxBins = 64;
 constexpr uint32_t kPurposeJoint = 1u;
 constexpr uint32_t kPurposeDraw = 3u;
 constexpr int32_t kNoWitness = 0x7fffffff;
-constexpr int kLutRes = 32;  // cube-map cells per face edge of the bin table
+constexpr int kLutRes = 28;  // cube-map cells per face edge of the bin table (18.4 KiB in LDS)
 
 // Device-side description of a hand and its field window (kernel argument).
 struct DevHand {

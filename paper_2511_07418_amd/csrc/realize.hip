@@ -25,7 +25,46 @@ struct SdfDev {
 struct IkDev {
     int iters, phase1;
     float lambda, beta, tol_pos, tol_ang, margin;
+    int self_collision;
 };
+
+// distance between segments [p1, q1] and [p2, q2]: the closest parameters
+// (s, t) in [0,1]^2 in closed form (Ericson, Real-Time Collision Detection,
+// Sec. 5.1.9)
+__device__ inline float segment_distance(const float *p1, const float *q1, const float *p2, const float *q2)
+{
+    const float d1x = q1[0] - p1[0], d1y = q1[1] - p1[1], d1z = q1[2] - p1[2];
+    const float d2x = q2[0] - p2[0], d2y = q2[1] - p2[1], d2z = q2[2] - p2[2];
+    const float rx = p1[0] - p2[0], ry = p1[1] - p2[1], rz = p1[2] - p2[2];
+    const float a = d1x * d1x + d1y * d1y + d1z * d1z, e = d2x * d2x + d2y * d2y + d2z * d2z;
+    const float f = d2x * rx + d2y * ry + d2z * rz;
+    float s, t;
+    if (a <= 1e-20f && e <= 1e-20f) {
+        s = t = 0.0f;
+    } else if (a <= 1e-20f) {
+        s = 0.0f;
+        t = fminf(fmaxf(f / e, 0.0f), 1.0f);
+    } else {
+        const float c = d1x * rx + d1y * ry + d1z * rz;
+        if (e <= 1e-20f) {
+            t = 0.0f;
+            s = fminf(fmaxf(-c / a, 0.0f), 1.0f);
+        } else {
+            const float b = d1x * d2x + d1y * d2y + d1z * d2z, den = a * e - b * b;
+            s = den > 0.0f ? fminf(fmaxf((b * f - c * e) / den, 0.0f), 1.0f) : 0.0f;
+            t = (b * s + f) / e;
+            if (t < 0.0f) {
+                t = 0.0f;
+                s = fminf(fmaxf(-c / a, 0.0f), 1.0f);
+            } else if (t > 1.0f) {
+                t = 1.0f;
+                s = fminf(fmaxf((b - c) / a, 0.0f), 1.0f);
+            }
+        }
+    }
+    const float x = rx + s * d1x - t * d2x, y = ry + s * d1y - t * d2y, z = rz + s * d1z - t * d2z;
+    return sqrtf(x * x + y * y + z * z);
+}
 
 __device__ inline float dot3f(float ax, float ay, float az, float bx, float by, float bz)
 {
@@ -166,10 +205,13 @@ k_realize(DevHand H, const int32_t *__restrict__ wit, SdfDev S, const float *__r
           uint8_t *__restrict__ valid_out)
 {
     __shared__ float cb[3 * kMaxBins];
+    // capsule axis end points of every lane's finger at its final configuration
+    __shared__ float caps[kRealizeThreads][DM][6];
     for (int i = threadIdx.x; i < 3 * H.B; i += blockDim.x) cb[i] = H.bin_c[i];
     __syncthreads();
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int f = (int)(gt & 7);
+    const int tid = threadIdx.x, base = tid & ~7;
     const int64_t nacc = min((int64_t)*n_acc_dev, (int64_t)max_acc);
     const int64_t stride = ((int64_t)gridDim.x * blockDim.x) >> 3;
     // grid-stride over accepted sets; the 8 lanes of a set move together
@@ -331,6 +373,12 @@ k_realize(DevHand H, const int32_t *__restrict__ wit, SdfDev S, const float *__r
                     float A[3], Bq[3];
                     tf_point(T, cj[0], cj[1], cj[2], A[0], A[1], A[2]);
                     tf_point(T, cj[3], cj[4], cj[5], Bq[0], Bq[1], Bq[2]);
+                    caps[tid][t][0] = A[0];
+                    caps[tid][t][1] = A[1];
+                    caps[tid][t][2] = A[2];
+                    caps[tid][t][3] = Bq[0];
+                    caps[tid][t][4] = Bq[1];
+                    caps[tid][t][5] = Bq[2];
                     if (t == tl) {
                         float pt[3], nt[3];
                         capsule_project(A, Bq, cj[6], p, pt, nt);
@@ -356,6 +404,27 @@ k_realize(DevHand H, const int32_t *__restrict__ wit, SdfDev S, const float *__r
             }
             cerr[a * k + f] = emax;
             cang[a * k + f] = amax;
+        }
+        // hand self-collision: this finger's links against those of the higher
+        // fingers of the set (the 8 lanes of a set are in one wave)
+        if (ik.self_collision) {
+            __builtin_amdgcn_wave_barrier();
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            if (f < H.F) {
+                const int first = H.finger_first[f], d = H.finger_dof[f];
+                for (int f2 = f + 1; f2 < H.F; ++f2) {
+                    const int first2 = H.finger_first[f2], d2 = H.finger_dof[f2];
+                    for (int t = 0; t < d; ++t)
+                        for (int t2 = 0; t2 < d2; ++t2) {
+                            const float *c1 = caps[tid][t], *c2 = caps[base + f2][t2];
+                            const float pen = H.capsule[7 * (first + t) + 6] + H.capsule[7 * (first2 + t2) + 6] -
+                                              segment_distance(c1, c1 + 3, c2, c2 + 3);
+                            dep = fmaxf(dep, pen);
+                        }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
         // set-level reductions over the 8 lanes of the set
 #pragma unroll
@@ -393,7 +462,7 @@ extern "C" lg_status lg_realize(const lg_field *field, const lg_sdf *sdf, const 
         !contact_ang || !depth || !valid)
         return fail(LG_EINVAL, "null device buffer");
     SdfDev S{sdf->origin[0], sdf->origin[1], sdf->origin[2], sdf->h, 1.0f / sdf->h, sdf->dims, sdf->values};
-    IkDev ik{p->iters, p->phase1, p->lambda, p->beta, p->tol_pos, p->tol_ang, p->margin};
+    IkDev ik{p->iters, p->phase1, p->lambda, p->beta, p->tol_pos, p->tol_ang, p->margin, p->self_collision};
     hipStream_t s = as_stream(stream);
     // grid-stride launch sized to the device, not to the max_acc upper bound
     int dev = 0, n_cu = 0;

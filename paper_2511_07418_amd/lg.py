@@ -64,7 +64,7 @@ class SearchParams(C.Structure):
 class IkParams(C.Structure):
     _fields_ = [("iters", C.c_int32), ("phase1", C.c_int32), ("lam", C.c_float),
                 ("beta", C.c_float), ("tol_pos", C.c_float), ("tol_ang", C.c_float),
-                ("margin", C.c_float)]
+                ("margin", C.c_float), ("self_collision", C.c_int32)]
 
 
 class Sdf(C.Structure):
@@ -323,7 +323,7 @@ def lg_search(field: Field, pts, nrm, poses, dom_bits, dom_count, sp, bufs: Opti
 
 def ik_params(ik) -> IkParams:
     return IkParams(int(ik.iters), int(ik.phase1), float(ik.lam), float(ik.beta), float(ik.tol_pos),
-                    float(ik.tol_ang), float(ik.margin))
+                    float(ik.tol_ang), float(ik.margin), int(getattr(ik, "self_collision", 0)))
 
 
 def sdf_struct(sdf_host, values_dev: torch.Tensor) -> Sdf:

@@ -355,3 +355,24 @@ def test_pipeline_end_to_end_c1_determinism():
     torch.cuda.synchronize()
     assert torch.equal(a1, pipe.sbuf.acc_list[:pipe.n_acc()])
     assert v1 == pipe.valid_count()
+
+
+# ---------------------------------------------------------------------------
+# realize with the hand self-collision filter (Sec. 5.6): depth covers the
+# capsules of different fingers too; same bars
+# ---------------------------------------------------------------------------
+def _with_self_collision(w):
+    import dataclasses
+    return dataclasses.replace(w, ik=dataclasses.replace(w.ik, self_collision=1))
+
+
+def test_realize_c1_sphere_self_collision():
+    w = _with_self_collision(synth.workload("c1", with_sdf=True))
+    _realize_check(w)
+
+
+def test_realize_c3_shape_self_collision():
+    w = _with_self_collision(synth.workload("c3", samples=8192, n_poses=96))
+    R, val = _realize_check(w)
+    base = _realize_check(synth.workload("c3", samples=8192, n_poses=96))[0]
+    assert R["valid"].sum() <= base["valid"].sum()
