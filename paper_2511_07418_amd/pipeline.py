@@ -49,7 +49,11 @@ class Pipeline:
         lg.lg_query_domains(self.field, self.pts, self.nrm, self.poses, self.dom_bits, self.dom_count,
                             stream=stream)
 
-    def search(self, stream=None):
+    def search(self, stream=None, request_id=None):
+        """Draws + verdicts on the current domains; another request_id resamples
+        the same domains (multi-pass reuse of a query)."""
+        if request_id is not None:
+            self.sbuf.p.request_id = int(request_id)
         lg.lg_search(self.field, self.pts, self.nrm, self.poses, self.dom_bits, self.dom_count, self.sp,
                      bufs=self.sbuf, stream=stream)
 

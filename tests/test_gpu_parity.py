@@ -376,3 +376,28 @@ def test_realize_c3_shape_self_collision():
     R, val = _realize_check(w)
     base = _realize_check(synth.workload("c3", samples=8192, n_poses=96))[0]
     assert R["valid"].sum() <= base["valid"].sum()
+
+
+def test_multipass_reuse_of_domains():
+    """Sec. 5.7 multi-pass generation: the same cached domains resampled with
+    another request id give other draws; the same id gives the same ones."""
+    from paper_2511_07418_amd.pipeline import Pipeline
+    lg = lgmod()
+    w = synth.workload("c1", n_poses=64)
+    field = lg.lg_build_field(w.hand, w.field, keep_witness=False)
+    pipe = Pipeline(field, w.obj.pts, w.obj.nrm, w.poses, w.search)
+    pipe.query()
+    pipe.search(request_id=1)
+    a = pipe.sbuf.set_pt.clone()
+    pipe.search(request_id=2)
+    b = pipe.sbuf.set_pt.clone()
+    pipe.search(request_id=1)
+    c = pipe.sbuf.set_pt.clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, c) and not torch.equal(a, b)
+    # both are draws from the same domains: every drawn point lies in its finger's domain
+    dom = pipe.dom_bits.cpu().numpy().view(np.uint32)
+    bb = b.cpu().numpy()
+    for g, d in zip(*np.nonzero((bb >= 0).all(-1))):
+        for i, p in enumerate(bb[g, d]):
+            assert (dom[g, i, p // 32] >> np.uint32(p % 32)) & 1
