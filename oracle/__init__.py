@@ -17,6 +17,8 @@ Each function cites the passage of the paper it follows (arXiv 2511.07418):
                        per-dependency-group domains of Sec. 5.3
 * ``draw``             Sec. 5.3 random selection + reverse lookup of Sec. 5.5
 * ``verdicts``/``set_tstar``  Eq. 1-2 with a linearised friction cone (LP)
+* ``place_exhaustive`` Sec. 5.1 exhaustive placement (object point onto a
+                       random contact vector of the field)
 * ``optimize``         Sec. 5.4 Alg. 2 (blockwise zeroth-order contact-point
                        optimisation), with ``project_domain`` and ``opt_noise``
 * ``relink``           the reverse lookup of Sec. 5.5 for optimised sets
@@ -107,6 +109,9 @@ def lib():
         L.orc_set_tstar.restype = dbl
         L.orc_verdicts.argtypes = [vp, vp, i32, i32, vp, dbl, i32, dbl, dbl, i32, vp, vp, vp, vp]
         L.orc_verdicts.restype = C.c_int
+        L.orc_rot_align.argtypes = [vp, vp, vp, vp]
+        L.orc_place_exhaustive.argtypes = [vp, vp, vp, vp, i32, i32, u64, C.c_uint32, i64, vp, vp]
+        L.orc_place_exhaustive.restype = C.c_int
         L.orc_opt_noise.argtypes = [u64, C.c_uint32, i64, C.c_int, C.c_uint32, dbl, vp]
         L.orc_project_domain.argtypes = [vp, i32, vp, vp, vp]
         L.orc_project_domain.restype = i64
@@ -331,6 +336,28 @@ def verdicts(pts, nrm, set_pt, sp, max_pivots: int = 1000) -> dict:
     if rc != 0:
         raise ValueError(f"orc_verdicts failed ({rc})")
     return {"verdict": v, "tstar": t, "vflag": vf, "status": st}
+
+
+def rot_align(a, b) -> np.ndarray:
+    """Rotation [3, 3] taking the direction of a onto the direction of b."""
+    R = np.zeros(9)
+    lib().orc_rot_align(_p(_c(a, np.float64)), _p(_c(b, np.float64)), _p(R), None)
+    return R.reshape(3, 3)
+
+
+def place_exhaustive(hand, fp, pts, nrm, n_poses: int, seed: int, request_id: int = 0,
+                     pose_offset: int = 0) -> dict:
+    """Sec. 5.1 exhaustive placement: poses [P, 12] (float64) and near-branch flags."""
+    pts, nrm = _c(pts, np.float32), _c(nrm, np.float32)
+    out = np.zeros((n_poses, 12), np.float64)
+    fl = np.zeros(n_poses, np.uint8)
+    H, Fp = _hand(hand), _field(fp)
+    rc = lib().orc_place_exhaustive(H.ref, Fp.ref, _p(pts), _p(nrm), pts.shape[0], int(n_poses),
+                                    int(seed) & 0xFFFFFFFFFFFFFFFF, int(request_id), int(pose_offset),
+                                    _p(out), _p(fl))
+    if rc != 0:
+        raise ValueError(f"orc_place_exhaustive failed ({rc})")
+    return {"poses": out, "pflag": fl}
 
 
 def opt_noise(seed: int, request_id: int, g: int, d: int, step: int, sigma: float) -> np.ndarray:

@@ -36,6 +36,7 @@
 #define PURPOSE_JOINT 1u
 #define PURPOSE_DRAW 3u
 #define PURPOSE_OPT 5u
+#define PURPOSE_PLACE 11u
 #define OPT_TAU 1e-9    /* candidates within OPT_TAU of the best criterion value tie */
 #define OPT_BAND 1e-7   /* m: projection near-tie band (FP32 candidate positions err by ~1e-8 m) */
 
@@ -871,6 +872,127 @@ int orc_verdicts(const float *pts, const float *nrm, int32_t n_sets, int32_t k,
         if (tstar) tstar[s] = t;
         if (vflag) vflag[s] = fabs(t - eps) <= BAND_VAL;
         if (status) status[s] = st;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exhaustive placement (Sec. 5.1): a random contact vector of the field      */
+/* (finger f, joint sample s, link l of f, surface sample j: hand-frame point */
+/* x and outward normal nu after FK) receives a random object point (p, n):   */
+/* the pose maps n onto -nu (the minimal rotation, then a roll psi about -nu) */
+/* and p onto x.  Pose g draws Philox blocks (g + pose_offset, b, PLACE,      */
+/* request_id), b = 0, 1: f, s, t (link index within f), j from words 0-3 as  */
+/* floor(w * count / 2^32); the object point from word 4; psi = 2 pi u(w5).   */
+/* The minimal rotation of unit a onto unit b: I + [v]x + [v]x^2 / (1 + c),   */
+/* v = a x b, c = a.b; for c <= -0.9999 a half-turn about the Duff x-axis of  */
+/* a first (a -> -a), then the minimal rotation of -a onto b.  pflag marks    */
+/* |c + 0.9999| <= 1e-5 (the branch is a float decision on the GPU).          */
+/* ------------------------------------------------------------------------ */
+static double dot3(const double *a, const double *b);
+
+static void cross3(const double *a, const double *b, double *c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static void mat3_mul(const double *A, const double *B, double *C)
+{
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) C[3 * r + c] = A[3 * r] * B[c] + A[3 * r + 1] * B[3 + c] + A[3 * r + 2] * B[6 + c];
+}
+
+static void rot_min(const double *a, const double *b, double *R)
+{
+    double v[3];
+    cross3(a, b, v);
+    const double c = a[0] * b[0] + a[1] * b[1] + a[2] * b[2], k = 1.0 / (1.0 + c);
+    const double K[9] = {0, -v[2], v[1], v[2], 0, -v[0], -v[1], v[0], 0};
+    double K2[9];
+    mat3_mul(K, K, K2);
+    for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0 ? 1.0 : 0.0) + K[i] + K2[i] * k;
+}
+
+void orc_rot_align(const double *a_in, const double *b_in, double *R, int *flag)
+{
+    double a[3], b[3];
+    const double na = sqrt(dot3(a_in, a_in)), nb = sqrt(dot3(b_in, b_in));
+    for (int i = 0; i < 3; ++i) {
+        a[i] = a_in[i] / na;
+        b[i] = b_in[i] / nb;
+    }
+    const double c = dot3(a, b);
+    if (flag) *flag = fabs(c + 0.9999) <= 1e-5;
+    if (c > -0.9999) {
+        rot_min(a, b, R);
+        return;
+    }
+    double x[3], y[3];
+    duff_basis(a, x, y);
+    double Rh[9];
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) Rh[3 * r + q] = 2.0 * x[r] * x[q] - (r == q ? 1.0 : 0.0);
+    const double na2[3] = {-a[0], -a[1], -a[2]};
+    double Rm[9];
+    rot_min(na2, b, Rm);
+    mat3_mul(Rm, Rh, R);
+}
+
+int orc_place_exhaustive(const orc_hand *H, const orc_field_params *fp, const float *pts, const float *nrm,
+                         int32_t n_points, int32_t n_poses, uint64_t seed, uint32_t request_id, int64_t pose_offset,
+                         double *poses /*[P][12]*/, uint8_t *pflag)
+{
+    if (n_points <= 0 || n_poses < 0 || fp->samples <= 0 || fp->samples > 0xffffffffLL) return ORC_EINVAL;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+#pragma omp parallel for schedule(static)
+    for (int g = 0; g < n_poses; ++g) {
+        uint32_t w[8];
+        for (int b = 0; b < 2; ++b) {
+            uint32_t ctr[4] = {(uint32_t)(pose_offset + g), (uint32_t)b, PURPOSE_PLACE, request_id};
+            orc_philox4x32_10(ctr, key, w + 4 * b);
+        }
+        const int f = (int)(((uint64_t)w[0] * (uint64_t)H->n_fingers) >> 32);
+        const int64_t smp = (int64_t)(((uint64_t)w[1] * (uint64_t)fp->samples) >> 32);
+        const int j0 = finger_first_joint(H, f), d = finger_dof(H, f);
+        const int l = j0 + (int)(((uint64_t)w[2] * (uint64_t)d) >> 32);
+        const int js = (int)(((uint64_t)w[3] * (uint64_t)H->n_surf) >> 32);
+        const int64_t i = (int64_t)(((uint64_t)w[4] * (uint64_t)n_points) >> 32);
+        const double psi = 2.0 * M_PI * u01(w[5]);
+        double q[16];
+        orc_joint_sample(H, fp->seed, f, smp, q);
+        double *T = (double *)malloc(sizeof(double) * 12 * H->n_joints);
+        orc_fk_finger(H, f, q, T);
+        const float *sf = H->surf + ((int64_t)l * H->n_surf + js) * 6;
+        const double ps[3] = {sf[0], sf[1], sf[2]}, ns[3] = {sf[3], sf[4], sf[5]};
+        double x[3], nu[3];
+        tf_point(T + 12 * l, ps, x);
+        tf_dir(T + 12 * l, ns, nu);
+        free(T);
+        const double a[3] = {nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2]};
+        double b[3] = {-nu[0], -nu[1], -nu[2]};
+        const double nb = sqrt(dot3(b, b));
+        for (int c = 0; c < 3; ++c) b[c] /= nb;
+        double R0[9], Rr[9], R[9];
+        int fl = 0;
+        orc_rot_align(a, b, R0, &fl);
+        /* roll psi about b (Rodrigues) */
+        const double cs = cos(psi), sn = sin(psi);
+        const double K[9] = {0, -b[2], b[1], b[2], 0, -b[0], -b[1], b[0], 0};
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c)
+                Rr[3 * r + c] = (r == c ? cs : 0.0) + sn * K[3 * r + c] + (1.0 - cs) * b[r] * b[c];
+        mat3_mul(Rr, R0, R);
+        const double p[3] = {pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]};
+        double *P = poses + 12 * (int64_t)g;
+        for (int r = 0; r < 3; ++r) {
+            P[4 * r + 0] = R[3 * r];
+            P[4 * r + 1] = R[3 * r + 1];
+            P[4 * r + 2] = R[3 * r + 2];
+            P[4 * r + 3] = x[r] - (R[3 * r] * p[0] + R[3 * r + 1] * p[1] + R[3 * r + 2] * p[2]);
+        }
+        if (pflag) pflag[g] = (uint8_t)fl;
     }
     return ORC_OK;
 }
