@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--eval-objects", type=int, default=200, help="proposer: held-out objects (seeds 100000..)")
     ap.add_argument("--epochs", type=int, default=60, help="proposer: training epochs")
     ap.add_argument("--passes", type=int, default=8, help="multipass: searches per query")
+    ap.add_argument("--placement", default="canonical", choices=["canonical", "exhaustive"],
+                    help="palm poses: canonical (random pose above the palm) or exhaustive (an object point "
+                         "on a random contact vector of the field)")
     ap.add_argument("--mode", default="full", choices=["full", "query", "search", "serve", "proposer", "multipass"],
                     help="query / search: only the field build and --steps launches of that stage "
                          "(query mode adds a 1 GiB device copy); for hardware-counter runs, no JSON")
@@ -282,8 +285,10 @@ def proposer_bench(torch, lg, pool, n_train: int, n_eval: int, epochs: int, seed
     res = {"uniform": {"valid": 0, "diversity": 0, "s": 0.0, "per_obj": []},
            "learned": {"valid": 0, "diversity": 0, "s": 0.0, "per_obj": []}}
     ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    held = []
     for i, (s_, obj, sdf) in enumerate(pool.imap(_c2_object, range(100000, 100000 + n_eval), chunksize=2)):
         x = _prop_input(torch, obj, s_)
+        held.append((s_, obj, sdf, x))
         for kind in ("uniform", "learned"):
             if kind == "uniform":
                 poses = torch.from_numpy(synth.palm_poses(PROP_POSES, s_ + 1)).cuda()
@@ -313,6 +318,35 @@ def proposer_bench(torch, lg, pool, n_train: int, n_eval: int, epochs: int, seed
                      "seconds": r["s"]}
     pu, pl = np.array(res["uniform"]["per_obj"]), np.array(res["learned"]["per_obj"])
     out["objects_learned_ge_uniform"] = int((pl >= pu).sum())
+    # the same held-out objects as a back-to-back request stream through the
+    # serving loop; pose generation (CPU for uniform, proposer forward +
+    # sampling on the GPU for learned) is inside the timed span
+    out["serving"] = {}
+    for kind in ("uniform", "learned"):
+        srv = lg.Server(budget_bytes=32 << 30, max_active=8, chunk_poses=PROP_POSES)
+        keep, tickets = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r_, (s_, obj, sdf, x) in enumerate(held):
+            if kind == "uniform":
+                poses = synth.palm_poses(PROP_POSES, s_ + 1)
+            else:
+                poses = prop.sample(x, PROP_POSES, seed=s_, uniform_frac=0.1).cpu().numpy()
+            sp = synth.SearchParams(draws=32, k=hand.n_fingers, mu=0.5, m_edges=8, eps=1e-3, seed=seed,
+                                    moment_scale=obj.rho)
+            req, kp = srv.make_request(field, obj.pts, obj.nrm, poses, sp, 1 + r_, ik=ik, sdf=sdf)
+            keep.append((req, kp))
+            tickets.append(srv.submit(req))
+        res = [srv.wait(t, 600.0) for t in tickets]
+        wall = time.perf_counter() - t0
+        srv.destroy()
+        assert all(r["state"] == lg.LG_REQ_DONE for r in res)
+        lat = np.array([r["t_done"] - r["t_submit"] for r in res]) * 1e3
+        nv = int(sum(r["n_valid"] for r in res))
+        out["serving"][kind] = {"valid_grasps": nv, "seconds": wall, "valid_grasps_per_s": nv / wall,
+                                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
+    out["serving"]["valid_per_s_ratio"] = (out["serving"]["learned"]["valid_grasps_per_s"] /
+                                           out["serving"]["uniform"]["valid_grasps_per_s"])
     # encoder throughput: one forward of 512 objects x 2048 points (dense MFMA work)
     big = lg.Proposer(max_batch=512, max_points=PROP_POINTS, max_targets=1, seed=seed)
     xb = X[torch.arange(512, device="cuda") % X.shape[0]].contiguous()
@@ -408,7 +442,13 @@ def main():
     t_build = time.perf_counter()
     field = lg.lg_build_field(w.hand, w.field, keep_witness=w.ik is not None)
     t_build = time.perf_counter() - t_build
-    pipe = Pipeline(field, w.obj.pts, w.obj.nrm, w.poses, w.search, ik=w.ik, sdf=w.sdf)
+    poses = w.poses
+    if args.placement == "exhaustive":
+        pts_soa = torch.from_numpy(np.ascontiguousarray(w.obj.pts.T)).cuda()
+        nrm_soa = torch.from_numpy(np.ascontiguousarray(w.obj.nrm.T)).cuda()
+        poses = lg.lg_place_exhaustive(field, pts_soa, nrm_soa, len(w.poses), seed=args.seed + 1)
+        torch.cuda.synchronize()
+    pipe = Pipeline(field, w.obj.pts, w.obj.nrm, poses, w.search, ik=w.ik, sdf=w.sdf)
     print(f"[bench] {args.workload}: field built in {t_build:.2f}s ({field.info()['bits_set']} bits), "
           f"P={pipe.P} N={pipe.N}", file=sys.stderr, flush=True)
 
@@ -434,32 +474,39 @@ def main():
 
     if args.mode == "multipass":
         # Sec. 5.7 multi-pass generation: one query, then R resamplings of the
-        # cached domains (request ids 1..R), each with the verdicts and realize
+        # cached domains (request ids 1..R), each with the verdicts and realize.
+        # Timed: the kernels only; the valid counts are summed on the device.
         pipe.step()
         torch.cuda.synchronize()
         R = args.passes
+        rows = torch.arange(pipe.max_acc, device="cuda", dtype=torch.int32)
+        counts = torch.zeros(R, dtype=torch.int64, device="cuda")
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         ev[0].record()
         pipe.query()
-        keys = []
-        n_valid = 0
-        for r in range(1, R + 1):
-            pipe.search(request_id=r)
+        for r in range(R):
+            pipe.search(request_id=r + 1)
             pipe.realize()
-            ids = pipe.valid_sets()
-            n_valid += int(ids.numel())
-            sets = pipe.sbuf.set_pt.view(-1, pipe.sbuf.set_pt.shape[-1])[ids.long()]
-            g = (ids // pipe.sbuf.set_pt.shape[1]).long()[:, None]
-            keys.append(torch.cat([g, torch.sort(sets.long(), dim=1).values], dim=1))
+            counts[r] = ((pipe.rbuf.valid != 0) & (rows < pipe.sbuf.n_acc)).sum()
         ev[1].record()
         torch.cuda.synchronize()
         ms = ev[0].elapsed_time(ev[1])
+        n_valid = int(counts.sum().item())
+        # distinct valid grasps over the passes (recomputed, untimed)
+        keys = []
+        for r in range(R):
+            pipe.search(request_id=r + 1)
+            pipe.realize()
+            ids = pipe.valid_sets()
+            sets = pipe.sbuf.set_pt.view(-1, pipe.sbuf.set_pt.shape[-1])[ids.long()]
+            g = (ids // pipe.sbuf.set_pt.shape[1]).long()[:, None]
+            keys.append(torch.cat([g, torch.sort(sets.long(), dim=1).values], dim=1))
         distinct = int(torch.unique(torch.cat(keys), dim=0).shape[0])
         print(json.dumps({"multipass": {"workload": args.workload, "passes": R, "ms": ms,
                                         "valid_grasps": n_valid, "distinct_valid_grasps": distinct,
                                         "valid_grasps_per_s": n_valid / (ms * 1e-3),
-                                        "note": "one query, R draws+verdicts+realize on the cached domains; "
-                                                "the valid-set bookkeeping (torch) is inside the timed region"}}))
+                                        "note": "one query, then R draws + verdicts + realize on the cached "
+                                                "domains (request ids 1..R)"}}))
         return
 
     for _ in range(args.warmup):
@@ -521,7 +568,7 @@ def main():
                    "points": pipe.N, "draws": int(w.search.draws), "seed": args.seed,
                    "contact_opt": ({"rounds": args.opt_outer, "candidates": args.opt_inner,
                                     "sigma_m": args.opt_sigma} if args.opt_outer > 0 else None),
-                   "self_collision": bool(args.self_collision)},
+                   "self_collision": bool(args.self_collision), "placement": args.placement},
         "valid_per_step": n_valid,
         "accepted_sets_per_step": n_acc,
         "stage_ms": {"query": q_ms, "search": float(st[:, 1].mean()), "realize": float(st[:, 2].mean())},

@@ -325,6 +325,23 @@ double lg_serve_clock(lg_server *srv);
 /* Finish in-flight chunks, cancel the rest, free everything. */
 lg_status lg_serve_destroy(lg_server *srv);
 
+/* ---- exhaustive placement ----------------------------------------------------
+ * lg_place_exhaustive -- object poses of the exhaustive placement of Sec. 5.1:
+ * pose g puts a random object surface point onto a random contact vector of
+ * the field with opposite normals.  Philox blocks (g + pose_offset, b, 11,
+ * request_id), b = 0, 1, key = seed, select as floor(w * count / 2^32): word 0
+ * the finger f, word 1 the joint sample s (the field's own FK of finger f at
+ * sample s), word 2 the link of f, word 3 the link surface sample (point x,
+ * outward normal nu), word 4 the object point i; word 5 a roll psi = 2 pi u.
+ * R takes n_i onto -nu (the minimal rotation; below a cosine of -0.9999 a
+ * half-turn about the Duff x-axis of n_i first), then rolls it by psi about
+ * -nu; t = x - R p_i.  pts/nrm: DEVICE SoA [3][N]; poses: DEVICE [P][12] out.
+ * LG_EINVAL on null buffers or n_points <= 0.
+ */
+lg_status lg_place_exhaustive(const lg_field *field, const float *pts, const float *nrm, int32_t n_points,
+                              int32_t n_poses, uint64_t seed, uint32_t request_id, int64_t pose_offset,
+                              float *poses, void *stream);
+
 /* ---- learned palm-pose proposer ------------------------------------------------
  * Data-driven search (Sec. 5.7) names learning where to search as a way to skip
  * unproductive regions of the pose space; the paper leaves it unimplemented.

@@ -129,6 +129,7 @@ def _load():
     L.lg_serve_clock.argtypes = [vp]
     L.lg_serve_clock.restype = C.c_double
     L.lg_serve_destroy.argtypes = [vp]
+    L.lg_place_exhaustive.argtypes = [vp, vp, vp, i32, i32, C.c_uint64, C.c_uint32, i64, vp, vp]
     L.lg_prop_num_params.restype = i64
     L.lg_prop_create.argtypes = [vp, vp, vp]
     L.lg_prop_release.argtypes = [vp]
@@ -143,7 +144,7 @@ def _load():
     for fn in ("lg_build_field", "lg_field_import", "lg_field_export", "lg_field_info",
                "lg_field_release", "lg_query_domains", "lg_search", "lg_realize", "lg_serve_create",
                "lg_serve_submit", "lg_serve_poll", "lg_serve_wait", "lg_serve_cancel", "lg_serve_stats",
-               "lg_serve_destroy", "lg_prop_create", "lg_prop_release", "lg_prop_get_params",
+               "lg_serve_destroy", "lg_place_exhaustive", "lg_prop_create", "lg_prop_release", "lg_prop_get_params",
                "lg_prop_set_params", "lg_prop_forward", "lg_prop_backward", "lg_prop_adam",
                "lg_prop_train_step", "lg_prop_sample_mixture", "lg_prop_sample"):
         getattr(L, fn).restype = i32
@@ -156,7 +157,7 @@ EXPORTED = ("lg_status_str", "lg_last_error", "lg_version", "lg_build_field", "l
             "lg_field_export", "lg_field_info", "lg_field_release", "lg_query_domains",
             "lg_search_workspace_bytes", "lg_search", "lg_realize", "lg_serve_request_bytes",
             "lg_serve_create", "lg_serve_submit", "lg_serve_poll", "lg_serve_wait", "lg_serve_cancel",
-            "lg_serve_stats", "lg_serve_clock", "lg_serve_destroy", "lg_prop_num_params",
+            "lg_serve_stats", "lg_serve_clock", "lg_serve_destroy", "lg_place_exhaustive", "lg_prop_num_params",
             "lg_prop_create", "lg_prop_release", "lg_prop_get_params", "lg_prop_set_params",
             "lg_prop_forward", "lg_prop_backward", "lg_prop_adam", "lg_prop_train_step",
             "lg_prop_sample_mixture", "lg_prop_sample")
@@ -357,6 +358,19 @@ def lg_realize(field: Field, sdf: Sdf, pts, nrm, poses, set_pt, set_link, k: int
 
 def version() -> str:
     return _lib.lg_version().decode()
+
+
+def lg_place_exhaustive(field: Field, pts: torch.Tensor, nrm: torch.Tensor, n_poses: int, seed: int,
+                        request_id: int = 0, pose_offset: int = 0, out: Optional[torch.Tensor] = None,
+                        stream=None) -> torch.Tensor:
+    """Exhaustive-placement poses [n_poses, 12] (device) for SoA points/normals [3, N]."""
+    N = int(pts.shape[1])
+    if out is None:
+        out = torch.empty((n_poses, 12), dtype=torch.float32, device=pts.device)
+    _check(_lib.lg_place_exhaustive(field.handle, _ptr(pts), _ptr(nrm), N, int(n_poses),
+                                    int(seed) & 0xFFFFFFFFFFFFFFFF, int(request_id), int(pose_offset),
+                                    _ptr(out), _stream(stream)), "lg_place_exhaustive")
+    return out
 
 
 # ---- serving -----------------------------------------------------------------

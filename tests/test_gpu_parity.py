@@ -401,3 +401,24 @@ def test_multipass_reuse_of_domains():
     for g, d in zip(*np.nonzero((bb >= 0).all(-1))):
         for i, p in enumerate(bb[g, d]):
             assert (dom[g, i, p // 32] >> np.uint32(p % 32)) & 1
+
+
+# ---------------------------------------------------------------------------
+# exhaustive placement (Sec. 5.1): poses from the GPU-built field's own joint
+# sampling and FK against the oracle's FP64 construction
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["c1", "c3"])
+def test_place_exhaustive(name):
+    lg = lgmod()
+    w = synth.workload(name, n_poses=1, with_sdf=False)
+    field = lg.lg_build_field(w.hand, w.field, keep_witness=False)
+    P = 4096
+    g = lg.lg_place_exhaustive(field, soa(w.obj.pts), soa(w.obj.nrm), P, seed=99, request_id=3,
+                               pose_offset=10).cpu().numpy().astype(np.float64)
+    ref = oracle.place_exhaustive(w.hand, w.field, w.obj.pts, w.obj.nrm, P, 99, request_id=3, pose_offset=10)
+    ok = ~ref["pflag"].astype(bool)
+    assert ok.mean() > 0.999
+    err = np.abs(g - ref["poses"])[ok]
+    assert err.max() <= 2e-5, err.max()
+    # the poses feed the unchanged query
+    assert lg.lg_place_exhaustive(field, soa(w.obj.pts), soa(w.obj.nrm), 0, seed=1).shape == (0, 12)
