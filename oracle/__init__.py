@@ -15,6 +15,8 @@ Each function cites the passage of the paper it follows (arXiv 2511.07418):
                        per-link (patch) tables of Sec. 4.4 and quantised normals
 * ``query``            object contact query of Sec. 4.3 and the merged
                        per-dependency-group domains of Sec. 5.3
+* ``query_cone``       the theta_hit test of Sec. 4.3 over the field's bin
+                       centres (cone query)
 * ``draw``             Sec. 5.3 random selection + reverse lookup of Sec. 5.5
 * ``verdicts``/``set_tstar``  Eq. 1-2 with a linearised friction cone (LP)
 * ``place_exhaustive`` Sec. 5.1 exhaustive placement (object point onto a
@@ -98,6 +100,8 @@ def lib():
         L.orc_build_field.restype = C.c_int
         L.orc_query.argtypes = [vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp]
         L.orc_query.restype = C.c_int
+        L.orc_query_cone.argtypes = [vp, vp, vp, vp, vp, i32, vp, i32, dbl, vp, vp, vp]
+        L.orc_query_cone.restype = C.c_int
         L.orc_draw.argtypes = [vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, i32, i32, u64,
                                C.c_uint32, i64, vp, vp]
         L.orc_draw.restype = C.c_int
@@ -270,6 +274,22 @@ def query(hand, fp, bits, pts, nrm, poses, flags: bool = True) -> dict:
     if rc != 0:
         raise ValueError(f"orc_query failed ({rc})")
     return {"dom_bits": db, "dom_count": dc, "dom_flag": df, "lookups": lk.value}
+
+
+def query_cone(hand, fp, bits, pts, nrm, poses, cos_hit: float, flags: bool = True) -> dict:
+    """Cone query (Sec. 4.3 theta_hit test over the field's bin centres)."""
+    pts, nrm, poses = _c(pts, np.float32), _c(nrm, np.float32), _c(poses, np.float32)
+    N, P, F = pts.shape[0], poses.shape[0], hand.n_fingers
+    NW = (N + 31) // 32
+    db = np.zeros((P, F, NW), np.uint32)
+    dc = np.zeros((P, F), np.uint32)
+    df = np.zeros((P, F, NW), np.uint32) if flags else None
+    H, Fp = _hand(hand), _field(fp)
+    rc = lib().orc_query_cone(H.ref, Fp.ref, _p(_c(bits, np.uint32)), _p(pts), _p(nrm), N, _p(poses), P,
+                              float(cos_hit), _p(db), _p(dc), _p(df))
+    if rc != 0:
+        raise ValueError(f"orc_query_cone failed ({rc})")
+    return {"dom_bits": db, "dom_count": dc, "dom_flag": df}
 
 
 def draw(hand, fp, bits, pts, nrm, poses, dom_bits, dom_count, sp) -> tuple[np.ndarray, np.ndarray]:

@@ -517,6 +517,101 @@ int orc_query(const orc_hand *H, const orc_field_params *fp, const uint32_t *bit
 }
 
 /* ------------------------------------------------------------------------ */
+/* Cone query (Sec. 4.3, the theta_hit test of the object contact query): a   */
+/* query (x, -nu) hits link l if some normal of l's field at voxel(x), i.e.   */
+/* a bin centre c_b whose bit is set, satisfies c_b . (-nu) >= cos_hit.  The  */
+/* domain of finger f is the OR over its links.  dom_flag marks points whose  */
+/* outcome could change under the float32 bands: a voxel face within 1e-6 m  */
+/* (as in orc_query) or a set bin whose dot product is within 1e-6 of        */
+/* cos_hit.                                                                   */
+/* ------------------------------------------------------------------------ */
+static int cone_hit(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits, const double *cb, int f,
+                    const int *vox, int in, const double *q, double cos_hit, int *near)
+{
+    if (!in) return 0;
+    const int G = fp->grid, B = fp->bins, nw = B / 32;
+    const int64_t G3 = (int64_t)G * G * G;
+    int hit = 0;
+    for (int l = 0; l < H->n_joints; ++l) {
+        if (H->joint_finger[l] != f) continue;
+        const int64_t v = (int64_t)l * G3 + ((int64_t)vox[2] * G + vox[1]) * G + vox[0];
+        for (int b = 0; b < B; ++b) {
+            if (!((bits[v * nw + (b >> 5)] >> (b & 31)) & 1u)) continue;
+            const double d = cb[3 * b] * q[0] + cb[3 * b + 1] * q[1] + cb[3 * b + 2] * q[2];
+            if (d >= cos_hit) hit = 1;
+            if (near && fabs(d - cos_hit) <= BAND_VAL) *near = 1;
+        }
+    }
+    return hit;
+}
+
+int orc_query_cone(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits,
+                   const float *pts /*[N][3]*/, const float *nrm /*[N][3]*/, int32_t n_points,
+                   const float *poses /*[P][12]*/, int32_t n_poses, double cos_hit,
+                   uint32_t *dom_bits, uint32_t *dom_count, uint32_t *dom_flag)
+{
+    const int F = H->n_fingers, G = fp->grid;
+    const int64_t NW = (n_points + 31) / 32;
+    if (n_points < 0 || n_poses < 0) return ORC_EINVAL;
+    double cb[3 * 64];
+    orc_bin_centers(fp->bins, cb);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int g = 0; g < n_poses; ++g) {
+        for (int f = 0; f < F; ++f) {
+            uint32_t *db = dom_bits + ((int64_t)g * F + f) * NW;
+            uint32_t *df = dom_flag ? dom_flag + ((int64_t)g * F + f) * NW : NULL;
+            memset(db, 0, NW * 4);
+            if (df) memset(df, 0, NW * 4);
+            uint32_t cnt = 0;
+            for (int i = 0; i < n_points; ++i) {
+                double x[3], u[3], gap;
+                int vox[3], b, b2;
+                int in = query_lookup(fp, cb, poses + 12 * (int64_t)g, pts + 3 * (int64_t)i,
+                                      nrm + 3 * (int64_t)i, f, x, u, vox, &b, &b2, &gap);
+                double T[12], nu[3], q[3];
+                tf_load(poses + 12 * (int64_t)g, T);
+                const double n[3] = {nrm[3 * (int64_t)i], nrm[3 * (int64_t)i + 1], nrm[3 * (int64_t)i + 2]};
+                tf_dir(T, n, nu);
+                for (int c = 0; c < 3; ++c) q[c] = -nu[c];
+                int near_ang = 0;
+                const int hit = cone_hit(H, fp, bits, cb, f, vox, in, q, cos_hit, &near_ang);
+                if (hit) {
+                    db[i >> 5] |= 1u << (i & 31);
+                    ++cnt;
+                }
+                if (!df) continue;
+                int near[3], any_near = 0;
+                for (int a = 0; a < 3; ++a) {
+                    near[a] = face_dist(u[a], fp->h) < BAND_POS;
+                    any_near |= near[a];
+                }
+                int differs = near_ang;
+                if (any_near && !differs) {
+                    int lo3[3], hi3[3];
+                    for (int a = 0; a < 3; ++a) {
+                        lo3[a] = hi3[a] = vox[a];
+                        if (near[a]) {
+                            double r = u[a] - floor(u[a]);
+                            if (r < 0.5) lo3[a] = vox[a] - 1; else hi3[a] = vox[a] + 1;
+                        }
+                    }
+                    for (int zz = lo3[2]; zz <= hi3[2] && !differs; ++zz)
+                        for (int yy = lo3[1]; yy <= hi3[1] && !differs; ++yy)
+                            for (int xx = lo3[0]; xx <= hi3[0] && !differs; ++xx) {
+                                int v3[3] = {xx, yy, zz};
+                                int in2 = xx >= 0 && yy >= 0 && zz >= 0 && xx < G && yy < G && zz < G;
+                                if (cone_hit(H, fp, bits, cb, f, v3, in2, q, cos_hit, NULL) != hit) differs = 1;
+                            }
+                }
+                if (differs) df[i >> 5] |= 1u << (i & 31);
+            }
+            dom_count[(int64_t)g * F + f] = cnt;
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Contact-set draws (Sec. 5.3: one domain per dependency group, then one     */
 /* point per domain, Alg. 2 initialisation) and the reverse lookup of the     */
 /* hand link (Sec. 5.5: pick one of the active patch fields at random).       */
