@@ -151,6 +151,19 @@ lg_status lg_query_domains(const lg_field *field, const float *pts, const float 
                            int32_t n_points, const float *poses, int32_t n_poses,
                            uint32_t *dom_bits, uint32_t *dom_count, void *stream);
 
+/*
+ * lg_query_domains_cone -- the theta_hit form of the object contact query
+ * (Sec. 4.3): point i is in finger f's domain at pose g if some normal-bin
+ * centre c_b set in the finger's field at voxel(R p_i + t) satisfies
+ * c_b . (-R n_i) >= cos_hit (cos_hit in [-1, 1]; the paper's test over the
+ * quantised normals of the leaf).  Same buffers, layout and errors as
+ * lg_query_domains; the domains contain lg_query_domains' once the cone is
+ * wider than the bins' covering radius.
+ */
+lg_status lg_query_domains_cone(const lg_field *field, const float *pts, const float *nrm, int32_t n_points,
+                                const float *poses, int32_t n_poses, float cos_hit, uint32_t *dom_bits,
+                                uint32_t *dom_count, void *stream);
+
 /* Search parameters (Sec. 5.3 draws, Eq. 1-2 criterion). */
 typedef struct {
     int32_t draws;        /* D sets per pose */

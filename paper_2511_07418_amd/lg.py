@@ -113,6 +113,7 @@ def _load():
     L.lg_field_info.argtypes = [vp, vp]
     L.lg_field_release.argtypes = [vp]
     L.lg_query_domains.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp]
+    L.lg_query_domains_cone.argtypes = [vp, vp, vp, i32, vp, i32, C.c_float, vp, vp, vp]
     L.lg_search_workspace_bytes.argtypes = [i32, i32, vp]
     L.lg_search_workspace_bytes.restype = sz
     L.lg_search.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
@@ -142,7 +143,7 @@ def _load():
     L.lg_prop_sample_mixture.argtypes = [vp, i32, C.c_uint64, C.c_float, C.c_float, C.c_float, vp, vp]
     L.lg_prop_sample.argtypes = [vp, vp, i32, i32, C.c_uint64, C.c_float, C.c_float, C.c_float, vp, vp]
     for fn in ("lg_build_field", "lg_field_import", "lg_field_export", "lg_field_info",
-               "lg_field_release", "lg_query_domains", "lg_search", "lg_realize", "lg_serve_create",
+               "lg_field_release", "lg_query_domains", "lg_query_domains_cone", "lg_search", "lg_realize", "lg_serve_create",
                "lg_serve_submit", "lg_serve_poll", "lg_serve_wait", "lg_serve_cancel", "lg_serve_stats",
                "lg_serve_destroy", "lg_place_exhaustive", "lg_prop_create", "lg_prop_release", "lg_prop_get_params",
                "lg_prop_set_params", "lg_prop_forward", "lg_prop_backward", "lg_prop_adam",
@@ -154,7 +155,7 @@ def _load():
 _lib = _load()
 
 EXPORTED = ("lg_status_str", "lg_last_error", "lg_version", "lg_build_field", "lg_field_import",
-            "lg_field_export", "lg_field_info", "lg_field_release", "lg_query_domains",
+            "lg_field_export", "lg_field_info", "lg_field_release", "lg_query_domains", "lg_query_domains_cone",
             "lg_search_workspace_bytes", "lg_search", "lg_realize", "lg_serve_request_bytes",
             "lg_serve_create", "lg_serve_submit", "lg_serve_poll", "lg_serve_wait", "lg_serve_cancel",
             "lg_serve_stats", "lg_serve_clock", "lg_serve_destroy", "lg_place_exhaustive", "lg_prop_num_params",
@@ -284,6 +285,21 @@ def lg_query_domains(field: Field, pts: torch.Tensor, nrm: torch.Tensor, poses: 
         dom_count = torch.empty((P, F), dtype=torch.int32, device=dev)
     _check(_lib.lg_query_domains(field.handle, _ptr(pts), _ptr(nrm), N, _ptr(poses), P,
                                  _ptr(dom_bits), _ptr(dom_count), _stream(stream)), "lg_query_domains")
+    return dom_bits, dom_count
+
+
+def lg_query_domains_cone(field: Field, pts, nrm, poses, cos_hit: float, dom_bits=None, dom_count=None,
+                          stream=None):
+    """Cone (theta_hit) query; same shapes as lg_query_domains."""
+    N, P, F = int(pts.shape[1]), int(poses.shape[0]), field.n_fingers
+    NW = (N + 31) // 32
+    dev = pts.device
+    if dom_bits is None:
+        dom_bits = torch.empty((P, F, NW), dtype=torch.int32, device=dev)
+    if dom_count is None:
+        dom_count = torch.empty((P, F), dtype=torch.int32, device=dev)
+    _check(_lib.lg_query_domains_cone(field.handle, _ptr(pts), _ptr(nrm), N, _ptr(poses), P, float(cos_hit),
+                                      _ptr(dom_bits), _ptr(dom_count), _stream(stream)), "lg_query_domains_cone")
     return dom_bits, dom_count
 
 

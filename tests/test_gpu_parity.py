@@ -422,3 +422,33 @@ def test_place_exhaustive(name):
     assert err.max() <= 2e-5, err.max()
     # the poses feed the unchanged query
     assert lg.lg_place_exhaustive(field, soa(w.obj.pts), soa(w.obj.nrm), 0, seed=1).shape == (0, 12)
+
+
+# ---------------------------------------------------------------------------
+# cone query (Sec. 4.3 theta_hit test over the bin centres): stage isolated,
+# bit-exact outside the oracle's flags
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,deg", [("c1", 15.0), ("c1", 40.0), ("c3", 12.0)])
+def test_query_cone(name, deg):
+    import math
+    lg = lgmod()
+    w = synth.workload(name, n_poses=24, samples=8192 if name == "c3" else None,
+                       n_points=4096 if name == "c3" else None, with_sdf=False)
+    ref = oracle.build_field(w.hand, w.field, flags=False)
+    field = lg.lg_field_import(w.hand, w.field, ref["bits"])
+    cos_hit = float(np.float32(math.cos(math.radians(deg))))
+    db, dc = lg.lg_query_domains_cone(field, soa(w.obj.pts), soa(w.obj.nrm), dev(w.poses), cos_hit)
+    torch.cuda.synchronize()
+    Q = oracle.query_cone(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses, cos_hit)
+    gb = db.cpu().numpy().view(np.uint32)
+    diff = (gb ^ Q["dom_bits"]) & ~Q["dom_flag"]
+    assert diff.sum() == 0
+    n_flag = int(np.unpackbits(Q["dom_flag"].view(np.uint8)).sum())
+    assert n_flag <= max(2, 1e-3 * len(w.poses) * w.hand.n_fingers * w.obj.n)
+    # counts agree up to the flagged points
+    assert np.abs(dc.cpu().numpy().astype(np.int64) - Q["dom_count"].astype(np.int64)).sum() <= n_flag
+    # with a cone wider than the bins' covering radius it contains the nearest-bin domain
+    nb, _ = lg.lg_query_domains(field, soa(w.obj.pts), soa(w.obj.nrm), dev(w.poses))
+    if deg >= 30.0:
+        nbb = nb.cpu().numpy().view(np.uint32)
+        assert ((nbb & ~gb) & ~Q["dom_flag"]).sum() == 0
