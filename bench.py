@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--eval-objects", type=int, default=200, help="proposer: held-out objects (seeds 100000..)")
     ap.add_argument("--epochs", type=int, default=60, help="proposer: training epochs")
     ap.add_argument("--passes", type=int, default=8, help="multipass: searches per query")
+    ap.add_argument("--cone-deg", type=float, default=0.0,
+                    help="use the cone (theta_hit) query with this half-angle in degrees; 0 = nearest bin")
     ap.add_argument("--placement", default="canonical", choices=["canonical", "exhaustive"],
                     help="palm poses: canonical (random pose above the palm) or exhaustive (an object point "
                          "on a random contact vector of the field)")
@@ -448,7 +450,8 @@ def main():
         nrm_soa = torch.from_numpy(np.ascontiguousarray(w.obj.nrm.T)).cuda()
         poses = lg.lg_place_exhaustive(field, pts_soa, nrm_soa, len(w.poses), seed=args.seed + 1)
         torch.cuda.synchronize()
-    pipe = Pipeline(field, w.obj.pts, w.obj.nrm, poses, w.search, ik=w.ik, sdf=w.sdf)
+    cos_hit = math.cos(math.radians(args.cone_deg)) if args.cone_deg > 0 else None
+    pipe = Pipeline(field, w.obj.pts, w.obj.nrm, poses, w.search, ik=w.ik, sdf=w.sdf, cos_hit=cos_hit)
     print(f"[bench] {args.workload}: field built in {t_build:.2f}s ({field.info()['bits_set']} bits), "
           f"P={pipe.P} N={pipe.N}", file=sys.stderr, flush=True)
 
@@ -568,7 +571,8 @@ def main():
                    "points": pipe.N, "draws": int(w.search.draws), "seed": args.seed,
                    "contact_opt": ({"rounds": args.opt_outer, "candidates": args.opt_inner,
                                     "sigma_m": args.opt_sigma} if args.opt_outer > 0 else None),
-                   "self_collision": bool(args.self_collision), "placement": args.placement},
+                   "self_collision": bool(args.self_collision), "placement": args.placement,
+                   "cone_deg": args.cone_deg or None},
         "valid_per_step": n_valid,
         "accepted_sets_per_step": n_acc,
         "stage_ms": {"query": q_ms, "search": float(st[:, 1].mean()), "realize": float(st[:, 2].mean())},

@@ -19,8 +19,9 @@ class Pipeline:
     synchronising; ``valid_count()`` synchronises and reads the result."""
 
     def __init__(self, field: lg.Field, pts: np.ndarray, nrm: np.ndarray, poses: np.ndarray, sp,
-                 ik=None, sdf=None, device: str = "cuda", max_pivots: int = 1000):
+                 ik=None, sdf=None, device: str = "cuda", max_pivots: int = 1000, cos_hit=None):
         self.field = field
+        self.cos_hit = cos_hit      # None: nearest-bin query; else the cone (theta_hit) query
         self.dev = torch.device(device)
         self.pts = torch.from_numpy(np.ascontiguousarray(np.asarray(pts, np.float32).T)).to(self.dev)
         self.nrm = torch.from_numpy(np.ascontiguousarray(np.asarray(nrm, np.float32).T)).to(self.dev)
@@ -46,8 +47,12 @@ class Pipeline:
             self.rbuf = lg.RealizeBuffers(self.max_acc, field.n_joints, int(sp.k), self.dev)
 
     def query(self, stream=None):
-        lg.lg_query_domains(self.field, self.pts, self.nrm, self.poses, self.dom_bits, self.dom_count,
-                            stream=stream)
+        if self.cos_hit is None:
+            lg.lg_query_domains(self.field, self.pts, self.nrm, self.poses, self.dom_bits, self.dom_count,
+                                stream=stream)
+        else:
+            lg.lg_query_domains_cone(self.field, self.pts, self.nrm, self.poses, self.cos_hit, self.dom_bits,
+                                     self.dom_count, stream=stream)
 
     def search(self, stream=None, request_id=None):
         """Draws + verdicts on the current domains; another request_id resamples
