@@ -119,10 +119,13 @@ def lib():
         L.orc_opt_noise.argtypes = [u64, C.c_uint32, i64, C.c_int, C.c_uint32, dbl, vp]
         L.orc_project_domain.argtypes = [vp, i32, vp, vp, vp]
         L.orc_project_domain.restype = i64
-        L.orc_optimize.argtypes = [vp, vp, i32, vp, i32, i32, i32, i32, vp, dbl, i32, dbl, i32, i32, dbl,
+        L.orc_choose_fingers.argtypes = [C.c_int, vp, C.c_int, u64, C.c_uint32, i64, C.c_int, vp]
+        L.orc_choose_fingers.restype = C.c_int
+        L.orc_unused_joints.argtypes = [vp, C.c_int, u64, C.c_uint32, i64, C.c_int, vp]
+        L.orc_optimize.argtypes = [vp, vp, i32, vp, vp, i32, i32, i32, i32, vp, dbl, i32, dbl, i32, i32, dbl,
                                    u64, C.c_uint32, i64, i32, vp, vp]
         L.orc_optimize.restype = C.c_int
-        L.orc_relink.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, i32, vp, u64, C.c_uint32, i64, vp]
+        L.orc_relink.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, i32, vp, vp, u64, C.c_uint32, i64, vp]
         L.orc_relink.restype = C.c_int
         L.orc_segment_distance.argtypes = [vp, vp, vp, vp]
         L.orc_segment_distance.restype = dbl
@@ -136,8 +139,8 @@ def lib():
         L.orc_axis_samples.restype = C.c_int
         L.orc_penetration.argtypes = [vp, vp, vp, vp]
         L.orc_penetration.restype = dbl
-        L.orc_realize.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, i32, vp,
-                                  vp, vp, vp, vp, vp, vp, vp]
+        L.orc_realize.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, i32, i32, vp, i32, vp,
+                                  u64, C.c_uint32, i64, vp, vp, vp, vp, vp, vp, vp]
         L.orc_realize.restype = C.c_int
         _lib = L
     return _lib
@@ -397,15 +400,50 @@ def project_domain(pts, dom_words, y) -> tuple[int, bool]:
     return int(i), bool(fl.value)
 
 
-def optimize(pts, nrm, dom_bits, set_pt, sp, F: int, max_pivots: int = 1000) -> dict:
+def _dom_count(dom_count, dom_bits, P: int, F: int) -> np.ndarray:
+    if dom_count is not None:
+        return _c(dom_count, np.uint32).reshape(P, F)
+    # the domains' sizes, counted from their bitsets
+    b = np.ascontiguousarray(dom_bits, np.uint32).reshape(P, F, -1)
+    return np.unpackbits(b.view(np.uint8), axis=-1).sum(-1).astype(np.uint32)
+
+
+def choose_fingers(dom_count, k: int, sp, draws: Optional[int] = None) -> np.ndarray:
+    """Contact fingers [P, D, k] of every set (-1 where fewer than k domains are non-empty)."""
+    cnt = _c(dom_count, np.uint32)
+    P, F = cnt.shape
+    D = sp.draws if draws is None else int(draws)
+    out = np.full((P, D, k), -1, np.int32)
+    row = np.zeros(k, np.int32)
+    for g in range(P):
+        for d in range(D):
+            if lib().orc_choose_fingers(F, _p(cnt[g]), int(k), int(sp.seed) & 0xFFFFFFFFFFFFFFFF,
+                                        int(sp.request_id), int(sp.pose_offset) + g, d, _p(row)):
+                out[g, d] = row
+    return out
+
+
+def unused_joints(hand, f: int, sp, g: int, d: int) -> np.ndarray:
+    """Random joint values [dof] of finger f when it carries no contact of set (g, d)."""
+    q = np.zeros(hand.n_joints)
+    H = _hand(hand)
+    lib().orc_unused_joints(H.ref, int(f), int(sp.seed) & 0xFFFFFFFFFFFFFFFF, int(sp.request_id),
+                            int(sp.pose_offset) + int(g), int(d), _p(q))
+    j = np.flatnonzero(np.asarray(hand.joint_finger) == f)
+    return q[j]
+
+
+def optimize(pts, nrm, dom_bits, set_pt, sp, F: int, max_pivots: int = 1000, dom_count=None) -> dict:
     """Sec. 5.4 Alg. 2 on drawn sets: optimised set_pt [P, D, k], t* of the final
-    sets (NaN for invalid draws) and the band flag of each set."""
+    sets (NaN for invalid draws) and the band flag of each set.  ``dom_count``
+    (default: the domains' popcounts) decides the sets' fingers."""
     pts, nrm = _c(pts, np.float32), _c(nrm, np.float32)
     spt = _c(set_pt, np.int32).copy()
     P, D, k = spt.shape
     t = np.zeros(P * D, np.float64)
     fl = np.zeros(P * D, np.uint8)
-    rc = lib().orc_optimize(_p(pts), _p(nrm), pts.shape[0], _p(_c(dom_bits, np.uint32)), P, int(F), D, k,
+    cnt = _dom_count(dom_count, dom_bits, P, int(F))
+    rc = lib().orc_optimize(_p(pts), _p(nrm), pts.shape[0], _p(_c(dom_bits, np.uint32)), _p(cnt), P, int(F), D, k,
                             _p(spt), float(np.float32(sp.mu)), sp.m_edges, float(np.float32(sp.moment_scale)),
                             int(sp.opt_outer), int(sp.opt_inner), float(np.float32(sp.opt_sigma)),
                             int(sp.seed) & 0xFFFFFFFFFFFFFFFF, int(sp.request_id), int(sp.pose_offset),
@@ -417,16 +455,24 @@ def optimize(pts, nrm, dom_bits, set_pt, sp, F: int, max_pivots: int = 1000) -> 
             "vflag": (np.abs(t - eps) <= BAND).astype(np.uint8)}
 
 
-def relink(hand, fp, bits, pts, nrm, poses, set_pt, sp) -> np.ndarray:
-    """Links of (optimised) sets, picked with each set's draw words."""
+def relink(hand, fp, bits, pts, nrm, poses, set_pt, sp, dom_count=None) -> np.ndarray:
+    """Links of (optimised) sets, picked with each set's draw words.  ``dom_count``
+    decides the sets' fingers; it may be left out when k equals the number of
+    fingers (every finger then carries contact i = finger i)."""
     pts, nrm, poses = _c(pts, np.float32), _c(nrm, np.float32), _c(poses, np.float32)
     spt = _c(set_pt, np.int32)
     P, D, k = spt.shape
+    F = hand.n_fingers
+    if dom_count is None:
+        if k != F:
+            raise ValueError("relink with k < number of fingers needs dom_count")
+        dom_count = np.ones((P, F), np.uint32)
+    cnt = _c(dom_count, np.uint32).reshape(P, F)
     sln = np.zeros((P, D, k), np.int32)
     H, Fp = _hand(hand), _field(fp)
     rc = lib().orc_relink(H.ref, Fp.ref, _p(_c(bits, np.uint32)), _p(pts), _p(nrm), _p(poses), P, D, k,
-                          _p(spt), int(sp.seed) & 0xFFFFFFFFFFFFFFFF, int(sp.request_id), int(sp.pose_offset),
-                          _p(sln))
+                          _p(cnt), _p(spt), int(sp.seed) & 0xFFFFFFFFFFFFFFFF, int(sp.request_id),
+                          int(sp.pose_offset), _p(sln))
     if rc != 0:
         raise ValueError(f"orc_relink failed ({rc})")
     return sln
@@ -500,10 +546,10 @@ def realize(hand, fp, wit, sdf, pts, nrm, poses, set_pt, set_link, sp, acc_list,
     H, Fp, S = _hand(hand), _field(fp), _sdf(sdf)
     ikp = _ik(ik)
     w = None if wit is None else _c(wit, np.int32)
-    rc = lib().orc_realize(H.ref, Fp.ref, _p(w), S.ref, _p(pts), _p(nrm), _p(poses),
-                           _p(_c(set_pt, np.int32)), _p(_c(set_link, np.int32)), k, sp.draws,
-                           _p(acc), n, C.byref(ikp), _p(q), _p(q0), _p(err), _p(ang), _p(dep),
-                           _p(val), _p(fl))
+    rc = lib().orc_realize(H.ref, Fp.ref, _p(w), S.ref, _p(pts), _p(nrm), pts.shape[0], _p(poses),
+                           poses.shape[0], _p(_c(set_pt, np.int32)), _p(_c(set_link, np.int32)), k, sp.draws,
+                           _p(acc), n, C.byref(ikp), int(sp.seed) & 0xFFFFFFFFFFFFFFFF, int(sp.request_id),
+                           int(sp.pose_offset), _p(q), _p(q0), _p(err), _p(ang), _p(dep), _p(val), _p(fl))
     if rc != 0:
         raise ValueError(f"orc_realize failed ({rc})")
     return {"q": q, "q0": q0, "contact_err": err, "contact_ang": ang, "depth": dep,

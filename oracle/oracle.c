@@ -37,6 +37,8 @@
 #define PURPOSE_DRAW 3u
 #define PURPOSE_OPT 5u
 #define PURPOSE_PLACE 11u
+#define PURPOSE_FINGERS 13u
+#define PURPOSE_UNUSED 15u
 #define OPT_TAU 1e-9    /* candidates within OPT_TAU of the best criterion value tie */
 #define OPT_BAND 1e-7   /* m: projection near-tie band (FP32 candidate positions err by ~1e-8 m) */
 
@@ -677,6 +679,43 @@ static int pick_link(const orc_hand *H, const orc_field_params *fp, const uint32
     return -1;
 }
 
+/* The k contact fingers of set d of pose g (Sec. 5.3: k contact domains
+ * chosen at random among the fingers' domains).  Eligible fingers are those
+ * with a non-empty domain; with c of them, k picks without replacement: pick
+ * j takes the floor(w_j (c - j) / 2^32)-th (0-based, increasing finger order)
+ * of the eligible fingers not yet picked, w = Philox blocks (g, d,
+ * PURPOSE_FINGERS | blk << 8, request_id), blk = 0, 1.  Contact i goes to the
+ * i-th smallest picked finger.  Returns 0 when fewer than k are eligible.  */
+int orc_choose_fingers(int F, const uint32_t *count /*[F]*/, int k, uint64_t seed, uint32_t request_id,
+                       int64_t g, int d, int32_t *fing /*[k]*/)
+{
+    int left[8], c = 0;
+    for (int f = 0; f < F; ++f)
+        if (count[f] > 0) left[c++] = f;
+    if (k < 1 || c < k) return 0;
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[8];
+    for (int blk = 0; blk < 2; ++blk) {
+        uint32_t ctr[4] = {(uint32_t)g, (uint32_t)d, PURPOSE_FINGERS | ((uint32_t)blk << 8), request_id};
+        orc_philox4x32_10(ctr, key, w + 4 * blk);
+    }
+    int picked[8];
+    for (int j = 0; j < k; ++j) {
+        int r = (int)(((uint64_t)w[j] * (uint32_t)(c - j)) >> 32);
+        picked[j] = left[r];
+        for (int t = r; t + 1 < c - j; ++t) left[t] = left[t + 1];  /* remove it, keep the order */
+    }
+    /* increasing finger order */
+    for (int a = 1; a < k; ++a)
+        for (int b = a; b > 0 && picked[b - 1] > picked[b]; --b) {
+            int t = picked[b];
+            picked[b] = picked[b - 1];
+            picked[b - 1] = t;
+        }
+    for (int j = 0; j < k; ++j) fing[j] = picked[j];
+    return 1;
+}
+
 int orc_draw(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits,
              const float *pts, const float *nrm, int32_t n_points,
              const float *poses, int32_t n_poses,
@@ -686,7 +725,7 @@ int orc_draw(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits
 {
     const int F = H->n_fingers;
     const int64_t NW = (n_points + 31) / 32;
-    if (k != F || k > 8 || draws <= 0) return ORC_EINVAL;
+    if (k < 1 || k > F || k > 8 || draws <= 0) return ORC_EINVAL;
     double cb[3 * 64];
     orc_bin_centers(fp->bins, cb);
 #pragma omp parallel for schedule(dynamic, 4)
@@ -696,17 +735,17 @@ int orc_draw(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits
             draw_words(seed, request_id, pose_offset + g, d, 2 * k, w);
             int32_t *sp = set_pt + ((int64_t)g * draws + d) * k;
             int32_t *sl = set_link + ((int64_t)g * draws + d) * k;
-            int ok = 1;
-            for (int i = 0; i < k; ++i)
-                if (dom_count[(int64_t)g * F + i] == 0) ok = 0;
+            int32_t fing[8];
             for (int i = 0; i < k; ++i) { sp[i] = -1; sl[i] = -1; }
-            if (!ok) continue;
+            if (!orc_choose_fingers(F, dom_count + (int64_t)g * F, k, seed, request_id, pose_offset + g, d, fing))
+                continue;
             for (int i = 0; i < k; ++i) {
-                uint32_t cnt = dom_count[(int64_t)g * F + i];
+                const int f = fing[i];
+                uint32_t cnt = dom_count[(int64_t)g * F + f];
                 uint32_t j = (uint32_t)(((uint64_t)w[i] * cnt) >> 32);
-                int64_t idx = select1(dom_bits + ((int64_t)g * F + i) * NW, NW, j);
+                int64_t idx = select1(dom_bits + ((int64_t)g * F + f) * NW, NW, j);
                 sp[i] = (int32_t)idx;
-                sl[i] = pick_link(H, fp, bits, cb, pts, nrm, poses + 12 * (int64_t)g, i, idx, w[k + i]);
+                sl[i] = idx < 0 ? -1 : pick_link(H, fp, bits, cb, pts, nrm, poses + 12 * (int64_t)g, f, idx, w[k + i]);
             }
         }
     }
@@ -1160,13 +1199,14 @@ int64_t orc_project_domain(const float *pts, int32_t n_points, const uint32_t *d
 }
 
 int orc_optimize(const float *pts, const float *nrm, int32_t n_points, const uint32_t *dom_bits /*[P][F][NW]*/,
+                 const uint32_t *dom_count /*[P][F]*/,
                  int32_t n_poses, int32_t F, int32_t draws, int32_t k, int32_t *set_pt /*[P][D][k] in/out*/,
                  double mu, int32_t m_edges, double rho, int32_t n_outer, int32_t n_inner, double sigma,
                  uint64_t seed, uint32_t request_id, int64_t pose_offset, int32_t max_pivots,
                  double *tstar /*[P][D]*/, uint8_t *oflag /*[P][D]*/)
 {
     const int64_t NW = (n_points + 31) / 32;
-    if (k <= 0 || k > 16 || k > F || n_outer < 0 || n_inner < 1 || n_inner > 64 || !(sigma >= 0.0))
+    if (k <= 0 || k > 8 || k > F || n_outer < 0 || n_inner < 1 || n_inner > 64 || !(sigma >= 0.0))
         return ORC_EINVAL;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t s = 0; s < (int64_t)n_poses * draws; ++s) {
@@ -1175,6 +1215,9 @@ int orc_optimize(const float *pts, const float *nrm, int32_t n_points, const uin
         int32_t *sp = set_pt + s * k;
         int valid = 1;
         for (int i = 0; i < k; ++i) valid &= sp[i] >= 0;
+        int32_t fing[8];
+        if (valid && k <= 8)
+            valid = orc_choose_fingers(F, dom_count + g * F, k, seed, request_id, pose_offset + g, d, fing);
         if (!valid) {
             tstar[s] = NAN;
             oflag[s] = 0;
@@ -1195,7 +1238,7 @@ int orc_optimize(const float *pts, const float *nrm, int32_t n_points, const uin
                 duff_basis(n + 3 * i, tx, ty);
                 double Jc[64] = {0};
                 int64_t idx[64];
-                const uint32_t *dom = dom_bits + (g * F + i) * NW;
+                const uint32_t *dom = dom_bits + (g * F + fing[i]) * NW;
                 for (int j = 0; j < n_inner; ++j) {
                     double dx, dy, y[3];
                     opt_noise(seed, request_id, pose_offset + g, d, (uint32_t)((r * k + i) * n_inner + j), sigma,
@@ -1239,10 +1282,11 @@ int orc_optimize(const float *pts, const float *nrm, int32_t n_points, const uin
 /* set's draw words (for sets whose points the optimisation moved).           */
 int orc_relink(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits, const float *pts,
                const float *nrm, const float *poses, int32_t n_poses, int32_t draws, int32_t k,
-               const int32_t *set_pt, uint64_t seed, uint32_t request_id, int64_t pose_offset,
-               int32_t *set_link)
+               const uint32_t *dom_count /*[P][F]*/, const int32_t *set_pt, uint64_t seed, uint32_t request_id,
+               int64_t pose_offset, int32_t *set_link)
 {
-    if (k != H->n_fingers || k > 8 || draws <= 0) return ORC_EINVAL;
+    const int F = H->n_fingers;
+    if (k < 1 || k > F || k > 8 || draws <= 0) return ORC_EINVAL;
     double cb[3 * 64];
     orc_bin_centers(fp->bins, cb);
 #pragma omp parallel for schedule(dynamic, 4)
@@ -1252,8 +1296,13 @@ int orc_relink(const orc_hand *H, const orc_field_params *fp, const uint32_t *bi
             draw_words(seed, request_id, pose_offset + g, d, 2 * k, w);
             const int32_t *sp = set_pt + ((int64_t)g * draws + d) * k;
             int32_t *sl = set_link + ((int64_t)g * draws + d) * k;
+            int32_t fing[8];
+            const int ok = orc_choose_fingers(F, dom_count + (int64_t)g * F, k, seed, request_id, pose_offset + g,
+                                              d, fing);
             for (int i = 0; i < k; ++i)
-                sl[i] = sp[i] < 0 ? -1 : pick_link(H, fp, bits, cb, pts, nrm, poses + 12 * (int64_t)g, i, sp[i], w[k + i]);
+                sl[i] = (!ok || sp[i] < 0) ? -1
+                                           : pick_link(H, fp, bits, cb, pts, nrm, poses + 12 * (int64_t)g, fing[i],
+                                                       sp[i], w[k + i]);
         }
     }
     return ORC_OK;
@@ -1641,23 +1690,54 @@ double orc_self_penetration(const orc_hand *H, const double *T /*[J][12]*/)
     return worst;
 }
 
+/* Uniform joint values of an unused finger f of set (g, d) (Sec. 5.6: joints
+ * not fixed by a contact take random values): joint t of the finger is
+ * lo + (hi - lo) u, u = (w_t >> 8) / 2^24, w = Philox blocks (g, d,
+ * PURPOSE_UNUSED | (2 f + blk) << 8, request_id), blk = 0, 1. */
+void orc_unused_joints(const orc_hand *H, int f, uint64_t seed, uint32_t request_id, int64_t g, int d,
+                       double *q /*[J]*/)
+{
+    const int j0 = finger_first_joint(H, f), dof = finger_dof(H, f);
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[8];
+    for (int blk = 0; blk < 2; ++blk) {
+        uint32_t ctr[4] = {(uint32_t)g, (uint32_t)d, PURPOSE_UNUSED | ((uint32_t)(2 * f + blk) << 8), request_id};
+        orc_philox4x32_10(ctr, key, w + 4 * blk);
+    }
+    for (int t = 0; t < dof; ++t) {
+        const double lo = H->limits[2 * (j0 + t)], hi = H->limits[2 * (j0 + t) + 1];
+        q[j0 + t] = lo + (hi - lo) * u01(w[t]);
+    }
+}
+
+/* Accepted set -> grasp.  The finger of contact i is that of its link; a set
+ * is realisable iff every link is a hand link, every point an object point and
+ * the fingers increase strictly with i.  Fingers carrying a contact start at
+ * the witness sample and run the IK; every other finger (all of them for a set
+ * that is not realisable, whose contact errors and angles are +inf) takes
+ * random joint values.  The penetration covers every link of the hand. */
 int orc_realize(const orc_hand *H, const orc_field_params *fp, const int32_t *wit,
-                const orc_sdf *S, const float *pts, const float *nrm, const float *poses,
+                const orc_sdf *S, const float *pts, const float *nrm, int32_t n_points,
+                const float *poses, int32_t n_poses,
                 const int32_t *set_pt, const int32_t *set_link, int32_t k, int32_t draws,
                 const int32_t *acc_list, int32_t n_acc, const orc_ik_params *ik,
+                uint64_t seed, uint32_t request_id, int64_t pose_offset,
                 double *q_out /*[n_acc][J]*/, double *q0_out /*[n_acc][J] opt*/,
                 double *contact_err /*[n_acc][k]*/, double *contact_ang /*[n_acc][k]*/,
                 double *depth, uint8_t *valid, uint8_t *rflag)
 {
     const int J = H->n_joints, F = H->n_fingers, G = fp->grid, B = fp->bins;
     const int64_t G3 = (int64_t)G * G * G;
-    if (k != F || draws <= 0) return ORC_EINVAL;
+    if (k < 1 || k > F || k > 8 || draws <= 0) return ORC_EINVAL;
+    for (int a = 0; a < n_acc; ++a)
+        if (acc_list[a] < 0 || acc_list[a] >= (int64_t)n_poses * draws) return ORC_EINVAL;
     double cb[3 * 64];
     orc_bin_centers(B, cb);
 #pragma omp parallel for schedule(dynamic, 4)
     for (int a = 0; a < n_acc; ++a) {
         const int64_t sid = acc_list[a]; /* set id g*D + d */
         const int64_t g = sid / draws;
+        const int d = (int)(sid % draws);
         const float *pose = poses + 12 * g;
         double Tp[12];
         tf_load(pose, Tp);
@@ -1665,9 +1745,30 @@ int orc_realize(const orc_hand *H, const orc_field_params *fp, const int32_t *wi
         double q0[64];
         int fl = 0;
         double worst_err = 0, worst_ang = 0;
+        /* contact of each finger (-1: none) */
+        int contact_of[8];
+        for (int f = 0; f < F; ++f) contact_of[f] = -1;
+        int ok = 1, prev = -1;
         for (int i = 0; i < k; ++i) {
-            const int f = i, l = set_link[sid * k + i], idx = set_pt[sid * k + i];
-            const int j0 = finger_first_joint(H, f), d = finger_dof(H, f);
+            const int l = set_link[sid * k + i], idx = set_pt[sid * k + i];
+            if (l < 0 || l >= J || idx < 0 || idx >= n_points || H->joint_finger[l] <= prev) {
+                ok = 0;
+                break;
+            }
+            prev = H->joint_finger[l];
+            contact_of[prev] = i;
+        }
+        if (!ok)
+            for (int f = 0; f < F; ++f) contact_of[f] = -1;
+        for (int f = 0; f < F; ++f) {
+            const int i = contact_of[f];
+            const int j0 = finger_first_joint(H, f), dof = finger_dof(H, f);
+            if (i < 0) {
+                orc_unused_joints(H, f, seed, request_id, pose_offset + g, d, q);
+                for (int t = 0; t < dof; ++t) q0[j0 + t] = q[j0 + t];
+                continue;
+            }
+            const int l = set_link[sid * k + i], idx = set_pt[sid * k + i];
             double pl[3] = {pts[3 * idx], pts[3 * idx + 1], pts[3 * idx + 2]};
             double nl[3] = {nrm[3 * idx], nrm[3 * idx + 1], nrm[3 * idx + 2]};
             double p[3], nu[3], n[3];
@@ -1688,10 +1789,10 @@ int orc_realize(const orc_hand *H, const orc_field_params *fp, const int32_t *wi
             if (w >= 0) {
                 orc_joint_sample(H, fp->seed, f, w, q + j0);
             } else {
-                for (int t = 0; t < d; ++t)
+                for (int t = 0; t < dof; ++t)
                     q[j0 + t] = 0.5 * ((double)H->limits[2 * (j0 + t)] + H->limits[2 * (j0 + t) + 1]);
             }
-            for (int t = 0; t < d; ++t) q0[j0 + t] = q[j0 + t];
+            for (int t = 0; t < dof; ++t) q0[j0 + t] = q[j0 + t];
             double err, ang;
             orc_ik_finger(H, f, l, p, n, ik, q + j0, &err, &ang, NULL, NULL);
             contact_err[(int64_t)a * k + i] = err;
@@ -1700,6 +1801,13 @@ int orc_realize(const orc_hand *H, const orc_field_params *fp, const int32_t *wi
             fl |= fabs(ang - ik->tol_ang) <= BAND_VAL;
             if (err > worst_err) worst_err = err;
             if (ang > worst_ang) worst_ang = ang;
+        }
+        if (!ok) {
+            for (int i = 0; i < k; ++i) {
+                contact_err[(int64_t)a * k + i] = INFINITY;
+                contact_ang[(int64_t)a * k + i] = INFINITY;
+            }
+            worst_err = worst_ang = INFINITY;
         }
         if (q0_out) memcpy(q0_out + (int64_t)a * J, q0, sizeof(double) * J);
         double *T = (double *)malloc(sizeof(double) * 12 * J);
