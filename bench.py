@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--passes", type=int, default=8, help="multipass: searches per query")
     ap.add_argument("--cone-deg", type=float, default=0.0,
                     help="use the cone (theta_hit) query with this half-angle in degrees; 0 = nearest bin")
+    ap.add_argument("--k", type=int, default=0,
+                    help="contacts per set (0 = one per finger); below the finger count, k fingers are drawn "
+                         "per set and the others take random joint values")
     ap.add_argument("--placement", default="canonical", choices=["canonical", "exhaustive"],
                     help="palm poses: canonical (random pose above the palm) or exhaustive (an object point "
                          "on a random contact vector of the field)")
@@ -441,6 +444,9 @@ def main():
         import dataclasses
         w.search = dataclasses.replace(w.search, opt_outer=args.opt_outer, opt_inner=args.opt_inner,
                                        opt_sigma=args.opt_sigma)
+    if args.k > 0:
+        import dataclasses
+        w.search = dataclasses.replace(w.search, k=args.k)
     t_build = time.perf_counter()
     field = lg.lg_build_field(w.hand, w.field, keep_witness=w.ik is not None)
     t_build = time.perf_counter() - t_build
@@ -572,7 +578,7 @@ def main():
                    "contact_opt": ({"rounds": args.opt_outer, "candidates": args.opt_inner,
                                     "sigma_m": args.opt_sigma} if args.opt_outer > 0 else None),
                    "self_collision": bool(args.self_collision), "placement": args.placement,
-                   "cone_deg": args.cone_deg or None},
+                   "cone_deg": args.cone_deg or None, "contacts": int(w.search.k)},
         "valid_per_step": n_valid,
         "accepted_sets_per_step": n_acc,
         "stage_ms": {"query": q_ms, "search": float(st[:, 1].mean()), "realize": float(st[:, 2].mean())},

@@ -167,7 +167,7 @@ lg_status lg_query_domains_cone(const lg_field *field, const float *pts, const f
 /* Search parameters (Sec. 5.3 draws, Eq. 1-2 criterion). */
 typedef struct {
     int32_t draws;        /* D sets per pose */
-    int32_t k;            /* contacts per set; must equal the number of fingers */
+    int32_t k;            /* contacts per set, 1..F: one per finger, on k fingers drawn per set */
     int32_t m_edges;      /* linearised cone edges, 3..16; k*m_edges <= 52 */
     int32_t max_pivots;   /* simplex pivot cap (status UNDECIDED when hit) */
     float mu;             /* friction coefficient >= 0 */
@@ -186,21 +186,27 @@ size_t lg_search_workspace_bytes(int32_t n_points, int32_t n_poses, const lg_sea
 
 /*
  * lg_search -- seeded contact-set draws, force-closure verdicts, compaction.
- * Draw d of pose g uses Philox blocks (g + pose_offset, 4d + blk, 3,
- * request_id), blk = 0, 1, ...: word i picks the point of contact i (finger i)
- * as the floor(w * count / 2^32)-th set bit of the domain; word k+i picks one
- * of the finger's links whose own table is hit at that point (reverse lookup
- * of Sec. 5.5).  A pose with an empty domain gives set_pt = -1, set_link = -1.
+ * Fingers (Sec. 5.3, k contact domains chosen at random): with c fingers of
+ * pose g having a non-empty domain (dom_count > 0) and c >= k, set d picks k
+ * of them without replacement, pick j taking the floor(w_j (c - j) / 2^32)-th
+ * remaining one in increasing finger order, w = Philox blocks (g +
+ * pose_offset, d, 13 | blk << 8, request_id), blk = 0, 1; contact i goes to
+ * the i-th smallest picked finger (k = F: contact i on finger i).  Draw d of
+ * pose g uses Philox blocks (g + pose_offset, 4d + blk, 3, request_id), blk =
+ * 0, 1, ...: word i picks the point of contact i as the floor(w * count /
+ * 2^32)-th set bit of its finger's domain; word k+i picks one of the finger's
+ * links whose own table is hit at that point (reverse lookup of Sec. 5.5; -1
+ * if none is, e.g. for domains of lg_query_domains_cone).  A pose with fewer
+ * than k non-empty domains gives set_pt = -1, set_link = -1.
  * Verdict (object frame): wrench columns w_ie = [d_ie; p_i x d_ie / rho],
  * d_ie = -n_i + mu (cos(2 pi e/m) x_i + sin(2 pi e/m) y_i) with the Duff et
  * al. (2017) tangent basis; t* = min sum_r |(W g)_r| over g >= 0, sum g = 1
  * (double-precision Phase-1 simplex, Bland's rule); verdict = t* <= eps.
- * With opt_outer > 0 the drawn sets of poses whose domains are all non-empty
- * are first refined by Alg. 2 of Sec. 5.4: for opt_outer rounds, each contact
- * i in turn gets opt_inner candidates, its point moved in the tangent plane of
- * its object normal (Duff basis x_i, y_i) by (dx, dy) ~ N(0, opt_sigma^2) and
- * projected onto its domain (nearest domain point, lowest index on ties);
- * contact i moves to the first candidate whose t* is within 1e-9 of the
+ * With opt_outer > 0 the drawn sets are first refined by Alg. 2 of Sec. 5.4:
+ * for opt_outer rounds, each contact i in turn gets opt_inner candidates, its
+ * point moved in the tangent plane of its object normal (Duff basis x_i, y_i)
+ * by (dx, dy) ~ N(0, opt_sigma^2) and projected onto its finger's domain
+ * (nearest domain point, lowest index on ties); contact i moves to the first candidate whose t* is within 1e-9 of the
  * candidates' minimum.  Candidate j of step s = (round * k + i) * opt_inner + j
  * uses Philox block (g + pose_offset, d, 5 | s << 8, request_id): Box-Muller of
  * u1 = ((w0 >> 8) + 1) / 2^24, u2 = (w1 >> 8) / 2^24.  tstar and verdict are
@@ -227,6 +233,10 @@ typedef struct {
     float margin;     /* acceptance: penetration depth <= margin (m) */
     int32_t self_collision; /* 1: depth also covers capsules of different fingers (Sec. 5.6
                                hand-to-hand check, closed-form segment distance); 0: object only */
+    uint64_t seed;          /* Philox key of the random joint values of fingers without contact
+                               (pass the search's seed) */
+    uint32_t request_id;    /* 4th Philox counter word of those values (the search's request_id) */
+    int64_t pose_offset;    /* global index of pose 0 (the search's pose_offset) */
 } lg_ik_params;
 
 /* Object signed-distance grid (object frame). */
@@ -238,9 +248,18 @@ typedef struct {
 } lg_sdf;
 
 /*
- * lg_realize -- turn accepted sets into grasps (P, q) (Sec. 5.5, Sec. 3.2).
- * For accepted set a (id = acc_list[a], pose g = id / draws), contact i on
- * finger i and link set_link[id][i]: q0 of the finger is the field's witness
+ * lg_realize -- turn accepted sets into grasps (P, q) (Sec. 5.5, Sec. 3.2,
+ * Sec. 5.6).  For accepted set a (id = acc_list[a], pose g = id / draws,
+ * draw d = id % draws), contact i is on the finger of link set_link[id][i].
+ * The set is realisable iff every link is a hand link, every point an object
+ * point and the fingers increase strictly with i (as lg_search writes them);
+ * otherwise its contact errors and angles are +inf and valid = 0.  A finger
+ * without contact (k < F, or every finger of a set that is not realisable)
+ * takes uniform joint values lo + (hi - lo) u, u = (w_t >> 8) / 2^24, w =
+ * Philox blocks (g + pose_offset, d, 15 | (2 f + blk) << 8, request_id), blk
+ * = 0, 1, key = seed (params).  An id outside [0, n_poses * draws) gives NaN
+ * joints and depth, +inf errors, valid = 0, and is not read through.
+ * For a finger with a contact, q0 is the field's witness
  * joint sample of (link, voxel(p), bin(n)) (mid-limits without witness);
  * `iters` DLS steps (Eq. 7-8) match the hand contact point -- the capsule
  * point closest to (p, n) in |x-p|^2 + beta^2 |n~-n|^2, held fixed for

@@ -26,7 +26,11 @@ struct IkDev {
     int iters, phase1;
     float lambda, beta, tol_pos, tol_ang, margin;
     int self_collision;
+    uint32_t seed_lo, seed_hi, request_id;
+    int64_t pose_offset;
 };
+
+constexpr uint32_t kPurposeUnused = 15u;
 
 // distance between segments [p1, q1] and [p2, q2]: the closest parameters
 // (s, t) in [0,1]^2 in closed form (Ericson, Real-Time Collision Detection,
@@ -195,18 +199,22 @@ __device__ inline float sdf_trilinear(const SdfDev &S, float yx, float yy, float
     return fmaf(fz, c1 - c0, c0);
 }
 
+#define LG_REALIZE_ARGS                                                                                         \
+    DevHand H, const int32_t *__restrict__ wit, SdfDev S, const float *__restrict__ pts,                        \
+        const float *__restrict__ nrm, int N, const float *__restrict__ poses,                                  \
+        const int32_t *__restrict__ set_pt, const int8_t *__restrict__ set_link, int k, int D, int64_t n_sets,  \
+        const int32_t *__restrict__ acc_list, const int32_t *__restrict__ n_acc_dev, int max_acc, IkDev ik,    \
+        float *__restrict__ q_out, float *__restrict__ cerr, float *__restrict__ cang,                          \
+        float *__restrict__ depth_out, uint8_t *__restrict__ valid_out
+#define LG_REALIZE_PASS                                                                                         \
+    H, wit, S, pts, nrm, N, poses, set_pt, set_link, k, D, n_sets, acc_list, n_acc_dev, max_acc, ik, q_out,     \
+        cerr, cang, depth_out, valid_out
+
+// cb: bin centres in LDS; caps: capsule axis end points of every lane's finger
+// at its final configuration (LDS)
 template <int DM>
-__global__ void __launch_bounds__(kRealizeThreads)
-k_realize(DevHand H, const int32_t *__restrict__ wit, SdfDev S, const float *__restrict__ pts,
-          const float *__restrict__ nrm, int N, const float *__restrict__ poses, const int32_t *__restrict__ set_pt,
-          const int8_t *__restrict__ set_link, int k, int D, const int32_t *__restrict__ acc_list,
-          const int32_t *__restrict__ n_acc_dev, int max_acc, IkDev ik, float *__restrict__ q_out,
-          float *__restrict__ cerr, float *__restrict__ cang, float *__restrict__ depth_out,
-          uint8_t *__restrict__ valid_out)
+__device__ __forceinline__ void realize_sets(float *cb, float (*caps)[DM][6], LG_REALIZE_ARGS)
 {
-    __shared__ float cb[3 * kMaxBins];
-    // capsule axis end points of every lane's finger at its final configuration
-    __shared__ float caps[kRealizeThreads][DM][6];
     for (int i = threadIdx.x; i < 3 * H.B; i += blockDim.x) cb[i] = H.bin_c[i];
     __syncthreads();
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -217,148 +225,199 @@ k_realize(DevHand H, const int32_t *__restrict__ wit, SdfDev S, const float *__r
     // grid-stride over accepted sets; the 8 lanes of a set move together
     for (int64_t a = gt >> 3; a < nacc; a += stride) {
         const int64_t id = acc_list[a];
+        if (id < 0 || id >= n_sets) {  // not a set id: no reads through it (uniform over the set's lanes)
+            if (f < H.F)
+                for (int t = 0; t < H.finger_dof[f]; ++t) q_out[a * H.J + H.finger_first[f] + t] = __builtin_nanf("");
+            if (f < k) {
+                cerr[a * k + f] = INFINITY;
+                cang[a * k + f] = INFINITY;
+            }
+            if (f == 0) {
+                depth_out[a] = __builtin_nanf("");
+                valid_out[a] = 0;
+            }
+            continue;
+        }
         const int64_t g = id / D;
+        const int dr = (int)(id % D);
         float P[12];
 #pragma unroll
         for (int i = 0; i < 12; ++i) P[i] = poses[12 * g + i];
+        // contact layout: the finger of contact i is that of its link; the set is
+        // realisable iff every link is a hand link, every point an object point
+        // and the fingers increase strictly with i
+        uint32_t used = 0;
+        bool ok = true;
+        int prev = -1;
+        for (int i = 0; i < k; ++i) {
+            const int l = set_link[id * k + i], idx = set_pt[id * k + i];
+            int fl = -1;
+            for (int ff = 0; ff < H.F; ++ff)
+                if (l >= H.finger_first[ff] && l < H.finger_first[ff] + H.finger_dof[ff]) fl = ff;
+            ok = ok && fl > prev && idx >= 0 && idx < N;
+            prev = fl;
+            if (fl >= 0) used |= 1u << fl;
+        }
+        if (!ok) used = 0;
         float dep = -INFINITY, emax = 0.f, amax = 0.f;
         if (f < H.F) {
             const int first = H.finger_first[f], d = H.finger_dof[f];
-            const int idx = set_pt[id * k + f];
-            const int l = set_link[id * k + f];
-            const float ox = pts[idx], oy = pts[N + idx], oz = pts[2 * N + idx];
-            float p[3], n[3];
-            p[0] = fmaf(P[0], ox, fmaf(P[1], oy, fmaf(P[2], oz, P[3])));
-            p[1] = fmaf(P[4], ox, fmaf(P[5], oy, fmaf(P[6], oz, P[7])));
-            p[2] = fmaf(P[8], ox, fmaf(P[9], oy, fmaf(P[10], oz, P[11])));
-            query_dir(P, nrm[idx], nrm[N + idx], nrm[2 * N + idx], n[0], n[1], n[2]);
-            // reverse lookup: witness sample of (link, voxel(p), bin(n))
-            int32_t w = kNoWitness;
-            if (wit) {
-                const Affine af = finger_affine(H, P, f);
-                const int v = window_voxel(af, H.G, ox, oy, oz);
-                const int b = nearest_bin(cb, H.B, n[0], n[1], n[2]);
-                if (v >= 0) w = wit[((int64_t)l * H.G * H.G * H.G + v) * H.B + b];
-            }
+            const int ci = ((used >> f) & 1u) ? __popc(used & ((1u << f) - 1u)) : -1;  // this finger's contact
             float q[DM];
-#pragma unroll
-            for (int t = 0; t < DM; ++t) {
-                q[t] = 0.f;
-                if (t < d) {
-                    const int j = first + t;
-                    q[t] = (w >= 0 && w < H.samples) ? joint_sample(H, f, (uint32_t)w, t)
-                                                     : 0.5f * (H.limits[2 * j] + H.limits[2 * j + 1]);
+            int tl = -1;  // link index within the finger of the contact (-1: none)
+            float p[3] = {0.f, 0.f, 0.f}, n[3] = {0.f, 0.f, 1.f};
+            if (ci >= 0) {
+                const int idx = set_pt[id * k + ci];
+                const int l = set_link[id * k + ci];
+                const float ox = pts[idx], oy = pts[N + idx], oz = pts[2 * N + idx];
+                p[0] = fmaf(P[0], ox, fmaf(P[1], oy, fmaf(P[2], oz, P[3])));
+                p[1] = fmaf(P[4], ox, fmaf(P[5], oy, fmaf(P[6], oz, P[7])));
+                p[2] = fmaf(P[8], ox, fmaf(P[9], oy, fmaf(P[10], oz, P[11])));
+                query_dir(P, nrm[idx], nrm[N + idx], nrm[2 * N + idx], n[0], n[1], n[2]);
+                // reverse lookup: witness sample of (link, voxel(p), bin(n))
+                int32_t w = kNoWitness;
+                if (wit) {
+                    const Affine af = finger_affine(H, P, f);
+                    const int v = window_voxel(af, H.G, ox, oy, oz);
+                    const int b = nearest_bin(cb, H.B, n[0], n[1], n[2]);
+                    if (v >= 0) w = wit[((int64_t)l * H.G * H.G * H.G + v) * H.B + b];
                 }
-            }
-            const int tl = l - first;  // link index within the finger
-            const float *cap = H.capsule + 7 * l;
-            const float r = cap[6];
-            float loc_p[3] = {0.f, 0.f, 0.f}, loc_n[3] = {0.f, 0.f, 1.f};
-            for (int it = 0; it < ik.iters; ++it) {
-                float o[DM][3], z[DM][3];
-                Tf T, Tl;
 #pragma unroll
                 for (int t = 0; t < DM; ++t) {
+                    q[t] = 0.f;
                     if (t < d) {
                         const int j = first + t;
-                        T = joint_frame(H, T, t > 0, j, q[t]);
-                        o[t][0] = T.m[3];
-                        o[t][1] = T.m[7];
-                        o[t][2] = T.m[11];
-                        tf_dir(T, H.axis[3 * j], H.axis[3 * j + 1], H.axis[3 * j + 2], z[t][0], z[t][1], z[t][2]);
-                        if (t == tl) Tl = T;
+                        q[t] = (w >= 0 && w < H.samples) ? joint_sample(H, f, (uint32_t)w, t)
+                                                         : 0.5f * (H.limits[2 * j] + H.limits[2 * j + 1]);
                     }
                 }
-                float pt[3], nt[3];
-                if (it == 0 || it >= ik.phase1) {
-                    float A[3], Bq[3];
-                    tf_point(Tl, cap[0], cap[1], cap[2], A[0], A[1], A[2]);
-                    tf_point(Tl, cap[3], cap[4], cap[5], Bq[0], Bq[1], Bq[2]);
-                    capsule_aligned(A, Bq, r, p, n, ik.beta, pt, nt);
-                    const float dx = pt[0] - Tl.m[3], dy = pt[1] - Tl.m[7], dz = pt[2] - Tl.m[11];
+                tl = l - first;
+                const float *cap = H.capsule + 7 * l;
+                const float r = cap[6];
+                float loc_p[3] = {0.f, 0.f, 0.f}, loc_n[3] = {0.f, 0.f, 1.f};
+                for (int it = 0; it < ik.iters; ++it) {
+                    float o[DM][3], z[DM][3];
+                    Tf T, Tl;
+#pragma unroll
+                    for (int t = 0; t < DM; ++t) {
+                        if (t < d) {
+                            const int j = first + t;
+                            T = joint_frame(H, T, t > 0, j, q[t]);
+                            o[t][0] = T.m[3];
+                            o[t][1] = T.m[7];
+                            o[t][2] = T.m[11];
+                            tf_dir(T, H.axis[3 * j], H.axis[3 * j + 1], H.axis[3 * j + 2], z[t][0], z[t][1], z[t][2]);
+                            if (t == tl) Tl = T;
+                        }
+                    }
+                    float pt[3], nt[3];
+                    if (it == 0 || it >= ik.phase1) {
+                        float A[3], Bq[3];
+                        tf_point(Tl, cap[0], cap[1], cap[2], A[0], A[1], A[2]);
+                        tf_point(Tl, cap[3], cap[4], cap[5], Bq[0], Bq[1], Bq[2]);
+                        capsule_aligned(A, Bq, r, p, n, ik.beta, pt, nt);
+                        const float dx = pt[0] - Tl.m[3], dy = pt[1] - Tl.m[7], dz = pt[2] - Tl.m[11];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            loc_p[c] = fmaf(Tl.m[c], dx, fmaf(Tl.m[4 + c], dy, Tl.m[8 + c] * dz));
+                            loc_n[c] = fmaf(Tl.m[c], nt[0], fmaf(Tl.m[4 + c], nt[1], Tl.m[8 + c] * nt[2]));
+                        }
+                    } else {
+                        tf_point(Tl, loc_p[0], loc_p[1], loc_p[2], pt[0], pt[1], pt[2]);
+                        tf_dir(Tl, loc_n[0], loc_n[1], loc_n[2], nt[0], nt[1], nt[2]);
+                    }
+                    float x2[3], e[6];
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        loc_p[c] = fmaf(Tl.m[c], dx, fmaf(Tl.m[4 + c], dy, Tl.m[8 + c] * dz));
-                        loc_n[c] = fmaf(Tl.m[c], nt[0], fmaf(Tl.m[4 + c], nt[1], Tl.m[8 + c] * nt[2]));
+                        x2[c] = fmaf(ik.beta, nt[c], pt[c]);
+                        e[c] = p[c] - pt[c];
+                        e[3 + c] = fmaf(ik.beta, n[c], p[c]) - x2[c];
                     }
-                } else {
-                    tf_point(Tl, loc_p[0], loc_p[1], loc_p[2], pt[0], pt[1], pt[2]);
-                    tf_dir(Tl, loc_n[0], loc_n[1], loc_n[2], nt[0], nt[1], nt[2]);
-                }
-                float x2[3], e[6];
+                    float Jc[DM][6];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    x2[c] = fmaf(ik.beta, nt[c], pt[c]);
-                    e[c] = p[c] - pt[c];
-                    e[3 + c] = fmaf(ik.beta, n[c], p[c]) - x2[c];
-                }
-                float Jc[DM][6];
+                    for (int t = 0; t < DM; ++t) {
+                        const bool on = t < d && t <= tl;
 #pragma unroll
-                for (int t = 0; t < DM; ++t) {
-                    const bool on = t < d && t <= tl;
-#pragma unroll
-                    for (int s = 0; s < 2; ++s) {
-                        const float *x = s == 0 ? pt : x2;
-                        const float vx = x[0] - o[t][0], vy = x[1] - o[t][1], vz = x[2] - o[t][2];
-                        Jc[t][3 * s + 0] = on ? z[t][1] * vz - z[t][2] * vy : 0.f;
-                        Jc[t][3 * s + 1] = on ? z[t][2] * vx - z[t][0] * vz : 0.f;
-                        Jc[t][3 * s + 2] = on ? z[t][0] * vy - z[t][1] * vx : 0.f;
+                        for (int s = 0; s < 2; ++s) {
+                            const float *x = s == 0 ? pt : x2;
+                            const float vx = x[0] - o[t][0], vy = x[1] - o[t][1], vz = x[2] - o[t][2];
+                            Jc[t][3 * s + 0] = on ? z[t][1] * vz - z[t][2] * vy : 0.f;
+                            Jc[t][3 * s + 1] = on ? z[t][2] * vx - z[t][0] * vz : 0.f;
+                            Jc[t][3 * s + 2] = on ? z[t][0] * vy - z[t][1] * vx : 0.f;
+                        }
                     }
-                }
-                // normal equations (J^T J + lambda I) dq = J^T e, Cholesky in place
-                float M[DM][DM], gv[DM];
+                    // normal equations (J^T J + lambda I) dq = J^T e, Cholesky in place
+                    float M[DM][DM], gv[DM];
 #pragma unroll
-                for (int i = 0; i < DM; ++i) {
-                    float acc = 0.f;
+                    for (int i = 0; i < DM; ++i) {
+                        float acc = 0.f;
 #pragma unroll
-                    for (int rr = 0; rr < 6; ++rr) acc = fmaf(Jc[i][rr], e[rr], acc);
-                    gv[i] = acc;
+                        for (int rr = 0; rr < 6; ++rr) acc = fmaf(Jc[i][rr], e[rr], acc);
+                        gv[i] = acc;
+#pragma unroll
+                        for (int j = 0; j < DM; ++j) {
+                            float s2 = 0.f;
+#pragma unroll
+                            for (int rr = 0; rr < 6; ++rr) s2 = fmaf(Jc[i][rr], Jc[j][rr], s2);
+                            M[i][j] = s2 + (i == j ? ik.lambda : 0.f);
+                        }
+                    }
+                    bool ok = true;
 #pragma unroll
                     for (int j = 0; j < DM; ++j) {
-                        float s2 = 0.f;
+                        float s2 = M[j][j];
 #pragma unroll
-                        for (int rr = 0; rr < 6; ++rr) s2 = fmaf(Jc[i][rr], Jc[j][rr], s2);
-                        M[i][j] = s2 + (i == j ? ik.lambda : 0.f);
+                        for (int kk = 0; kk < j; ++kk) s2 = fmaf(-M[j][kk], M[j][kk], s2);
+                        ok &= s2 > 0.f;
+                        const float dd = sqrtf(fmaxf(s2, 1e-30f));
+                        M[j][j] = dd;
+                        const float inv = 1.0f / dd;
+#pragma unroll
+                        for (int i = j + 1; i < DM; ++i) {
+                            float t2 = M[i][j];
+#pragma unroll
+                            for (int kk = 0; kk < j; ++kk) t2 = fmaf(-M[i][kk], M[j][kk], t2);
+                            M[i][j] = t2 * inv;
+                        }
+                    }
+                    if (!ok) break;
+#pragma unroll
+                    for (int i = 0; i < DM; ++i) {
+                        float t2 = gv[i];
+#pragma unroll
+                        for (int kk = 0; kk < i; ++kk) t2 = fmaf(-M[i][kk], gv[kk], t2);
+                        gv[i] = t2 / M[i][i];
+                    }
+#pragma unroll
+                    for (int i = DM - 1; i >= 0; --i) {
+                        float t2 = gv[i];
+#pragma unroll
+                        for (int kk = i + 1; kk < DM; ++kk) t2 = fmaf(-M[kk][i], gv[kk], t2);
+                        gv[i] = t2 / M[i][i];
+                    }
+#pragma unroll
+                    for (int t = 0; t < DM; ++t) {
+                        if (t < d) {
+                            const int j = first + t;
+                            q[t] = fminf(fmaxf(q[t] + gv[t], H.limits[2 * j]), H.limits[2 * j + 1]);
+                        }
                     }
                 }
-                bool ok = true;
-#pragma unroll
-                for (int j = 0; j < DM; ++j) {
-                    float s2 = M[j][j];
-#pragma unroll
-                    for (int kk = 0; kk < j; ++kk) s2 = fmaf(-M[j][kk], M[j][kk], s2);
-                    ok &= s2 > 0.f;
-                    const float dd = sqrtf(fmaxf(s2, 1e-30f));
-                    M[j][j] = dd;
-                    const float inv = 1.0f / dd;
-#pragma unroll
-                    for (int i = j + 1; i < DM; ++i) {
-                        float t2 = M[i][j];
-#pragma unroll
-                        for (int kk = 0; kk < j; ++kk) t2 = fmaf(-M[i][kk], M[j][kk], t2);
-                        M[i][j] = t2 * inv;
-                    }
-                }
-                if (!ok) break;
-#pragma unroll
-                for (int i = 0; i < DM; ++i) {
-                    float t2 = gv[i];
-#pragma unroll
-                    for (int kk = 0; kk < i; ++kk) t2 = fmaf(-M[i][kk], gv[kk], t2);
-                    gv[i] = t2 / M[i][i];
-                }
-#pragma unroll
-                for (int i = DM - 1; i >= 0; --i) {
-                    float t2 = gv[i];
-#pragma unroll
-                    for (int kk = i + 1; kk < DM; ++kk) t2 = fmaf(-M[kk][i], gv[kk], t2);
-                    gv[i] = t2 / M[i][i];
-                }
+            } else {
+                // a finger without contact takes uniform random joint values (Sec. 5.6)
+                uint32_t w[8];
+                philox4x32_10((uint32_t)(ik.pose_offset + g), (uint32_t)dr, kPurposeUnused | ((uint32_t)(2 * f) << 8),
+                              ik.request_id, ik.seed_lo, ik.seed_hi, w);
+                if (d > 4)
+                    philox4x32_10((uint32_t)(ik.pose_offset + g), (uint32_t)dr,
+                                  kPurposeUnused | ((uint32_t)(2 * f + 1) << 8), ik.request_id, ik.seed_lo,
+                                  ik.seed_hi, w + 4);
 #pragma unroll
                 for (int t = 0; t < DM; ++t) {
+                    q[t] = 0.f;
                     if (t < d) {
-                        const int j = first + t;
-                        q[t] = fminf(fmaxf(q[t] + gv[t], H.limits[2 * j]), H.limits[2 * j + 1]);
+                        const float lo = H.limits[2 * (first + t)], hi = H.limits[2 * (first + t) + 1];
+                        q[t] = fmaf(hi - lo, u01f(w[t]), lo);
                     }
                 }
             }
@@ -402,8 +461,16 @@ k_realize(DevHand H, const int32_t *__restrict__ wit, SdfDev S, const float *__r
                     q_out[a * H.J + j] = q[t];
                 }
             }
-            cerr[a * k + f] = emax;
-            cang[a * k + f] = amax;
+            if (ci >= 0) {
+                cerr[a * k + ci] = emax;
+                cang[a * k + ci] = amax;
+            }
+        }
+        if (!ok && f < k) {  // not realisable: no contact is met
+            cerr[a * k + f] = INFINITY;
+            cang[a * k + f] = INFINITY;
+            emax = INFINITY;
+            amax = INFINITY;
         }
         // hand self-collision: this finger's links against those of the higher
         // fingers of the set (the 8 lanes of a set are in one wave)
@@ -440,6 +507,27 @@ k_realize(DevHand H, const int32_t *__restrict__ wit, SdfDev S, const float *__r
     }
 }
 
+// up to 6 joints per finger: two waves per SIMD (at most 256 registers)
+template <int DM>
+__global__ void __launch_bounds__(kRealizeThreads) __attribute__((amdgpu_waves_per_eu(2)))
+k_realize(LG_REALIZE_ARGS)
+{
+    __shared__ float cb[3 * kMaxBins];
+    __shared__ float caps[kRealizeThreads][DM][6];
+    realize_sets<DM>(cb, caps, LG_REALIZE_PASS);
+}
+
+// 7 or 8 joints per finger: one wave per SIMD rather than spilling
+__global__ void __launch_bounds__(kRealizeThreads) k_realize_wide(LG_REALIZE_ARGS)
+{
+    __shared__ float cb[3 * kMaxBins];
+    __shared__ float caps[kRealizeThreads][8][6];
+    realize_sets<8>(cb, caps, LG_REALIZE_PASS);
+}
+
+#undef LG_REALIZE_ARGS
+#undef LG_REALIZE_PASS
+
 }  // namespace lg
 
 using namespace lg;
@@ -452,7 +540,7 @@ extern "C" lg_status lg_realize(const lg_field *field, const lg_sdf *sdf, const 
 {
     if (!field || !sdf || !p) return fail(LG_EINVAL, "null field, sdf or params");
     const DevHand &H = field->dh;
-    if (k != H.F) return fail(LG_EINVAL, "k must equal the number of fingers");
+    if (k < 1 || k > H.F) return fail(LG_EINVAL, "need 1 <= k <= number of fingers");
     if (n_points <= 0 || n_poses <= 0 || draws <= 0 || max_acc < 0)
         return fail(LG_EINVAL, "bad sizes");
     if (sdf->dims < 2 || !(sdf->h > 0.f) || !sdf->values) return fail(LG_EINVAL, "bad sdf");
@@ -462,7 +550,8 @@ extern "C" lg_status lg_realize(const lg_field *field, const lg_sdf *sdf, const 
         !contact_ang || !depth || !valid)
         return fail(LG_EINVAL, "null device buffer");
     SdfDev S{sdf->origin[0], sdf->origin[1], sdf->origin[2], sdf->h, 1.0f / sdf->h, sdf->dims, sdf->values};
-    IkDev ik{p->iters, p->phase1, p->lambda, p->beta, p->tol_pos, p->tol_ang, p->margin, p->self_collision};
+    IkDev ik{p->iters, p->phase1, p->lambda, p->beta, p->tol_pos, p->tol_ang, p->margin, p->self_collision,
+             (uint32_t)p->seed, (uint32_t)(p->seed >> 32), p->request_id, p->pose_offset};
     hipStream_t s = as_stream(stream);
     // grid-stride launch sized to the device, not to the max_acc upper bound
     int dev = 0, n_cu = 0;
@@ -471,16 +560,17 @@ extern "C" lg_status lg_realize(const lg_field *field, const lg_sdf *sdf, const 
     const int64_t threads = std::min<int64_t>((int64_t)max_acc * 8, (int64_t)n_cu * 16 * kRealizeThreads);
     const dim3 grid((unsigned)std::max<int64_t>(1, (threads + kRealizeThreads - 1) / kRealizeThreads));
     const int32_t *wit = field->has_witness ? field->d_wit : nullptr;
-#define LG_REALIZE(DM)                                                                                          \
-    hipLaunchKernelGGL(k_realize<DM>, grid, dim3(kRealizeThreads), 0, s, H, wit, S, pts, nrm, n_points, poses,  \
-                       set_pt, set_link, k, draws, acc_list, n_acc_dev, max_acc, ik, q_out, contact_err,        \
+#define LG_REALIZE(KERNEL)                                                                                      \
+    hipLaunchKernelGGL(KERNEL, grid, dim3(kRealizeThreads), 0, s, H, wit, S, pts, nrm, n_points, poses,     \
+                       set_pt, set_link, k, draws, (int64_t)n_poses * draws, acc_list, n_acc_dev, max_acc, ik,  \
+                       q_out, contact_err,                                                                      \
                        contact_ang, depth, valid)
     if (field->max_dof <= 4)
-        LG_REALIZE(4);
+        LG_REALIZE(k_realize<4>);
     else if (field->max_dof <= 6)
-        LG_REALIZE(6);
+        LG_REALIZE(k_realize<6>);
     else
-        LG_REALIZE(8);
+        LG_REALIZE(k_realize_wide);
 #undef LG_REALIZE
     LG_HIP(hipGetLastError());
     return LG_OK;

@@ -22,6 +22,40 @@ __device__ inline int select_in_word(uint32_t x, uint32_t r)
     return __ffs(x) - 1;
 }
 
+constexpr uint32_t kPurposeFingers = 13u;
+
+// Contact fingers of set d of pose gg (global index) as a bit mask: k picks
+// without replacement among the eligible fingers (non-empty domains), pick j
+// taking the floor(w_j (c - j) / 2^32)-th remaining one in increasing finger
+// order; contact i goes to the i-th lowest bit.  With c == k every eligible
+// finger is picked whatever the words, so they are not drawn.
+__device__ inline uint32_t choose_fingers(uint32_t elig, int k, uint32_t gg, int d, uint32_t request_id,
+                                          uint32_t seed_lo, uint32_t seed_hi)
+{
+    const int c = __popc(elig);
+    if (c <= k) return c == k ? elig : 0u;
+    uint32_t w[8];
+    philox4x32_10(gg, (uint32_t)d, kPurposeFingers, request_id, seed_lo, seed_hi, w);
+    if (k > 4) philox4x32_10(gg, (uint32_t)d, kPurposeFingers | (1u << 8), request_id, seed_lo, seed_hi, w + 4);
+    uint32_t left = elig, mask = 0;
+    for (int j = 0; j < k; ++j) {
+        uint32_t x = left;
+        for (uint32_t r = __umulhi(w[j], (uint32_t)(c - j)); r > 0; --r) x &= x - 1u;
+        const uint32_t bit = x & (0u - x);
+        mask |= bit;
+        left &= ~bit;
+    }
+    return mask;
+}
+
+// eligible fingers of pose g: those whose domain is non-empty
+__device__ inline uint32_t eligible_fingers(const uint32_t *__restrict__ dom_count, int64_t g, int F)
+{
+    uint32_t e = 0;
+    for (int f = 0; f < F; ++f) e |= (dom_count[g * F + f] > 0 ? 1u : 0u) << f;
+    return e;
+}
+
 // Reverse lookup (Sec. 5.5): among the links of finger i whose own table is
 // hit at point idx under the pose, the floor(r * count / 2^32)-th; -1 if none.
 __device__ inline int pick_link(const DevHand &H, const uint32_t *__restrict__ bits, const float *cb,
@@ -62,8 +96,9 @@ k_draw(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ p
     for (int i = threadIdx.x; i < 3 * H.B; i += blockDim.x) cb[i] = H.bin_c[i];
     if (threadIdx.x < F) counts[threadIdx.x] = dom_count[(int64_t)g * F + threadIdx.x];
     __syncthreads();
-    bool empty = false;
-    for (int f = 0; f < F; ++f) empty |= counts[f] == 0;
+    uint32_t elig = 0;
+    for (int f = 0; f < F; ++f) elig |= (counts[f] > 0 ? 1u : 0u) << f;
+    const bool empty = __popc(elig) < k;  // fewer than k usable domains
     if (threadIdx.x == 0) pose_valid[g] = empty ? 0 : 1;
     if (empty) {
         for (int i = threadIdx.x; i < D * k; i += blockDim.x) {
@@ -98,11 +133,14 @@ k_draw(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ p
                           seed_hi, w + 4 * blk);
         int32_t *sp = set_pt + ((int64_t)g * D + d) * k;
         int8_t *sl = set_link + ((int64_t)g * D + d) * k;
+        uint32_t fm = choose_fingers(elig, k, (uint32_t)(pose_offset + g), d, request_id, seed_lo, seed_hi);
         for (int i = 0; i < k; ++i) {
-            const uint32_t cnt = counts[i];
+            const int f = __ffs(fm) - 1;  // finger of contact i
+            fm &= fm - 1u;
+            const uint32_t cnt = counts[f];
             const uint32_t j = __umulhi(w[i], cnt);
             // rank: last superblock with prefix <= j
-            const uint32_t *pf = prefix + i * (nsb + 1);
+            const uint32_t *pf = prefix + f * (nsb + 1);
             int lo = 0, hi = nsb;  // invariant pf[lo] <= j < pf[hi]
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
@@ -111,7 +149,7 @@ k_draw(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ p
             uint32_t rem = j - pf[lo];
             int idx = -1;
             for (int wi = lo * kSuper; wi < min(NW, (lo + 1) * kSuper); ++wi) {
-                const uint32_t x = dom[(int64_t)i * NW + wi];
+                const uint32_t x = dom[(int64_t)f * NW + wi];
                 const uint32_t pc = __popc(x);
                 if (rem < pc) {
                     idx = wi * 32 + select_in_word(x, rem);
@@ -120,7 +158,7 @@ k_draw(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ p
                 rem -= pc;
             }
             sp[i] = idx;
-            sl[i] = (int8_t)(idx >= 0 ? pick_link(H, bits, cb, pts, nrm, N, pose, i, idx, w[k + i]) : -1);
+            sl[i] = (int8_t)(idx >= 0 ? pick_link(H, bits, cb, pts, nrm, N, pose, f, idx, w[k + i]) : -1);
         }
     }
 }
@@ -407,7 +445,7 @@ k_verdict_lane(const float *__restrict__ pts, const float *__restrict__ nrm, int
     const int tid = threadIdx.x;
     const int64_t n_work = (int64_t)(*n_valid_poses) * D;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    // grid-stride over the sets of poses whose domains are all non-empty
+    // grid-stride over the sets of poses with at least k non-empty domains
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + tid; t < n_work; t += stride) {
         const int64_t sid = (int64_t)valid_poses[t / D] * D + (t % D);
         const int32_t *sp = set_pt + sid * k;
@@ -610,7 +648,8 @@ __device__ int project_domain(const GridDev &g, const uint32_t *__restrict__ cel
 template <int KM, int GS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, const int32_t *__restrict__ valid_poses,
-           const int32_t *__restrict__ n_valid_poses, const uint32_t *__restrict__ dom_bits, int F, int D, int k, int m,
+           const int32_t *__restrict__ n_valid_poses, const uint32_t *__restrict__ dom_bits,
+           const uint32_t *__restrict__ dom_count, int F, int D, int k, int m,
            double mu, double rho, double eps, int max_pivots, LpConst cs, int n_outer, int n_inner, double sigma,
            uint32_t seed_lo, uint32_t seed_hi, uint32_t request_id, int64_t pose_offset,
            const GridDev *__restrict__ gdp, const uint32_t *__restrict__ cell_start,
@@ -637,6 +676,17 @@ k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, 
         const int d = (int)(t % D);
         const int64_t sid = pg * D + d;
         int32_t *sp = set_pt + sid * k;
+        const uint32_t fm = choose_fingers(eligible_fingers(dom_count, pg, F), k, (uint32_t)(pose_offset + pg), d,
+                                           request_id, seed_lo, seed_hi);
+        bool drawn = fm != 0;
+        for (int i = 0; i < k; ++i) drawn &= sp[i] >= 0 && sp[i] < N;
+        if (!drawn) {  // not a drawn set (inconsistent domain sizes): no criterion
+            if (j == 0) {
+                verdict[sid] = 0;
+                tstar[sid] = __builtin_nan("");
+            }
+            continue;  // uniform over the group
+        }
         for (int i = 0; i < k; ++i) {
             cur[i][tid] = sp[i];
             load(i, sp[i]);
@@ -658,10 +708,11 @@ k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, 
                     const double u2 = (double)(w[1] >> 8) * (1.0 / 16777216.0);
                     const double rr = sqrt(-2.0 * log(u1));
                     const double dx = sigma * rr * cos(2.0 * M_PI * u2), dy = sigma * rr * sin(2.0 * M_PI * u2);
-                    cand = project_domain(g, cell_start, cell_pts, pts, N, dom_bits + (pg * F + i) * NW,
+                    const int fi = select_in_word(fm, (uint32_t)i);  // finger of contact i
+                    cand = project_domain(g, cell_start, cell_pts, pts, N, dom_bits + (pg * F + fi) * NW,
                                           px + dx * tx[0] + dy * ty[0], py + dx * tx[1] + dy * ty[1],
                                           pz + dx * tx[2] + dy * ty[2]);
-                    if (cand >= 0) {  // always, for a pose whose domains are all non-empty
+                    if (cand >= 0) {  // always, for a drawn set (its domains are non-empty)
                         load(i, cand);
                         int st = 0;
                         Jc = lp_lane<KM>(cd, tid, k, m, mu, rho, max_pivots, cs, st);
@@ -693,9 +744,10 @@ k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, 
 // picked with the set's draw words exactly as k_draw does
 __global__ void k_relink(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ pts,
                          const float *__restrict__ nrm, int N, const float *__restrict__ poses,
-                         const int32_t *__restrict__ valid_poses, const int32_t *__restrict__ n_valid_poses, int D,
-                         int k, uint32_t seed_lo, uint32_t seed_hi, uint32_t request_id, int64_t pose_offset,
-                         const int32_t *__restrict__ set_pt, int8_t *__restrict__ set_link)
+                         const int32_t *__restrict__ valid_poses, const int32_t *__restrict__ n_valid_poses,
+                         const uint32_t *__restrict__ dom_count, int D, int k, uint32_t seed_lo, uint32_t seed_hi,
+                         uint32_t request_id, int64_t pose_offset, const int32_t *__restrict__ set_pt,
+                         int8_t *__restrict__ set_link)
 {
     const int64_t n_work = (int64_t)(*n_valid_poses) * D;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_work;
@@ -708,8 +760,16 @@ __global__ void k_relink(DevHand H, const uint32_t *__restrict__ bits, const flo
                           seed_hi, w + 4 * blk);
         const int32_t *sp = set_pt + (g * D + d) * k;
         int8_t *sl = set_link + (g * D + d) * k;
-        for (int i = 0; i < k; ++i)
-            sl[i] = (int8_t)pick_link(H, bits, H.bin_c, pts, nrm, N, poses + 12 * g, i, sp[i], w[k + i]);
+        uint32_t fm = choose_fingers(eligible_fingers(dom_count, g, H.F), k, (uint32_t)(pose_offset + g), d,
+                                     request_id, seed_lo, seed_hi);
+        for (int i = 0; i < k; ++i) {
+            const int f = __ffs(fm) - 1;
+            fm &= fm - 1u;
+            const int idx = sp[i];
+            sl[i] = (int8_t)((f >= 0 && idx >= 0 && idx < N)
+                                 ? pick_link(H, bits, H.bin_c, pts, nrm, N, poses + 12 * g, f, idx, w[k + i])
+                                 : -1);
+        }
     }
 }
 
@@ -851,7 +911,7 @@ lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, i
     if (!field || !p) return fail(LG_EINVAL, "null field or params");
     const DevHand &H = field->dh;
     if (n_points <= 0 || n_poses < 0) return fail(LG_EINVAL, "n_points must be > 0 and n_poses >= 0");
-    if (p->k != H.F) return fail(LG_EINVAL, "k must equal the number of fingers (one contact per finger)");
+    if (p->k < 1 || p->k > H.F) return fail(LG_EINVAL, "need 1 <= k <= number of fingers (one contact per finger)");
     if (p->draws <= 0 || p->m_edges < 3 || p->m_edges > 16 || p->k > 8)
         return fail(LG_EINVAL, "need draws > 0, 3 <= m_edges <= 16, k <= 8");
     if (!(p->mu >= 0.0f) || !(p->moment_scale > 0.0f) || p->max_pivots < 0)
@@ -875,7 +935,7 @@ lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, i
                        poses, dom_bits, dom_count, p->draws, p->k, (uint32_t)p->seed, (uint32_t)(p->seed >> 32),
                        p->request_id, p->pose_offset, set_pt, set_link, ws.pose_valid, verdict, tstar);
     LG_HIP(hipGetLastError());
-    // list of poses whose domains are all non-empty (ordered)
+    // list of poses with at least k non-empty domains (ordered)
     const int64_t npc = (n_poses + kChunk - 1) / kChunk;
     hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)npc), dim3(kCompactThreads), 0, s, ws.pose_valid,
                        (int64_t)n_poses, ws.pchunk_count);
@@ -918,7 +978,7 @@ lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, i
             1, std::min<int64_t>((n_sets * gs + 255) / 256, (int64_t)n_cu * 8)));
 #define LG_OPT(KM, GS)                                                                                           \
     hipLaunchKernelGGL((k_optimize<KM, GS>), ogrid, dim3(256), 0, s, pts, nrm, n_points, ws.valid_poses,           \
-                       ws.n_valid_poses, dom_bits, H.F, p->draws, p->k, p->m_edges, (double)p->mu,                \
+                       ws.n_valid_poses, dom_bits, dom_count, H.F, p->draws, p->k, p->m_edges, (double)p->mu,     \
                        (double)p->moment_scale, (double)p->eps, p->max_pivots, cs, p->opt_outer, p->opt_inner,    \
                        (double)p->opt_sigma, (uint32_t)p->seed, (uint32_t)(p->seed >> 32), p->request_id,         \
                        p->pose_offset, ws.grid, ws.cell_start, ws.cell_pts, set_pt, verdict, tstar)
@@ -931,7 +991,7 @@ lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, i
 #undef LG_OPT
         LG_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_relink, lgrid, dim3(256), 0, s, H, field->d_bits, pts, nrm, n_points, poses,
-                           ws.valid_poses, ws.n_valid_poses, p->draws, p->k, (uint32_t)p->seed,
+                           ws.valid_poses, ws.n_valid_poses, dom_count, p->draws, p->k, (uint32_t)p->seed,
                            (uint32_t)(p->seed >> 32), p->request_id, p->pose_offset, set_pt, set_link);
     }
 #undef LG_VERDICT

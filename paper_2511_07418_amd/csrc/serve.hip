@@ -217,7 +217,8 @@ static lg_status validate_request(const lg_server_params &sp, const lg_request *
     if (!r || !r->field) return fail(LG_EINVAL, "null request or field");
     if (r->n_points <= 0 || r->n_poses <= 0 || !r->pts || !r->nrm || !r->poses)
         return fail(LG_EINVAL, "request needs points, normals and poses");
-    if (r->search.k != r->field->dh.F) return fail(LG_EINVAL, "k must equal the field's number of fingers");
+    if (r->search.k < 1 || r->search.k > r->field->dh.F)
+        return fail(LG_EINVAL, "need 1 <= k <= the field's number of fingers");
     if (r->search.draws <= 0 || r->search.m_edges < 3 || r->search.m_edges > 16)
         return fail(LG_EINVAL, "bad search parameters");
     if ((int64_t)std::min<int64_t>(sp.chunk_poses, r->n_poses) * r->search.draws > 0x7fffffffLL)
@@ -262,8 +263,12 @@ static lg_status launch_chunk(lg_server *S, Req *q)
         sdf.dims = r.sdf_dims;
         sdf.values = reinterpret_cast<const float *>(base + L.sdf);
         valid = reinterpret_cast<uint8_t *>(base + L.valid);
+        lg_ik_params ik = r.ik;  // random joints of fingers without contact: keyed like the search
+        ik.seed = sp.seed;
+        ik.request_id = sp.request_id;
+        ik.pose_offset = sp.pose_offset;
         st = lg_realize(r.field, &sdf, pts, nrm, r.n_points, poses, P, set_pt, set_link, sp.k, sp.draws, acc, n_acc,
-                        P * sp.draws, &r.ik, reinterpret_cast<float *>(base + L.q),
+                        P * sp.draws, &ik, reinterpret_cast<float *>(base + L.q),
                         reinterpret_cast<float *>(base + L.err), reinterpret_cast<float *>(base + L.ang),
                         reinterpret_cast<float *>(base + L.depth), valid, s);
         if (st != LG_OK) return st;

@@ -64,7 +64,8 @@ class SearchParams(C.Structure):
 class IkParams(C.Structure):
     _fields_ = [("iters", C.c_int32), ("phase1", C.c_int32), ("lam", C.c_float),
                 ("beta", C.c_float), ("tol_pos", C.c_float), ("tol_ang", C.c_float),
-                ("margin", C.c_float), ("self_collision", C.c_int32)]
+                ("margin", C.c_float), ("self_collision", C.c_int32), ("seed", C.c_uint64),
+                ("request_id", C.c_uint32), ("pose_offset", C.c_int64)]
 
 
 class Sdf(C.Structure):
@@ -338,9 +339,13 @@ def lg_search(field: Field, pts, nrm, poses, dom_bits, dom_count, sp, bufs: Opti
     return bufs
 
 
-def ik_params(ik) -> IkParams:
+def ik_params(ik, sp=None) -> IkParams:
+    """Realize parameters; the random joints of fingers without contact are keyed
+    by the search parameters ``sp`` (seed, request_id, pose_offset)."""
+    seed, rid, off = (0, 0, 0) if sp is None else (int(sp.seed) & 0xFFFFFFFFFFFFFFFF, int(sp.request_id),
+                                                    int(sp.pose_offset))
     return IkParams(int(ik.iters), int(ik.phase1), float(ik.lam), float(ik.beta), float(ik.tol_pos),
-                    float(ik.tol_ang), float(ik.margin), int(getattr(ik, "self_collision", 0)))
+                    float(ik.tol_ang), float(ik.margin), int(getattr(ik, "self_collision", 0)), seed, rid, off)
 
 
 def sdf_struct(sdf_host, values_dev: torch.Tensor) -> Sdf:
@@ -359,11 +364,11 @@ class RealizeBuffers:
 
 
 def lg_realize(field: Field, sdf: Sdf, pts, nrm, poses, set_pt, set_link, k: int, draws: int, acc_list,
-               n_acc_dev, max_acc: int, ik, bufs: Optional[RealizeBuffers] = None, stream=None):
+               n_acc_dev, max_acc: int, ik, bufs: Optional[RealizeBuffers] = None, stream=None, sp=None):
     N, P = int(pts.shape[1]), int(poses.shape[0])
     if bufs is None:
         bufs = RealizeBuffers(max_acc, field.n_joints, k, pts.device)
-    ikp = ik_params(ik)
+    ikp = ik_params(ik, sp)
     _check(_lib.lg_realize(field.handle, C.byref(sdf), _ptr(pts), _ptr(nrm), N, _ptr(poses), P,
                            _ptr(set_pt), _ptr(set_link), int(k), int(draws), _ptr(acc_list), _ptr(n_acc_dev),
                            int(max_acc), C.byref(ikp), _ptr(bufs.q), _ptr(bufs.contact_err),

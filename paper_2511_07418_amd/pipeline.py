@@ -68,7 +68,7 @@ class Pipeline:
         b = self.sbuf
         lg.lg_realize(self.field, self.sdf, self.pts, self.nrm, self.poses, b.set_pt, b.set_link,
                       int(self.sp.k), int(self.sp.draws), b.acc_list, b.n_acc, self.max_acc, self.ik,
-                      bufs=self.rbuf, stream=stream)
+                      bufs=self.rbuf, stream=stream, sp=b.p)
 
     def step(self, stream=None):
         self.query(stream)

@@ -45,8 +45,9 @@ def _opt_check(w, sp, max_flag_frac=0.08):
     acc = bufs.acc_list[:int(bufs.n_acc.item())].cpu().numpy()
     d_spt, _ = oracle.draw(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses, Q["dom_bits"],
                            Q["dom_count"], sp)
-    O = oracle.optimize(w.obj.pts, w.obj.nrm, Q["dom_bits"], d_spt, sp, w.hand.n_fingers)
-    o_sln = oracle.relink(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses, O["set_pt"], sp)
+    O = oracle.optimize(w.obj.pts, w.obj.nrm, Q["dom_bits"], d_spt, sp, w.hand.n_fingers, dom_count=Q["dom_count"])
+    o_sln = oracle.relink(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses, O["set_pt"], sp,
+                          dom_count=Q["dom_count"])
     P, D, k = spt.shape
     valid = (d_spt >= 0).all(-1).reshape(-1)
     flag = O["oflag"].astype(bool)
@@ -77,6 +78,13 @@ def test_optimize_c1_full():
 def test_optimize_group_sizes(inner):
     w = synth.workload("c1", n_poses=96)
     sp = dataclasses.replace(w.search, opt_outer=1, opt_inner=inner, opt_sigma=0.006, request_id=inner)
+    _opt_check(w, sp)
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_optimize_k_below_f(k):
+    w = synth.workload("c3", samples=4096, n_poses=48, n_points=4096)
+    sp = dataclasses.replace(w.search, k=k, opt_outer=1, opt_inner=8, opt_sigma=0.004)
     _opt_check(w, sp)
 
 

@@ -296,7 +296,8 @@ def _realize_check(w, n_sets_max=4000):
     sdf = lg.sdf_struct(w.sdf, sdf_vals)
     n_acc = dev(np.array([len(acc)], np.int32))
     bufs = lg.lg_realize(field, sdf, soa(w.obj.pts), soa(w.obj.nrm), dev(w.poses), dev(o_spt),
-                         dev(o_sln.astype(np.int8)), k, w.search.draws, dev(acc), n_acc, len(acc), w.ik)
+                         dev(o_sln.astype(np.int8)), k, w.search.draws, dev(acc), n_acc, len(acc), w.ik,
+                         sp=w.search)
     torch.cuda.synchronize()
     q = bufs.q.cpu().numpy().astype(np.float64)
     err = bufs.contact_err.cpu().numpy()
