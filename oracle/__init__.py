@@ -139,6 +139,8 @@ def lib():
         L.orc_axis_samples.restype = C.c_int
         L.orc_penetration.argtypes = [vp, vp, vp, vp]
         L.orc_penetration.restype = dbl
+        L.orc_concave_filter.argtypes = [vp, vp, vp, i32, dbl, i32, dbl, vp, vp, vp]
+        L.orc_concave_filter.restype = C.c_int
         L.orc_realize.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, i32, i32, vp, i32, vp,
                                   u64, C.c_uint32, i64, vp, vp, vp, vp, vp, vp, vp]
         L.orc_realize.restype = C.c_int
@@ -533,6 +535,23 @@ def penetration(hand, q, sdf, pose) -> float:
     T = fk(hand, q)
     pp = _c(pose, np.float32)
     return lib().orc_penetration(H.ref, _p(T), S.ref, _p(pp))
+
+
+def concave_filter(sdf, pts, nrm, box_edge: float, lattice: int, max_depth: float) -> dict:
+    """Sec. 5.2 object preprocessing: per point the penetration depth of a cube of
+    edge ``box_edge`` standing on the surface there, keep = depth <= max_depth,
+    and the band flag of each decision."""
+    pts, nrm = _c(pts, np.float32), _c(nrm, np.float32)
+    n = pts.shape[0]
+    dep = np.zeros(n)
+    keep = np.zeros(n, np.uint8)
+    fl = np.zeros(n, np.uint8)
+    S = _sdf(sdf)
+    rc = lib().orc_concave_filter(S.ref, _p(pts), _p(nrm), n, float(np.float32(box_edge)), int(lattice),
+                                  float(np.float32(max_depth)), _p(dep), _p(keep), _p(fl))
+    if rc != 0:
+        raise ValueError(f"orc_concave_filter failed ({rc})")
+    return {"depth": dep, "keep": keep, "flag": fl}
 
 
 def realize(hand, fp, wit, sdf, pts, nrm, poses, set_pt, set_link, sp, acc_list, ik) -> dict:

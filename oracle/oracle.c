@@ -1587,6 +1587,44 @@ double orc_sdf_eval(const orc_sdf *S, const double *y)
     return acc;
 }
 
+/* Object preprocessing (Sec. 5.2): penetration of a small box placed at each
+ * object point.  The box is a cube of edge s whose bottom face is centred at
+ * the point p, with axes (x, y, n): the Duff basis of the unit outward normal
+ * n, and n itself, so the cube stands on the surface outside the object.  Its
+ * penetration is the largest -SDF over the lattice p + a x + b y + c n,
+ * a, b in {-s/2 + s i / m}, c in {s i / m}, i = 0..m (corners included); a
+ * lattice point outside the SDF grid counts as outside the object.  The point
+ * is kept iff the penetration is at most max_depth; flag marks penetrations
+ * within BAND_VAL of max_depth. */
+int orc_concave_filter(const orc_sdf *S, const float *pts, const float *nrm, int32_t n_points, double s, int32_t m,
+                       double max_depth, double *depth, uint8_t *keep, uint8_t *flag)
+{
+    if (n_points < 0 || !(s > 0.0) || m < 1) return ORC_EINVAL;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n_points; ++i) {
+        double p[3] = {pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]};
+        double n[3] = {nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2]};
+        const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        for (int c = 0; c < 3; ++c) n[c] /= nn;
+        double x[3], y[3];
+        duff_basis(n, x, y);
+        double worst = -INFINITY;
+        for (int ia = 0; ia <= m; ++ia)
+            for (int ib = 0; ib <= m; ++ib)
+                for (int ic = 0; ic <= m; ++ic) {
+                    const double a = -0.5 * s + s * ia / m, b = -0.5 * s + s * ib / m, c = s * ic / m;
+                    double q[3];
+                    for (int e = 0; e < 3; ++e) q[e] = p[e] + a * x[e] + b * y[e] + c * n[e];
+                    const double d = -orc_sdf_eval(S, q);
+                    if (d > worst) worst = d;
+                }
+        depth[i] = worst;
+        keep[i] = worst <= max_depth;
+        flag[i] = fabs(worst - max_depth) <= BAND_VAL;
+    }
+    return ORC_OK;
+}
+
 /* number of axis samples of a capsule: one per millimetre of axis, ends included */
 int orc_axis_samples(const orc_hand *H, int l)
 {
