@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--k", type=int, default=0,
                     help="contacts per set (0 = one per finger); below the finger count, k fingers are drawn "
                          "per set and the others take random joint values")
+    ap.add_argument("--concave-filter", action="store_true",
+                    help="drop the object's concave points first (8 mm box, 1 mm depth); the steps use the rest")
     ap.add_argument("--placement", default="canonical", choices=["canonical", "exhaustive"],
                     help="palm poses: canonical (random pose above the palm) or exhaustive (an object point "
                          "on a random contact vector of the field)")
@@ -457,7 +459,28 @@ def main():
         poses = lg.lg_place_exhaustive(field, pts_soa, nrm_soa, len(w.poses), seed=args.seed + 1)
         torch.cuda.synchronize()
     cos_hit = math.cos(math.radians(args.cone_deg)) if args.cone_deg > 0 else None
-    pipe = Pipeline(field, w.obj.pts, w.obj.nrm, poses, w.search, ik=w.ik, sdf=w.sdf, cos_hit=cos_hit)
+    obj_pts, obj_nrm, concave = w.obj.pts, w.obj.nrm, None
+    if args.concave_filter:
+        if w.sdf is None:
+            raise SystemExit("--concave-filter needs the object's SDF (workload c3)")
+        sdf_vals = torch.from_numpy(np.ascontiguousarray(w.sdf.values, np.float32)).cuda()
+        sdf_s = lg.sdf_struct(w.sdf, sdf_vals)
+        p_soa = torch.from_numpy(np.ascontiguousarray(w.obj.pts.T)).cuda()
+        n_soa = torch.from_numpy(np.ascontiguousarray(w.obj.nrm.T)).cuda()
+        lg.lg_concave_filter(sdf_s, p_soa, n_soa)          # warm-up (module load)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        cr = lg.lg_concave_filter(sdf_s, p_soa, n_soa, 0.008, 4, 0.001)
+        e1.record()
+        torch.cuda.synchronize()
+        nk = int(cr.n_kept.item())
+        po, no = lg.lg_gather_points(p_soa, n_soa, cr.kept_idx, nk)
+        obj_pts, obj_nrm = po.t().cpu().numpy(), no.t().cpu().numpy()
+        concave = {"box_edge_m": 0.008, "lattice": 4, "max_depth_m": 0.001, "kept": nk, "of": int(w.obj.n),
+                   "filter_ms": e0.elapsed_time(e1)}
+        print(f"[bench] concave filter kept {nk} of {w.obj.n} points in {concave['filter_ms']:.3f} ms",
+              file=sys.stderr, flush=True)
+    pipe = Pipeline(field, obj_pts, obj_nrm, poses, w.search, ik=w.ik, sdf=w.sdf, cos_hit=cos_hit)
     print(f"[bench] {args.workload}: field built in {t_build:.2f}s ({field.info()['bits_set']} bits), "
           f"P={pipe.P} N={pipe.N}", file=sys.stderr, flush=True)
 
@@ -578,13 +601,17 @@ def main():
                    "contact_opt": ({"rounds": args.opt_outer, "candidates": args.opt_inner,
                                     "sigma_m": args.opt_sigma} if args.opt_outer > 0 else None),
                    "self_collision": bool(args.self_collision), "placement": args.placement,
-                   "cone_deg": args.cone_deg or None, "contacts": int(w.search.k)},
+                   "cone_deg": args.cone_deg or None, "contacts": int(w.search.k), "concave_filter": concave},
         "valid_per_step": n_valid,
         "accepted_sets_per_step": n_acc,
         "stage_ms": {"query": q_ms, "search": float(st[:, 1].mean()), "realize": float(st[:, 2].mean())},
         "query_gbps": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": query_traffic(),
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     # the counters were taken on the default query (canonical poses, all points, nearest bin)
+                     "traffic": (query_traffic() if (args.placement == "canonical" and not args.cone_deg
+                                                     and not args.concave_filter and args.workload == "c3"
+                                                     and args.seed == 0) else None),
                      "kernel": "k_query", "alg_bytes_per_launch": alg_bytes,
                      "in_window_link_lookups": link_lookups, "in_window_finger_lookups": finger_lookups,
                      "impl_bytes_per_launch": impl_bytes,

@@ -357,6 +357,31 @@ double lg_serve_clock(lg_server *srv);
 /* Finish in-flight chunks, cancel the rest, free everything. */
 lg_status lg_serve_destroy(lg_server *srv);
 
+/* ---- object preprocessing ----------------------------------------------------
+ * lg_concave_filter -- concave-point removal of Sec. 5.2: a point is dropped
+ * when a small box placed at it penetrates the object.  The box is a cube of
+ * edge box_edge (m) standing on the surface: bottom face centred at the point
+ * p, axes (x, y, n) with n the unit outward normal and (x, y) its Duff et al.
+ * (2017) tangents.  depth = max of -SDF (trilinear, +inf outside the grid)
+ * over the lattice p + a x + b y + c n, a, b = -s/2 + s i / m, c = s i / m,
+ * i = 0..m (m = lattice, 1..16); keep = depth <= max_depth.
+ * Inputs: sdf (device grid), pts/nrm DEVICE SoA [3][N].  Outputs (device):
+ * depth [N] float, keep [N] uint8, kept_idx [N] int32 (kept point indices in
+ * increasing order; entries past n_kept are not written), n_kept [1] int32.
+ * LG_EINVAL on a bad sdf, box_edge <= 0, lattice outside 1..16, NaN max_depth
+ * or null buffers.  N = 0 writes n_kept = 0 only.
+ */
+lg_status lg_concave_filter(const lg_sdf *sdf, const float *pts, const float *nrm, int32_t n_points,
+                            float box_edge, int32_t lattice, float max_depth, float *depth, uint8_t *keep,
+                            int32_t *kept_idx, int32_t *n_kept, void *stream);
+
+/* lg_gather_points -- pts_out/nrm_out DEVICE SoA [3][n_out] = the columns
+ * idx[0..n_out) of pts/nrm DEVICE SoA [3][N] (e.g. the points lg_concave_filter
+ * kept, n_out read back from n_kept).  An index outside [0, N) gives NaN
+ * columns.  LG_EINVAL on negative sizes or null buffers. */
+lg_status lg_gather_points(const float *pts, const float *nrm, int32_t n_points, const int32_t *idx, int32_t n_out,
+                           float *pts_out, float *nrm_out, void *stream);
+
 /* ---- exhaustive placement ----------------------------------------------------
  * lg_place_exhaustive -- object poses of the exhaustive placement of Sec. 5.1:
  * pose g puts a random object surface point onto a random contact vector of

@@ -278,6 +278,31 @@ __device__ inline bool table_bit(const uint32_t *tab, int W, int64_t voxel, int 
     return (tab[voxel * W + (b >> 5)] >> (b & 31)) & 1u;
 }
 
+// Object signed-distance grid (object frame), [iz][iy][ix] node values.
+struct SdfDev {
+    float ox, oy, oz, h, inv_h;
+    int G;
+    const float *v;
+};
+
+// Trilinear SDF at object-frame point y; +inf outside the grid.
+__device__ inline float sdf_trilinear(const SdfDev &S, float yx, float yy, float yz)
+{
+    const float ux = (yx - S.ox) * S.inv_h, uy = (yy - S.oy) * S.inv_h, uz = (yz - S.oz) * S.inv_h;
+    const float gm = (float)(S.G - 1);
+    if (!((ux >= 0.f) & (ux <= gm) & (uy >= 0.f) & (uy <= gm) & (uz >= 0.f) & (uz <= gm))) return INFINITY;
+    const int ix = min((int)ux, S.G - 2), iy = min((int)uy, S.G - 2), iz = min((int)uz, S.G - 2);
+    const float fx = ux - ix, fy = uy - iy, fz = uz - iz;
+    const int64_t G = S.G;
+    const float *v = S.v + (iz * G + iy) * G + ix;
+    const float c00 = fmaf(fx, v[1] - v[0], v[0]);
+    const float c10 = fmaf(fx, v[G + 1] - v[G], v[G]);
+    const float c01 = fmaf(fx, v[G * G + 1] - v[G * G], v[G * G]);
+    const float c11 = fmaf(fx, v[G * G + G + 1] - v[G * G + G], v[G * G + G]);
+    const float c0 = fmaf(fy, c10 - c00, c00), c1 = fmaf(fy, c11 - c01, c01);
+    return fmaf(fz, c1 - c0, c0);
+}
+
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 }  // namespace lg

@@ -132,6 +132,8 @@ def _load():
     L.lg_serve_clock.restype = C.c_double
     L.lg_serve_destroy.argtypes = [vp]
     L.lg_place_exhaustive.argtypes = [vp, vp, vp, i32, i32, C.c_uint64, C.c_uint32, i64, vp, vp]
+    L.lg_concave_filter.argtypes = [vp, vp, vp, i32, C.c_float, i32, C.c_float, vp, vp, vp, vp, vp]
+    L.lg_gather_points.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
     L.lg_prop_num_params.restype = i64
     L.lg_prop_create.argtypes = [vp, vp, vp]
     L.lg_prop_release.argtypes = [vp]
@@ -159,7 +161,8 @@ EXPORTED = ("lg_status_str", "lg_last_error", "lg_version", "lg_build_field", "l
             "lg_field_export", "lg_field_info", "lg_field_release", "lg_query_domains", "lg_query_domains_cone",
             "lg_search_workspace_bytes", "lg_search", "lg_realize", "lg_serve_request_bytes",
             "lg_serve_create", "lg_serve_submit", "lg_serve_poll", "lg_serve_wait", "lg_serve_cancel",
-            "lg_serve_stats", "lg_serve_clock", "lg_serve_destroy", "lg_place_exhaustive", "lg_prop_num_params",
+            "lg_serve_stats", "lg_serve_clock", "lg_serve_destroy", "lg_place_exhaustive", "lg_concave_filter",
+            "lg_gather_points", "lg_prop_num_params",
             "lg_prop_create", "lg_prop_release", "lg_prop_get_params", "lg_prop_set_params",
             "lg_prop_forward", "lg_prop_backward", "lg_prop_adam", "lg_prop_train_step",
             "lg_prop_sample_mixture", "lg_prop_sample")
@@ -392,6 +395,39 @@ def lg_place_exhaustive(field: Field, pts: torch.Tensor, nrm: torch.Tensor, n_po
                                     int(seed) & 0xFFFFFFFFFFFFFFFF, int(request_id), int(pose_offset),
                                     _ptr(out), _stream(stream)), "lg_place_exhaustive")
     return out
+
+
+class ConcaveResult:
+    """Device outputs of lg_concave_filter for N points."""
+
+    def __init__(self, n_points: int, device):
+        n = max(1, n_points)
+        self.depth = torch.empty((n,), dtype=torch.float32, device=device)
+        self.keep = torch.empty((n,), dtype=torch.uint8, device=device)
+        self.kept_idx = torch.empty((n,), dtype=torch.int32, device=device)
+        self.n_kept = torch.zeros((1,), dtype=torch.int32, device=device)
+
+
+def lg_concave_filter(sdf: Sdf, pts: torch.Tensor, nrm: torch.Tensor, box_edge: float = 0.008, lattice: int = 4,
+                      max_depth: float = 0.001, out: Optional[ConcaveResult] = None, stream=None) -> ConcaveResult:
+    """Sec. 5.2 concave-point removal over SoA points/normals [3, N] (device)."""
+    N = int(pts.shape[1])
+    if out is None:
+        out = ConcaveResult(N, pts.device)
+    _check(_lib.lg_concave_filter(C.byref(sdf), _ptr(pts), _ptr(nrm), N, float(box_edge), int(lattice),
+                                  float(max_depth), _ptr(out.depth), _ptr(out.keep), _ptr(out.kept_idx),
+                                  _ptr(out.n_kept), _stream(stream)), "lg_concave_filter")
+    return out
+
+
+def lg_gather_points(pts: torch.Tensor, nrm: torch.Tensor, idx: torch.Tensor, n_out: int, stream=None):
+    """SoA [3, n_out] copies of the columns idx[:n_out] of pts/nrm [3, N] (device)."""
+    N = int(pts.shape[1])
+    po = torch.empty((3, n_out), dtype=torch.float32, device=pts.device)
+    no = torch.empty((3, n_out), dtype=torch.float32, device=pts.device)
+    _check(_lib.lg_gather_points(_ptr(pts), _ptr(nrm), N, _ptr(idx), int(n_out), _ptr(po), _ptr(no),
+                                 _stream(stream)), "lg_gather_points")
+    return po, no
 
 
 # ---- serving -----------------------------------------------------------------

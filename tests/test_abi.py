@@ -100,3 +100,25 @@ def test_search_workspace_grows_with_the_optimisation(lglib):
     b0 = L.lg_search_workspace_bytes(2048, 256, C.byref(p0))
     b1 = L.lg_search_workspace_bytes(2048, 256, C.byref(p1))
     assert b1 >= b0 + 2048 * 4 and L.lg_search_workspace_bytes(2048, 0, C.byref(p1)) == 256
+
+
+def test_concave_filter_validation_without_device_work(lglib):
+    L = lglib.lib()
+    EINVAL = lglib.LG_EINVAL
+    dummy = C.c_void_p(16)        # never dereferenced: validation fails first
+    good = lglib.Sdf((C.c_float * 3)(0, 0, 0), 0.002, 64, dummy)
+    args = (dummy, dummy, 8, 0.008, 4, 0.001, dummy, dummy, dummy, dummy, None)
+    assert L.lg_concave_filter(None, *args) == EINVAL
+    bad_sdf = lglib.Sdf((C.c_float * 3)(0, 0, 0), 0.0, 64, dummy)
+    assert L.lg_concave_filter(C.byref(bad_sdf), *args) == EINVAL
+    for edge, lat, depth in ((0.0, 4, 0.001), (-1.0, 4, 0.001), (0.008, 0, 0.001), (0.008, 17, 0.001),
+                             (0.008, 4, float("nan"))):
+        assert L.lg_concave_filter(C.byref(good), dummy, dummy, 8, edge, lat, depth, dummy, dummy, dummy, dummy,
+                                   None) == EINVAL
+    assert L.lg_concave_filter(C.byref(good), dummy, dummy, -1, 0.008, 4, 0.001, dummy, dummy, dummy, dummy,
+                               None) == EINVAL
+    assert L.lg_concave_filter(C.byref(good), None, dummy, 8, 0.008, 4, 0.001, dummy, dummy, dummy, dummy,
+                               None) == EINVAL
+    assert L.lg_gather_points(dummy, dummy, 8, dummy, -1, dummy, dummy, None) == EINVAL
+    assert L.lg_gather_points(dummy, None, 8, dummy, 4, dummy, dummy, None) == EINVAL
+    assert L.lg_gather_points(None, None, 8, None, 0, None, None, None) == lglib.LG_OK   # nothing to do
