@@ -102,8 +102,8 @@ def lib():
         L.orc_query.restype = C.c_int
         L.orc_query_cone.argtypes = [vp, vp, vp, vp, vp, i32, vp, i32, dbl, vp, vp, vp]
         L.orc_query_cone.restype = C.c_int
-        L.orc_draw.argtypes = [vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, i32, i32, u64,
-                               C.c_uint32, i64, vp, vp]
+        L.orc_draw.argtypes = [vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, i32, i32, u64, C.c_uint32, i64, vp,
+                               vp, vp]
         L.orc_draw.restype = C.c_int
         L.orc_tangent_basis.argtypes = [vp, vp, vp]
         L.orc_wrench_matrix.argtypes = [C.c_int, vp, vp, dbl, C.c_int, dbl, vp]
@@ -122,7 +122,10 @@ def lib():
         L.orc_choose_fingers.argtypes = [C.c_int, vp, C.c_int, u64, C.c_uint32, i64, C.c_int, vp]
         L.orc_choose_fingers.restype = C.c_int
         L.orc_unused_joints.argtypes = [vp, C.c_int, u64, C.c_uint32, i64, C.c_int, vp]
-        L.orc_optimize.argtypes = [vp, vp, i32, vp, vp, i32, i32, i32, i32, vp, dbl, i32, dbl, i32, i32, dbl,
+        L.orc_place_palm.argtypes = [vp, vp, i32, vp, i32, vp, vp, i32, i32, dbl, dbl, u64, C.c_uint32, i64, vp,
+                                     vp, vp]
+        L.orc_place_palm.restype = C.c_int
+        L.orc_optimize.argtypes = [vp, vp, i32, vp, vp, vp, i32, i32, i32, i32, vp, dbl, i32, dbl, i32, i32, dbl,
                                    u64, C.c_uint32, i64, i32, vp, vp]
         L.orc_optimize.restype = C.c_int
         L.orc_relink.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, i32, vp, vp, u64, C.c_uint32, i64, vp]
@@ -297,8 +300,9 @@ def query_cone(hand, fp, bits, pts, nrm, poses, cos_hit: float, flags: bool = Tr
     return {"dom_bits": db, "dom_count": dc, "dom_flag": df}
 
 
-def draw(hand, fp, bits, pts, nrm, poses, dom_bits, dom_count, sp) -> tuple[np.ndarray, np.ndarray]:
-    """Seeded contact-set draws: ``set_pt``, ``set_link`` int32 [P, D, k]."""
+def draw(hand, fp, bits, pts, nrm, poses, dom_bits, dom_count, sp, palm_pt=None) -> tuple[np.ndarray, np.ndarray]:
+    """Seeded contact-set draws: ``set_pt``, ``set_link`` int32 [P, D, k]
+    (none for poses whose palm placement was rejected, ``palm_pt == -2``)."""
     pts, nrm, poses = _c(pts, np.float32), _c(nrm, np.float32), _c(poses, np.float32)
     P, N = poses.shape[0], pts.shape[0]
     spt = np.zeros((P, sp.draws, sp.k), np.int32)
@@ -307,7 +311,7 @@ def draw(hand, fp, bits, pts, nrm, poses, dom_bits, dom_count, sp) -> tuple[np.n
     rc = lib().orc_draw(H.ref, Fp.ref, _p(_c(bits, np.uint32)), _p(pts), _p(nrm), N, _p(poses), P,
                         _p(_c(dom_bits, np.uint32)), _p(_c(dom_count, np.uint32)), sp.draws, sp.k,
                         int(sp.seed) & 0xFFFFFFFFFFFFFFFF, int(sp.request_id), int(sp.pose_offset),
-                        _p(spt), _p(sln))
+                        _p(None if palm_pt is None else _c(palm_pt, np.int32)), _p(spt), _p(sln))
     if rc != 0:
         raise ValueError(f"orc_draw failed ({rc})")
     return spt, sln
@@ -435,7 +439,8 @@ def unused_joints(hand, f: int, sp, g: int, d: int) -> np.ndarray:
     return q[j]
 
 
-def optimize(pts, nrm, dom_bits, set_pt, sp, F: int, max_pivots: int = 1000, dom_count=None) -> dict:
+def optimize(pts, nrm, dom_bits, set_pt, sp, F: int, max_pivots: int = 1000, dom_count=None,
+             palm_pt=None) -> dict:
     """Sec. 5.4 Alg. 2 on drawn sets: optimised set_pt [P, D, k], t* of the final
     sets (NaN for invalid draws) and the band flag of each set.  ``dom_count``
     (default: the domains' popcounts) decides the sets' fingers."""
@@ -445,7 +450,9 @@ def optimize(pts, nrm, dom_bits, set_pt, sp, F: int, max_pivots: int = 1000, dom
     t = np.zeros(P * D, np.float64)
     fl = np.zeros(P * D, np.uint8)
     cnt = _dom_count(dom_count, dom_bits, P, int(F))
-    rc = lib().orc_optimize(_p(pts), _p(nrm), pts.shape[0], _p(_c(dom_bits, np.uint32)), _p(cnt), P, int(F), D, k,
+    palm = None if palm_pt is None else _c(palm_pt, np.int32)
+    rc = lib().orc_optimize(_p(pts), _p(nrm), pts.shape[0], _p(_c(dom_bits, np.uint32)), _p(cnt), _p(palm), P,
+                            int(F), D, k,
                             _p(spt), float(np.float32(sp.mu)), sp.m_edges, float(np.float32(sp.moment_scale)),
                             int(sp.opt_outer), int(sp.opt_inner), float(np.float32(sp.opt_sigma)),
                             int(sp.seed) & 0xFFFFFFFFFFFFFFFF, int(sp.request_id), int(sp.pose_offset),
@@ -455,6 +462,57 @@ def optimize(pts, nrm, dom_bits, set_pt, sp, F: int, max_pivots: int = 1000, dom
     eps = float(np.float32(sp.eps))
     return {"set_pt": spt, "tstar": t, "oflag": fl, "verdict": (t <= eps).astype(np.uint8),
             "vflag": (np.abs(t - eps) <= BAND).astype(np.uint8)}
+
+
+def verdicts_palm(pts, nrm, set_pt, palm_pt, sp, max_pivots: int = 1000) -> dict:
+    """Verdicts of drawn sets with each pose's palm contact (Sec. 5.1 static
+    link) as one more contact: sets of poses with palm_pt >= 0 are scored with
+    k + 1 contacts, the others with their k."""
+    spt = _c(set_pt, np.int32)
+    P, D, k = spt.shape
+    palm = _c(palm_pt, np.int32)
+    out = {"verdict": np.zeros(P * D, np.uint8), "tstar": np.full(P * D, np.nan),
+           "vflag": np.zeros(P * D, np.uint8), "status": np.zeros(P * D, np.int32)}
+    with_palm = palm >= 0
+    for mask, kk in ((with_palm, k + 1), (~with_palm, k)):
+        g = np.flatnonzero(mask)
+        if len(g) == 0:
+            continue
+        sets = spt[g]
+        if kk > k:
+            sets = np.concatenate([sets, np.broadcast_to(palm[g][:, None, None], (len(g), D, 1))], axis=2)
+            # an undrawn set stays undrawn
+            sets = np.where((spt[g] < 0).any(-1, keepdims=True), -1, sets)
+        V = verdicts(pts, nrm, np.ascontiguousarray(sets, np.int32), _with_k(sp, kk), max_pivots)
+        rows = (g[:, None] * D + np.arange(D)[None, :]).reshape(-1)
+        for key in out:
+            out[key][rows] = V[key]
+    return out
+
+
+def _with_k(sp, k: int):
+    import dataclasses
+    return dataclasses.replace(sp, k=int(k))
+
+
+def place_palm(palm, sdf, pts, nrm, poses, prob: float, margin: float, seed: int, request_id: int = 0,
+               pose_offset: int = 0) -> dict:
+    """Sec. 5.1 static-link placement over ``poses`` [P, 12] (float64 out): the
+    palm poses, palm_pt (i / -1 / -2) and the band flags."""
+    pts, nrm = _c(pts, np.float32), _c(nrm, np.float32)
+    out = np.ascontiguousarray(poses, np.float64).copy()
+    P = out.shape[0]
+    pp = np.zeros(P, np.int32)
+    fl = np.zeros(P, np.uint8)
+    S = _sdf(sdf)
+    surf, caps = _c(palm.surf, np.float32), _c(palm.caps, np.float32)
+    rc = lib().orc_place_palm(S.ref, _p(surf), surf.shape[0], _p(caps), caps.shape[0], _p(pts), _p(nrm),
+                              pts.shape[0], P, float(np.float32(prob)), float(np.float32(margin)),
+                              int(seed) & 0xFFFFFFFFFFFFFFFF, int(request_id), int(pose_offset), _p(out), _p(pp),
+                              _p(fl))
+    if rc != 0:
+        raise ValueError(f"orc_place_palm failed ({rc})")
+    return {"poses": out, "palm_pt": pp, "pflag": fl}
 
 
 def relink(hand, fp, bits, pts, nrm, poses, set_pt, sp, dom_count=None) -> np.ndarray:

@@ -39,6 +39,7 @@
 #define PURPOSE_PLACE 11u
 #define PURPOSE_FINGERS 13u
 #define PURPOSE_UNUSED 15u
+#define PURPOSE_PALM 17u
 #define OPT_TAU 1e-9    /* candidates within OPT_TAU of the best criterion value tie */
 #define OPT_BAND 1e-7   /* m: projection near-tie band (FP32 candidate positions err by ~1e-8 m) */
 
@@ -721,6 +722,7 @@ int orc_draw(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits
              const float *poses, int32_t n_poses,
              const uint32_t *dom_bits, const uint32_t *dom_count,
              int32_t draws, int32_t k, uint64_t seed, uint32_t request_id, int64_t pose_offset,
+             const int32_t *palm_pt /*[P] or NULL: -2 = rejected placement, no sets*/,
              int32_t *set_pt /*[P][D][k]*/, int32_t *set_link /*[P][D][k]*/)
 {
     const int F = H->n_fingers;
@@ -737,6 +739,7 @@ int orc_draw(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits
             int32_t *sl = set_link + ((int64_t)g * draws + d) * k;
             int32_t fing[8];
             for (int i = 0; i < k; ++i) { sp[i] = -1; sl[i] = -1; }
+            if (palm_pt && palm_pt[g] == -2) continue;
             if (!orc_choose_fingers(F, dom_count + (int64_t)g * F, k, seed, request_id, pose_offset + g, d, fing))
                 continue;
             for (int i = 0; i < k; ++i) {
@@ -1131,6 +1134,102 @@ int orc_place_exhaustive(const orc_hand *H, const orc_field_params *fp, const fl
     return ORC_OK;
 }
 
+/* Object signed-distance grid (object frame): trilinear between nodes, +inf
+ * outside the grid (orc_sdf_eval below). */
+typedef struct {
+    double origin[3];
+    double h;
+    int32_t dims;
+    const float *values; /* [G][G][G] as [iz][iy][ix] */
+} orc_sdf;
+double orc_sdf_eval(const orc_sdf *S, const double *y);
+
+/* Static-link (palm) placement, Sec. 5.1: with probability prob, pose g is
+ * replaced by one that puts object point i onto a palm contact vector (x, nu)
+ * with normals opposed and a random roll about the contact normal (the
+ * alignment of orc_place_exhaustive), and is kept only if no palm capsule
+ * penetrates the object by more than margin: axis samples one per mm, ends
+ * included (at least 2), depth = max (r - SDF(R^T (x - t))).  Philox blocks
+ * (g, b, PURPOSE_PALM, request_id), b = 0, 1, key = seed: u01(w0) < prob
+ * selects the pose, w1 the palm sample, w2 the object point, w3 the roll
+ * psi = 2 pi u01(w3).  palm_pt[g] = i (accepted), -1 (pose left unchanged),
+ * -2 (rejected; its palm pose is still written).  flag: the rotation's
+ * branch band, or a penetration within BAND_VAL of margin, or u01(w0)
+ * within BAND_VAL of prob. */
+int orc_place_palm(const orc_sdf *S, const float *palm_surf, int32_t n_surf, const float *palm_caps, int32_t n_caps,
+                   const float *pts, const float *nrm, int32_t n_points, int32_t n_poses, double prob, double margin,
+                   uint64_t seed, uint32_t request_id, int64_t pose_offset, double *poses /*[P][12] in/out*/,
+                   int32_t *palm_pt, uint8_t *flag)
+{
+    if (n_points <= 0 || n_poses < 0 || n_surf <= 0 || n_caps < 0 || !(prob >= 0.0)) return ORC_EINVAL;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+#pragma omp parallel for schedule(static)
+    for (int g = 0; g < n_poses; ++g) {
+        uint32_t w[8];
+        for (int b = 0; b < 2; ++b) {
+            uint32_t ctr[4] = {(uint32_t)(pose_offset + g), (uint32_t)b, PURPOSE_PALM, request_id};
+            orc_philox4x32_10(ctr, key, w + 4 * b);
+        }
+        int fl = fabs(u01(w[0]) - prob) <= BAND_VAL;
+        if (!(u01(w[0]) < prob)) {
+            palm_pt[g] = -1;
+            if (flag) flag[g] = (uint8_t)fl;
+            continue;
+        }
+        const int js = (int)(((uint64_t)w[1] * (uint64_t)n_surf) >> 32);
+        const int64_t i = (int64_t)(((uint64_t)w[2] * (uint64_t)n_points) >> 32);
+        const double psi = 2.0 * M_PI * u01(w[3]);
+        const float *sf = palm_surf + 6 * (int64_t)js;
+        const double x[3] = {sf[0], sf[1], sf[2]};
+        double b[3] = {-sf[3], -sf[4], -sf[5]};
+        const double nb = sqrt(dot3(b, b));
+        for (int c = 0; c < 3; ++c) b[c] /= nb;
+        const double a[3] = {nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2]};
+        double R0[9], Rr[9], R[9];
+        int rf = 0;
+        orc_rot_align(a, b, R0, &rf);
+        fl |= rf;
+        const double cs = cos(psi), sn = sin(psi);
+        const double K[9] = {0, -b[2], b[1], b[2], 0, -b[0], -b[1], b[0], 0};
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c)
+                Rr[3 * r + c] = (r == c ? cs : 0.0) + sn * K[3 * r + c] + (1.0 - cs) * b[r] * b[c];
+        mat3_mul(Rr, R0, R);
+        const double p[3] = {pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]};
+        double *P = poses + 12 * (int64_t)g;
+        double t[3];
+        for (int r = 0; r < 3; ++r) {
+            t[r] = x[r] - (R[3 * r] * p[0] + R[3 * r + 1] * p[1] + R[3 * r + 2] * p[2]);
+            P[4 * r + 0] = R[3 * r];
+            P[4 * r + 1] = R[3 * r + 1];
+            P[4 * r + 2] = R[3 * r + 2];
+            P[4 * r + 3] = t[r];
+        }
+        /* the palm's capsules against the placed object */
+        double depth = -INFINITY;
+        for (int c = 0; c < n_caps; ++c) {
+            const float *cp = palm_caps + 7 * (int64_t)c;
+            const double A[3] = {cp[0], cp[1], cp[2]}, Bq[3] = {cp[3], cp[4], cp[5]};
+            const double L = sqrt((Bq[0] - A[0]) * (Bq[0] - A[0]) + (Bq[1] - A[1]) * (Bq[1] - A[1]) +
+                                  (Bq[2] - A[2]) * (Bq[2] - A[2]));
+            int M = (int)ceil(L / 1e-3) + 1;
+            if (M < 2) M = 2;
+            for (int s = 0; s < M; ++s) {
+                const double u = (double)s / (double)(M - 1);
+                double d[3], y[3];
+                for (int e = 0; e < 3; ++e) d[e] = A[e] + u * (Bq[e] - A[e]) - t[e];
+                for (int e = 0; e < 3; ++e) y[e] = R[e] * d[0] + R[3 + e] * d[1] + R[6 + e] * d[2];
+                const double v = (double)cp[6] - orc_sdf_eval(S, y);
+                if (v > depth) depth = v;
+            }
+        }
+        fl |= fabs(depth - margin) <= BAND_VAL;
+        palm_pt[g] = depth <= margin ? (int32_t)i : -2;
+        if (flag) flag[g] = (uint8_t)fl;
+    }
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Blockwise zeroth-order contact-point optimisation (Sec. 5.4, Alg. 2).       */
 /* A drawn set (Alg. 2's random start) is refined in n_outer rounds; in each   */
@@ -1199,7 +1298,7 @@ int64_t orc_project_domain(const float *pts, int32_t n_points, const uint32_t *d
 }
 
 int orc_optimize(const float *pts, const float *nrm, int32_t n_points, const uint32_t *dom_bits /*[P][F][NW]*/,
-                 const uint32_t *dom_count /*[P][F]*/,
+                 const uint32_t *dom_count /*[P][F]*/, const int32_t *palm_pt /*[P] or NULL*/,
                  int32_t n_poses, int32_t F, int32_t draws, int32_t k, int32_t *set_pt /*[P][D][k] in/out*/,
                  double mu, int32_t m_edges, double rho, int32_t n_outer, int32_t n_inner, double sigma,
                  uint64_t seed, uint32_t request_id, int64_t pose_offset, int32_t max_pivots,
@@ -1208,6 +1307,7 @@ int orc_optimize(const float *pts, const float *nrm, int32_t n_points, const uin
     const int64_t NW = (n_points + 31) / 32;
     if (k <= 0 || k > 8 || k > F || n_outer < 0 || n_inner < 1 || n_inner > 64 || !(sigma >= 0.0))
         return ORC_EINVAL;
+    /* a palm contact (Sec. 5.1 static link) is one more, fixed, contact of every set of its pose */
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t s = 0; s < (int64_t)n_poses * draws; ++s) {
         const int64_t g = s / draws;
@@ -1223,14 +1323,17 @@ int orc_optimize(const float *pts, const float *nrm, int32_t n_points, const uin
             oflag[s] = 0;
             continue;
         }
+        const int kc = k + ((palm_pt && palm_pt[g] >= 0) ? 1 : 0);
         double p[3 * 16], n[3 * 16];
-        for (int i = 0; i < k; ++i)
+        for (int i = 0; i < kc; ++i) {
+            const int64_t idx = i < k ? sp[i] : palm_pt[g];
             for (int a = 0; a < 3; ++a) {
-                p[3 * i + a] = pts[3 * (int64_t)sp[i] + a];
-                n[3 * i + a] = nrm[3 * (int64_t)sp[i] + a];
+                p[3 * i + a] = pts[3 * idx + a];
+                n[3 * i + a] = nrm[3 * idx + a];
             }
+        }
         int st, pv, fl = 0;
-        double J = orc_set_tstar(k, p, n, mu, m_edges, rho, max_pivots, &st, &pv);
+        double J = orc_set_tstar(kc, p, n, mu, m_edges, rho, max_pivots, &st, &pv);
         if (st != 0) J = INFINITY;
         for (int r = 0; r < n_outer; ++r) {
             for (int i = 0; i < k; ++i) {
@@ -1248,13 +1351,13 @@ int orc_optimize(const float *pts, const float *nrm, int32_t n_points, const uin
                     idx[j] = orc_project_domain(pts, n_points, dom, y, &pf);
                     fl |= pf;
                     double pc[3 * 16], nc[3 * 16];
-                    memcpy(pc, p, sizeof(double) * 3 * k);
-                    memcpy(nc, n, sizeof(double) * 3 * k);
+                    memcpy(pc, p, sizeof(double) * 3 * kc);
+                    memcpy(nc, n, sizeof(double) * 3 * kc);
                     for (int a = 0; a < 3; ++a) {
                         pc[3 * i + a] = pts[3 * idx[j] + a];
                         nc[3 * i + a] = nrm[3 * idx[j] + a];
                     }
-                    Jc[j] = orc_set_tstar(k, pc, nc, mu, m_edges, rho, max_pivots, &st, &pv);
+                    Jc[j] = orc_set_tstar(kc, pc, nc, mu, m_edges, rho, max_pivots, &st, &pv);
                     if (st != 0) Jc[j] = INFINITY;
                 }
                 double mn = INFINITY;
@@ -1555,12 +1658,6 @@ void orc_ik_finger(const orc_hand *H, int f, int link, const double *p, const do
 
 /* Object SDF on a G^3 node grid (object frame), trilinear interpolation,
  * +inf outside the grid.                                                    */
-typedef struct {
-    double origin[3];
-    double h;
-    int32_t dims;
-    const float *values; /* [G][G][G] as [iz][iy][ix] */
-} orc_sdf;
 
 double orc_sdf_eval(const orc_sdf *S, const double *y)
 {

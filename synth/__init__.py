@@ -234,6 +234,42 @@ def hand_c3(seed: int = 0, n_surf: int = 256, splay: float = 0.9) -> Hand:
     return _build_hand(fingers, n_surf)
 
 
+@dataclass
+class Palm:
+    """Static link of the hand (the palm, Sec. 5.1 static-link contacts): a
+    disc of radius R at z = 0 of the hand base frame, facing +z.
+
+    surf: float32 [S,6] contact vectors (point on the disc, normal +z), a
+    Fibonacci disc lattice; caps: float32 [C,7] capsules a(3), b(3), radius in
+    the base frame -- parallel rods of radius r_c along x at z = -r_c whose
+    tops reach the disc plane, at most 1.6 r_c apart in y, each as long as the
+    disc's chord at its y."""
+    surf: np.ndarray
+    caps: np.ndarray
+    radius: float
+
+
+def palm_disc(radius: float, n_surf: int = 512, rod: float = 0.005) -> Palm:
+    i = np.arange(n_surf) + 0.5
+    r = radius * np.sqrt(i / n_surf)
+    ph = np.arange(n_surf) * GOLDEN
+    surf = np.zeros((n_surf, 6))
+    surf[:, 0], surf[:, 1], surf[:, 5] = r * np.cos(ph), r * np.sin(ph), 1.0
+    caps = []
+    edge = radius - 0.8 * rod
+    n_rods = int(math.floor(2 * edge / (1.6 * rod))) + 1
+    for y in np.linspace(-edge, edge, n_rods):
+        hx = math.sqrt(radius * radius - y * y)
+        caps.append((-hx, y, -rod, hx, y, -rod, rod))
+    return Palm(surf=surf.astype(np.float32), caps=np.asarray(caps, np.float32), radius=radius)
+
+
+def palm_for(name: str) -> Palm:
+    """The palm of workload ``name``'s hand: inside the circle of finger bases
+    (30 mm for c1/c2, 35-40 mm for c3)."""
+    return palm_disc({"c1": 0.025, "c2": 0.025, "c3": 0.030}[name])
+
+
 # --------------------------------------------------------------------------
 # contact-field grid placement
 # --------------------------------------------------------------------------
