@@ -74,6 +74,11 @@ typedef struct {
     const float *limits;          /* host [J][2] lo, hi */
     int32_t n_surf;               /* surface samples per link (patch points) */
     const float *surf;            /* host [J][n_surf][6] link-frame point, outward normal */
+    /* static link (the palm, Sec. 5.1 static-link contacts); 0 / NULL = none */
+    int32_t n_palm_surf;          /* palm contact vectors */
+    const float *palm_surf;       /* host [n_palm_surf][6] base-frame point, outward normal */
+    int32_t n_palm_caps;          /* palm capsules (penetration test) */
+    const float *palm_caps;       /* host [n_palm_caps][7] a(3), b(3), radius, base frame */
 } lg_hand_desc;
 
 /* Field construction parameters (Sec. 4.3, Alg. 1 as a dense grid cover). */
@@ -168,7 +173,7 @@ lg_status lg_query_domains_cone(const lg_field *field, const float *pts, const f
 typedef struct {
     int32_t draws;        /* D sets per pose */
     int32_t k;            /* contacts per set, 1..F: one per finger, on k fingers drawn per set */
-    int32_t m_edges;      /* linearised cone edges, 3..16; k*m_edges <= 52 */
+    int32_t m_edges;      /* linearised cone edges, 3..16 */
     int32_t max_pivots;   /* simplex pivot cap (status UNDECIDED when hit) */
     float mu;             /* friction coefficient >= 0 */
     float eps;            /* stability threshold on t* */
@@ -179,6 +184,10 @@ typedef struct {
     int32_t opt_outer;    /* rounds of contact-point optimisation (Sec. 5.4, Alg. 2); 0 = none */
     int32_t opt_inner;    /* candidates per contact and round, 1..16 */
     float opt_sigma;      /* std of the tangent-plane mutations (m) */
+    const int32_t *palm_pt; /* DEVICE [P] or NULL: static-link contacts of lg_place_palm.  >= 0: that
+                               object point is one more, fixed, contact of every set of the pose (in the
+                               verdict and in Alg. 2; k <= 7); -1: none; -2: rejected placement, the pose
+                               draws no sets.  Not supported by the server (must be NULL there). */
 } lg_search_params;
 
 /* Bytes of device workspace lg_search needs for n_points points and n_poses poses. */
@@ -398,6 +407,24 @@ lg_status lg_gather_points(const float *pts, const float *nrm, int32_t n_points,
 lg_status lg_place_exhaustive(const lg_field *field, const float *pts, const float *nrm, int32_t n_points,
                               int32_t n_poses, uint64_t seed, uint32_t request_id, int64_t pose_offset,
                               float *poses, void *stream);
+
+/* lg_place_palm -- static-link (palm) placements of Sec. 5.1, in place over
+ * `poses` (DEVICE [P][12]): with probability prob (u01(w0) < prob), pose g is
+ * replaced by one that puts object point i onto palm contact vector js (the
+ * field's hand desc), normals opposed, rolled by psi about the contact normal
+ * (the alignment of lg_place_exhaustive); Philox block (g + pose_offset, 0,
+ * 17, request_id), key = seed: word 0 the selection, word 1 js, word 2 i,
+ * word 3 psi = 2 pi u.  The placement is kept when no palm capsule (axis
+ * samples one per mm, ends included) penetrates the object's trilinear SDF by
+ * more than margin.  palm_pt (DEVICE [P] int32 out): i (kept), -1 (pose not
+ * selected, left untouched), -2 (rejected; the palm pose is still written).
+ * Feed palm_pt to lg_search through lg_search_params.palm_pt.
+ * LG_EINVAL without palm contact vectors in the hand, on a bad sdf,
+ * n_points <= 0, prob outside [0, 1], NaN margin or null buffers.
+ */
+lg_status lg_place_palm(const lg_field *field, const lg_sdf *sdf, const float *pts, const float *nrm,
+                        int32_t n_points, int32_t n_poses, float prob, float margin, uint64_t seed,
+                        uint32_t request_id, int64_t pose_offset, float *poses, int32_t *palm_pt, void *stream);
 
 /* ---- learned palm-pose proposer ------------------------------------------------
  * Data-driven search (Sec. 5.7) names learning where to search as a way to skip

@@ -60,6 +60,11 @@ lg_status validate_hand(const lg_hand_desc *hand, const lg_field_params *p)
         if (!(hand->limits[2 * j] <= hand->limits[2 * j + 1])) return fail(LG_EINVAL, "limits lo > hi");
     }
     if (prev_f != F - 1) return fail(LG_EINVAL, "every finger needs at least one joint");
+    if (hand->n_palm_surf < 0 || hand->n_palm_caps < 0 || (hand->n_palm_surf > 0 && !hand->palm_surf) ||
+        (hand->n_palm_caps > 0 && !hand->palm_caps) || hand->n_palm_surf > (1 << 20) || hand->n_palm_caps > 1024)
+        return fail(LG_EINVAL, "palm: need 0 <= n_palm_surf <= 2^20, 0 <= n_palm_caps <= 1024 and their arrays");
+    for (int c = 0; c < hand->n_palm_caps; ++c)
+        if (!(hand->palm_caps[7 * c + 6] >= 0.0f)) return fail(LG_EINVAL, "palm capsule radius must be >= 0");
     if (p->bins != 32 && p->bins != 64) return fail(LG_EINVAL, "bins must be 32 or 64");
     if (p->grid < 4 || p->grid > 128) return fail(LG_EINVAL, "grid must be 4..128");
     if (!(p->h > 0.0f)) return fail(LG_EINVAL, "h must be > 0");
@@ -155,6 +160,9 @@ lg_status make_field_shell(const lg_hand_desc *hand, const lg_field_params *p, l
     f->limits.assign(hand->limits, hand->limits + 2 * J);
     f->surf.assign(hand->surf, hand->surf + (size_t)6 * J * S);
     f->grid_frame.assign(p->grid_frame, p->grid_frame + 12 * F);
+    const int PS = hand->n_palm_surf, PC = hand->n_palm_caps;
+    if (PS > 0) f->palm_surf.assign(hand->palm_surf, hand->palm_surf + (size_t)6 * PS);
+    if (PC > 0) f->palm_caps.assign(hand->palm_caps, hand->palm_caps + (size_t)7 * PC);
     // spherical Fibonacci lattice, evaluated in double and rounded once
     f->bin_c.resize(3 * B);
     const double golden = M_PI * (3.0 - sqrt(5.0));
@@ -167,12 +175,13 @@ lg_status make_field_shell(const lg_hand_desc *hand, const lg_field_params *p, l
     std::vector<uint32_t> lut;
     build_bin_lut(f->bin_c, B, lut);
     // capsule axis samples for the penetration test: one per mm, ends included
-    f->axis_samples.resize(J);
-    for (int j = 0; j < J; ++j) {
-        const float *c = hand->capsule + 7 * j;
+    // (links, then the palm's capsules, which take at least their two ends)
+    f->axis_samples.resize(J + PC);
+    for (int j = 0; j < J + PC; ++j) {
+        const float *c = j < J ? hand->capsule + 7 * j : hand->palm_caps + 7 * (j - J);
         const double dx = (double)c[3] - c[0], dy = (double)c[4] - c[1], dz = (double)c[5] - c[2];
         const double L = sqrt((dx * dx + dy * dy) + dz * dz);
-        f->axis_samples[j] = (int32_t)ceil(L / 1e-3) + 1;
+        f->axis_samples[j] = std::max((int32_t)ceil(L / 1e-3) + 1, j < J ? 1 : 2);
     }
     DevHand &H = f->dh;
     memset(&H, 0, sizeof H);
@@ -203,21 +212,22 @@ lg_status make_field_shell(const lg_hand_desc *hand, const lg_field_params *p, l
     // packed float parameters
     const size_t n_origin = f->origin.size(), n_axis = f->axis.size(), n_cap = f->capsule.size(),
                  n_lim = f->limits.size(), n_surf = f->surf.size(), n_gf = f->grid_frame.size(),
-                 n_bc = f->bin_c.size();
+                 n_bc = f->bin_c.size(), n_ps = f->palm_surf.size(), n_pc = f->palm_caps.size();
     const size_t n_lut = lut.size();
-    const size_t n_all = n_origin + n_axis + n_cap + n_lim + n_surf + n_gf + n_bc + n_lut;
+    const size_t n_all = n_origin + n_axis + n_cap + n_lim + n_surf + n_gf + n_bc + n_ps + n_pc + n_lut;
     std::vector<float> packed;
     packed.reserve(n_all);
-    for (auto *v : {&f->origin, &f->axis, &f->capsule, &f->limits, &f->surf, &f->grid_frame, &f->bin_c})
+    for (auto *v : {&f->origin, &f->axis, &f->capsule, &f->limits, &f->surf, &f->grid_frame, &f->bin_c,
+                    &f->palm_surf, &f->palm_caps})
         packed.insert(packed.end(), v->begin(), v->end());
     packed.resize(n_all);
     memcpy(packed.data() + (n_all - n_lut), lut.data(), n_lut * sizeof(uint32_t));
     const int64_t G3 = (int64_t)G * G * G;
     hipError_t e = hipMalloc(&f->d_params, n_all * sizeof(float));
     if (e == hipSuccess) e = hipMemcpy(f->d_params, packed.data(), n_all * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc(&f->d_axis_samples, J * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&f->d_axis_samples, (J + PC) * sizeof(int32_t));
     if (e == hipSuccess)
-        e = hipMemcpy(f->d_axis_samples, f->axis_samples.data(), J * sizeof(int32_t), hipMemcpyHostToDevice);
+        e = hipMemcpy(f->d_axis_samples, f->axis_samples.data(), (J + PC) * sizeof(int32_t), hipMemcpyHostToDevice);
     const size_t bits_bytes = (size_t)J * G3 * H.W * 4, merged_bytes = (size_t)F * G3 * H.W * 4;
     if (e == hipSuccess) e = hipMalloc(&f->d_bits, bits_bytes);
     if (e == hipSuccess) e = hipMalloc(&f->d_merged, merged_bytes);
@@ -239,7 +249,7 @@ lg_status make_field_shell(const lg_hand_desc *hand, const lg_field_params *p, l
         free_field(f);
         return st;
     }
-    f->device_bytes = n_all * 4 + J * 4 + bits_bytes + merged_bytes + wit_bytes;
+    f->device_bytes = n_all * 4 + (J + PC) * 4 + bits_bytes + merged_bytes + wit_bytes;
     float *base = f->d_params;
     H.origin = base;
     base += n_origin;
@@ -255,8 +265,14 @@ lg_status make_field_shell(const lg_hand_desc *hand, const lg_field_params *p, l
     base += n_gf;
     H.bin_c = base;
     base += n_bc;
+    H.palm_surf = n_ps ? base : nullptr;
+    base += n_ps;
+    H.palm_caps = n_pc ? base : nullptr;
+    base += n_pc;
     H.bin_lut = reinterpret_cast<const uint32_t *>(base);
     H.axis_samples = f->d_axis_samples;
+    H.n_palm_surf = PS;
+    H.n_palm_caps = PC;
     *out = f;
     return LG_OK;
 }

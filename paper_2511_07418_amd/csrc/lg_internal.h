@@ -39,7 +39,10 @@ struct DevHand {
     const float *grid_frame;  // [F][12]
     const float *bin_c;       // [B][3]
     const uint32_t *bin_lut;  // [6][kLutRes][kLutRes] candidate bins (4 x 8 bit), 0xffffffff = all
-    const int32_t *axis_samples;  // [J]
+    const int32_t *axis_samples;  // [J + n_palm_caps]: links, then the palm's capsules
+    int n_palm_surf, n_palm_caps; // static link (palm): contact vectors and capsules, base frame
+    const float *palm_surf;       // [n_palm_surf][6]
+    const float *palm_caps;       // [n_palm_caps][7]
     int finger_first[kMaxFingers];
     int finger_dof[kMaxFingers];
 };
@@ -57,7 +60,7 @@ struct lg_field {
     uint64_t device_bytes;
     // host copies
     std::vector<int32_t> joint_finger, joint_parent, axis_samples;
-    std::vector<float> origin, axis, capsule, limits, surf, grid_frame, bin_c;
+    std::vector<float> origin, axis, capsule, limits, surf, grid_frame, bin_c, palm_surf, palm_caps;
     // device allocations
     float *d_params = nullptr;     // packed float arrays (origin..bin_c)
     int32_t *d_axis_samples = nullptr;

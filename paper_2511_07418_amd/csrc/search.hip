@@ -83,9 +83,10 @@ __device__ inline int pick_link(const DevHand &H, const uint32_t *__restrict__ b
 __global__ void __launch_bounds__(kDrawThreads)
 k_draw(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ pts, const float *__restrict__ nrm,
        int N, const float *__restrict__ poses, const uint32_t *__restrict__ dom_bits,
-       const uint32_t *__restrict__ dom_count, int D, int k, uint32_t seed_lo, uint32_t seed_hi,
-       uint32_t request_id, int64_t pose_offset, int32_t *__restrict__ set_pt, int8_t *__restrict__ set_link,
-       uint8_t *__restrict__ pose_valid, uint8_t *__restrict__ verdict, double *__restrict__ tstar)
+       const uint32_t *__restrict__ dom_count, const int32_t *__restrict__ palm_pt, int D, int k, uint32_t seed_lo,
+       uint32_t seed_hi, uint32_t request_id, int64_t pose_offset, int32_t *__restrict__ set_pt,
+       int8_t *__restrict__ set_link, uint8_t *__restrict__ pose_valid, uint8_t *__restrict__ verdict,
+       double *__restrict__ tstar)
 {
     extern __shared__ uint32_t prefix[];  // [F][nsb + 1]
     __shared__ float cb[3 * kMaxBins];
@@ -98,7 +99,8 @@ k_draw(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ p
     __syncthreads();
     uint32_t elig = 0;
     for (int f = 0; f < F; ++f) elig |= (counts[f] > 0 ? 1u : 0u) << f;
-    const bool empty = __popc(elig) < k;  // fewer than k usable domains
+    // fewer than k usable domains, or a palm placement that was rejected
+    const bool empty = __popc(elig) < k || (palm_pt && palm_pt[g] == -2);
     if (threadIdx.x == 0) pose_valid[g] = empty ? 0 : 1;
     if (empty) {
         for (int i = threadIdx.x; i < D * k; i += blockDim.x) {
@@ -436,9 +438,9 @@ __device__ inline double lp_lane(float (&cd)[KM * 6][256], int tid, int k, int m
 template <int KM>
 __global__ void __launch_bounds__(256)
 k_verdict_lane(const float *__restrict__ pts, const float *__restrict__ nrm, int N, const int32_t *__restrict__ set_pt,
-               const int32_t *__restrict__ valid_poses, const int32_t *__restrict__ n_valid_poses, int D, int k,
-               int m, double mu, double rho, double eps, int max_pivots, LpConst cs, uint8_t *__restrict__ verdict,
-               double *__restrict__ tstar)
+               const int32_t *__restrict__ palm_pt, const int32_t *__restrict__ valid_poses,
+               const int32_t *__restrict__ n_valid_poses, int D, int k, int m, double mu, double rho, double eps,
+               int max_pivots, LpConst cs, uint8_t *__restrict__ verdict, double *__restrict__ tstar)
 {
     // contact data of this lane's set in LDS, lane-contiguous: cd[6*i + c][tid]
     __shared__ float cd[KM * 6][256];
@@ -447,13 +449,17 @@ k_verdict_lane(const float *__restrict__ pts, const float *__restrict__ nrm, int
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     // grid-stride over the sets of poses with at least k non-empty domains
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + tid; t < n_work; t += stride) {
-        const int64_t sid = (int64_t)valid_poses[t / D] * D + (t % D);
+        const int64_t g = valid_poses[t / D];
+        const int64_t sid = g * D + (t % D);
         const int32_t *sp = set_pt + sid * k;
+        // a palm contact (Sec. 5.1 static link) is one more, fixed, contact
+        const int pc = palm_pt ? palm_pt[g] : -1;
+        const int kc = pc >= 0 ? k + 1 : k;
         bool valid = true;
-        for (int i = 0; i < k; ++i) {
-            const int idx = sp[i];
-            valid &= idx >= 0;
-            const int ii = idx >= 0 ? idx : 0;
+        for (int i = 0; i < kc; ++i) {
+            const int idx = i < k ? sp[i] : pc;
+            valid &= idx >= 0 && idx < N;
+            const int ii = (idx >= 0 && idx < N) ? idx : 0;
             cd[6 * i + 0][tid] = pts[ii];
             cd[6 * i + 1][tid] = pts[N + ii];
             cd[6 * i + 2][tid] = pts[2 * N + ii];
@@ -467,7 +473,7 @@ k_verdict_lane(const float *__restrict__ pts, const float *__restrict__ nrm, int
             continue;
         }
         int status = 0;
-        const double ts = lp_lane<KM>(cd, tid, k, m, mu, rho, max_pivots, cs, status);
+        const double ts = lp_lane<KM>(cd, tid, kc, m, mu, rho, max_pivots, cs, status);
         verdict[sid] = (status == 0 && ts <= eps) ? 1 : 0;
         tstar[sid] = status == 0 ? ts : __builtin_nan("");
     }
@@ -649,7 +655,7 @@ template <int KM, int GS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, const int32_t *__restrict__ valid_poses,
            const int32_t *__restrict__ n_valid_poses, const uint32_t *__restrict__ dom_bits,
-           const uint32_t *__restrict__ dom_count, int F, int D, int k, int m,
+           const uint32_t *__restrict__ dom_count, const int32_t *__restrict__ palm_pt, int F, int D, int k, int m,
            double mu, double rho, double eps, int max_pivots, LpConst cs, int n_outer, int n_inner, double sigma,
            uint32_t seed_lo, uint32_t seed_hi, uint32_t request_id, int64_t pose_offset,
            const GridDev *__restrict__ gdp, const uint32_t *__restrict__ cell_start,
@@ -678,7 +684,9 @@ k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, 
         int32_t *sp = set_pt + sid * k;
         const uint32_t fm = choose_fingers(eligible_fingers(dom_count, pg, F), k, (uint32_t)(pose_offset + pg), d,
                                            request_id, seed_lo, seed_hi);
-        bool drawn = fm != 0;
+        const int pc = palm_pt ? palm_pt[pg] : -1;  // fixed palm contact (-1: none)
+        const int kc = pc >= 0 ? k + 1 : k;
+        bool drawn = fm != 0 && pc < N;
         for (int i = 0; i < k; ++i) drawn &= sp[i] >= 0 && sp[i] < N;
         if (!drawn) {  // not a drawn set (inconsistent domain sizes): no criterion
             if (j == 0) {
@@ -691,6 +699,7 @@ k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, 
             cur[i][tid] = sp[i];
             load(i, sp[i]);
         }
+        if (pc >= 0) load(k, pc);
         double J = INFINITY;
         for (int r = 0; r < n_outer; ++r) {
             for (int i = 0; i < k; ++i) {
@@ -715,7 +724,7 @@ k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, 
                     if (cand >= 0) {  // always, for a drawn set (its domains are non-empty)
                         load(i, cand);
                         int st = 0;
-                        Jc = lp_lane<KM>(cd, tid, k, m, mu, rho, max_pivots, cs, st);
+                        Jc = lp_lane<KM>(cd, tid, kc, m, mu, rho, max_pivots, cs, st);
                         if (st != 0) Jc = INFINITY;
                     }
                 }
@@ -912,8 +921,10 @@ lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, i
     const DevHand &H = field->dh;
     if (n_points <= 0 || n_poses < 0) return fail(LG_EINVAL, "n_points must be > 0 and n_poses >= 0");
     if (p->k < 1 || p->k > H.F) return fail(LG_EINVAL, "need 1 <= k <= number of fingers (one contact per finger)");
-    if (p->draws <= 0 || p->m_edges < 3 || p->m_edges > 16 || p->k > 8)
-        return fail(LG_EINVAL, "need draws > 0, 3 <= m_edges <= 16, k <= 8");
+    const int32_t *palm = p->palm_pt;
+    const int kk = p->k + (palm ? 1 : 0);  // contacts of the largest set (with a palm contact)
+    if (p->draws <= 0 || p->m_edges < 3 || p->m_edges > 16 || kk > 8)
+        return fail(LG_EINVAL, "need draws > 0, 3 <= m_edges <= 16, k <= 8 (k <= 7 with palm contacts)");
     if (!(p->mu >= 0.0f) || !(p->moment_scale > 0.0f) || p->max_pivots < 0)
         return fail(LG_EINVAL, "need mu >= 0, moment_scale > 0, max_pivots >= 0");
     if ((int64_t)n_poses * p->draws > 0x7fffffffLL) return fail(LG_EINVAL, "P * D must be < 2^31");
@@ -932,7 +943,7 @@ lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, i
     const bool opt = p->opt_outer > 0;
     const SearchWs ws = search_ws(workspace, n_points, n_poses, p->draws, opt);
     hipLaunchKernelGGL(k_draw, dim3(n_poses), dim3(kDrawThreads), lds, s, H, field->d_bits, pts, nrm, n_points,
-                       poses, dom_bits, dom_count, p->draws, p->k, (uint32_t)p->seed, (uint32_t)(p->seed >> 32),
+                       poses, dom_bits, dom_count, palm, p->draws, p->k, (uint32_t)p->seed, (uint32_t)(p->seed >> 32),
                        p->request_id, p->pose_offset, set_pt, set_link, ws.pose_valid, verdict, tstar);
     LG_HIP(hipGetLastError());
     // list of poses with at least k non-empty domains (ordered)
@@ -957,12 +968,13 @@ lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, i
     LG_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     const dim3 lgrid((unsigned)std::max<int64_t>(1, std::min<int64_t>((n_sets + 255) / 256, (int64_t)n_cu * 8)));
 #define LG_VERDICT(KM)                                                                                          \
-    hipLaunchKernelGGL(k_verdict_lane<KM>, lgrid, dim3(256), 0, s, pts, nrm, n_points, set_pt, ws.valid_poses,   \
+    hipLaunchKernelGGL(k_verdict_lane<KM>, lgrid, dim3(256), 0, s, pts, nrm, n_points, set_pt, palm,             \
+                       ws.valid_poses,                                                                          \
                        ws.n_valid_poses, p->draws, p->k, p->m_edges, (double)p->mu, (double)p->moment_scale,     \
                        (double)p->eps, p->max_pivots, cs, verdict, tstar)
     if (!opt) {
-        if (p->k <= 3) LG_VERDICT(3); else if (p->k <= 4) LG_VERDICT(4); else if (p->k <= 5) LG_VERDICT(5);
-        else if (p->k <= 6) LG_VERDICT(6); else LG_VERDICT(8);
+        if (kk <= 3) LG_VERDICT(3); else if (kk <= 4) LG_VERDICT(4); else if (kk <= 5) LG_VERDICT(5);
+        else if (kk <= 6) LG_VERDICT(6); else LG_VERDICT(8);
     } else {
         // cell grid of the object, then Alg. 2 on the drawn sets, then the links of the moved contacts
         const int64_t ncell = (int64_t)(kGridMax + 1) * (kGridMax + 1) * (kGridMax + 1);
@@ -978,13 +990,13 @@ lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, i
             1, std::min<int64_t>((n_sets * gs + 255) / 256, (int64_t)n_cu * 8)));
 #define LG_OPT(KM, GS)                                                                                           \
     hipLaunchKernelGGL((k_optimize<KM, GS>), ogrid, dim3(256), 0, s, pts, nrm, n_points, ws.valid_poses,           \
-                       ws.n_valid_poses, dom_bits, dom_count, H.F, p->draws, p->k, p->m_edges, (double)p->mu,     \
+                       ws.n_valid_poses, dom_bits, dom_count, palm, H.F, p->draws, p->k, p->m_edges, (double)p->mu, \
                        (double)p->moment_scale, (double)p->eps, p->max_pivots, cs, p->opt_outer, p->opt_inner,    \
                        (double)p->opt_sigma, (uint32_t)p->seed, (uint32_t)(p->seed >> 32), p->request_id,         \
                        p->pose_offset, ws.grid, ws.cell_start, ws.cell_pts, set_pt, verdict, tstar)
 #define LG_OPT_K(GS)                                                                                             \
-    if (p->k <= 3) LG_OPT(3, GS); else if (p->k <= 4) LG_OPT(4, GS); else if (p->k <= 5) LG_OPT(5, GS);        \
-    else if (p->k <= 6) LG_OPT(6, GS); else LG_OPT(8, GS)
+    if (kk <= 3) LG_OPT(3, GS); else if (kk <= 4) LG_OPT(4, GS); else if (kk <= 5) LG_OPT(5, GS);              \
+    else if (kk <= 6) LG_OPT(6, GS); else LG_OPT(8, GS)
         if (gs == 1) { LG_OPT_K(1); } else if (gs == 2) { LG_OPT_K(2); } else if (gs == 4) { LG_OPT_K(4); }
         else if (gs == 8) { LG_OPT_K(8); } else { LG_OPT_K(16); }
 #undef LG_OPT_K

@@ -219,6 +219,7 @@ static lg_status validate_request(const lg_server_params &sp, const lg_request *
         return fail(LG_EINVAL, "request needs points, normals and poses");
     if (r->search.k < 1 || r->search.k > r->field->dh.F)
         return fail(LG_EINVAL, "need 1 <= k <= the field's number of fingers");
+    if (r->search.palm_pt) return fail(LG_EINVAL, "palm contacts are not served (search.palm_pt must be NULL)");
     if (r->search.draws <= 0 || r->search.m_edges < 3 || r->search.m_edges > 16)
         return fail(LG_EINVAL, "bad search parameters");
     if ((int64_t)std::min<int64_t>(sp.chunk_poses, r->n_poses) * r->search.draws > 0x7fffffffLL)

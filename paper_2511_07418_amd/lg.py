@@ -37,7 +37,9 @@ class HandDesc(C.Structure):
                 ("joint_finger", C.c_void_p), ("joint_parent", C.c_void_p),
                 ("joint_origin", C.c_void_p), ("joint_axis", C.c_void_p),
                 ("capsule", C.c_void_p), ("limits", C.c_void_p),
-                ("n_surf", C.c_int32), ("surf", C.c_void_p)]
+                ("n_surf", C.c_int32), ("surf", C.c_void_p),
+                ("n_palm_surf", C.c_int32), ("palm_surf", C.c_void_p),
+                ("n_palm_caps", C.c_int32), ("palm_caps", C.c_void_p)]
 
 
 class FieldParams(C.Structure):
@@ -58,7 +60,7 @@ class SearchParams(C.Structure):
                 ("max_pivots", C.c_int32), ("mu", C.c_float), ("eps", C.c_float),
                 ("moment_scale", C.c_float), ("seed", C.c_uint64), ("request_id", C.c_uint32),
                 ("pose_offset", C.c_int64), ("opt_outer", C.c_int32), ("opt_inner", C.c_int32),
-                ("opt_sigma", C.c_float)]
+                ("opt_sigma", C.c_float), ("palm_pt", C.c_void_p)]
 
 
 class IkParams(C.Structure):
@@ -132,6 +134,8 @@ def _load():
     L.lg_serve_clock.restype = C.c_double
     L.lg_serve_destroy.argtypes = [vp]
     L.lg_place_exhaustive.argtypes = [vp, vp, vp, i32, i32, C.c_uint64, C.c_uint32, i64, vp, vp]
+    L.lg_place_palm.argtypes = [vp, vp, vp, vp, i32, i32, C.c_float, C.c_float, C.c_uint64, C.c_uint32, i64, vp,
+                                vp, vp]
     L.lg_concave_filter.argtypes = [vp, vp, vp, i32, C.c_float, i32, C.c_float, vp, vp, vp, vp, vp]
     L.lg_gather_points.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
     L.lg_prop_num_params.restype = i64
@@ -161,7 +165,8 @@ EXPORTED = ("lg_status_str", "lg_last_error", "lg_version", "lg_build_field", "l
             "lg_field_export", "lg_field_info", "lg_field_release", "lg_query_domains", "lg_query_domains_cone",
             "lg_search_workspace_bytes", "lg_search", "lg_realize", "lg_serve_request_bytes",
             "lg_serve_create", "lg_serve_submit", "lg_serve_poll", "lg_serve_wait", "lg_serve_cancel",
-            "lg_serve_stats", "lg_serve_clock", "lg_serve_destroy", "lg_place_exhaustive", "lg_concave_filter",
+            "lg_serve_stats", "lg_serve_clock", "lg_serve_destroy", "lg_place_exhaustive", "lg_place_palm",
+            "lg_concave_filter",
             "lg_gather_points", "lg_prop_num_params",
             "lg_prop_create", "lg_prop_release", "lg_prop_get_params", "lg_prop_set_params",
             "lg_prop_forward", "lg_prop_backward", "lg_prop_adam", "lg_prop_train_step",
@@ -202,7 +207,7 @@ def _stream(stream) -> C.c_void_p:
 
 
 class _HandKeep:
-    def __init__(self, hand):
+    def __init__(self, hand, palm=None):
         self.arrs = [np.ascontiguousarray(hand.joint_finger, np.int32),
                      np.ascontiguousarray(hand.joint_parent, np.int32),
                      np.ascontiguousarray(hand.joint_origin, np.float32),
@@ -212,7 +217,13 @@ class _HandKeep:
                      np.ascontiguousarray(hand.surf, np.float32)]
         a = self.arrs
         self.desc = HandDesc(int(hand.n_fingers), int(a[0].shape[0]), _hp(a[0]), _hp(a[1]), _hp(a[2]),
-                             _hp(a[3]), _hp(a[4]), _hp(a[5]), int(a[6].shape[1]), _hp(a[6]))
+                             _hp(a[3]), _hp(a[4]), _hp(a[5]), int(a[6].shape[1]), _hp(a[6]), 0, None, 0, None)
+        if palm is not None:
+            ps = np.ascontiguousarray(palm.surf, np.float32)
+            pc = np.ascontiguousarray(palm.caps, np.float32)
+            self.arrs += [ps, pc]
+            self.desc.n_palm_surf, self.desc.palm_surf = int(ps.shape[0]), _hp(ps)
+            self.desc.n_palm_caps, self.desc.palm_caps = int(pc.shape[0]), _hp(pc)
 
 
 def _field_params(fp, keep_witness: bool):
@@ -256,8 +267,10 @@ class Field:
 
 
 # ---- the four calls of the hot path -----------------------------------------
-def lg_build_field(hand, fp, keep_witness: bool = True, stream=None) -> Field:
-    hk = _HandKeep(hand)
+def lg_build_field(hand, fp, keep_witness: bool = True, stream=None, palm=None) -> Field:
+    """Build the contact field of ``hand``; ``palm`` (a static link with
+    ``surf`` [S, 6] and ``caps`` [C, 7], base frame) is kept with it."""
+    hk = _HandKeep(hand, palm)
     p, gf = _field_params(fp, keep_witness)
     out = C.c_void_p()
     _check(_lib.lg_build_field(C.byref(hk.desc), C.byref(p), _stream(stream), C.byref(out)),
@@ -265,8 +278,8 @@ def lg_build_field(hand, fp, keep_witness: bool = True, stream=None) -> Field:
     return Field(out, hand)
 
 
-def lg_field_import(hand, fp, bits: np.ndarray, witness: Optional[np.ndarray] = None) -> Field:
-    hk = _HandKeep(hand)
+def lg_field_import(hand, fp, bits: np.ndarray, witness: Optional[np.ndarray] = None, palm=None) -> Field:
+    hk = _HandKeep(hand, palm)
     p, gf = _field_params(fp, witness is not None)
     b = np.ascontiguousarray(bits, np.uint32)
     w = None if witness is None else np.ascontiguousarray(witness, np.int32)
@@ -331,10 +344,13 @@ class SearchBuffers:
 
 
 def lg_search(field: Field, pts, nrm, poses, dom_bits, dom_count, sp, bufs: Optional[SearchBuffers] = None,
-              max_pivots: int = 1000, stream=None) -> SearchBuffers:
+              max_pivots: int = 1000, stream=None, palm_pt: Optional[torch.Tensor] = None) -> SearchBuffers:
+    """``palm_pt`` (device int32 [P], from lg_place_palm): each pose's fixed palm contact."""
     N, P = int(pts.shape[1]), int(poses.shape[0])
     if bufs is None:
         bufs = SearchBuffers(P, sp, pts.device, max_pivots, n_points=N)
+    bufs.p.palm_pt = None if palm_pt is None else palm_pt.data_ptr()
+    bufs.palm_pt = palm_pt          # the struct holds only its address
     _check(_lib.lg_search(field.handle, _ptr(pts), _ptr(nrm), N, _ptr(poses), P, _ptr(dom_bits),
                           _ptr(dom_count), C.byref(bufs.p), _ptr(bufs.set_pt), _ptr(bufs.set_link),
                           _ptr(bufs.verdict), _ptr(bufs.tstar), _ptr(bufs.acc_list), _ptr(bufs.n_acc),
@@ -382,6 +398,19 @@ def lg_realize(field: Field, sdf: Sdf, pts, nrm, poses, set_pt, set_link, k: int
 
 def version() -> str:
     return _lib.lg_version().decode()
+
+
+def lg_place_palm(field: Field, sdf: Sdf, pts: torch.Tensor, nrm: torch.Tensor, poses: torch.Tensor, prob: float,
+                  margin: float, seed: int, request_id: int = 0, pose_offset: int = 0,
+                  palm_pt: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Static-link placements in place over device poses [P, 12]; returns palm_pt [P] int32."""
+    N, P = int(pts.shape[1]), int(poses.shape[0])
+    if palm_pt is None:
+        palm_pt = torch.empty((P,), dtype=torch.int32, device=pts.device)
+    _check(_lib.lg_place_palm(field.handle, C.byref(sdf), _ptr(pts), _ptr(nrm), N, P, float(prob), float(margin),
+                              int(seed) & 0xFFFFFFFFFFFFFFFF, int(request_id), int(pose_offset), _ptr(poses),
+                              _ptr(palm_pt), _stream(stream)), "lg_place_palm")
+    return palm_pt
 
 
 def lg_place_exhaustive(field: Field, pts: torch.Tensor, nrm: torch.Tensor, n_poses: int, seed: int,

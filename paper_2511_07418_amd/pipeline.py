@@ -19,8 +19,9 @@ class Pipeline:
     synchronising; ``valid_count()`` synchronises and reads the result."""
 
     def __init__(self, field: lg.Field, pts: np.ndarray, nrm: np.ndarray, poses: np.ndarray, sp,
-                 ik=None, sdf=None, device: str = "cuda", max_pivots: int = 1000, cos_hit=None):
+                 ik=None, sdf=None, device: str = "cuda", max_pivots: int = 1000, cos_hit=None, palm_pt=None):
         self.field = field
+        self.palm_pt = palm_pt      # device int32 [P] of lg_place_palm, or None (no static-link contacts)
         self.cos_hit = cos_hit      # None: nearest-bin query; else the cone (theta_hit) query
         self.dev = torch.device(device)
         self.pts = torch.from_numpy(np.ascontiguousarray(np.asarray(pts, np.float32).T)).to(self.dev)
@@ -60,7 +61,7 @@ class Pipeline:
         if request_id is not None:
             self.sbuf.p.request_id = int(request_id)
         lg.lg_search(self.field, self.pts, self.nrm, self.poses, self.dom_bits, self.dom_count, self.sp,
-                     bufs=self.sbuf, stream=stream)
+                     bufs=self.sbuf, stream=stream, palm_pt=self.palm_pt)
 
     def realize(self, stream=None):
         if self.ik is None:
