@@ -66,6 +66,8 @@ def parse():
                          "per set and the others take random joint values")
     ap.add_argument("--concave-filter", action="store_true",
                     help="drop the object's concave points first (8 mm box, 1 mm depth); the steps use the rest")
+    ap.add_argument("--palm-prob", type=float, default=0.0,
+                    help="probability of a static-link (palm) placement per pose (Sec. 5.1); 0 = none")
     ap.add_argument("--placement", default="canonical", choices=["canonical", "exhaustive"],
                     help="palm poses: canonical (random pose above the palm) or exhaustive (an object point "
                          "on a random contact vector of the field)")
@@ -449,24 +451,23 @@ def main():
     if args.k > 0:
         import dataclasses
         w.search = dataclasses.replace(w.search, k=args.k)
+    palm = synth.palm_for(args.workload) if args.palm_prob > 0 else None
+    if palm is not None and w.sdf is None:
+        raise SystemExit("--palm-prob needs the object's SDF (workload c3)")
     t_build = time.perf_counter()
-    field = lg.lg_build_field(w.hand, w.field, keep_witness=w.ik is not None)
+    field = lg.lg_build_field(w.hand, w.field, keep_witness=w.ik is not None, palm=palm)
     t_build = time.perf_counter() - t_build
-    poses = w.poses
-    if args.placement == "exhaustive":
-        pts_soa = torch.from_numpy(np.ascontiguousarray(w.obj.pts.T)).cuda()
-        nrm_soa = torch.from_numpy(np.ascontiguousarray(w.obj.nrm.T)).cuda()
-        poses = lg.lg_place_exhaustive(field, pts_soa, nrm_soa, len(w.poses), seed=args.seed + 1)
-        torch.cuda.synchronize()
     cos_hit = math.cos(math.radians(args.cone_deg)) if args.cone_deg > 0 else None
     obj_pts, obj_nrm, concave = w.obj.pts, w.obj.nrm, None
+    sdf_vals = sdf_s = None
+    if w.sdf is not None:
+        sdf_vals = torch.from_numpy(np.ascontiguousarray(w.sdf.values, np.float32)).cuda()
+        sdf_s = lg.sdf_struct(w.sdf, sdf_vals)
+    p_soa = torch.from_numpy(np.ascontiguousarray(w.obj.pts.T)).cuda()
+    n_soa = torch.from_numpy(np.ascontiguousarray(w.obj.nrm.T)).cuda()
     if args.concave_filter:
         if w.sdf is None:
             raise SystemExit("--concave-filter needs the object's SDF (workload c3)")
-        sdf_vals = torch.from_numpy(np.ascontiguousarray(w.sdf.values, np.float32)).cuda()
-        sdf_s = lg.sdf_struct(w.sdf, sdf_vals)
-        p_soa = torch.from_numpy(np.ascontiguousarray(w.obj.pts.T)).cuda()
-        n_soa = torch.from_numpy(np.ascontiguousarray(w.obj.nrm.T)).cuda()
         lg.lg_concave_filter(sdf_s, p_soa, n_soa)          # warm-up (module load)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -474,13 +475,29 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         nk = int(cr.n_kept.item())
-        po, no = lg.lg_gather_points(p_soa, n_soa, cr.kept_idx, nk)
-        obj_pts, obj_nrm = po.t().cpu().numpy(), no.t().cpu().numpy()
+        p_soa, n_soa = lg.lg_gather_points(p_soa, n_soa, cr.kept_idx, nk)
+        obj_pts, obj_nrm = p_soa.t().cpu().numpy(), n_soa.t().cpu().numpy()
         concave = {"box_edge_m": 0.008, "lattice": 4, "max_depth_m": 0.001, "kept": nk, "of": int(w.obj.n),
                    "filter_ms": e0.elapsed_time(e1)}
         print(f"[bench] concave filter kept {nk} of {w.obj.n} points in {concave['filter_ms']:.3f} ms",
               file=sys.stderr, flush=True)
-    pipe = Pipeline(field, obj_pts, obj_nrm, poses, w.search, ik=w.ik, sdf=w.sdf, cos_hit=cos_hit)
+    # placement (Sec. 5.1): the poses are the step's input, made before the timed region
+    poses = w.poses
+    if args.placement == "exhaustive":
+        poses = lg.lg_place_exhaustive(field, p_soa, n_soa, len(w.poses), seed=args.seed + 1)
+        torch.cuda.synchronize()
+    palm_pt, palm_info = None, None
+    if palm is not None:
+        if not isinstance(poses, torch.Tensor):
+            poses = torch.from_numpy(np.ascontiguousarray(poses, np.float32)).cuda()
+        palm_pt = lg.lg_place_palm(field, sdf_s, p_soa, n_soa, poses, args.palm_prob, 0.002, seed=args.seed + 2)
+        torch.cuda.synchronize()
+        pc = palm_pt.cpu().numpy()
+        palm_info = {"prob": args.palm_prob, "placed": int((pc >= 0).sum()), "rejected": int((pc == -2).sum()),
+                     "radius_m": palm.radius, "margin_m": 0.002}
+        print(f"[bench] palm placements: {palm_info['placed']} kept, {palm_info['rejected']} rejected",
+              file=sys.stderr, flush=True)
+    pipe = Pipeline(field, obj_pts, obj_nrm, poses, w.search, ik=w.ik, sdf=w.sdf, cos_hit=cos_hit, palm_pt=palm_pt)
     print(f"[bench] {args.workload}: field built in {t_build:.2f}s ({field.info()['bits_set']} bits), "
           f"P={pipe.P} N={pipe.N}", file=sys.stderr, flush=True)
 
@@ -601,7 +618,8 @@ def main():
                    "contact_opt": ({"rounds": args.opt_outer, "candidates": args.opt_inner,
                                     "sigma_m": args.opt_sigma} if args.opt_outer > 0 else None),
                    "self_collision": bool(args.self_collision), "placement": args.placement,
-                   "cone_deg": args.cone_deg or None, "contacts": int(w.search.k), "concave_filter": concave},
+                   "cone_deg": args.cone_deg or None, "contacts": int(w.search.k), "concave_filter": concave,
+                   "palm": palm_info},
         "valid_per_step": n_valid,
         "accepted_sets_per_step": n_acc,
         "stage_ms": {"query": q_ms, "search": float(st[:, 1].mean()), "realize": float(st[:, 2].mean())},
@@ -611,7 +629,7 @@ def main():
                      # the counters were taken on the default query (canonical poses, all points, nearest bin)
                      "traffic": (query_traffic() if (args.placement == "canonical" and not args.cone_deg
                                                      and not args.concave_filter and args.workload == "c3"
-                                                     and args.seed == 0) else None),
+                                                     and args.seed == 0 and not args.palm_prob) else None),
                      "kernel": "k_query", "alg_bytes_per_launch": alg_bytes,
                      "in_window_link_lookups": link_lookups, "in_window_finger_lookups": finger_lookups,
                      "impl_bytes_per_launch": impl_bytes,
