@@ -169,6 +169,31 @@ lg_status lg_query_domains_cone(const lg_field *field, const float *pts, const f
                                 const float *poses, int32_t n_poses, float cos_hit, uint32_t *dom_bits,
                                 uint32_t *dom_count, void *stream);
 
+/*
+ * lg_chunk_bounds -- bounding spheres of the object's chunks of 64 consecutive
+ * points (a one-level bounding-volume hierarchy over the object, as the
+ * paper's BVH over contact patches in Alg. 1): bounds DEVICE [ceil(N/64)][4]
+ * float (centre of the chunk's box, radius padded by 1e-5 relative + 1e-7 m),
+ * 16-byte aligned.  pts DEVICE SoA [3][N].  Compute once per object.
+ * lg_query_domains_bounded -- lg_query_domains with those bounds: a (chunk,
+ * finger) pair whose sphere (plus 1e-3 voxel) misses the finger's window is
+ * skipped (its domain bits are 0, as the lookups would give), and a chunk
+ * missing every window is not read.  Outputs are identical to
+ * lg_query_domains'; the saving depends on spatially compact chunks, e.g.
+ * points in the order of lg_morton_order.  LG_EINVAL on null or misaligned
+ * bounds, plus lg_query_domains' errors.
+ */
+lg_status lg_chunk_bounds(const float *pts, int32_t n_points, float *bounds, void *stream);
+lg_status lg_query_domains_bounded(const lg_field *field, const float *pts, const float *nrm, int32_t n_points,
+                                   const float *poses, int32_t n_poses, const float *bounds, uint32_t *dom_bits,
+                                   uint32_t *dom_count, void *stream);
+/* lg_morton_order -- perm_host[j] = index of the j-th point in Morton order
+ * (10 bits per axis over the points' bounding cube, x lowest; stable).
+ * pts_host: HOST [N][3].  Reorder points and normals with it once per object
+ * (e.g. lg_gather_points); domain bits then index the reordered points.
+ * LG_EINVAL on null buffers or non-finite points. */
+lg_status lg_morton_order(const float *pts_host, int32_t n_points, int32_t *perm_host);
+
 /* Search parameters (Sec. 5.3 draws, Eq. 1-2 criterion). */
 typedef struct {
     int32_t draws;        /* D sets per pose */

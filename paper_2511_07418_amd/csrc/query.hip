@@ -2,12 +2,21 @@
 // merge of Sec. 5.3.
 //
 // One workgroup per pose; each wave sweeps 64 consecutive object points
-// (structure-of-arrays, Morton-sorted by the caller so a wave touches a
-// compact patch of the field).  Per point: x = R p + t folded into one affine
-// map per finger window, query normal -R n, its bin, one 4/8-byte gather of
-// the finger's merged table, and a wave ballot that yields the 64 domain bits
-// of the finger for the chunk.  Counts are popcounts of the ballots.
+// (structure-of-arrays).  Per point: x = R p + t folded into one affine map
+// per finger window, query normal -R n, its bin, one 4/8-byte gather of the
+// finger's merged table, and a wave ballot that yields the 64 domain bits of
+// the finger for the chunk.  Counts are popcounts of the ballots.
+//
+// With chunk bounds (a bounding sphere per 64 consecutive points, a one-level
+// bounding-volume hierarchy over the object; tight when the points are in
+// Morton order), a (chunk, finger) pair whose sphere misses the finger's
+// window is skipped: its 64 domain bits are zero without a lookup, and a
+// chunk that misses every window is not loaded at all.
+#include <math.h>
+
 #include <algorithm>
+#include <utility>
+#include <vector>
 
 #include "lg_internal.h"
 
@@ -15,11 +24,36 @@ namespace lg {
 
 constexpr int kQueryThreads = 256;
 constexpr int kQueryWaves = kQueryThreads / 64;
+constexpr float kCullMargin = 1e-3f;  // voxels added to a chunk's radius (float rounding is ~1e-4)
+
+// Bounding sphere (centre of the box, largest distance) of each chunk of 64
+// consecutive points; one wave per chunk, radius padded for rounding.
+__global__ void __launch_bounds__(256)
+k_chunk_bounds(const float *__restrict__ pts, int N, float4 *__restrict__ bounds)
+{
+    const int nchunks = (N + 63) >> 6;
+    const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (chunk >= nchunks) return;  // uniform per wave
+    const int i = min(chunk * 64 + lane, N - 1);  // lanes past N repeat the last point
+    const float x = pts[i], y = pts[N + i], z = pts[2 * N + i];
+    float lo[3] = {x, y, z}, hi[3] = {x, y, z};
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], off, 64));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off, 64));
+        }
+    const float cx = 0.5f * (lo[0] + hi[0]), cy = 0.5f * (lo[1] + hi[1]), cz = 0.5f * (lo[2] + hi[2]);
+    const float dx = x - cx, dy = y - cy, dz = z - cz;
+    float r = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+    for (int off = 32; off > 0; off >>= 1) r = fmaxf(r, __shfl_xor(r, off, 64));
+    if (lane == 0) bounds[chunk] = make_float4(cx, cy, cz, fmaf(r, 1e-5f, r + 1e-7f));
+}
 
 template <int W, int FM>
-__global__ void __launch_bounds__(kQueryThreads)
+__global__ void __launch_bounds__(kQueryThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict__ pts,
-        const float *__restrict__ nrm, int N, const float *__restrict__ poses,
+        const float *__restrict__ nrm, int N, const float *__restrict__ poses, const float4 *__restrict__ bounds,
         uint32_t *__restrict__ dom_bits, uint32_t *__restrict__ dom_count)
 {
     __shared__ float cb[3 * kMaxBins];
@@ -52,7 +86,46 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
 #pragma unroll
         for (int f = 0; f < FM; ++f) acc[f] = 0;
         const int c_end = min(nchunks, (blk + 1) * 32);
+        // skip[f] bit j: chunk blk * 32 + j cannot reach finger f's window.
+        // Lane l tests chunk l % 32 against finger f0 + l / 32, two fingers per
+        // ballot: the distance from the sphere's centre (biased voxel
+        // coordinates) to the window box [G, 2G]^3 against its radius.
+        uint32_t skip[FM];
+#pragma unroll
+        for (int f = 0; f < FM; ++f) skip[f] = 0u;
+        uint32_t skip_all = 0u;
+        if (bounds) {
+#pragma unroll
+            for (int f0 = 0; f0 < FM; f0 += 2) {
+                if (f0 >= F) break;
+                const int f = min(f0 + (lane >> 5), F - 1);
+                const int ch = blk * 32 + (lane & 31);
+                bool out = true;
+                if (ch < nchunks) {
+                    const float4 sb = bounds[ch];
+                    const Affine &a = aff[f];
+                    const float ux = fmaf(a.m[0], sb.x, fmaf(a.m[1], sb.y, fmaf(a.m[2], sb.z, a.m[3])));
+                    const float uy = fmaf(a.m[4], sb.x, fmaf(a.m[5], sb.y, fmaf(a.m[6], sb.z, a.m[7])));
+                    const float uz = fmaf(a.m[8], sb.x, fmaf(a.m[9], sb.y, fmaf(a.m[10], sb.z, a.m[11])));
+                    const float gl = (float)G, gh = (float)(2 * G);
+                    const float dx = fmaxf(fmaxf(gl - ux, ux - gh), 0.f);
+                    const float dy = fmaxf(fmaxf(gl - uy, uy - gh), 0.f);
+                    const float dz = fmaxf(fmaxf(gl - uz, uz - gh), 0.f);
+                    const float rv = fmaf(sb.w, H.inv_h, kCullMargin);
+                    out = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) > rv * rv;
+                }
+                const unsigned long long m = __ballot(out);
+                skip[f0] = (uint32_t)m;
+                if (f0 + 1 < FM) skip[f0 + 1] = (uint32_t)(m >> 32);
+            }
+            skip_all = ~0u;
+#pragma unroll
+            for (int f = 0; f < FM; ++f)
+                if (f < F) skip_all &= skip[f];
+        }
         for (int chunk = blk * 32; chunk < c_end; ++chunk) {
+            const uint32_t cbit = 1u << (chunk - blk * 32);
+            if (skip_all & cbit) continue;  // no window in reach: its ballot words stay 0
             // re-read the per-finger maps from LDS every chunk instead of pinning
             // 12 x F registers for them: halves the register footprint
             asm volatile("" ::: "memory");
@@ -76,7 +149,7 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
 #pragma unroll
             for (int f = 0; f < FM; ++f) {
                 word[f] = 0;
-                if (f < F) {
+                if (f < F && !(skip[f] & cbit)) {
                     const int v = window_voxel(aff[f], G, px, py, pz);
                     const uint32_t *tab = merged + f * G3W;  // uniform base, 32-bit lane offsets
                     if (valid && v >= 0) word[f] = tab[(uint32_t)v * W + (uint32_t)(b >> 5)];
@@ -86,6 +159,7 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
 #pragma unroll
             for (int f = 0; f < FM; ++f) {
                 if (f >= F) break;
+                if (skip[f] & cbit) continue;  // the ballot would be 0
                 const bool hit = (word[f] >> (b & 31)) & 1u;
                 const unsigned long long m = __ballot(hit);
                 c[f] += (uint32_t)__popcll(m);
@@ -217,9 +291,9 @@ k_query_cone(DevHand H, const uint32_t *__restrict__ merged, const float *__rest
 
 using namespace lg;
 
-extern "C" lg_status lg_query_domains(const lg_field *field, const float *pts, const float *nrm, int32_t n_points,
-                                      const float *poses, int32_t n_poses, uint32_t *dom_bits, uint32_t *dom_count,
-                                      void *stream)
+static lg_status query_domains(const lg_field *field, const float *pts, const float *nrm, int32_t n_points,
+                               const float *poses, int32_t n_poses, const float4 *bounds, uint32_t *dom_bits,
+                               uint32_t *dom_count, void *stream)
 {
     if (!field) return fail(LG_EINVAL, "null field");
     if (n_points < 0 || n_poses < 0) return fail(LG_EINVAL, "negative size");
@@ -230,7 +304,7 @@ extern "C" lg_status lg_query_domains(const lg_field *field, const float *pts, c
     const DevHand &H = field->dh;
 #define LG_QUERY(W, FM)                                                                                     \
     hipLaunchKernelGGL((k_query<W, FM>), dim3(n_poses), dim3(kQueryThreads), 0, s, H, field->d_merged, pts, nrm, \
-                       n_points, poses, dom_bits, dom_count)
+                       n_points, poses, bounds, dom_bits, dom_count)
     if (H.W == 1) {
         if (H.F <= 3) LG_QUERY(1, 3); else if (H.F <= 4) LG_QUERY(1, 4); else if (H.F <= 5) LG_QUERY(1, 5); else LG_QUERY(1, 8);
     } else {
@@ -238,6 +312,71 @@ extern "C" lg_status lg_query_domains(const lg_field *field, const float *pts, c
     }
 #undef LG_QUERY
     LG_HIP(hipGetLastError());
+    return LG_OK;
+}
+
+extern "C" lg_status lg_query_domains(const lg_field *field, const float *pts, const float *nrm, int32_t n_points,
+                                      const float *poses, int32_t n_poses, uint32_t *dom_bits, uint32_t *dom_count,
+                                      void *stream)
+{
+    return query_domains(field, pts, nrm, n_points, poses, n_poses, nullptr, dom_bits, dom_count, stream);
+}
+
+extern "C" lg_status lg_query_domains_bounded(const lg_field *field, const float *pts, const float *nrm,
+                                              int32_t n_points, const float *poses, int32_t n_poses,
+                                              const float *bounds, uint32_t *dom_bits, uint32_t *dom_count,
+                                              void *stream)
+{
+    if (n_points > 0 && n_poses > 0 && !bounds) return fail(LG_EINVAL, "null chunk bounds");
+    if (reinterpret_cast<uintptr_t>(bounds) % 16 != 0) return fail(LG_EINVAL, "chunk bounds must be 16-byte aligned");
+    return query_domains(field, pts, nrm, n_points, poses, n_poses, reinterpret_cast<const float4 *>(bounds),
+                         dom_bits, dom_count, stream);
+}
+
+extern "C" lg_status lg_chunk_bounds(const float *pts, int32_t n_points, float *bounds, void *stream)
+{
+    if (n_points < 0) return fail(LG_EINVAL, "negative size");
+    if (n_points == 0) return LG_OK;
+    if (!pts || !bounds) return fail(LG_EINVAL, "null device buffer");
+    if (reinterpret_cast<uintptr_t>(bounds) % 16 != 0) return fail(LG_EINVAL, "chunk bounds must be 16-byte aligned");
+    const int nchunks = (n_points + 63) / 64;
+    hipLaunchKernelGGL(k_chunk_bounds, dim3((unsigned)((nchunks + 3) / 4)), dim3(256), 0, as_stream(stream), pts,
+                       n_points, reinterpret_cast<float4 *>(bounds));
+    LG_HIP(hipGetLastError());
+    return LG_OK;
+}
+
+// Morton (Z-order) permutation of host points: 10 bits per axis over the
+// points' bounding cube, bits interleaved x, y, z from the lowest; ties keep
+// the input order.
+extern "C" lg_status lg_morton_order(const float *pts_host, int32_t n_points, int32_t *perm_host)
+{
+    if (n_points < 0) return fail(LG_EINVAL, "negative size");
+    if (n_points == 0) return LG_OK;
+    if (!pts_host || !perm_host) return fail(LG_EINVAL, "null host buffer");
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = 0; i < n_points; ++i)
+        for (int a = 0; a < 3; ++a) {
+            const double v = pts_host[3 * i + a];
+            if (!std::isfinite(v)) return fail(LG_EINVAL, "non-finite point");
+            lo[a] = std::min(lo[a], v);
+            hi[a] = std::max(hi[a], v);
+        }
+    const double ext = std::max(std::max(hi[0] - lo[0], hi[1] - lo[1]), std::max(hi[2] - lo[2], 1e-30));
+    std::vector<std::pair<uint32_t, int32_t>> key((size_t)n_points);
+    for (int i = 0; i < n_points; ++i) {
+        uint32_t code = 0;
+        for (int a = 0; a < 3; ++a) {
+            const uint32_t q = (uint32_t)std::min(1023.0, std::max(0.0, (pts_host[3 * i + a] - lo[a]) / ext * 1023.0));
+            for (int b = 0; b < 10; ++b) code |= ((q >> b) & 1u) << (3 * b + a);
+        }
+        key[(size_t)i] = {code, i};
+    }
+    std::stable_sort(key.begin(), key.end(),
+                     [](const std::pair<uint32_t, int32_t> &x, const std::pair<uint32_t, int32_t> &y) {
+                         return x.first < y.first;
+                     });
+    for (int i = 0; i < n_points; ++i) perm_host[i] = key[(size_t)i].second;
     return LG_OK;
 }
 

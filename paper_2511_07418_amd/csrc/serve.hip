@@ -125,7 +125,7 @@ class Slab {
 
 // Sizes of one request's device buffers (inputs + one chunk of work).
 struct ReqLayout {
-    uint64_t pts, nrm, poses, sdf, dom_bits, dom_count, set_pt, set_link, verdict, tstar, acc, n_acc, ws;
+    uint64_t pts, nrm, bounds, poses, sdf, dom_bits, dom_count, set_pt, set_link, verdict, tstar, acc, n_acc, ws;
     uint64_t q, err, ang, depth, valid, counters, total;
 };
 
@@ -144,6 +144,7 @@ static ReqLayout layout_of(const lg_server_params &sp, const lg_request &r)
     };
     L.pts = take(12 * N);
     L.nrm = take(12 * N);
+    L.bounds = take(16 * (uint64_t)((N + 63) / 64));  // chunk bounding spheres of the object
     L.poses = take(48 * (uint64_t)r.n_poses);
     const int64_t G = r.realize ? r.sdf_dims : 0;
     L.sdf = take(4 * (uint64_t)(G * G * G));
@@ -243,7 +244,8 @@ static lg_status launch_chunk(lg_server *S, Req *q)
     const float *poses = reinterpret_cast<const float *>(base + L.poses) + 12 * g0;
     uint32_t *db = reinterpret_cast<uint32_t *>(base + L.dom_bits);
     uint32_t *dc = reinterpret_cast<uint32_t *>(base + L.dom_count);
-    lg_status st = lg_query_domains(r.field, pts, nrm, r.n_points, poses, P, db, dc, s);
+    lg_status st = lg_query_domains_bounded(r.field, pts, nrm, r.n_points, poses, P,
+                                            reinterpret_cast<const float *>(base + L.bounds), db, dc, s);
     if (st != LG_OK) return st;
     lg_search_params sp = r.search;
     sp.request_id = r.request_id;
@@ -310,6 +312,9 @@ static lg_status admit(lg_server *S, Req *q)
     LG_HIP(hipMemcpyAsync(base + L.pts, q->pts.data(), 12 * N, hipMemcpyHostToDevice, s));
     LG_HIP(hipMemcpyAsync(base + L.nrm, q->nrm.data(), 12 * N, hipMemcpyHostToDevice, s));
     LG_HIP(hipMemcpyAsync(base + L.poses, q->poses.data(), 48 * (size_t)q->r.n_poses, hipMemcpyHostToDevice, s));
+    const lg_status st = lg_chunk_bounds(reinterpret_cast<const float *>(base + L.pts), (int32_t)N,
+                                         reinterpret_cast<float *>(base + L.bounds), s);
+    if (st != LG_OK) return st;
     if (q->r.realize)
         LG_HIP(hipMemcpyAsync(base + L.sdf, q->sdf.data(), 4 * q->sdf.size(), hipMemcpyHostToDevice, s));
     LG_HIP(hipMemsetAsync(base + L.counters, 0, 24, s));

@@ -117,6 +117,9 @@ def _load():
     L.lg_field_release.argtypes = [vp]
     L.lg_query_domains.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp]
     L.lg_query_domains_cone.argtypes = [vp, vp, vp, i32, vp, i32, C.c_float, vp, vp, vp]
+    L.lg_query_domains_bounded.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp, vp]
+    L.lg_chunk_bounds.argtypes = [vp, i32, vp, vp]
+    L.lg_morton_order.argtypes = [vp, i32, vp]
     L.lg_search_workspace_bytes.argtypes = [i32, i32, vp]
     L.lg_search_workspace_bytes.restype = sz
     L.lg_search.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
@@ -163,6 +166,7 @@ _lib = _load()
 
 EXPORTED = ("lg_status_str", "lg_last_error", "lg_version", "lg_build_field", "lg_field_import",
             "lg_field_export", "lg_field_info", "lg_field_release", "lg_query_domains", "lg_query_domains_cone",
+            "lg_query_domains_bounded", "lg_chunk_bounds", "lg_morton_order",
             "lg_search_workspace_bytes", "lg_search", "lg_realize", "lg_serve_request_bytes",
             "lg_serve_create", "lg_serve_submit", "lg_serve_poll", "lg_serve_wait", "lg_serve_cancel",
             "lg_serve_stats", "lg_serve_clock", "lg_serve_destroy", "lg_place_exhaustive", "lg_place_palm",
@@ -318,6 +322,38 @@ def lg_query_domains_cone(field: Field, pts, nrm, poses, cos_hit: float, dom_bit
     _check(_lib.lg_query_domains_cone(field.handle, _ptr(pts), _ptr(nrm), N, _ptr(poses), P, float(cos_hit),
                                       _ptr(dom_bits), _ptr(dom_count), _stream(stream)), "lg_query_domains_cone")
     return dom_bits, dom_count
+
+
+def lg_chunk_bounds(pts: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Bounding spheres [ceil(N/64), 4] (device) of the chunks of 64 consecutive points of SoA pts [3, N]."""
+    N = int(pts.shape[1])
+    if out is None:
+        out = torch.empty((max(1, (N + 63) // 64), 4), dtype=torch.float32, device=pts.device)
+    _check(_lib.lg_chunk_bounds(_ptr(pts), N, _ptr(out), _stream(stream)), "lg_chunk_bounds")
+    return out
+
+
+def lg_query_domains_bounded(field: Field, pts, nrm, poses, bounds, dom_bits=None, dom_count=None, stream=None):
+    """lg_query_domains with chunk bounds (lg_chunk_bounds of the same points); identical outputs."""
+    N, P, F = int(pts.shape[1]), int(poses.shape[0]), field.n_fingers
+    NW = (N + 31) // 32
+    dev = pts.device
+    if dom_bits is None:
+        dom_bits = torch.empty((P, F, NW), dtype=torch.int32, device=dev)
+    if dom_count is None:
+        dom_count = torch.empty((P, F), dtype=torch.int32, device=dev)
+    _check(_lib.lg_query_domains_bounded(field.handle, _ptr(pts), _ptr(nrm), N, _ptr(poses), P, _ptr(bounds),
+                                         _ptr(dom_bits), _ptr(dom_count), _stream(stream)),
+           "lg_query_domains_bounded")
+    return dom_bits, dom_count
+
+
+def lg_morton_order(pts_host: np.ndarray) -> np.ndarray:
+    """Morton permutation (int32 [N]) of host points [N, 3]."""
+    p = np.ascontiguousarray(pts_host, np.float32)
+    perm = np.zeros(p.shape[0], np.int32)
+    _check(_lib.lg_morton_order(_hp(p), int(p.shape[0]), _hp(perm)), "lg_morton_order")
+    return perm
 
 
 def search_params(sp, max_pivots: int = 1000) -> SearchParams:

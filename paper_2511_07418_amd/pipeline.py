@@ -31,6 +31,9 @@ class Pipeline:
         else:
             self.poses = torch.from_numpy(np.ascontiguousarray(poses, np.float32)).to(self.dev)
         self.N, self.P = int(self.pts.shape[1]), int(self.poses.shape[0])
+        # bounding spheres of the object's 64-point chunks (once per object): the
+        # query skips (chunk, finger) pairs that cannot reach the finger's window
+        self.bounds = lg.lg_chunk_bounds(self.pts) if self.N > 0 else None
         self.sp = sp
         F = field.n_fingers
         NW = (self.N + 31) // 32
@@ -49,8 +52,8 @@ class Pipeline:
 
     def query(self, stream=None):
         if self.cos_hit is None:
-            lg.lg_query_domains(self.field, self.pts, self.nrm, self.poses, self.dom_bits, self.dom_count,
-                                stream=stream)
+            lg.lg_query_domains_bounded(self.field, self.pts, self.nrm, self.poses, self.bounds, self.dom_bits,
+                                        self.dom_count, stream=stream)
         else:
             lg.lg_query_domains_cone(self.field, self.pts, self.nrm, self.poses, self.cos_hit, self.dom_bits,
                                      self.dom_count, stream=stream)

@@ -122,3 +122,32 @@ def test_concave_filter_validation_without_device_work(lglib):
     assert L.lg_gather_points(dummy, dummy, 8, dummy, -1, dummy, dummy, None) == EINVAL
     assert L.lg_gather_points(dummy, None, 8, dummy, 4, dummy, dummy, None) == EINVAL
     assert L.lg_gather_points(None, None, 8, None, 0, None, None, None) == lglib.LG_OK   # nothing to do
+
+
+def test_morton_order_on_the_host(lglib):
+    """lg_morton_order is a host routine: a permutation whose Morton codes,
+    recomputed here from the definition (10 bits per axis over the bounding
+    cube, x lowest), never decrease, with ties in input order."""
+    rng = np.random.default_rng(4)
+    p = rng.normal(size=(5000, 3)).astype(np.float32) * np.float32([0.05, 0.02, 0.08])
+    p[100:110] = p[100]                                  # ties
+    perm = lglib.lg_morton_order(p)
+    assert sorted(perm.tolist()) == list(range(len(p)))
+    q = p.astype(np.float64)
+    lo = q.min(0)
+    ext = (q.max(0) - lo).max()
+    iq = np.clip(np.floor((q - lo) / ext * 1023.0), 0, 1023).astype(np.uint64)
+    code = np.zeros(len(p), np.uint64)
+    for b in range(10):
+        for a in range(3):
+            code |= ((iq[:, a] >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + a)
+    assert (np.diff(code[perm].astype(np.int64)) >= 0).all()
+    tied = [i for i in perm if 100 <= i < 110]
+    assert tied == sorted(tied)
+    L = lglib.lib()
+    assert L.lg_morton_order(None, 4, None) == lglib.LG_EINVAL
+    bad = p.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(lglib.LgError):
+        lglib.lg_morton_order(bad)
+    assert L.lg_chunk_bounds(None, 10, None, None) == lglib.LG_EINVAL

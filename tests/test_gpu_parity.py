@@ -137,12 +137,15 @@ def test_field_build_c3_full_samples_witness_certificates():
 # ---------------------------------------------------------------------------
 # contact-domain query (stage isolated: the oracle's field imported)
 # ---------------------------------------------------------------------------
-def _query_check(w, ref_bits, poses_idx=None, chunk_poses=None):
+def _query_check(w, ref_bits, poses_idx=None, chunk_poses=None, bounded=False):
     lg = lgmod()
     field = lg.lg_field_import(w.hand, w.field, ref_bits)
     pts, nrm = soa(w.obj.pts), soa(w.obj.nrm)
     poses = dev(w.poses)
-    db, dc = lg.lg_query_domains(field, pts, nrm, poses)
+    if bounded:
+        db, dc = lg.lg_query_domains_bounded(field, pts, nrm, poses, lg.lg_chunk_bounds(pts))
+    else:
+        db, dc = lg.lg_query_domains(field, pts, nrm, poses)
     torch.cuda.synchronize()
     sel = np.arange(w.poses.shape[0]) if poses_idx is None else poses_idx
     gb = db[torch.from_numpy(sel).cuda().long()].cpu().numpy().view(np.uint32)
@@ -209,6 +212,59 @@ def test_query_c3_full_shape_sampled_poses():
     ref = oracle.build_field(w.hand, w.field, flags=False)
     sel = np.random.default_rng(2).choice(w.poses.shape[0], size=12, replace=False)
     _query_check(w, ref["bits"], poses_idx=np.sort(sel))
+
+
+# ---------------------------------------------------------------------------
+# bounded query: chunk bounding spheres skip (chunk, finger) pairs out of reach;
+# the outputs must be those of the plain query, bit for bit
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,n_points,morton", [("c1", None, False), ("c1", 1, False), ("c1", 65, True),
+                                                  ("c1", 2047, True), ("c2", None, True), ("c3", 8192, False),
+                                                  ("c3", 8192, True)])
+def test_query_bounded_equals_plain(name, n_points, morton):
+    lg = lgmod()
+    kw = {"samples": 2048} if name != "c1" else {}
+    w = synth.workload(name, n_points=n_points, n_poses=512, with_sdf=False, **kw)
+    field = lg.lg_build_field(w.hand, w.field, keep_witness=False)
+    order = lg.lg_morton_order(w.obj.pts) if morton else np.arange(w.obj.n)
+    pts, nrm = soa(w.obj.pts[order]), soa(w.obj.nrm[order])
+    poses = dev(w.poses)
+    b = lg.lg_chunk_bounds(pts)
+    d0, c0 = lg.lg_query_domains(field, pts, nrm, poses)
+    d1, c1 = lg.lg_query_domains_bounded(field, pts, nrm, poses, b)
+    torch.cuda.synchronize()
+    assert torch.equal(d0, d1) and torch.equal(c0, c1)
+    assert int(c0.sum()) > 0
+    # every point lies in its chunk's sphere
+    bb = b.cpu().numpy().astype(np.float64)
+    p = w.obj.pts[order].astype(np.float64)
+    ch = np.arange(len(p)) // 64
+    assert (np.linalg.norm(p - bb[ch, :3], axis=1) <= bb[ch, 3]).all()
+
+
+def test_query_bounded_against_the_oracle():
+    w = synth.workload("c3", samples=4096, n_points=16384, n_poses=256, with_sdf=False)
+    ref = oracle.build_field(w.hand, w.field, flags=False)
+    sel = np.random.default_rng(5).choice(w.poses.shape[0], size=16, replace=False)
+    _query_check(w, ref["bits"], poses_idx=np.sort(sel), bounded=True)
+
+
+def test_query_bounded_far_poses_and_errors():
+    lg = lgmod()
+    w = synth.workload("c1", n_poses=8)
+    field = lg.lg_build_field(w.hand, w.field, keep_witness=False)
+    pts, nrm = soa(w.obj.pts), soa(w.obj.nrm)
+    b = lg.lg_chunk_bounds(pts)
+    far = w.poses.copy().reshape(-1, 3, 4)
+    far[:, :, 3] += 5.0
+    db, dc = lg.lg_query_domains_bounded(field, pts, nrm, dev(far.reshape(-1, 12)), b)
+    torch.cuda.synchronize()
+    assert int(dc.sum()) == 0 and int(db.abs().sum()) == 0
+    L = lg.lib()
+    assert L.lg_query_domains_bounded(field.handle, lg._ptr(pts), lg._ptr(nrm), w.obj.n, lg._ptr(dev(w.poses)), 8,
+                                      None, lg._ptr(db), lg._ptr(dc), None) == lg.LG_EINVAL
+    assert L.lg_query_domains_bounded(field.handle, lg._ptr(pts), lg._ptr(nrm), w.obj.n, lg._ptr(dev(w.poses)), 8,
+                                      b.data_ptr() + 4, lg._ptr(db), lg._ptr(dc), None) == lg.LG_EINVAL
 
 
 # ---------------------------------------------------------------------------
