@@ -26,6 +26,13 @@ constexpr int kQueryThreads = 256;
 constexpr int kQueryWaves = kQueryThreads / 64;
 constexpr float kCullMargin = 1e-3f;  // voxels added to a chunk's radius (float rounding is ~1e-4)
 
+// the LLVM writelane intrinsic: lane `lane` (uniform) of v replaced by the uniform x
+extern "C" __device__ int lg_writelane(int x, int lane, int v) __asm("llvm.amdgcn.writelane");
+__device__ inline uint32_t write_lane(uint32_t v, uint32_t x, int lane)
+{
+    return (uint32_t)lg_writelane((int)x, lane, (int)v);
+}
+
 // Bounding sphere (centre of the box, largest distance) of each chunk of 64
 // consecutive points; one wave per chunk, radius padded for rounding.
 __global__ void __launch_bounds__(256)
@@ -66,7 +73,9 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
     for (int i = threadIdx.x; i < 6 * kLutRes * kLutRes; i += blockDim.x) lut[i] = H.bin_lut[i];
     if (threadIdx.x < H.F) aff[threadIdx.x] = finger_affine(H, pose, threadIdx.x);
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index is uniform: in a scalar register, the block and chunk
+    // bookkeeping (and the skip tests) stay on the scalar unit
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int F = H.F, G = H.G, B = H.B;
     const int64_t G3W = (int64_t)G * G * G * W;
     const int NW = (N + 31) >> 5, nchunks = (N + 63) >> 6;
@@ -162,8 +171,9 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
                 if (skip[f] & cbit) continue;  // the ballot would be 0
                 const bool hit = (word[f] >> (b & 31)) & 1u;
                 const unsigned long long m = __ballot(hit);
-                c[f] += (uint32_t)__popcll(m);
-                acc[f] = lane == j2 ? (uint32_t)m : lane == j2 + 1 ? (uint32_t)(m >> 32) : acc[f];
+                // the chunk's two ballot halves into lanes j2, j2 + 1 (j2 is uniform)
+                acc[f] = write_lane(acc[f], (uint32_t)m, j2);
+                acc[f] = write_lane(acc[f], (uint32_t)(m >> 32), j2 + 1);
             }
         }
         const int wi = blk * 64 + lane;
@@ -172,7 +182,13 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
             for (int f = 0; f < FM; ++f)
                 if (f < F) dom_bits[((int64_t)g * F + f) * NW + wi] = acc[f];
         }
+        // counts per lane from the block's words (bits past N are 0)
+#pragma unroll
+        for (int f = 0; f < FM; ++f) c[f] += (uint32_t)__popc(acc[f]);
     }
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+        for (int off = 32; off > 0; off >>= 1) c[f] += __shfl_xor(c[f], off, 64);
     if (lane == 0) {
 #pragma unroll
         for (int f = 0; f < FM; ++f)
