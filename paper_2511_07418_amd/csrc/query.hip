@@ -141,13 +141,15 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
             const int i = chunk * 64 + lane;
             const bool valid = i < N;
             float px = 0.f, py = 0.f, pz = 0.f, nx = 0.f, ny = 0.f, nz = 1.f;
-            if (valid) {
-                px = pts[i];
-                py = pts[N + i];
-                pz = pts[2 * N + i];
-                nx = nrm[i];
-                ny = nrm[N + i];
-                nz = nrm[2 * N + i];
+            if (valid) {  // 32-bit byte offsets from uniform bases (SoA rows of 4 N bytes)
+                const char *pb = reinterpret_cast<const char *>(pts), *nb = reinterpret_cast<const char *>(nrm);
+                const uint32_t o0 = (uint32_t)i << 2, o1 = (uint32_t)(N + i) << 2, o2 = (uint32_t)(2 * N + i) << 2;
+                px = *reinterpret_cast<const float *>(pb + o0);
+                py = *reinterpret_cast<const float *>(pb + o1);
+                pz = *reinterpret_cast<const float *>(pb + o2);
+                nx = *reinterpret_cast<const float *>(nb + o0);
+                ny = *reinterpret_cast<const float *>(nb + o1);
+                nz = *reinterpret_cast<const float *>(nb + o2);
             }
             float qx, qy, qz;
             query_dir(P, nx, ny, nz, qx, qy, qz);
@@ -159,9 +161,19 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
             for (int f = 0; f < FM; ++f) {
                 word[f] = 0;
                 if (f < F && !(skip[f] & cbit)) {
-                    const int v = window_voxel(aff[f], G, px, py, pz);
-                    const uint32_t *tab = merged + f * G3W;  // uniform base, 32-bit lane offsets
-                    if (valid && v >= 0) word[f] = tab[(uint32_t)v * W + (uint32_t)(b >> 5)];
+                    // window_voxel's arithmetic, with only the load predicated
+                    const Affine &a = aff[f];
+                    const float ux = fmaf(a.m[0], px, fmaf(a.m[1], py, fmaf(a.m[2], pz, a.m[3])));
+                    const float uy = fmaf(a.m[4], px, fmaf(a.m[5], py, fmaf(a.m[6], pz, a.m[7])));
+                    const float uz = fmaf(a.m[8], px, fmaf(a.m[9], py, fmaf(a.m[10], pz, a.m[11])));
+                    const unsigned ix = (unsigned)((int)ux - G), iy = (unsigned)((int)uy - G),
+                                   iz = (unsigned)((int)uz - G);
+                    const bool in = valid & (max(ix, max(iy, iz)) < (unsigned)G);
+                    // one uniform base and a 32-bit byte offset per lane (the tables
+                    // are far below 4 GiB): the load takes the scalar-base form
+                    const uint32_t v = __umul24(__umul24(iz, G) + iy, G) + ix;
+                    const uint32_t boff = ((uint32_t)f * (uint32_t)G3W + v * W + (uint32_t)(b >> 5)) << 2;
+                    if (in) word[f] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(merged) + boff);
                 }
             }
             const int j2 = 2 * (chunk - blk * 32);
