@@ -1,9 +1,10 @@
 // Kinematics optimisation (Sec. 5.5, Eq. 7-8, Phase I and II) and the
 // penetration part of the validity criterion (Sec. 3.2), fused in one kernel.
 //
-// Lane layout: 8 lanes per accepted set, lane f realises the contact of
-// finger f (lanes f >= F idle), so one wave covers 8 sets and the set-level
-// reductions (max depth, worst contact error / angle) are 3 xor-shuffles.
+// Lane layout: F lanes per accepted set, lane f realises finger f, so a wave
+// covers 64 / F sets (the 64 mod F lanes left over idle) and the set-level
+// reductions (max depth, worst contact error / angle) read the set's lanes
+// with shuffles.
 // Everything per lane lives in registers; the kernel is templated on the
 // largest finger DOF so the small dense solves unroll.
 #include <math.h>
@@ -196,12 +197,15 @@ __device__ __forceinline__ void realize_sets(float *cb, float (*caps)[DM][6], LG
     for (int i = threadIdx.x; i < 3 * H.B; i += blockDim.x) cb[i] = H.bin_c[i];
     __syncthreads();
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int f = (int)(gt & 7);
-    const int tid = threadIdx.x, base = tid & ~7;
+    const int spw = 64 / H.F;                    // sets per wave
+    const int lane = threadIdx.x & 63, slot = lane / H.F;
+    const int f = lane - slot * H.F;             // this lane's finger
+    const int tid = threadIdx.x, base = tid - f;  // the set's first lane in the block
     const int64_t nacc = min((int64_t)*n_acc_dev, (int64_t)max_acc);
-    const int64_t stride = ((int64_t)gridDim.x * blockDim.x) >> 3;
-    // grid-stride over accepted sets; the 8 lanes of a set move together
-    for (int64_t a = gt >> 3; a < nacc; a += stride) {
+    const int64_t stride = (((int64_t)gridDim.x * blockDim.x) >> 6) * spw;
+    // grid-stride over accepted sets; the F lanes of a set move together, the
+    // lanes past spw * F do nothing
+    for (int64_t a = slot < spw ? (gt >> 6) * spw + slot : nacc; a < nacc; a += stride) {
         const int64_t id = acc_list[a];
         if (id < 0 || id >= n_sets) {  // not a set id: no reads through it (uniform over the set's lanes)
             if (f < H.F)
@@ -451,7 +455,7 @@ __device__ __forceinline__ void realize_sets(float *cb, float (*caps)[DM][6], LG
             amax = INFINITY;
         }
         // hand self-collision: this finger's links against those of the higher
-        // fingers of the set (the 8 lanes of a set are in one wave)
+        // fingers of the set (the F lanes of a set are in one wave)
         if (ik.self_collision) {
             __builtin_amdgcn_wave_barrier();
             __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -471,12 +475,18 @@ __device__ __forceinline__ void realize_sets(float *cb, float (*caps)[DM][6], LG
             __builtin_amdgcn_wave_barrier();
             __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
-        // set-level reductions over the 8 lanes of the set
-#pragma unroll
-        for (int off = 1; off < 8; off <<= 1) {
-            dep = fmaxf(dep, __shfl_xor(dep, off, 8));
-            emax = fmaxf(emax, __shfl_xor(emax, off, 8));
-            amax = fmaxf(amax, __shfl_xor(amax, off, 8));
+        // set-level reductions over the F lanes of the set (all active: same set)
+        {
+            const int first_lane = lane - f;
+            float d2 = dep, e2 = emax, a2 = amax;
+            for (int j = 0; j < H.F; ++j) {
+                d2 = fmaxf(d2, __shfl(dep, first_lane + j, 64));
+                e2 = fmaxf(e2, __shfl(emax, first_lane + j, 64));
+                a2 = fmaxf(a2, __shfl(amax, first_lane + j, 64));
+            }
+            dep = d2;
+            emax = e2;
+            amax = a2;
         }
         if (f == 0) {
             depth_out[a] = dep;
@@ -535,7 +545,8 @@ extern "C" lg_status lg_realize(const lg_field *field, const lg_sdf *sdf, const 
     int dev = 0, n_cu = 0;
     LG_HIP(hipGetDevice(&dev));
     LG_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int64_t threads = std::min<int64_t>((int64_t)max_acc * 8, (int64_t)n_cu * 16 * kRealizeThreads);
+    const int64_t spw = 64 / H.F;  // sets per wave
+    const int64_t threads = std::min<int64_t>((max_acc + spw - 1) / spw * 64, (int64_t)n_cu * 16 * kRealizeThreads);
     const dim3 grid((unsigned)std::max<int64_t>(1, (threads + kRealizeThreads - 1) / kRealizeThreads));
     const int32_t *wit = field->has_witness ? field->d_wit : nullptr;
 #define LG_REALIZE(KERNEL)                                                                                      \
