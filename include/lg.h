@@ -163,11 +163,13 @@ lg_status lg_query_domains(const lg_field *field, const float *pts, const float 
  * c_b . (-R n_i) >= cos_hit (cos_hit in [-1, 1]; the paper's test over the
  * quantised normals of the leaf).  Same buffers, layout and errors as
  * lg_query_domains; the domains contain lg_query_domains' once the cone is
- * wider than the bins' covering radius.
+ * wider than the bins' covering radius.  bounds: NULL or the chunk bounds of
+ * lg_chunk_bounds (below) for the same points, which skip (chunk, finger)
+ * pairs out of a window's reach without changing the output.
  */
 lg_status lg_query_domains_cone(const lg_field *field, const float *pts, const float *nrm, int32_t n_points,
-                                const float *poses, int32_t n_poses, float cos_hit, uint32_t *dom_bits,
-                                uint32_t *dom_count, void *stream);
+                                const float *poses, int32_t n_poses, const float *bounds, float cos_hit,
+                                uint32_t *dom_bits, uint32_t *dom_count, void *stream);
 
 /*
  * lg_chunk_bounds -- bounding spheres of the object's chunks of 64 consecutive

@@ -57,6 +57,48 @@ k_chunk_bounds(const float *__restrict__ pts, int N, float4 *__restrict__ bounds
     if (lane == 0) bounds[chunk] = make_float4(cx, cy, cz, fmaf(r, 1e-5f, r + 1e-7f));
 }
 
+// skip[f] bit j: chunk blk * 32 + j cannot reach finger f's window (all 0
+// without bounds); returns the chunks that reach no window.  Lane l tests
+// chunk l % 32 against finger f0 + l / 32, two fingers per ballot: the distance
+// from the sphere's centre (biased voxel coordinates) to the window box
+// [G, 2G]^3 against its radius.
+template <int FM>
+__device__ inline uint32_t block_skip(const float4 *__restrict__ bounds, const Affine *aff, int F, int G, float inv_h,
+                                      int blk, int nchunks, int lane, uint32_t (&skip)[FM])
+{
+#pragma unroll
+    for (int f = 0; f < FM; ++f) skip[f] = 0u;
+    if (!bounds) return 0u;
+#pragma unroll
+    for (int f0 = 0; f0 < FM; f0 += 2) {
+        if (f0 >= F) break;
+        const int f = min(f0 + (lane >> 5), F - 1);
+        const int ch = blk * 32 + (lane & 31);
+        bool out = true;
+        if (ch < nchunks) {
+            const float4 sb = bounds[ch];
+            const Affine &a = aff[f];
+            const float ux = fmaf(a.m[0], sb.x, fmaf(a.m[1], sb.y, fmaf(a.m[2], sb.z, a.m[3])));
+            const float uy = fmaf(a.m[4], sb.x, fmaf(a.m[5], sb.y, fmaf(a.m[6], sb.z, a.m[7])));
+            const float uz = fmaf(a.m[8], sb.x, fmaf(a.m[9], sb.y, fmaf(a.m[10], sb.z, a.m[11])));
+            const float gl = (float)G, gh = (float)(2 * G);
+            const float dx = fmaxf(fmaxf(gl - ux, ux - gh), 0.f);
+            const float dy = fmaxf(fmaxf(gl - uy, uy - gh), 0.f);
+            const float dz = fmaxf(fmaxf(gl - uz, uz - gh), 0.f);
+            const float rv = fmaf(sb.w, inv_h, kCullMargin);
+            out = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) > rv * rv;
+        }
+        const unsigned long long m = __ballot(out);
+        skip[f0] = (uint32_t)m;
+        if (f0 + 1 < FM) skip[f0 + 1] = (uint32_t)(m >> 32);
+    }
+    uint32_t all = ~0u;
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+        if (f < F) all &= skip[f];
+    return all;
+}
+
 template <int W, int FM>
 __global__ void __launch_bounds__(kQueryThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict__ pts,
@@ -95,43 +137,8 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
 #pragma unroll
         for (int f = 0; f < FM; ++f) acc[f] = 0;
         const int c_end = min(nchunks, (blk + 1) * 32);
-        // skip[f] bit j: chunk blk * 32 + j cannot reach finger f's window.
-        // Lane l tests chunk l % 32 against finger f0 + l / 32, two fingers per
-        // ballot: the distance from the sphere's centre (biased voxel
-        // coordinates) to the window box [G, 2G]^3 against its radius.
         uint32_t skip[FM];
-#pragma unroll
-        for (int f = 0; f < FM; ++f) skip[f] = 0u;
-        uint32_t skip_all = 0u;
-        if (bounds) {
-#pragma unroll
-            for (int f0 = 0; f0 < FM; f0 += 2) {
-                if (f0 >= F) break;
-                const int f = min(f0 + (lane >> 5), F - 1);
-                const int ch = blk * 32 + (lane & 31);
-                bool out = true;
-                if (ch < nchunks) {
-                    const float4 sb = bounds[ch];
-                    const Affine &a = aff[f];
-                    const float ux = fmaf(a.m[0], sb.x, fmaf(a.m[1], sb.y, fmaf(a.m[2], sb.z, a.m[3])));
-                    const float uy = fmaf(a.m[4], sb.x, fmaf(a.m[5], sb.y, fmaf(a.m[6], sb.z, a.m[7])));
-                    const float uz = fmaf(a.m[8], sb.x, fmaf(a.m[9], sb.y, fmaf(a.m[10], sb.z, a.m[11])));
-                    const float gl = (float)G, gh = (float)(2 * G);
-                    const float dx = fmaxf(fmaxf(gl - ux, ux - gh), 0.f);
-                    const float dy = fmaxf(fmaxf(gl - uy, uy - gh), 0.f);
-                    const float dz = fmaxf(fmaxf(gl - uz, uz - gh), 0.f);
-                    const float rv = fmaf(sb.w, H.inv_h, kCullMargin);
-                    out = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) > rv * rv;
-                }
-                const unsigned long long m = __ballot(out);
-                skip[f0] = (uint32_t)m;
-                if (f0 + 1 < FM) skip[f0 + 1] = (uint32_t)(m >> 32);
-            }
-            skip_all = ~0u;
-#pragma unroll
-            for (int f = 0; f < FM; ++f)
-                if (f < F) skip_all &= skip[f];
-        }
+        const uint32_t skip_all = block_skip<FM>(bounds, aff, F, G, H.inv_h, blk, nchunks, lane, skip);
         for (int chunk = blk * 32; chunk < c_end; ++chunk) {
             const uint32_t cbit = 1u << (chunk - blk * 32);
             if (skip_all & cbit) continue;  // no window in reach: its ballot words stay 0
@@ -221,8 +228,8 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
 template <int W, int FM>
 __global__ void __launch_bounds__(kQueryThreads)
 k_query_cone(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict__ pts,
-             const float *__restrict__ nrm, int N, const float *__restrict__ poses, float cos_hit,
-             uint32_t *__restrict__ dom_bits, uint32_t *__restrict__ dom_count)
+             const float *__restrict__ nrm, int N, const float *__restrict__ poses, const float4 *__restrict__ bounds,
+             float cos_hit, uint32_t *__restrict__ dom_bits, uint32_t *__restrict__ dom_count)
 {
     __shared__ float cb[3 * kMaxBins];
     __shared__ Affine aff[FM];
@@ -232,8 +239,9 @@ k_query_cone(DevHand H, const uint32_t *__restrict__ merged, const float *__rest
     for (int i = threadIdx.x; i < 3 * H.B; i += blockDim.x) cb[i] = H.bin_c[i];
     if (threadIdx.x < H.F) aff[threadIdx.x] = finger_affine(H, pose, threadIdx.x);
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int F = H.F, G = H.G;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int F = H.F, G = H.G, B = H.B;
+    const float sin_hit = sqrtf(fmaxf(0.f, fmaf(-cos_hit, cos_hit, 1.f)));
     const int64_t G3W = (int64_t)G * G * G * W;
     const int NW = (N + 31) >> 5, nchunks = (N + 63) >> 6;
     float P[12];
@@ -248,7 +256,11 @@ k_query_cone(DevHand H, const uint32_t *__restrict__ merged, const float *__rest
 #pragma unroll
         for (int f = 0; f < FM; ++f) acc[f] = 0;
         const int c_end = min(nchunks, (blk + 1) * 32);
+        uint32_t skip[FM];
+        const uint32_t skip_all = block_skip<FM>(bounds, aff, F, G, H.inv_h, blk, nchunks, lane, skip);
         for (int chunk = blk * 32; chunk < c_end; ++chunk) {
+            const uint32_t cbit = 1u << (chunk - blk * 32);
+            if (skip_all & cbit) continue;  // no window in reach: its ballot words stay 0
             asm volatile("" ::: "memory");
             const int i = chunk * 64 + lane;
             const bool valid = i < N;
@@ -263,11 +275,22 @@ k_query_cone(DevHand H, const uint32_t *__restrict__ merged, const float *__rest
             }
             float qx, qy, qz;
             query_dir(P, nx, ny, nz, qx, qy, qz);
+            // bins that can lie within the cone: the polar band |phi_b - phi_q| <=
+            // theta_hit, a contiguous index range of the Fibonacci lattice (z_b =
+            // 1 - (2b + 1) / B decreases with b), widened by one bin for rounding
+            const float sq = sqrtf(fmaxf(0.f, fmaf(-qz, qz, 1.f)));
+            const float zhi = qz >= cos_hit ? 1.f : fmaf(qz, cos_hit, sq * sin_hit);
+            const float zlo = qz <= -cos_hit ? -1.f : fmaf(qz, cos_hit, -sq * sin_hit);
+            const int blo = max(0, (int)floorf(0.5f * fmaf((float)B, 1.f - zhi, -1.f)) - 1);
+            const int bhi = min(B - 1, (int)ceilf(0.5f * fmaf((float)B, 1.f - zlo, -1.f)) + 1);
+            const unsigned long long band = blo > bhi ? 0ull
+                                                      : ((bhi - blo == 63 ? ~0ull : ((1ull << (bhi - blo + 1)) - 1ull))
+                                                         << blo);
             unsigned long long ent[FM];
 #pragma unroll
             for (int f = 0; f < FM; ++f) {
                 ent[f] = 0ull;
-                if (f < F) {
+                if (f < F && !(skip[f] & cbit)) {
                     const int v = window_voxel(aff[f], G, px, py, pz);
                     const uint32_t *tab = merged + f * G3W;
                     if (valid && v >= 0) {
@@ -280,8 +303,9 @@ k_query_cone(DevHand H, const uint32_t *__restrict__ merged, const float *__rest
 #pragma unroll
             for (int f = 0; f < FM; ++f) {
                 if (f >= F) break;
+                if (skip[f] & cbit) continue;  // the ballot would be 0
                 bool hit = false;
-                unsigned long long m = ent[f];
+                unsigned long long m = ent[f] & band;
                 while (m) {
                     const int b = __ffsll((long long)m) - 1;
                     m &= m - 1ull;
@@ -291,8 +315,8 @@ k_query_cone(DevHand H, const uint32_t *__restrict__ merged, const float *__rest
                     }
                 }
                 const unsigned long long bm = __ballot(hit);
-                c[f] += (uint32_t)__popcll(bm);
-                acc[f] = lane == j2 ? (uint32_t)bm : lane == j2 + 1 ? (uint32_t)(bm >> 32) : acc[f];
+                acc[f] = write_lane(acc[f], (uint32_t)bm, j2);
+                acc[f] = write_lane(acc[f], (uint32_t)(bm >> 32), j2 + 1);
             }
         }
         const int wi = blk * 64 + lane;
@@ -301,7 +325,12 @@ k_query_cone(DevHand H, const uint32_t *__restrict__ merged, const float *__rest
             for (int f = 0; f < FM; ++f)
                 if (f < F) dom_bits[((int64_t)g * F + f) * NW + wi] = acc[f];
         }
+#pragma unroll
+        for (int f = 0; f < FM; ++f) c[f] += (uint32_t)__popc(acc[f]);
     }
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+        for (int off = 32; off > 0; off >>= 1) c[f] += __shfl_xor(c[f], off, 64);
     if (lane == 0) {
 #pragma unroll
         for (int f = 0; f < FM; ++f)
@@ -409,10 +438,11 @@ extern "C" lg_status lg_morton_order(const float *pts_host, int32_t n_points, in
 }
 
 extern "C" lg_status lg_query_domains_cone(const lg_field *field, const float *pts, const float *nrm, int32_t n_points,
-                                           const float *poses, int32_t n_poses, float cos_hit, uint32_t *dom_bits,
-                                           uint32_t *dom_count, void *stream)
+                                           const float *poses, int32_t n_poses, const float *bounds, float cos_hit,
+                                           uint32_t *dom_bits, uint32_t *dom_count, void *stream)
 {
     if (!field) return fail(LG_EINVAL, "null field");
+    if (reinterpret_cast<uintptr_t>(bounds) % 16 != 0) return fail(LG_EINVAL, "chunk bounds must be 16-byte aligned");
     if (n_points < 0 || n_poses < 0) return fail(LG_EINVAL, "negative size");
     if (!(cos_hit >= -1.0f && cos_hit <= 1.0f)) return fail(LG_EINVAL, "cos_hit outside [-1, 1]");
     if (n_poses == 0) return LG_OK;
@@ -422,7 +452,7 @@ extern "C" lg_status lg_query_domains_cone(const lg_field *field, const float *p
     const DevHand &H = field->dh;
 #define LG_QCONE(W, FM)                                                                                        \
     hipLaunchKernelGGL((k_query_cone<W, FM>), dim3(n_poses), dim3(kQueryThreads), 0, s, H, field->d_merged, pts, \
-                       nrm, n_points, poses, cos_hit, dom_bits, dom_count)
+                       nrm, n_points, poses, reinterpret_cast<const float4 *>(bounds), cos_hit, dom_bits, dom_count)
     if (H.W == 1) {
         if (H.F <= 3) LG_QCONE(1, 3); else if (H.F <= 4) LG_QCONE(1, 4); else if (H.F <= 5) LG_QCONE(1, 5); else LG_QCONE(1, 8);
     } else {

@@ -116,7 +116,7 @@ def _load():
     L.lg_field_info.argtypes = [vp, vp]
     L.lg_field_release.argtypes = [vp]
     L.lg_query_domains.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp]
-    L.lg_query_domains_cone.argtypes = [vp, vp, vp, i32, vp, i32, C.c_float, vp, vp, vp]
+    L.lg_query_domains_cone.argtypes = [vp, vp, vp, i32, vp, i32, vp, C.c_float, vp, vp, vp]
     L.lg_query_domains_bounded.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp, vp]
     L.lg_chunk_bounds.argtypes = [vp, i32, vp, vp]
     L.lg_morton_order.argtypes = [vp, i32, vp]
@@ -155,7 +155,9 @@ def _load():
     for fn in ("lg_build_field", "lg_field_import", "lg_field_export", "lg_field_info",
                "lg_field_release", "lg_query_domains", "lg_query_domains_cone", "lg_search", "lg_realize", "lg_serve_create",
                "lg_serve_submit", "lg_serve_poll", "lg_serve_wait", "lg_serve_cancel", "lg_serve_stats",
-               "lg_serve_destroy", "lg_place_exhaustive", "lg_prop_create", "lg_prop_release", "lg_prop_get_params",
+               "lg_serve_destroy", "lg_place_exhaustive", "lg_place_palm", "lg_concave_filter", "lg_gather_points",
+               "lg_query_domains_bounded", "lg_chunk_bounds", "lg_morton_order",
+               "lg_prop_create", "lg_prop_release", "lg_prop_get_params",
                "lg_prop_set_params", "lg_prop_forward", "lg_prop_backward", "lg_prop_adam",
                "lg_prop_train_step", "lg_prop_sample_mixture", "lg_prop_sample"):
         getattr(L, fn).restype = i32
@@ -310,8 +312,8 @@ def lg_query_domains(field: Field, pts: torch.Tensor, nrm: torch.Tensor, poses: 
 
 
 def lg_query_domains_cone(field: Field, pts, nrm, poses, cos_hit: float, dom_bits=None, dom_count=None,
-                          stream=None):
-    """Cone (theta_hit) query; same shapes as lg_query_domains."""
+                          stream=None, bounds=None):
+    """Cone (theta_hit) query; same shapes as lg_query_domains (``bounds``: optional chunk bounds)."""
     N, P, F = int(pts.shape[1]), int(poses.shape[0]), field.n_fingers
     NW = (N + 31) // 32
     dev = pts.device
@@ -319,8 +321,9 @@ def lg_query_domains_cone(field: Field, pts, nrm, poses, cos_hit: float, dom_bit
         dom_bits = torch.empty((P, F, NW), dtype=torch.int32, device=dev)
     if dom_count is None:
         dom_count = torch.empty((P, F), dtype=torch.int32, device=dev)
-    _check(_lib.lg_query_domains_cone(field.handle, _ptr(pts), _ptr(nrm), N, _ptr(poses), P, float(cos_hit),
-                                      _ptr(dom_bits), _ptr(dom_count), _stream(stream)), "lg_query_domains_cone")
+    _check(_lib.lg_query_domains_cone(field.handle, _ptr(pts), _ptr(nrm), N, _ptr(poses), P, _ptr(bounds),
+                                      float(cos_hit), _ptr(dom_bits), _ptr(dom_count), _stream(stream)),
+           "lg_query_domains_cone")
     return dom_bits, dom_count
 
 

@@ -56,7 +56,7 @@ class Pipeline:
                                         self.dom_count, stream=stream)
         else:
             lg.lg_query_domains_cone(self.field, self.pts, self.nrm, self.poses, self.cos_hit, self.dom_bits,
-                                     self.dom_count, stream=stream)
+                                     self.dom_count, stream=stream, bounds=self.bounds)
 
     def search(self, stream=None, request_id=None):
         """Draws + verdicts on the current domains; another request_id resamples

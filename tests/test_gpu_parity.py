@@ -504,6 +504,11 @@ def test_query_cone(name, deg):
     assert n_flag <= max(2, 1e-3 * len(w.poses) * w.hand.n_fingers * w.obj.n)
     # counts agree up to the flagged points
     assert np.abs(dc.cpu().numpy().astype(np.int64) - Q["dom_count"].astype(np.int64)).sum() <= n_flag
+    # with chunk bounds: the same domains
+    P_, N_ = soa(w.obj.pts), soa(w.obj.nrm)
+    db2, dc2 = lg.lg_query_domains_cone(field, P_, N_, dev(w.poses), cos_hit, bounds=lg.lg_chunk_bounds(P_))
+    torch.cuda.synchronize()
+    assert torch.equal(db2, db) and torch.equal(dc2, dc)
     # with a cone wider than the bins' covering radius it contains the nearest-bin domain
     nb, _ = lg.lg_query_domains(field, soa(w.obj.pts), soa(w.obj.nrm), dev(w.poses))
     if deg >= 30.0:
