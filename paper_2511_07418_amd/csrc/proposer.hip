@@ -12,13 +12,15 @@
 // SO(3) by Gram-Schmidt (the 6-D representation of Zhou et al. 2019).
 //
 // Work decomposition:
-//  * k_encode: 128 points per workgroup (4 waves x 32 points); layer 1 is one
-//    32x32x16 MFMA per 32 output channels (K = 6 padded to 16), its ReLU
-//    output goes to LDS as BF16; layer 2 reads W2 (BF16, 68 KiB) from LDS and
-//    issues 8 x 8 MFMAs per wave; the max-pool folds bias, ReLU, the max over
-//    the wave's rows and the argmax into one 64-bit key per channel (value
-//    bits above the inverted point index) merged with atomicMax, so equal
-//    maxima resolve to the lowest point index.
+//  * k_encode: 8 waves x 32 points per tile, 8 tiles per workgroup (W2 is
+//    staged in LDS once for all of them); layer 1 is one 32x32x16 MFMA per 32
+//    output channels (K = 6 padded to 16), its ReLU output goes to LDS as
+//    BF16; layer 2 reads W2 (BF16, 68 KiB) from LDS and issues 8 x 8 MFMAs per
+//    wave and tile; the max-pool folds bias, ReLU, the max over the rows and
+//    the argmax into one 64-bit key per channel (value bits above the inverted
+//    point index), kept in registers over the tiles and merged with one
+//    atomicMax per channel and workgroup, so equal maxima resolve to the
+//    lowest point index.
 //  * the head and every backward product are small GEMMs (rows = objects)
 //    run by k_gemm, one wave per 32x32 output tile;
 //  * the encoder backward is sparse: the max-pool routes each channel's
@@ -142,8 +144,16 @@ __global__ void k_fill_u64(unsigned long long *__restrict__ p, int64_t n)
 }
 
 // ---- encoder -----------------------------------------------------------------
-constexpr int kEncWaves = 4;
-constexpr int kEncRows = 32 * kEncWaves;  // points per workgroup
+#ifndef LG_ENC_WAVES
+#define LG_ENC_WAVES 8
+#endif
+constexpr int kEncWaves = LG_ENC_WAVES;
+constexpr int kEncThreads = 64 * kEncWaves;
+constexpr int kEncRows = 32 * kEncWaves;  // points per tile
+#ifndef LG_ENC_TILES
+#define LG_ENC_TILES 8
+#endif
+constexpr int kEncTiles = LG_ENC_TILES;   // tiles per workgroup: W2 is staged once for all of them
 constexpr int kLd = kH1 + 8;              // padded LDS row of H1 and W2^T (BF16 elements)
 
 __device__ inline u16x8_t input_row(const float *__restrict__ xp)
@@ -158,8 +168,8 @@ __device__ inline u16x8_t input_row(const float *__restrict__ xp)
     return a;
 }
 
-// grid (ceil(Np / 128), B), 256 threads
-__global__ __launch_bounds__(256) void k_encode(const float *__restrict__ x, int Np,
+// grid (ceil(Np / (kEncRows kEncTiles)), B), kEncThreads threads
+__global__ __launch_bounds__(kEncThreads) void k_encode(const float *__restrict__ x, int Np,
                                                 const uint16_t *__restrict__ T,
                                                 const float *__restrict__ P,
                                                 unsigned long long *__restrict__ keys)
@@ -169,59 +179,73 @@ __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ x, int
     __shared__ float sB1[kH1], sB2[kH2];
     const int b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 31, half = lane >> 5;
-    for (int i = tid; i < kH2 * (kH1 / 8); i += 256) {
+    for (int i = tid; i < kH2 * (kH1 / 8); i += kEncThreads) {
         const int n = i / (kH1 / 8), k8 = i % (kH1 / 8);
         *(u16x8_t *)&sW2[n * kLd + 8 * k8] = *(const u16x8_t *)&T[kT2 + (int64_t)n * kH1 + 8 * k8];
     }
-    for (int i = tid; i < kH1; i += 256) sB1[i] = P[kB1 + i];
-    for (int i = tid; i < kH2; i += 256) sB2[i] = P[kB2 + i];
+    for (int i = tid; i < kH1; i += kEncThreads) sB1[i] = P[kB1 + i];
+    for (int i = tid; i < kH2; i += kEncThreads) sB2[i] = P[kB2 + i];
     __syncthreads();
 
-    const int row0 = blockIdx.x * kEncRows + wave * 32;
-    const int pt = row0 + r;
-    u16x8_t xa = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (half == 0 && pt < Np) xa = input_row(x + ((int64_t)b * Np + pt) * kIn);
+    // running max-pool key per column block (lanes r < 32 own column 32 blk + r)
+    unsigned long long kmax[kH2 / 32];
+#pragma unroll
+    for (int blk = 0; blk < kH2 / 32; ++blk) kmax[blk] = 0ull;
     uint16_t *h1 = sH1 + wave * 32 * kLd;
+    for (int tile = 0; tile < kEncTiles; ++tile) {
+        const int tile0 = (blockIdx.x * kEncTiles + tile) * kEncRows;
+        if (tile0 >= Np) break;  // uniform over the workgroup
+        const int row0 = tile0 + wave * 32;
+        const int pt = row0 + r;
+        u16x8_t xa = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (half == 0 && pt < Np) xa = input_row(x + ((int64_t)b * Np + pt) * kIn);
 #pragma unroll
-    for (int blk = 0; blk < kH1 / 32; ++blk) {
-        const int col = 32 * blk + r;
-        const u16x8_t wb = *(const u16x8_t *)&T[kT1 + col * kInPad + 8 * half];
-        f32x16_t acc = {};
-        acc = mfma(xa, wb, acc);
-        const float bias = sB1[col];
+        for (int blk = 0; blk < kH1 / 32; ++blk) {
+            const int col = 32 * blk + r;
+            const u16x8_t wb = *(const u16x8_t *)&T[kT1 + col * kInPad + 8 * half];
+            f32x16_t acc = {};
+            acc = mfma(xa, wb, acc);
+            const float bias = sB1[col];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) h1[c_row(i, lane) * kLd + col] = bf16_bits(fmaxf(acc[i] + bias, 0.0f));
-    }
-    __syncthreads();
+            for (int i = 0; i < 16; ++i) h1[c_row(i, lane) * kLd + col] = bf16_bits(fmaxf(acc[i] + bias, 0.0f));
+        }
+        __syncthreads();
 
-    for (int blk = 0; blk < kH2 / 32; ++blk) {
-        const int col = 32 * blk + r;
-        f32x16_t acc = {};
 #pragma unroll
-        for (int kk = 0; kk < kH1 / 16; ++kk) {
-            const u16x8_t av = *(const u16x8_t *)&h1[r * kLd + 16 * kk + 8 * half];
-            const u16x8_t bv = *(const u16x8_t *)&sW2[col * kLd + 16 * kk + 8 * half];
-            acc = mfma(av, bv, acc);
-        }
-        const float bias = sB2[col];
-        float best = -1.0f;
-        int bi = 0;
+        for (int blk = 0; blk < kH2 / 32; ++blk) {
+            const int col = 32 * blk + r;
+            f32x16_t acc = {};
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {  // rows ascend with i: '>' keeps the lowest index
-            const int p = row0 + c_row(i, lane);
-            const float v = fmaxf(acc[i] + bias, 0.0f);
-            if (p < Np && v > best) {
-                best = v;
-                bi = p;
+            for (int kk = 0; kk < kH1 / 16; ++kk) {
+                const u16x8_t av = *(const u16x8_t *)&h1[r * kLd + 16 * kk + 8 * half];
+                const u16x8_t bv = *(const u16x8_t *)&sW2[col * kLd + 16 * kk + 8 * half];
+                acc = mfma(av, bv, acc);
             }
+            const float bias = sB2[col];
+            float best = -1.0f;
+            int bi = 0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {  // rows ascend with i: '>' keeps the lowest index
+                const int p = row0 + c_row(i, lane);
+                const float v = fmaxf(acc[i] + bias, 0.0f);
+                if (p < Np && v > best) {
+                    best = v;
+                    bi = p;
+                }
+            }
+            unsigned long long key = best < 0.0f ? 0ull
+                                                 : (((unsigned long long)__float_as_uint(best)) << 32) |
+                                                       (0xFFFFFFFFu - (uint32_t)bi);
+            const uint32_t lo = __shfl_xor((uint32_t)key, 32, 64), hi = __shfl_xor((uint32_t)(key >> 32), 32, 64);
+            const unsigned long long other = ((unsigned long long)hi << 32) | lo;
+            key = key > other ? key : other;
+            kmax[blk] = key > kmax[blk] ? key : kmax[blk];
         }
-        unsigned long long key =
-            best < 0.0f ? 0ull : (((unsigned long long)__float_as_uint(best)) << 32) | (0xFFFFFFFFu - (uint32_t)bi);
-        const uint32_t lo = __shfl_xor((uint32_t)key, 32, 64), hi = __shfl_xor((uint32_t)(key >> 32), 32, 64);
-        const unsigned long long other = ((unsigned long long)hi << 32) | lo;
-        key = key > other ? key : other;
-        if (half == 0 && key) atomicMax(&keys[(int64_t)b * kH2 + col], key);
+        __syncthreads();  // the next tile overwrites H1
     }
+#pragma unroll
+    for (int blk = 0; blk < kH2 / 32; ++blk)
+        if (half == 0 && kmax[blk]) atomicMax(&keys[(int64_t)b * kH2 + 32 * blk + r], kmax[blk]);
 }
 
 __global__ void k_pool_finish(const unsigned long long *__restrict__ keys, int n, float *__restrict__ feat,
@@ -598,7 +622,8 @@ lg_status forward(lg_prop *p, const float *x, int B, int Np, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fill_u64, dim3(blocks((int64_t)B * kH2, 256)), dim3(256), 0, s, p->keys,
                        (int64_t)B * kH2);
-    hipLaunchKernelGGL(k_encode, dim3(blocks(Np, kEncRows), B), dim3(256), 0, s, x, Np, p->T, p->P, p->keys);
+    hipLaunchKernelGGL(k_encode, dim3(blocks(Np, kEncRows * kEncTiles), B), dim3(kEncThreads), 0, s, x, Np, p->T,
+                       p->P, p->keys);
     hipLaunchKernelGGL(k_pool_finish, dim3(blocks((int64_t)B * kH2, 256)), dim3(256), 0, s, p->keys, B * kH2,
                        p->feat, p->arg);
     gemm<uint16_t, kEpiBiasRelu>(s, B, kHH, kH2, p->feat, kH2, 1, p->T + kTa, 1, kH2, p->P + kBa, nullptr, 0, p->ua,
