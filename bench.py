@@ -71,7 +71,8 @@ def parse():
     ap.add_argument("--placement", default="canonical", choices=["canonical", "exhaustive"],
                     help="palm poses: canonical (random pose above the palm) or exhaustive (an object point "
                          "on a random contact vector of the field)")
-    ap.add_argument("--mode", default="full", choices=["full", "query", "search", "serve", "proposer", "multipass"],
+    ap.add_argument("--mode", default="full",
+                    choices=["full", "query", "search", "serve", "proposer", "encoder", "multipass"],
                     help="query / search: only the field build and --steps launches of that stage "
                          "(query mode adds a 1 GiB device copy); for hardware-counter runs, no JSON")
     return ap.parse_args()
@@ -230,6 +231,29 @@ def _diversity(torch, pipe, ids) -> int:
     return int(torch.unique(torch.sort(sets, dim=1).values, dim=0).shape[0])
 
 
+def encoder_bench(torch, lg, X, seed: int = 0, reps: int = 10) -> dict:
+    """Forward pass of 512 objects x 2048 points (the rows of X repeated):
+    the encoder's dense BF16 MFMA work, then the pooled head.  The FLOP count
+    is the encoder's alone (the head adds 0.25 %)."""
+    big = lg.Proposer(max_batch=512, max_points=PROP_POINTS, max_targets=1, seed=seed)
+    xb = X[torch.arange(512, device="cuda") % X.shape[0]].contiguous()
+    for _ in range(3):
+        big.forward(xb)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        big.forward(xb)
+    ev[1].record()
+    torch.cuda.synchronize()
+    f_ms = ev[0].elapsed_time(ev[1]) / reps
+    flops = 2.0 * 512 * PROP_POINTS * (6 * 128 + 128 * 256)
+    big.release()
+    return {"objects": 512, "points": PROP_POINTS, "forward_ms": f_ms, "encoder_gflop": flops / 1e9,
+            "tflops": flops / (f_ms * 1e-3) / 1e12, "peak_tflops": 2500.0,
+            "frac": flops / (f_ms * 1e-3) / 1e12 / 2500.0}
+
+
 def proposer_bench(torch, lg, pool, n_train: int, n_eval: int, epochs: int, seed: int = 0) -> dict:
     """C5: train the proposer on the valid grasps of uniform search over
     n_train C2 objects, then compare learned and uniform proposals on n_eval
@@ -356,23 +380,7 @@ def proposer_bench(torch, lg, pool, n_train: int, n_eval: int, epochs: int, seed
                                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
     out["serving"]["valid_per_s_ratio"] = (out["serving"]["learned"]["valid_grasps_per_s"] /
                                            out["serving"]["uniform"]["valid_grasps_per_s"])
-    # encoder throughput: one forward of 512 objects x 2048 points (dense MFMA work)
-    big = lg.Proposer(max_batch=512, max_points=PROP_POINTS, max_targets=1, seed=seed)
-    xb = X[torch.arange(512, device="cuda") % X.shape[0]].contiguous()
-    for _ in range(3):
-        big.forward(xb)
-    torch.cuda.synchronize()
-    ev[0].record()
-    for _ in range(10):
-        big.forward(xb)
-    ev[1].record()
-    torch.cuda.synchronize()
-    f_ms = ev[0].elapsed_time(ev[1]) / 10
-    flops = 2.0 * 512 * PROP_POINTS * (6 * 128 + 128 * 256)
-    out["encoder_forward"] = {"objects": 512, "points": PROP_POINTS, "ms": f_ms,
-                              "tflops": flops / (f_ms * 1e-3) / 1e12, "peak_tflops": 2500.0,
-                              "frac": flops / (f_ms * 1e-3) / 1e12 / 2500.0}
-    big.release()
+    out["encoder_forward"] = encoder_bench(torch, lg, X, seed)
     out["valid_per_s_ratio"] = out["learned"]["valid_grasps_per_s"] / max(out["uniform"]["valid_grasps_per_s"], 1e-9)
     prop.release()
     field.release()
@@ -435,6 +443,12 @@ def main():
         out = proposer_bench(torch, lg, pool, args.train_objects, args.eval_objects, args.epochs, args.seed)
         pool.close()
         print(json.dumps({"proposer": out}))
+        return
+    if args.mode == "encoder":
+        # proposer forward alone: random-init weights, 8 c2 objects' point subsamples repeated
+        objs = [synth.superquadric_object(args.seed + i, 16384) for i in range(8)]
+        X = torch.stack([_prop_input(torch, o, args.seed + i) for i, o in enumerate(objs)])
+        print(json.dumps({"encoder_forward": encoder_bench(torch, lg, X, args.seed, reps=max(args.steps, 1))}))
         return
     if args.mode == "serve":
         for rate in [float(r) for r in args.serve_rates.split(",")]:

@@ -499,8 +499,10 @@ lg_status lg_prop_set_params(lg_prop *p, const float *host_in);
 
 /* Forward pass of B objects with Np points each.  Optional outputs (NULL =
  * skip): out [B][152] mixture parameters, feat [B][256] pooled features,
- * arg [B][256] the point index of each channel's maximum (lowest index among
- * equal maxima).  LG_EINVAL if B or Np is outside the proposer's limits. */
+ * arg [B][256] the point index of each channel's maximum: the point with the
+ * largest FP32 layer-2 sum before the bias (lowest index among equal sums),
+ * or 0 for a channel cut to zero by the ReLU (every point then ties at 0).
+ * LG_EINVAL if B or Np is outside the proposer's limits. */
 lg_status lg_prop_forward(lg_prop *p, const float *x, int32_t B, int32_t Np, float *out, float *feat,
                           int32_t *arg, void *stream);
 

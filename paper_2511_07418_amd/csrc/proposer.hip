@@ -12,19 +12,24 @@
 // SO(3) by Gram-Schmidt (the 6-D representation of Zhou et al. 2019).
 //
 // Work decomposition:
-//  * k_encode: 8 waves x 32 points per tile, 8 tiles per workgroup (W2 is
-//    staged in LDS once for all of them); layer 1 is one 32x32x16 MFMA per 32
-//    output channels (K = 6 padded to 16), its ReLU output goes to LDS as
-//    BF16; layer 2 reads W2 (BF16, 68 KiB) from LDS and issues 8 x 8 MFMAs per
-//    wave and tile; the max-pool folds bias, ReLU, the max over the rows and
-//    the argmax into one 64-bit key per channel (value bits above the inverted
-//    point index), kept in registers over the tiles and merged with one
-//    atomicMax per channel and workgroup, so equal maxima resolve to the
-//    lowest point index.
+//  * k_encode: 2048 points of one object per workgroup of 8 waves; W2 (BF16,
+//    68 KiB) is staged in LDS once, then every wave runs its own 64-point
+//    steps without a barrier.  Layer 1 is computed transposed (one 32x32x16
+//    MFMA per 32 channels, K = 6 padded to 16, the bias as the accumulator),
+//    so a lane holds 4-channel groups of one point; a lane-half swap
+//    (v_permlane32_swap) turns them into layer 2's A operand in registers.
+//    Layer 2 is 8 x 8 MFMAs per 32 points; the max-pool keeps, per lane and
+//    channel, the largest pre-activation and its lowest point (a max tree,
+//    then a first-match scan); the pairs are merged across the lane halves,
+//    the waves (LDS) and the workgroups (64-bit atomicMax of ordered value
+//    bits above the inverted point index); bias and ReLU are applied to the
+//    pooled maximum.
 //  * the head and every backward product are small GEMMs (rows = objects)
 //    run by k_gemm, one wave per 32x32 output tile;
 //  * the encoder backward is sparse: the max-pool routes each channel's
 //    gradient to one point, so only B x 256 point rows are revisited (FP32).
+
+#include <type_traits>
 
 #include "lg_internal.h"
 
@@ -144,17 +149,19 @@ __global__ void k_fill_u64(unsigned long long *__restrict__ p, int64_t n)
 }
 
 // ---- encoder -----------------------------------------------------------------
-#ifndef LG_ENC_WAVES
-#define LG_ENC_WAVES 8
-#endif
-constexpr int kEncWaves = LG_ENC_WAVES;
+constexpr int kEncWaves = 8;
 constexpr int kEncThreads = 64 * kEncWaves;
-constexpr int kEncRows = 32 * kEncWaves;  // points per tile
-#ifndef LG_ENC_TILES
-#define LG_ENC_TILES 8
-#endif
-constexpr int kEncTiles = LG_ENC_TILES;   // tiles per workgroup: W2 is staged once for all of them
-constexpr int kLd = kH1 + 8;              // padded LDS row of H1 and W2^T (BF16 elements)
+constexpr int kEncPair = 64;                         // points a wave takes per step: two 32-row blocks
+constexpr int kEncChunk = kEncPair * kEncWaves * 4;  // points per workgroup (4 steps per wave)
+constexpr int kLd = kH1 + 8;                                   // padded LDS row of W2^T (BF16 elements)
+static_assert(kEncThreads >= kH2, "the pooled-key merge takes one thread per channel");
+static_assert(kEncWaves * kH2 * 8 <= kH2 * kLd * 2, "the pooled-key merge reuses the W2 buffer");
+
+typedef short s16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
 __device__ inline u16x8_t input_row(const float *__restrict__ xp)
 {
@@ -168,102 +175,194 @@ __device__ inline u16x8_t input_row(const float *__restrict__ xp)
     return a;
 }
 
-// grid (ceil(Np / (kEncRows kEncTiles)), B), kEncThreads threads
-__global__ __launch_bounds__(kEncThreads) void k_encode(const float *__restrict__ x, int Np,
-                                                const uint16_t *__restrict__ T,
-                                                const float *__restrict__ P,
-                                                unsigned long long *__restrict__ keys)
+// (bf16(relu(a)), bf16(relu(b))) packed low/high.  Round to nearest even, then
+// a signed 16-bit max with 0: a negative BF16 (and -0) has its sign bit set.
+__device__ inline uint32_t relu_pk_bf16(float a, float b)
+{
+    const f32x2_t v = {a, b};
+    const s16x2_t h = __builtin_bit_cast(s16x2_t, __builtin_convertvector(v, bf16x2_t));
+    const s16x2_t z = {0, 0};
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(h, z));
+}
+
+// FP32 -> unsigned with the same order (sign-magnitude flipped); 0 never
+// comes out of a finite value, so a zero key means "no point"
+__device__ inline uint32_t ord_bits(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float ord_val(uint32_t o) { return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o); }
+
+// Fold one 32-row block of a layer-2 column block into the lane's running
+// (max, point) pair: rows ascend with the register index, so the first
+// register equal to the maximum is the lowest point.
+__device__ inline void fold_rows(f32x16_t a, int row0, int end, int half, float &best, int &bidx)
+{
+    if (row0 + 32 > end) {  // wave-uniform: the object's last rows
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (row0 + 8 * (i >> 2) + 4 * half + (i & 3) >= end) a[i] = -INFINITY;
+    }
+    float m = a[0];
+#pragma unroll
+    for (int i = 1; i < 16; ++i) m = fmaxf(m, a[i]);
+    int ii = 8 * 3 + 3;
+#pragma unroll
+    for (int i = 14; i >= 0; --i) ii = a[i] == m ? 8 * (i >> 2) + (i & 3) : ii;
+    if (m > best) {
+        best = m;
+        bidx = row0 + 4 * half + ii;
+    }
+}
+
+// grid (ceil(Np / kEncChunk), B), kEncThreads threads.  Each wave runs its
+// own 64-point steps with no barrier: layer 1 is computed transposed
+// (channels x points), so a lane ends up holding 4-channel groups of one
+// point; one lane-half swap per dword turns them into the layer-2 A operand
+// (8 consecutive channels of one point) without going through LDS.
+// Two waves per SIMD: the W2 copy (68 KiB of LDS) allows no more.
+__global__ __launch_bounds__(kEncThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_encode(const float *__restrict__ x, int Np,
+                                                        const uint16_t *__restrict__ T,
+                                                        const float *__restrict__ P,
+                                                        unsigned long long *__restrict__ keys)
 {
     __shared__ __attribute__((aligned(16))) uint16_t sW2[kH2 * kLd];
-    __shared__ __attribute__((aligned(16))) uint16_t sH1[kEncRows * kLd];
-    __shared__ float sB1[kH1], sB2[kH2];
-    const int b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ __attribute__((aligned(16))) float sB1[kH1];
+    const int b = blockIdx.y, tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int r = lane & 31, half = lane >> 5;
     for (int i = tid; i < kH2 * (kH1 / 8); i += kEncThreads) {
         const int n = i / (kH1 / 8), k8 = i % (kH1 / 8);
         *(u16x8_t *)&sW2[n * kLd + 8 * k8] = *(const u16x8_t *)&T[kT2 + (int64_t)n * kH1 + 8 * k8];
     }
     for (int i = tid; i < kH1; i += kEncThreads) sB1[i] = P[kB1 + i];
-    for (int i = tid; i < kH2; i += kEncThreads) sB2[i] = P[kB2 + i];
     __syncthreads();
 
-    // running max-pool key per column block (lanes r < 32 own column 32 blk + r)
-    unsigned long long kmax[kH2 / 32];
+    float best[kH2 / 32];
+    int bidx[kH2 / 32];
 #pragma unroll
-    for (int blk = 0; blk < kH2 / 32; ++blk) kmax[blk] = 0ull;
-    uint16_t *h1 = sH1 + wave * 32 * kLd;
-    for (int tile = 0; tile < kEncTiles; ++tile) {
-        const int tile0 = (blockIdx.x * kEncTiles + tile) * kEncRows;
-        if (tile0 >= Np) break;  // uniform over the workgroup
-        const int row0 = tile0 + wave * 32;
-        const int pt = row0 + r;
-        u16x8_t xa = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (half == 0 && pt < Np) xa = input_row(x + ((int64_t)b * Np + pt) * kIn);
+    for (int c = 0; c < kH2 / 32; ++c) {
+        best[c] = -INFINITY;
+        bidx[c] = 0;
+    }
+    const int c0 = blockIdx.x * kEncChunk, c1 = min(Np, c0 + kEncChunk);
+    for (int p0 = c0 + wave * kEncPair; p0 < c1; p0 += kEncWaves * kEncPair) {
+        u16x8_t h[2][kH1 / 16];
 #pragma unroll
-        for (int blk = 0; blk < kH1 / 32; ++blk) {
-            const int col = 32 * blk + r;
-            const u16x8_t wb = *(const u16x8_t *)&T[kT1 + col * kInPad + 8 * half];
-            f32x16_t acc = {};
-            acc = mfma(xa, wb, acc);
-            const float bias = sB1[col];
+        for (int j = 0; j < 2; ++j) {
+            const int pt = p0 + 32 * j + r;
+            u16x8_t xb = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (half == 0 && pt < c1) xb = input_row(x + ((int64_t)b * Np + pt) * kIn);
 #pragma unroll
-            for (int i = 0; i < 16; ++i) h1[c_row(i, lane) * kLd + col] = bf16_bits(fmaxf(acc[i] + bias, 0.0f));
-        }
-        __syncthreads();
-
+            for (int cb = 0; cb < kH1 / 32; ++cb) {
+                // D[channel][point] = b1 + W1^T x: the bias enters as the accumulator
+                f32x16_t acc;
 #pragma unroll
-        for (int blk = 0; blk < kH2 / 32; ++blk) {
-            const int col = 32 * blk + r;
-            f32x16_t acc = {};
+                for (int g = 0; g < 4; ++g) {
+                    const f32x4_t bb = *(const f32x4_t *)&sB1[32 * cb + 8 * g + 4 * half];
 #pragma unroll
-            for (int kk = 0; kk < kH1 / 16; ++kk) {
-                const u16x8_t av = *(const u16x8_t *)&h1[r * kLd + 16 * kk + 8 * half];
-                const u16x8_t bv = *(const u16x8_t *)&sW2[col * kLd + 16 * kk + 8 * half];
-                acc = mfma(av, bv, acc);
-            }
-            const float bias = sB2[col];
-            float best = -1.0f;
-            int bi = 0;
+                    for (int e = 0; e < 4; ++e) acc[4 * g + e] = bb[e];
+                }
+                const u16x8_t wa = *(const u16x8_t *)&T[kT1 + (32 * cb + r) * kInPad + 8 * half];
+                acc = mfma(wa, xb, acc);
+                // group g holds channels 32 cb + 8 g + 4 half + (0..3) of point r
+                uint32_t pk[4][2];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {  // rows ascend with i: '>' keeps the lowest index
-                const int p = row0 + c_row(i, lane);
-                const float v = fmaxf(acc[i] + bias, 0.0f);
-                if (p < Np && v > best) {
-                    best = v;
-                    bi = p;
+                for (int g = 0; g < 4; ++g) {
+                    pk[g][0] = relu_pk_bf16(acc[4 * g], acc[4 * g + 1]);
+                    pk[g][1] = relu_pk_bf16(acc[4 * g + 2], acc[4 * g + 3]);
+                }
+                // K-step kk = 2 cb + gg covers groups 2 gg (half 0 needs both halves' copy)
+                // and 2 gg + 1 (half 1 likewise): swap the upper lanes of the first
+                // with the lower lanes of the second
+#pragma unroll
+                for (int gg = 0; gg < 2; ++gg) {
+                    uint32_t v1[2] = {pk[2 * gg][0], pk[2 * gg][1]};
+                    uint32_t v2[2] = {pk[2 * gg + 1][0], pk[2 * gg + 1][1]};
+#pragma unroll
+                    for (int d = 0; d < 2; ++d) {
+                        const auto sw = __builtin_amdgcn_permlane32_swap(v1[d], v2[d], false, false);
+                        v1[d] = sw[0];
+                        v2[d] = sw[1];
+                    }
+                    const u32x4_t q = {v1[0], v1[1], v2[0], v2[1]};
+                    h[j][2 * cb + gg] = __builtin_bit_cast(u16x8_t, q);
                 }
             }
-            unsigned long long key = best < 0.0f ? 0ull
-                                                 : (((unsigned long long)__float_as_uint(best)) << 32) |
-                                                       (0xFFFFFFFFu - (uint32_t)bi);
-            const uint32_t lo = __shfl_xor((uint32_t)key, 32, 64), hi = __shfl_xor((uint32_t)(key >> 32), 32, 64);
-            const unsigned long long other = ((unsigned long long)hi << 32) | lo;
-            key = key > other ? key : other;
-            kmax[blk] = key > kmax[blk] ? key : kmax[blk];
         }
-        __syncthreads();  // the next tile overwrites H1
-    }
 #pragma unroll
-    for (int blk = 0; blk < kH2 / 32; ++blk)
-        if (half == 0 && kmax[blk]) atomicMax(&keys[(int64_t)b * kH2 + 32 * blk + r], kmax[blk]);
+        for (int cb2 = 0; cb2 < kH2 / 32; ++cb2) {
+            f32x16_t a0 = {}, a1 = {};
+#pragma unroll
+            for (int kk = 0; kk < kH1 / 16; ++kk) {
+                const u16x8_t bv = *(const u16x8_t *)&sW2[(32 * cb2 + r) * kLd + 16 * kk + 8 * half];
+                a0 = mfma(h[0][kk], bv, a0);
+                a1 = mfma(h[1][kk], bv, a1);
+            }
+            fold_rows(a0, p0, c1, half, best[cb2], bidx[cb2]);
+            fold_rows(a1, p0 + 32, c1, half, best[cb2], bidx[cb2]);
+            __builtin_amdgcn_sched_barrier(0);  // keep the next block's LDS reads after this fold
+        }
+    }
+
+    // merge: the two lane halves, then the waves (through LDS), then the
+    // workgroups (64-bit atomicMax of (ordered value, inverted point))
+    __syncthreads();  // every wave is done with W2
+    unsigned long long *sKey = reinterpret_cast<unsigned long long *>(sW2);
+#pragma unroll
+    for (int c = 0; c < kH2 / 32; ++c) {
+        const unsigned long long key =
+            best[c] == -INFINITY ? 0ull
+                                 : ((unsigned long long)ord_bits(best[c]) << 32) | (0xFFFFFFFFu - (uint32_t)bidx[c]);
+        const uint32_t lo = __shfl_xor((uint32_t)key, 32, 64), hi = __shfl_xor((uint32_t)(key >> 32), 32, 64);
+        const unsigned long long other = ((unsigned long long)hi << 32) | lo;
+        if (half == 0) sKey[wave * kH2 + 32 * c + r] = key > other ? key : other;
+    }
+    __syncthreads();
+    if (tid < kH2) {
+        unsigned long long k = sKey[tid];
+#pragma unroll
+        for (int w = 1; w < kEncWaves; ++w) {
+            const unsigned long long o = sKey[w * kH2 + tid];
+            k = o > k ? o : k;
+        }
+        if (k) atomicMax(&keys[(int64_t)b * kH2 + tid], k);
+    }
 }
 
-__global__ void k_pool_finish(const unsigned long long *__restrict__ keys, int n, float *__restrict__ feat,
-                              int32_t *__restrict__ arg)
+// feat = relu(max pre-activation + b2); arg = its point, or 0 where the
+// channel is cut to zero (every point then ties at 0 and the lowest wins)
+__global__ void k_pool_finish(const unsigned long long *__restrict__ keys, int n, const float *__restrict__ P,
+                              float *__restrict__ feat, int32_t *__restrict__ arg)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const unsigned long long k = keys[i];
-    feat[i] = __uint_as_float((uint32_t)(k >> 32));
-    arg[i] = (int32_t)(0xFFFFFFFFu - (uint32_t)k);
+    float f = 0.0f;
+    int32_t a = 0;
+    if (k) {
+        const float t = ord_val((uint32_t)(k >> 32)) + P[kB2 + i % kH2];
+        if (t > 0.0f) {
+            f = t;
+            a = (int32_t)(0xFFFFFFFFu - (uint32_t)k);
+        }
+    }
+    feat[i] = f;
+    arg[i] = a;
 }
 
 // ---- small GEMMs -------------------------------------------------------------
 // C[m][n] = epi(sum_k A(m,k) B(k,n)), operands rounded to BF16, FP32 accumulate.
 // A(m,k) = A[m*a_ms + k*a_ks] (FP32); B(k,n) = B[k*b_ks + n*b_ns] (FP32 or BF16 bits).
 enum { kEpiNone = 0, kEpiBias = 1, kEpiBiasRelu = 2, kEpiMask = 3 };
+constexpr int kGemmSteps = 8;  // k-steps of 16 per trip of the main loop
 
-template <typename TB, int EPI>
+// KC: k is contiguous in both operands (a_ks = b_ks = 1, K % 16 = 0, rows
+// 16-byte aligned; B is BF16): 8 consecutive k are two float4 loads of A
+// and one 16-byte load of B.  The main loop issues the loads of kGemmSteps
+// k-steps before their MFMAs, so that they are in flight together.
+template <typename TB, int EPI, bool KC>
 __global__ __launch_bounds__(64) void k_gemm(int Mr, int Nc, int K, const float *__restrict__ A, int64_t a_ms,
                                              int64_t a_ks, const TB *__restrict__ Bm, int64_t b_ks, int64_t b_ns,
                                              const float *__restrict__ bias, const float *__restrict__ mask,
@@ -273,15 +372,54 @@ __global__ __launch_bounds__(64) void k_gemm(int Mr, int Nc, int K, const float 
     const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
     const int m = m0 + r, n = n0 + r;
     f32x16_t acc = {};
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    // rows m >= Mr and columns n >= Nc repeat the last one (KC) or read zeros
+    // and are not stored
+    const float *ar = A + (int64_t)min(m, Mr - 1) * a_ms + 8 * half;
+    const TB *br = Bm + (int64_t)min(n, Nc - 1) * b_ns + 8 * half;
+    // operands of one k-step (the 8 consecutive k of this lane's half)
+    struct Ops {
+        float4 a0, a1;
         u16x8_t av, bv;
+    };
+    auto load = [&](int k0, Ops &o) {
+        if constexpr (KC) {
+            o.a0 = *(const float4 *)(ar + k0);
+            o.a1 = *(const float4 *)(ar + k0 + 4);
+            o.bv = *(const u16x8_t *)(br + k0);
+        } else {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int k = k0 + 8 * half + j;
-            av[j] = (m < Mr && k < K) ? bf16_bits(A[m * a_ms + k * a_ks]) : (uint16_t)0;
-            bv[j] = (n < Nc && k < K) ? bf16_bits(Bm[k * b_ks + n * b_ns]) : (uint16_t)0;
+            for (int j = 0; j < 8; ++j) {
+                const int k = k0 + 8 * half + j;
+                o.av[j] = (m < Mr && k < K) ? bf16_bits(A[m * a_ms + k * a_ks]) : (uint16_t)0;
+                o.bv[j] = (n < Nc && k < K) ? bf16_bits(Bm[k * b_ks + n * b_ns]) : (uint16_t)0;
+            }
         }
-        acc = mfma(av, bv, acc);
+    };
+    auto use = [&](Ops &o) {
+        if constexpr (KC) {
+            o.av[0] = bf16_bits(o.a0.x);
+            o.av[1] = bf16_bits(o.a0.y);
+            o.av[2] = bf16_bits(o.a0.z);
+            o.av[3] = bf16_bits(o.a0.w);
+            o.av[4] = bf16_bits(o.a1.x);
+            o.av[5] = bf16_bits(o.a1.y);
+            o.av[6] = bf16_bits(o.a1.z);
+            o.av[7] = bf16_bits(o.a1.w);
+        }
+        acc = mfma(o.av, o.bv, acc);
+    };
+    int k0 = 0;
+    for (; k0 + 16 * kGemmSteps <= K; k0 += 16 * kGemmSteps) {  // all loads of a trip go out first
+        Ops o[kGemmSteps];
+#pragma unroll
+        for (int t = 0; t < kGemmSteps; ++t) load(k0 + 16 * t, o[t]);
+#pragma unroll
+        for (int t = 0; t < kGemmSteps; ++t) use(o[t]);
+    }
+    for (; k0 < K; k0 += 16) {
+        Ops o;
+        load(k0, o);
+        use(o);
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -605,8 +743,14 @@ template <typename TB, int EPI>
 void gemm(hipStream_t s, int Mr, int Nc, int K, const float *A, int64_t a_ms, int64_t a_ks, const TB *Bm,
           int64_t b_ks, int64_t b_ns, const float *bias, const float *mask, int64_t mask_ld, float *C, int64_t ldc)
 {
-    hipLaunchKernelGGL((k_gemm<TB, EPI>), dim3(blocks(Nc, 32), blocks(Mr, 32)), dim3(64), 0, s, Mr, Nc, K, A, a_ms,
-                       a_ks, Bm, b_ks, b_ns, bias, mask, mask_ld, C, ldc);
+    const bool kc = std::is_same<TB, uint16_t>::value && a_ks == 1 && b_ks == 1 && K % 16 == 0 && a_ms % 4 == 0 &&
+                    b_ns % 8 == 0 && ((uintptr_t)A & 15) == 0 && ((uintptr_t)Bm & 15) == 0;
+    if (kc)
+        hipLaunchKernelGGL((k_gemm<TB, EPI, true>), dim3(blocks(Nc, 32), blocks(Mr, 32)), dim3(64), 0, s, Mr, Nc, K,
+                           A, a_ms, a_ks, Bm, b_ks, b_ns, bias, mask, mask_ld, C, ldc);
+    else
+        hipLaunchKernelGGL((k_gemm<TB, EPI, false>), dim3(blocks(Nc, 32), blocks(Mr, 32)), dim3(64), 0, s, Mr, Nc,
+                           K, A, a_ms, a_ks, Bm, b_ks, b_ns, bias, mask, mask_ld, C, ldc);
 }
 
 lg_status check_batch(const lg_prop *p, const float *x, int B, int Np)
@@ -622,9 +766,9 @@ lg_status forward(lg_prop *p, const float *x, int B, int Np, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fill_u64, dim3(blocks((int64_t)B * kH2, 256)), dim3(256), 0, s, p->keys,
                        (int64_t)B * kH2);
-    hipLaunchKernelGGL(k_encode, dim3(blocks(Np, kEncRows * kEncTiles), B), dim3(kEncThreads), 0, s, x, Np, p->T,
-                       p->P, p->keys);
-    hipLaunchKernelGGL(k_pool_finish, dim3(blocks((int64_t)B * kH2, 256)), dim3(256), 0, s, p->keys, B * kH2,
+    hipLaunchKernelGGL(k_encode, dim3(blocks(Np, kEncChunk), B), dim3(kEncThreads), 0, s, x, Np, p->T, p->P,
+                       p->keys);
+    hipLaunchKernelGGL(k_pool_finish, dim3(blocks((int64_t)B * kH2, 256)), dim3(256), 0, s, p->keys, B * kH2, p->P,
                        p->feat, p->arg);
     gemm<uint16_t, kEpiBiasRelu>(s, B, kHH, kH2, p->feat, kH2, 1, p->T + kTa, 1, kH2, p->P + kBa, nullptr, 0, p->ua,
                                  kHH);
