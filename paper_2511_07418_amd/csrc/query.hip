@@ -99,19 +99,78 @@ __device__ inline uint32_t block_skip(const float4 *__restrict__ bounds, const A
     return all;
 }
 
+// a * b + c on the 24-bit multiplier (a, b < 2^24; b uniform)
+__device__ inline uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+
+// nearest_bin_lut with the candidate slots evaluated branch-free: the four
+// slots' centres (float4 rows, an absent slot repeats the first candidate) are
+// read before any dot product, so a wave pays one LDS round trip instead of
+// one per candidate of its worst lane.  Same arithmetic and tie rule (slots in
+// increasing bin order, strict >).
+__device__ inline int nearest_bin_lut4(const uint32_t *lut, const float4 *c4, int B, float dx, float dy, float dz)
+{
+    const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+    const bool xm = (ax >= ay) & (ax >= az);
+    const bool ym = !xm & (ay >= az);
+    const float m = xm ? ax : (ym ? ay : az);
+    const float u = xm ? dy : (ym ? dz : dx);
+    const float v = xm ? dz : (ym ? dx : dy);
+    const float dm = xm ? dx : (ym ? dy : dz);
+    const int face = (xm ? 0 : (ym ? 2 : 4)) + (dm < 0.f ? 1 : 0);
+    const float s = (0.5f * kLutRes) * __builtin_amdgcn_rcpf(m);
+    const int iu = min(max((int)fmaf(u, s, 0.5f * kLutRes), 0), kLutRes - 1);
+    const int iv = min(max((int)fmaf(v, s, 0.5f * kLutRes), 0), kLutRes - 1);
+    const uint32_t e = lut[(face * kLutRes + iv) * kLutRes + iu];
+    float best = -3.0e38f;
+    int bi = 0;
+    if (e == 0xffffffffu) {  // more than four candidates: every bin
+        for (int b = 0; b < B; ++b) {
+            const float4 c = c4[b];
+            const float sc = fmaf(c.x, dx, fmaf(c.y, dy, c.z * dz));
+            if (sc > best) {
+                best = sc;
+                bi = b;
+            }
+        }
+        return bi;
+    }
+    const uint32_t b0 = e & 0xffu;
+    uint32_t bk[4] = {b0, e >> 8 & 0xffu, e >> 16 & 0xffu, e >> 24};
+#pragma unroll
+    for (int k = 1; k < 4; ++k) bk[k] = bk[k] == 0xffu ? b0 : bk[k];
+    float4 ck[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ck[k] = c4[bk[k]];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float sc = fmaf(ck[k].x, dx, fmaf(ck[k].y, dy, ck[k].z * dz));
+        if (sc > best) {
+            best = sc;
+            bi = (int)bk[k];
+        }
+    }
+    return bi;
+}
+
 template <int W, int FM>
 __global__ void __launch_bounds__(kQueryThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict__ pts,
         const float *__restrict__ nrm, int N, const float *__restrict__ poses, const float4 *__restrict__ bounds,
         uint32_t *__restrict__ dom_bits, uint32_t *__restrict__ dom_count)
 {
-    __shared__ float cb[3 * kMaxBins];
+    __shared__ float4 cb4[kMaxBins];
     __shared__ uint32_t lut[6 * kLutRes * kLutRes];
     __shared__ Affine aff[FM];
     __shared__ uint32_t cnt[FM][kQueryWaves];
     const int g = blockIdx.x;
     const float *pose = poses + 12 * (int64_t)g;
-    for (int i = threadIdx.x; i < 3 * H.B; i += blockDim.x) cb[i] = H.bin_c[i];
+    for (int i = threadIdx.x; i < H.B; i += blockDim.x)
+        cb4[i] = make_float4(H.bin_c[3 * i], H.bin_c[3 * i + 1], H.bin_c[3 * i + 2], 0.0f);
     for (int i = threadIdx.x; i < 6 * kLutRes * kLutRes; i += blockDim.x) lut[i] = H.bin_lut[i];
     if (threadIdx.x < H.F) aff[threadIdx.x] = finger_affine(H, pose, threadIdx.x);
     __syncthreads();
@@ -120,6 +179,10 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int F = H.F, G = H.G, B = H.B;
     const int64_t G3W = (int64_t)G * G * G * W;
+    // finger f's table starts fstride bytes after finger f-1's; qbase is shifted
+    // back by the biased index of voxel (0, 0, 0), ((G G + G) + 1) G words of W
+    const char *qbase = reinterpret_cast<const char *>(merged) - 4 * (int64_t)W * G * ((int64_t)G * G + G + 1);
+    const int64_t fstride = 4 * G3W;
     const int NW = (N + 31) >> 5, nchunks = (N + 63) >> 6;
     float P[12];
 #pragma unroll
@@ -160,7 +223,8 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
             }
             float qx, qy, qz;
             query_dir(P, nx, ny, nz, qx, qy, qz);
-            const int b = nearest_bin_lut(lut, cb, B, qx, qy, qz);
+            const int b = nearest_bin_lut4(lut, cb4, B, qx, qy, qz);
+            const uint32_t bsel4 = (uint32_t)(b >> 5) << 2;  // byte offset of the word holding bit b
             // one 32-bit word per finger: the word of the table that holds bit b;
             // all finger gathers are issued before any is consumed
             uint32_t word[FM];
@@ -168,19 +232,20 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
             for (int f = 0; f < FM; ++f) {
                 word[f] = 0;
                 if (f < F && !(skip[f] & cbit)) {
-                    // window_voxel's arithmetic, with only the load predicated
+                    // window_voxel's voxel, with the -G of each coordinate moved into
+                    // the base address and only the load predicated
                     const Affine &a = aff[f];
                     const float ux = fmaf(a.m[0], px, fmaf(a.m[1], py, fmaf(a.m[2], pz, a.m[3])));
                     const float uy = fmaf(a.m[4], px, fmaf(a.m[5], py, fmaf(a.m[6], pz, a.m[7])));
                     const float uz = fmaf(a.m[8], px, fmaf(a.m[9], py, fmaf(a.m[10], pz, a.m[11])));
-                    const unsigned ix = (unsigned)((int)ux - G), iy = (unsigned)((int)uy - G),
-                                   iz = (unsigned)((int)uz - G);
-                    const bool in = valid & (max(ix, max(iy, iz)) < (unsigned)G);
+                    const int Ix = (int)ux, Iy = (int)uy, Iz = (int)uz;  // biased voxel coordinates
+                    const bool in = valid & (min(Ix, min(Iy, Iz)) >= G) & (max(Ix, max(Iy, Iz)) < 2 * G);
                     // one uniform base and a 32-bit byte offset per lane (the tables
                     // are far below 4 GiB): the load takes the scalar-base form
-                    const uint32_t v = __umul24(__umul24(iz, G) + iy, G) + ix;
-                    const uint32_t boff = ((uint32_t)f * (uint32_t)G3W + v * W + (uint32_t)(b >> 5)) << 2;
-                    if (in) word[f] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(merged) + boff);
+                    const uint32_t v =
+                        mad_u24(mad_u24((uint32_t)Iz, (uint32_t)G, (uint32_t)Iy), (uint32_t)G, (uint32_t)Ix);
+                    const uint32_t boff = v * (4u * W) + bsel4 + (uint32_t)f * (uint32_t)fstride;
+                    if (in) word[f] = *reinterpret_cast<const uint32_t *>(qbase + boff);
                 }
             }
             const int j2 = 2 * (chunk - blk * 32);
