@@ -57,9 +57,11 @@ def _oracle_inputs(xs):
     return [op.inputs(x[:, :3].astype(np.float64), x[:, 3:].astype(np.float64)) for x in xs]
 
 
-@pytest.mark.parametrize("B,Np", [(3, 2048), (2, 300), (1, 1)])
+# 2048 points fill one encoder workgroup; 5000 take three (the last ragged), so
+# the pooled keys of several workgroups meet in the 64-bit atomicMax
+@pytest.mark.parametrize("B,Np", [(3, 2048), (2, 300), (1, 1), (2, 5000)])
 def test_forward_parity(lg, B, Np):
-    prop = lg.Proposer(max_batch=4, max_points=2048, max_targets=64, seed=11)
+    prop = lg.Proposer(max_batch=4, max_points=max(2048, Np), max_targets=64, seed=11)
     p = op.unflatten(prop.get_params().astype(np.float64))
     xs = _objects(B, Np)
     x = torch.from_numpy(np.stack(xs)).cuda()
