@@ -221,11 +221,11 @@ __device__ inline void fold_rows(f32x16_t a, int row0, int end, int half, float 
 // (channels x points), so a lane ends up holding 4-channel groups of one
 // point; one lane-half swap per dword turns them into the layer-2 A operand
 // (8 consecutive channels of one point) without going through LDS.
-// Two waves per SIMD: the W2 copy (68 KiB of LDS) allows no more.
-__global__ __launch_bounds__(kEncThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_encode(const float *__restrict__ x, int Np,
-                                                        const uint16_t *__restrict__ T,
-                                                        const float *__restrict__ P,
-                                                        unsigned long long *__restrict__ keys)
+// Registers, not LDS, set the occupancy: the H1 of two row blocks, two
+// accumulators and the running pairs take 174 VGPRs, two waves per SIMD.
+__global__ __launch_bounds__(kEncThreads) __attribute__((amdgpu_waves_per_eu(2))) void
+k_encode(const float *__restrict__ x, int Np, const uint16_t *__restrict__ T, const float *__restrict__ P,
+         unsigned long long *__restrict__ keys)
 {
     __shared__ __attribute__((aligned(16))) uint16_t sW2[kH2 * kLd];
     __shared__ __attribute__((aligned(16))) float sB1[kH1];
