@@ -249,6 +249,19 @@ def test_query_bounded_against_the_oracle():
     _query_check(w, ref["bits"], poses_idx=np.sort(sel), bounded=True)
 
 
+def test_query_c3_full_shape_as_benchmarked():
+    """The launch the benchmark times: C3 at full shape (N = P = 65,536), points
+    in Morton order, the bounded query; 12 sampled poses against the oracle."""
+    import dataclasses
+    lg = lgmod()
+    w = synth.workload("c3", samples=4096, with_sdf=False)
+    order = lg.lg_morton_order(w.obj.pts)
+    w = dataclasses.replace(w, obj=dataclasses.replace(w.obj, pts=w.obj.pts[order], nrm=w.obj.nrm[order]))
+    ref = oracle.build_field(w.hand, w.field, flags=False)
+    sel = np.random.default_rng(7).choice(w.poses.shape[0], size=12, replace=False)
+    _query_check(w, ref["bits"], poses_idx=np.sort(sel), bounded=True)
+
+
 def test_query_bounded_far_poses_and_errors():
     lg = lgmod()
     w = synth.workload("c1", n_poses=8)
