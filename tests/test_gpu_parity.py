@@ -331,6 +331,48 @@ def test_search_c2_shape():
     assert len(acc) > 0
 
 
+def test_search_c3_full_shape_as_benchmarked():
+    """The search launch the benchmark times: C3 at full shape (65,536 poses x
+    64 draws of 5 contacts) on the bounded query's domains.  Sampled poses are
+    recomputed by the oracle from the same domains at their global pose index:
+    draws and links bit-exact, verdicts exact outside |t* - eps| <= 1e-6, t*
+    within 1e-9, and the compacted list holds exactly the accepted sets."""
+    import dataclasses
+    lg = lgmod()
+    w = synth.workload("c3", samples=4096, with_sdf=False)
+    order = lg.lg_morton_order(w.obj.pts)
+    w = dataclasses.replace(w, obj=dataclasses.replace(w.obj, pts=w.obj.pts[order], nrm=w.obj.nrm[order]))
+    ref = oracle.build_field(w.hand, w.field, flags=False)
+    field = lg.lg_field_import(w.hand, w.field, ref["bits"])
+    pts, nrm = soa(w.obj.pts), soa(w.obj.nrm)
+    poses = dev(w.poses)
+    db, dc = lg.lg_query_domains_bounded(field, pts, nrm, poses, lg.lg_chunk_bounds(pts))
+    bufs = lg.lg_search(field, pts, nrm, poses, db, dc, w.search)
+    torch.cuda.synchronize()
+    D, k = w.search.draws, w.search.k
+    ver_all = bufs.verdict.cpu().numpy().reshape(-1)
+    n_acc = int(bufs.n_acc.item())
+    assert n_acc > 0
+    assert (bufs.acc_list[:n_acc].cpu().numpy() == np.flatnonzero(ver_all)).all(), "compaction order"
+    sel = np.sort(np.random.default_rng(11).choice(w.poses.shape[0], size=8, replace=False))
+    for g in sel:
+        g = int(g)
+        gb = db[g:g + 1].cpu().numpy().view(np.uint32)
+        gc = dc[g:g + 1].cpu().numpy().view(np.uint32)
+        sp = dataclasses.replace(w.search, pose_offset=g)
+        o_spt, o_sln = oracle.draw(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses[g:g + 1], gb, gc, sp)
+        spt = bufs.set_pt[g].cpu().numpy()
+        sln = bufs.set_link[g].cpu().numpy().astype(np.int32)
+        assert (spt == o_spt[0]).all() and (sln == o_sln[0]).all(), g
+        V = oracle.verdicts(w.obj.pts, w.obj.nrm, o_spt, sp)
+        ver = ver_all[g * D:(g + 1) * D]
+        assert ((ver != V["verdict"].reshape(-1)) & ~V["vflag"].reshape(-1).astype(bool)).sum() == 0, g
+        tst = bufs.tstar[g].cpu().numpy().reshape(-1)
+        ot = V["tstar"].reshape(-1)
+        fin = ~np.isnan(ot)
+        assert np.allclose(tst[fin], ot[fin], atol=1e-9, rtol=0) and np.isnan(tst[~fin]).all(), g
+
+
 def test_search_pivot_cap_gives_no_verdict():
     lg = lgmod()
     w = synth.workload("c1", n_poses=64)
