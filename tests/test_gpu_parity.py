@@ -445,6 +445,59 @@ def test_realize_c3_shape():
     assert R["valid"].sum() > 0
 
 
+def test_realize_c3_full_shape_as_benchmarked():
+    """The realize launch the benchmark times: every accepted set of a full-shape
+    C3 step (65,536 poses, bounded query, search) in one launch; 256 sampled
+    accepted sets recomputed by the oracle.  Bars as for the reduced shape."""
+    import dataclasses
+    lg = lgmod()
+    w = synth.workload("c3", samples=4096)
+    order = lg.lg_morton_order(w.obj.pts)
+    w = dataclasses.replace(w, obj=dataclasses.replace(w.obj, pts=w.obj.pts[order], nrm=w.obj.nrm[order]))
+    ref = oracle.build_field(w.hand, w.field, witness=True, flags=False)
+    field = lg.lg_field_import(w.hand, w.field, ref["bits"], ref["wit"])
+    pts, nrm = soa(w.obj.pts), soa(w.obj.nrm)
+    poses = dev(w.poses)
+    db, dc = lg.lg_query_domains_bounded(field, pts, nrm, poses, lg.lg_chunk_bounds(pts))
+    sb = lg.lg_search(field, pts, nrm, poses, db, dc, w.search)
+    torch.cuda.synchronize()
+    n_acc = int(sb.n_acc.item())
+    assert n_acc > 1000
+    k = w.search.k
+    sdf_vals = dev(w.sdf.values)
+    sdf = lg.sdf_struct(w.sdf, sdf_vals)
+    rb = lg.lg_realize(field, sdf, pts, nrm, poses, sb.set_pt, sb.set_link, k, w.search.draws, sb.acc_list,
+                       sb.n_acc, n_acc, w.ik, sp=w.search)
+    torch.cuda.synchronize()
+    acc = sb.acc_list[:n_acc].cpu().numpy()
+    pick = np.sort(np.random.default_rng(13).choice(n_acc, size=256, replace=False))
+    spt = sb.set_pt.cpu().numpy().reshape(-1, k)
+    sln = sb.set_link.cpu().numpy().astype(np.int32).reshape(-1, k)
+    R = oracle.realize(w.hand, w.field, ref["wit"], w.sdf, w.obj.pts, w.obj.nrm, w.poses, spt, sln, w.search,
+                       acc[pick], w.ik)
+    q = rb.q[:n_acc].cpu().numpy().astype(np.float64)[pick]
+    err = rb.contact_err[:n_acc].cpu().numpy()[pick]
+    dep = rb.depth[:n_acc].cpu().numpy()[pick]
+    val = rb.valid[:n_acc].cpu().numpy()[pick]
+    bad_sets = 0
+    for a in range(len(pick)):
+        Tg, To = oracle.fk(w.hand, q[a]), oracle.fk(w.hand, R["q"][a])
+        d = 0.0
+        for l in range(w.hand.n_joints):
+            cap = w.hand.capsule[l].astype(np.float64)
+            for e in (cap[:3], cap[3:6]):
+                pe = np.append(e, 1.0)
+                d = max(d, np.abs(Tg[l].reshape(3, 4) @ pe - To[l].reshape(3, 4) @ pe).max())
+        bad_sets += d > 1e-5
+    assert bad_sets <= 1, bad_sets
+    close = np.abs(err - R["contact_err"]).max(axis=1) <= 1e-5
+    assert close.mean() >= 0.99
+    fl = R["rflag"].astype(bool)
+    assert ((val != R["valid"]) & ~fl & close).sum() == 0
+    assert (np.abs(dep - R["depth"]) <= 1e-5).mean() >= 0.99
+    assert R["valid"].sum() > 0
+
+
 def test_realize_c1_sphere():
     w = synth.workload("c1", with_sdf=True)
     _realize_check(w)
