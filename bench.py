@@ -662,7 +662,7 @@ def main():
         out["p50_ms"] = out["serving"]["p50_ms"]
         out["p99_ms"] = out["serving"]["p99_ms"]
     if not args.no_cpu_baseline:
-        n = args.cpu_poses or {"c1": 256, "c2": 2048, "c3": 4096}[args.workload]
+        n = args.cpu_poses or {"c1": 256, "c2": 2048, "c3": 5120}[args.workload]
         out["cpu_baseline"] = cpu_baseline(w, n, samples=16384)
     print(json.dumps(out))
 
