@@ -288,8 +288,9 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
 
 // Cone query (Sec. 4.3's theta_hit test): a query (x, -R n) hits finger f if
 // a bin b set in the finger's merged word(s) at voxel(x) has c_b . q >= cos_hit.
-// Same sweep and block stores as k_query; the set bits of the voxel's entry
-// are tested one by one against the cone.
+// Same sweep and block stores as k_query.  Per point the cone is built once as
+// a bin mask over the bins of its polar band that some finger's entry holds;
+// each finger's test is then one AND with its entry.
 template <int W, int FM>
 __global__ void __launch_bounds__(kQueryThreads)
 k_query_cone(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict__ pts,
@@ -365,20 +366,25 @@ k_query_cone(DevHand H, const uint32_t *__restrict__ merged, const float *__rest
                 }
             }
             const int j2 = 2 * (chunk - blk * 32);
+            // the point's cone as a bin mask over the band's bins that some
+            // finger's entry holds (the per-finger test is then one AND)
+            unsigned long long cone = 0ull;
+            {
+                unsigned long long u = 0ull;
+#pragma unroll
+                for (int f = 0; f < FM; ++f) u |= ent[f];
+                unsigned long long m = u & band;
+                while (m) {
+                    const int b = __ffsll((long long)m) - 1;
+                    m &= m - 1ull;
+                    if (fmaf(cb[3 * b], qx, fmaf(cb[3 * b + 1], qy, cb[3 * b + 2] * qz)) >= cos_hit) cone |= 1ull << b;
+                }
+            }
 #pragma unroll
             for (int f = 0; f < FM; ++f) {
                 if (f >= F) break;
                 if (skip[f] & cbit) continue;  // the ballot would be 0
-                bool hit = false;
-                unsigned long long m = ent[f] & band;
-                while (m) {
-                    const int b = __ffsll((long long)m) - 1;
-                    m &= m - 1ull;
-                    if (fmaf(cb[3 * b], qx, fmaf(cb[3 * b + 1], qy, cb[3 * b + 2] * qz)) >= cos_hit) {
-                        hit = true;
-                        break;
-                    }
-                }
+                const bool hit = (ent[f] & cone) != 0ull;
                 const unsigned long long bm = __ballot(hit);
                 acc[f] = write_lane(acc[f], (uint32_t)bm, j2);
                 acc[f] = write_lane(acc[f], (uint32_t)(bm >> 32), j2 + 1);
