@@ -332,13 +332,15 @@ k_encode(const float *__restrict__ x, int Np, const uint16_t *__restrict__ T, co
 }
 
 // feat = relu(max pre-activation + b2); arg = its point, or 0 where the
-// channel is cut to zero (every point then ties at 0 and the lowest wins)
-__global__ void k_pool_finish(const unsigned long long *__restrict__ keys, int n, const float *__restrict__ P,
+// channel is cut to zero (every point then ties at 0 and the lowest wins).
+// Each key is reset to 0 once read, ready for the next pass.
+__global__ void k_pool_finish(unsigned long long *__restrict__ keys, int n, const float *__restrict__ P,
                               float *__restrict__ feat, int32_t *__restrict__ arg)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const unsigned long long k = keys[i];
+    keys[i] = 0ull;
     float f = 0.0f;
     int32_t a = 0;
     if (k) {
@@ -726,7 +728,8 @@ struct lg_prop {
     void *slab = nullptr;
     float *P, *G, *Mo, *Vo;       // [kNParams]
     uint16_t *T;                  // [kNT]
-    unsigned long long *keys;     // [maxB][256]
+    unsigned long long *keys;     // [maxB][256], all 0 between forward passes
+    bool keys_dirty = false;      // a forward pass stopped between k_encode and k_pool_finish
     float *feat, *ua, *ub, *out;  // [maxB][256] x3, [maxB][152]
     float *dO, *dub, *dua, *dfeat;
     int32_t *arg;                 // [maxB][256]
@@ -764,12 +767,16 @@ lg_status check_batch(const lg_prop *p, const float *x, int B, int Np)
 
 lg_status forward(lg_prop *p, const float *x, int B, int Np, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fill_u64, dim3(blocks((int64_t)B * kH2, 256)), dim3(256), 0, s, p->keys,
-                       (int64_t)B * kH2);
+    // k_pool_finish leaves the keys it read at 0, so the next pass needs no fill
+    if (p->keys_dirty)
+        hipLaunchKernelGGL(k_fill_u64, dim3(blocks((int64_t)p->max_batch * kH2, 256)), dim3(256), 0, s, p->keys,
+                           (int64_t)p->max_batch * kH2);
+    p->keys_dirty = true;
     hipLaunchKernelGGL(k_encode, dim3(blocks(Np, kEncChunk), B), dim3(kEncThreads), 0, s, x, Np, p->T, p->P,
                        p->keys);
     hipLaunchKernelGGL(k_pool_finish, dim3(blocks((int64_t)B * kH2, 256)), dim3(256), 0, s, p->keys, B * kH2, p->P,
                        p->feat, p->arg);
+    if (hipPeekAtLastError() == hipSuccess) p->keys_dirty = false;
     gemm<uint16_t, kEpiBiasRelu>(s, B, kHH, kH2, p->feat, kH2, 1, p->T + kTa, 1, kH2, p->P + kBa, nullptr, 0, p->ua,
                                  kHH);
     gemm<uint16_t, kEpiBiasRelu>(s, B, kHH, kHH, p->ua, kHH, 1, p->T + kTb, 1, kHH, p->P + kBb, nullptr, 0, p->ub,
@@ -875,6 +882,7 @@ lg_status lg_prop_create(const lg_prop_params *params, void *stream, lg_prop **o
     hipLaunchKernelGGL(k_init, dim3(blocks(kNParams, 256)), dim3(256), 0, s, p->P,
                        (uint32_t)params->seed, (uint32_t)(params->seed >> 32));
     hipLaunchKernelGGL(k_refresh_bf16, dim3(blocks(kNT, 256)), dim3(256), 0, s, p->P, p->T);
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks((int64_t)B * kH2, 256)), dim3(256), 0, s, p->keys, (int64_t)B * kH2);
     e = hipMemsetAsync(p->Mo, 0, kNParams * 4, s);
     if (e == hipSuccess) e = hipMemsetAsync(p->Vo, 0, kNParams * 4, s);
     if (e == hipSuccess) e = hipMemsetAsync(p->G, 0, kNParams * 4, s);
