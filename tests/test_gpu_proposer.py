@@ -95,6 +95,27 @@ def test_forward_parity(lg, B, Np):
     prop.release()
 
 
+def test_forward_repeats_across_batch_sizes(lg):
+    """The pooled keys are reset by each pass (no fill kernel): passes of
+    3, 1 and 3 objects on one proposer give every object the same bits, and a
+    fresh proposer with the same seed agrees."""
+    xs = _objects(3, 700, seed=4)
+    x3 = torch.from_numpy(np.stack(xs)).cuda()
+    x1 = x3[:1].contiguous()
+    prop = lg.Proposer(max_batch=4, max_points=700, max_targets=8, seed=21)
+    r1 = {k: v.clone() for k, v in prop.forward(x3).items()}
+    r2 = {k: v.clone() for k, v in prop.forward(x1).items()}
+    r3 = prop.forward(x3)
+    fresh = lg.Proposer(max_batch=4, max_points=700, max_targets=8, seed=21)
+    r4 = fresh.forward(x3)
+    torch.cuda.synchronize()
+    for k in ("out", "feat", "arg"):
+        assert torch.equal(r1[k], r3[k]) and torch.equal(r1[k], r4[k]), k
+        assert torch.equal(r2[k][0], r1[k][0]), k
+    prop.release()
+    fresh.release()
+
+
 def test_backward_parity(lg):
     B, Np = 4, 256
     prop = lg.Proposer(max_batch=4, max_points=Np, max_targets=64, seed=5)
