@@ -593,6 +593,34 @@ def test_place_exhaustive(name):
 # cone query (Sec. 4.3 theta_hit test over the bin centres): stage isolated,
 # bit-exact outside the oracle's flags
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("deg", [10.0, 15.0])
+def test_query_cone_c3_full_shape_as_benchmarked(deg):
+    """The cone launch the benchmark times: C3 at full shape (N = P = 65,536),
+    Morton-ordered points, chunk bounds; 6 sampled poses against the oracle."""
+    import dataclasses
+    import math
+    lg = lgmod()
+    w = synth.workload("c3", samples=4096, with_sdf=False)
+    order = lg.lg_morton_order(w.obj.pts)
+    w = dataclasses.replace(w, obj=dataclasses.replace(w.obj, pts=w.obj.pts[order], nrm=w.obj.nrm[order]))
+    ref = oracle.build_field(w.hand, w.field, flags=False)
+    field = lg.lg_field_import(w.hand, w.field, ref["bits"])
+    cos_hit = float(np.float32(math.cos(math.radians(deg))))
+    P_, N_ = soa(w.obj.pts), soa(w.obj.nrm)
+    db, dc = lg.lg_query_domains_cone(field, P_, N_, dev(w.poses), cos_hit, bounds=lg.lg_chunk_bounds(P_))
+    torch.cuda.synchronize()
+    sel = np.sort(np.random.default_rng(int(deg)).choice(w.poses.shape[0], size=6, replace=False))
+    Q = oracle.query_cone(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses[sel], cos_hit)
+    idx = torch.from_numpy(sel).cuda().long()
+    gb = db[idx].cpu().numpy().view(np.uint32)
+    gc = dc[idx].cpu().numpy().astype(np.int64)
+    assert ((gb ^ Q["dom_bits"]) & ~Q["dom_flag"]).sum() == 0
+    n_flag = int(np.unpackbits(Q["dom_flag"].view(np.uint8)).sum())
+    assert n_flag <= max(2, 1e-3 * len(sel) * w.hand.n_fingers * w.obj.n)
+    assert np.abs(gc - Q["dom_count"].astype(np.int64)).sum() <= n_flag
+    assert int(gc.sum()) > 0
+
+
 @pytest.mark.parametrize("name,deg", [("c1", 15.0), ("c1", 40.0), ("c3", 12.0)])
 def test_query_cone(name, deg):
     import math
