@@ -134,7 +134,8 @@ def lib():
         L.orc_segment_distance.restype = dbl
         L.orc_self_penetration.argtypes = [vp, vp]
         L.orc_self_penetration.restype = dbl
-        L.orc_ik_finger.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_ik_finger.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_capsule_aligned_point.argtypes = [vp, vp, C.c_double, vp, vp, C.c_double, vp, vp, vp]
         L.orc_point_jacobian.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp]
         L.orc_sdf_eval.argtypes = [vp, vp]
         L.orc_sdf_eval.restype = dbl
@@ -145,7 +146,7 @@ def lib():
         L.orc_concave_filter.argtypes = [vp, vp, vp, i32, dbl, i32, dbl, vp, vp, vp]
         L.orc_concave_filter.restype = C.c_int
         L.orc_realize.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, i32, i32, vp, i32, vp,
-                                  u64, C.c_uint32, i64, vp, vp, vp, vp, vp, vp, vp]
+                                  u64, C.c_uint32, i64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_realize.restype = C.c_int
         _lib = L
     return _lib
@@ -194,8 +195,9 @@ def _sdf(sdf) -> _Keep:
 
 
 def _ik(ik) -> _IK:
-    return _IK(int(ik.iters), int(ik.phase1), float(ik.lam), float(ik.beta), float(ik.tol_pos),
-               float(ik.tol_ang), float(ik.margin), int(getattr(ik, "self_collision", 0)))
+    f32 = lambda x: float(np.float32(x))  # the parameters arrive as float32, promoted exactly
+    return _IK(int(ik.iters), int(ik.phase1), f32(ik.lam), f32(ik.beta), f32(ik.tol_pos),
+               f32(ik.tol_ang), f32(ik.margin), int(getattr(ik, "self_collision", 0)))
 
 
 # ---------------------------------------------------------------------------
@@ -547,12 +549,24 @@ def ik_finger(hand, f: int, link: int, p, n, q0, ik) -> dict:
     H = _hand(hand)
     q = _c(q0, np.float64).copy()
     pp, nn = _c(p, np.float64), _c(n, np.float64)
-    err, ang = C.c_double(0), C.c_double(0)
+    err, ang, gap = C.c_double(0), C.c_double(0), C.c_double(0)
     pt, nt = np.zeros(3), np.zeros(3)
     ikp = _ik(ik)
     lib().orc_ik_finger(H.ref, f, link, _p(pp), _p(nn), C.byref(ikp), _p(q), C.byref(err),
-                        C.byref(ang), _p(pt), _p(nt))
-    return {"q": q, "err": err.value, "ang": ang.value, "pt": pt, "nt": nt}
+                        C.byref(ang), _p(pt), _p(nt), C.byref(gap))
+    return {"q": q, "err": err.value, "ang": ang.value, "pt": pt, "nt": nt, "choice_gap": gap.value}
+
+
+def capsule_aligned_point(a, b, r: float, p, n, beta: float) -> dict:
+    """Point of the capsule (axis a-b, radius r) of least |x - p|^2 + beta^2 |nt - n|^2
+    (the hand contact point of the reverse lookup, Sec. 5.5), its outward normal and
+    the tie margin of the choice between distant candidates (+inf: none)."""
+    a, b, p, n = (_c(v, np.float64) for v in (a, b, p, n))
+    pt, nt = np.zeros(3), np.zeros(3)
+    gap = C.c_double(0)
+    lib().orc_capsule_aligned_point(_p(a), _p(b), float(r), _p(p), _p(n), float(beta), _p(pt), _p(nt),
+                                    C.byref(gap))
+    return {"pt": pt, "nt": nt, "gap": gap.value}
 
 
 def point_jacobian(hand, f: int, link: int, q, x) -> np.ndarray:
@@ -619,15 +633,16 @@ def realize(hand, fp, wit, sdf, pts, nrm, poses, set_pt, set_link, sp, acc_list,
     n, J, k = acc.shape[0], hand.n_joints, sp.k
     q = np.zeros((n, J)); q0 = np.zeros((n, J))
     err = np.zeros((n, k)); ang = np.zeros((n, k)); dep = np.zeros(n)
-    val = np.zeros(n, np.uint8); fl = np.zeros(n, np.uint8)
+    val = np.zeros(n, np.uint8); fl = np.zeros(n, np.uint8); mg = np.zeros((n, 3))
     H, Fp, S = _hand(hand), _field(fp), _sdf(sdf)
     ikp = _ik(ik)
     w = None if wit is None else _c(wit, np.int32)
     rc = lib().orc_realize(H.ref, Fp.ref, _p(w), S.ref, _p(pts), _p(nrm), pts.shape[0], _p(poses),
                            poses.shape[0], _p(_c(set_pt, np.int32)), _p(_c(set_link, np.int32)), k, sp.draws,
                            _p(acc), n, C.byref(ikp), int(sp.seed) & 0xFFFFFFFFFFFFFFFF, int(sp.request_id),
-                           int(sp.pose_offset), _p(q), _p(q0), _p(err), _p(ang), _p(dep), _p(val), _p(fl))
+                           int(sp.pose_offset), _p(q), _p(q0), _p(err), _p(ang), _p(dep), _p(val), _p(fl),
+                           _p(mg))
     if rc != 0:
         raise ValueError(f"orc_realize failed ({rc})")
     return {"q": q, "q0": q0, "contact_err": err, "contact_ang": ang, "depth": dep,
-            "valid": val, "rflag": fl}
+            "valid": val, "rflag": fl, "margin": mg}

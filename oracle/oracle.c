@@ -32,6 +32,11 @@
 #define BAND_POS 1e-6   /* m   */
 #define BAND_ANG 1e-6   /* rad */
 #define BAND_VAL 1e-6   /* thresholds (t*, contact error, angle, depth) */
+#define BAND_CHOICE 1e-6 /* m: IK contact-point choice between two distant capsule candidates */
+/* causes of a realize flag (bit mask) */
+#define RF_THRESHOLD 1u /* contact error, angle or depth within BAND_VAL of its threshold */
+#define RF_LOOKUP 2u    /* reverse lookup: voxel face within BAND_POS or bin boundary within BAND_ANG */
+#define RF_CHOICE 4u    /* an IK contact-point choice within BAND_CHOICE of a tie */
 
 #define PURPOSE_JOINT 1u
 #define PURPOSE_DRAW 3u
@@ -1472,16 +1477,22 @@ static void capsule_project(const double *A, const double *Bp, double r, const d
  * r (p - c) + beta^2 n perpendicular to the axis.  Caps (centres A, B):
  * nt = unit r (p - centre) + beta^2 n when it points into the cap's half
  * space.  The candidate of least cost wins (cylinder, then end cap, then
- * start cap on exact ties).                                                 */
+ * start cap on exact ties).
+ * gap (optional): how close the choice is to a tie between two candidates
+ * that are far apart: sqrt(runner-up cost) - sqrt(best cost) in metres, or
+ * +inf when no other candidate lies more than BAND_POS away from the chosen
+ * one in the same metric (a flip between two candidates that nearly coincide
+ * moves the point by less than that).                                      */
 static void capsule_aligned_point(const double *A, const double *Bp, double r, const double *p,
-                                  const double *n, double beta, double *pt, double *nt)
+                                  const double *n, double beta, double *pt, double *nt, double *gap)
 {
     double ab[3] = {Bp[0] - A[0], Bp[1] - A[1], Bp[2] - A[2]};
     double L = sqrt(dot3(ab, ab));
     double ax[3] = {0, 0, 1};
     if (L > 0) for (int a = 0; a < 3; ++a) ax[a] = ab[a] / L;
     double b2 = beta * beta;
-    double best = INFINITY;
+    double cx[3][3], cv[3][3], cc[3];
+    int ok[3] = {1, 0, 0};
     /* cylinder */
     {
         double ap[3] = {p[0] - A[0], p[1] - A[1], p[2] - A[2]};
@@ -1494,14 +1505,12 @@ static void capsule_aligned_point(const double *A, const double *Bp, double r, c
         double va = dot3(v, ax);
         for (int a = 0; a < 3; ++a) v[a] -= va * ax[a];
         normalize_or(v, ax);
-        double x[3], cost = 0;
+        cc[0] = 0;
         for (int a = 0; a < 3; ++a) {
-            x[a] = c[a] + r * v[a];
-            cost += (x[a] - p[a]) * (x[a] - p[a]) + b2 * (v[a] - n[a]) * (v[a] - n[a]);
+            cx[0][a] = c[a] + r * v[a];
+            cv[0][a] = v[a];
+            cc[0] += (cx[0][a] - p[a]) * (cx[0][a] - p[a]) + b2 * (v[a] - n[a]) * (v[a] - n[a]);
         }
-        best = cost;
-        memcpy(pt, x, sizeof x);
-        memcpy(nt, v, sizeof v);
     }
     /* end cap (centre B, half space ax . nt >= 0), then start cap (centre A) */
     for (int cap = 0; cap < 2; ++cap) {
@@ -1513,17 +1522,37 @@ static void capsule_aligned_point(const double *A, const double *Bp, double r, c
         if (!(nv > 1e-300)) continue;
         for (int a = 0; a < 3; ++a) v[a] /= nv;
         if (sg * dot3(v, ax) < 0) continue;
-        double x[3], cost = 0;
+        ok[1 + cap] = 1;
+        cc[1 + cap] = 0;
         for (int a = 0; a < 3; ++a) {
-            x[a] = c[a] + r * v[a];
-            cost += (x[a] - p[a]) * (x[a] - p[a]) + b2 * (v[a] - n[a]) * (v[a] - n[a]);
-        }
-        if (cost < best) {
-            best = cost;
-            memcpy(pt, x, sizeof x);
-            memcpy(nt, v, sizeof v);
+            cx[1 + cap][a] = c[a] + r * v[a];
+            cv[1 + cap][a] = v[a];
+            cc[1 + cap] += (cx[1 + cap][a] - p[a]) * (cx[1 + cap][a] - p[a]) + b2 * (v[a] - n[a]) * (v[a] - n[a]);
         }
     }
+    int w = 0;
+    for (int i = 1; i < 3; ++i)
+        if (ok[i] && cc[i] < cc[w]) w = i;
+    memcpy(pt, cx[w], sizeof cx[w]);
+    memcpy(nt, cv[w], sizeof cv[w]);
+    if (gap) {
+        double g = INFINITY;
+        for (int i = 0; i < 3; ++i) {
+            if (i == w || !ok[i]) continue;
+            double sep = 0;
+            for (int a = 0; a < 3; ++a)
+                sep += (cx[i][a] - cx[w][a]) * (cx[i][a] - cx[w][a]) + b2 * (cv[i][a] - cv[w][a]) * (cv[i][a] - cv[w][a]);
+            if (sqrt(sep) > BAND_POS) g = fmin(g, sqrt(cc[i]) - sqrt(cc[w]));
+        }
+        *gap = g;
+    }
+}
+
+/* exported for the tests: the capsule point of least |x - p|^2 + beta^2 |nt - n|^2 */
+void orc_capsule_aligned_point(const double *A, const double *Bp, double r, const double *p, const double *n,
+                               double beta, double *pt, double *nt, double *gap)
+{
+    capsule_aligned_point(A, Bp, r, p, n, beta, pt, nt, gap);
 }
 
 /* Position Jacobian (3 x d_f, row-major) of a point x fixed to link `link`
@@ -1591,18 +1620,21 @@ typedef struct {
 /* One finger's IK towards one contact.  q_f in/out (finger joints).       */
 void orc_ik_finger(const orc_hand *H, int f, int link, const double *p, const double *n,
                    const orc_ik_params *ik, double *q_f, double *err, double *ang,
-                   double *pt_out, double *nt_out)
+                   double *pt_out, double *nt_out, double *sel_gap)
 {
     const int J = H->n_joints, j0 = finger_first_joint(H, f), d = finger_dof(H, f);
     double *T = (double *)malloc(sizeof(double) * 12 * J);
     double pt[3], nt[3], loc_p[3] = {0, 0, 0}, loc_n[3] = {0, 0, 1};
+    double min_gap = INFINITY; /* closest tie of the contact-point choices made */
     for (int it = 0; it < ik->iters; ++it) {
         orc_fk_finger(H, f, q_f, T);
         const double *Tl = T + 12 * link;
         double A[3], Bp[3], r;
         capsule_world(H, T, link, A, Bp, &r);
         if (it >= ik->phase1 || it == 0) {
-            capsule_aligned_point(A, Bp, r, p, n, ik->beta, pt, nt);
+            double gap;
+            capsule_aligned_point(A, Bp, r, p, n, ik->beta, pt, nt, &gap);
+            if (gap < min_gap) min_gap = gap;
             /* link-frame copy: R^T (x - t), R^T n */
             double dx[3] = {pt[0] - Tl[3], pt[1] - Tl[7], pt[2] - Tl[11]};
             for (int a = 0; a < 3; ++a) {
@@ -1653,6 +1685,7 @@ void orc_ik_finger(const orc_hand *H, int f, int link, const double *p, const do
     *ang = acos(c);
     if (pt_out) memcpy(pt_out, pt, sizeof pt);
     if (nt_out) memcpy(nt_out, nt, sizeof nt);
+    if (sel_gap) *sel_gap = min_gap;
     free(T);
 }
 
@@ -1859,7 +1892,7 @@ int orc_realize(const orc_hand *H, const orc_field_params *fp, const int32_t *wi
                 uint64_t seed, uint32_t request_id, int64_t pose_offset,
                 double *q_out /*[n_acc][J]*/, double *q0_out /*[n_acc][J] opt*/,
                 double *contact_err /*[n_acc][k]*/, double *contact_ang /*[n_acc][k]*/,
-                double *depth, uint8_t *valid, uint8_t *rflag)
+                double *depth, uint8_t *valid, uint8_t *rflag, double *rmargin /*[n_acc][3] opt*/)
 {
     const int J = H->n_joints, F = H->n_fingers, G = fp->grid, B = fp->bins;
     const int64_t G3 = (int64_t)G * G * G;
@@ -1880,6 +1913,7 @@ int orc_realize(const orc_hand *H, const orc_field_params *fp, const int32_t *wi
         double q0[64];
         int fl = 0;
         double worst_err = 0, worst_ang = 0;
+        double m_face = INFINITY, m_bin = INFINITY, m_gap = INFINITY;
         /* contact of each finger (-1: none) */
         int contact_of[8];
         for (int f = 0; f < F; ++f) contact_of[f] = -1;
@@ -1913,9 +1947,13 @@ int orc_realize(const orc_hand *H, const orc_field_params *fp, const int32_t *wi
             /* reverse lookup: witness sample of (l, voxel(p), bin(n)) */
             int32_t w = -1;
             if (wit) {
-                double u[3];
+                double u[3], half_gap;
                 int in = voxel_coords(fp, f, p, u);
-                int b = bin_of(B, cb, n, NULL, NULL);
+                int b = bin_of(B, cb, n, NULL, &half_gap);
+                /* the lookup's discrete choices: a voxel face (window faces
+                 * included) within BAND_POS, a bin boundary within BAND_ANG */
+                for (int c = 0; c < 3; ++c) m_face = fmin(m_face, face_dist(u[c], fp->h));
+                m_bin = fmin(m_bin, half_gap);
                 if (in) {
                     int64_t v = ((int64_t)(int)floor(u[2]) * G + (int)floor(u[1])) * G + (int)floor(u[0]);
                     w = wit[((int64_t)l * G3 + v) * B + b];
@@ -1928,12 +1966,12 @@ int orc_realize(const orc_hand *H, const orc_field_params *fp, const int32_t *wi
                     q[j0 + t] = 0.5 * ((double)H->limits[2 * (j0 + t)] + H->limits[2 * (j0 + t) + 1]);
             }
             for (int t = 0; t < dof; ++t) q0[j0 + t] = q[j0 + t];
-            double err, ang;
-            orc_ik_finger(H, f, l, p, n, ik, q + j0, &err, &ang, NULL, NULL);
+            double err, ang, gap;
+            orc_ik_finger(H, f, l, p, n, ik, q + j0, &err, &ang, NULL, NULL, &gap);
             contact_err[(int64_t)a * k + i] = err;
             contact_ang[(int64_t)a * k + i] = ang;
-            fl |= fabs(err - ik->tol_pos) <= BAND_VAL;
-            fl |= fabs(ang - ik->tol_ang) <= BAND_VAL;
+            m_gap = fmin(m_gap, gap);
+            fl |= (fabs(err - ik->tol_pos) <= BAND_VAL || fabs(ang - ik->tol_ang) <= BAND_VAL) ? RF_THRESHOLD : 0;
             if (err > worst_err) worst_err = err;
             if (ang > worst_ang) worst_ang = ang;
         }
@@ -1951,9 +1989,16 @@ int orc_realize(const orc_hand *H, const orc_field_params *fp, const int32_t *wi
         if (ik->self_collision) dp = fmax(dp, orc_self_penetration(H, T));
         free(T);
         depth[a] = dp;
-        fl |= fabs(dp - ik->margin) <= BAND_VAL;
+        fl |= fabs(dp - ik->margin) <= BAND_VAL ? RF_THRESHOLD : 0;
+        fl |= (m_face < BAND_POS || m_bin < BAND_ANG) ? RF_LOOKUP : 0;
+        fl |= m_gap <= BAND_CHOICE ? RF_CHOICE : 0;
         valid[a] = worst_err <= ik->tol_pos && worst_ang <= ik->tol_ang && dp <= ik->margin;
         if (rflag) rflag[a] = (uint8_t)fl;
+        if (rmargin) {
+            rmargin[3 * a + 0] = m_face;
+            rmargin[3 * a + 1] = m_bin;
+            rmargin[3 * a + 2] = m_gap;
+        }
     }
     return ORC_OK;
 }
