@@ -90,13 +90,15 @@ def lib():
         L = C.CDLL(_LIB)
         vp, i32, i64, u64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
         L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_get_threads.restype = C.c_int
         L.orc_joint_sample.argtypes = [vp, u64, C.c_int, i64, vp]
         L.orc_fk.argtypes = [vp, vp, vp]
         L.orc_fk_finger.argtypes = [vp, C.c_int, vp, vp]
         L.orc_bin_centers.argtypes = [C.c_int, vp]
         L.orc_bin.argtypes = [C.c_int, vp, vp, vp]
         L.orc_bin.restype = C.c_int
-        L.orc_build_field.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_build_field.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i64]
         L.orc_build_field.restype = C.c_int
         L.orc_query.argtypes = [vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp]
         L.orc_query.restype = C.c_int
@@ -123,11 +125,14 @@ def lib():
         L.orc_choose_fingers.restype = C.c_int
         L.orc_unused_joints.argtypes = [vp, C.c_int, u64, C.c_uint32, i64, C.c_int, vp]
         L.orc_place_palm.argtypes = [vp, vp, i32, vp, i32, vp, vp, i32, i32, dbl, dbl, u64, C.c_uint32, i64, vp,
-                                     vp, vp]
+                                     vp, vp, vp, i32]
         L.orc_place_palm.restype = C.c_int
         L.orc_optimize.argtypes = [vp, vp, i32, vp, vp, vp, i32, i32, i32, i32, vp, dbl, i32, dbl, i32, i32, dbl,
                                    u64, C.c_uint32, i64, i32, vp, vp]
         L.orc_optimize.restype = C.c_int
+        L.orc_optimize_outcomes.argtypes = [vp, vp, i32, vp, vp, vp, i32, i32, i64, i32, vp, dbl, i32, dbl, i32, i32,
+                                            dbl, u64, C.c_uint32, i64, i32, i32, vp, vp]
+        L.orc_optimize_outcomes.restype = C.c_int
         L.orc_relink.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, i32, vp, vp, u64, C.c_uint32, i64, vp]
         L.orc_relink.restype = C.c_int
         L.orc_segment_distance.argtypes = [vp, vp, vp, vp]
@@ -201,6 +206,15 @@ def _ik(ik) -> _IK:
 
 
 # ---------------------------------------------------------------------------
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
+
+
 def philox(ctr, key) -> np.ndarray:
     """Philox4x32-10 block for counter ``ctr`` (4 x uint32) and ``key`` (2 x uint32)."""
     c, k = _c(ctr, np.uint32), _c(key, np.uint32)
@@ -241,12 +255,14 @@ def bin_of(B: int, d) -> tuple[int, int, float]:
     return b, b2.value, gap.value
 
 
-def build_field(hand, fp, witness: bool = False, flags: bool = True) -> dict:
+def build_field(hand, fp, witness: bool = False, flags: bool = True, sample_ids=None) -> dict:
     """Per-link voxel x normal-bin bit tables (Alg. 1 as a dense grid cover).
 
     Returns ``bits``/``sure``/``maybe`` uint32 [L, G^3, B/32] and, with
     ``witness``, int32 [L, G^3, B] ``wit``/``wit_lo``/``wit_hi`` (-1 = none),
-    plus ``stats`` = (vectors, in-window, dropped, flagged)."""
+    plus ``stats`` = (vectors, in-window, dropped, flagged).  ``sample_ids``
+    restricts the cover to those joint samples of every finger (default: all
+    ``fp.samples``)."""
     G, B, L = fp.grid, fp.bins, hand.n_joints
     shp = (L, G ** 3, B // 32)
     bits = np.zeros(shp, np.uint32)
@@ -258,8 +274,11 @@ def build_field(hand, fp, witness: bool = False, flags: bool = True) -> dict:
     whi = np.zeros(wshp, np.int32) if (witness and flags) else None
     stats = np.zeros(4, np.int64)
     H, Fp = _hand(hand), _field(fp)
+    ids = None if sample_ids is None else _c(sample_ids, np.int64)
+    if ids is not None and ((ids < 0) | (ids >= fp.samples)).any():
+        raise ValueError("sample id outside 0..samples-1")
     rc = lib().orc_build_field(H.ref, Fp.ref, _p(bits), _p(sure), _p(maybe), _p(wit), _p(wlo),
-                               _p(whi), _p(stats))
+                               _p(whi), _p(stats), _p(ids), 0 if ids is None else len(ids))
     if rc != 0:
         raise ValueError(f"orc_build_field failed ({rc})")
     return {"bits": bits, "sure": sure, "maybe": maybe, "wit": wit, "wit_lo": wlo,
@@ -466,6 +485,37 @@ def optimize(pts, nrm, dom_bits, set_pt, sp, F: int, max_pivots: int = 1000, dom
             "vflag": (np.abs(t - eps) <= BAND).astype(np.uint8)}
 
 
+def optimize_outcomes(pts, nrm, dom_bits, set_pt, sp, F: int, sets, max_pivots: int = 1000, dom_count=None,
+                      palm_pt=None, max_out: int = 64) -> list:
+    """Every outcome of Alg. 2 (Sec. 5.4) the rounding bands admit, for each flat
+    set id in ``sets`` of the drawn ``set_pt`` [P, D, k]: a list of (points
+    [n, k], J [n]) pairs, where n = 0 for a set that is not valid and None
+    when more than ``max_out`` outcomes exist.  ``optimize``'s result is always
+    one of them, and the only one for a set it does not flag."""
+    pts, nrm = _c(pts, np.float32), _c(nrm, np.float32)
+    spt = _c(set_pt, np.int32)
+    P, D, k = spt.shape
+    cnt = _dom_count(dom_count, dom_bits, P, int(F))
+    bits = _c(dom_bits, np.uint32)
+    palm = None if palm_pt is None else _c(palm_pt, np.int32)
+    out = []
+    for s in np.asarray(sets, np.int64):
+        g, d = int(s) // D, int(s) % D
+        opt = np.zeros((max_out, k), np.int32)
+        ot = np.zeros(max_out, np.float64)
+        start = np.ascontiguousarray(spt[g, d])
+        n = lib().orc_optimize_outcomes(_p(pts), _p(nrm), pts.shape[0], _p(bits), _p(cnt), _p(palm), int(F), k, g, d,
+                                        _p(start), float(np.float32(sp.mu)), sp.m_edges,
+                                        float(np.float32(sp.moment_scale)), int(sp.opt_outer), int(sp.opt_inner),
+                                        float(np.float32(sp.opt_sigma)), int(sp.seed) & 0xFFFFFFFFFFFFFFFF,
+                                        int(sp.request_id), int(sp.pose_offset), int(max_pivots), int(max_out),
+                                        _p(opt), _p(ot))
+        if n < -1:
+            raise ValueError("orc_optimize_outcomes: bad parameters")
+        out.append(None if n < 0 else (opt[:n].copy(), ot[:n].copy()))
+    return out
+
+
 def verdicts_palm(pts, nrm, set_pt, palm_pt, sp, max_pivots: int = 1000) -> dict:
     """Verdicts of drawn sets with each pose's palm contact (Sec. 5.1 static
     link) as one more contact: sets of poses with palm_pt >= 0 are scored with
@@ -498,23 +548,26 @@ def _with_k(sp, k: int):
 
 
 def place_palm(palm, sdf, pts, nrm, poses, prob: float, margin: float, seed: int, request_id: int = 0,
-               pose_offset: int = 0) -> dict:
+               pose_offset: int = 0, flip: bool = False) -> dict:
     """Sec. 5.1 static-link placement over ``poses`` [P, 12] (float64 out): the
-    palm poses, palm_pt (i / -1 / -2) and the band flags."""
+    palm poses, palm_pt (i / -1 / -2), the selected point sel_pt (i, or -1)
+    and the band flags (bit 1: rotation branch, bit 2: penetration at the
+    margin).  ``flip`` takes the other rotation branch on bit-1 poses."""
     pts, nrm = _c(pts, np.float32), _c(nrm, np.float32)
     out = np.ascontiguousarray(poses, np.float64).copy()
     P = out.shape[0]
     pp = np.zeros(P, np.int32)
+    sel = np.zeros(P, np.int32)
     fl = np.zeros(P, np.uint8)
     S = _sdf(sdf)
     surf, caps = _c(palm.surf, np.float32), _c(palm.caps, np.float32)
     rc = lib().orc_place_palm(S.ref, _p(surf), surf.shape[0], _p(caps), caps.shape[0], _p(pts), _p(nrm),
                               pts.shape[0], P, float(np.float32(prob)), float(np.float32(margin)),
                               int(seed) & 0xFFFFFFFFFFFFFFFF, int(request_id), int(pose_offset), _p(out), _p(pp),
-                              _p(fl))
+                              _p(fl), _p(sel), int(bool(flip)))
     if rc != 0:
         raise ValueError(f"orc_place_palm failed ({rc})")
-    return {"poses": out, "palm_pt": pp, "pflag": fl}
+    return {"poses": out, "palm_pt": pp, "pflag": fl, "sel_pt": sel}
 
 
 def relink(hand, fp, bits, pts, nrm, poses, set_pt, sp, dom_count=None) -> np.ndarray:

@@ -23,6 +23,10 @@
 #include <string.h>
 #ifdef _OPENMP
 #include <omp.h>
+
+/* threads of the parallel loops (timing at one thread and at all cores) */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
 #endif
 
 #define ORC_OK 0
@@ -307,7 +311,8 @@ static inline void wmin(int32_t *w, int64_t idx, int32_t s)
 
 int orc_build_field(const orc_hand *H, const orc_field_params *fp,
                     uint32_t *bits, uint32_t *sure, uint32_t *maybe,
-                    int32_t *wit, int32_t *wit_lo, int32_t *wit_hi, int64_t *stats)
+                    int32_t *wit, int32_t *wit_lo, int32_t *wit_hi, int64_t *stats,
+                    const int64_t *sample_ids /* NULL: samples 0..S-1 */, int64_t n_ids)
 {
     const int G = fp->grid, B = fp->bins, J = H->n_joints;
     if (G <= 0 || (B != 32 && B != 64) || fp->h <= 0 || fp->samples <= 0) return ORC_EINVAL;
@@ -331,7 +336,9 @@ int orc_build_field(const orc_hand *H, const orc_field_params *fp,
         const int j0 = finger_first_joint(H, f);
         double q[32], T[12 * 64];
         const int64_t lbase = (int64_t)l * G3;
-        for (int64_t s = 0; s < fp->samples; ++s) {
+        const int64_t n_s = sample_ids ? n_ids : fp->samples;
+        for (int64_t si = 0; si < n_s; ++si) {
+            const int64_t s = sample_ids ? sample_ids[si] : si;
             orc_joint_sample(H, fp->seed, f, s, q);
             orc_fk_finger(H, f, q, T);
             (void)j0;
@@ -1057,7 +1064,9 @@ static void rot_min(const double *a, const double *b, double *R)
     for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0 ? 1.0 : 0.0) + K[i] + K2[i] * k;
 }
 
-void orc_rot_align(const double *a_in, const double *b_in, double *R, int *flag)
+/* flip = 1 takes the other branch of a rotation whose cosine is inside the
+ * branch band (an implementation in other precision may take it) */
+static void rot_align_pick(const double *a_in, const double *b_in, double *R, int *flag, int flip)
 {
     double a[3], b[3];
     const double na = sqrt(dot3(a_in, a_in)), nb = sqrt(dot3(b_in, b_in));
@@ -1066,8 +1075,9 @@ void orc_rot_align(const double *a_in, const double *b_in, double *R, int *flag)
         b[i] = b_in[i] / nb;
     }
     const double c = dot3(a, b);
-    if (flag) *flag = fabs(c + 0.9999) <= 1e-5;
-    if (c > -0.9999) {
+    const int band = fabs(c + 0.9999) <= 1e-5;
+    if (flag) *flag = band;
+    if ((c > -0.9999) != (flip && band)) {
         rot_min(a, b, R);
         return;
     }
@@ -1080,6 +1090,11 @@ void orc_rot_align(const double *a_in, const double *b_in, double *R, int *flag)
     double Rm[9];
     rot_min(na2, b, Rm);
     mat3_mul(Rm, Rh, R);
+}
+
+void orc_rot_align(const double *a_in, const double *b_in, double *R, int *flag)
+{
+    rot_align_pick(a_in, b_in, R, flag, 0);
 }
 
 int orc_place_exhaustive(const orc_hand *H, const orc_field_params *fp, const float *pts, const float *nrm,
@@ -1158,13 +1173,16 @@ double orc_sdf_eval(const orc_sdf *S, const double *y);
  * (g, b, PURPOSE_PALM, request_id), b = 0, 1, key = seed: u01(w0) < prob
  * selects the pose, w1 the palm sample, w2 the object point, w3 the roll
  * psi = 2 pi u01(w3).  palm_pt[g] = i (accepted), -1 (pose left unchanged),
- * -2 (rejected; its palm pose is still written).  flag: the rotation's
- * branch band, or a penetration within BAND_VAL of margin, or u01(w0)
- * within BAND_VAL of prob. */
+ * -2 (rejected; its palm pose is still written); sel_pt[g] (optional) = i
+ * for a selected pose, else -1.  flag bits: 1 = the rotation's cosine in its
+ * branch band, 2 = a penetration within BAND_VAL of margin.  The selection
+ * u01(w0) < prob is exact in float32 and double alike (u01 has 24 bits and
+ * prob arrives as float32), so it carries no band.  flip = 1 takes the other
+ * rotation branch on the poses of flag bit 1. */
 int orc_place_palm(const orc_sdf *S, const float *palm_surf, int32_t n_surf, const float *palm_caps, int32_t n_caps,
                    const float *pts, const float *nrm, int32_t n_points, int32_t n_poses, double prob, double margin,
                    uint64_t seed, uint32_t request_id, int64_t pose_offset, double *poses /*[P][12] in/out*/,
-                   int32_t *palm_pt, uint8_t *flag)
+                   int32_t *palm_pt, uint8_t *flag, int32_t *sel_pt, int32_t flip)
 {
     if (n_points <= 0 || n_poses < 0 || n_surf <= 0 || n_caps < 0 || !(prob >= 0.0)) return ORC_EINVAL;
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
@@ -1175,7 +1193,8 @@ int orc_place_palm(const orc_sdf *S, const float *palm_surf, int32_t n_surf, con
             uint32_t ctr[4] = {(uint32_t)(pose_offset + g), (uint32_t)b, PURPOSE_PALM, request_id};
             orc_philox4x32_10(ctr, key, w + 4 * b);
         }
-        int fl = fabs(u01(w[0]) - prob) <= BAND_VAL;
+        int fl = 0;
+        if (sel_pt) sel_pt[g] = -1;
         if (!(u01(w[0]) < prob)) {
             palm_pt[g] = -1;
             if (flag) flag[g] = (uint8_t)fl;
@@ -1192,8 +1211,9 @@ int orc_place_palm(const orc_sdf *S, const float *palm_surf, int32_t n_surf, con
         const double a[3] = {nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2]};
         double R0[9], Rr[9], R[9];
         int rf = 0;
-        orc_rot_align(a, b, R0, &rf);
-        fl |= rf;
+        rot_align_pick(a, b, R0, &rf, flip);
+        fl |= rf ? 1 : 0;
+        if (sel_pt) sel_pt[g] = (int32_t)i;
         const double cs = cos(psi), sn = sin(psi);
         const double K[9] = {0, -b[2], b[1], b[2], 0, -b[0], -b[1], b[0], 0};
         for (int r = 0; r < 3; ++r)
@@ -1228,7 +1248,7 @@ int orc_place_palm(const orc_sdf *S, const float *palm_surf, int32_t n_surf, con
                 if (v > depth) depth = v;
             }
         }
-        fl |= fabs(depth - margin) <= BAND_VAL;
+        fl |= fabs(depth - margin) <= BAND_VAL ? 2 : 0;
         palm_pt[g] = depth <= margin ? (int32_t)i : -2;
         if (flag) flag[g] = (uint8_t)fl;
     }
@@ -1384,6 +1404,181 @@ int orc_optimize(const float *pts, const float *nrm, int32_t n_points, const uin
         oflag[s] = (uint8_t)fl;
     }
     return ORC_OK;
+}
+
+/* Every outcome of Alg. 2 on one set that the rounding bands admit.  Where   */
+/* orc_optimize takes a decision inside a band (a runner-up domain point      */
+/* within OPT_BAND of the nearest, or a candidate whose J lies within 1e-10   */
+/* of the tie threshold min + OPT_TAU), an implementation in other precision  */
+/* may take the other side; this walks every such side: each admissible      */
+/* projection of each candidate, and each candidate that can be the first     */
+/* within the threshold.  The outcomes (final points and J) are collected,    */
+/* duplicates removed.  orc_optimize's own result is one of them; for a set   */
+/* it does not flag it is the only one.                                       */
+typedef struct {
+    const float *pts, *nrm;
+    int32_t n_points;
+    const uint32_t *dom_bits;
+    const int32_t *fing;
+    int64_t g, gpose;
+    int d, k, kc, n_outer, n_inner, m_edges, max_pivots;
+    double mu, rho, sigma;
+    uint64_t seed;
+    uint32_t request_id;
+    int max_out, n_out, overflow;
+    int32_t *out_pt;
+    double *out_t;
+} opt_walk;
+
+/* admissible projections of y onto the domain: the nearest point and every
+ * other within OPT_BAND of its distance, nearest first; returns the count */
+static int project_admissible(const float *pts, int32_t n_points, const uint32_t *dom, const double *y,
+                              int64_t *idx, int max_idx)
+{
+    const int64_t NW = (n_points + 31) / 32;
+    double bd = INFINITY;
+    int64_t best = -1;
+    for (int64_t w = 0; w < NW; ++w)
+        for (int b = 0; b < 32; ++b) {
+            if (!((dom[w] >> b) & 1u)) continue;
+            const int64_t i = w * 32 + b;
+            if (i >= n_points) break;
+            double dd = 0.0;
+            for (int a = 0; a < 3; ++a) dd += ((double)pts[3 * i + a] - y[a]) * ((double)pts[3 * i + a] - y[a]);
+            if (sqrt(dd) < bd) { bd = sqrt(dd); best = i; }
+        }
+    if (best < 0) return 0;
+    int n = 0;
+    idx[n++] = best;
+    for (int64_t w = 0; w < NW; ++w)
+        for (int b = 0; b < 32; ++b) {
+            if (!((dom[w] >> b) & 1u)) continue;
+            const int64_t i = w * 32 + b;
+            if (i >= n_points) break;
+            if (i == best) continue;
+            double dd = 0.0;
+            for (int a = 0; a < 3; ++a) dd += ((double)pts[3 * i + a] - y[a]) * ((double)pts[3 * i + a] - y[a]);
+            if (sqrt(dd) - bd <= OPT_BAND && n < max_idx) idx[n++] = i;
+        }
+    return n;
+}
+
+static void opt_walk_step(opt_walk *W, int r, int i, int32_t *sp, double *p, double *n, double J)
+{
+    if (W->overflow) return;
+    if (r == W->n_outer) {
+        for (int o = 0; o < W->n_out; ++o) {
+            int same = 1;
+            for (int c = 0; c < W->k; ++c) same &= W->out_pt[o * W->k + c] == sp[c];
+            if (same && W->out_t[o] == J) return;
+        }
+        if (W->n_out == W->max_out) { W->overflow = 1; return; }
+        memcpy(W->out_pt + W->n_out * W->k, sp, sizeof(int32_t) * W->k);
+        W->out_t[W->n_out++] = J;
+        return;
+    }
+    const int nr = i + 1 == W->k ? r + 1 : r, ni = i + 1 == W->k ? 0 : i + 1;
+    const int64_t NW = (W->n_points + 31) / 32;
+    const uint32_t *dom = W->dom_bits + (int64_t)W->fing[i] * NW; /* dom_bits starts at pose g */
+    double tx[3], ty[3];
+    duff_basis(n + 3 * i, tx, ty);
+    /* candidates with their admissible projections and criterion values */
+    enum { MAXALT = 4 };
+    int64_t alt[64][MAXALT];
+    double Jalt[64][MAXALT];
+    int nalt[64];
+    for (int j = 0; j < W->n_inner; ++j) {
+        double dx, dy, y[3];
+        opt_noise(W->seed, W->request_id, W->gpose, W->d, (uint32_t)((r * W->k + i) * W->n_inner + j), W->sigma,
+                  &dx, &dy);
+        for (int a = 0; a < 3; ++a) y[a] = p[3 * i + a] + dx * tx[a] + dy * ty[a];
+        nalt[j] = project_admissible(W->pts, W->n_points, dom, y, alt[j], MAXALT);
+        if (nalt[j] == 0) { W->overflow = 1; return; } /* an empty domain: not a valid set */
+        for (int v = 0; v < nalt[j]; ++v) {
+            double pc[3 * 16], nc[3 * 16];
+            memcpy(pc, p, sizeof(double) * 3 * W->kc);
+            memcpy(nc, n, sizeof(double) * 3 * W->kc);
+            for (int a = 0; a < 3; ++a) {
+                pc[3 * i + a] = W->pts[3 * alt[j][v] + a];
+                nc[3 * i + a] = W->nrm[3 * alt[j][v] + a];
+            }
+            int st, pv;
+            Jalt[j][v] = orc_set_tstar(W->kc, pc, nc, W->mu, W->m_edges, W->rho, W->max_pivots, &st, &pv);
+            if (st != 0) Jalt[j][v] = INFINITY;
+        }
+    }
+    /* every combination of projections (an odometer over the candidates) */
+    int pick[64] = {0};
+    for (;;) {
+        double mn = INFINITY;
+        for (int j = 0; j < W->n_inner; ++j) mn = fmin(mn, Jalt[j][pick[j]]);
+        const double thr = mn + OPT_TAU;
+        for (int j = 0; j < W->n_inner; ++j) {
+            const double v = Jalt[j][pick[j]];
+            /* j may be chosen if it can fall within the threshold and every earlier
+             * candidate can fall outside it */
+            if (!(v <= thr || (isfinite(mn) && fabs(v - thr) <= 1e-10))) continue;
+            const int64_t q = alt[j][pick[j]];
+            int32_t sp2[16];
+            double p2[3 * 16], n2[3 * 16];
+            memcpy(sp2, sp, sizeof(int32_t) * W->k);
+            memcpy(p2, p, sizeof(double) * 3 * W->kc);
+            memcpy(n2, n, sizeof(double) * 3 * W->kc);
+            sp2[i] = (int32_t)q;
+            for (int a = 0; a < 3; ++a) {
+                p2[3 * i + a] = W->pts[3 * q + a];
+                n2[3 * i + a] = W->nrm[3 * q + a];
+            }
+            opt_walk_step(W, nr, ni, sp2, p2, n2, v);
+            if (!(v > thr || (isfinite(mn) && fabs(v - thr) <= 1e-10))) break; /* j is surely within: no later pick */
+        }
+        int j = 0;
+        while (j < W->n_inner && ++pick[j] == nalt[j]) pick[j++] = 0;
+        if (j == W->n_inner) break;
+    }
+    (void)J;
+}
+
+/* Outcomes of Alg. 2 for set (g, d) started from set_pt0 [k] (the draw).  */
+/* Returns the number of outcomes written to out_pt [max_out][k] and out_t  */
+/* [max_out], 0 for a set that is not valid, -1 when more than max_out.     */
+int orc_optimize_outcomes(const float *pts, const float *nrm, int32_t n_points, const uint32_t *dom_bits,
+                          const uint32_t *dom_count, const int32_t *palm_pt, int32_t F, int32_t k, int64_t g,
+                          int32_t d, const int32_t *set_pt0, double mu, int32_t m_edges, double rho, int32_t n_outer,
+                          int32_t n_inner, double sigma, uint64_t seed, uint32_t request_id, int64_t pose_offset,
+                          int32_t max_pivots, int32_t max_out, int32_t *out_pt, double *out_t)
+{
+    const int64_t NW = (n_points + 31) / 32;
+    if (k <= 0 || k > 8 || k > F || n_outer < 0 || n_inner < 1 || n_inner > 64 || !(sigma >= 0.0) || max_out < 1)
+        return -2;
+    int valid = 1;
+    for (int i = 0; i < k; ++i) valid &= set_pt0[i] >= 0;
+    int32_t fing[8];
+    if (valid) valid = orc_choose_fingers(F, dom_count + g * F, k, seed, request_id, pose_offset + g, d, fing);
+    if (!valid) return 0;
+    opt_walk W = {pts, nrm, n_points, dom_bits + g * F * NW, fing, g, pose_offset + g, d, k,
+                  k + ((palm_pt && palm_pt[g] >= 0) ? 1 : 0), n_outer, n_inner, m_edges, max_pivots, mu, rho, sigma,
+                  seed, request_id, max_out, 0, 0, out_pt, out_t};
+    double p[3 * 16], n[3 * 16];
+    int32_t sp[16];
+    for (int i = 0; i < W.kc; ++i) {
+        const int64_t idx = i < k ? set_pt0[i] : palm_pt[g];
+        if (i < k) sp[i] = set_pt0[i];
+        for (int a = 0; a < 3; ++a) {
+            p[3 * i + a] = pts[3 * idx + a];
+            n[3 * i + a] = nrm[3 * idx + a];
+        }
+    }
+    int st, pv;
+    double J = orc_set_tstar(W.kc, p, n, mu, m_edges, rho, max_pivots, &st, &pv);
+    if (st != 0) J = INFINITY;
+    if (n_outer == 0) {
+        out_t[0] = J;
+        memcpy(out_pt, sp, sizeof(int32_t) * k);
+        return 1;
+    }
+    opt_walk_step(&W, 0, 0, sp, p, n, J);
+    return W.overflow ? -1 : W.n_out;
 }
 
 /* Link of every contact of every valid set, picked as in orc_draw with the  */

@@ -6,9 +6,11 @@ are fed to the GPU.  Bars: for every set the oracle does not flag (a
 projection whose runner-up domain point is within 1e-7 m, or a candidate
 criterion value within 1e-10 of the tie threshold), the optimised point
 indices are identical and t* agrees to 1e-9; verdicts are identical outside
-|t* - eps| <= 1e-6; links follow the draw bar (<= 1e-4 of entries, from
-voxel/bin rounding bands).  Flagged sets are counted (a decision chain of
-n_outer * k * n_inner projections per set makes them a few percent).
+|t* - eps| <= 1e-6.  A flagged set (a decision chain of n_outer * k * n_inner
+projections per set makes them a few percent) must end on one of the outcomes
+the oracle reaches by taking either side of each near-tie, at that outcome's
+t*.  Links of the final points follow the draw bar (<= 1e-4 of entries, from
+voxel/bin rounding bands).
 """
 import dataclasses
 
@@ -30,6 +32,27 @@ def _gpu():
     torch.cuda.set_device(0)
 
 
+def check_flagged_outcomes(w, sp, Q, d_spt, sets, spt, tst, ver, palm_pt=None):
+    """Sets the oracle flags (a near-tie somewhere in their Alg. 2 chain): the
+    GPU's final points must be one of the outcomes the oracle reaches by taking
+    either side of every near-tie, with t* within 1e-9 of that outcome's and
+    the verdict of that t* (outside |t* - eps| <= 1e-6)."""
+    k = sp.k
+    eps = float(np.float32(sp.eps))
+    outs = oracle.optimize_outcomes(w.obj.pts, w.obj.nrm, Q["dom_bits"], d_spt, sp, w.hand.n_fingers, sets,
+                                    dom_count=Q["dom_count"], palm_pt=palm_pt, max_out=256)
+    for s, o in zip(sets, outs):
+        assert o is not None, f"set {s}: more than 256 admissible outcomes"
+        pts_o, t_o = o
+        hit = np.flatnonzero((pts_o == spt.reshape(-1, k)[s]).all(-1))
+        assert len(hit) > 0, f"set {s}: GPU points {spt.reshape(-1, k)[s]} not among {pts_o.tolist()}"
+        t = t_o[hit]
+        near = np.abs(t - tst[s]) <= 1e-9
+        assert near.any(), (s, tst[s], t)
+        tt = t[near][0]
+        assert abs(tt - eps) <= 1e-6 or ver[s] == (tt <= eps)
+
+
 def _opt_check(w, sp, max_flag_frac=0.08):
     lg = lgmod()
     ref = oracle.build_field(w.hand, w.field, flags=False)
@@ -46,8 +69,6 @@ def _opt_check(w, sp, max_flag_frac=0.08):
     d_spt, _ = oracle.draw(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses, Q["dom_bits"],
                            Q["dom_count"], sp)
     O = oracle.optimize(w.obj.pts, w.obj.nrm, Q["dom_bits"], d_spt, sp, w.hand.n_fingers, dom_count=Q["dom_count"])
-    o_sln = oracle.relink(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses, O["set_pt"], sp,
-                          dom_count=Q["dom_count"])
     P, D, k = spt.shape
     valid = (d_spt >= 0).all(-1).reshape(-1)
     flag = O["oflag"].astype(bool)
@@ -59,8 +80,12 @@ def _opt_check(w, sp, max_flag_frac=0.08):
     assert np.allclose(tst[ok], O["tstar"][ok], atol=1e-9, rtol=0)
     vf = O["vflag"].astype(bool)
     assert ((ver != O["verdict"]) & ok & ~vf).sum() == 0
+    check_flagged_outcomes(w, sp, Q, d_spt, np.flatnonzero(valid & flag), spt, tst, ver)
     assert (spt.reshape(-1, k)[~valid] == -1).all() and np.isnan(tst[~valid]).all()
-    mis = (sln.reshape(-1, k) != o_sln.reshape(-1, k))[ok]
+    # links of the final points (the GPU's own, so flagged sets are covered too)
+    o_sln = oracle.relink(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses, spt, sp,
+                          dom_count=Q["dom_count"])
+    mis = (sln.reshape(-1, k) != o_sln.reshape(-1, k))[valid]
     assert mis.sum() <= max(1, 1e-4 * mis.size)
     assert (acc == np.flatnonzero(ver)).all()
     return O, ver, d_spt

@@ -3,8 +3,10 @@ oracle, through the C ABI: palm placements, then the search with each pose's
 palm contact as one more fixed contact (verdicts and Alg. 2).
 
 Bars: placements within 2e-5 of the FP64 construction and palm_pt exact
-outside the oracle's flags (rotation branch, selection or penetration within
-1e-6 of its threshold); unselected poses untouched; draws bit-exact; verdicts
+outside the oracle's flags; a pose whose penetration is within 1e-6 of the
+margin keeps or rejects the oracle's point, one whose alignment cosine is in
+the rotation's branch band matches one of the two branches; unselected poses
+untouched; draws bit-exact; verdicts
 exact outside |t* - eps| <= 1e-6, t* within 1e-9; Alg. 2 at its own bar.
 """
 import dataclasses
@@ -14,6 +16,7 @@ import pytest
 
 import oracle
 import synth
+from tests.test_gpu_optimize import check_flagged_outcomes
 from tests.test_gpu_parity import dev, lgmod, soa
 
 pytestmark = pytest.mark.gpu
@@ -50,14 +53,31 @@ def test_place_palm(name):
     w, palm, ref, field, poses, pp, O, _ = _placed(name, 2048, **kw)
     g_pp = pp.cpu().numpy()
     g_poses = poses.cpu().numpy().astype(np.float64)
-    ok = ~O["pflag"].astype(bool)
+    fl = O["pflag"]
+    ok = fl == 0
     assert ok.mean() > 0.99
     assert (g_pp[ok] == O["palm_pt"][ok]).all()
-    sel = O["palm_pt"] != -1
+    sel = O["sel_pt"] >= 0
+    assert ((O["palm_pt"] != -1) == sel).all()
     assert 0.4 < sel.mean() < 0.6
+    assert (g_pp[~sel] == -1).all()
     np.testing.assert_array_equal(g_poses[~sel], w.poses[~sel].astype(np.float64))
-    err = np.abs(g_poses[sel & ok] - O["poses"][sel & ok])
+    rot = (fl & 1) != 0
+    err = np.abs(g_poses[sel & ~rot] - O["poses"][sel & ~rot])
     assert err.max() <= 2e-5, err.max()
+    # a penetration at the margin: the GPU keeps or rejects the same point
+    pen = (fl == 2)
+    assert ((g_pp[pen] == O["sel_pt"][pen]) | (g_pp[pen] == -2)).all()
+    # a cosine in the rotation's branch band: the pose of one of the two branches,
+    # with that branch's outcome
+    if rot.any():
+        A = oracle.place_palm(palm, w.sdf, w.obj.pts, w.obj.nrm, w.poses, 0.5, 0.002, 9, request_id=2,
+                              pose_offset=5, flip=True)
+        for g in np.flatnonzero(rot):
+            e = [np.abs(g_poses[g] - B["poses"][g]).max() for B in (O, A)]
+            assert min(e) <= 2e-5, (g, e)
+            B = (O, A)[int(e[1] < e[0])]
+            assert g_pp[g] == B["palm_pt"][g] or ((B["pflag"][g] & 2) and g_pp[g] in (B["sel_pt"][g], -2))
     if name == "c3":
         assert (O["palm_pt"] == -2).any()
 
@@ -119,7 +139,8 @@ def test_optimize_with_palm_contacts():
     assert same[ok].all()
     assert np.allclose(tst[ok], Opt["tstar"][ok], atol=1e-9, rtol=0)
     assert ((ver != Opt["verdict"]) & ok & ~Opt["vflag"].astype(bool)).sum() == 0
-
+    check_flagged_outcomes(dataclasses.replace(w, poses=p32), sp, Q, d_spt, np.flatnonzero(valid & flag), spt, tst,
+                           ver, palm_pt=o_pp)
 
 def test_pipeline_with_palm_contacts():
     from paper_2511_07418_amd.pipeline import Pipeline

@@ -80,7 +80,10 @@ def test_forward_parity(lg, B, Np):
         assert np.all(np.abs(picked - e["feat"]) <= 2.0 * flip)
         # exact argmax wherever the best point leads by more than FP32 accumulation noise;
         # a rounding flip of one intermediate may still move a few (counted)
-        clear = (e["gap"] * np.abs(e["feat"]) > 2.0 * accum) & (e["feat"] > 0.0)
+        # (a channel with a single point has no runner-up: gap = inf, a clear lead)
+        lead = np.full_like(e["feat"], np.inf)
+        np.multiply(e["gap"], np.abs(e["feat"]), out=lead, where=np.isfinite(e["gap"]))
+        clear = (lead > 2.0 * accum) & (e["feat"] > 0.0)
         moved += int((arg[b][clear] != e["arg"][clear]).sum())
         zero = e["feat"] <= 0.0       # every point cut to 0: the tie goes to the lowest index
         np.testing.assert_array_equal(arg[b][zero], 0)

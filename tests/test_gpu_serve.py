@@ -7,7 +7,8 @@
 * admission by the HBM budget: a request larger than the budget is rejected
   with LG_EBUDGET; with room for one request at a time, requests are admitted
   in order as memory frees up;
-* cancellation of a queued request.
+* cancellation of a queued request;
+* one served request against the FP64 oracle (accepted ids and valid count).
 """
 import numpy as np
 import pytest
@@ -130,3 +131,52 @@ def test_serve_with_realize(env):
     torch.cuda.synchronize()
     assert (r["n_acc"], r["n_valid"]) == (pipe.n_acc(), pipe.valid_count())
     srv.destroy()
+
+
+def _splitmix64(z: int) -> int:
+    """The splitmix64 output function (Steele, Lea and Flood, OOPSLA 2014)."""
+    m = (1 << 64) - 1
+    z = (z + 0x9E3779B97F4A7C15) & m
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31)
+
+
+def test_served_request_matches_oracle(env):
+    """One c1 request served (chunked, on the server's stream) against the FP64
+    oracle on the same field: the accepted (pose, draw) ids are the oracle's
+    (count and order-independent digest: the sum of splitmix64 of
+    request_id << 40 ^ id), and the valid count is the oracle's up to the
+    sets its realize flags.  The request's poses are those whose domains the
+    oracle does not flag, so no accepted set is tainted upstream."""
+    import dataclasses
+
+    import oracle
+    lg = env[0]
+    w = synth.workload("c1", n_poses=400, with_sdf=True)
+    ref = oracle.build_field(w.hand, w.field, witness=True, flags=False)
+    Q = oracle.query(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses, flags=True)
+    clean = ~(Q["dom_flag"].reshape(len(w.poses), -1) != 0).any(1)
+    poses = np.ascontiguousarray(w.poses[clean])
+    sp = dataclasses.replace(w.search, request_id=11)
+    Q = oracle.query(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, poses, flags=True)
+    assert (Q["dom_flag"] == 0).all()
+    spt, sln = oracle.draw(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, poses, Q["dom_bits"],
+                           Q["dom_count"], sp)
+    V = oracle.verdicts(w.obj.pts, w.obj.nrm, spt, sp)
+    assert V["vflag"].sum() == 0
+    acc = oracle.compact(V["verdict"])
+    R = oracle.realize(w.hand, w.field, ref["wit"], w.sdf, w.obj.pts, w.obj.nrm, poses, spt.reshape(-1, sp.k),
+                       sln.reshape(-1, sp.k), sp, acc, w.ik)
+    want_hash = 0
+    for i in acc:
+        want_hash = (want_hash + _splitmix64((11 << 40) ^ int(i))) & ((1 << 64) - 1)
+    field = lg.lg_field_import(w.hand, w.field, ref["bits"], ref["wit"])
+    srv = lg.Server(budget_bytes=1 << 30, max_active=2, chunk_poses=96)
+    req, keep = srv.make_request(field, w.obj.pts, w.obj.nrm, poses, sp, request_id=11, ik=w.ik, sdf=w.sdf)
+    r = srv.wait(srv.submit(req), 60.0)
+    srv.destroy()
+    assert r["state"] == lg.LG_REQ_DONE
+    assert len(acc) > 50 and R["valid"].sum() > 0
+    assert (r["n_acc"], r["acc_hash"]) == (len(acc), want_hash)
+    assert abs(r["n_valid"] - int(R["valid"].sum())) <= int((R["rflag"] != 0).sum())

@@ -257,3 +257,22 @@ def test_draw_uniformity_chi_square(c1_small):
     chi2 = ((counts - e) ** 2 / e).sum()
     dof = cnt - 1
     assert chi2 < dof + 5 * math.sqrt(2 * dof)
+
+
+def test_field_over_a_subset_of_joint_samples():
+    """The cover restricted to a subset of joint samples is contained in the
+    full cover (bits and sure bits), its smallest reaching sample is never
+    below the full cover's, and the subset of every sample is the full cover."""
+    w = synth.workload("c1", n_poses=8)
+    full = oracle.build_field(w.hand, w.field, witness=True)
+    ids = np.sort(np.random.default_rng(1).choice(w.field.samples, 500, replace=False))
+    sub = oracle.build_field(w.hand, w.field, witness=True, sample_ids=ids)
+    assert ((sub["bits"] & ~full["bits"]) == 0).all() and ((sub["sure"] & ~full["sure"]) == 0).all()
+    assert (sub["bits"] != full["bits"]).any()
+    h = sub["wit"] >= 0
+    assert (full["wit"][h] <= sub["wit"][h]).all()
+    assert np.isin(sub["wit"][h], ids).all()
+    every = oracle.build_field(w.hand, w.field, witness=True, sample_ids=np.arange(w.field.samples))
+    assert (every["bits"] == full["bits"]).all() and (every["wit"] == full["wit"]).all()
+    with pytest.raises(ValueError):
+        oracle.build_field(w.hand, w.field, sample_ids=[w.field.samples])

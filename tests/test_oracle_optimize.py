@@ -161,3 +161,59 @@ def test_relink_matches_draw_links_for_unmoved_sets(c1):
     w, fld, q, spt, sln = c1
     np.testing.assert_array_equal(
         oracle.relink(w.hand, w.field, fld["bits"], w.obj.pts, w.obj.nrm, w.poses, spt, w.search), sln)
+
+
+def test_outcomes_hold_the_oracle_result(c1):
+    """The enumeration of admissible outcomes (each near-tie taken both ways)
+    contains optimize's own result for every set, and it is the only outcome
+    of every set optimize does not flag."""
+    w, fld, q, spt, _ = c1
+    sp = dataclasses.replace(w.search, opt_outer=2, opt_inner=8, opt_sigma=0.004)
+    O = oracle.optimize(w.obj.pts, w.obj.nrm, q["dom_bits"], spt, sp, w.hand.n_fingers, dom_count=q["dom_count"])
+    k = sp.k
+    valid = np.flatnonzero((spt >= 0).all(-1).reshape(-1))
+    sets = valid[:: max(1, len(valid) // 160)]
+    outs = oracle.optimize_outcomes(w.obj.pts, w.obj.nrm, q["dom_bits"], spt, sp, w.hand.n_fingers, sets,
+                                    dom_count=q["dom_count"])
+    for s, o in zip(sets, outs):
+        assert o is not None
+        pts_o, t_o = o
+        mine = O["set_pt"].reshape(-1, k)[s]
+        hit = (pts_o == mine).all(-1) & (t_o == O["tstar"][s])
+        assert hit.any(), s
+        if not O["oflag"][s]:
+            assert len(t_o) == 1
+    # an invalid draw has no outcome
+    bad = np.flatnonzero(~(spt >= 0).all(-1).reshape(-1))
+    if len(bad):
+        assert len(oracle.optimize_outcomes(w.obj.pts, w.obj.nrm, q["dom_bits"], spt, sp, w.hand.n_fingers,
+                                            bad[:1], dom_count=q["dom_count"])[0][1]) == 0
+
+
+def test_outcomes_of_exact_projection_ties(c1):
+    """Every object point given an exact twin (a copy at index i + N, in the same
+    domains): every projection is then an exact tie, optimize takes the lower
+    index, and the admissible outcomes of one round are exactly the 2^k sets
+    that replace any subset of its final points by their twins, at one J."""
+    w, fld, q, spt, _ = c1
+    N = w.obj.n
+    pts2 = np.concatenate([w.obj.pts, w.obj.pts])
+    nrm2 = np.concatenate([w.obj.nrm, w.obj.nrm])
+    P, F = q["dom_count"].shape
+    nw = (N + 31) // 32
+    assert N % 32 == 0
+    bits2 = np.concatenate([q["dom_bits"], q["dom_bits"]], axis=-1)          # [P][F][2 nw]
+    sp = dataclasses.replace(w.search, opt_outer=1, opt_inner=4, opt_sigma=0.004)
+    k = sp.k
+    O = oracle.optimize(pts2, nrm2, bits2, spt, sp, F, dom_count=q["dom_count"])
+    valid = np.flatnonzero((spt >= 0).all(-1).reshape(-1))
+    sets = valid[:24]
+    outs = oracle.optimize_outcomes(pts2, nrm2, bits2, spt, sp, F, sets, dom_count=q["dom_count"])
+    for s, o in zip(sets, outs):
+        mine = O["set_pt"].reshape(-1, k)[s]
+        assert (mine < N).all() and O["oflag"][s]
+        pts_o, t_o = o
+        want = {tuple(int(mine[c]) + N * ((m >> c) & 1) for c in range(k)) for m in range(2 ** k)}
+        assert {tuple(int(v) for v in row) for row in pts_o} == want
+        assert (t_o == O["tstar"][s]).all()
+    assert nw * 2 == bits2.shape[-1]

@@ -160,3 +160,38 @@ def test_draws_and_optimisation_with_the_palm(c3):
     # over the batch the acceptance rises and the mean t* falls
     assert O2["verdict"][ok2].sum() >= V["verdict"][ok2].sum()
     assert O2["tstar"][ok2].mean() < V["tstar"][ok2].mean()
+
+
+
+def test_placement_flags_and_the_other_branch():
+    """Flag bits name their cause; the selected point is recorded for every
+    selected pose; flipping the rotation branch changes only poses whose
+    alignment cosine lies in the branch band.  A one-point object whose normal
+    meets the (upward) palm normals at a cosine inside the band: both branches
+    put the point onto the palm sample with the normals opposed, in two
+    different rotations."""
+    w = synth.workload("c3", n_poses=512, samples=4096, with_sdf=True)
+    palm = synth.palm_for("c3")
+    r = oracle.place_palm(palm, w.sdf, w.obj.pts, w.obj.nrm, w.poses, 0.5, 0.002, 5)
+    f = oracle.place_palm(palm, w.sdf, w.obj.pts, w.obj.nrm, w.poses, 0.5, 0.002, 5, flip=True)
+    assert set(np.unique(r["pflag"])) <= {0, 1, 2, 3}
+    sel = r["sel_pt"] >= 0
+    kept = r["palm_pt"] >= 0
+    assert ((r["palm_pt"] != -1) == sel).all() and (r["palm_pt"][kept] == r["sel_pt"][kept]).all()
+    same = (r["poses"] == f["poses"]).all(1)
+    assert (same | ((r["pflag"] & 1) != 0)).all()
+    # the crafted point: cosine of its normal with b = -(palm normal) = -z is -0.9999 + 3e-6
+    c = -0.9999 + 3e-6
+    a = np.array([[np.sqrt(1 - c * c), 0.0, -c]], np.float32)
+    pt = np.array([[0.0, 0.0, 0.04]], np.float32)
+    poses = np.tile(np.eye(3, 4, dtype=np.float32).reshape(1, 12), (64, 1))
+    r = oracle.place_palm(palm, w.sdf, pt, a, poses, 1.0, 0.002, 5)
+    f = oracle.place_palm(palm, w.sdf, pt, a, poses, 1.0, 0.002, 5, flip=True)
+    assert ((r["pflag"] & 1) != 0).all()
+    an = a[0].astype(np.float64) / np.linalg.norm(a[0])
+    for B in (r, f):
+        for g in range(len(poses)):
+            M = B["poses"][g].reshape(3, 4)
+            assert abs(np.linalg.det(M[:, :3]) - 1) < 1e-9   # 1 / (1 + c) amplifies the rounding
+            assert np.allclose(M[:, :3] @ an, [0, 0, -1], atol=1e-9)
+    assert not np.allclose(r["poses"], f["poses"], atol=1e-3)
