@@ -239,7 +239,7 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
                     const float uy = fmaf(a.m[4], px, fmaf(a.m[5], py, fmaf(a.m[6], pz, a.m[7])));
                     const float uz = fmaf(a.m[8], px, fmaf(a.m[9], py, fmaf(a.m[10], pz, a.m[11])));
                     const int Ix = (int)ux, Iy = (int)uy, Iz = (int)uz;  // biased voxel coordinates
-                    const bool in = valid & (min(Ix, min(Iy, Iz)) >= G) & (max(Ix, max(Iy, Iz)) < 2 * G);
+                    const bool in = (int)valid & (int)(min(Ix, min(Iy, Iz)) >= G) & (int)(max(Ix, max(Iy, Iz)) < 2 * G);
                     // one uniform base and a 32-bit byte offset per lane (the tables
                     // are far below 4 GiB): the load takes the scalar-base form
                     const uint32_t v =

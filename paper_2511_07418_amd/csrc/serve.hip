@@ -288,7 +288,11 @@ static lg_status launch_chunk(lg_server *S, Req *q)
 static void finish(lg_server *S, Req *q, int32_t state)
 {
     if (q->slot >= 0) {
-        // all work of the request is complete (its last event fired)
+        // Work of the request may still be queued on its stream when admit() or a
+        // launch failed part-way (its event then does not cover it): drain the
+        // stream before the block can be handed to another request.  After a
+        // normal completion the last event fired and this returns at once.
+        (void)hipStreamSynchronize(S->streams[q->slot]);
         char *base = S->slab.base + q->off;
         if (state == LG_REQ_DONE)
             (void)hipMemcpy(q->counters, base + q->L.counters, sizeof q->counters, hipMemcpyDeviceToHost);
