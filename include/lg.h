@@ -258,6 +258,28 @@ lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, i
                     int8_t *set_link, uint8_t *verdict, double *tstar, int32_t *acc_list,
                     int32_t *n_acc, void *workspace, size_t workspace_bytes, void *stream);
 
+/*
+ * lg_search_noalloc -- lg_search without a caller workspace, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, kernels and outputs
+ * as lg_search, minus workspace/workspace_bytes: the workspace is a static
+ * device array of lg_search_noalloc_max_bytes() bytes (8 MiB) per GPU, held
+ * until the process ends; its device address is looked up once per device on
+ * the first call there.  Calls whose lg_search_workspace_bytes() exceeds that
+ * size fail with LG_EINVAL before anything is enqueued.  No call allocates:
+ * no hipMalloc, hipFree or allocating library routine, and no memset node
+ * (the cell counts of Alg. 2 are cleared by a kernel).  Every call on a GPU
+ * shares that GPU's array, and each call rewrites what it reads from it:
+ * calls that overlap in time on one GPU (different streams or threads) race
+ * and give undefined results; serialise them.
+ */
+size_t lg_search_noalloc_max_bytes(void);
+lg_status lg_search_noalloc(const lg_field *field, const float *pts, const float *nrm, int32_t n_points,
+                            const float *poses, int32_t n_poses, const uint32_t *dom_bits,
+                            const uint32_t *dom_count, const lg_search_params *params, int32_t *set_pt,
+                            int8_t *set_link, uint8_t *verdict, double *tstar, int32_t *acc_list,
+                            int32_t *n_acc, void *stream);
+
 /* Kinematics optimisation parameters (Sec. 5.5). */
 typedef struct {
     int32_t iters;    /* DLS iterations (Eq. 7) */

@@ -4,6 +4,8 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
+#include <string>
 
 #include "lg_internal.h"
 
@@ -549,6 +551,12 @@ __device__ inline int point_cell(const GridDev &g, const float *pts, int N, int 
     return (c[2] * g.dims[1] + c[1]) * g.dims[0] + c[0];
 }
 
+__global__ void k_fill_u32(uint32_t *__restrict__ a, int64_t n, uint32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
 __global__ void k_grid_count(const float *__restrict__ pts, int N, const GridDev *__restrict__ gd,
                              uint32_t *__restrict__ cell_count)
 {
@@ -912,10 +920,15 @@ size_t lg_search_workspace_bytes(int32_t n_points, int32_t n_poses, const lg_sea
     return search_ws(nullptr, std::max(n_points, 0), n_poses, p->draws, p->opt_outer > 0).bytes;
 }
 
-lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, int32_t n_points, const float *poses,
-                    int32_t n_poses, const uint32_t *dom_bits, const uint32_t *dom_count,
-                    const lg_search_params *p, int32_t *set_pt, int8_t *set_link, uint8_t *verdict, double *tstar,
-                    int32_t *acc_list, int32_t *n_acc, void *workspace, size_t workspace_bytes, void *stream)
+}  // extern "C"
+
+// the whole search on a given workspace (the caller's, or the static scratch
+// array of lg_search_noalloc); allocates nothing
+static lg_status search_impl(const lg_field *field, const float *pts, const float *nrm, int32_t n_points,
+                             const float *poses, int32_t n_poses, const uint32_t *dom_bits, const uint32_t *dom_count,
+                             const lg_search_params *p, int32_t *set_pt, int8_t *set_link, uint8_t *verdict,
+                             double *tstar, int32_t *acc_list, int32_t *n_acc, void *workspace,
+                             size_t workspace_bytes, void *stream)
 {
     if (!field || !p) return fail(LG_EINVAL, "null field or params");
     const DevHand &H = field->dh;
@@ -979,7 +992,9 @@ lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, i
         // cell grid of the object, then Alg. 2 on the drawn sets, then the links of the moved contacts
         const int64_t ncell = (int64_t)(kGridMax + 1) * (kGridMax + 1) * (kGridMax + 1);
         hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(1024), 0, s, pts, n_points, p->opt_sigma, ws.grid);
-        LG_HIP(hipMemsetAsync(ws.cell_count, 0, (size_t)ncell * 4, s));
+        // zeroed by a kernel, not a memset node (callers may capture the stream in a graph)
+        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, ws.cell_count,
+                           ncell, 0u);
         const unsigned pb = (unsigned)((n_points + 255) / 256);
         hipLaunchKernelGGL(k_grid_count, dim3(pb), dim3(256), 0, s, pts, n_points, ws.grid, ws.cell_count);
         hipLaunchKernelGGL(k_grid_scan, dim3(1), dim3(1024), 0, s, ws.cell_count, ws.grid, ws.cell_start);
@@ -1018,6 +1033,62 @@ lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, i
                        chunk_off, acc_list);
     LG_HIP(hipGetLastError());
     return LG_OK;
+}
+
+// Scratch of lg_search_noalloc: one array per device, held until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it
+// is only a stand-in symbol); it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device.
+constexpr size_t kStaticScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static lg_status scratch_address(void **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    LG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LG_EUNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *ptr = nullptr;
+        LG_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(LG_EDEVICE, "no device address for the static scratch array");
+        addr[dev] = ptr;
+    }
+    *out = addr[dev];
+    return LG_OK;
+}
+
+extern "C" {
+
+size_t lg_search_noalloc_max_bytes(void) { return kStaticScratchBytes; }
+
+lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, int32_t n_points, const float *poses,
+                    int32_t n_poses, const uint32_t *dom_bits, const uint32_t *dom_count,
+                    const lg_search_params *p, int32_t *set_pt, int8_t *set_link, uint8_t *verdict, double *tstar,
+                    int32_t *acc_list, int32_t *n_acc, void *workspace, size_t workspace_bytes, void *stream)
+{
+    return search_impl(field, pts, nrm, n_points, poses, n_poses, dom_bits, dom_count, p, set_pt, set_link, verdict,
+                       tstar, acc_list, n_acc, workspace, workspace_bytes, stream);
+}
+
+lg_status lg_search_noalloc(const lg_field *field, const float *pts, const float *nrm, int32_t n_points,
+                            const float *poses, int32_t n_poses, const uint32_t *dom_bits, const uint32_t *dom_count,
+                            const lg_search_params *p, int32_t *set_pt, int8_t *set_link, uint8_t *verdict,
+                            double *tstar, int32_t *acc_list, int32_t *n_acc, void *stream)
+{
+    if (!p) return fail(LG_EINVAL, "null params");
+    const size_t need = lg_search_workspace_bytes(n_points, n_poses, p);
+    if (need > kStaticScratchBytes)
+        return fail(LG_EINVAL, "search needs " + std::to_string(need) + " bytes of workspace, above the " +
+                                   std::to_string(kStaticScratchBytes) + "-byte static scratch");
+    void *ws = nullptr;
+    const lg_status st = scratch_address(&ws);
+    if (st != LG_OK) return st;
+    return search_impl(field, pts, nrm, n_points, poses, n_poses, dom_bits, dom_count, p, set_pt, set_link, verdict,
+                       tstar, acc_list, n_acc, ws, kStaticScratchBytes, stream);
 }
 
 }  // extern "C"

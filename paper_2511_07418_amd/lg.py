@@ -123,6 +123,9 @@ def _load():
     L.lg_search_workspace_bytes.argtypes = [i32, i32, vp]
     L.lg_search_workspace_bytes.restype = sz
     L.lg_search.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.lg_search_noalloc.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.lg_search_noalloc_max_bytes.argtypes = []
+    L.lg_search_noalloc_max_bytes.restype = sz
     L.lg_realize.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, i32, i32, vp, vp, i32, vp,
                              vp, vp, vp, vp, vp, vp]
     L.lg_serve_request_bytes.argtypes = [vp, vp]
@@ -153,7 +156,8 @@ def _load():
     L.lg_prop_sample_mixture.argtypes = [vp, i32, C.c_uint64, C.c_float, C.c_float, C.c_float, vp, vp]
     L.lg_prop_sample.argtypes = [vp, vp, i32, i32, C.c_uint64, C.c_float, C.c_float, C.c_float, vp, vp]
     for fn in ("lg_build_field", "lg_field_import", "lg_field_export", "lg_field_info",
-               "lg_field_release", "lg_query_domains", "lg_query_domains_cone", "lg_search", "lg_realize", "lg_serve_create",
+               "lg_field_release", "lg_query_domains", "lg_query_domains_cone", "lg_search", "lg_search_noalloc",
+               "lg_realize", "lg_serve_create",
                "lg_serve_submit", "lg_serve_poll", "lg_serve_wait", "lg_serve_cancel", "lg_serve_stats",
                "lg_serve_destroy", "lg_place_exhaustive", "lg_place_palm", "lg_concave_filter", "lg_gather_points",
                "lg_query_domains_bounded", "lg_chunk_bounds", "lg_morton_order",
@@ -169,7 +173,8 @@ _lib = _load()
 EXPORTED = ("lg_status_str", "lg_last_error", "lg_version", "lg_build_field", "lg_field_import",
             "lg_field_export", "lg_field_info", "lg_field_release", "lg_query_domains", "lg_query_domains_cone",
             "lg_query_domains_bounded", "lg_chunk_bounds", "lg_morton_order",
-            "lg_search_workspace_bytes", "lg_search", "lg_realize", "lg_serve_request_bytes",
+            "lg_search_workspace_bytes", "lg_search", "lg_search_noalloc", "lg_search_noalloc_max_bytes",
+            "lg_realize", "lg_serve_request_bytes",
             "lg_serve_create", "lg_serve_submit", "lg_serve_poll", "lg_serve_wait", "lg_serve_cancel",
             "lg_serve_stats", "lg_serve_clock", "lg_serve_destroy", "lg_place_exhaustive", "lg_place_palm",
             "lg_concave_filter",
@@ -394,6 +399,21 @@ def lg_search(field: Field, pts, nrm, poses, dom_bits, dom_count, sp, bufs: Opti
                           _ptr(dom_count), C.byref(bufs.p), _ptr(bufs.set_pt), _ptr(bufs.set_link),
                           _ptr(bufs.verdict), _ptr(bufs.tstar), _ptr(bufs.acc_list), _ptr(bufs.n_acc),
                           _ptr(bufs.workspace), bufs.workspace.numel(), _stream(stream)), "lg_search")
+    return bufs
+
+
+def lg_search_noalloc(field: Field, pts, nrm, poses, dom_bits, dom_count, sp, bufs: SearchBuffers,
+                      max_pivots: int = 1000, stream=None, palm_pt: Optional[torch.Tensor] = None) -> SearchBuffers:
+    """lg_search on the library's static device scratch (no workspace argument,
+    nothing allocated by the call; ``bufs`` holds the caller's outputs)."""
+    N, P = int(pts.shape[1]), int(poses.shape[0])
+    bufs.p = search_params(sp, max_pivots)
+    bufs.p.palm_pt = None if palm_pt is None else palm_pt.data_ptr()
+    bufs.palm_pt = palm_pt
+    _check(_lib.lg_search_noalloc(field.handle, _ptr(pts), _ptr(nrm), N, _ptr(poses), P, _ptr(dom_bits),
+                                  _ptr(dom_count), C.byref(bufs.p), _ptr(bufs.set_pt), _ptr(bufs.set_link),
+                                  _ptr(bufs.verdict), _ptr(bufs.tstar), _ptr(bufs.acc_list), _ptr(bufs.n_acc),
+                                  _stream(stream)), "lg_search_noalloc")
     return bufs
 
 
