@@ -102,6 +102,9 @@ typedef struct {
     int64_t vectors;          /* contact vectors generated (S * sum_l n_surf) */
     int64_t dropped;          /* vectors outside their finger's window */
     int32_t has_witness;
+    int32_t lattice;          /* 1: the windows share one rotation and lie whole 4-voxel bricks
+                                 apart (G a power of two), so the query maps each point once for
+                                 all fingers; 0: each finger's window is mapped on its own */
 } lg_field_info_t;
 
 /*

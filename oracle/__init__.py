@@ -105,7 +105,7 @@ def lib():
         L.orc_query_cone.argtypes = [vp, vp, vp, vp, vp, i32, vp, i32, dbl, vp, vp, vp]
         L.orc_query_cone.restype = C.c_int
         L.orc_draw.argtypes = [vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, i32, i32, u64, C.c_uint32, i64, vp,
-                               vp, vp]
+                               vp, vp, vp]
         L.orc_draw.restype = C.c_int
         L.orc_tangent_basis.argtypes = [vp, vp, vp]
         L.orc_wrench_matrix.argtypes = [C.c_int, vp, vp, dbl, C.c_int, dbl, vp]
@@ -133,7 +133,7 @@ def lib():
         L.orc_optimize_outcomes.argtypes = [vp, vp, i32, vp, vp, vp, i32, i32, i64, i32, vp, dbl, i32, dbl, i32, i32,
                                             dbl, u64, C.c_uint32, i64, i32, i32, vp, vp]
         L.orc_optimize_outcomes.restype = C.c_int
-        L.orc_relink.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, i32, vp, vp, u64, C.c_uint32, i64, vp]
+        L.orc_relink.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, i32, vp, vp, u64, C.c_uint32, i64, vp, vp]
         L.orc_relink.restype = C.c_int
         L.orc_segment_distance.argtypes = [vp, vp, vp, vp]
         L.orc_segment_distance.restype = dbl
@@ -321,21 +321,25 @@ def query_cone(hand, fp, bits, pts, nrm, poses, cos_hit: float, flags: bool = Tr
     return {"dom_bits": db, "dom_count": dc, "dom_flag": df}
 
 
-def draw(hand, fp, bits, pts, nrm, poses, dom_bits, dom_count, sp, palm_pt=None) -> tuple[np.ndarray, np.ndarray]:
+def draw(hand, fp, bits, pts, nrm, poses, dom_bits, dom_count, sp, palm_pt=None, link_flags: bool = False):
     """Seeded contact-set draws: ``set_pt``, ``set_link`` int32 [P, D, k]
-    (none for poses whose palm placement was rejected, ``palm_pt == -2``)."""
+    (none for poses whose palm placement was rejected, ``palm_pt == -2``).
+    With ``link_flags`` a third array uint8 [P, D, k] marks links decided
+    inside a rounding band (voxel face within 1e-6 m or bin boundary within
+    1e-6 rad, with another link on the other side)."""
     pts, nrm, poses = _c(pts, np.float32), _c(nrm, np.float32), _c(poses, np.float32)
     P, N = poses.shape[0], pts.shape[0]
     spt = np.zeros((P, sp.draws, sp.k), np.int32)
     sln = np.zeros((P, sp.draws, sp.k), np.int32)
+    lfl = np.zeros((P, sp.draws, sp.k), np.uint8) if link_flags else None
     H, Fp = _hand(hand), _field(fp)
     rc = lib().orc_draw(H.ref, Fp.ref, _p(_c(bits, np.uint32)), _p(pts), _p(nrm), N, _p(poses), P,
                         _p(_c(dom_bits, np.uint32)), _p(_c(dom_count, np.uint32)), sp.draws, sp.k,
                         int(sp.seed) & 0xFFFFFFFFFFFFFFFF, int(sp.request_id), int(sp.pose_offset),
-                        _p(None if palm_pt is None else _c(palm_pt, np.int32)), _p(spt), _p(sln))
+                        _p(None if palm_pt is None else _c(palm_pt, np.int32)), _p(spt), _p(sln), _p(lfl))
     if rc != 0:
         raise ValueError(f"orc_draw failed ({rc})")
-    return spt, sln
+    return (spt, sln, lfl) if link_flags else (spt, sln)
 
 
 def tangent_basis(n) -> tuple[np.ndarray, np.ndarray]:
@@ -570,10 +574,11 @@ def place_palm(palm, sdf, pts, nrm, poses, prob: float, margin: float, seed: int
     return {"poses": out, "palm_pt": pp, "pflag": fl, "sel_pt": sel}
 
 
-def relink(hand, fp, bits, pts, nrm, poses, set_pt, sp, dom_count=None) -> np.ndarray:
+def relink(hand, fp, bits, pts, nrm, poses, set_pt, sp, dom_count=None, link_flags: bool = False):
     """Links of (optimised) sets, picked with each set's draw words.  ``dom_count``
     decides the sets' fingers; it may be left out when k equals the number of
-    fingers (every finger then carries contact i = finger i)."""
+    fingers (every finger then carries contact i = finger i).  ``link_flags``:
+    also return the band flags of ``draw``."""
     pts, nrm, poses = _c(pts, np.float32), _c(nrm, np.float32), _c(poses, np.float32)
     spt = _c(set_pt, np.int32)
     P, D, k = spt.shape
@@ -584,13 +589,14 @@ def relink(hand, fp, bits, pts, nrm, poses, set_pt, sp, dom_count=None) -> np.nd
         dom_count = np.ones((P, F), np.uint32)
     cnt = _c(dom_count, np.uint32).reshape(P, F)
     sln = np.zeros((P, D, k), np.int32)
+    lfl = np.zeros((P, D, k), np.uint8) if link_flags else None
     H, Fp = _hand(hand), _field(fp)
     rc = lib().orc_relink(H.ref, Fp.ref, _p(_c(bits, np.uint32)), _p(pts), _p(nrm), _p(poses), P, D, k,
                           _p(cnt), _p(spt), int(sp.seed) & 0xFFFFFFFFFFFFFFFF, int(sp.request_id),
-                          int(sp.pose_offset), _p(sln))
+                          int(sp.pose_offset), _p(sln), _p(lfl))
     if rc != 0:
         raise ValueError(f"orc_relink failed ({rc})")
-    return sln
+    return (sln, lfl) if link_flags else sln
 
 
 def compact(verdict) -> np.ndarray:

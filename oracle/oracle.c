@@ -665,17 +665,10 @@ static void draw_words(uint64_t seed, uint32_t request_id, int64_t g, int d, int
     }
 }
 
-/* Reverse lookup of the link (Sec. 5.5): among the links of finger f whose
- * table bit is set at point idx under the pose, the floor(r * count / 2^32)-th;
- * -1 if none. */
-static int pick_link(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits, const double *cb,
-                     const float *pts, const float *nrm, const float *pose, int f, int64_t idx, uint32_t r)
+/* the floor(r * popcount(mask) / 2^32)-th link of finger f in mask (bit t =
+ * the finger's t-th link); -1 for an empty mask */
+static int link_of_mask(const orc_hand *H, int f, uint32_t mask, uint32_t r)
 {
-    double x[3], u[3], gap;
-    int vox[3], b, b2;
-    int in = query_lookup(fp, cb, pose, pts + 3 * idx, nrm + 3 * idx, f, x, u, vox, &b, &b2, &gap);
-    uint32_t mask = 0;
-    link_hits_at(H, fp, bits, f, vox, in, b, &mask);
     uint32_t pc = popcount32(mask);
     if (pc == 0) return -1;
     uint32_t jj = (uint32_t)(((uint64_t)r * pc) >> 32);
@@ -690,6 +683,54 @@ static int pick_link(const orc_hand *H, const orc_field_params *fp, const uint32
         ++t;
     }
     return -1;
+}
+
+/* Reverse lookup of the link (Sec. 5.5): among the links of finger f whose
+ * table bit is set at point idx under the pose, the floor(r * count / 2^32)-th;
+ * -1 if none.  *flag (optional) is set when the voxel lies within 1e-6 m of a
+ * face or the bin within 1e-6 rad of a boundary and a cell on the other side
+ * gives another link (an implementation in float32 may take either). */
+static int pick_link(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits, const double *cb,
+                     const float *pts, const float *nrm, const float *pose, int f, int64_t idx, uint32_t r,
+                     int *flag)
+{
+    double x[3], u[3], gap;
+    int vox[3], b, b2;
+    int in = query_lookup(fp, cb, pose, pts + 3 * idx, nrm + 3 * idx, f, x, u, vox, &b, &b2, &gap);
+    uint32_t mask = 0;
+    link_hits_at(H, fp, bits, f, vox, in, b, &mask);
+    const int link = link_of_mask(H, f, mask, r);
+    if (!flag) return link;
+    *flag = 0;
+    const int G = fp->grid;
+    int near[3], any_near = 0;
+    for (int a = 0; a < 3; ++a) {
+        near[a] = face_dist(u[a], fp->h) < BAND_POS;
+        any_near |= near[a];
+    }
+    const int bin_near = gap < BAND_ANG;
+    if (!any_near && !bin_near) return link;
+    int lo3[3], hi3[3];
+    for (int a = 0; a < 3; ++a) {
+        lo3[a] = hi3[a] = vox[a];
+        if (near[a]) {
+            double rr = u[a] - floor(u[a]);
+            if (rr < 0.5) lo3[a] = vox[a] - 1; else hi3[a] = vox[a] + 1;
+        }
+    }
+    int bb[2] = {b, b2}, nb = bin_near ? 2 : 1;
+    for (int zz = lo3[2]; zz <= hi3[2]; ++zz)
+        for (int yy = lo3[1]; yy <= hi3[1]; ++yy)
+            for (int xx = lo3[0]; xx <= hi3[0]; ++xx) {
+                int v3[3] = {xx, yy, zz};
+                int in2 = xx >= 0 && yy >= 0 && zz >= 0 && xx < G && yy < G && zz < G;
+                for (int kk = 0; kk < nb; ++kk) {
+                    uint32_t m2 = 0;
+                    link_hits_at(H, fp, bits, f, v3, in2, bb[kk], &m2);
+                    if (link_of_mask(H, f, m2, r) != link) *flag = 1;
+                }
+            }
+    return link;
 }
 
 /* The k contact fingers of set d of pose g (Sec. 5.3: k contact domains
@@ -735,7 +776,8 @@ int orc_draw(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits
              const uint32_t *dom_bits, const uint32_t *dom_count,
              int32_t draws, int32_t k, uint64_t seed, uint32_t request_id, int64_t pose_offset,
              const int32_t *palm_pt /*[P] or NULL: -2 = rejected placement, no sets*/,
-             int32_t *set_pt /*[P][D][k]*/, int32_t *set_link /*[P][D][k]*/)
+             int32_t *set_pt /*[P][D][k]*/, int32_t *set_link /*[P][D][k]*/,
+             uint8_t *link_flag /*[P][D][k] or NULL: link decided inside a band (see pick_link)*/)
 {
     const int F = H->n_fingers;
     const int64_t NW = (n_points + 31) / 32;
@@ -750,7 +792,8 @@ int orc_draw(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits
             int32_t *sp = set_pt + ((int64_t)g * draws + d) * k;
             int32_t *sl = set_link + ((int64_t)g * draws + d) * k;
             int32_t fing[8];
-            for (int i = 0; i < k; ++i) { sp[i] = -1; sl[i] = -1; }
+            uint8_t *lf = link_flag ? link_flag + ((int64_t)g * draws + d) * k : NULL;
+            for (int i = 0; i < k; ++i) { sp[i] = -1; sl[i] = -1; if (lf) lf[i] = 0; }
             if (palm_pt && palm_pt[g] == -2) continue;
             if (!orc_choose_fingers(F, dom_count + (int64_t)g * F, k, seed, request_id, pose_offset + g, d, fing))
                 continue;
@@ -760,7 +803,11 @@ int orc_draw(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits
                 uint32_t j = (uint32_t)(((uint64_t)w[i] * cnt) >> 32);
                 int64_t idx = select1(dom_bits + ((int64_t)g * F + f) * NW, NW, j);
                 sp[i] = (int32_t)idx;
-                sl[i] = idx < 0 ? -1 : pick_link(H, fp, bits, cb, pts, nrm, poses + 12 * (int64_t)g, f, idx, w[k + i]);
+                int fl = 0;
+                sl[i] = idx < 0 ? -1
+                                : pick_link(H, fp, bits, cb, pts, nrm, poses + 12 * (int64_t)g, f, idx, w[k + i],
+                                            lf ? &fl : NULL);
+                if (lf) lf[i] = (uint8_t)fl;
             }
         }
     }
@@ -1586,7 +1633,7 @@ int orc_optimize_outcomes(const float *pts, const float *nrm, int32_t n_points, 
 int orc_relink(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits, const float *pts,
                const float *nrm, const float *poses, int32_t n_poses, int32_t draws, int32_t k,
                const uint32_t *dom_count /*[P][F]*/, const int32_t *set_pt, uint64_t seed, uint32_t request_id,
-               int64_t pose_offset, int32_t *set_link)
+               int64_t pose_offset, int32_t *set_link, uint8_t *link_flag /*[P][D][k] or NULL*/)
 {
     const int F = H->n_fingers;
     if (k < 1 || k > F || k > 8 || draws <= 0) return ORC_EINVAL;
@@ -1602,10 +1649,14 @@ int orc_relink(const orc_hand *H, const orc_field_params *fp, const uint32_t *bi
             int32_t fing[8];
             const int ok = orc_choose_fingers(F, dom_count + (int64_t)g * F, k, seed, request_id, pose_offset + g,
                                               d, fing);
-            for (int i = 0; i < k; ++i)
+            uint8_t *lf = link_flag ? link_flag + ((int64_t)g * draws + d) * k : NULL;
+            for (int i = 0; i < k; ++i) {
+                int fl = 0;
                 sl[i] = (!ok || sp[i] < 0) ? -1
                                            : pick_link(H, fp, bits, cb, pts, nrm, poses + 12 * (int64_t)g, fing[i],
-                                                       sp[i], w[k + i]);
+                                                       sp[i], w[k + i], lf ? &fl : NULL);
+                if (lf) lf[i] = (uint8_t)fl;
+            }
         }
     }
     return ORC_OK;

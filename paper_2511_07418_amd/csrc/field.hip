@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 
 #include "lg_internal.h"
@@ -66,7 +67,7 @@ lg_status validate_hand(const lg_hand_desc *hand, const lg_field_params *p)
     for (int c = 0; c < hand->n_palm_caps; ++c)
         if (!(hand->palm_caps[7 * c + 6] >= 0.0f)) return fail(LG_EINVAL, "palm capsule radius must be >= 0");
     if (p->bins != 32 && p->bins != 64) return fail(LG_EINVAL, "bins must be 32 or 64");
-    if (p->grid < 4 || p->grid > 128) return fail(LG_EINVAL, "grid must be 4..128");
+    if (p->grid < 4 || p->grid > 128 || p->grid % 4 != 0) return fail(LG_EINVAL, "grid must be a multiple of 4 in 4..128");
     if (!(p->h > 0.0f)) return fail(LG_EINVAL, "h must be > 0");
     if (p->samples < 1 || p->samples > 0x7fffffffLL) return fail(LG_EINVAL, "samples must be 1..2^31-1");
     if (!p->grid_frame) return fail(LG_EINVAL, "null grid_frame");
@@ -142,6 +143,48 @@ static void build_bin_lut(const std::vector<float> &bc, int B, std::vector<uint3
     }
 }
 
+// Lattice form of the windows (see DevHand::lat): every frame has finger 0's
+// rotation (same floats), G is a power of two, and each origin is a whole
+// number of 4-voxel bricks from finger 0's, within 1e-4 voxel (a few float
+// ulps of the origins; the window faces move by far less than the 1e-6 m
+// bands in which the oracle flags voxel decisions).  Otherwise lat = 0 and
+// every kernel maps each finger's window on its own.
+static void set_lattice(DevHand &H, const float *gf)
+{
+    H.lat = 0;
+    const int F = H.F, G = H.G;
+    if (G < 4 || (G & (G - 1)) != 0) return;
+    for (int f = 1; f < F; ++f)
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c)
+                if (gf[12 * f + 4 * r + c] != gf[4 * r + c]) return;
+    long k[kMaxFingers][3];
+    long lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int f = 0; f < F; ++f) {
+        const double d[3] = {(double)gf[12 * f + 3] - gf[3], (double)gf[12 * f + 7] - gf[7],
+                             (double)gf[12 * f + 11] - gf[11]};
+        for (int a = 0; a < 3; ++a) {
+            // a-th coordinate in finger 0's frame: column a of its rotation
+            const double u = (gf[a] * d[0] + gf[4 + a] * d[1] + gf[8 + a] * d[2]) / (double)H.h;
+            const double r = 4.0 * std::nearbyint(u / 4.0);
+            if (!(std::fabs(u - r) <= 1e-4) || std::fabs(r) > 4096.0) return;
+            k[f][a] = (long)r;
+            lo[a] = std::min(lo[a], k[f][a]);
+            hi[a] = std::max(hi[a], k[f][a]);
+        }
+    }
+    for (int a = 0; a < 3; ++a)
+        if (hi[a] - lo[a] + 3L * G > 1024L) return;
+    const uint32_t GB = (uint32_t)(G / 4), m = (uint32_t)(G - 1);
+    for (int f = 0; f < F; ++f) {
+        for (int a = 0; a < 3; ++a) H.lat_o[f][a] = (int)(k[f][a] - lo[a] + G);
+        H.lat_pk[f] = (uint32_t)H.lat_o[f][0] | (uint32_t)H.lat_o[f][1] << 10 | (uint32_t)H.lat_o[f][2] << 20;
+        H.lat_idx[f] = brick_word((uint32_t)H.lat_o[f][0], (uint32_t)H.lat_o[f][1], (uint32_t)H.lat_o[f][2], GB);
+    }
+    H.lat_hi = ~(m | m << 10 | m << 20);
+    H.lat = 1;
+}
+
 // Copy the hand, compute bin centres and axis sample counts on the host,
 // upload them and allocate the (zeroed) tables.
 lg_status make_field_shell(const lg_hand_desc *hand, const lg_field_params *p, lg_field **out)
@@ -209,6 +252,7 @@ lg_status make_field_shell(const lg_hand_desc *hand, const lg_field_params *p, l
         maxd = std::max(maxd, d);
     }
     f->max_dof = maxd;
+    set_lattice(H, p->grid_frame);
     // packed float parameters
     const size_t n_origin = f->origin.size(), n_axis = f->axis.size(), n_cap = f->capsule.size(),
                  n_lim = f->limits.size(), n_surf = f->surf.size(), n_gf = f->grid_frame.size(),
@@ -351,16 +395,22 @@ k_field_build(DevHand H, uint32_t *__restrict__ bits, int32_t *__restrict__ wit,
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(dropped, c);
 }
 
-// merged[f][v][w] = OR over links l of f of bits[l][v][w]
+// Merged finger tables: OR over the links of finger f of their words, laid
+// out as merged[f][w][brick_word(v)] (one plane per 32-bin word w, 4x4x4
+// voxel bricks), from the canonical per-link tables bits[l][v][w].
 __global__ void k_field_merge(DevHand H, const uint32_t *__restrict__ bits, uint32_t *__restrict__ merged)
 {
-    const int64_t G3W = (int64_t)H.G * H.G * H.G * H.W;
+    const int G = H.G, W = H.W;
+    const int64_t G3 = (int64_t)G * G * G, G3W = G3 * W;
     const int f = blockIdx.y;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < G3W; i += (int64_t)gridDim.x * blockDim.x) {
         uint32_t acc = 0;
         const int first = H.finger_first[f], d = H.finger_dof[f];
         for (int t = 0; t < d; ++t) acc |= bits[(int64_t)(first + t) * G3W + i];
-        merged[(int64_t)f * G3W + i] = acc;
+        const int64_t v = i / W;
+        const int w = (int)(i - v * W);
+        const uint32_t ix = (uint32_t)(v % G), iy = (uint32_t)((v / G) % G), iz = (uint32_t)(v / ((int64_t)G * G));
+        merged[((int64_t)f * W + w) * G3 + brick_word(ix, iy, iz, (uint32_t)(G / 4))] = acc;
     }
 }
 
@@ -521,6 +571,7 @@ lg_status lg_field_info(const lg_field *f, lg_field_info_t *info)
     info->vectors = f->vectors;
     info->dropped = f->dropped;
     info->has_witness = f->has_witness ? 1 : 0;
+    info->lattice = f->dh.lat;
     return LG_OK;
 }
 

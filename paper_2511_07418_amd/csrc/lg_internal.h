@@ -45,6 +45,16 @@ struct DevHand {
     const float *palm_caps;       // [n_palm_caps][7]
     int finger_first[kMaxFingers];
     int finger_dof[kMaxFingers];
+    // Lattice form of the windows (lat != 0): every finger's window has the
+    // rotation of finger 0's and its origin lies a whole number of 4-voxel
+    // bricks from the others, G is a power of two.  Lattice coordinates are
+    // finger 0's window coordinates shifted by lat_o[0]; finger f's window is
+    // the lattice box [lat_o[f], lat_o[f] + G)^3, with G <= lat_o <= 1024 - 2G.
+    int lat;
+    int lat_o[kMaxFingers][3];
+    uint32_t lat_pk[kMaxFingers];  // lat_o packed as x | y << 10 | z << 20
+    uint32_t lat_idx[kMaxFingers]; // brick_word(lat_o) (its in-brick part is 0)
+    uint32_t lat_hi;               // bits of a packed difference that must be 0 inside a window
 };
 
 }  // namespace lg
@@ -219,6 +229,58 @@ __device__ inline int window_voxel(const Affine &a, int G, float px, float py, f
     const unsigned ix = (unsigned)((int)ux - G), iy = (unsigned)((int)uy - G), iz = (unsigned)((int)uz - G);
     const bool in = max(ix, max(iy, iz)) < (unsigned)G;
     return in ? (int)__umul24(__umul24(iz, G) + iy, G) + (int)ix : -1;
+}
+
+// Lattice map of pose P: finger 0's affine map with the bias lat_o[0]
+// instead of G (same fmaf chains as finger_affine).
+__device__ inline Affine lattice_affine(const DevHand &H, const float *pose)
+{
+    const float *g = H.grid_frame;
+    Affine a;
+    const float dx = pose[3] - g[3], dy = pose[7] - g[7], dz = pose[11] - g[11];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            a.m[4 * r + c] = fmaf(g[r], pose[c], fmaf(g[4 + r], pose[4 + c], g[8 + r] * pose[8 + c])) * H.inv_h;
+        a.m[4 * r + 3] = fmaf(fmaf(g[r], dx, fmaf(g[4 + r], dy, g[8 + r] * dz)), H.inv_h, (float)H.lat_o[0][r]);
+    }
+    return a;
+}
+
+// Lattice cell of object point p (truncation; every window lies at lattice
+// coordinates >= G, so a truncated negative value is outside all of them).
+__device__ inline void lattice_cell(const Affine &a, float px, float py, float pz, int &Ix, int &Iy, int &Iz)
+{
+    Ix = (int)fmaf(a.m[0], px, fmaf(a.m[1], py, fmaf(a.m[2], pz, a.m[3])));
+    Iy = (int)fmaf(a.m[4], px, fmaf(a.m[5], py, fmaf(a.m[6], pz, a.m[7])));
+    Iz = (int)fmaf(a.m[8], px, fmaf(a.m[9], py, fmaf(a.m[10], pz, a.m[11])));
+}
+
+// Word of voxel (ix, iy, iz) in a plane of a merged finger table: 4x4x4
+// bricks in (z, y, x) order, voxels in a brick in (z, y, x) order.  The map is
+// linear in the brick and in-brick coordinates, so for a brick-aligned offset
+// O, brick_word(I - O) = brick_word(I) - brick_word(O).
+__host__ __device__ inline uint32_t brick_word(uint32_t ix, uint32_t iy, uint32_t iz, uint32_t GB)
+{
+    return ((((iz >> 2) * GB + (iy >> 2)) * GB + (ix >> 2)) << 6) | ((iz & 3u) << 4) | ((iy & 3u) << 2) | (ix & 3u);
+}
+
+// Voxel of object point p in finger f's window under pose P (-1 outside):
+// window_voxel of finger_affine, or, for lattice windows, the lattice cell
+// less the finger's offset (the query takes the same decisions).
+__device__ inline int finger_window_voxel(const DevHand &H, const float *pose, int f, float px, float py, float pz)
+{
+    if (H.lat) {
+        const Affine a = lattice_affine(H, pose);
+        int Ix, Iy, Iz;
+        lattice_cell(a, px, py, pz, Ix, Iy, Iz);
+        const unsigned ix = (unsigned)(Ix - H.lat_o[f][0]), iy = (unsigned)(Iy - H.lat_o[f][1]),
+                       iz = (unsigned)(Iz - H.lat_o[f][2]);
+        const bool in = max(ix, max(iy, iz)) < (unsigned)H.G;
+        return in ? (int)__umul24(__umul24(iz, H.G) + iy, H.G) + (int)ix : -1;
+    }
+    return window_voxel(finger_affine(H, pose, f), H.G, px, py, pz);
 }
 
 // Query direction of object normal n under pose P: q = -R_P n.

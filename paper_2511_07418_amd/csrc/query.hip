@@ -2,10 +2,19 @@
 // merge of Sec. 5.3.
 //
 // One workgroup per pose; each wave sweeps 64 consecutive object points
-// (structure-of-arrays).  Per point: x = R p + t folded into one affine map
-// per finger window, query normal -R n, its bin, one 4/8-byte gather of the
-// finger's merged table, and a wave ballot that yields the 64 domain bits of
-// the finger for the chunk.  Counts are popcounts of the ballots.
+// (structure-of-arrays).  Per point: the query normal -R n and its bin, the
+// point's voxel in each finger window, one 4-byte gather per finger from the
+// plane of its merged table that holds the bin, and a wave ballot that yields
+// the 64 domain bits of the finger for the chunk.  Counts are popcounts of
+// the ballots.
+//
+// Windows in lattice form (a shared rotation, origins a whole number of
+// 4-voxel bricks apart) take one affine map per point instead of one per
+// finger: the point's lattice cell is packed as x | y << 10 | z << 20, and
+// finger f's in-window test is one subtraction of its packed offset and one
+// mask (a field that went negative or reached G sets a bit of lat_hi).  The
+// bricked table word is linear in the cell, so one per-point byte offset
+// serves every finger, each finger's offset folded into its scalar base.
 //
 // With chunk bounds (a bounding sphere per 64 consecutive points, a one-level
 // bounding-volume hierarchy over the object; tight when the points are in
@@ -60,12 +69,14 @@ k_chunk_bounds(const float *__restrict__ pts, int N, float4 *__restrict__ bounds
 // skip[f] bit j: chunk blk * 32 + j cannot reach finger f's window (all 0
 // without bounds); returns the chunks that reach no window.  Lane l tests
 // chunk l % 32 against finger f0 + l / 32, two fingers per ballot: the distance
-// from the sphere's centre (biased voxel coordinates) to the window box
-// [G, 2G]^3 against its radius.
-template <int FM>
-__device__ inline uint32_t block_skip(const float4 *__restrict__ bounds, const Affine *aff, int F, int G, float inv_h,
+// from the sphere's centre (voxel coordinates of map aff[LAT ? 0 : f]) to the
+// finger's window box [lo, lo + G]^3 against its radius; lo = G for a
+// finger's own (biased) map, lat_o[f] in lattice coordinates.
+template <int FM, bool LAT>
+__device__ inline uint32_t block_skip(const float4 *__restrict__ bounds, const Affine *aff, const DevHand &H,
                                       int blk, int nchunks, int lane, uint32_t (&skip)[FM])
 {
+    const int F = H.F, G = H.G;
 #pragma unroll
     for (int f = 0; f < FM; ++f) skip[f] = 0u;
     if (!bounds) return 0u;
@@ -77,15 +88,16 @@ __device__ inline uint32_t block_skip(const float4 *__restrict__ bounds, const A
         bool out = true;
         if (ch < nchunks) {
             const float4 sb = bounds[ch];
-            const Affine &a = aff[f];
+            const Affine &a = aff[LAT ? 0 : f];
             const float ux = fmaf(a.m[0], sb.x, fmaf(a.m[1], sb.y, fmaf(a.m[2], sb.z, a.m[3])));
             const float uy = fmaf(a.m[4], sb.x, fmaf(a.m[5], sb.y, fmaf(a.m[6], sb.z, a.m[7])));
             const float uz = fmaf(a.m[8], sb.x, fmaf(a.m[9], sb.y, fmaf(a.m[10], sb.z, a.m[11])));
-            const float gl = (float)G, gh = (float)(2 * G);
-            const float dx = fmaxf(fmaxf(gl - ux, ux - gh), 0.f);
-            const float dy = fmaxf(fmaxf(gl - uy, uy - gh), 0.f);
-            const float dz = fmaxf(fmaxf(gl - uz, uz - gh), 0.f);
-            const float rv = fmaf(sb.w, inv_h, kCullMargin);
+            const float lx = LAT ? (float)H.lat_o[f][0] : (float)G, ly = LAT ? (float)H.lat_o[f][1] : (float)G,
+                        lz = LAT ? (float)H.lat_o[f][2] : (float)G;
+            const float dx = fmaxf(fmaxf(lx - ux, ux - (lx + G)), 0.f);
+            const float dy = fmaxf(fmaxf(ly - uy, uy - (ly + G)), 0.f);
+            const float dz = fmaxf(fmaxf(lz - uz, uz - (lz + G)), 0.f);
+            const float rv = fmaf(sb.w, H.inv_h, kCullMargin);
             out = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) > rv * rv;
         }
         const unsigned long long m = __ballot(out);
@@ -157,7 +169,7 @@ __device__ inline int nearest_bin_lut4(const uint32_t *lut, const float4 *c4, in
     return bi;
 }
 
-template <int W, int FM>
+template <int W, int FM, bool LAT>
 __global__ void __launch_bounds__(kQueryThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict__ pts,
         const float *__restrict__ nrm, int N, const float *__restrict__ poses, const float4 *__restrict__ bounds,
@@ -165,24 +177,34 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
 {
     __shared__ float4 cb4[kMaxBins];
     __shared__ uint32_t lut[6 * kLutRes * kLutRes];
-    __shared__ Affine aff[FM];
+    __shared__ Affine aff[LAT ? 1 : FM];
     __shared__ uint32_t cnt[FM][kQueryWaves];
     const int g = blockIdx.x;
     const float *pose = poses + 12 * (int64_t)g;
     for (int i = threadIdx.x; i < H.B; i += blockDim.x)
         cb4[i] = make_float4(H.bin_c[3 * i], H.bin_c[3 * i + 1], H.bin_c[3 * i + 2], 0.0f);
     for (int i = threadIdx.x; i < 6 * kLutRes * kLutRes; i += blockDim.x) lut[i] = H.bin_lut[i];
-    if (threadIdx.x < H.F) aff[threadIdx.x] = finger_affine(H, pose, threadIdx.x);
+    if (LAT) {
+        if (threadIdx.x == 0) aff[0] = lattice_affine(H, pose);
+    } else if (threadIdx.x < H.F) {
+        aff[threadIdx.x] = finger_affine(H, pose, threadIdx.x);
+    }
     __syncthreads();
     // the wave index is uniform: in a scalar register, the block and chunk
     // bookkeeping (and the skip tests) stay on the scalar unit
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int F = H.F, G = H.G, B = H.B;
-    const int64_t G3W = (int64_t)G * G * G * W;
-    // finger f's table starts fstride bytes after finger f-1's; qbase is shifted
-    // back by the biased index of voxel (0, 0, 0), ((G G + G) + 1) G words of W
-    const char *qbase = reinterpret_cast<const char *>(merged) - 4 * (int64_t)W * G * ((int64_t)G * G + G + 1);
-    const int64_t fstride = 4 * G3W;
+    const uint32_t GB = (uint32_t)(G >> 2), G3 = (uint32_t)G * G * G;
+    // Byte offset of finger f's table less (lattice form) the word of its
+    // window origin, or (general form) of the +G bias of each coordinate, so
+    // that it plus 4 * (word of the point's cell) addresses the finger's word.
+    // The sum is taken in 32 bits: it wraps to the right offset for every
+    // lane inside the window (the tables are far below 4 GiB).
+    const char *mbase = reinterpret_cast<const char *>(merged);
+    uint32_t koff[FM];
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+        koff[f] = 4u * ((uint32_t)f * W * G3 - (LAT ? H.lat_idx[f < F ? f : 0] : brick_word(G, G, G, GB)));
     const int NW = (N + 31) >> 5, nchunks = (N + 63) >> 6;
     float P[12];
 #pragma unroll
@@ -201,12 +223,12 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
         for (int f = 0; f < FM; ++f) acc[f] = 0;
         const int c_end = min(nchunks, (blk + 1) * 32);
         uint32_t skip[FM];
-        const uint32_t skip_all = block_skip<FM>(bounds, aff, F, G, H.inv_h, blk, nchunks, lane, skip);
+        const uint32_t skip_all = block_skip<FM, LAT>(bounds, aff, H, blk, nchunks, lane, skip);
         for (int chunk = blk * 32; chunk < c_end; ++chunk) {
             const uint32_t cbit = 1u << (chunk - blk * 32);
             if (skip_all & cbit) continue;  // no window in reach: its ballot words stay 0
-            // re-read the per-finger maps from LDS every chunk instead of pinning
-            // 12 x F registers for them: halves the register footprint
+            // re-read the maps from LDS every chunk instead of pinning their
+            // registers for the whole sweep
             asm volatile("" ::: "memory");
             const int i = chunk * 64 + lane;
             const bool valid = i < N;
@@ -224,28 +246,40 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
             float qx, qy, qz;
             query_dir(P, nx, ny, nz, qx, qy, qz);
             const int b = nearest_bin_lut4(lut, cb4, B, qx, qy, qz);
-            const uint32_t bsel4 = (uint32_t)(b >> 5) << 2;  // byte offset of the word holding bit b
-            // one 32-bit word per finger: the word of the table that holds bit b;
+            const uint32_t plane = W == 2 ? (uint32_t)(b >> 5) * G3 : 0u;
+            uint32_t word[FM];  // 0 outside the window
+            uint32_t voff = 0, ip = 0;
+            if (LAT) {
+                int Ix, Iy, Iz;
+                lattice_cell(aff[0], px, py, pz, Ix, Iy, Iz);
+                Ix = min(max(Ix, 0), 1023);
+                Iy = min(max(Iy, 0), 1023);
+                Iz = min(max(Iz, 0), 1023);
+                ip = (uint32_t)Ix | (uint32_t)Iy << 10 | (uint32_t)Iz << 20;
+                voff = (brick_word((uint32_t)Ix, (uint32_t)Iy, (uint32_t)Iz, GB) + plane) << 2;
+                asm volatile("" : "+v"(voff));  // one add per finger below, not a re-associated pair
+            }
             // all finger gathers are issued before any is consumed
-            uint32_t word[FM];
 #pragma unroll
             for (int f = 0; f < FM; ++f) {
-                word[f] = 0;
+                word[f] = 0u;
                 if (f < F && !(skip[f] & cbit)) {
-                    // window_voxel's voxel, with the -G of each coordinate moved into
-                    // the base address and only the load predicated
-                    const Affine &a = aff[f];
-                    const float ux = fmaf(a.m[0], px, fmaf(a.m[1], py, fmaf(a.m[2], pz, a.m[3])));
-                    const float uy = fmaf(a.m[4], px, fmaf(a.m[5], py, fmaf(a.m[6], pz, a.m[7])));
-                    const float uz = fmaf(a.m[8], px, fmaf(a.m[9], py, fmaf(a.m[10], pz, a.m[11])));
-                    const int Ix = (int)ux, Iy = (int)uy, Iz = (int)uz;  // biased voxel coordinates
-                    const bool in = (int)valid & (int)(min(Ix, min(Iy, Iz)) >= G) & (int)(max(Ix, max(Iy, Iz)) < 2 * G);
-                    // one uniform base and a 32-bit byte offset per lane (the tables
-                    // are far below 4 GiB): the load takes the scalar-base form
-                    const uint32_t v =
-                        mad_u24(mad_u24((uint32_t)Iz, (uint32_t)G, (uint32_t)Iy), (uint32_t)G, (uint32_t)Ix);
-                    const uint32_t boff = v * (4u * W) + bsel4 + (uint32_t)f * (uint32_t)fstride;
-                    if (in) word[f] = *reinterpret_cast<const uint32_t *>(qbase + boff);
+                    uint32_t off;
+                    bool in;
+                    if (LAT) {
+                        in = ((int)valid & (int)(((ip - H.lat_pk[f]) & H.lat_hi) == 0u)) != 0;
+                        off = voff;
+                    } else {
+                        // biased window coordinates (see window_voxel): inside iff all in [G, 2G)
+                        const Affine &a = aff[f];
+                        const float ux = fmaf(a.m[0], px, fmaf(a.m[1], py, fmaf(a.m[2], pz, a.m[3])));
+                        const float uy = fmaf(a.m[4], px, fmaf(a.m[5], py, fmaf(a.m[6], pz, a.m[7])));
+                        const float uz = fmaf(a.m[8], px, fmaf(a.m[9], py, fmaf(a.m[10], pz, a.m[11])));
+                        const int Ix = (int)ux, Iy = (int)uy, Iz = (int)uz;
+                        in = ((int)valid & (int)(min(Ix, min(Iy, Iz)) >= G) & (int)(max(Ix, max(Iy, Iz)) < 2 * G)) != 0;
+                        off = (brick_word((uint32_t)Ix, (uint32_t)Iy, (uint32_t)Iz, GB) + plane) << 2;
+                    }
+                    if (in) word[f] = *reinterpret_cast<const uint32_t *>(mbase + (off + koff[f]));
                 }
             }
             const int j2 = 2 * (chunk - blk * 32);
@@ -253,7 +287,7 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
             for (int f = 0; f < FM; ++f) {
                 if (f >= F) break;
                 if (skip[f] & cbit) continue;  // the ballot would be 0
-                const bool hit = (word[f] >> (b & 31)) & 1u;
+                const bool hit = ((word[f] >> (b & 31)) & 1u) != 0u;
                 const unsigned long long m = __ballot(hit);
                 // the chunk's two ballot halves into lanes j2, j2 + 1 (j2 is uniform)
                 acc[f] = write_lane(acc[f], (uint32_t)m, j2);
@@ -308,7 +342,7 @@ k_query_cone(DevHand H, const uint32_t *__restrict__ merged, const float *__rest
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int F = H.F, G = H.G, B = H.B;
     const float sin_hit = sqrtf(fmaxf(0.f, fmaf(-cos_hit, cos_hit, 1.f)));
-    const int64_t G3W = (int64_t)G * G * G * W;
+    const uint32_t GB = (uint32_t)(G >> 2), G3 = (uint32_t)G * G * G;
     const int NW = (N + 31) >> 5, nchunks = (N + 63) >> 6;
     float P[12];
 #pragma unroll
@@ -323,7 +357,7 @@ k_query_cone(DevHand H, const uint32_t *__restrict__ merged, const float *__rest
         for (int f = 0; f < FM; ++f) acc[f] = 0;
         const int c_end = min(nchunks, (blk + 1) * 32);
         uint32_t skip[FM];
-        const uint32_t skip_all = block_skip<FM>(bounds, aff, F, G, H.inv_h, blk, nchunks, lane, skip);
+        const uint32_t skip_all = block_skip<FM, false>(bounds, aff, H, blk, nchunks, lane, skip);
         for (int chunk = blk * 32; chunk < c_end; ++chunk) {
             const uint32_t cbit = 1u << (chunk - blk * 32);
             if (skip_all & cbit) continue;  // no window in reach: its ballot words stay 0
@@ -357,11 +391,18 @@ k_query_cone(DevHand H, const uint32_t *__restrict__ merged, const float *__rest
             for (int f = 0; f < FM; ++f) {
                 ent[f] = 0ull;
                 if (f < F && !(skip[f] & cbit)) {
-                    const int v = window_voxel(aff[f], G, px, py, pz);
-                    const uint32_t *tab = merged + f * G3W;
-                    if (valid && v >= 0) {
-                        if (W == 2) ent[f] = *reinterpret_cast<const unsigned long long *>(tab + (uint32_t)v * 2u);
-                        else ent[f] = tab[(uint32_t)v];
+                    // biased window coordinates (see window_voxel): inside iff all in [G, 2G)
+                    const Affine &a = aff[f];
+                    const float ux = fmaf(a.m[0], px, fmaf(a.m[1], py, fmaf(a.m[2], pz, a.m[3])));
+                    const float uy = fmaf(a.m[4], px, fmaf(a.m[5], py, fmaf(a.m[6], pz, a.m[7])));
+                    const float uz = fmaf(a.m[8], px, fmaf(a.m[9], py, fmaf(a.m[10], pz, a.m[11])));
+                    const unsigned ix = (unsigned)((int)ux - G), iy = (unsigned)((int)uy - G),
+                                   iz = (unsigned)((int)uz - G);
+                    if (valid && max(ix, max(iy, iz)) < (unsigned)G) {
+                        const uint32_t *tab = merged + (int64_t)f * W * G3;
+                        const uint32_t wv = brick_word(ix, iy, iz, GB);
+                        ent[f] = tab[wv];
+                        if (W == 2) ent[f] |= (unsigned long long)tab[G3 + wv] << 32;
                     }
                 }
             }
@@ -430,14 +471,18 @@ static lg_status query_domains(const lg_field *field, const float *pts, const fl
         return fail(LG_EINVAL, "null device buffer");
     hipStream_t s = as_stream(stream);
     const DevHand &H = field->dh;
-#define LG_QUERY(W, FM)                                                                                     \
-    hipLaunchKernelGGL((k_query<W, FM>), dim3(n_poses), dim3(kQueryThreads), 0, s, H, field->d_merged, pts, nrm, \
-                       n_points, poses, bounds, dom_bits, dom_count)
-    if (H.W == 1) {
-        if (H.F <= 3) LG_QUERY(1, 3); else if (H.F <= 4) LG_QUERY(1, 4); else if (H.F <= 5) LG_QUERY(1, 5); else LG_QUERY(1, 8);
+#define LG_QUERY(W, FM, LAT)                                                                                 \
+    hipLaunchKernelGGL((k_query<W, FM, LAT>), dim3(n_poses), dim3(kQueryThreads), 0, s, H, field->d_merged, pts, \
+                       nrm, n_points, poses, bounds, dom_bits, dom_count)
+#define LG_QUERY_F(W, LAT)                                                                                   \
+    if (H.F <= 3) LG_QUERY(W, 3, LAT); else if (H.F <= 4) LG_QUERY(W, 4, LAT);                               \
+    else if (H.F <= 5) LG_QUERY(W, 5, LAT); else LG_QUERY(W, 8, LAT)
+    if (H.lat) {
+        if (H.W == 1) { LG_QUERY_F(1, true); } else { LG_QUERY_F(2, true); }
     } else {
-        if (H.F <= 3) LG_QUERY(2, 3); else if (H.F <= 4) LG_QUERY(2, 4); else if (H.F <= 5) LG_QUERY(2, 5); else LG_QUERY(2, 8);
+        if (H.W == 1) { LG_QUERY_F(1, false); } else { LG_QUERY_F(2, false); }
     }
+#undef LG_QUERY_F
 #undef LG_QUERY
     LG_HIP(hipGetLastError());
     return LG_OK;

@@ -259,8 +259,7 @@ __device__ __forceinline__ void realize_sets(float *cb, float (*caps)[DM][6], LG
                 // reverse lookup: witness sample of (link, voxel(p), bin(n))
                 int32_t w = kNoWitness;
                 if (wit) {
-                    const Affine af = finger_affine(H, P, f);
-                    const int v = window_voxel(af, H.G, ox, oy, oz);
+                    const int v = finger_window_voxel(H, P, f, ox, oy, oz);
                     const int b = nearest_bin(cb, H.B, n[0], n[1], n[2]);
                     if (v >= 0) w = wit[((int64_t)l * H.G * H.G * H.G + v) * H.B + b];
                 }

@@ -65,8 +65,7 @@ __device__ inline int pick_link(const DevHand &H, const uint32_t *__restrict__ b
                                 const float *pose, int i, int idx, uint32_t r)
 {
     const int64_t G3 = (int64_t)H.G * H.G * H.G;
-    const Affine a = finger_affine(H, pose, i);
-    const int v = window_voxel(a, H.G, pts[idx], pts[N + idx], pts[2 * N + idx]);
+    const int v = finger_window_voxel(H, pose, i, pts[idx], pts[N + idx], pts[2 * N + idx]);
     float qx, qy, qz;
     query_dir(pose, nrm[idx], nrm[N + idx], nrm[2 * N + idx], qx, qy, qz);
     const int b = nearest_bin(cb, H.B, qx, qy, qz);

@@ -287,22 +287,45 @@ class FieldParams:
 # the finger's reach (total link length + radius).  Flexion curls towards -y,
 # so the reachable set lies mostly on the palm side (-y) and above the palm.
 GRID_CENTER_FRAC = (0.0, -0.30, 0.22)
-# Lateral shift of the window (voxel units) so that the flexion plane of a
-# planar finger does not coincide with a voxel face.
-GRID_LATERAL_SHIFT = 0.37
+# Shift of the window lattice off the hand frame's planes (voxel units), so
+# that symmetry planes of the hand (a planar finger's flexion plane through a
+# base axis) do not coincide with voxel faces.
+GRID_LATTICE_SHIFT = (0.37, 0.29, 0.41)
+# Window origins sit on a lattice of this many voxels (the field's brick edge).
+GRID_SNAP = 4
 
 
 def grid_frames(hand: Hand, G: int, h: float) -> np.ndarray:
-    """Per-finger grid frames: axes aligned with the finger base frame, the
-    G^3 window centred at a fixed fraction of the finger's reach.  No
-    kinematics is evaluated; only link lengths enter."""
+    """Per-finger grid frames, all with the axes of the hand (palm) frame.
+    Finger f's G^3 window is centred near a fixed fraction of the finger's
+    reach, placed along the finger's base frame; its origin is snapped to a
+    lattice of GRID_SNAP voxels shifted by GRID_LATTICE_SHIFT, shared by all
+    fingers, so the windows differ by whole bricks.  No kinematics is
+    evaluated; only link lengths enter."""
+    out = []
+    shift = np.array(GRID_LATTICE_SHIFT) * h
+    for f in range(hand.n_fingers):
+        js = hand.finger_joints(f)
+        reach = float(hand.capsule[js, 5].astype(np.float64).sum() + hand.capsule[js[0], 6])
+        Rb = hand.finger_base[f][:, :3].astype(np.float64)
+        tb = hand.finger_base[f][:, 3].astype(np.float64)
+        centre = tb + Rb @ (np.array(GRID_CENTER_FRAC) * reach)
+        step = GRID_SNAP * h
+        o = np.round((centre - 0.5 * G * h - shift) / step) * step + shift
+        out.append(_pack34(np.eye(3), o))
+    return np.asarray(out, np.float64).astype(np.float32)
+
+
+def grid_frames_finger_aligned(hand: Hand, G: int, h: float) -> np.ndarray:
+    """Per-finger grid frames with the axes of each finger's base frame (no
+    shared rotation, no common lattice): windows mapped finger by finger."""
     out = []
     for f in range(hand.n_fingers):
         js = hand.finger_joints(f)
         reach = float(hand.capsule[js, 5].astype(np.float64).sum() + hand.capsule[js[0], 6])
         Rb = hand.finger_base[f][:, :3]
         tb = hand.finger_base[f][:, 3]
-        c_local = np.array(GRID_CENTER_FRAC) * reach + np.array([GRID_LATERAL_SHIFT * h, 0.0, 0.0])
+        c_local = np.array(GRID_CENTER_FRAC) * reach + np.array([GRID_LATTICE_SHIFT[0] * h, 0.0, 0.0])
         o_local = c_local - 0.5 * G * h
         o = tb + Rb @ o_local
         out.append(_pack34(Rb, o))

@@ -119,8 +119,12 @@ def test_cone_domains_through_search_and_realize():
     cos_hit = float(np.float32(math.cos(math.radians(15.0))))
     Q = oracle.query_cone(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses, cos_hit)
     Q = {"dom_bits": Q["dom_bits"], "dom_count": Q["dom_count"]}
-    spt, sln, ver, acc = _search_check(w, ref["bits"], Q)
+    _search_check(w, ref["bits"], Q)
+    # realize on the oracle's own sets (stage isolated)
     k = w.search.k
+    spt, sln = oracle.draw(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses, Q["dom_bits"],
+                           Q["dom_count"], w.search)
+    acc = oracle.compact(oracle.verdicts(w.obj.pts, w.obj.nrm, spt, w.search)["verdict"])
     S, L = spt.reshape(-1, k), sln.reshape(-1, k)
     assert (L[acc] < 0).any(), "no accepted set with a contact lacking a link"
     acc = acc[:1500]

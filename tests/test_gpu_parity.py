@@ -231,6 +231,49 @@ def test_query_c3_full_shape_sampled_poses():
 
 
 # ---------------------------------------------------------------------------
+# window forms: the synthetic windows share the hand frame's axes and lie whole
+# 4-voxel bricks apart (lattice form, one map per point); windows aligned with
+# each finger's base, or off the brick lattice, are mapped finger by finger
+# ---------------------------------------------------------------------------
+def _with_frames(w, gf):
+    import dataclasses
+    return dataclasses.replace(w, field=dataclasses.replace(w.field, grid_frame=gf))
+
+
+def test_window_forms_reported():
+    lg = lgmod()
+    for name in ("c1", "c2", "c3"):
+        w = synth.workload(name, samples=64, n_poses=4, n_points=64, with_sdf=False)
+        f = lg.lg_build_field(w.hand, w.field)
+        assert f.info()["lattice"] == 1, name
+        f.release()
+        f = lg.lg_build_field(w.hand, _with_frames(w, synth.grid_frames_finger_aligned(w.hand, w.field.grid,
+                                                                                         w.field.h)).field)
+        assert f.info()["lattice"] == 0, name
+        f.release()
+        off = w.field.grid_frame.copy()
+        off[-1, 3] += np.float32(w.field.h)       # one voxel: not a whole brick
+        f = lg.lg_build_field(w.hand, _with_frames(w, off).field)
+        assert f.info()["lattice"] == 0, name
+        f.release()
+
+
+@pytest.mark.parametrize("name", ["c1", "c3"])
+def test_query_windows_mapped_per_finger(name):
+    """The general form (each finger's window mapped on its own) against the
+    oracle, plain and bounded, with windows aligned with the finger bases."""
+    kw = {"samples": 4096, "n_points": 8192, "n_poses": 64} if name == "c3" else {"n_poses": 96}
+    w = synth.workload(name, with_sdf=False, **kw)
+    w = _with_frames(w, synth.grid_frames_finger_aligned(w.hand, w.field.grid, w.field.h))
+    ref = oracle.build_field(w.hand, w.field, flags=False)
+    assert lgmod().lg_field_import(w.hand, w.field, ref["bits"]).info()["lattice"] == 0
+    Q, _ = _query_check(w, ref["bits"])
+    assert Q["dom_count"].sum() > 0
+    _query_check(w, ref["bits"], bounded=True)
+    _search_check(w, ref["bits"], Q)
+
+
+# ---------------------------------------------------------------------------
 # bounded query: chunk bounding spheres skip (chunk, finger) pairs out of reach;
 # the outputs must be those of the plain query, bit for bit
 # ---------------------------------------------------------------------------
@@ -314,11 +357,12 @@ def _search_check(w, ref_bits, Q, pose_sel=None):
     tst = bufs.tstar.cpu().numpy()
     n_acc = int(bufs.n_acc.item())
     acc = bufs.acc_list[:n_acc].cpu().numpy()
-    o_spt, o_sln = oracle.draw(w.hand, w.field, ref_bits, w.obj.pts, w.obj.nrm, w.poses, Q["dom_bits"],
-                               Q["dom_count"], w.search)
+    o_spt, o_sln, o_lf = oracle.draw(w.hand, w.field, ref_bits, w.obj.pts, w.obj.nrm, w.poses, Q["dom_bits"],
+                                     Q["dom_count"], w.search, link_flags=True)
     assert (spt == o_spt).all(), "drawn point indices differ"
     link_mis = (sln != o_sln)
-    assert link_mis.sum() <= max(1, 1e-4 * sln.size), "drawn links differ"
+    assert (link_mis & (o_lf == 0)).sum() == 0, "drawn links differ outside the rounding bands"
+    assert link_mis.sum() <= max(1, 1e-3 * sln.size), "drawn links differ"
     V = oracle.verdicts(w.obj.pts, w.obj.nrm, o_spt, w.search)
     vo = V["verdict"].reshape(ver.shape)
     vf = V["vflag"].reshape(ver.shape).astype(bool)
@@ -371,15 +415,22 @@ def test_search_c3_full_shape_as_benchmarked():
     assert n_acc > 0
     assert (bufs.acc_list[:n_acc].cpu().numpy() == np.flatnonzero(ver_all)).all(), "compaction order"
     sel = np.sort(np.random.default_rng(11).choice(w.poses.shape[0], size=8, replace=False))
+    tainted = 0
     for g in sel:
         g = int(g)
-        gb = db[g:g + 1].cpu().numpy().view(np.uint32)
-        gc = dc[g:g + 1].cpu().numpy().view(np.uint32)
+        # the oracle's own domains of the pose; a pose whose GPU domains differ
+        # (only ever in flagged bits, see the query tests) is tainted downstream
+        Qg = oracle.query(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses[g:g + 1], flags=False)
+        if not (np.array_equal(db[g:g + 1].cpu().numpy().view(np.uint32), Qg["dom_bits"])):
+            tainted += 1
+            continue
         sp = dataclasses.replace(w.search, pose_offset=g)
-        o_spt, o_sln = oracle.draw(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses[g:g + 1], gb, gc, sp)
+        o_spt, o_sln, o_lf = oracle.draw(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses[g:g + 1],
+                                         Qg["dom_bits"], Qg["dom_count"], sp, link_flags=True)
         spt = bufs.set_pt[g].cpu().numpy()
         sln = bufs.set_link[g].cpu().numpy().astype(np.int32)
-        assert (spt == o_spt[0]).all() and (sln == o_sln[0]).all(), g
+        assert (spt == o_spt[0]).all(), g
+        assert ((sln != o_sln[0]) & (o_lf[0] == 0)).sum() == 0, g
         V = oracle.verdicts(w.obj.pts, w.obj.nrm, o_spt, sp)
         ver = ver_all[g * D:(g + 1) * D]
         assert ((ver != V["verdict"].reshape(-1)) & ~V["vflag"].reshape(-1).astype(bool)).sum() == 0, g
@@ -387,6 +438,7 @@ def test_search_c3_full_shape_as_benchmarked():
         ot = V["tstar"].reshape(-1)
         fin = ~np.isnan(ot)
         assert np.allclose(tst[fin], ot[fin], atol=1e-9, rtol=0) and np.isnan(tst[~fin]).all(), g
+    assert tainted <= 1, tainted
 
 
 def test_search_pivot_cap_gives_no_verdict():
@@ -441,8 +493,9 @@ def test_realize_c3_shape():
 
 def test_realize_c3_full_shape_as_benchmarked():
     """The realize launch the benchmark times: every accepted set of a full-shape
-    C3 step (65,536 poses, bounded query, search) in one launch; 1,024 sampled
-    accepted sets recomputed by the oracle.  Bars as for the reduced shape."""
+    C3 step (65,536 poses, bounded query, search) in one launch; the accepted
+    sets of 48 sampled poses recomputed by the oracle from its own domains and
+    draws.  Bars as for the reduced shape."""
     import dataclasses
     lg = lgmod()
     w = synth.workload("c3", samples=4096)
@@ -464,14 +517,48 @@ def test_realize_c3_full_shape_as_benchmarked():
                        sb.n_acc, n_acc, w.ik, sp=w.search)
     torch.cuda.synchronize()
     acc = sb.acc_list[:n_acc].cpu().numpy()
-    pick = np.sort(np.random.default_rng(13).choice(n_acc, size=1024, replace=False))
-    spt = sb.set_pt.cpu().numpy().reshape(-1, k)
-    sln = sb.set_link.cpu().numpy().astype(np.int32).reshape(-1, k)
-    R = oracle.realize(w.hand, w.field, ref["wit"], w.sdf, w.obj.pts, w.obj.nrm, w.poses, spt, sln, w.search,
-                       acc[pick], w.ik)
-    check_realize(w.hand, R, rb.q[:n_acc].cpu().numpy()[pick], rb.contact_err[:n_acc].cpu().numpy()[pick],
-                  rb.depth[:n_acc].cpu().numpy()[pick], rb.valid[:n_acc].cpu().numpy()[pick])
-    assert R["valid"].sum() > 0
+    D = w.search.draws
+    gpu_spt = sb.set_pt.cpu().numpy().reshape(-1, k)
+    gpu_sln = sb.set_link.cpu().numpy().astype(np.int32).reshape(-1, k)
+    db_h = db.cpu().numpy().view(np.uint32)
+    # sampled poses with accepted sets: the oracle's own domains (the GPU's
+    # differ from them only in flagged bits), draws and verdicts of the pose at
+    # its global index, then its realize of the pose's accepted sets whose
+    # points and links are the GPU's too, against the GPU's rows of those sets.
+    # A set drawn differently (downstream of a flagged domain bit or link) is
+    # tainted and left out.
+    poses_acc = np.unique(acc // D)
+    sel = np.sort(np.random.default_rng(13).choice(poses_acc, size=48, replace=False))
+    rows, R_all, n_tainted, n_sets = [], [], 0, 0
+    for g in sel:
+        g = int(g)
+        sp = dataclasses.replace(w.search, pose_offset=g)
+        Qg = oracle.query(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses[g:g + 1])
+        assert (((db_h[g:g + 1] ^ Qg["dom_bits"]) & ~Qg["dom_flag"]) == 0).all(), g
+        o_spt, o_sln = oracle.draw(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses[g:g + 1],
+                                   Qg["dom_bits"], Qg["dom_count"], sp)
+        V = oracle.verdicts(w.obj.pts, w.obj.nrm, o_spt, sp)
+        o_acc = oracle.compact(V["verdict"])
+        mine = np.flatnonzero(acc // D == g)
+        d_gpu = acc[mine] - g * D
+        same_set = ((o_spt.reshape(-1, k) == gpu_spt[g * D:(g + 1) * D]).all(-1) &
+                    (o_sln.reshape(-1, k) == gpu_sln[g * D:(g + 1) * D]).all(-1))
+        both = np.intersect1d(o_acc, d_gpu)
+        both = both[same_set[both]]
+        n_sets += len(d_gpu)
+        n_tainted += len(d_gpu) - len(both)
+        if len(both) == 0:
+            continue
+        R_all.append(oracle.realize(w.hand, w.field, ref["wit"], w.sdf, w.obj.pts, w.obj.nrm, w.poses[g:g + 1],
+                                    o_spt.reshape(-1, k), o_sln.reshape(-1, k), sp, both, w.ik))
+        rows.append(mine[np.searchsorted(d_gpu, both)])
+    assert n_tainted <= 0.5 * n_sets, (n_tainted, n_sets)
+    rows = np.concatenate(rows)
+    assert len(rows) >= 150, len(rows)
+    R = {key: np.concatenate([r[key] for r in R_all]) for key in R_all[0]}
+    check_realize(w.hand, R, rb.q[:n_acc].cpu().numpy()[rows], rb.contact_err[:n_acc].cpu().numpy()[rows],
+                  rb.depth[:n_acc].cpu().numpy()[rows], rb.valid[:n_acc].cpu().numpy()[rows])
+    assert len(rows) >= 256 and R["valid"].sum() > 0
 
 
 def test_realize_c1_sphere():

@@ -171,3 +171,71 @@ def test_unrealisable_sets(c3k):
     with pytest.raises(ValueError):
         oracle.realize(H, w.field, fld["wit"], w.sdf, w.obj.pts, w.obj.nrm, w.poses, S, L, sp,
                        np.array([len(w.poses) * sp.draws], np.int32), w.ik)
+
+
+def test_link_flags_cover_every_band_decision():
+    """The reverse lookup's band flag (Sec. 5.5 link pick): moving each pose
+    by 8e-7 m along an axis, or turning it by 8e-7 rad about one, never
+    changes a link the oracle does not flag (the bands are 1e-6 m and
+    1e-6 rad); on poses moved to put a contact 3e-7 m from a voxel face, the
+    links that do change across it are all flagged, and some do."""
+    w = synth.workload("c1", n_poses=96)
+    ref = oracle.build_field(w.hand, w.field, flags=False)
+    Q = oracle.query(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses, flags=False)
+    spt, sln, lf = oracle.draw(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses, Q["dom_bits"],
+                               Q["dom_count"], w.search, link_flags=True)
+    # relink on the same points gives the same links and flags
+    s2, f2 = oracle.relink(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses, spt, w.search,
+                           dom_count=Q["dom_count"], link_flags=True)
+    assert np.array_equal(s2, sln) and np.array_equal(f2, lf)
+    on = spt >= 0
+    P0 = w.poses.astype(np.float64).reshape(-1, 3, 4)
+    for axis in range(3):
+        for sgn in (-1.0, 1.0):
+            for kind in ("move", "turn"):
+                P = P0.copy()
+                if kind == "move":
+                    P[:, axis, 3] += sgn * 8e-7
+                else:
+                    a = sgn * 8e-7
+                    c, s = math.cos(a), math.sin(a)
+                    i, j = [(1, 2), (2, 0), (0, 1)][axis]
+                    Rt = np.eye(3)
+                    Rt[i, i], Rt[i, j], Rt[j, i], Rt[j, j] = c, -s, s, c
+                    P[:, :, :3] = Rt @ P[:, :, :3]
+                ln = oracle.relink(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm,
+                                   P.reshape(-1, 12).astype(np.float32), spt, w.search, dom_count=Q["dom_count"])
+                ch = on & (ln != sln)
+                assert (ch & (lf == 0)).sum() == 0, (axis, sgn, kind)
+    assert lf[on].mean() < 0.02
+    # poses moved so that a contact's point lies 3e-7 m from a voxel face of
+    # its finger's window (the synthetic windows have the hand frame's axes):
+    # the link must be flagged wherever the other side gives another link
+    h = float(np.float32(w.field.h))
+    D, k = w.search.draws, w.search.k
+    rng = np.random.default_rng(5)
+    cand = np.argwhere(on.reshape(-1, k))
+    differ = 0
+    for s_, i in cand[rng.choice(len(cand), size=240, replace=False)]:
+        g = s_ // D
+        f = int(w.hand.joint_finger[sln.reshape(-1, k)[s_, i]])
+        o = w.field.grid_frame[f].reshape(3, 4)[:, 3].astype(np.float64)
+        x = P0[g, :, :3] @ w.obj.pts[spt.reshape(-1, k)[s_, i]].astype(np.float64) + P0[g, :, 3]
+        a = int(rng.integers(3))
+        u = (x[a] - o[a]) / h
+        Pg = P0[g:g + 1].copy()
+        Pg[0, a, 3] += (np.round(u) - u) * h + 3e-7
+        sp1 = dataclasses.replace(w.search, pose_offset=g)
+        one = spt[g:g + 1]
+        base, fl = oracle.relink(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm,
+                                 Pg.reshape(-1, 12).astype(np.float32), one, sp1,
+                                 dom_count=Q["dom_count"][g:g + 1], link_flags=True)
+        for sgn in (-1.0, 1.0):
+            Pm = Pg.copy()
+            Pm[0, a, 3] += sgn * 8e-7
+            ln = oracle.relink(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm,
+                               Pm.reshape(-1, 12).astype(np.float32), one, sp1, dom_count=Q["dom_count"][g:g + 1])
+            ch = (one >= 0) & (ln != base)
+            assert (ch & (fl == 0)).sum() == 0, (s_, i, a, sgn)
+            differ += int(ch.sum())
+    assert differ > 0
