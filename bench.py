@@ -27,6 +27,7 @@ if ROOT not in sys.path:
 
 METRIC = "valid grasps/sec per object (1 GPU); field-query HBM GB/s; p50/p99 latency"
 HBM_PEAK_GBPS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
 
 DESCR = {
     "c1": "3-finger 9-DOF hand, sphere R=40mm N=2048, P=256, D=16, k=3, field 32^3@4mm B=32 S=8192",
@@ -116,6 +117,68 @@ def query_traffic():
     if not m or not t or m.group(1) != h.hexdigest():
         return None
     return int(t.group(1))
+
+
+def counter_summary(name: str, sources: tuple) -> dict | None:
+    """Per-launch counter values (lines ``- <key> per launch: <number>``) of a
+    committed counter summary under profiles/, or None when it is missing or
+    the kernel sources changed since it was taken (its ``source sha256`` line
+    is the sha256 of ``sources`` in order)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    h = hashlib.sha256()
+    for f in sources:
+        h.update(open(os.path.join(ROOT, "paper_2511_07418_amd", "csrc", f), "rb").read())
+    m = re.search(r"source sha256: ([0-9a-f]{64})", txt)
+    if not m or m.group(1) != h.hexdigest():
+        return None
+    return {k: float(v) for k, v in re.findall(r"^- ([A-Za-z0-9_ ]+?) per launch: ([0-9.eE+-]+)", txt, re.M)}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def build_flops(w, vectors: int, dropped: int) -> float:
+    """FP32 FLOPs of the field build as the kernel computes them (FMA = 2):
+    per (joint sample, link) the joint frame (two 3x4 products, 63 each, the
+    first joint of a finger has one; Rodrigues 34) and the composite window
+    map (84); per contact vector the window map (18); per contact vector inside
+    the window the normal (15) and the nearest of the B bin centres by their
+    definition (5 B)."""
+    hand, S, B = w.hand, w.field.samples, w.field.bins
+    per_sample = 0
+    for f in range(hand.n_fingers):
+        d = len(hand.finger_joints(f))
+        per_sample += d * (63 + 34 + 84) + (d - 1) * 63
+    return float(S) * per_sample + 18.0 * vectors + (15.0 + 5.0 * B) * (vectors - dropped)
+
+
+def realize_flops_per_set(w) -> float:
+    """Algorithmic FP32 FLOPs per accepted set (FMA = 2): 10 iterations x sum
+    over fingers of (40 d FK + 12 d Jacobian + 6 d^2 J^T J + d^3/3 Cholesky)
+    multiply-adds, and the penetration test's axis samples (one per mm, ends
+    included) at 63 FLOP each (two rigid transforms, trilinear weights and
+    seven interpolations)."""
+    hand, it = w.hand, int(w.ik.iters)
+    fma = 0.0
+    for f in range(hand.n_fingers):
+        d = len(hand.finger_joints(f))
+        fma += 40 * d + 12 * d + 6 * d * d + d ** 3 / 3.0
+    cap = hand.capsule.astype(np.float64)
+    L = np.linalg.norm(cap[:, 3:6] - cap[:, 0:3], axis=1)
+    samples = float(np.sum(np.ceil(L / 1e-3) + 1))
+    return 2.0 * it * fma + 63.0 * samples
 
 
 def serve_bench(torch, lg, rate: float, seconds: float, seed: int = 0, alone_sample: int = 40) -> dict:
@@ -387,38 +450,46 @@ def proposer_bench(torch, lg, pool, n_train: int, n_eval: int, epochs: int, seed
     return out
 
 
-def cpu_baseline(w, n_poses: int, samples: int) -> dict:
-    """The FP64 oracle, as it stands, on the first ``n_poses`` poses: query,
-    draws, verdicts, compaction and (with an SDF) IK + penetration.  Its field
-    is the oracle's own, built untimed with ``samples`` joint samples per
-    finger (the step itself does not depend on S, only the field density)."""
-    import dataclasses
-
+def cpu_baseline(w, n_all: int, n_one: int) -> dict:
+    """The FP64 oracle, as it stands, on the same workload: its own field built
+    with the GPU's joint-sample count S (untimed), then query, draws, verdicts,
+    compaction and (with an SDF) IK + penetration on the first ``n_all``
+    poses with every host thread, and on the first ``n_one`` poses with one."""
     import oracle
-    import synth
 
-    fp = dataclasses.replace(w.field, samples=min(samples, w.field.samples))
-    sub = synth.Workload(name=w.name, hand=w.hand, field=fp, obj=w.obj, poses=w.poses[:n_poses],
-                         search=w.search, ik=w.ik, sdf=w.sdf)
-    fld = oracle.build_field(sub.hand, sub.field, witness=sub.ik is not None, flags=False)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    t0 = time.perf_counter()
-    Q = oracle.query(sub.hand, sub.field, fld["bits"], sub.obj.pts, sub.obj.nrm, sub.poses, flags=False)
-    spt, sln = oracle.draw(sub.hand, sub.field, fld["bits"], sub.obj.pts, sub.obj.nrm, sub.poses,
-                           Q["dom_bits"], Q["dom_count"], sub.search)
-    V = oracle.verdicts(sub.obj.pts, sub.obj.nrm, spt, sub.search)
-    acc = oracle.compact(V["verdict"])
-    n_valid = len(acc)
-    if sub.ik is not None and len(acc):
-        k = sub.search.k
-        R = oracle.realize(sub.hand, sub.field, fld["wit"], sub.sdf, sub.obj.pts, sub.obj.nrm, sub.poses,
-                           spt.reshape(-1, k), sln.reshape(-1, k), sub.search, acc, sub.ik)
-        n_valid = int(R["valid"].sum())
-    dt = time.perf_counter() - t0
-    return {"value": n_valid / dt, "unit": "valid grasps/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n_poses} of {w.poses.shape[0]} poses of the same workload, full N and D; "
-                      f"oracle-built field with S={fp.samples} (untimed); {n_valid} valid grasps in {dt:.2f} s",
-            "seconds": dt, "poses_per_s": n_poses / dt}
+    fld = oracle.build_field(w.hand, w.field, witness=w.ik is not None, flags=False)
+    all_threads = oracle.get_threads()
+
+    def run(n: int) -> tuple:
+        poses = w.poses[:n]
+        t0 = time.perf_counter()
+        Q = oracle.query(w.hand, w.field, fld["bits"], w.obj.pts, w.obj.nrm, poses, flags=False)
+        spt, sln = oracle.draw(w.hand, w.field, fld["bits"], w.obj.pts, w.obj.nrm, poses, Q["dom_bits"],
+                               Q["dom_count"], w.search)
+        V = oracle.verdicts(w.obj.pts, w.obj.nrm, spt, w.search)
+        acc = oracle.compact(V["verdict"])
+        n_valid = len(acc)
+        if w.ik is not None and len(acc):
+            k = w.search.k
+            R = oracle.realize(w.hand, w.field, fld["wit"], w.sdf, w.obj.pts, w.obj.nrm, poses,
+                               spt.reshape(-1, k), sln.reshape(-1, k), w.search, acc, w.ik)
+            n_valid = int(R["valid"].sum())
+        return n_valid, time.perf_counter() - t0
+
+    v_all, t_all = run(n_all)
+    oracle.set_threads(1)
+    try:
+        v_one, t_one = run(n_one)
+    finally:
+        oracle.set_threads(all_threads)
+    return {"value": v_all / t_all, "unit": "valid grasps/s", "cores": all_threads, "kind": "oracle",
+            "sample": f"first {n_all} of {w.poses.shape[0]} poses of the same workload (full N and D, the "
+                      f"oracle's own field at S = {w.field.samples}, built untimed): {v_all} valid grasps in "
+                      f"{t_all:.2f} s on {all_threads} threads",
+            "cpu_model": cpu_model(), "seconds": t_all, "poses_per_s": n_all / t_all,
+            "single_thread": {"value": v_one / t_one, "unit": "valid grasps/s", "cores": 1,
+                              "sample": f"first {n_one} poses: {v_one} valid grasps in {t_one:.2f} s",
+                              "seconds": t_one, "poses_per_s": n_one / t_one}}
 
 
 def main():
@@ -600,12 +671,13 @@ def main():
     ms_per_step = wall * 1000.0 / args.steps
     value = n_valid / (ms_per_step / 1000.0)
 
-    # query roofline.  Algorithmic bytes per launch (per-unit figures of the
-    # method): one W-byte field word (W = B/8) per in-window (pose, point,
-    # link) lookup, the domain bits written (P*F*ceil(N/32)*4), 48 B per pose
-    # and 24 B per point.  The kernel itself reads one 4-byte word per
-    # in-window (pose, point, finger) from the merged finger tables; those
-    # bytes are reported as impl_bytes_per_launch.
+    # Query roofline (HBM, the gather bound of the method).  Algorithmic bytes
+    # per launch: 4 B per in-window (pose, point, finger) lookup -- the word of
+    # the finger's merged table (the OR of its links' tables, Sec. 5.3) that
+    # holds the query's bin -- plus the domain bits written (P*F*ceil(N/32)*4),
+    # the counts (4*P*F), 48 B per pose and 24 B per point.  The per-link
+    # figure (B/8 bytes per in-window (pose, point, link) lookup, as if each
+    # link's table were read) is kept as a labelled diagnostic.
     W = w.field.bins // 8
     per_finger = in_window_lookups(torch, pipe, w)
     dof = w.hand.dof
@@ -614,10 +686,51 @@ def main():
     F = w.hand.n_fingers
     NW = (pipe.N + 31) // 32
     out_bytes = pipe.P * F * NW * 4 + pipe.P * F * 4 + pipe.P * 48 + pipe.N * 24
-    alg_bytes = link_lookups * W + out_bytes
-    impl_bytes = finger_lookups * 4 + out_bytes
+    alg_bytes = finger_lookups * 4 + out_bytes
+    link_bytes = link_lookups * W + out_bytes
     q_ms = float(st[:, 0].mean())
-    achieved = alg_bytes / (q_ms * 1e-3) / 1e9
+    q_s = q_ms * 1e-3
+    achieved = alg_bytes / q_s / 1e9
+    # counters of the default c3 launch (canonical poses, all points, nearest bin)
+    canonical = (args.placement == "canonical" and not args.cone_deg and not args.concave_filter
+                 and args.workload == "c3" and args.seed == 0 and not args.palm_prob)
+    qc = counter_summary("k_query_c3_counters.md", ("query.hip", "lg_internal.h")) if canonical else None
+    issue = None
+    if qc:
+        miss_bytes = qc["TCC_MISS_sum"] * 128.0
+        issue = {"valu_wave_instr_per_launch": qc["SQ_INSTS_VALU"], "salu_instr_per_launch": qc["SQ_INSTS_SALU"],
+                 "valu_g_per_s": qc["SQ_INSTS_VALU"] / q_s / 1e9,
+                 "valu_issue_limit_g_per_s": 1024 * 2.4 / 4.0,
+                 "l2_miss_bytes_per_launch": miss_bytes, "l2_miss_gbps": miss_bytes / q_s / 1e9,
+                 "l2_miss_frac_of_hbm_peak": miss_bytes / q_s / 1e9 / HBM_PEAK_GBPS,
+                 "l2_hit_rate": qc["TCC_HIT_sum"] / (qc["TCC_HIT_sum"] + qc["TCC_MISS_sum"])}
+    # FP32 FLOP fractions of FK (the field build) and IK (realize) against the
+    # 157.3 TFLOP/s FP32 vector peak: algorithmic counts (build_flops,
+    # realize_flops_per_set) and the VALU FP32 counters (64 lanes per
+    # wave-instruction, FMA = 2) of the committed summary
+    finfo = field.info()
+    fc = counter_summary("fp32_flops_c3.md", ("field.hip", "realize.hip", "lg_internal.h")) if canonical else None
+    r_ms = float(st[:, 2].mean())
+    fp32 = {"peak_tflops": FP32_PEAK_TFLOPS}
+    b_ms = float(finfo["build_kernel_ms"])
+    if b_ms > 0:
+        bf = build_flops(w, int(finfo["vectors"]), int(finfo["dropped"]))
+        fp32["fk_field_build"] = {"kernel": "k_field_build", "ms": b_ms, "alg_gflop": bf / 1e9,
+                                  "alg_tflops": bf / (b_ms * 1e-3) / 1e12,
+                                  "alg_frac": bf / (b_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS}
+        if fc:
+            cf = fc["k_field_build SQ_INSTS_VALU_FLOPS_FP32"] * 64.0
+            fp32["fk_field_build"].update({"counter_gflop": cf / 1e9,
+                                           "counter_frac": cf / (b_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS})
+    if w.ik is not None and n_acc > 0:
+        rf = realize_flops_per_set(w) * n_acc
+        fp32["ik_realize"] = {"kernel": "k_realize", "ms": r_ms, "sets": n_acc, "alg_gflop": rf / 1e9,
+                              "alg_tflops": rf / (r_ms * 1e-3) / 1e12,
+                              "alg_frac": rf / (r_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS}
+        if fc:
+            cf = fc["k_realize SQ_INSTS_VALU_FLOPS_FP32"] * 64.0
+            fp32["ik_realize"].update({"counter_gflop": cf / 1e9,
+                                       "counter_frac": cf / (r_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS})
     out = {
         "metric": METRIC,
         "value": value,
@@ -644,14 +757,17 @@ def main():
         "query_gbps": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
-                     # the counters were taken on the default query (canonical poses, all points, nearest bin)
-                     "traffic": (query_traffic() if (args.placement == "canonical" and not args.cone_deg
-                                                     and not args.concave_filter and args.workload == "c3"
-                                                     and args.seed == 0 and not args.palm_prob) else None),
+                     "traffic": query_traffic() if canonical else None,
                      "kernel": "k_query", "alg_bytes_per_launch": alg_bytes,
-                     "in_window_link_lookups": link_lookups, "in_window_finger_lookups": finger_lookups,
-                     "impl_bytes_per_launch": impl_bytes,
-                     "impl_gbps": impl_bytes / (q_ms * 1e-3) / 1e9},
+                     "alg_per_unit": "4 B per in-window (pose, point, finger) lookup of the merged finger table, "
+                                     "P*F*ceil(N/32)*4 B domain bits, 4*P*F B counts, 48 B per pose, 24 B per point",
+                     "in_window_finger_lookups": finger_lookups,
+                     "issue": issue,
+                     "per_link_diagnostic": {"bytes_per_launch": link_bytes, "gbps": link_bytes / q_s / 1e9,
+                                             "in_window_link_lookups": link_lookups,
+                                             "note": "B/8 bytes per in-window (pose, point, link) lookup, as if "
+                                                     "every link's own table were read; not a roofline"}},
+        "fp32_flops": fp32,
     }
     out["poses_per_s"] = pipe.P / (ms_per_step / 1000.0)
     if not args.no_serve:
@@ -663,7 +779,7 @@ def main():
         out["p99_ms"] = out["serving"]["p99_ms"]
     if not args.no_cpu_baseline:
         n = args.cpu_poses or {"c1": 256, "c2": 2048, "c3": 5120}[args.workload]
-        out["cpu_baseline"] = cpu_baseline(w, n, samples=16384)
+        out["cpu_baseline"] = cpu_baseline(w, n, max(1, n // 16))
     print(json.dumps(out))
 
 

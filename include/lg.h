@@ -105,6 +105,8 @@ typedef struct {
     int32_t lattice;          /* 1: the windows share one rotation and lie whole 4-voxel bricks
                                  apart (G a power of two), so the query maps each point once for
                                  all fingers; 0: each finger's window is mapped on its own */
+    double build_kernel_ms;   /* duration of the sampling + binning kernel of lg_build_field (HIP
+                                 events on its stream); 0 for an imported field */
 } lg_field_info_t;
 
 /*

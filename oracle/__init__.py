@@ -135,6 +135,9 @@ def lib():
         L.orc_optimize_outcomes.restype = C.c_int
         L.orc_relink.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, i32, vp, vp, u64, C.c_uint32, i64, vp, vp]
         L.orc_relink.restype = C.c_int
+        L.orc_extend.argtypes = [vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, i32, i32, vp, vp, vp, i32, u64,
+                                 C.c_uint32, i64, vp, vp, vp]
+        L.orc_extend.restype = C.c_int
         L.orc_segment_distance.argtypes = [vp, vp, vp, vp]
         L.orc_segment_distance.restype = dbl
         L.orc_self_penetration.argtypes = [vp, vp]
@@ -597,6 +600,32 @@ def relink(hand, fp, bits, pts, nrm, poses, set_pt, sp, dom_count=None, link_fla
     if rc != 0:
         raise ValueError(f"orc_relink failed ({rc})")
     return (sln, lfl) if link_flags else sln
+
+
+def extend(hand, fp, bits, pts, nrm, poses, dom_bits, dom_count, set_pt, set_link, take, k_add: int, sp,
+           request_id: int = 0) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Second contact round on the unused fingers: ``k_add`` more contacts for
+    each round-1 set marked in ``take`` [P, D] (round-1 sets ``set_pt``,
+    ``set_link`` [P, D, k1] of the search ``sp``: its seed and pose offset key
+    the draws, ``request_id`` is this round's).  Returns the extended sets
+    ``set_pt``, ``set_link`` int32 [P, D, k1 + k_add] (all -1 where not
+    extended) and the new links' band flags (see ``draw``)."""
+    pts, nrm, poses = _c(pts, np.float32), _c(nrm, np.float32), _c(poses, np.float32)
+    s1, l1 = _c(set_pt, np.int32), _c(set_link, np.int32)
+    P, D, k1 = s1.shape
+    k2 = k1 + int(k_add)
+    spt = np.zeros((P, D, k2), np.int32)
+    sln = np.zeros((P, D, k2), np.int32)
+    lfl = np.zeros((P, D, k2), np.uint8)
+    H, Fp = _hand(hand), _field(fp)
+    rc = lib().orc_extend(H.ref, Fp.ref, _p(_c(bits, np.uint32)), _p(pts), _p(nrm), pts.shape[0], _p(poses), P,
+                          _p(_c(dom_bits, np.uint32)), _p(_c(dom_count, np.uint32)), D, k1, _p(s1), _p(l1),
+                          _p(_c(np.asarray(take).reshape(P, D), np.uint8)), int(k_add),
+                          int(sp.seed) & 0xFFFFFFFFFFFFFFFF, int(request_id), int(sp.pose_offset), _p(spt),
+                          _p(sln), _p(lfl))
+    if rc != 0:
+        raise ValueError(f"orc_extend failed ({rc})")
+    return spt, sln, lfl
 
 
 def compact(verdict) -> np.ndarray:

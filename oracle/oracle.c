@@ -49,6 +49,8 @@ int orc_get_threads(void) { return omp_get_max_threads(); }
 #define PURPOSE_FINGERS 13u
 #define PURPOSE_UNUSED 15u
 #define PURPOSE_PALM 17u
+#define PURPOSE_EXT_FINGERS 19u
+#define PURPOSE_EXT_DRAW 21u
 #define OPT_TAU 1e-9    /* candidates within OPT_TAU of the best criterion value tie */
 #define OPT_BAND 1e-7   /* m: projection near-tie band (FP32 candidate positions err by ~1e-8 m) */
 
@@ -808,6 +810,115 @@ int orc_draw(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits
                                 : pick_link(H, fp, bits, cb, pts, nrm, poses + 12 * (int64_t)g, f, idx, w[k + i],
                                             lf ? &fl : NULL);
                 if (lf) lf[i] = (uint8_t)fl;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Second contact round on the unused fingers (Sec. 5.3's additional search   */
+/* phase, named the general form in Sec. 5.6).  A round-1 set (k1 contacts on */
+/* k1 fingers) marked in take[] gets k_add more contacts on fingers that it   */
+/* does not use and whose domain is non-empty:                                */
+/*  - fingers: with c such fingers (c >= k_add, else the set is not          */
+/*    extended), pick j takes the floor(w_j (c - j) / 2^32)-th remaining one  */
+/*    in increasing finger order, w = Philox blocks (g, d,                    */
+/*    PURPOSE_EXT_FINGERS | blk << 8, request_id), blk = 0, 1;                */
+/*  - points and links: Philox blocks (g, 4d + blk, PURPOSE_EXT_DRAW,         */
+/*    request_id): word i picks the point of the i-th smallest new finger as  */
+/*    the floor(w * count / 2^32)-th domain point, word k_add + i its link by */
+/*    the reverse lookup;                                                     */
+/*  - the extended set lists all k1 + k_add contacts in increasing finger     */
+/*    order (its verdict is that of the larger set, orc_verdicts).            */
+/* A round-1 set whose contacts lack a point or a link is not extended.  Not  */
+/* extended: every entry -1.  g is the global pose index (pose_offset + local). */
+/* ------------------------------------------------------------------------ */
+int orc_extend(const orc_hand *H, const orc_field_params *fp, const uint32_t *bits,
+               const float *pts, const float *nrm, int32_t n_points, const float *poses, int32_t n_poses,
+               const uint32_t *dom_bits, const uint32_t *dom_count, int32_t draws, int32_t k1,
+               const int32_t *set_pt1 /*[P][D][k1]*/, const int32_t *set_link1, const uint8_t *take /*[P][D]*/,
+               int32_t k_add, uint64_t seed, uint32_t request_id, int64_t pose_offset,
+               int32_t *set_pt2 /*[P][D][k1 + k_add]*/, int32_t *set_link2,
+               uint8_t *link_flag /*[P][D][k1 + k_add] or NULL*/)
+{
+    const int F = H->n_fingers, k2 = k1 + k_add;
+    const int64_t NW = (n_points + 31) / 32;
+    if (k1 < 1 || k_add < 1 || k2 > F || k2 > 8 || draws <= 0) return ORC_EINVAL;
+    double cb[3 * 64];
+    orc_bin_centers(fp->bins, cb);
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int g = 0; g < n_poses; ++g) {
+        const int64_t gg = pose_offset + g;
+        for (int d = 0; d < draws; ++d) {
+            const int64_t s = (int64_t)g * draws + d;
+            int32_t *sp2 = set_pt2 + s * k2;
+            int32_t *sl2 = set_link2 + s * k2;
+            uint8_t *lf = link_flag ? link_flag + s * k2 : NULL;
+            for (int i = 0; i < k2; ++i) { sp2[i] = -1; sl2[i] = -1; if (lf) lf[i] = 0; }
+            if (!take[s]) continue;
+            const int32_t *sp1 = set_pt1 + s * k1, *sl1 = set_link1 + s * k1;
+            int used[8] = {0}, fin1[8], ok = 1;
+            for (int i = 0; i < k1; ++i) {
+                if (sp1[i] < 0 || sl1[i] < 0 || sl1[i] >= H->n_joints) { ok = 0; break; }
+                fin1[i] = H->joint_finger[sl1[i]];
+                used[fin1[i]] = 1;
+            }
+            if (!ok) continue;
+            int left[8], c = 0;
+            for (int f = 0; f < F; ++f)
+                if (!used[f] && dom_count[(int64_t)g * F + f] > 0) left[c++] = f;
+            if (c < k_add) continue;
+            uint32_t wf[8];
+            for (int blk = 0; blk < 2; ++blk) {
+                uint32_t ctr[4] = {(uint32_t)gg, (uint32_t)d, PURPOSE_EXT_FINGERS | ((uint32_t)blk << 8), request_id};
+                orc_philox4x32_10(ctr, key, wf + 4 * blk);
+            }
+            int newf[8];
+            for (int j = 0; j < k_add; ++j) {
+                int r = (int)(((uint64_t)wf[j] * (uint32_t)(c - j)) >> 32);
+                newf[j] = left[r];
+                for (int t = r; t + 1 < c - j; ++t) left[t] = left[t + 1];
+            }
+            for (int a = 1; a < k_add; ++a)
+                for (int b = a; b > 0 && newf[b - 1] > newf[b]; --b) {
+                    int t = newf[b];
+                    newf[b] = newf[b - 1];
+                    newf[b - 1] = t;
+                }
+            uint32_t w[16];
+            for (int blk = 0; blk * 4 < 2 * k_add; ++blk) {
+                uint32_t ctr[4] = {(uint32_t)gg, (uint32_t)(4 * d + blk), PURPOSE_EXT_DRAW, request_id};
+                orc_philox4x32_10(ctr, key, w + 4 * blk);
+            }
+            int32_t np[8], nl[8];
+            int nf[8];
+            for (int i = 0; i < k_add; ++i) {
+                const int f = newf[i];
+                const uint32_t cnt = dom_count[(int64_t)g * F + f];
+                const uint32_t j = (uint32_t)(((uint64_t)w[i] * cnt) >> 32);
+                const int64_t idx = select1(dom_bits + ((int64_t)g * F + f) * NW, NW, j);
+                int fl = 0;
+                np[i] = (int32_t)idx;
+                nl[i] = idx < 0 ? -1 : pick_link(H, fp, bits, cb, pts, nrm, poses + 12 * (int64_t)g, f, idx,
+                                                 w[k_add + i], &fl);
+                nf[i] = fl;
+            }
+            /* union in increasing finger order (both groups are sorted) */
+            int a = 0, b = 0;
+            for (int o = 0; o < k2; ++o) {
+                const int take_old = b >= k_add || (a < k1 && fin1[a] < newf[b]);
+                if (take_old) {
+                    sp2[o] = sp1[a];
+                    sl2[o] = sl1[a];
+                    ++a;
+                } else {
+                    sp2[o] = np[b];
+                    sl2[o] = nl[b];
+                    if (lf) lf[o] = (uint8_t)nf[b];
+                    ++b;
+                }
             }
         }
     }

@@ -134,9 +134,9 @@ static void build_bin_lut(const std::vector<float> &bc, int B, std::vector<uint3
                     }
                 std::sort(cand.begin(), cand.end());
                 if (cand.size() <= 4) {
-                    uint32_t e = 0xffffffffu;
-                    for (size_t i = 0; i < cand.size(); ++i)
-                        e = (e & ~(0xffu << (8 * i))) | ((uint32_t)cand[i] << (8 * i));
+                    // absent slots repeat the first candidate (the kernel evaluates all four)
+                    uint32_t e = 0;
+                    for (size_t i = 0; i < 4; ++i) e |= (uint32_t)cand[i < cand.size() ? i : 0] << (8 * i);
                     lut[(face * R + iv) * R + iu] = e;
                 }
             }
@@ -482,11 +482,24 @@ lg_status lg_build_field(const lg_hand_desc *hand, const lg_field_params *params
         return hip_fail(e, "build scratch");
     }
     dim3 grid((unsigned)((H.samples + kBuildThreads - 1) / kBuildThreads), H.F);
-    hipLaunchKernelGGL(k_field_build, grid, dim3(kBuildThreads), 0, s, H, f->d_bits, f->d_wit, d_drop);
-    e = hipGetLastError();
+    // the build kernel's own duration (events on the build stream), reported by lg_field_info
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_field_build, grid, dim3(kBuildThreads), 0, s, H, f->d_bits, f->d_wit, d_drop);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
     unsigned long long drop = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&drop, d_drop, sizeof drop, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    float build_ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&build_ms, ev[0], ev[1]);
+    f->build_kernel_ms = build_ms;
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
     (void)hipFree(d_drop);
     if (e != hipSuccess) {
         free_field(f);
@@ -572,6 +585,7 @@ lg_status lg_field_info(const lg_field *f, lg_field_info_t *info)
     info->dropped = f->dropped;
     info->has_witness = f->has_witness ? 1 : 0;
     info->lattice = f->dh.lat;
+    info->build_kernel_ms = f->build_kernel_ms;
     return LG_OK;
 }
 

@@ -38,7 +38,8 @@ struct DevHand {
     const float *surf;        // [J][nsurf][6]
     const float *grid_frame;  // [F][12]
     const float *bin_c;       // [B][3]
-    const uint32_t *bin_lut;  // [6][kLutRes][kLutRes] candidate bins (4 x 8 bit), 0xffffffff = all
+    const uint32_t *bin_lut;  // [6][kLutRes][kLutRes] 4 candidate bins (8 bit each, absent ones repeat the
+                              // first), 0xffffffff = more than four: every bin
     const int32_t *axis_samples;  // [J + n_palm_caps]: links, then the palm's capsules
     int n_palm_surf, n_palm_caps; // static link (palm): contact vectors and capsules, base frame
     const float *palm_surf;       // [n_palm_surf][6]
@@ -66,6 +67,7 @@ struct lg_field {
     int max_dof;
     bool has_witness;
     int64_t vectors, dropped;
+    double build_kernel_ms = 0.0;  // k_field_build's duration (0 for imported fields)
     uint64_t bits_set;
     uint64_t device_bytes;
     // host copies
@@ -257,6 +259,14 @@ __device__ inline void lattice_cell(const Affine &a, float px, float py, float p
     Iz = (int)fmaf(a.m[8], px, fmaf(a.m[9], py, fmaf(a.m[10], pz, a.m[11])));
 }
 
+// a * b + c on the 24-bit multiplier (a, b < 2^24; b uniform)
+__device__ inline uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+
 // Word of voxel (ix, iy, iz) in a plane of a merged finger table: 4x4x4
 // bricks in (z, y, x) order, voxels in a brick in (z, y, x) order.  The map is
 // linear in the brick and in-brick coordinates, so for a brick-aligned offset
@@ -264,6 +274,13 @@ __device__ inline void lattice_cell(const Affine &a, float px, float py, float p
 __host__ __device__ inline uint32_t brick_word(uint32_t ix, uint32_t iy, uint32_t iz, uint32_t GB)
 {
     return ((((iz >> 2) * GB + (iy >> 2)) * GB + (ix >> 2)) << 6) | ((iz & 3u) << 4) | ((iy & 3u) << 2) | (ix & 3u);
+}
+
+// brick_word on the 24-bit multiplier (coordinates below 2^22, GB uniform)
+__device__ inline uint32_t brick_word_u24(uint32_t ix, uint32_t iy, uint32_t iz, uint32_t GB)
+{
+    const uint32_t blk = mad_u24(mad_u24(iz >> 2, GB, iy >> 2), GB, ix >> 2);
+    return (blk << 6) | ((iz & 3u) << 4) | ((iy & 3u) << 2) | (ix & 3u);
 }
 
 // Voxel of object point p in finger f's window under pose P (-1 outside):
@@ -301,38 +318,6 @@ __device__ inline int nearest_bin(const float *c, int B, float dx, float dy, flo
         if (s > best) {
             best = s;
             bi = b;
-        }
-    }
-    return bi;
-}
-
-// Same result as nearest_bin, through the cube-map candidate table.
-__device__ inline int nearest_bin_lut(const uint32_t *lut, const float *c, int B, float dx, float dy, float dz)
-{
-    const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
-    // major axis (ties to the lower axis), branch-free
-    const bool xm = (ax >= ay) & (ax >= az);
-    const bool ym = !xm & (ay >= az);
-    const float m = xm ? ax : (ym ? ay : az);
-    const float u = xm ? dy : (ym ? dz : dx);
-    const float v = xm ? dz : (ym ? dx : dy);
-    const float dm = xm ? dx : (ym ? dy : dz);
-    const int face = (xm ? 0 : (ym ? 2 : 4)) + (dm < 0.f ? 1 : 0);
-    // the table is conservative, so an approximate reciprocal is enough
-    const float s = (0.5f * kLutRes) * __builtin_amdgcn_rcpf(m);
-    const int iu = min(max((int)fmaf(u, s, 0.5f * kLutRes), 0), kLutRes - 1);
-    const int iv = min(max((int)fmaf(v, s, 0.5f * kLutRes), 0), kLutRes - 1);
-    const uint32_t e = lut[(face * kLutRes + iv) * kLutRes + iu];
-    if ((e >> 8 & 0xffu) == 0xffu) return (int)(e & 0xffu);  // single candidate
-    if (e == 0xffffffffu) return nearest_bin(c, B, dx, dy, dz);
-    float best = -3.0e38f;
-    int bi = 0;
-    for (uint32_t r = e; (r & 0xffu) != 0xffu; r = (r >> 8) | 0xff000000u) {
-        const uint32_t b = r & 0xffu;
-        const float sc = fmaf(c[3 * b], dx, fmaf(c[3 * b + 1], dy, c[3 * b + 2] * dz));
-        if (sc > best) {
-            best = sc;
-            bi = (int)b;
         }
     }
     return bi;

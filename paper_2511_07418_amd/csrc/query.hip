@@ -111,19 +111,12 @@ __device__ inline uint32_t block_skip(const float4 *__restrict__ bounds, const A
     return all;
 }
 
-// a * b + c on the 24-bit multiplier (a, b < 2^24; b uniform)
-__device__ inline uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c)
-{
-    uint32_t r;
-    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
-    return r;
-}
-
-// nearest_bin_lut with the candidate slots evaluated branch-free: the four
-// slots' centres (float4 rows, an absent slot repeats the first candidate) are
-// read before any dot product, so a wave pays one LDS round trip instead of
-// one per candidate of its worst lane.  Same arithmetic and tie rule (slots in
-// increasing bin order, strict >).
+// argmax_b <d, c_b> (ties to the lowest b, as nearest_bin) through the
+// cube-map candidate table: the four candidate slots of the direction's cell
+// (absent ones repeat the first, so the result is unchanged) are evaluated
+// without a branch.  Their centres are float4 rows in LDS, all four read
+// before the first dot product.  A cell with more than four candidates scans
+// every bin.
 __device__ inline int nearest_bin_lut4(const uint32_t *lut, const float4 *c4, int B, float dx, float dy, float dz)
 {
     const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
@@ -151,19 +144,17 @@ __device__ inline int nearest_bin_lut4(const uint32_t *lut, const float4 *c4, in
         }
         return bi;
     }
-    const uint32_t b0 = e & 0xffu;
-    uint32_t bk[4] = {b0, e >> 8 & 0xffu, e >> 16 & 0xffu, e >> 24};
-#pragma unroll
-    for (int k = 1; k < 4; ++k) bk[k] = bk[k] == 0xffu ? b0 : bk[k];
+    // byte offsets (bin * 16) of the four slots' float4 centres
+    const uint32_t off[4] = {(e << 4) & 0xff0u, (e >> 4) & 0xff0u, (e >> 12) & 0xff0u, (e >> 20) & 0xff0u};
     float4 ck[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) ck[k] = c4[bk[k]];
+    for (int k = 0; k < 4; ++k) ck[k] = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(c4) + off[k]);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const float sc = fmaf(ck[k].x, dx, fmaf(ck[k].y, dy, ck[k].z * dz));
         if (sc > best) {
             best = sc;
-            bi = (int)bk[k];
+            bi = (int)(off[k] >> 4);
         }
     }
     return bi;
@@ -232,21 +223,21 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
             asm volatile("" ::: "memory");
             const int i = chunk * 64 + lane;
             const bool valid = i < N;
-            float px = 0.f, py = 0.f, pz = 0.f, nx = 0.f, ny = 0.f, nz = 1.f;
-            if (valid) {  // 32-bit byte offsets from uniform bases (SoA rows of 4 N bytes)
-                const char *pb = reinterpret_cast<const char *>(pts), *nb = reinterpret_cast<const char *>(nrm);
-                const uint32_t o0 = (uint32_t)i << 2, o1 = (uint32_t)(N + i) << 2, o2 = (uint32_t)(2 * N + i) << 2;
-                px = *reinterpret_cast<const float *>(pb + o0);
-                py = *reinterpret_cast<const float *>(pb + o1);
-                pz = *reinterpret_cast<const float *>(pb + o2);
-                nx = *reinterpret_cast<const float *>(nb + o0);
-                ny = *reinterpret_cast<const float *>(nb + o1);
-                nz = *reinterpret_cast<const float *>(nb + o2);
-            }
+            // lanes past N read the last point (in bounds, no branch); they
+            // are outside every window through `valid`
+            const uint32_t il = (uint32_t)min(i, N - 1);
+            const char *pb = reinterpret_cast<const char *>(pts), *nb = reinterpret_cast<const char *>(nrm);
+            const uint32_t o0 = il << 2, o1 = o0 + ((uint32_t)N << 2), o2 = o1 + ((uint32_t)N << 2);
+            const float px = *reinterpret_cast<const float *>(pb + o0);
+            const float py = *reinterpret_cast<const float *>(pb + o1);
+            const float pz = *reinterpret_cast<const float *>(pb + o2);
+            const float nx = *reinterpret_cast<const float *>(nb + o0);
+            const float ny = *reinterpret_cast<const float *>(nb + o1);
+            const float nz = *reinterpret_cast<const float *>(nb + o2);
             float qx, qy, qz;
             query_dir(P, nx, ny, nz, qx, qy, qz);
             const int b = nearest_bin_lut4(lut, cb4, B, qx, qy, qz);
-            const uint32_t plane = W == 2 ? (uint32_t)(b >> 5) * G3 : 0u;
+            const uint32_t plane = W == 2 ? __umul24((uint32_t)(b >> 5), G3) : 0u;
             uint32_t word[FM];  // 0 outside the window
             uint32_t voff = 0, ip = 0;
             if (LAT) {
@@ -256,7 +247,7 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
                 Iy = min(max(Iy, 0), 1023);
                 Iz = min(max(Iz, 0), 1023);
                 ip = (uint32_t)Ix | (uint32_t)Iy << 10 | (uint32_t)Iz << 20;
-                voff = (brick_word((uint32_t)Ix, (uint32_t)Iy, (uint32_t)Iz, GB) + plane) << 2;
+                voff = (brick_word_u24((uint32_t)Ix, (uint32_t)Iy, (uint32_t)Iz, GB) + plane) << 2;
                 asm volatile("" : "+v"(voff));  // one add per finger below, not a re-associated pair
             }
             // all finger gathers are issued before any is consumed
@@ -277,7 +268,7 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
                         const float uz = fmaf(a.m[8], px, fmaf(a.m[9], py, fmaf(a.m[10], pz, a.m[11])));
                         const int Ix = (int)ux, Iy = (int)uy, Iz = (int)uz;
                         in = ((int)valid & (int)(min(Ix, min(Iy, Iz)) >= G) & (int)(max(Ix, max(Iy, Iz)) < 2 * G)) != 0;
-                        off = (brick_word((uint32_t)Ix, (uint32_t)Iy, (uint32_t)Iz, GB) + plane) << 2;
+                        off = (brick_word_u24((uint32_t)Ix, (uint32_t)Iy, (uint32_t)Iz, GB) + plane) << 2;
                     }
                     if (in) word[f] = *reinterpret_cast<const uint32_t *>(mbase + (off + koff[f]));
                 }
@@ -469,6 +460,8 @@ static lg_status query_domains(const lg_field *field, const float *pts, const fl
     if (n_poses == 0) return LG_OK;
     if (!poses || !dom_count || (n_points > 0 && (!pts || !nrm || !dom_bits)))
         return fail(LG_EINVAL, "null device buffer");
+    if ((int64_t)n_points * 12 > 0xffffffffLL)
+        return fail(LG_EUNSUPPORTED, "n_points above 357,913,941 (32-bit byte offsets into the point rows)");
     hipStream_t s = as_stream(stream);
     const DevHand &H = field->dh;
 #define LG_QUERY(W, FM, LAT)                                                                                 \

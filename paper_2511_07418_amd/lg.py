@@ -52,7 +52,7 @@ class FieldInfo(C.Structure):
     _fields_ = [("n_fingers", C.c_int32), ("n_joints", C.c_int32), ("grid", C.c_int32),
                 ("bins", C.c_int32), ("samples", C.c_int64), ("device_bytes", C.c_uint64),
                 ("bits_set", C.c_uint64), ("vectors", C.c_int64), ("dropped", C.c_int64),
-                ("has_witness", C.c_int32), ("lattice", C.c_int32)]
+                ("has_witness", C.c_int32), ("lattice", C.c_int32), ("build_kernel_ms", C.c_double)]
 
 
 class SearchParams(C.Structure):
