@@ -65,6 +65,10 @@ def parse():
     ap.add_argument("--k", type=int, default=0,
                     help="contacts per set (0 = one per finger); below the finger count, k fingers are drawn "
                          "per set and the others take random joint values")
+    ap.add_argument("--extend", type=int, default=0,
+                    help="second contact round (the general form, Sec. 5.3/5.6): unstable sets that realise "
+                         "collision-free get this many more contacts on unused fingers (needs --k below the "
+                         "finger count)")
     ap.add_argument("--concave-filter", action="store_true",
                     help="drop the object's concave points first (8 mm box, 1 mm depth); the steps use the rest")
     ap.add_argument("--palm-prob", type=float, default=0.0,
@@ -582,7 +586,10 @@ def main():
                      "radius_m": palm.radius, "margin_m": 0.002}
         print(f"[bench] palm placements: {palm_info['placed']} kept, {palm_info['rejected']} rejected",
               file=sys.stderr, flush=True)
-    pipe = Pipeline(field, obj_pts, obj_nrm, poses, w.search, ik=w.ik, sdf=w.sdf, cos_hit=cos_hit, palm_pt=palm_pt)
+    if args.extend > 0 and (w.ik is None or int(w.search.k) + args.extend > w.hand.n_fingers):
+        raise SystemExit("--extend needs the c3 workload and --k + --extend <= the number of fingers")
+    pipe = Pipeline(field, obj_pts, obj_nrm, poses, w.search, ik=w.ik, sdf=w.sdf, cos_hit=cos_hit, palm_pt=palm_pt,
+                    extend_k=args.extend)
     print(f"[bench] {args.workload}: field built in {t_build:.2f}s ({field.info()['bits_set']} bits), "
           f"P={pipe.P} N={pipe.N}", file=sys.stderr, flush=True)
 
@@ -651,7 +658,7 @@ def main():
         pipe.step()
     torch.cuda.synchronize()
 
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
     valid = []
     t0 = time.perf_counter()
     for s in range(args.steps):
@@ -663,11 +670,14 @@ def main():
         e[2].record()
         pipe.realize()
         e[3].record()
+        if pipe.extend_k > 0:
+            pipe.extend()
+        e[4].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n_valid = pipe.valid_count()
     n_acc = pipe.n_acc()
-    st = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in ev])  # ms
+    st = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in ev])  # ms
     ms_per_step = wall * 1000.0 / args.steps
     value = n_valid / (ms_per_step / 1000.0)
 
@@ -750,10 +760,12 @@ def main():
                                     "sigma_m": args.opt_sigma} if args.opt_outer > 0 else None),
                    "self_collision": bool(args.self_collision), "placement": args.placement,
                    "cone_deg": args.cone_deg or None, "contacts": int(w.search.k), "concave_filter": concave,
+                   "second_round_contacts": args.extend or None,
                    "palm": palm_info},
         "valid_per_step": n_valid,
         "accepted_sets_per_step": n_acc,
-        "stage_ms": {"query": q_ms, "search": float(st[:, 1].mean()), "realize": float(st[:, 2].mean())},
+        "stage_ms": {"query": q_ms, "search": float(st[:, 1].mean()), "realize": float(st[:, 2].mean()),
+                     **({"second_round": float(st[:, 3].mean())} if pipe.extend_k > 0 else {})},
         "query_gbps": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,

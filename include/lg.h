@@ -285,6 +285,61 @@ lg_status lg_search_noalloc(const lg_field *field, const float *pts, const float
                             int8_t *set_link, uint8_t *verdict, double *tstar, int32_t *acc_list,
                             int32_t *n_acc, void *stream);
 
+/*
+ * lg_compact_unstable -- the ids (g * draws + d, increasing) of the sets of a
+ * search whose draw is whole (every point and link >= 0) and whose verdict
+ * is 0: the candidates of the second contact round once realised.  set_pt
+ * [P][D][k] int32, set_link int8, verdict [P][D] uint8 (device); outputs list
+ * [P*D] int32 and n_list [1] int32 (device).  workspace: device,
+ * lg_compact_unstable_workspace_bytes().
+ */
+size_t lg_compact_unstable_workspace_bytes(int32_t n_poses, int32_t draws);
+lg_status lg_compact_unstable(const int32_t *set_pt, const int8_t *set_link, const uint8_t *verdict,
+                              int32_t n_poses, int32_t draws, int32_t k, int32_t *list, int32_t *n_list,
+                              void *workspace, size_t workspace_bytes, void *stream);
+
+/* Second contact round parameters. */
+typedef struct {
+    int32_t k_add;           /* contacts added on unused fingers, k + k_add <= fingers, <= 8 */
+    uint32_t request_id;     /* 4th Philox counter word of this round's draws */
+    const int32_t *list;     /* DEVICE, increasing set ids to extend, or NULL: every round-1 set with a
+                                whole draw and verdict 0 */
+    const int32_t *list_n;   /* DEVICE [1]: entries of list (required with a list) */
+    const uint8_t *list_ok;  /* DEVICE, aligned with list, or NULL: only entries != 0 are extended
+                                (e.g. lg_realize's valid of the listed sets: collision-free, contacts met) */
+} lg_extend_params;
+
+/*
+ * lg_search_extend -- the second contact round on the unused fingers
+ * (Sec. 5.3: an additional search phase adds contacts; Sec. 5.6: grasps that
+ * are collision-free but not stable get an additional contact search on the
+ * unused fingers, the general form of the method).  Round-1 sets are those
+ * of lg_search with params (k contacts, draws, seed, pose_offset) on the same
+ * domains.  Each set taken (see lg_extend_params) whose contacts all have a
+ * point and a link gets k_add more: with c fingers unused by the set and with
+ * a non-empty domain (c >= k_add, else the set is not extended), pick j takes
+ * the floor(w_j (c - j) / 2^32)-th remaining one in increasing finger order,
+ * w = Philox blocks (g + pose_offset, d, 19 | blk << 8, request_id); the
+ * i-th smallest new finger's point is the floor(w * count / 2^32)-th bit of
+ * its domain and its link the reverse lookup, w = word i and k_add + i of
+ * Philox blocks (g + pose_offset, 4d + blk, 21, request_id).  The extended
+ * set lists its k + k_add contacts in increasing finger order; its verdict
+ * and t* are the criterion of lg_search on all of them; acc_list2 holds the
+ * accepted extended sets.  Sets not extended: set_pt2 -1, verdict 0, t* NaN.
+ * Outputs (device): set_pt2 [P][D][k + k_add] int32, set_link2 int8, verdict2
+ * [P][D] uint8, tstar2 double, acc_list2 [P*D] int32, n_acc2 [1] int32.
+ * workspace: device, lg_search_workspace_bytes() of params with k + k_add.
+ * No palm contacts (params->palm_pt must be NULL).  Realize the extended sets
+ * with lg_realize and k = k + k_add.
+ */
+lg_status lg_search_extend(const lg_field *field, const float *pts, const float *nrm, int32_t n_points,
+                           const float *poses, int32_t n_poses, const uint32_t *dom_bits,
+                           const uint32_t *dom_count, const lg_search_params *params, const int32_t *set_pt1,
+                           const int8_t *set_link1, const uint8_t *verdict1, const lg_extend_params *ext,
+                           int32_t *set_pt2, int8_t *set_link2, uint8_t *verdict2, double *tstar2,
+                           int32_t *acc_list2, int32_t *n_acc2, void *workspace, size_t workspace_bytes,
+                           void *stream);
+
 /* Kinematics optimisation parameters (Sec. 5.5). */
 typedef struct {
     int32_t iters;    /* DLS iterations (Eq. 7) */

@@ -25,6 +25,8 @@ __device__ inline int select_in_word(uint32_t x, uint32_t r)
 }
 
 constexpr uint32_t kPurposeFingers = 13u;
+constexpr uint32_t kPurposeExtFingers = 19u;  // second contact round: fingers
+constexpr uint32_t kPurposeExtDraw = 21u;     // second contact round: points and links
 
 // Contact fingers of set d of pose gg (global index) as a bit mask: k picks
 // without replacement among the eligible fingers (non-empty domains), pick j
@@ -32,13 +34,13 @@ constexpr uint32_t kPurposeFingers = 13u;
 // order; contact i goes to the i-th lowest bit.  With c == k every eligible
 // finger is picked whatever the words, so they are not drawn.
 __device__ inline uint32_t choose_fingers(uint32_t elig, int k, uint32_t gg, int d, uint32_t request_id,
-                                          uint32_t seed_lo, uint32_t seed_hi)
+                                          uint32_t seed_lo, uint32_t seed_hi, uint32_t purpose = kPurposeFingers)
 {
     const int c = __popc(elig);
     if (c <= k) return c == k ? elig : 0u;
     uint32_t w[8];
-    philox4x32_10(gg, (uint32_t)d, kPurposeFingers, request_id, seed_lo, seed_hi, w);
-    if (k > 4) philox4x32_10(gg, (uint32_t)d, kPurposeFingers | (1u << 8), request_id, seed_lo, seed_hi, w + 4);
+    philox4x32_10(gg, (uint32_t)d, purpose, request_id, seed_lo, seed_hi, w);
+    if (k > 4) philox4x32_10(gg, (uint32_t)d, purpose | (1u << 8), request_id, seed_lo, seed_hi, w + 4);
     uint32_t left = elig, mask = 0;
     for (int j = 0; j < k; ++j) {
         uint32_t x = left;
@@ -78,6 +80,45 @@ __device__ inline int pick_link(const DevHand &H, const uint32_t *__restrict__ b
     return pc ? first + select_in_word(mask, __umulhi(r, pc)) : -1;
 }
 
+// The j-th (0-based) set bit of a domain of NW words through its superblock
+// prefix pf (nsb + 1 exclusive popcounts of kSuper-word superblocks): binary
+// search for the last superblock with pf <= j, then a scan of at most kSuper
+// words; -1 if the domain has no j-th bit.
+__device__ inline int select_domain(const uint32_t *pf, int nsb, const uint32_t *__restrict__ dom, int NW, uint32_t j)
+{
+    int lo = 0, hi = nsb;  // invariant pf[lo] <= j < pf[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pf[mid] <= j) lo = mid; else hi = mid;
+    }
+    uint32_t rem = j - pf[lo];
+    for (int wi = lo * kSuper; wi < min(NW, (lo + 1) * kSuper); ++wi) {
+        const uint32_t x = dom[wi];
+        const uint32_t pc = __popc(x);
+        if (rem < pc) return wi * 32 + select_in_word(x, rem);
+        rem -= pc;
+    }
+    return -1;
+}
+
+// Superblock popcount prefixes of the F domains of one pose into LDS
+// (prefix[f * (nsb + 1) + sb]); the caller synchronises after.
+__device__ inline void build_prefix(uint32_t *prefix, const uint32_t *__restrict__ dom, int F, int NW, int nsb)
+{
+    for (int i = threadIdx.x; i < F * nsb; i += blockDim.x) {
+        const int f = i / nsb, sb = i % nsb;
+        uint32_t c = 0;
+        for (int w = sb * kSuper; w < min(NW, (sb + 1) * kSuper); ++w) c += __popc(dom[(int64_t)f * NW + w]);
+        prefix[f * (nsb + 1) + sb + 1] = c;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < F) {
+        uint32_t *pf = prefix + threadIdx.x * (nsb + 1);
+        pf[0] = 0;
+        for (int sb = 1; sb <= nsb; ++sb) pf[sb] += pf[sb - 1];
+    }
+}
+
 // One workgroup per pose.  Rank structure: exclusive popcount prefix per
 // superblock of 8 domain words, in LDS; a draw binary-searches it and scans
 // at most 8 words.
@@ -114,19 +155,7 @@ k_draw(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ p
         }
         return;  // uniform over the block
     }
-    // superblock popcounts, then a per-finger exclusive scan
-    for (int i = threadIdx.x; i < F * nsb; i += blockDim.x) {
-        const int f = i / nsb, sb = i % nsb;
-        uint32_t c = 0;
-        for (int w = sb * kSuper; w < min(NW, (sb + 1) * kSuper); ++w) c += __popc(dom[(int64_t)f * NW + w]);
-        prefix[f * (nsb + 1) + sb + 1] = c;
-    }
-    __syncthreads();
-    if (threadIdx.x < F) {
-        uint32_t *pf = prefix + threadIdx.x * (nsb + 1);
-        pf[0] = 0;
-        for (int sb = 1; sb <= nsb; ++sb) pf[sb] += pf[sb - 1];
-    }
+    build_prefix(prefix, dom, F, NW, nsb);
     __syncthreads();
     const float *pose = poses + 12 * (int64_t)g;
     for (int d = threadIdx.x; d < D; d += blockDim.x) {
@@ -140,26 +169,8 @@ k_draw(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ p
         for (int i = 0; i < k; ++i) {
             const int f = __ffs(fm) - 1;  // finger of contact i
             fm &= fm - 1u;
-            const uint32_t cnt = counts[f];
-            const uint32_t j = __umulhi(w[i], cnt);
-            // rank: last superblock with prefix <= j
-            const uint32_t *pf = prefix + f * (nsb + 1);
-            int lo = 0, hi = nsb;  // invariant pf[lo] <= j < pf[hi]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (pf[mid] <= j) lo = mid; else hi = mid;
-            }
-            uint32_t rem = j - pf[lo];
-            int idx = -1;
-            for (int wi = lo * kSuper; wi < min(NW, (lo + 1) * kSuper); ++wi) {
-                const uint32_t x = dom[(int64_t)f * NW + wi];
-                const uint32_t pc = __popc(x);
-                if (rem < pc) {
-                    idx = wi * 32 + select_in_word(x, rem);
-                    break;
-                }
-                rem -= pc;
-            }
+            const int idx = select_domain(prefix + f * (nsb + 1), nsb, dom + (int64_t)f * NW, NW,
+                                          __umulhi(w[i], counts[f]));
             sp[i] = idx;
             sl[i] = (int8_t)(idx >= 0 ? pick_link(H, bits, cb, pts, nrm, N, pose, f, idx, w[k + i]) : -1);
         }
@@ -789,6 +800,150 @@ __global__ void k_relink(DevHand H, const uint32_t *__restrict__ bits, const flo
     }
 }
 
+// ---- second contact round (Sec. 5.3, additional search phase; Sec. 5.6) -------
+// Finger of link l (its joint's finger).
+__device__ inline int link_finger(const DevHand &H, int l)
+{
+    for (int f = 0; f < H.F; ++f)
+        if (l >= H.finger_first[f] && l < H.finger_first[f] + H.finger_dof[f]) return f;
+    return -1;
+}
+
+// One workgroup per pose.  A round-1 set (k1 contacts) is extended when it is
+// listed (list: sorted set ids, list_ok[i] != 0 if given) or, without a list,
+// when its draw is whole and its verdict 0; its contacts must all have a
+// point and a link.  It gets k_add contacts on unused fingers with non-empty
+// domains: the fingers by choose_fingers over them (Philox purpose 19), the
+// points as the floor(w * count / 2^32)-th domain bit and the links by the
+// reverse lookup (purpose 21: word i and k_add + i for the i-th new finger).
+// The extended set lists its k1 + k_add contacts in increasing finger order.
+// Sets not extended get set_pt -1, verdict 0, t* NaN; pose_valid[g] = some
+// set of the pose was extended (its verdicts are computed next).
+__global__ void __launch_bounds__(kDrawThreads)
+k_extend(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ pts, const float *__restrict__ nrm,
+         int N, const float *__restrict__ poses, const uint32_t *__restrict__ dom_bits,
+         const uint32_t *__restrict__ dom_count, int D, int k1, int k_add, const int32_t *__restrict__ set_pt1,
+         const int8_t *__restrict__ set_link1, const uint8_t *__restrict__ verdict1, const int32_t *__restrict__ list,
+         const int32_t *__restrict__ list_n, const uint8_t *__restrict__ list_ok, uint32_t seed_lo, uint32_t seed_hi,
+         uint32_t request_id, int64_t pose_offset, int32_t *__restrict__ set_pt2, int8_t *__restrict__ set_link2,
+         uint8_t *__restrict__ pose_valid, uint8_t *__restrict__ verdict2, double *__restrict__ tstar2)
+{
+    extern __shared__ uint32_t prefix[];  // [F][nsb + 1]
+    __shared__ float cb[3 * kMaxBins];
+    __shared__ uint32_t counts[kMaxFingers];
+    __shared__ int32_t range[2];
+    __shared__ uint32_t any;
+    const int g = blockIdx.x, F = H.F, k2 = k1 + k_add;
+    const int NW = (N + 31) >> 5, nsb = (NW + kSuper - 1) / kSuper;
+    const uint32_t *dom = dom_bits + (int64_t)g * F * NW;
+    for (int i = threadIdx.x; i < 3 * H.B; i += blockDim.x) cb[i] = H.bin_c[i];
+    if ((int)threadIdx.x < F) counts[threadIdx.x] = dom_count[(int64_t)g * F + threadIdx.x];
+    if (threadIdx.x == 0) {
+        any = 0;
+        range[0] = range[1] = 0;
+        if (list) {  // this pose's entries: ids in [g D, (g + 1) D) of the sorted list
+            const int n = *list_n;
+            int lo = 0, hi = n;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if ((int64_t)list[mid] < (int64_t)g * D) lo = mid + 1; else hi = mid;
+            }
+            range[0] = lo;
+            hi = n;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if ((int64_t)list[mid] < (int64_t)(g + 1) * D) lo = mid + 1; else hi = mid;
+            }
+            range[1] = lo;
+        }
+    }
+    build_prefix(prefix, dom, F, NW, nsb);
+    __syncthreads();
+    const float *pose = poses + 12 * (int64_t)g;
+    const uint32_t gg = (uint32_t)(pose_offset + g);
+    for (int d = threadIdx.x; d < D; d += blockDim.x) {
+        const int64_t sid = (int64_t)g * D + d;
+        const int32_t *sp1 = set_pt1 + sid * k1;
+        const int8_t *sl1 = set_link1 + sid * k1;
+        int32_t *sp2 = set_pt2 + sid * k2;
+        int8_t *sl2 = set_link2 + sid * k2;
+        bool take;
+        if (list) {
+            int lo = range[0], hi = range[1];
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if ((int64_t)list[mid] < sid) lo = mid + 1; else hi = mid;
+            }
+            take = lo < range[1] && (int64_t)list[lo] == sid && (!list_ok || list_ok[lo] != 0);
+        } else {
+            take = verdict1[sid] == 0;
+        }
+        uint32_t used = 0;
+        int fin1[8];
+        for (int i = 0; i < k1 && take; ++i) {
+            const int l = sl1[i];
+            const int f = (l >= 0 && sp1[i] >= 0 && sp1[i] < N) ? link_finger(H, l) : -1;
+            if (f < 0) take = false; else { fin1[i] = f; used |= 1u << f; }
+        }
+        uint32_t fm = 0;
+        if (take) {
+            uint32_t elig = 0;
+            for (int f = 0; f < F; ++f) elig |= (counts[f] > 0 && !((used >> f) & 1u) ? 1u : 0u) << f;
+            fm = choose_fingers(elig, k_add, gg, d, request_id, seed_lo, seed_hi, kPurposeExtFingers);
+            take = fm != 0u;
+        }
+        if (!take) {
+            for (int i = 0; i < k2; ++i) {
+                sp2[i] = -1;
+                sl2[i] = -1;
+            }
+            verdict2[sid] = 0;
+            tstar2[sid] = __builtin_nan("");
+            continue;
+        }
+        any = 1u;  // benign race: every writer stores 1
+        uint32_t w[16];
+        for (int blk = 0; blk * 4 < 2 * k_add; ++blk)
+            philox4x32_10(gg, (uint32_t)(4 * d + blk), kPurposeExtDraw, request_id, seed_lo, seed_hi, w + 4 * blk);
+        int np[8], nl[8], nf[8];
+        for (int i = 0; i < k_add; ++i) {
+            const int f = __ffs(fm) - 1;  // the i-th smallest new finger
+            fm &= fm - 1u;
+            const int idx = select_domain(prefix + f * (nsb + 1), nsb, dom + (int64_t)f * NW, NW,
+                                          __umulhi(w[i], counts[f]));
+            nf[i] = f;
+            np[i] = idx;
+            nl[i] = idx >= 0 ? pick_link(H, bits, cb, pts, nrm, N, pose, f, idx, w[k_add + i]) : -1;
+        }
+        // union in increasing finger order (both groups sorted)
+        int a = 0, b = 0;
+        for (int o = 0; o < k2; ++o) {
+            if (b >= k_add || (a < k1 && fin1[a] < nf[b])) {
+                sp2[o] = sp1[a];
+                sl2[o] = sl1[a];
+                ++a;
+            } else {
+                sp2[o] = np[b];
+                sl2[o] = (int8_t)nl[b];
+                ++b;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) pose_valid[g] = any ? 1 : 0;
+}
+
+// flag[s] = set s has every point and link and verdict 0 (an unstable set)
+__global__ void k_flag_unstable(const int32_t *__restrict__ set_pt, const int8_t *__restrict__ set_link,
+                                const uint8_t *__restrict__ verdict, int64_t n_sets, int k, uint8_t *__restrict__ flag)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_sets) return;
+    bool ok = verdict[s] == 0;
+    for (int i = 0; i < k; ++i) ok &= set_pt[s * k + i] >= 0 && set_link[s * k + i] >= 0;
+    flag[s] = ok ? 1 : 0;
+}
+
 // ---- compaction ------------------------------------------------------------
 __global__ void __launch_bounds__(kCompactThreads)
 k_chunk_count(const uint8_t *__restrict__ verdict, int64_t n, uint32_t *__restrict__ chunk_count)
@@ -1033,6 +1188,125 @@ static lg_status search_impl(const lg_field *field, const float *pts, const floa
     LG_HIP(hipGetLastError());
     return LG_OK;
 }
+
+// Bytes of device workspace of lg_compact_unstable: set flags, chunk counts and offsets.
+static size_t unstable_ws_bytes(int64_t n_sets)
+{
+    const int64_t nc = (n_sets + kChunk - 1) / kChunk;
+    return (((size_t)n_sets + 255) & ~(size_t)255) + (size_t)(2 * nc) * 4 + 256;
+}
+
+extern "C" {
+
+size_t lg_compact_unstable_workspace_bytes(int32_t n_poses, int32_t draws)
+{
+    if (n_poses <= 0 || draws <= 0) return 256;
+    return unstable_ws_bytes((int64_t)n_poses * draws);
+}
+
+lg_status lg_compact_unstable(const int32_t *set_pt, const int8_t *set_link, const uint8_t *verdict, int32_t n_poses,
+                              int32_t draws, int32_t k, int32_t *list, int32_t *n_list, void *workspace,
+                              size_t workspace_bytes, void *stream)
+{
+    if (n_poses < 0 || draws <= 0 || k < 1 || k > 8) return fail(LG_EINVAL, "need n_poses >= 0, draws > 0, 1 <= k <= 8");
+    if ((int64_t)n_poses * draws > 0x7fffffffLL) return fail(LG_EINVAL, "P * D must be < 2^31");
+    if (!n_list) return fail(LG_EINVAL, "null n_list");
+    hipStream_t s = as_stream(stream);
+    const int64_t n_sets = (int64_t)n_poses * draws;
+    if (n_sets == 0) {  // a count of 0 (a kernel, not a memset node, for callers that capture the stream)
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(n_list), (int64_t)1, 0u);
+        LG_HIP(hipGetLastError());
+        return LG_OK;
+    }
+    if (!set_pt || !set_link || !verdict || !list || !workspace) return fail(LG_EINVAL, "null device buffer");
+    if (workspace_bytes < unstable_ws_bytes(n_sets)) return fail(LG_EINVAL, "workspace too small");
+    uint8_t *flag = static_cast<uint8_t *>(workspace);
+    uint32_t *cc = reinterpret_cast<uint32_t *>(flag + (((size_t)n_sets + 255) & ~(size_t)255));
+    const int64_t nc = (n_sets + kChunk - 1) / kChunk;
+    hipLaunchKernelGGL(k_flag_unstable, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, s, set_pt, set_link,
+                       verdict, n_sets, k, flag);
+    hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)nc), dim3(kCompactThreads), 0, s, flag, n_sets, cc);
+    hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kCompactThreads), 0, s, cc, nc, cc + nc, n_list);
+    hipLaunchKernelGGL(k_chunk_scatter, dim3((unsigned)nc), dim3(kCompactThreads), 0, s, flag, n_sets, cc + nc, list);
+    LG_HIP(hipGetLastError());
+    return LG_OK;
+}
+
+lg_status lg_search_extend(const lg_field *field, const float *pts, const float *nrm, int32_t n_points,
+                           const float *poses, int32_t n_poses, const uint32_t *dom_bits, const uint32_t *dom_count,
+                           const lg_search_params *p, const int32_t *set_pt1, const int8_t *set_link1,
+                           const uint8_t *verdict1, const lg_extend_params *ep, int32_t *set_pt2, int8_t *set_link2,
+                           uint8_t *verdict2, double *tstar2, int32_t *acc_list2, int32_t *n_acc2, void *workspace,
+                           size_t workspace_bytes, void *stream)
+{
+    if (!field || !p || !ep) return fail(LG_EINVAL, "null field or params");
+    const DevHand &H = field->dh;
+    if (n_points <= 0 || n_poses < 0) return fail(LG_EINVAL, "n_points must be > 0 and n_poses >= 0");
+    const int k1 = p->k, k2 = p->k + ep->k_add;
+    if (k1 < 1 || ep->k_add < 1 || k2 > H.F || k2 > 8)
+        return fail(LG_EINVAL, "need k >= 1, k_add >= 1 and k + k_add <= number of fingers (and <= 8)");
+    if (p->palm_pt) return fail(LG_EUNSUPPORTED, "the second contact round takes no palm contacts");
+    if (p->draws <= 0 || p->m_edges < 3 || p->m_edges > 16 || !(p->mu >= 0.0f) || !(p->moment_scale > 0.0f) ||
+        p->max_pivots < 0)
+        return fail(LG_EINVAL, "need draws > 0, 3 <= m_edges <= 16, mu >= 0, moment_scale > 0, max_pivots >= 0");
+    if ((int64_t)n_poses * p->draws > 0x7fffffffLL) return fail(LG_EINVAL, "P * D must be < 2^31");
+    if (n_poses == 0) return LG_OK;
+    if (!pts || !nrm || !poses || !dom_bits || !dom_count || !set_pt1 || !set_link1 || !verdict1 || !set_pt2 ||
+        !set_link2 || !verdict2 || !tstar2 || !acc_list2 || !n_acc2 || !workspace)
+        return fail(LG_EINVAL, "null device buffer");
+    if (ep->list && !ep->list_n) return fail(LG_EINVAL, "a set list needs its device count");
+    lg_search_params p2 = *p;
+    p2.k = k2;
+    p2.opt_outer = 0;
+    if (workspace_bytes < lg_search_workspace_bytes(n_points, n_poses, &p2)) return fail(LG_EINVAL, "workspace too small");
+    const int NW = (n_points + 31) / 32, nsb = (NW + kSuper - 1) / kSuper;
+    const size_t lds = (size_t)H.F * (nsb + 1) * sizeof(uint32_t);
+    if (lds > 48 * 1024) return fail(LG_EUNSUPPORTED, "too many points for the draw rank structure");
+    hipStream_t s = as_stream(stream);
+    const SearchWs ws = search_ws(workspace, n_points, n_poses, p->draws, false);
+    hipLaunchKernelGGL(k_extend, dim3(n_poses), dim3(kDrawThreads), lds, s, H, field->d_bits, pts, nrm, n_points,
+                       poses, dom_bits, dom_count, p->draws, k1, ep->k_add, set_pt1, set_link1, verdict1, ep->list,
+                       ep->list_n, ep->list_ok, (uint32_t)p->seed, (uint32_t)(p->seed >> 32), ep->request_id,
+                       p->pose_offset, set_pt2, set_link2, ws.pose_valid, verdict2, tstar2);
+    LG_HIP(hipGetLastError());
+    const int64_t npc = (n_poses + kChunk - 1) / kChunk;
+    hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)npc), dim3(kCompactThreads), 0, s, ws.pose_valid,
+                       (int64_t)n_poses, ws.pchunk_count);
+    hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kCompactThreads), 0, s, ws.pchunk_count, npc, ws.pchunk_off,
+                       ws.n_valid_poses);
+    hipLaunchKernelGGL(k_chunk_scatter, dim3((unsigned)npc), dim3(kCompactThreads), 0, s, ws.pose_valid,
+                       (int64_t)n_poses, ws.pchunk_off, ws.valid_poses);
+    const int64_t n_sets = (int64_t)n_poses * p->draws;
+    LpConst cs;
+    for (int e = 0; e < 16; ++e) {
+        const double th = 2.0 * M_PI * e / p->m_edges;
+        cs.ce[e] = e < p->m_edges ? cos(th) : 0.0;
+        cs.se[e] = e < p->m_edges ? sin(th) : 0.0;
+    }
+    int dev = 0, n_cu = 0;
+    LG_HIP(hipGetDevice(&dev));
+    LG_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    const dim3 lgrid((unsigned)std::max<int64_t>(1, std::min<int64_t>((n_sets + 255) / 256, (int64_t)n_cu * 8)));
+#define LG_VERDICT2(KM)                                                                                         \
+    hipLaunchKernelGGL(k_verdict_lane<KM>, lgrid, dim3(256), 0, s, pts, nrm, n_points, set_pt2, nullptr,          \
+                       ws.valid_poses, ws.n_valid_poses, p->draws, k2, p->m_edges, (double)p->mu,                \
+                       (double)p->moment_scale, (double)p->eps, p->max_pivots, cs, verdict2, tstar2)
+    if (k2 <= 3) LG_VERDICT2(3); else if (k2 <= 4) LG_VERDICT2(4); else if (k2 <= 5) LG_VERDICT2(5);
+    else if (k2 <= 6) LG_VERDICT2(6); else LG_VERDICT2(8);
+#undef LG_VERDICT2
+    LG_HIP(hipGetLastError());
+    const int64_t n_chunks = (n_sets + kChunk - 1) / kChunk;
+    hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)n_chunks), dim3(kCompactThreads), 0, s, verdict2, n_sets,
+                       ws.chunk_count);
+    hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kCompactThreads), 0, s, ws.chunk_count, n_chunks, ws.chunk_off,
+                       n_acc2);
+    hipLaunchKernelGGL(k_chunk_scatter, dim3((unsigned)n_chunks), dim3(kCompactThreads), 0, s, verdict2, n_sets,
+                       ws.chunk_off, acc_list2);
+    LG_HIP(hipGetLastError());
+    return LG_OK;
+}
+
+}  // extern "C"
 
 // Scratch of lg_search_noalloc: one array per device, held until the process
 // ends.  Host code never passes the array's name to a kernel (on the host it

@@ -55,6 +55,11 @@ class FieldInfo(C.Structure):
                 ("has_witness", C.c_int32), ("lattice", C.c_int32), ("build_kernel_ms", C.c_double)]
 
 
+class ExtendParams(C.Structure):
+    _fields_ = [("k_add", C.c_int32), ("request_id", C.c_uint32), ("list", C.c_void_p), ("list_n", C.c_void_p),
+                ("list_ok", C.c_void_p)]
+
+
 class SearchParams(C.Structure):
     _fields_ = [("draws", C.c_int32), ("k", C.c_int32), ("m_edges", C.c_int32),
                 ("max_pivots", C.c_int32), ("mu", C.c_float), ("eps", C.c_float),
@@ -126,6 +131,11 @@ def _load():
     L.lg_search_noalloc.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.lg_search_noalloc_max_bytes.argtypes = []
     L.lg_search_noalloc_max_bytes.restype = sz
+    L.lg_compact_unstable_workspace_bytes.argtypes = [i32, i32]
+    L.lg_compact_unstable_workspace_bytes.restype = sz
+    L.lg_compact_unstable.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp, sz, vp]
+    L.lg_search_extend.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                   vp, sz, vp]
     L.lg_realize.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, i32, i32, vp, vp, i32, vp,
                              vp, vp, vp, vp, vp, vp]
     L.lg_serve_request_bytes.argtypes = [vp, vp]
@@ -157,6 +167,7 @@ def _load():
     L.lg_prop_sample.argtypes = [vp, vp, i32, i32, C.c_uint64, C.c_float, C.c_float, C.c_float, vp, vp]
     for fn in ("lg_build_field", "lg_field_import", "lg_field_export", "lg_field_info",
                "lg_field_release", "lg_query_domains", "lg_query_domains_cone", "lg_search", "lg_search_noalloc",
+               "lg_compact_unstable", "lg_search_extend",
                "lg_realize", "lg_serve_create",
                "lg_serve_submit", "lg_serve_poll", "lg_serve_wait", "lg_serve_cancel", "lg_serve_stats",
                "lg_serve_destroy", "lg_place_exhaustive", "lg_place_palm", "lg_concave_filter", "lg_gather_points",
@@ -174,6 +185,7 @@ EXPORTED = ("lg_status_str", "lg_last_error", "lg_version", "lg_build_field", "l
             "lg_field_export", "lg_field_info", "lg_field_release", "lg_query_domains", "lg_query_domains_cone",
             "lg_query_domains_bounded", "lg_chunk_bounds", "lg_morton_order",
             "lg_search_workspace_bytes", "lg_search", "lg_search_noalloc", "lg_search_noalloc_max_bytes",
+            "lg_compact_unstable_workspace_bytes", "lg_compact_unstable", "lg_search_extend",
             "lg_realize", "lg_serve_request_bytes",
             "lg_serve_create", "lg_serve_submit", "lg_serve_poll", "lg_serve_wait", "lg_serve_cancel",
             "lg_serve_stats", "lg_serve_clock", "lg_serve_destroy", "lg_place_exhaustive", "lg_place_palm",
@@ -414,6 +426,60 @@ def lg_search_noalloc(field: Field, pts, nrm, poses, dom_bits, dom_count, sp, bu
                                   _ptr(dom_count), C.byref(bufs.p), _ptr(bufs.set_pt), _ptr(bufs.set_link),
                                   _ptr(bufs.verdict), _ptr(bufs.tstar), _ptr(bufs.acc_list), _ptr(bufs.n_acc),
                                   _stream(stream)), "lg_search_noalloc")
+    return bufs
+
+
+def lg_compact_unstable(bufs: SearchBuffers, stream=None, out=None):
+    """Increasing ids of the sets of ``bufs`` (a search) with a whole draw and
+    verdict 0; returns (list [P*D] int32, n_list [1] int32, workspace) on the
+    device (``out``: the same triple from an earlier call, reused)."""
+    P, D, k = (int(x) for x in bufs.set_pt.shape)
+    dev = bufs.set_pt.device
+    nb = int(_lib.lg_compact_unstable_workspace_bytes(P, D))
+    if out is None:
+        out = (torch.empty((P * D,), dtype=torch.int32, device=dev), torch.zeros((1,), dtype=torch.int32, device=dev),
+               torch.empty((nb,), dtype=torch.uint8, device=dev))
+    lst, n, ws = out
+    _check(_lib.lg_compact_unstable(_ptr(bufs.set_pt), _ptr(bufs.set_link), _ptr(bufs.verdict), P, D, k, _ptr(lst),
+                                    _ptr(n), _ptr(ws), nb, _stream(stream)), "lg_compact_unstable")
+    return out
+
+
+class ExtendBuffers:
+    """Device outputs + workspace of lg_search_extend for P poses."""
+
+    def __init__(self, n_poses: int, sp, k_add: int, device, max_pivots: int = 1000, n_points: int = 0):
+        P, D, k2 = n_poses, int(sp.draws), int(sp.k) + int(k_add)
+        self.set_pt = torch.empty((P, D, k2), dtype=torch.int32, device=device)
+        self.set_link = torch.empty((P, D, k2), dtype=torch.int8, device=device)
+        self.verdict = torch.empty((P, D), dtype=torch.uint8, device=device)
+        self.tstar = torch.empty((P, D), dtype=torch.float64, device=device)
+        self.acc_list = torch.empty((P * D,), dtype=torch.int32, device=device)
+        self.n_acc = torch.zeros((1,), dtype=torch.int32, device=device)
+        p2 = search_params(sp, max_pivots)
+        p2.k = k2
+        p2.opt_outer = 0
+        nb = int(_lib.lg_search_workspace_bytes(int(n_points), P, C.byref(p2)))
+        self.workspace = torch.empty((nb,), dtype=torch.uint8, device=device)
+
+
+def lg_search_extend(field: Field, pts, nrm, poses, dom_bits, dom_count, sp, round1: SearchBuffers, k_add: int,
+                     request_id: int = 0, set_list=None, list_n=None, list_ok=None,
+                     bufs: Optional[ExtendBuffers] = None, max_pivots: int = 1000, stream=None) -> ExtendBuffers:
+    """Second contact round on the unused fingers of ``round1``'s sets (search
+    parameters ``sp``); ``set_list``/``list_n``/``list_ok``: device arrays
+    choosing the sets (default: every unstable set with a whole draw)."""
+    N, P = int(pts.shape[1]), int(poses.shape[0])
+    if bufs is None:
+        bufs = ExtendBuffers(P, sp, k_add, pts.device, max_pivots, n_points=N)
+    p1 = search_params(sp, max_pivots)
+    ep = ExtendParams(int(k_add), int(request_id), None if set_list is None else set_list.data_ptr(),
+                      None if list_n is None else list_n.data_ptr(), None if list_ok is None else list_ok.data_ptr())
+    _check(_lib.lg_search_extend(field.handle, _ptr(pts), _ptr(nrm), N, _ptr(poses), P, _ptr(dom_bits),
+                                 _ptr(dom_count), C.byref(p1), _ptr(round1.set_pt), _ptr(round1.set_link),
+                                 _ptr(round1.verdict), C.byref(ep), _ptr(bufs.set_pt), _ptr(bufs.set_link),
+                                 _ptr(bufs.verdict), _ptr(bufs.tstar), _ptr(bufs.acc_list), _ptr(bufs.n_acc),
+                                 _ptr(bufs.workspace), bufs.workspace.numel(), _stream(stream)), "lg_search_extend")
     return bufs
 
 

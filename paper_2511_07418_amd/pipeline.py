@@ -19,7 +19,8 @@ class Pipeline:
     synchronising; ``valid_count()`` synchronises and reads the result."""
 
     def __init__(self, field: lg.Field, pts: np.ndarray, nrm: np.ndarray, poses: np.ndarray, sp,
-                 ik=None, sdf=None, device: str = "cuda", max_pivots: int = 1000, cos_hit=None, palm_pt=None):
+                 ik=None, sdf=None, device: str = "cuda", max_pivots: int = 1000, cos_hit=None, palm_pt=None,
+                 extend_k: int = 0, extend_request: int = 7):
         self.field = field
         self.palm_pt = palm_pt      # device int32 [P] of lg_place_palm, or None (no static-link contacts)
         self.cos_hit = cos_hit      # None: nearest-bin query; else the cone (theta_hit) query
@@ -49,6 +50,19 @@ class Pipeline:
             self.sdf = lg.sdf_struct(sdf, self.sdf_vals)
             self.max_acc = self.P * int(sp.draws)
             self.rbuf = lg.RealizeBuffers(self.max_acc, field.n_joints, int(sp.k), self.dev)
+        # the general form (Sec. 5.3, 5.6): unstable round-1 sets that realise
+        # collision-free get extend_k more contacts on unused fingers
+        self.extend_k = int(extend_k)
+        self.extend_request = int(extend_request)
+        if self.extend_k > 0:
+            if ik is None:
+                raise ValueError("the second contact round needs realize (ik, sdf)")
+            self.unstable = None
+            self.rbuf_rej = lg.RealizeBuffers(self.max_acc, field.n_joints, int(sp.k), self.dev)
+            self.ebuf = lg.ExtendBuffers(self.P, sp, self.extend_k, self.dev, max_pivots, n_points=self.N)
+            self.rbuf2 = lg.RealizeBuffers(self.max_acc, field.n_joints, int(sp.k) + self.extend_k, self.dev)
+            import dataclasses
+            self.sp2 = dataclasses.replace(sp, k=int(sp.k) + self.extend_k)
 
     def query(self, stream=None):
         if self.cos_hit is None:
@@ -74,10 +88,29 @@ class Pipeline:
                       int(self.sp.k), int(self.sp.draws), b.acc_list, b.n_acc, self.max_acc, self.ik,
                       bufs=self.rbuf, stream=stream, sp=b.p)
 
+    def extend(self, stream=None):
+        """Second contact round: list the unstable sets, realise them with k
+        contacts, extend those that realise collision-free, realise the
+        accepted extended sets."""
+        b, k = self.sbuf, int(self.sp.k)
+        self.unstable = lg.lg_compact_unstable(b, stream=stream, out=self.unstable)
+        lst, n, _ = self.unstable
+        lg.lg_realize(self.field, self.sdf, self.pts, self.nrm, self.poses, b.set_pt, b.set_link, k,
+                      int(self.sp.draws), lst, n, self.max_acc, self.ik, bufs=self.rbuf_rej, stream=stream, sp=b.p)
+        lg.lg_search_extend(self.field, self.pts, self.nrm, self.poses, self.dom_bits, self.dom_count, self.sp, b,
+                            self.extend_k, request_id=self.extend_request, set_list=lst, list_n=n,
+                            list_ok=self.rbuf_rej.valid, bufs=self.ebuf, stream=stream)
+        e = self.ebuf
+        lg.lg_realize(self.field, self.sdf, self.pts, self.nrm, self.poses, e.set_pt, e.set_link,
+                      int(self.sp2.k), int(self.sp.draws), e.acc_list, e.n_acc, self.max_acc, self.ik,
+                      bufs=self.rbuf2, stream=stream, sp=b.p)
+
     def step(self, stream=None):
         self.query(stream)
         self.search(stream)
         self.realize(stream)
+        if self.extend_k > 0:
+            self.extend(stream)
 
     def n_acc(self) -> int:
         return int(self.sbuf.n_acc.item())
@@ -92,8 +125,13 @@ class Pipeline:
 
     def valid_count(self) -> int:
         """Valid grasps of the last step: accepted sets that pass IK and
-        penetration (with realize), else accepted (verdict) sets."""
+        penetration (with realize), else accepted (verdict) sets; with the
+        second contact round, plus its accepted extended sets that pass."""
         n = self.n_acc()
         if self.ik is None:
             return n
-        return int(self.rbuf.valid[:n].sum().item())
+        v = int(self.rbuf.valid[:n].sum().item())
+        if self.extend_k > 0:
+            n2 = int(self.ebuf.n_acc.item())
+            v += int(self.rbuf2.valid[:n2].sum().item())
+        return v
