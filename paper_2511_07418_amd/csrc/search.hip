@@ -215,9 +215,9 @@ struct LpConst {
 
 // t* of the set held in this lane's LDS column (cd[6 i + c][tid]); status
 // 0 = optimal, 1 = pivot cap, 2 = unbounded ratio test (not expected).
-template <int KM>
+template <int KM, bool WARM = false>
 __device__ inline double lp_lane(float (&cd)[KM * 6][256], int tid, int k, int m, double mu, double rho,
-                                 int max_pivots, const LpConst &cs, int &status_out)
+                                 int max_pivots, const LpConst &cs, int &status_out, int (*warm)[256] = nullptr)
 {
     const int n = k * m;
     const double inv_rho = 1.0 / rho;
@@ -262,25 +262,94 @@ __device__ inline double lp_lane(float (&cd)[KM * 6][256], int tid, int k, int m
     // initial basis: g_0 on the normalisation row, s-_r (w0_r <= 0) or s+_r
     double Bi[7][7], xB[7];
     int basis[7];
-    {
-        double w0[7];
-        column(0, w0);
+#define LG_LP_COLD()                                                                                        \
+    do {                                                                                                    \
+        double w0[7];                                                                                       \
+        column(0, w0);                                                                                      \
+        _Pragma("unroll") for (int r = 0; r < 7; ++r) _Pragma("unroll") for (int c = 0; c < 7; ++c) Bi[r][c] = 0.0; \
+        _Pragma("unroll") for (int r = 0; r < 6; ++r) {                                                       \
+            const double sg = w0[r] <= 0.0 ? 1.0 : -1.0;                                                    \
+            basis[r] = w0[r] <= 0.0 ? n + 6 + r : n + r;                                                    \
+            Bi[r][r] = sg;                                                                                  \
+            Bi[r][6] = -sg * w0[r];                                                                         \
+            xB[r] = -sg * w0[r];                                                                            \
+        }                                                                                                   \
+        Bi[6][6] = 1.0;                                                                                     \
+        basis[6] = 0;                                                                                       \
+        xB[6] = 1.0;                                                                                        \
+    } while (0)
+// replace the basic variable of row lr by column e (al = B^-1 a_e)
+#define LG_LP_PIVOT(lr, al, e)                                                                              \
+    do {                                                                                                    \
+        double pv = 1.0, prow[7], px = 0.0;                                                                 \
+        _Pragma("unroll") for (int c = 0; c < 7; ++c) prow[c] = 0.0;                                        \
+        _Pragma("unroll") for (int r = 0; r < 7; ++r) if (r == (lr)) {                                      \
+            pv = (al)[r];                                                                                   \
+            px = xB[r];                                                                                     \
+            _Pragma("unroll") for (int c = 0; c < 7; ++c) prow[c] = Bi[r][c];                               \
+        }                                                                                                   \
+        const double inv = 1.0 / pv;                                                                        \
+        _Pragma("unroll") for (int c = 0; c < 7; ++c) prow[c] *= inv;                                       \
+        px *= inv;                                                                                          \
+        _Pragma("unroll") for (int r = 0; r < 7; ++r) {                                                     \
+            if (r == (lr)) {                                                                                \
+                _Pragma("unroll") for (int c = 0; c < 7; ++c) Bi[r][c] = prow[c];                           \
+                xB[r] = px;                                                                                 \
+                basis[r] = (e);                                                                             \
+            } else {                                                                                        \
+                _Pragma("unroll") for (int c = 0; c < 7; ++c) Bi[r][c] -= (al)[r] * prow[c];                \
+                xB[r] -= (al)[r] * px;                                                                      \
+            }                                                                                               \
+        }                                                                                                   \
+    } while (0)
+    bool need_cold = true;
+    // Warm start (the "free lunch" of Sec. 5.4): the optimal basis of a
+    // neighbouring problem -- the same column ids, one contact's columns
+    // rebuilt from its new point -- is brought into the cold basis column by
+    // column, each by a primal pivot with the usual ratio test (so the basis
+    // stays feasible; a column without an admissible pivot is left out).  The
+    // simplex then continues from that basis, near the optimum when the
+    // problems are close.  The optimum, t*, does not depend on the start.
+    // warm[r][tid]: the column ids in, the final basis out.
+    if constexpr (WARM) {
+        if (warm[0][tid] >= 0) {
+            LG_LP_COLD();
+            need_cold = false;
+#pragma unroll 1
+            for (int w = 0; w < 7; ++w) {
+                const int col = warm[w][tid];
+                bool inb = false;
 #pragma unroll
-        for (int r = 0; r < 7; ++r)
+                for (int r = 0; r < 7; ++r) inb |= basis[r] == col;
+                if (inb) continue;
+                double a[7], al[7];
+                column(col, a);
 #pragma unroll
-            for (int c = 0; c < 7; ++c) Bi[r][c] = 0.0;
+                for (int r = 0; r < 7; ++r) {
+                    double sacc = 0.0;
 #pragma unroll
-        for (int r = 0; r < 6; ++r) {
-            const double sg = w0[r] <= 0.0 ? 1.0 : -1.0;
-            basis[r] = w0[r] <= 0.0 ? n + 6 + r : n + r;
-            Bi[r][r] = sg;
-            Bi[r][6] = -sg * w0[r];
-            xB[r] = -sg * w0[r];
+                    for (int c = 0; c < 7; ++c) sacc += Bi[r][c] * a[c];
+                    al[r] = sacc;
+                }
+                int lr = -1;
+                double bx = 0.0, ba = 1.0;
+#pragma unroll
+                for (int r = 0; r < 7; ++r) {
+                    if (al[r] > kLpPiv) {
+                        const double lhs = xB[r] * ba, rhs = bx * al[r];
+                        const double band = kLpTol * (ba + fabs(bx)) * al[r];
+                        if (lr < 0 || lhs < rhs - band || (fabs(lhs - rhs) <= band && basis[r] < basis[lr])) {
+                            lr = r;
+                            bx = xB[r];
+                            ba = al[r];
+                        }
+                    }
+                }
+                if (lr >= 0) LG_LP_PIVOT(lr, al, col);
+            }
         }
-        Bi[6][6] = 1.0;
-        basis[6] = 0;
-        xB[6] = 1.0;
     }
+    if (need_cold) LG_LP_COLD();
     auto cost = [&](int j) { return j >= n ? 1.0 : 0.0; };
     auto duals = [&](double *y) {
 #pragma unroll
@@ -409,40 +478,19 @@ __device__ inline double lp_lane(float (&cd)[KM * 6][256], int tid, int k, int m
             status = 2;
             break;
         }
-        double pv = 1.0, prow[7], px = 0.0;
-#pragma unroll
-        for (int c = 0; c < 7; ++c) prow[c] = 0.0;
-#pragma unroll
-        for (int r = 0; r < 7; ++r)
-            if (r == lr) {
-                pv = al[r];
-                px = xB[r];
-#pragma unroll
-                for (int c = 0; c < 7; ++c) prow[c] = Bi[r][c];
-            }
-        const double inv = 1.0 / pv;
-#pragma unroll
-        for (int c = 0; c < 7; ++c) prow[c] *= inv;
-        px *= inv;
-#pragma unroll
-        for (int r = 0; r < 7; ++r) {
-            if (r == lr) {
-#pragma unroll
-                for (int c = 0; c < 7; ++c) Bi[r][c] = prow[c];
-                xB[r] = px;
-                basis[r] = e;
-            } else {
-#pragma unroll
-                for (int c = 0; c < 7; ++c) Bi[r][c] -= al[r] * prow[c];
-                xB[r] -= al[r] * px;
-            }
-        }
+        LG_LP_PIVOT(lr, al, e);
         ++piv;
     }
+#undef LG_LP_PIVOT
+#undef LG_LP_COLD
     double ts = 0.0;
 #pragma unroll
     for (int r = 0; r < 7; ++r)
         if (basis[r] >= n) ts += xB[r];
+    if constexpr (WARM) {
+#pragma unroll
+        for (int r = 0; r < 7; ++r) warm[r][tid] = basis[r];
+    }
     status_out = status;
     return ts;
 }
@@ -497,11 +545,9 @@ k_verdict_lane(const float *__restrict__ pts, const float *__restrict__ nrm, int
 // edge c = max(sigma, extent / kGridMax); points are bucketed by a counting
 // sort.  The search scans shells of cells at Chebyshev distance R = 0, 1, ...
 // around the candidate's cell; points in unscanned cells are at least R c away,
-// so once the best distance is below R c (less a rounding margin) it is exact.
-// Beyond kProjShells the whole domain bitset is scanned.  Distances are FP64,
-// ties go to the lowest point index.
+// so once the best distance is below R c (less a rounding margin) it is exact
+// (project_domain_inc).  Distances are FP64, ties go to the lowest point index.
 constexpr int kGridMax = 64;
-constexpr int kProjShells = 4;
 constexpr uint32_t kPurposeOpt = 5u;
 constexpr double kOptTau = 1e-9;  // candidates within kOptTau of the best criterion value tie
 
@@ -613,16 +659,29 @@ __global__ void k_grid_scatter(const float *__restrict__ pts, int N, const GridD
 
 __device__ inline bool dom_has(const uint32_t *dom, int i) { return (dom[i >> 5] >> (i & 31)) & 1u; }
 
-// nearest point of the domain to y (FP64 distances, lowest index on ties)
-__device__ int project_domain(const GridDev &g, const uint32_t *__restrict__ cell_start,
-                              const int32_t *__restrict__ cell_pts, const float *__restrict__ pts, int N,
-                              const uint32_t *__restrict__ dom, double yx, double yy, double yz)
+// Nearest domain point to y given a domain point `inc` (the contact's current
+// point): the same result as project_domain (FP64 distances, lowest index on
+// ties), with inc as the incumbent.  Shell R is scanned only while R c can
+// still beat the best distance, cells whose box lies farther than the best
+// are skipped, and no point beyond |y - inc| needs a look: the scan ends by
+// R = ceil(|y - inc| / c) + 1 (the whole domain is scanned only past
+// kProjShellsInc shells, for steps of many cell edges).  Points are binned in
+// float: the shell and box tests keep 1e-6 m of slack.
+constexpr int kProjShellsInc = 8;
+__device__ int project_domain_inc(const GridDev &g, const uint32_t *__restrict__ cell_start,
+                                  const int32_t *__restrict__ cell_pts, const float *__restrict__ pts, int N,
+                                  const uint32_t *__restrict__ dom, double yx, double yy, double yz, int inc)
 {
-    const int cx = (int)floor((yx - g.lo[0]) * (double)g.inv_cell);
-    const int cy = (int)floor((yy - g.lo[1]) * (double)g.inv_cell);
-    const int cz = (int)floor((yz - g.lo[2]) * (double)g.inv_cell);
-    double best = INFINITY;
-    int bi = -1;
+    const double fx = (yx - g.lo[0]) * (double)g.inv_cell, fy = (yy - g.lo[1]) * (double)g.inv_cell,
+                 fz = (yz - g.lo[2]) * (double)g.inv_cell;
+    const int cx = (int)floor(fx), cy = (int)floor(fy), cz = (int)floor(fz);
+    const double c = (double)g.cell;
+    double best;
+    int bi = inc;
+    {
+        const double ex = (double)pts[inc] - yx, ey = (double)pts[N + inc] - yy, ez = (double)pts[2 * N + inc] - yz;
+        best = ex * ex + ey * ey + ez * ez;
+    }
     auto consider = [&](int i) {
         const double ex = (double)pts[i] - yx, ey = (double)pts[N + i] - yy, ez = (double)pts[2 * N + i] - yz;
         const double d2 = ex * ex + ey * ey + ez * ez;
@@ -631,7 +690,15 @@ __device__ int project_domain(const GridDev &g, const uint32_t *__restrict__ cel
             bi = i;
         }
     };
-    for (int R = 0; R <= kProjShells; ++R) {
+    // squared distance from y to the box of cell (x, yv, z), in cell units
+    auto box_d2 = [&](int x, int yv, int z) {
+        const double ax = fmax(fmax((double)x - fx, fx - (double)(x + 1)), 0.0);
+        const double ay = fmax(fmax((double)yv - fy, fy - (double)(yv + 1)), 0.0);
+        const double az = fmax(fmax((double)z - fz, fz - (double)(z + 1)), 0.0);
+        return (ax * ax + ay * ay + az * az) * c * c;
+    };
+    for (int R = 0; R <= kProjShellsInc; ++R) {
+        if (R > 0 && sqrt(best) < (double)(R - 1) * c - 1e-6) return bi;  // shell R cannot hold a closer point
         for (int dz = -R; dz <= R; ++dz) {
             const int z = cz + dz;
             if (z < 0 || z >= g.dims[2]) continue;
@@ -641,9 +708,11 @@ __device__ int project_domain(const GridDev &g, const uint32_t *__restrict__ cel
                 const bool edge = (dz == -R || dz == R || dy == -R || dy == R);
                 for (int dx = -R; dx <= R; dx += (edge ? 1 : 2 * R)) {
                     const int x = cx + dx;
-                    if (x >= 0 && x < g.dims[0]) {
-                        const int c = (z * g.dims[1] + yv) * g.dims[0] + x;
-                        for (uint32_t q = cell_start[c]; q < cell_start[c + 1]; ++q) {
+                    // points are binned in float: keep 1e-6 m of slack on the box test
+                    const double lim = sqrt(best) + 1e-6;
+                    if (x >= 0 && x < g.dims[0] && box_d2(x, yv, z) <= lim * lim) {
+                        const int cc = (z * g.dims[1] + yv) * g.dims[0] + x;
+                        for (uint32_t q = cell_start[cc]; q < cell_start[cc + 1]; ++q) {
                             const int i = cell_pts[q];
                             if (dom_has(dom, i)) consider(i);
                         }
@@ -652,9 +721,8 @@ __device__ int project_domain(const GridDev &g, const uint32_t *__restrict__ cel
                 }
             }
         }
-        if (bi >= 0 && sqrt(best) < (double)R * (double)g.cell - 1e-6) return bi;
     }
-    // far from every scanned cell: the whole domain
+    if (sqrt(best) < (double)kProjShellsInc * c - 1e-6) return bi;
     const int NW = (N + 31) >> 5;
     for (int w = 0; w < NW; ++w) {
         uint32_t x = dom[w];
@@ -667,24 +735,89 @@ __device__ int project_domain(const GridDev &g, const uint32_t *__restrict__ cel
     return bi;
 }
 
+
 // GS lanes per set (GS >= n_inner, a power of two): lane j evaluates candidate
 // j of every step; the group agrees on the pick by shuffles and one ballot.
+// Alg. 2, the candidates of one round (Sec. 5.4): thread per (set, contact
+// i, candidate j).  Contact i's candidates are drawn around its point at the
+// start of the round (contact i moves only at its own step), so a round's
+// projections are independent of its criterion evaluations and run here, at
+// full occupancy, before them: y = p_i + dx x_i + dy y_i with (dx, dy) =
+// sigma * Box-Muller of Philox block (g + pose_offset, d, 5 | step << 8,
+// request_id), step = (round k + i) n_inner + j, and cand = the nearest point
+// of contact i's domain (incumbent p_i).  cands[((t k + i) n_inner + j)], t =
+// the set's rank among the sets of valid poses; -1 for sets not drawn.
+__global__ void __launch_bounds__(256)
+k_opt_project(const float *__restrict__ pts, const float *__restrict__ nrm, int N,
+              const int32_t *__restrict__ valid_poses, const int32_t *__restrict__ n_valid_poses,
+              const uint32_t *__restrict__ dom_bits, const uint32_t *__restrict__ dom_count,
+              const int32_t *__restrict__ palm_pt, int F, int D, int k, int round, int n_inner, double sigma,
+              uint32_t seed_lo, uint32_t seed_hi, uint32_t request_id, int64_t pose_offset,
+              const GridDev *__restrict__ gdp, const uint32_t *__restrict__ cell_start,
+              const int32_t *__restrict__ cell_pts, const int32_t *__restrict__ set_pt, int32_t *__restrict__ cands)
+{
+    const GridDev g = *gdp;
+    const int NW = (N + 31) >> 5;
+    const int64_t per_set = (int64_t)k * n_inner;
+    const int64_t n_total = (int64_t)(*n_valid_poses) * D * per_set;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n_total; u += stride) {
+        const int64_t t = u / per_set;
+        const int rem = (int)(u - t * per_set), i = rem / n_inner, j = rem - i * n_inner;
+        const int64_t pg = valid_poses[t / D];
+        const int d = (int)(t % D);
+        const int32_t *sp = set_pt + (pg * D + d) * k;
+        const uint32_t fm = choose_fingers(eligible_fingers(dom_count, pg, F), k, (uint32_t)(pose_offset + pg), d,
+                                           request_id, seed_lo, seed_hi);
+        const int pc = palm_pt ? palm_pt[pg] : -1;
+        bool drawn = fm != 0 && pc < N;
+        for (int q = 0; q < k; ++q) drawn &= sp[q] >= 0 && sp[q] < N;
+        if (!drawn) {
+            cands[u] = -1;
+            continue;
+        }
+        const int idx = sp[i];
+        const double px = pts[idx], py = pts[N + idx], pz = pts[2 * N + idx];
+        double tx[3], ty[3];
+        duff_basis(nrm[idx], nrm[N + idx], nrm[2 * N + idx], tx, ty);
+        uint32_t w[4];
+        const uint32_t step = (uint32_t)((round * k + i) * n_inner + j);
+        philox4x32_10((uint32_t)(pose_offset + pg), (uint32_t)d, kPurposeOpt | (step << 8), request_id, seed_lo,
+                      seed_hi, w);
+        const double u1 = ((double)(w[0] >> 8) + 1.0) * (1.0 / 16777216.0);
+        const double u2 = (double)(w[1] >> 8) * (1.0 / 16777216.0);
+        const double rr = sqrt(-2.0 * log(u1));
+        const double dx = sigma * rr * cos(2.0 * M_PI * u2), dy = sigma * rr * sin(2.0 * M_PI * u2);
+        const int fi = select_in_word(fm, (uint32_t)i);  // finger of contact i
+        cands[u] = project_domain_inc(g, cell_start, cell_pts, pts, N, dom_bits + (pg * F + fi) * NW,
+                                      px + dx * tx[0] + dy * ty[0], py + dx * tx[1] + dy * ty[1],
+                                      pz + dx * tx[2] + dy * ty[2], idx);
+    }
+}
+
+// Alg. 2, the criterion side of one round: a group of GS = pow2 >= n_inner
+// lanes per set (lane = candidate), grid-stride over the sets of poses with
+// non-empty domains.  Contacts i = 0..k-1 in turn: each lane evaluates the LP
+// of the set with contact i at its candidate (cands of k_opt_project), the
+// group takes the minimum by xor-shuffles and the first lane within kOptTau
+// of it by one ballot; contact i moves there.  The set's points are written
+// back after the round; tstar (the last step's J) and, after the last round,
+// the verdict.
 template <int KM, int GS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, const int32_t *__restrict__ valid_poses,
-           const int32_t *__restrict__ n_valid_poses, const uint32_t *__restrict__ dom_bits,
-           const uint32_t *__restrict__ dom_count, const int32_t *__restrict__ palm_pt, int F, int D, int k, int m,
-           double mu, double rho, double eps, int max_pivots, LpConst cs, int n_outer, int n_inner, double sigma,
-           uint32_t seed_lo, uint32_t seed_hi, uint32_t request_id, int64_t pose_offset,
-           const GridDev *__restrict__ gdp, const uint32_t *__restrict__ cell_start,
-           const int32_t *__restrict__ cell_pts, int32_t *__restrict__ set_pt, uint8_t *__restrict__ verdict,
-           double *__restrict__ tstar)
+           const int32_t *__restrict__ n_valid_poses, const uint32_t *__restrict__ dom_count,
+           const int32_t *__restrict__ palm_pt, int F, int D, int k, int m, double mu, double rho, double eps,
+           int max_pivots, LpConst cs, int n_inner, bool last, uint32_t seed_lo, uint32_t seed_hi,
+           uint32_t request_id, int64_t pose_offset, const int32_t *__restrict__ cands, int32_t *__restrict__ set_pt,
+           uint8_t *__restrict__ verdict, double *__restrict__ tstar)
 {
     __shared__ float cd[KM * 6][256];
     __shared__ int cur[KM][256];  // the set's current point indices (every lane of a group holds them)
+    __shared__ int wbs[7][256];   // per lane: the warm basis of its LP in, its final basis out
+    __shared__ int cbs[7][256];   // per lane: the current set's optimal basis (the last pick's)
     const int tid = threadIdx.x, lane = tid & 63, j = tid % GS, gbase = lane - j;
-    const GridDev g = *gdp;
-    const int NW = (N + 31) >> 5;
+    const int wbase = tid - lane;  // first thread of this wave
     const int64_t n_work = (int64_t)(*n_valid_poses) * D;
     const int64_t groups = ((int64_t)gridDim.x * blockDim.x) / GS;
     auto load = [&](int ci, int idx) {
@@ -719,50 +852,44 @@ k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, 
         }
         if (pc >= 0) load(k, pc);
         double J = INFINITY;
-        for (int r = 0; r < n_outer; ++r) {
-            for (int i = 0; i < k; ++i) {
-                int cand = -1;
-                double Jc = INFINITY;
-                if (j < n_inner) {
-                    const double px = cd[6 * i + 0][tid], py = cd[6 * i + 1][tid], pz = cd[6 * i + 2][tid];
-                    double tx[3], ty[3];
-                    duff_basis(cd[6 * i + 3][tid], cd[6 * i + 4][tid], cd[6 * i + 5][tid], tx, ty);
-                    uint32_t w[4];
-                    const uint32_t step = (uint32_t)((r * k + i) * n_inner + j);
-                    philox4x32_10((uint32_t)(pose_offset + pg), (uint32_t)d, kPurposeOpt | (step << 8), request_id,
-                                  seed_lo, seed_hi, w);
-                    const double u1 = ((double)(w[0] >> 8) + 1.0) * (1.0 / 16777216.0);
-                    const double u2 = (double)(w[1] >> 8) * (1.0 / 16777216.0);
-                    const double rr = sqrt(-2.0 * log(u1));
-                    const double dx = sigma * rr * cos(2.0 * M_PI * u2), dy = sigma * rr * sin(2.0 * M_PI * u2);
-                    const int fi = select_in_word(fm, (uint32_t)i);  // finger of contact i
-                    cand = project_domain(g, cell_start, cell_pts, pts, N, dom_bits + (pg * F + fi) * NW,
-                                          px + dx * tx[0] + dy * ty[0], py + dx * tx[1] + dy * ty[1],
-                                          pz + dx * tx[2] + dy * ty[2]);
-                    if (cand >= 0) {  // always, for a drawn set (its domains are non-empty)
-                        load(i, cand);
-                        int st = 0;
-                        Jc = lp_lane<KM>(cd, tid, kc, m, mu, rho, max_pivots, cs, st);
-                        if (st != 0) Jc = INFINITY;
-                    }
+        // optimal basis of the current set (the last pick's), the warm start of
+        // the next contact's candidates; none before the round's first pick
+        cbs[0][tid] = -1;
+        for (int i = 0; i < k; ++i) {
+            int cand = -1;
+            double Jc = INFINITY;
+#pragma unroll
+            for (int r = 0; r < 7; ++r) wbs[r][tid] = cbs[r][tid];
+            if (j < n_inner) {
+                cand = cands[(t * k + i) * n_inner + j];
+                if (cand >= 0) {  // always, for a drawn set (its domains are non-empty)
+                    load(i, cand);
+                    int st = 0;
+                    Jc = lp_lane<KM, true>(cd, tid, kc, m, mu, rho, max_pivots, cs, st, wbs);
+                    if (st != 0) Jc = INFINITY;
                 }
-                double mn = Jc;
-                for (int off = GS >> 1; off > 0; off >>= 1) mn = fmin(mn, __shfl_xor(mn, off, GS));
-                const unsigned long long ok = __ballot(Jc <= mn + kOptTau);
-                const int js = __ffsll((long long)((ok >> gbase) & ((GS == 64) ? ~0ull : ((1ull << GS) - 1)))) - 1;
-                const int pick = __shfl(cand, gbase + js, 64);
-                const double Jp = __shfl(Jc, gbase + js, 64);
-                if (pick >= 0) {
-                    J = Jp;
-                    cur[i][tid] = pick;
-                }
-                load(i, cur[i][tid]);
             }
+            double mn = Jc;
+            for (int off = GS >> 1; off > 0; off >>= 1) mn = fmin(mn, __shfl_xor(mn, off, GS));
+            const unsigned long long ok = __ballot(Jc <= mn + kOptTau);
+            const int js = __ffsll((long long)((ok >> gbase) & ((GS == 64) ? ~0ull : ((1ull << GS) - 1)))) - 1;
+            const int pick = __shfl(cand, gbase + js, 64);
+            const double Jp = __shfl(Jc, gbase + js, 64);
+            if (pick >= 0) {
+                J = Jp;
+                cur[i][tid] = pick;
+                // the picked lane's final basis (written by that lane of this wave)
+                if (!isinf(Jp)) {
+#pragma unroll
+                    for (int r = 0; r < 7; ++r) cbs[r][tid] = wbs[r][wbase + gbase + js];
+                }
+            }
+            load(i, cur[i][tid]);
         }
         if (j == 0) {
             for (int i = 0; i < k; ++i) sp[i] = cur[i][tid];
-            verdict[sid] = J <= eps ? 1 : 0;
             tstar[sid] = isinf(J) ? __builtin_nan("") : J;
+            if (last) verdict[sid] = J <= eps ? 1 : 0;
         }
     }
 }
@@ -1025,6 +1152,7 @@ extern "C" {
 //            [valid pose list P] [n_valid_poses] [pose_valid P bytes]
 //            and, for the contact-point optimisation, [grid params]
 //            [cell counts/cursor (kGridMax+1)^3] [cell starts +1] [cell points N]
+//            [a round's candidates P D k n_inner]
 struct SearchWs {
     uint32_t *chunk_count, *chunk_off, *pchunk_count, *pchunk_off;
     int32_t *valid_poses, *n_valid_poses;
@@ -1032,10 +1160,12 @@ struct SearchWs {
     GridDev *grid;
     uint32_t *cell_count, *cell_start;
     int32_t *cell_pts;
+    int32_t *cands;
     size_t bytes;
 };
 
-static SearchWs search_ws(void *base, int64_t n_points, int64_t n_poses, int64_t draws, bool opt)
+static SearchWs search_ws(void *base, int64_t n_points, int64_t n_poses, int64_t draws, bool opt, int64_t k = 0,
+                          int64_t n_inner = 0)
 {
     const int64_t n_sets = n_poses * draws;
     const int64_t nc = (n_sets + kChunk - 1) / kChunk, npc = (n_poses + kChunk - 1) / kChunk;
@@ -1052,6 +1182,7 @@ static SearchWs search_ws(void *base, int64_t n_points, int64_t n_poses, int64_t
     w.grid = nullptr;
     w.cell_count = w.cell_start = nullptr;
     w.cell_pts = nullptr;
+    w.cands = nullptr;
     if (opt) {
         const int64_t ncell = (int64_t)(kGridMax + 1) * (kGridMax + 1) * (kGridMax + 1);
         char *b = static_cast<char *>(base);
@@ -1062,7 +1193,9 @@ static SearchWs search_ws(void *base, int64_t n_points, int64_t n_poses, int64_t
         w.cell_start = reinterpret_cast<uint32_t *>(b + off);
         off += (size_t)(ncell + 1) * 4;
         w.cell_pts = reinterpret_cast<int32_t *>(b + off);
-        off += (size_t)n_points * 4;
+        off += ((size_t)n_points * 4 + 255) & ~(size_t)255;
+        w.cands = reinterpret_cast<int32_t *>(b + off);
+        off += (size_t)n_sets * k * n_inner * 4;
     }
     w.bytes = off + 256;
     return w;
@@ -1071,7 +1204,8 @@ static SearchWs search_ws(void *base, int64_t n_points, int64_t n_poses, int64_t
 size_t lg_search_workspace_bytes(int32_t n_points, int32_t n_poses, const lg_search_params *p)
 {
     if (!p || n_poses <= 0 || p->draws <= 0) return 256;
-    return search_ws(nullptr, std::max(n_points, 0), n_poses, p->draws, p->opt_outer > 0).bytes;
+    return search_ws(nullptr, std::max(n_points, 0), n_poses, p->draws, p->opt_outer > 0, p->k,
+                     p->opt_outer > 0 ? p->opt_inner : 0).bytes;
 }
 
 }  // extern "C"
@@ -1108,7 +1242,7 @@ static lg_status search_impl(const lg_field *field, const float *pts, const floa
     if (lds > 48 * 1024) return fail(LG_EUNSUPPORTED, "too many points for the draw rank structure");
     hipStream_t s = as_stream(stream);
     const bool opt = p->opt_outer > 0;
-    const SearchWs ws = search_ws(workspace, n_points, n_poses, p->draws, opt);
+    const SearchWs ws = search_ws(workspace, n_points, n_poses, p->draws, opt, p->k, opt ? p->opt_inner : 0);
     hipLaunchKernelGGL(k_draw, dim3(n_poses), dim3(kDrawThreads), lds, s, H, field->d_bits, pts, nrm, n_points,
                        poses, dom_bits, dom_count, palm, p->draws, p->k, (uint32_t)p->seed, (uint32_t)(p->seed >> 32),
                        p->request_id, p->pose_offset, set_pt, set_link, ws.pose_valid, verdict, tstar);
@@ -1157,17 +1291,25 @@ static lg_status search_impl(const lg_field *field, const float *pts, const floa
         const int gs = p->opt_inner <= 1 ? 1 : p->opt_inner <= 2 ? 2 : p->opt_inner <= 4 ? 4 : p->opt_inner <= 8 ? 8 : 16;
         const dim3 ogrid((unsigned)std::max<int64_t>(
             1, std::min<int64_t>((n_sets * gs + 255) / 256, (int64_t)n_cu * 8)));
+        const dim3 pgrid((unsigned)std::max<int64_t>(
+            1, std::min<int64_t>((n_sets * p->k * p->opt_inner + 255) / 256, (int64_t)n_cu * 32)));
 #define LG_OPT(KM, GS)                                                                                           \
     hipLaunchKernelGGL((k_optimize<KM, GS>), ogrid, dim3(256), 0, s, pts, nrm, n_points, ws.valid_poses,           \
-                       ws.n_valid_poses, dom_bits, dom_count, palm, H.F, p->draws, p->k, p->m_edges, (double)p->mu, \
-                       (double)p->moment_scale, (double)p->eps, p->max_pivots, cs, p->opt_outer, p->opt_inner,    \
-                       (double)p->opt_sigma, (uint32_t)p->seed, (uint32_t)(p->seed >> 32), p->request_id,         \
-                       p->pose_offset, ws.grid, ws.cell_start, ws.cell_pts, set_pt, verdict, tstar)
+                       ws.n_valid_poses, dom_count, palm, H.F, p->draws, p->k, p->m_edges, (double)p->mu,         \
+                       (double)p->moment_scale, (double)p->eps, p->max_pivots, cs, p->opt_inner,                  \
+                       r == p->opt_outer - 1, (uint32_t)p->seed, (uint32_t)(p->seed >> 32), p->request_id,        \
+                       p->pose_offset, ws.cands, set_pt, verdict, tstar)
 #define LG_OPT_K(GS)                                                                                             \
     if (kk <= 3) LG_OPT(3, GS); else if (kk <= 4) LG_OPT(4, GS); else if (kk <= 5) LG_OPT(5, GS);              \
     else if (kk <= 6) LG_OPT(6, GS); else LG_OPT(8, GS)
-        if (gs == 1) { LG_OPT_K(1); } else if (gs == 2) { LG_OPT_K(2); } else if (gs == 4) { LG_OPT_K(4); }
-        else if (gs == 8) { LG_OPT_K(8); } else { LG_OPT_K(16); }
+        for (int r = 0; r < p->opt_outer; ++r) {
+            hipLaunchKernelGGL(k_opt_project, pgrid, dim3(256), 0, s, pts, nrm, n_points, ws.valid_poses,
+                               ws.n_valid_poses, dom_bits, dom_count, palm, H.F, p->draws, p->k, r, p->opt_inner,
+                               (double)p->opt_sigma, (uint32_t)p->seed, (uint32_t)(p->seed >> 32), p->request_id,
+                               p->pose_offset, ws.grid, ws.cell_start, ws.cell_pts, set_pt, ws.cands);
+            if (gs == 1) { LG_OPT_K(1); } else if (gs == 2) { LG_OPT_K(2); } else if (gs == 4) { LG_OPT_K(4); }
+            else if (gs == 8) { LG_OPT_K(8); } else { LG_OPT_K(16); }
+        }
 #undef LG_OPT_K
 #undef LG_OPT
         LG_HIP(hipGetLastError());
