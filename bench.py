@@ -49,6 +49,12 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving run (req/s)")
     ap.add_argument("--serve-rates", default="5,20,50,100,400", help="serve mode: comma-separated arrival rates")
     ap.add_argument("--serve-seconds", type=float, default=6.0, help="arrival window of the serving run (s)")
+    ap.add_argument("--serve-requests", type=int, default=0,
+                    help="serve mode: exactly this many requests per rate (0: Poisson count over --serve-seconds)")
+    ap.add_argument("--serve-modes", default="batched",
+                    help="serve mode: comma-separated server modes, 'batched' (descriptor-table launches) "
+                         "and/or 'streams' (one stream per request)")
+    ap.add_argument("--serve-alone", type=int, default=40, help="requests of each stream re-run one at a time")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--opt-outer", type=int, default=0,
                     help="rounds of contact-point optimisation (Alg. 2) before the verdicts; 0 = the plain method")
@@ -185,8 +191,11 @@ def realize_flops_per_set(w) -> float:
     return 2.0 * it * fma + 63.0 * samples
 
 
-def serve_bench(torch, lg, rate: float, seconds: float, seed: int = 0, alone_sample: int = 40) -> dict:
-    """Serving stream: Poisson arrivals at ``rate`` req/s for ``seconds``.
+def serve_bench(torch, lg, rate: float, seconds: float, seed: int = 0, alone_sample: int = 40,
+                n_requests: int = 0, batched: bool = True) -> dict:
+    """Serving stream: Poisson arrivals at ``rate`` req/s for ``seconds``
+    (or exactly ``n_requests`` arrivals), on a server in batched or
+    per-stream mode.
 
     Each request is a sphere (R = 40 mm) or a superquadric (axes U[30,80] mm,
     exponents U[0.3,2]) with N log-uniform in [2k, 64k] points, a pose budget
@@ -210,7 +219,7 @@ def serve_bench(torch, lg, rate: float, seconds: float, seed: int = 0, alone_sam
         o = synth.superquadric_object(seed + i, 65536)
         pool.append((o, synth.sdf_superquadric(o)))
     ik = synth.IKParams()
-    n_req = max(1, int(rng.poisson(rate * seconds)))
+    n_req = n_requests if n_requests > 0 else max(1, int(rng.poisson(rate * seconds)))
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
     reqs = []
     for r in range(n_req):
@@ -228,15 +237,20 @@ def serve_bench(torch, lg, rate: float, seconds: float, seed: int = 0, alone_sam
         f, p, nm, po, sp, rid, ik_, sdf_ = a
         return srv.make_request(f, p, nm, po, sp, rid, ik=ik_, sdf=sdf_)
 
-    srv = lg.Server(budget_bytes=48 << 30, max_active=8, chunk_poses=4096)
+    mode = "batched" if batched else "streams"
+    srv = lg.Server(budget_bytes=48 << 30, max_active=8, chunk_poses=4096, batched=batched)
     built = [make(srv, a) for _, a in reqs]
+    print(f"serve {mode} {rate:g} req/s: {n_req} requests over {arrivals[-1]:.1f} s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     tickets = []
-    for (arr, _), (req, keep) in zip(reqs, built):
+    for i, ((arr, _), (req, keep)) in enumerate(zip(reqs, built)):
         dt = arr - (time.perf_counter() - t0)
         if dt > 0:
             time.sleep(dt)
         tickets.append(srv.submit(req))
+        if (i + 1) % 100 == 0:
+            print(f"  submitted {i + 1}/{n_req} at {time.perf_counter() - t0:.1f} s, "
+                  f"completed {srv.stats()['completed']}", file=sys.stderr, flush=True)
     res = [srv.wait(t, 600.0) for t in tickets]
     assert all(r["state"] == lg.LG_REQ_DONE for r in res), "serving request did not complete"
     lat = np.array([r["t_done"] - r["t_submit"] for r in res]) * 1e3
@@ -245,7 +259,7 @@ def serve_bench(torch, lg, rate: float, seconds: float, seed: int = 0, alone_sam
     st = srv.stats()
     srv.destroy()
     # a sample of the same requests, one at a time
-    srv = lg.Server(budget_bytes=48 << 30, max_active=8, chunk_poses=4096)
+    srv = lg.Server(budget_bytes=48 << 30, max_active=8, chunk_poses=4096, batched=batched)
     idx = np.linspace(0, n_req - 1, min(alone_sample, n_req)).astype(int)
     alone, alone_valid, same = [], 0, True
     for i in idx:
@@ -259,7 +273,9 @@ def serve_bench(torch, lg, rate: float, seconds: float, seed: int = 0, alone_sam
     for f in fields.values():
         f.release()
     alone = np.array(alone)
-    return {"rate_rps": rate, "requests": n_req, "poses": int(sum(len(a[3]) for _, a in reqs)),
+    return {"mode": mode, "rate_rps": rate, "requests": n_req, "poses": int(sum(len(a[3]) for _, a in reqs)),
+            "span_s": span, "batches": int(st["batches"]),
+            "chunks_per_batch": (st["batched_chunks"] / st["batches"]) if st["batches"] else None,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "valid_grasps": int(n_valid), "valid_grasps_per_s": n_valid / span,
             "peak_bytes": int(st["peak_bytes"]),
@@ -527,7 +543,12 @@ def main():
         return
     if args.mode == "serve":
         for rate in [float(r) for r in args.serve_rates.split(",")]:
-            print(json.dumps({"serving": serve_bench(torch, lg, rate, args.serve_seconds, args.seed)}), flush=True)
+            for mode in args.serve_modes.split(","):
+                if mode not in ("batched", "streams"):
+                    raise SystemExit(f"unknown serve mode {mode!r}")
+                r = serve_bench(torch, lg, rate, args.serve_seconds, args.seed, args.serve_alone,
+                                args.serve_requests, batched=(mode == "batched"))
+                print(json.dumps({"serving": r}), flush=True)
         return
     w = synth.workload(args.workload, seed=args.seed, with_sdf=(args.workload == "c3"))
     if args.self_collision and w.ik is not None:

@@ -404,17 +404,30 @@ lg_status lg_realize(const lg_field *field, const lg_sdf *sdf, const float *pts,
 /* resident and interleaves many requests on one GPU.  A request (object +    */
 /* palm poses + search parameters) is admitted when its device memory fits   */
 /* the HBM budget (FIFO); its poses are processed in chunks of `chunk_poses`, */
-/* chunks of different requests run concurrently on up to `max_active`        */
-/* streams, and a request's RNG counters depend only on (request_id, pose     */
-/* index within the request, draw), so its result is the same alone and in    */
-/* any mix.  Host API, thread-safe; work runs on a server thread.             */
+/* chunks of different requests run concurrently, and a request's RNG        */
+/* counters depend only on (request_id, pose index within the request,        */
+/* draw), so its result is the same alone and in any mix.                     */
+/* Two ways to run the chunks:                                                */
+/*  - batched = 0: each request's chunk launches its own kernels on the       */
+/*    request's stream (up to `max_active` streams);                          */
+/*  - batched = 1: the next chunk of every idle request is described in a     */
+/*    per-chunk descriptor table (its field, buffers, sizes and parameters)   */
+/*    and the batch runs as one launch per stage: query, draws, pose list,    */
+/*    verdicts, accepted-set list, IK + penetration, counters.  Chunks of     */
+/*    uneven size share a launch (each owns the blocks its size needs); the   */
+/*    kernels with a size template (fingers, contacts, joints per finger)     */
+/*    take one launch per size class present.  Two batches are in flight at   */
+/*    most.  Requests with the contact-point optimisation (opt_outer > 0)     */
+/*    run on their own streams in either mode.                                */
+/* Host API, thread-safe; work runs on a server thread.                       */
 /* ------------------------------------------------------------------------ */
 typedef struct lg_server lg_server;
 
 typedef struct {
     uint64_t budget_bytes;  /* device memory reserved for admitted requests */
-    int32_t max_active;     /* requests in flight at once (one stream each), 1..64 */
+    int32_t max_active;     /* requests in flight at once, 1..64 */
     int32_t chunk_poses;    /* poses per scheduling quantum, >= 1 */
+    int32_t batched;        /* 1: batched launches over a descriptor table (see above) */
 } lg_server_params;
 
 typedef struct {
@@ -454,6 +467,7 @@ typedef struct {
     int64_t submitted, admitted, completed, cancelled, rejected, failed;
     uint64_t budget_bytes, bytes_in_use, peak_bytes;
     int32_t queued, active;
+    int64_t batches, batched_chunks;  /* batched launches so far and the chunks they held */
 } lg_server_stats;
 
 /* Device bytes a request reserves while admitted (inputs + one chunk of

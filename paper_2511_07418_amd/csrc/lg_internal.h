@@ -355,4 +355,97 @@ __device__ inline float sdf_trilinear(const SdfDev &S, float yx, float yy, float
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// cos, sin of 2 pi e / m for the m edges of the linearised friction cone
+struct LpConst {
+    double ce[16], se[16];
+};
+
+// IK and penetration parameters of lg_realize on the device
+struct IkDev {
+    int iters, phase1;
+    float lambda, beta, tol_pos, tol_ang, margin;
+    int self_collision;
+    uint32_t seed_lo, seed_hi, request_id;
+    int64_t pose_offset;
+};
+
+// ---- batched chunks ---------------------------------------------------------
+// A server runs the chunks of several requests through one launch per stage
+// (query, draws, pose compaction, verdicts, set compaction, realize,
+// counters).  A ChunkDesc holds every argument of one chunk's kernels; its
+// buffers are the request's own, so chunks of a batch share nothing.
+struct ChunkDesc {
+    DevHand H;
+    const uint32_t *merged, *bits;
+    const int32_t *wit;  // witness table, or null
+    const float *pts, *nrm, *poses;  // poses: the chunk's first pose
+    const float4 *bounds;
+    int N, P, D, k, m, max_pivots;
+    uint32_t seed_lo, seed_hi, request_id;
+    int64_t pose_offset;  // the chunk's first pose within its request
+    double mu, rho, eps;
+    LpConst cs;
+    uint32_t *dom_bits, *dom_count;
+    int32_t *set_pt;
+    int8_t *set_link;
+    uint8_t *verdict;
+    double *tstar;
+    uint8_t *pose_valid;
+    uint32_t *pchunk_count, *pchunk_off;
+    int32_t *valid_poses, *n_valid_poses;
+    uint32_t *chunk_count, *chunk_off;
+    int32_t *acc, *n_acc;
+    int realize;
+    SdfDev S;
+    IkDev ik;
+    float *q, *err, *ang, *depth;
+    uint8_t *valid;
+    unsigned long long *counters;
+};
+
+// One launch over some chunks of a batch (all pointers on the device):
+// member j is table entry idx[j] and owns blocks [first[j], first[j + 1]);
+// first[0] = 0, first[n] = blocks; a member may own no block.
+struct BatchLaunch {
+    const ChunkDesc *d;
+    const uint16_t *idx;
+    const uint32_t *first;
+    int n;
+    uint32_t blocks;
+};
+
+// the member that owns block b (first[lo] <= b < first[lo + 1])
+__device__ inline int batch_member(const uint32_t *__restrict__ first, int n, uint32_t b)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (first[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Batched launchers (one kernel launch each; the member's blocks follow the
+// single-chunk kernel's grid).  Blocks per member:
+//   query, draws: P;  compaction count/scatter: compact_blocks(n);
+//   compaction scan: 1;  verdicts: verdict_blocks;  realize: realize_blocks.
+lg_status query_batch(const BatchLaunch &b, int W, int F, bool lat, hipStream_t s);
+size_t draw_lds_bytes(int F, int N);
+lg_status draw_batch(const BatchLaunch &b, size_t lds, hipStream_t s);
+uint32_t compact_blocks(int64_t n);
+// poses = true: the pose list of the draws; false: the accepted set list
+lg_status compact_count_batch(const BatchLaunch &b, bool poses, hipStream_t s);
+lg_status compact_scan_batch(const BatchLaunch &b, bool poses, hipStream_t s);
+lg_status compact_scatter_batch(const BatchLaunch &b, bool poses, hipStream_t s);
+uint32_t verdict_blocks(int64_t n_sets, int n_cu);
+LpConst lp_const(int m);
+// the search workspace's lists of a chunk of P poses (no contact optimisation)
+void chunk_workspace(void *ws, int64_t n_points, int64_t n_poses, int64_t draws, ChunkDesc &c);
+lg_status verdict_batch(const BatchLaunch &b, int km, hipStream_t s);
+uint32_t realize_blocks(int64_t max_acc, int F, int n_cu);
+lg_status realize_batch(const BatchLaunch &b, int max_dof, hipStream_t s);
+
 }  // namespace lg

@@ -160,21 +160,30 @@ __device__ inline int nearest_bin_lut4(const uint32_t *lut, const float4 *c4, in
     return bi;
 }
 
+// LDS of one query block
+template <int FM, bool LAT>
+struct QueryLds {
+    float4 cb4[kMaxBins];
+    uint32_t lut[6 * kLutRes * kLutRes];
+    Affine aff[LAT ? 1 : FM];
+    uint32_t cnt[FM][kQueryWaves];
+};
+
+// the domains of pose g (one block)
 template <int W, int FM, bool LAT>
-__global__ void __launch_bounds__(kQueryThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
-k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict__ pts,
-        const float *__restrict__ nrm, int N, const float *__restrict__ poses, const float4 *__restrict__ bounds,
-        uint32_t *__restrict__ dom_bits, uint32_t *__restrict__ dom_count)
+__device__ __forceinline__ void query_pose(QueryLds<FM, LAT> &L, const DevHand &H, const uint32_t *__restrict__ merged,
+                                           const float *__restrict__ pts, const float *__restrict__ nrm, int N,
+                                           const float *__restrict__ poses, const float4 *__restrict__ bounds,
+                                           uint32_t *__restrict__ dom_bits, uint32_t *__restrict__ dom_count, int g)
 {
-    __shared__ float4 cb4[kMaxBins];
-    __shared__ uint32_t lut[6 * kLutRes * kLutRes];
-    __shared__ Affine aff[LAT ? 1 : FM];
-    __shared__ uint32_t cnt[FM][kQueryWaves];
-    const int g = blockIdx.x;
+    float4 *cb4 = L.cb4;
+    uint32_t *lut = L.lut;
+    Affine *aff = L.aff;
+    auto &cnt = L.cnt;
     const float *pose = poses + 12 * (int64_t)g;
-    for (int i = threadIdx.x; i < H.B; i += blockDim.x)
+    for (int i = threadIdx.x; i < H.B; i += kQueryThreads)
         cb4[i] = make_float4(H.bin_c[3 * i], H.bin_c[3 * i + 1], H.bin_c[3 * i + 2], 0.0f);
-    for (int i = threadIdx.x; i < 6 * kLutRes * kLutRes; i += blockDim.x) lut[i] = H.bin_lut[i];
+    for (int i = threadIdx.x; i < 6 * kLutRes * kLutRes; i += kQueryThreads) lut[i] = H.bin_lut[i];
     if (LAT) {
         if (threadIdx.x == 0) aff[0] = lattice_affine(H, pose);
     } else if (threadIdx.x < H.F) {
@@ -309,6 +318,29 @@ k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict_
         for (int w = 0; w < kQueryWaves; ++w) s += cnt[threadIdx.x][w];
         dom_count[(int64_t)g * F + threadIdx.x] = s;
     }
+}
+
+template <int W, int FM, bool LAT>
+__global__ void __launch_bounds__(kQueryThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_query(DevHand H, const uint32_t *__restrict__ merged, const float *__restrict__ pts,
+        const float *__restrict__ nrm, int N, const float *__restrict__ poses, const float4 *__restrict__ bounds,
+        uint32_t *__restrict__ dom_bits, uint32_t *__restrict__ dom_count)
+{
+    __shared__ QueryLds<FM, LAT> L;
+    query_pose<W, FM, LAT>(L, H, merged, pts, nrm, N, poses, bounds, dom_bits, dom_count, blockIdx.x);
+}
+
+// The same over the poses of several chunks (one block per pose).
+template <int W, int FM, bool LAT>
+__global__ void __launch_bounds__(kQueryThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_query_batch(const ChunkDesc *__restrict__ d, const uint16_t *__restrict__ idx, const uint32_t *__restrict__ first,
+              int n)
+{
+    __shared__ QueryLds<FM, LAT> L;
+    const int j = batch_member(first, n, blockIdx.x);
+    const ChunkDesc &c = d[idx[j]];
+    query_pose<W, FM, LAT>(L, c.H, c.merged, c.pts, c.nrm, c.N, c.poses, c.bounds, c.dom_bits, c.dom_count,
+                           (int)(blockIdx.x - first[j]));
 }
 
 // Cone query (Sec. 4.3's theta_hit test): a query (x, -R n) hits finger f if
@@ -497,6 +529,26 @@ extern "C" lg_status lg_query_domains_bounded(const lg_field *field, const float
     if (reinterpret_cast<uintptr_t>(bounds) % 16 != 0) return fail(LG_EINVAL, "chunk bounds must be 16-byte aligned");
     return query_domains(field, pts, nrm, n_points, poses, n_poses, reinterpret_cast<const float4 *>(bounds),
                          dom_bits, dom_count, stream);
+}
+
+lg_status lg::query_batch(const BatchLaunch &b, int W, int F, bool lat, hipStream_t s)
+{
+    if (b.n <= 0 || b.blocks == 0) return LG_OK;
+#define LG_QUERY(W_, FM, LAT)                                                                                \
+    hipLaunchKernelGGL((k_query_batch<W_, FM, LAT>), dim3(b.blocks), dim3(kQueryThreads), 0, s, b.d, b.idx,  \
+                       b.first, b.n)
+#define LG_QUERY_F(W_, LAT)                                                                                  \
+    if (F <= 3) LG_QUERY(W_, 3, LAT); else if (F <= 4) LG_QUERY(W_, 4, LAT);                                 \
+    else if (F <= 5) LG_QUERY(W_, 5, LAT); else LG_QUERY(W_, 8, LAT)
+    if (lat) {
+        if (W == 1) { LG_QUERY_F(1, true); } else { LG_QUERY_F(2, true); }
+    } else {
+        if (W == 1) { LG_QUERY_F(1, false); } else { LG_QUERY_F(2, false); }
+    }
+#undef LG_QUERY_F
+#undef LG_QUERY
+    LG_HIP(hipGetLastError());
+    return LG_OK;
 }
 
 extern "C" lg_status lg_chunk_bounds(const float *pts, int32_t n_points, float *bounds, void *stream)

@@ -17,14 +17,6 @@ namespace lg {
 
 constexpr int kRealizeThreads = 256;
 
-struct IkDev {
-    int iters, phase1;
-    float lambda, beta, tol_pos, tol_ang, margin;
-    int self_collision;
-    uint32_t seed_lo, seed_hi, request_id;
-    int64_t pose_offset;
-};
-
 constexpr uint32_t kPurposeUnused = 15u;
 
 // distance between segments [p1, q1] and [p2, q2]: the closest parameters
@@ -190,19 +182,25 @@ __device__ inline void capsule_project(const float *A, const float *Bp, float r,
         cerr, cang, depth_out, valid_out
 
 // cb: bin centres in LDS; caps: capsule axis end points of every lane's finger
-// at its final configuration (LDS)
+// at its final configuration (LDS); block bid of nb (grid-stride)
 template <int DM>
-__device__ __forceinline__ void realize_sets(float *cb, float (*caps)[DM][6], LG_REALIZE_ARGS)
+__device__ __forceinline__ void realize_sets(
+    float *cb, float (*caps)[DM][6], int64_t bid, int64_t nb, const DevHand &H, const int32_t *__restrict__ wit,
+    const SdfDev &S, const float *__restrict__ pts, const float *__restrict__ nrm, int N,
+    const float *__restrict__ poses, const int32_t *__restrict__ set_pt, const int8_t *__restrict__ set_link, int k,
+    int D, int64_t n_sets, const int32_t *__restrict__ acc_list, const int32_t *__restrict__ n_acc_dev, int max_acc,
+    const IkDev &ik, float *__restrict__ q_out, float *__restrict__ cerr, float *__restrict__ cang,
+    float *__restrict__ depth_out, uint8_t *__restrict__ valid_out)
 {
-    for (int i = threadIdx.x; i < 3 * H.B; i += blockDim.x) cb[i] = H.bin_c[i];
+    for (int i = threadIdx.x; i < 3 * H.B; i += kRealizeThreads) cb[i] = H.bin_c[i];
     __syncthreads();
-    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gt = bid * kRealizeThreads + threadIdx.x;
     const int spw = 64 / H.F;                    // sets per wave
     const int lane = threadIdx.x & 63, slot = lane / H.F;
     const int f = lane - slot * H.F;             // this lane's finger
     const int tid = threadIdx.x, base = tid - f;  // the set's first lane in the block
     const int64_t nacc = min((int64_t)*n_acc_dev, (int64_t)max_acc);
-    const int64_t stride = (((int64_t)gridDim.x * blockDim.x) >> 6) * spw;
+    const int64_t stride = ((nb * kRealizeThreads) >> 6) * spw;
     // grid-stride over accepted sets; the F lanes of a set move together, the
     // lanes past spw * F do nothing
     for (int64_t a = slot < spw ? (gt >> 6) * spw + slot : nacc; a < nacc; a += stride) {
@@ -501,7 +499,7 @@ k_realize(LG_REALIZE_ARGS)
 {
     __shared__ float cb[3 * kMaxBins];
     __shared__ float caps[kRealizeThreads][DM][6];
-    realize_sets<DM>(cb, caps, LG_REALIZE_PASS);
+    realize_sets<DM>(cb, caps, blockIdx.x, gridDim.x, LG_REALIZE_PASS);
 }
 
 // 7 or 8 joints per finger: one wave per SIMD rather than spilling
@@ -509,7 +507,24 @@ __global__ void __launch_bounds__(kRealizeThreads) k_realize_wide(LG_REALIZE_ARG
 {
     __shared__ float cb[3 * kMaxBins];
     __shared__ float caps[kRealizeThreads][8][6];
-    realize_sets<8>(cb, caps, LG_REALIZE_PASS);
+    realize_sets<8>(cb, caps, blockIdx.x, gridDim.x, LG_REALIZE_PASS);
+}
+
+// The same over the accepted sets of several chunks (max_acc = the chunk's
+// P * D); DM = 8 takes one wave per SIMD like k_realize_wide.
+template <int DM>
+__global__ void __launch_bounds__(kRealizeThreads) __attribute__((amdgpu_waves_per_eu(DM <= 6 ? 2 : 1)))
+k_realize_batch(const ChunkDesc *__restrict__ d, const uint16_t *__restrict__ idx, const uint32_t *__restrict__ first,
+                int n)
+{
+    __shared__ float cb[3 * kMaxBins];
+    __shared__ float caps[kRealizeThreads][DM][6];
+    const int j = batch_member(first, n, blockIdx.x);
+    const ChunkDesc &c = d[idx[j]];
+    const int64_t n_sets = (int64_t)c.P * c.D;
+    realize_sets<DM>(cb, caps, blockIdx.x - first[j], first[j + 1] - first[j], c.H, c.wit, c.S, c.pts, c.nrm, c.N,
+                     c.poses, c.set_pt, c.set_link, c.k, c.D, n_sets, c.acc, c.n_acc, (int)n_sets, c.ik, c.q, c.err,
+                     c.ang, c.depth, c.valid);
 }
 
 #undef LG_REALIZE_ARGS
@@ -544,9 +559,7 @@ extern "C" lg_status lg_realize(const lg_field *field, const lg_sdf *sdf, const 
     int dev = 0, n_cu = 0;
     LG_HIP(hipGetDevice(&dev));
     LG_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int64_t spw = 64 / H.F;  // sets per wave
-    const int64_t threads = std::min<int64_t>((max_acc + spw - 1) / spw * 64, (int64_t)n_cu * 16 * kRealizeThreads);
-    const dim3 grid((unsigned)std::max<int64_t>(1, (threads + kRealizeThreads - 1) / kRealizeThreads));
+    const dim3 grid(realize_blocks(max_acc, H.F, n_cu));
     const int32_t *wit = field->has_witness ? field->d_wit : nullptr;
 #define LG_REALIZE(KERNEL)                                                                                      \
     hipLaunchKernelGGL(KERNEL, grid, dim3(kRealizeThreads), 0, s, H, wit, S, pts, nrm, n_points, poses,     \
@@ -560,6 +573,26 @@ extern "C" lg_status lg_realize(const lg_field *field, const lg_sdf *sdf, const 
     else
         LG_REALIZE(k_realize_wide);
 #undef LG_REALIZE
+    LG_HIP(hipGetLastError());
+    return LG_OK;
+}
+
+uint32_t lg::realize_blocks(int64_t max_acc, int F, int n_cu)
+{
+    const int64_t spw = 64 / F;  // sets per wave
+    const int64_t threads = std::min<int64_t>((max_acc + spw - 1) / spw * 64, (int64_t)n_cu * 16 * kRealizeThreads);
+    return (uint32_t)std::max<int64_t>(1, (threads + kRealizeThreads - 1) / kRealizeThreads);
+}
+
+lg_status lg::realize_batch(const BatchLaunch &b, int max_dof, hipStream_t s)
+{
+    if (b.n <= 0 || b.blocks == 0) return LG_OK;
+    if (max_dof <= 4)
+        hipLaunchKernelGGL(k_realize_batch<4>, dim3(b.blocks), dim3(kRealizeThreads), 0, s, b.d, b.idx, b.first, b.n);
+    else if (max_dof <= 6)
+        hipLaunchKernelGGL(k_realize_batch<6>, dim3(b.blocks), dim3(kRealizeThreads), 0, s, b.d, b.idx, b.first, b.n);
+    else
+        hipLaunchKernelGGL(k_realize_batch<8>, dim3(b.blocks), dim3(kRealizeThreads), 0, s, b.d, b.idx, b.first, b.n);
     LG_HIP(hipGetLastError());
     return LG_OK;
 }

@@ -122,18 +122,18 @@ __device__ inline void build_prefix(uint32_t *prefix, const uint32_t *__restrict
 // One workgroup per pose.  Rank structure: exclusive popcount prefix per
 // superblock of 8 domain words, in LDS; a draw binary-searches it and scans
 // at most 8 words.
-__global__ void __launch_bounds__(kDrawThreads)
-k_draw(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ pts, const float *__restrict__ nrm,
-       int N, const float *__restrict__ poses, const uint32_t *__restrict__ dom_bits,
-       const uint32_t *__restrict__ dom_count, const int32_t *__restrict__ palm_pt, int D, int k, uint32_t seed_lo,
-       uint32_t seed_hi, uint32_t request_id, int64_t pose_offset, int32_t *__restrict__ set_pt,
-       int8_t *__restrict__ set_link, uint8_t *__restrict__ pose_valid, uint8_t *__restrict__ verdict,
-       double *__restrict__ tstar)
+// the D sets of pose g (one block); prefix: [F][nsb + 1] words of LDS
+__device__ __forceinline__ void draw_pose(uint32_t *prefix, float *cb, uint32_t *counts, const DevHand &H,
+                                          const uint32_t *__restrict__ bits, const float *__restrict__ pts,
+                                          const float *__restrict__ nrm, int N, const float *__restrict__ poses,
+                                          const uint32_t *__restrict__ dom_bits, const uint32_t *__restrict__ dom_count,
+                                          const int32_t *__restrict__ palm_pt, int D, int k, uint32_t seed_lo,
+                                          uint32_t seed_hi, uint32_t request_id, int64_t pose_offset,
+                                          int32_t *__restrict__ set_pt, int8_t *__restrict__ set_link,
+                                          uint8_t *__restrict__ pose_valid, uint8_t *__restrict__ verdict,
+                                          double *__restrict__ tstar, int g)
 {
-    extern __shared__ uint32_t prefix[];  // [F][nsb + 1]
-    __shared__ float cb[3 * kMaxBins];
-    __shared__ uint32_t counts[kMaxFingers];
-    const int g = blockIdx.x, F = H.F;
+    const int F = H.F;
     const int NW = (N + 31) >> 5, nsb = (NW + kSuper - 1) / kSuper;
     const uint32_t *dom = dom_bits + (int64_t)g * F * NW;
     for (int i = threadIdx.x; i < 3 * H.B; i += blockDim.x) cb[i] = H.bin_c[i];
@@ -177,6 +177,36 @@ k_draw(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ p
     }
 }
 
+__global__ void __launch_bounds__(kDrawThreads)
+k_draw(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ pts, const float *__restrict__ nrm,
+       int N, const float *__restrict__ poses, const uint32_t *__restrict__ dom_bits,
+       const uint32_t *__restrict__ dom_count, const int32_t *__restrict__ palm_pt, int D, int k, uint32_t seed_lo,
+       uint32_t seed_hi, uint32_t request_id, int64_t pose_offset, int32_t *__restrict__ set_pt,
+       int8_t *__restrict__ set_link, uint8_t *__restrict__ pose_valid, uint8_t *__restrict__ verdict,
+       double *__restrict__ tstar)
+{
+    extern __shared__ uint32_t prefix[];
+    __shared__ float cb[3 * kMaxBins];
+    __shared__ uint32_t counts[kMaxFingers];
+    draw_pose(prefix, cb, counts, H, bits, pts, nrm, N, poses, dom_bits, dom_count, palm_pt, D, k, seed_lo, seed_hi,
+              request_id, pose_offset, set_pt, set_link, pose_valid, verdict, tstar, blockIdx.x);
+}
+
+// the same over the poses of several chunks (no palm contacts)
+__global__ void __launch_bounds__(kDrawThreads)
+k_draw_batch(const ChunkDesc *__restrict__ d, const uint16_t *__restrict__ idx, const uint32_t *__restrict__ first,
+             int n)
+{
+    extern __shared__ uint32_t prefix[];
+    __shared__ float cb[3 * kMaxBins];
+    __shared__ uint32_t counts[kMaxFingers];
+    const int j = batch_member(first, n, blockIdx.x);
+    const ChunkDesc &c = d[idx[j]];
+    draw_pose(prefix, cb, counts, c.H, c.bits, c.pts, c.nrm, c.N, c.poses, c.dom_bits, c.dom_count, nullptr, c.D,
+              c.k, c.seed_lo, c.seed_hi, c.request_id, c.pose_offset, c.set_pt, c.set_link, c.pose_valid, c.verdict,
+              c.tstar, (int)(blockIdx.x - first[j]));
+}
+
 // ---- force-closure LP ---------------------------------------------------------
 // Duff et al. (2017) branchless orthonormal basis of unit n.
 __device__ inline void duff_basis(double nx, double ny, double nz, double *x, double *y)
@@ -209,9 +239,7 @@ constexpr int kBlandAfter = 48;   // pivots priced by Dantzig's rule before Blan
 // At a candidate optimum x_B and y are refined twice against the original
 // columns (residual correction through the current B^-1) and the pricing is
 // repeated, so drift in B^-1 cannot end the search early or bias t*.
-struct LpConst {
-    double ce[16], se[16];  // cos, sin of 2 pi e / m
-};
+// (LpConst: the cone edge directions, shared with the batched launch.)
 
 // t* of the set held in this lane's LDS column (cd[6 i + c][tid]); status
 // 0 = optimal, 1 = pivot cap, 2 = unbounded ratio test (not expected).
@@ -495,20 +523,22 @@ __device__ inline double lp_lane(float (&cd)[KM * 6][256], int tid, int k, int m
     return ts;
 }
 
+// block bid of nb blocks (grid-stride); cd: contact data of each lane's set
+// in LDS, lane-contiguous: cd[6*i + c][tid]
 template <int KM>
-__global__ void __launch_bounds__(256)
-k_verdict_lane(const float *__restrict__ pts, const float *__restrict__ nrm, int N, const int32_t *__restrict__ set_pt,
-               const int32_t *__restrict__ palm_pt, const int32_t *__restrict__ valid_poses,
-               const int32_t *__restrict__ n_valid_poses, int D, int k, int m, double mu, double rho, double eps,
-               int max_pivots, LpConst cs, uint8_t *__restrict__ verdict, double *__restrict__ tstar)
+__device__ __forceinline__ void verdict_sets(float (&cd)[KM * 6][256], int64_t bid, int64_t nb,
+                                             const float *__restrict__ pts, const float *__restrict__ nrm, int N,
+                                             const int32_t *__restrict__ set_pt, const int32_t *__restrict__ palm_pt,
+                                             const int32_t *__restrict__ valid_poses,
+                                             const int32_t *__restrict__ n_valid_poses, int D, int k, int m, double mu,
+                                             double rho, double eps, int max_pivots, const LpConst &cs,
+                                             uint8_t *__restrict__ verdict, double *__restrict__ tstar)
 {
-    // contact data of this lane's set in LDS, lane-contiguous: cd[6*i + c][tid]
-    __shared__ float cd[KM * 6][256];
     const int tid = threadIdx.x;
     const int64_t n_work = (int64_t)(*n_valid_poses) * D;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t stride = nb * 256;
     // grid-stride over the sets of poses with at least k non-empty domains
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + tid; t < n_work; t += stride) {
+    for (int64_t t = bid * 256 + tid; t < n_work; t += stride) {
         const int64_t g = valid_poses[t / D];
         const int64_t sid = g * D + (t % D);
         const int32_t *sp = set_pt + sid * k;
@@ -537,6 +567,31 @@ k_verdict_lane(const float *__restrict__ pts, const float *__restrict__ nrm, int
         verdict[sid] = (status == 0 && ts <= eps) ? 1 : 0;
         tstar[sid] = status == 0 ? ts : __builtin_nan("");
     }
+}
+
+template <int KM>
+__global__ void __launch_bounds__(256)
+k_verdict_lane(const float *__restrict__ pts, const float *__restrict__ nrm, int N, const int32_t *__restrict__ set_pt,
+               const int32_t *__restrict__ palm_pt, const int32_t *__restrict__ valid_poses,
+               const int32_t *__restrict__ n_valid_poses, int D, int k, int m, double mu, double rho, double eps,
+               int max_pivots, LpConst cs, uint8_t *__restrict__ verdict, double *__restrict__ tstar)
+{
+    __shared__ float cd[KM * 6][256];
+    verdict_sets<KM>(cd, blockIdx.x, gridDim.x, pts, nrm, N, set_pt, palm_pt, valid_poses, n_valid_poses, D, k, m, mu,
+                     rho, eps, max_pivots, cs, verdict, tstar);
+}
+
+template <int KM>
+__global__ void __launch_bounds__(256)
+k_verdict_batch(const ChunkDesc *__restrict__ d, const uint16_t *__restrict__ idx, const uint32_t *__restrict__ first,
+                int n)
+{
+    __shared__ float cd[KM * 6][256];
+    const int j = batch_member(first, n, blockIdx.x);
+    const ChunkDesc &c = d[idx[j]];
+    verdict_sets<KM>(cd, blockIdx.x - first[j], first[j + 1] - first[j], c.pts, c.nrm, c.N, c.set_pt, nullptr,
+                     c.valid_poses, c.n_valid_poses, c.D, c.k, c.m, c.mu, c.rho, c.eps, c.max_pivots, c.cs, c.verdict,
+                     c.tstar);
 }
 
 // ---- contact-point optimisation (Sec. 5.4, Alg. 2) ---------------------------
@@ -1072,30 +1127,29 @@ __global__ void k_flag_unstable(const int32_t *__restrict__ set_pt, const int8_t
 }
 
 // ---- compaction ------------------------------------------------------------
-__global__ void __launch_bounds__(kCompactThreads)
-k_chunk_count(const uint8_t *__restrict__ verdict, int64_t n, uint32_t *__restrict__ chunk_count)
+// block bid: the number of nonzero flags in its kChunk flags
+__device__ __forceinline__ void chunk_count_block(uint32_t *part, int64_t bid, const uint8_t *__restrict__ flag,
+                                                  int64_t n, uint32_t *__restrict__ chunk_count)
 {
-    __shared__ uint32_t part[kCompactThreads / 64];
-    const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kChunkPerThread;
+    const int64_t base = bid * kChunk + (int64_t)threadIdx.x * kChunkPerThread;
     uint32_t c = 0;
     for (int i = 0; i < kChunkPerThread; ++i)
-        if (base + i < n) c += verdict[base + i] != 0;
+        if (base + i < n) c += flag[base + i] != 0;
     for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t s = 0;
         for (int w = 0; w < kCompactThreads / 64; ++w) s += part[w];
-        chunk_count[blockIdx.x] = s;
+        chunk_count[bid] = s;
     }
 }
 
-// single workgroup: exclusive scan of chunk counts, total into n_acc
-__global__ void __launch_bounds__(kCompactThreads)
-k_chunk_scan(const uint32_t *__restrict__ chunk_count, int64_t n_chunks, uint32_t *__restrict__ chunk_off,
-             int32_t *__restrict__ n_acc)
+// one block: exclusive scan of chunk counts, total into n_acc
+__device__ __forceinline__ void chunk_scan_block(uint32_t *tot, const uint32_t *__restrict__ chunk_count,
+                                                 int64_t n_chunks, uint32_t *__restrict__ chunk_off,
+                                                 int32_t *__restrict__ n_acc)
 {
-    __shared__ uint32_t tot[kCompactThreads];
     const int64_t per = (n_chunks + kCompactThreads - 1) / kCompactThreads;
     const int64_t b0 = threadIdx.x * per;
     uint32_t s = 0;
@@ -1119,15 +1173,15 @@ k_chunk_scan(const uint32_t *__restrict__ chunk_count, int64_t n_chunks, uint32_
     }
 }
 
-__global__ void __launch_bounds__(kCompactThreads)
-k_chunk_scatter(const uint8_t *__restrict__ verdict, int64_t n, const uint32_t *__restrict__ chunk_off,
-                int32_t *__restrict__ acc_list)
+// block bid: the indices of its nonzero flags, in order, from chunk_off[bid]
+__device__ __forceinline__ void chunk_scatter_block(uint32_t *pre, int64_t bid, const uint8_t *__restrict__ flag,
+                                                    int64_t n, const uint32_t *__restrict__ chunk_off,
+                                                    int32_t *__restrict__ list)
 {
-    __shared__ uint32_t pre[kCompactThreads];
-    const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kChunkPerThread;
+    const int64_t base = bid * kChunk + (int64_t)threadIdx.x * kChunkPerThread;
     uint32_t c = 0;
     for (int i = 0; i < kChunkPerThread; ++i)
-        if (base + i < n) c += verdict[base + i] != 0;
+        if (base + i < n) c += flag[base + i] != 0;
     pre[threadIdx.x] = c;
     __syncthreads();
     // Hillis-Steele inclusive scan over the block
@@ -1137,9 +1191,81 @@ k_chunk_scatter(const uint8_t *__restrict__ verdict, int64_t n, const uint32_t *
         pre[threadIdx.x] += v;
         __syncthreads();
     }
-    uint32_t pos = chunk_off[blockIdx.x] + pre[threadIdx.x] - c;
+    uint32_t pos = chunk_off[bid] + pre[threadIdx.x] - c;
     for (int i = 0; i < kChunkPerThread; ++i)
-        if (base + i < n && verdict[base + i]) acc_list[pos++] = (int32_t)(base + i);
+        if (base + i < n && flag[base + i]) list[pos++] = (int32_t)(base + i);
+}
+
+__global__ void __launch_bounds__(kCompactThreads)
+k_chunk_count(const uint8_t *__restrict__ verdict, int64_t n, uint32_t *__restrict__ chunk_count)
+{
+    __shared__ uint32_t part[kCompactThreads / 64];
+    chunk_count_block(part, blockIdx.x, verdict, n, chunk_count);
+}
+
+__global__ void __launch_bounds__(kCompactThreads)
+k_chunk_scan(const uint32_t *__restrict__ chunk_count, int64_t n_chunks, uint32_t *__restrict__ chunk_off,
+             int32_t *__restrict__ n_acc)
+{
+    __shared__ uint32_t tot[kCompactThreads];
+    chunk_scan_block(tot, chunk_count, n_chunks, chunk_off, n_acc);
+}
+
+__global__ void __launch_bounds__(kCompactThreads)
+k_chunk_scatter(const uint8_t *__restrict__ verdict, int64_t n, const uint32_t *__restrict__ chunk_off,
+                int32_t *__restrict__ acc_list)
+{
+    __shared__ uint32_t pre[kCompactThreads];
+    chunk_scatter_block(pre, blockIdx.x, verdict, n, chunk_off, acc_list);
+}
+
+// Batched compaction: POSES = the chunk's poses with a usable draw (the
+// verdict launch's work list), else its accepted sets.
+struct CompactView {
+    const uint8_t *flag;
+    int64_t n;
+    uint32_t *count, *off;
+    int32_t *total, *list;
+};
+
+template <bool POSES>
+__device__ __forceinline__ CompactView compact_view(const ChunkDesc &c)
+{
+    if (POSES) return {c.pose_valid, (int64_t)c.P, c.pchunk_count, c.pchunk_off, c.n_valid_poses, c.valid_poses};
+    return {c.verdict, (int64_t)c.P * c.D, c.chunk_count, c.chunk_off, c.n_acc, c.acc};
+}
+
+template <bool POSES>
+__global__ void __launch_bounds__(kCompactThreads)
+k_count_batch(const ChunkDesc *__restrict__ d, const uint16_t *__restrict__ idx, const uint32_t *__restrict__ first,
+              int n)
+{
+    __shared__ uint32_t part[kCompactThreads / 64];
+    const int j = batch_member(first, n, blockIdx.x);
+    const CompactView v = compact_view<POSES>(d[idx[j]]);
+    chunk_count_block(part, blockIdx.x - first[j], v.flag, v.n, v.count);
+}
+
+template <bool POSES>
+__global__ void __launch_bounds__(kCompactThreads)
+k_scan_batch(const ChunkDesc *__restrict__ d, const uint16_t *__restrict__ idx, const uint32_t *__restrict__ first,
+             int n)
+{
+    __shared__ uint32_t tot[kCompactThreads];
+    const int j = batch_member(first, n, blockIdx.x);
+    const CompactView v = compact_view<POSES>(d[idx[j]]);
+    chunk_scan_block(tot, v.count, (v.n + kChunk - 1) / kChunk, v.off, v.total);
+}
+
+template <bool POSES>
+__global__ void __launch_bounds__(kCompactThreads)
+k_scatter_batch(const ChunkDesc *__restrict__ d, const uint16_t *__restrict__ idx, const uint32_t *__restrict__ first,
+                int n)
+{
+    __shared__ uint32_t pre[kCompactThreads];
+    const int j = batch_member(first, n, blockIdx.x);
+    const CompactView v = compact_view<POSES>(d[idx[j]]);
+    chunk_scatter_block(pre, blockIdx.x - first[j], v.flag, v.n, v.off, v.list);
 }
 
 }  // namespace lg
@@ -1210,6 +1336,34 @@ size_t lg_search_workspace_bytes(int32_t n_points, int32_t n_poses, const lg_sea
 
 }  // extern "C"
 
+LpConst lg::lp_const(int m)
+{
+    LpConst cs;
+    for (int e = 0; e < 16; ++e) {
+        const double th = 2.0 * M_PI * e / m;
+        cs.ce[e] = e < m ? cos(th) : 0.0;
+        cs.se[e] = e < m ? sin(th) : 0.0;
+    }
+    return cs;
+}
+
+uint32_t lg::verdict_blocks(int64_t n_sets, int n_cu)
+{
+    return (uint32_t)std::max<int64_t>(1, std::min<int64_t>((n_sets + 255) / 256, (int64_t)n_cu * 8));
+}
+
+void lg::chunk_workspace(void *ws, int64_t n_points, int64_t n_poses, int64_t draws, ChunkDesc &c)
+{
+    const SearchWs w = search_ws(ws, n_points, n_poses, draws, false);
+    c.pose_valid = w.pose_valid;
+    c.pchunk_count = w.pchunk_count;
+    c.pchunk_off = w.pchunk_off;
+    c.valid_poses = w.valid_poses;
+    c.n_valid_poses = w.n_valid_poses;
+    c.chunk_count = w.chunk_count;
+    c.chunk_off = w.chunk_off;
+}
+
 // the whole search on a given workspace (the caller's, or the static scratch
 // array of lg_search_noalloc); allocates nothing
 static lg_status search_impl(const lg_field *field, const float *pts, const float *nrm, int32_t n_points,
@@ -1257,17 +1411,12 @@ static lg_status search_impl(const lg_field *field, const float *pts, const floa
                        (int64_t)n_poses, ws.pchunk_off, ws.valid_poses);
     LG_HIP(hipGetLastError());
     const int64_t n_sets = (int64_t)n_poses * p->draws;
-    LpConst cs;
-    for (int e = 0; e < 16; ++e) {
-        const double th = 2.0 * M_PI * e / p->m_edges;
-        cs.ce[e] = e < p->m_edges ? cos(th) : 0.0;
-        cs.se[e] = e < p->m_edges ? sin(th) : 0.0;
-    }
+    const LpConst cs = lp_const(p->m_edges);
     // grid-stride LP launch sized to the device (the valid count is on the device)
     int dev = 0, n_cu = 0;
     LG_HIP(hipGetDevice(&dev));
     LG_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    const dim3 lgrid((unsigned)std::max<int64_t>(1, std::min<int64_t>((n_sets + 255) / 256, (int64_t)n_cu * 8)));
+    const dim3 lgrid(verdict_blocks(n_sets, n_cu));
 #define LG_VERDICT(KM)                                                                                          \
     hipLaunchKernelGGL(k_verdict_lane<KM>, lgrid, dim3(256), 0, s, pts, nrm, n_points, set_pt, palm,             \
                        ws.valid_poses,                                                                          \
@@ -1507,3 +1656,67 @@ lg_status lg_search_noalloc(const lg_field *field, const float *pts, const float
 }
 
 }  // extern "C"
+
+// ---- batched launches over the chunks of several requests -------------------
+size_t lg::draw_lds_bytes(int F, int N)
+{
+    const int NW = (N + 31) / 32, nsb = (NW + kSuper - 1) / kSuper;
+    return (size_t)F * (nsb + 1) * sizeof(uint32_t);
+}
+
+uint32_t lg::compact_blocks(int64_t n) { return (uint32_t)((n + kChunk - 1) / kChunk); }
+
+lg_status lg::draw_batch(const BatchLaunch &b, size_t lds, hipStream_t s)
+{
+    if (b.n <= 0 || b.blocks == 0) return LG_OK;
+    if (lds > 48 * 1024) return fail(LG_EUNSUPPORTED, "too many points for the draw rank structure");
+    hipLaunchKernelGGL(k_draw_batch, dim3(b.blocks), dim3(kDrawThreads), lds, s, b.d, b.idx, b.first, b.n);
+    LG_HIP(hipGetLastError());
+    return LG_OK;
+}
+
+lg_status lg::compact_count_batch(const BatchLaunch &b, bool poses, hipStream_t s)
+{
+    if (b.n <= 0 || b.blocks == 0) return LG_OK;
+    if (poses)
+        hipLaunchKernelGGL(k_count_batch<true>, dim3(b.blocks), dim3(kCompactThreads), 0, s, b.d, b.idx, b.first, b.n);
+    else
+        hipLaunchKernelGGL(k_count_batch<false>, dim3(b.blocks), dim3(kCompactThreads), 0, s, b.d, b.idx, b.first, b.n);
+    LG_HIP(hipGetLastError());
+    return LG_OK;
+}
+
+lg_status lg::compact_scan_batch(const BatchLaunch &b, bool poses, hipStream_t s)
+{
+    if (b.n <= 0 || b.blocks == 0) return LG_OK;
+    if (poses)
+        hipLaunchKernelGGL(k_scan_batch<true>, dim3(b.blocks), dim3(kCompactThreads), 0, s, b.d, b.idx, b.first, b.n);
+    else
+        hipLaunchKernelGGL(k_scan_batch<false>, dim3(b.blocks), dim3(kCompactThreads), 0, s, b.d, b.idx, b.first, b.n);
+    LG_HIP(hipGetLastError());
+    return LG_OK;
+}
+
+lg_status lg::compact_scatter_batch(const BatchLaunch &b, bool poses, hipStream_t s)
+{
+    if (b.n <= 0 || b.blocks == 0) return LG_OK;
+    if (poses)
+        hipLaunchKernelGGL(k_scatter_batch<true>, dim3(b.blocks), dim3(kCompactThreads), 0, s, b.d, b.idx, b.first,
+                           b.n);
+    else
+        hipLaunchKernelGGL(k_scatter_batch<false>, dim3(b.blocks), dim3(kCompactThreads), 0, s, b.d, b.idx, b.first,
+                           b.n);
+    LG_HIP(hipGetLastError());
+    return LG_OK;
+}
+
+lg_status lg::verdict_batch(const BatchLaunch &b, int km, hipStream_t s)
+{
+    if (b.n <= 0 || b.blocks == 0) return LG_OK;
+#define LG_VB(KM) hipLaunchKernelGGL(k_verdict_batch<KM>, dim3(b.blocks), dim3(256), 0, s, b.d, b.idx, b.first, b.n)
+    if (km <= 3) LG_VB(3); else if (km <= 4) LG_VB(4); else if (km <= 5) LG_VB(5); else if (km <= 6) LG_VB(6);
+    else LG_VB(8);
+#undef LG_VB
+    LG_HIP(hipGetLastError());
+    return LG_OK;
+}

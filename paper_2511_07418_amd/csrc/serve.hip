@@ -6,11 +6,15 @@
 //  * admission: one device slab of `budget_bytes` is sub-allocated first-fit;
 //    a request is admitted (FIFO) when its inputs and one chunk of working
 //    buffers fit, and its block is returned when it completes;
-//  * interleaving: every admitted request owns a stream (default priority);
-//    the server thread enqueues one chunk of `chunk_poses` poses per request
-//    at a time (query -> draws/verdicts/compaction -> optional IK +
-//    penetration -> counters), so chunks of different requests overlap on the
-//    device and a long request never blocks a short one behind it;
+//  * interleaving: the server thread runs one chunk of `chunk_poses` poses
+//    per request at a time (query -> draws/verdicts/compaction -> optional
+//    IK + penetration -> counters), so a long request never blocks a short
+//    one behind it.  Per-stream mode: every admitted request owns a stream
+//    (default priority) and its chunk launches its own kernels.  Batched
+//    mode: the next chunks of all idle requests are written into a
+//    descriptor table (one ChunkDesc each) and run as one launch per stage,
+//    each chunk owning the blocks its size needs; two batches can be in
+//    flight, on two streams, so a batch is assembled while the other runs;
 //  * determinism: RNG counters depend on (request_id, pose index within the
 //    request, draw) only, so results are identical alone and in any mix.
 #include <math.h>
@@ -34,7 +38,7 @@ namespace lg {
 
 constexpr uint64_t kAlign = 256;
 
-static uint64_t align_up(uint64_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+static constexpr uint64_t align_up(uint64_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 // splitmix64 finaliser (Steele, Lea, Flood 2014) of (request, set id)
 __device__ inline uint64_t mix64(uint64_t z)
@@ -45,14 +49,18 @@ __device__ inline uint64_t mix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
-// counters[0] += n_acc, counters[1] += valid, counters[2] += sum of mix64(id)
-__global__ void k_serve_accumulate(const int32_t *__restrict__ acc_list, const int32_t *__restrict__ n_acc_dev,
-                                   const uint8_t *__restrict__ valid, int64_t set_base, uint32_t request_id,
-                                   unsigned long long *__restrict__ counters)
+constexpr int kAccThreads = 256;
+
+// counters[0] += n_acc, counters[1] += valid, counters[2] += sum of mix64(id);
+// block bid of nb (grid-stride)
+__device__ __forceinline__ void accumulate_block(int bid, int nb, const int32_t *__restrict__ acc_list,
+                                                 const int32_t *__restrict__ n_acc_dev,
+                                                 const uint8_t *__restrict__ valid, int64_t set_base,
+                                                 uint32_t request_id, unsigned long long *__restrict__ counters)
 {
     const int n = *n_acc_dev;
     unsigned long long c = 0, v = 0, h = 0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    for (int i = bid * kAccThreads + threadIdx.x; i < n; i += nb * kAccThreads) {
         const uint64_t id = (uint64_t)(set_base + acc_list[i]);
         c += 1;
         v += valid ? (valid[i] != 0) : 1;
@@ -68,6 +76,24 @@ __global__ void k_serve_accumulate(const int32_t *__restrict__ acc_list, const i
         atomicAdd(counters + 1, v);
         atomicAdd(counters + 2, h);
     }
+}
+
+__global__ void __launch_bounds__(kAccThreads)
+k_serve_accumulate(const int32_t *__restrict__ acc_list, const int32_t *__restrict__ n_acc_dev,
+                   const uint8_t *__restrict__ valid, int64_t set_base, uint32_t request_id,
+                   unsigned long long *__restrict__ counters)
+{
+    accumulate_block(blockIdx.x, gridDim.x, acc_list, n_acc_dev, valid, set_base, request_id, counters);
+}
+
+__global__ void __launch_bounds__(kAccThreads)
+k_accumulate_batch(const ChunkDesc *__restrict__ d, const uint16_t *__restrict__ idx,
+                   const uint32_t *__restrict__ first, int n)
+{
+    const int j = batch_member(first, n, blockIdx.x);
+    const ChunkDesc &c = d[idx[j]];
+    accumulate_block(blockIdx.x - first[j], first[j + 1] - first[j], c.acc, c.n_acc, c.realize ? c.valid : nullptr,
+                     c.pose_offset * c.D, c.request_id, c.counters);
 }
 
 // First-fit sub-allocator over one device slab (host-side bookkeeping only).
@@ -179,10 +205,30 @@ struct Req {
     int32_t state = LG_REQ_QUEUED;
     int32_t status = LG_OK;
     bool cancel = false, in_flight = false;
+    bool batched = false;  // chunks go through the batched launches
+    bool fresh = false;    // admission copies not yet waited for by a batch
     int64_t next_pose = 0;
     double t_submit = 0, t_admit = 0, t_done = 0;
     unsigned long long counters[3] = {0, 0, 0};
     hipEvent_t ev = nullptr;
+};
+
+// Batched launches: one descriptor table per batch slot, staged in pinned
+// host memory and copied to the device ahead of the batch's kernels.  A table
+// holds kMaxBatch chunk descriptors and up to kMaxLaunch member lists.
+constexpr int kMaxBatch = 64;
+constexpr int kMaxLaunch = 48;
+constexpr int kBatchSlots = 2;
+constexpr size_t kListBytes = align_up(2 * kMaxBatch) + align_up(4 * (kMaxBatch + 1));
+constexpr size_t kTableBytes = align_up(sizeof(ChunkDesc) * kMaxBatch) + kMaxLaunch * kListBytes;
+
+struct BatchSlot {
+    hipStream_t s = nullptr;
+    hipEvent_t ev = nullptr;
+    char *dev = nullptr;   // device table
+    char *host = nullptr;  // pinned staging copy
+    std::vector<Req *> members;
+    bool busy = false;
 };
 
 }  // namespace lg
@@ -194,6 +240,8 @@ struct lg_server {
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
     std::vector<int> free_slots;
+    lg::BatchSlot batch[lg::kBatchSlots];
+    int n_cu = 0;
     std::mutex mu;
     std::condition_variable cv;
     std::thread worker;
@@ -225,8 +273,18 @@ static lg_status validate_request(const lg_server_params &sp, const lg_request *
         return fail(LG_EINVAL, "bad search parameters");
     if ((int64_t)std::min<int64_t>(sp.chunk_poses, r->n_poses) * r->search.draws > 0x7fffffffLL)
         return fail(LG_EINVAL, "chunk_poses * draws must be < 2^31");
-    if (r->realize && (!r->sdf_values || r->sdf_dims < 2 || !(r->sdf_h > 0.f) || !(r->ik.lambda > 0.f)))
+    if (r->realize && (!r->sdf_values || r->sdf_dims < 2 || !(r->sdf_h > 0.f) || !(r->ik.lambda > 0.f) ||
+                       r->ik.iters < 0 || r->ik.phase1 < 0))
         return fail(LG_EINVAL, "realize needs an SDF and IK parameters");
+    // what the search and the query refuse at launch is refused here, in either mode
+    const lg_search_params &p = r->search;
+    if (p.k > 8 || !(p.mu >= 0.0f) || !(p.moment_scale > 0.0f) || p.max_pivots < 0)
+        return fail(LG_EINVAL, "need k <= 8, mu >= 0, moment_scale > 0, max_pivots >= 0");
+    if (p.opt_outer < 0 || p.opt_outer > 64 || (p.opt_outer > 0 && (p.opt_inner < 1 || p.opt_inner > 16)) ||
+        !(p.opt_sigma >= 0.0f) || (int64_t)p.opt_outer * p.k * p.opt_inner >= (1 << 24))
+        return fail(LG_EINVAL, "need 0 <= opt_outer <= 64, 1 <= opt_inner <= 16, opt_sigma >= 0");
+    if ((int64_t)r->n_points * 12 > 0xffffffffLL || draw_lds_bytes(r->field->dh.F, r->n_points) > 48 * 1024)
+        return fail(LG_EUNSUPPORTED, "too many points for the query offsets or the draw rank structure");
     return LG_OK;
 }
 
@@ -285,6 +343,212 @@ static lg_status launch_chunk(lg_server *S, Req *q)
     return LG_OK;
 }
 
+// ---- batched launches ----------------------------------------------------------
+// The next chunk of each member goes through one launch per stage; members
+// are grouped by the template bucket of the kernels that have one.
+static int fm_bucket(int F) { return F <= 3 ? 3 : F <= 4 ? 4 : F <= 5 ? 5 : 8; }
+static int km_bucket(int k) { return k <= 3 ? 3 : k <= 4 ? 4 : k <= 5 ? 5 : k <= 6 ? 6 : 8; }
+static int dm_bucket(int d) { return d <= 4 ? 4 : d <= 6 ? 6 : 8; }
+
+// host view of a slot's table while it is filled
+struct TableWriter {
+    char *host, *dev;
+    int n_lists = 0;
+    static constexpr size_t kListBase = align_up(sizeof(ChunkDesc) * kMaxBatch);
+    ChunkDesc *descs() { return reinterpret_cast<ChunkDesc *>(host); }
+    // member list `who` (table entries) owning nb[j] blocks each
+    lg_status list(const std::vector<int> &who, const std::vector<uint32_t> &nb, BatchLaunch &out)
+    {
+        if (n_lists >= kMaxLaunch) return fail(LG_EINVAL, "batch needs more member lists than its table holds");
+        const size_t off = kListBase + (size_t)n_lists * kListBytes, foff = off + align_up(2 * kMaxBatch);
+        uint16_t *idx = reinterpret_cast<uint16_t *>(host + off);
+        uint32_t *first = reinterpret_cast<uint32_t *>(host + foff);
+        uint64_t t = 0;
+        first[0] = 0;
+        for (size_t j = 0; j < who.size(); ++j) {
+            idx[j] = (uint16_t)who[j];
+            t += nb[j];
+            first[j + 1] = (uint32_t)t;
+        }
+        if (t > 0x7fffffffull) return fail(LG_EINVAL, "batched launch above 2^31 - 1 blocks");
+        out.d = reinterpret_cast<const ChunkDesc *>(dev);
+        out.idx = reinterpret_cast<const uint16_t *>(dev + off);
+        out.first = reinterpret_cast<const uint32_t *>(dev + foff);
+        out.n = (int)who.size();
+        out.blocks = (uint32_t)t;
+        ++n_lists;
+        return LG_OK;
+    }
+};
+
+// every argument of request q's next chunk of P poses
+static void fill_desc(const lg_server *S, const Req *q, int32_t P, ChunkDesc &c)
+{
+    const lg_request &r = q->r;
+    const lg_field *f = r.field;
+    char *base = S->slab.base + q->off;
+    const ReqLayout &L = q->L;
+    const int64_t g0 = q->next_pose;
+    memset(&c, 0, sizeof c);
+    c.H = f->dh;
+    c.merged = f->d_merged;
+    c.bits = f->d_bits;
+    c.wit = f->has_witness ? f->d_wit : nullptr;
+    c.pts = reinterpret_cast<const float *>(base + L.pts);
+    c.nrm = reinterpret_cast<const float *>(base + L.nrm);
+    c.poses = reinterpret_cast<const float *>(base + L.poses) + 12 * g0;
+    c.bounds = reinterpret_cast<const float4 *>(base + L.bounds);
+    c.N = r.n_points;
+    c.P = P;
+    c.D = r.search.draws;
+    c.k = r.search.k;
+    c.m = r.search.m_edges;
+    c.max_pivots = r.search.max_pivots;
+    c.seed_lo = (uint32_t)r.search.seed;
+    c.seed_hi = (uint32_t)(r.search.seed >> 32);
+    c.request_id = r.request_id;
+    c.pose_offset = g0;
+    c.mu = (double)r.search.mu;
+    c.rho = (double)r.search.moment_scale;
+    c.eps = (double)r.search.eps;
+    c.cs = lp_const(c.m);
+    c.dom_bits = reinterpret_cast<uint32_t *>(base + L.dom_bits);
+    c.dom_count = reinterpret_cast<uint32_t *>(base + L.dom_count);
+    c.set_pt = reinterpret_cast<int32_t *>(base + L.set_pt);
+    c.set_link = reinterpret_cast<int8_t *>(base + L.set_link);
+    c.verdict = reinterpret_cast<uint8_t *>(base + L.verdict);
+    c.tstar = reinterpret_cast<double *>(base + L.tstar);
+    c.acc = reinterpret_cast<int32_t *>(base + L.acc);
+    c.n_acc = reinterpret_cast<int32_t *>(base + L.n_acc);
+    chunk_workspace(base + L.ws, r.n_points, P, r.search.draws, c);
+    c.realize = r.realize ? 1 : 0;
+    if (r.realize) {
+        c.S = SdfDev{r.sdf_origin[0], r.sdf_origin[1], r.sdf_origin[2], r.sdf_h, 1.0f / r.sdf_h, r.sdf_dims,
+                     reinterpret_cast<const float *>(base + L.sdf)};
+        const lg_ik_params &p = r.ik;  // random joints of fingers without contact: keyed like the search
+        c.ik = IkDev{p.iters, p.phase1, p.lambda, p.beta, p.tol_pos, p.tol_ang, p.margin, p.self_collision,
+                     c.seed_lo, c.seed_hi, r.request_id, g0};
+        c.q = reinterpret_cast<float *>(base + L.q);
+        c.err = reinterpret_cast<float *>(base + L.err);
+        c.ang = reinterpret_cast<float *>(base + L.ang);
+        c.depth = reinterpret_cast<float *>(base + L.depth);
+        c.valid = reinterpret_cast<uint8_t *>(base + L.valid);
+    }
+    c.counters = reinterpret_cast<unsigned long long *>(base + L.counters);
+}
+
+// members with the same bucket value, in member order
+template <class Key>
+static std::vector<std::vector<int>> buckets(const std::vector<int> &who, Key key)
+{
+    std::vector<std::vector<int>> out;
+    std::vector<int> keys;
+    for (int m : who) {
+        const int kv = key(m);
+        size_t b = std::find(keys.begin(), keys.end(), kv) - keys.begin();
+        if (b == keys.size()) {
+            keys.push_back(kv);
+            out.emplace_back();
+        }
+        out[b].push_back(m);
+    }
+    return out;
+}
+
+// Fill slot B's table with the next chunk of each member and enqueue the
+// batch (server lock held).  Members are marked in flight even when a launch
+// fails part-way: the slot's event still ends what was enqueued.
+static lg_status launch_batch(lg_server *S, BatchSlot &B)
+{
+    const int n = (int)B.members.size();
+    TableWriter T{B.host, B.dev};
+    ChunkDesc *cd = T.descs();
+    std::vector<int> all(n);
+    for (int j = 0; j < n; ++j) {
+        Req *q = B.members[j];
+        const int32_t P = (int32_t)std::min<int64_t>(S->p.chunk_poses, q->r.n_poses - q->next_pose);
+        fill_desc(S, q, P, cd[j]);
+        all[j] = j;
+        if (q->fresh) {  // the admission copies ran on the request's own stream
+            LG_HIP(hipStreamWaitEvent(B.s, q->ev, 0));
+            q->fresh = false;
+        }
+        q->next_pose += P;
+        q->in_flight = true;
+    }
+    auto blocks = [&](const std::vector<int> &who, auto per) {
+        std::vector<uint32_t> nb;
+        for (int m : who) nb.push_back((uint32_t)per(cd[m]));
+        return nb;
+    };
+    // member lists of every stage, then one copy of the table
+    struct Keyed {
+        BatchLaunch b;
+        int rep;  // a member: its field and parameters give the bucket
+    };
+    std::vector<Keyed> lq, lv, lr;
+    BatchLaunch ld, pc, ps, sc, ss, la;
+    lg_status st;
+    auto one = [](const ChunkDesc &) { return 1u; };
+    auto poses = [](const ChunkDesc &c) { return (uint32_t)c.P; };
+    auto pose_chunks = [](const ChunkDesc &c) { return compact_blocks(c.P); };
+    auto set_chunks = [](const ChunkDesc &c) { return compact_blocks((int64_t)c.P * c.D); };
+    const int ncu = S->n_cu;
+    auto lp_blocks = [ncu](const ChunkDesc &c) { return verdict_blocks((int64_t)c.P * c.D, ncu); };
+    auto ik_blocks = [ncu](const ChunkDesc &c) { return realize_blocks((int64_t)c.P * c.D, c.H.F, ncu); };
+    auto acc_blocks = [](const ChunkDesc &c) {
+        return (uint32_t)std::max<int64_t>(1, std::min<int64_t>(64, ((int64_t)c.P * c.D + 4095) / 4096));
+    };
+    for (auto &g : buckets(all, [&](int m) { return (cd[m].H.W << 16) | (fm_bucket(cd[m].H.F) << 1) | cd[m].H.lat; })) {
+        lq.push_back({BatchLaunch{}, g[0]});
+        if ((st = T.list(g, blocks(g, poses), lq.back().b)) != LG_OK) return st;
+    }
+    if ((st = T.list(all, blocks(all, poses), ld)) != LG_OK) return st;
+    if ((st = T.list(all, blocks(all, pose_chunks), pc)) != LG_OK) return st;
+    if ((st = T.list(all, blocks(all, one), ps)) != LG_OK) return st;
+    for (auto &g : buckets(all, [&](int m) { return km_bucket(cd[m].k); })) {
+        lv.push_back({BatchLaunch{}, g[0]});
+        if ((st = T.list(g, blocks(g, lp_blocks), lv.back().b)) != LG_OK) return st;
+    }
+    if ((st = T.list(all, blocks(all, set_chunks), sc)) != LG_OK) return st;
+    if ((st = T.list(all, blocks(all, one), ss)) != LG_OK) return st;
+    std::vector<int> rz;
+    for (int m : all)
+        if (cd[m].realize) rz.push_back(m);
+    auto max_dof = [&](int m) { return B.members[m]->r.field->max_dof; };
+    for (auto &g : buckets(rz, [&](int m) { return dm_bucket(max_dof(m)); })) {
+        lr.push_back({BatchLaunch{}, g[0]});
+        if ((st = T.list(g, blocks(g, ik_blocks), lr.back().b)) != LG_OK) return st;
+    }
+    if ((st = T.list(all, blocks(all, acc_blocks), la)) != LG_OK) return st;
+    size_t lds = 0;
+    for (int m : all) lds = std::max(lds, draw_lds_bytes(cd[m].H.F, cd[m].N));
+    LG_HIP(hipMemcpyAsync(B.dev, B.host, sizeof(ChunkDesc) * n, hipMemcpyHostToDevice, B.s));
+    LG_HIP(hipMemcpyAsync(B.dev + TableWriter::kListBase, B.host + TableWriter::kListBase,
+                          (size_t)T.n_lists * kListBytes, hipMemcpyHostToDevice, B.s));
+    // the stages, in the order of the single-chunk path
+    for (const Keyed &g : lq) {
+        const DevHand &H = cd[g.rep].H;
+        if ((st = query_batch(g.b, H.W, H.F, H.lat != 0, B.s)) != LG_OK) return st;
+    }
+    if ((st = draw_batch(ld, lds, B.s)) != LG_OK) return st;
+    if ((st = compact_count_batch(pc, true, B.s)) != LG_OK) return st;
+    if ((st = compact_scan_batch(ps, true, B.s)) != LG_OK) return st;
+    if ((st = compact_scatter_batch(pc, true, B.s)) != LG_OK) return st;
+    for (const Keyed &g : lv)
+        if ((st = verdict_batch(g.b, cd[g.rep].k, B.s)) != LG_OK) return st;
+    if ((st = compact_count_batch(sc, false, B.s)) != LG_OK) return st;
+    if ((st = compact_scan_batch(ss, false, B.s)) != LG_OK) return st;
+    if ((st = compact_scatter_batch(sc, false, B.s)) != LG_OK) return st;
+    for (const Keyed &g : lr)
+        if ((st = realize_batch(g.b, max_dof(g.rep), B.s)) != LG_OK) return st;
+    if (la.blocks) {
+        hipLaunchKernelGGL(k_accumulate_batch, dim3(la.blocks), dim3(kAccThreads), 0, B.s, la.d, la.idx, la.first, la.n);
+        LG_HIP(hipGetLastError());
+    }
+    return LG_OK;
+}
+
 static void finish(lg_server *S, Req *q, int32_t state)
 {
     if (q->slot >= 0) {
@@ -300,6 +564,11 @@ static void finish(lg_server *S, Req *q, int32_t state)
         S->free_slots.push_back(q->slot);
         q->slot = -1;
     }
+    // the host copies are no longer read (the stream above has drained)
+    std::vector<float>().swap(q->pts);
+    std::vector<float>().swap(q->nrm);
+    std::vector<float>().swap(q->poses);
+    std::vector<float>().swap(q->sdf);
     q->state = state;
     q->t_done = S->now();
     if (state == LG_REQ_DONE) ++S->st.completed;
@@ -322,7 +591,29 @@ static lg_status admit(lg_server *S, Req *q)
     if (q->r.realize)
         LG_HIP(hipMemcpyAsync(base + L.sdf, q->sdf.data(), 4 * q->sdf.size(), hipMemcpyHostToDevice, s));
     LG_HIP(hipMemsetAsync(base + L.counters, 0, 24, s));
+    if (q->batched) {  // the first batch with this request waits for these copies
+        LG_HIP(hipEventRecord(q->ev, s));
+        q->fresh = true;
+    }
     return LG_OK;
+}
+
+// free the server's device resources (streams, events, tables, slab)
+static void release(lg_server *S)
+{
+    for (auto s : S->streams) (void)hipStreamDestroy(s);
+    for (auto e : S->events) (void)hipEventDestroy(e);
+    S->streams.clear();
+    S->events.clear();
+    for (BatchSlot &B : S->batch) {
+        if (B.s) (void)hipStreamDestroy(B.s);
+        if (B.ev) (void)hipEventDestroy(B.ev);
+        if (B.dev) (void)hipFree(B.dev);
+        if (B.host) (void)hipHostFree(B.host);
+        B = BatchSlot{};
+    }
+    if (S->slab.base) (void)hipFree(S->slab.base);
+    S->slab.base = nullptr;
 }
 
 static void worker_loop(lg_server *S)
@@ -331,10 +622,18 @@ static void worker_loop(lg_server *S)
     std::unique_lock<std::mutex> lk(S->mu);
     while (true) {
         bool progressed = false;
-        // completions
+        // completions: batches, then requests
+        for (BatchSlot &B : S->batch) {
+            if (B.busy && hipEventQuery(B.ev) == hipSuccess) {
+                for (Req *q : B.members) q->in_flight = false;
+                B.members.clear();
+                B.busy = false;
+                progressed = true;
+            }
+        }
         for (size_t i = 0; i < S->active.size();) {
             Req *q = S->active[i];
-            if (q->in_flight && hipEventQuery(q->ev) == hipSuccess) {
+            if (q->in_flight && !q->batched && hipEventQuery(q->ev) == hipSuccess) {
                 q->in_flight = false;
                 progressed = true;
             }
@@ -359,6 +658,7 @@ static void worker_loop(lg_server *S)
             q->slot = S->free_slots.back();
             S->free_slots.pop_back();
             q->ev = S->events[q->slot];
+            q->batched = S->p.batched && q->r.search.opt_outer == 0;
             q->state = LG_REQ_RUNNING;
             q->t_admit = S->now();
             lg_status st = admit(S, q);
@@ -370,11 +670,31 @@ static void worker_loop(lg_server *S)
             S->st.peak_bytes = std::max<uint64_t>(S->st.peak_bytes, S->slab.used());
             progressed = true;
         }
-        // one chunk per idle active request, round-robin by admission order
+        // one chunk per idle active request, round-robin by admission order:
+        // on the request's own stream, or in one batch of all idle batched
+        // requests when a batch slot is free
+        BatchSlot *free_batch = nullptr;
+        for (BatchSlot &B : S->batch)
+            if (!B.busy && !free_batch) free_batch = &B;
         for (Req *q : S->active) {
             if (q->in_flight || q->cancel || q->status != LG_OK || q->next_pose >= q->r.n_poses) continue;
+            if (q->batched) {
+                if (free_batch && (int)free_batch->members.size() < kMaxBatch) free_batch->members.push_back(q);
+                continue;
+            }
             lg_status st = launch_chunk(S, q);
             if (st != LG_OK) q->status = st;
+            progressed = true;
+        }
+        if (free_batch && !free_batch->members.empty()) {
+            const lg_status st = launch_batch(S, *free_batch);
+            if (st != LG_OK)
+                for (Req *q : free_batch->members) q->status = st;
+            // the event ends whatever was enqueued, also after a failure
+            if (hipEventRecord(free_batch->ev, free_batch->s) != hipSuccess) (void)hipStreamSynchronize(free_batch->s);
+            free_batch->busy = true;
+            ++S->st.batches;
+            S->st.batched_chunks += (int64_t)free_batch->members.size();
             progressed = true;
         }
         S->st.bytes_in_use = S->slab.used();
@@ -403,25 +723,44 @@ uint64_t lg_serve_request_bytes(const lg_server_params *params, const lg_request
 lg_status lg_serve_create(const lg_server_params *params, lg_server **out)
 {
     if (!params || !out) return fail(LG_EINVAL, "null params or out");
-    if (params->max_active < 1 || params->max_active > 64 || params->chunk_poses < 1 || params->budget_bytes < kAlign)
+    if (params->max_active < 1 || params->max_active > kMaxBatch || params->chunk_poses < 1 ||
+        params->budget_bytes < kAlign)
         return fail(LG_EINVAL, "need 1 <= max_active <= 64, chunk_poses >= 1, budget >= 256 B");
     auto S = std::make_unique<lg_server>();
     S->p = *params;
     S->t0 = std::chrono::steady_clock::now();
-    LG_HIP(hipGetDevice(&S->device));
-    void *slab = nullptr;
-    LG_HIP(hipMalloc(&slab, params->budget_bytes));
-    S->slab.base = static_cast<char *>(slab);
-    S->slab.reset(params->budget_bytes);
-    S->st.budget_bytes = params->budget_bytes;
-    for (int i = 0; i < params->max_active; ++i) {
-        hipStream_t s;
-        hipEvent_t e;
-        LG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-        LG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        S->streams.push_back(s);
-        S->events.push_back(e);
-        S->free_slots.push_back(params->max_active - 1 - i);
+    // device resources; what was made before a failure is freed again
+    auto init = [&]() -> lg_status {
+        LG_HIP(hipGetDevice(&S->device));
+        void *slab = nullptr;
+        LG_HIP(hipMalloc(&slab, params->budget_bytes));
+        S->slab.base = static_cast<char *>(slab);
+        S->slab.reset(params->budget_bytes);
+        S->st.budget_bytes = params->budget_bytes;
+        for (int i = 0; i < params->max_active; ++i) {
+            hipStream_t s;
+            hipEvent_t e;
+            LG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            S->streams.push_back(s);
+            LG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            S->events.push_back(e);
+            S->free_slots.push_back(params->max_active - 1 - i);
+        }
+        if (params->batched) {
+            LG_HIP(hipDeviceGetAttribute(&S->n_cu, hipDeviceAttributeMultiprocessorCount, S->device));
+            for (BatchSlot &B : S->batch) {
+                LG_HIP(hipStreamCreateWithFlags(&B.s, hipStreamNonBlocking));
+                LG_HIP(hipEventCreateWithFlags(&B.ev, hipEventDisableTiming));
+                LG_HIP(hipMalloc(&B.dev, kTableBytes));
+                LG_HIP(hipHostMalloc(&B.host, kTableBytes, hipHostMallocDefault));
+            }
+        }
+        return LG_OK;
+    };
+    const lg_status st = init();
+    if (st != LG_OK) {
+        release(S.get());
+        return st;
     }
     lg_server *raw = S.release();
     raw->worker = std::thread(worker_loop, raw);
@@ -546,9 +885,7 @@ lg_status lg_serve_destroy(lg_server *S)
         S->cv.notify_all();
     }
     if (S->worker.joinable()) S->worker.join();
-    for (auto s : S->streams) (void)hipStreamDestroy(s);
-    for (auto e : S->events) (void)hipEventDestroy(e);
-    (void)hipFree(S->slab.base);
+    release(S);
     delete S;
     return LG_OK;
 }

@@ -81,7 +81,8 @@ class Sdf(C.Structure):
 
 
 class ServerParams(C.Structure):
-    _fields_ = [("budget_bytes", C.c_uint64), ("max_active", C.c_int32), ("chunk_poses", C.c_int32)]
+    _fields_ = [("budget_bytes", C.c_uint64), ("max_active", C.c_int32), ("chunk_poses", C.c_int32),
+                ("batched", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -102,7 +103,8 @@ class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
                 ("cancelled", C.c_int64), ("rejected", C.c_int64), ("failed", C.c_int64),
                 ("budget_bytes", C.c_uint64), ("bytes_in_use", C.c_uint64), ("peak_bytes", C.c_uint64),
-                ("queued", C.c_int32), ("active", C.c_int32)]
+                ("queued", C.c_int32), ("active", C.c_int32), ("batches", C.c_int64),
+                ("batched_chunks", C.c_int64)]
 
 
 def _load():
@@ -590,10 +592,12 @@ def result_dict(r: Result) -> dict:
 
 
 class Server:
-    """Continuous-batching server over resident fields (see ``lg_serve_*``)."""
+    """Continuous-batching server over resident fields (see ``lg_serve_*``).
+    ``batched``: run the chunks of all idle requests as one launch per stage
+    over a per-chunk descriptor table (else one stream per request)."""
 
-    def __init__(self, budget_bytes: int, max_active: int = 8, chunk_poses: int = 4096):
-        self.params = ServerParams(int(budget_bytes), int(max_active), int(chunk_poses))
+    def __init__(self, budget_bytes: int, max_active: int = 8, chunk_poses: int = 4096, batched: bool = True):
+        self.params = ServerParams(int(budget_bytes), int(max_active), int(chunk_poses), int(bool(batched)))
         h = C.c_void_p()
         _check(_lib.lg_serve_create(C.byref(self.params), C.byref(h)), "lg_serve_create")
         self.handle = h

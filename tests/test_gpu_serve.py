@@ -1,7 +1,13 @@
-"""Serving (continuous batching over resident fields) through the C ABI.
+"""Serving (continuous batching over resident fields) through the C ABI, in
+both modes: one stream per request, and batched launches over a per-chunk
+descriptor table.
 
 * a request's result (accepted count, valid count, hash of the accepted
   (pose, draw) ids) is identical alone and mixed with other requests;
+* batched launches over uneven requests (two hands, object sizes from 333 to
+  4,096 points, ragged last chunks, with and without IK, one request with the
+  contact-point optimisation on its own stream) give every request the
+  result of the per-stream server, and batches hold several chunks;
 * it equals the direct lg_query_domains / lg_search pipeline on the same
   request id;
 * admission by the HBM budget: a request larger than the budget is rejected
@@ -44,9 +50,13 @@ def _direct(lg, field, w, rid):
     return n, lg.accepted_hash(rid, acc)
 
 
-def test_serve_alone_equals_mix_equals_direct(env):
+MODES = [pytest.param(False, id="streams"), pytest.param(True, id="batched")]
+
+
+@pytest.mark.parametrize("batched", MODES)
+def test_serve_alone_equals_mix_equals_direct(env, batched):
     lg, w1, w2, f1, f2 = env
-    srv = lg.Server(budget_bytes=1 << 30, max_active=4, chunk_poses=128)
+    srv = lg.Server(budget_bytes=1 << 30, max_active=4, chunk_poses=128, batched=batched)
     reqA, keepA = srv.make_request(f1, w1.obj.pts, w1.obj.nrm, w1.poses, w1.search, request_id=7)
     ta = srv.submit(reqA)
     alone = srv.wait(ta, 60.0)
@@ -114,14 +124,15 @@ def test_serve_cancel_queued(env):
     probe.destroy()
 
 
-def test_serve_with_realize(env):
+@pytest.mark.parametrize("batched", MODES)
+def test_serve_with_realize(env, batched):
     """Requests that run IK + penetration report valid <= accepted, and the
     valid count equals the direct pipeline's."""
     lg, _, _, _, _ = env
     from paper_2511_07418_amd.pipeline import Pipeline
     w = synth.workload("c1", n_poses=200, with_sdf=True)
     field = lg.lg_build_field(w.hand, w.field, keep_witness=True)
-    srv = lg.Server(budget_bytes=1 << 30, max_active=2, chunk_poses=64)
+    srv = lg.Server(budget_bytes=1 << 30, max_active=2, chunk_poses=64, batched=batched)
     req, keep = srv.make_request(field, w.obj.pts, w.obj.nrm, w.poses, w.search, request_id=5, ik=w.ik, sdf=w.sdf)
     r = srv.wait(srv.submit(req), 60.0)
     assert r["state"] == lg.LG_REQ_DONE and r["n_valid"] <= r["n_acc"]
@@ -142,7 +153,8 @@ def _splitmix64(z: int) -> int:
     return z ^ (z >> 31)
 
 
-def test_served_request_matches_oracle(env):
+@pytest.mark.parametrize("batched", MODES)
+def test_served_request_matches_oracle(env, batched):
     """One c1 request served (chunked, on the server's stream) against the FP64
     oracle on the same field: the accepted (pose, draw) ids are the oracle's
     (count and order-independent digest: the sum of splitmix64 of
@@ -172,7 +184,7 @@ def test_served_request_matches_oracle(env):
     for i in acc:
         want_hash = (want_hash + _splitmix64((11 << 40) ^ int(i))) & ((1 << 64) - 1)
     field = lg.lg_field_import(w.hand, w.field, ref["bits"], ref["wit"])
-    srv = lg.Server(budget_bytes=1 << 30, max_active=2, chunk_poses=96)
+    srv = lg.Server(budget_bytes=1 << 30, max_active=2, chunk_poses=96, batched=batched)
     req, keep = srv.make_request(field, w.obj.pts, w.obj.nrm, poses, sp, request_id=11, ik=w.ik, sdf=w.sdf)
     r = srv.wait(srv.submit(req), 60.0)
     srv.destroy()
@@ -180,3 +192,51 @@ def test_served_request_matches_oracle(env):
     assert len(acc) > 50 and R["valid"].sum() > 0
     assert (r["n_acc"], r["acc_hash"]) == (len(acc), want_hash)
     assert abs(r["n_valid"] - int(R["valid"].sum())) <= int((R["rflag"] != 0).sum())
+
+
+def test_batched_equals_streams_on_uneven_mix(env):
+    """Twelve uneven requests submitted at once: the batched server gives each
+    the per-stream server's (accepted, valid, hash), several chunks share a
+    batch, and a request with the contact-point optimisation (run on its own
+    stream by the batched server) still matches."""
+    import dataclasses
+    lg, w1, w2, f1, f2 = env
+    wr = synth.workload("c1", n_poses=300, with_sdf=True)
+    fr = lg.lg_build_field(wr.hand, wr.field, keep_witness=True)
+    specs = []  # (field, workload, n_points, n_poses, realize, search)
+    rng = np.random.default_rng(5)
+    for i in range(11):
+        if i % 3 == 0:
+            f, w, ik = fr, wr, True
+        elif i % 3 == 1:
+            f, w, ik = f1, w1, False
+        else:
+            f, w, ik = f2, w2, False
+        n = int(rng.integers(333, w.obj.n + 1))
+        P = int(rng.integers(40, len(w.poses) + 1))
+        specs.append((f, w, n, P, ik, w.search))
+    opt = dataclasses.replace(w1.search, opt_outer=1, opt_inner=2)
+    specs.append((f1, w1, w1.obj.n, 120, False, opt))
+    results = {}
+    for batched in (False, True):
+        srv = lg.Server(budget_bytes=2 << 30, max_active=8, chunk_poses=96, batched=batched)
+        keep, tickets = [], []
+        for i, (f, w, n, P, ik, sp) in enumerate(specs):
+            kw = dict(ik=w.ik, sdf=w.sdf) if ik else {}
+            req, kp = srv.make_request(f, w.obj.pts[:n], w.obj.nrm[:n], w.poses[:P], sp, request_id=100 + i, **kw)
+            keep.append((req, kp))
+            tickets.append(srv.submit(req))
+        out = [srv.wait(t, 180.0) for t in tickets]
+        st = srv.stats()
+        srv.destroy()
+        assert all(r["state"] == lg.LG_REQ_DONE for r in out), [r["status"] for r in out]
+        results[batched] = [(r["n_acc"], r["n_valid"], r["acc_hash"]) for r in out]
+        if batched:
+            assert st["batches"] > 0 and st["batched_chunks"] > st["batches"], st
+            # every chunk of the eleven batchable requests went through a batch
+            chunks = sum((P + 95) // 96 for (_, _, _, P, _, sp) in specs if sp.opt_outer == 0)
+            assert st["batched_chunks"] == chunks
+        else:
+            assert st["batches"] == 0
+    assert results[True] == results[False]
+    assert sum(r[0] for r in results[True]) > 0 and any(r[1] < r[0] for r in results[True])
