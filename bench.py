@@ -55,6 +55,12 @@ def parse():
                     help="serve mode: comma-separated server modes, 'batched' (descriptor-table launches) "
                          "and/or 'streams' (one stream per request)")
     ap.add_argument("--serve-alone", type=int, default=40, help="requests of each stream re-run one at a time")
+    ap.add_argument("--serve-slots", type=int, default=0, help="batched server: batches in flight (0: default)")
+    ap.add_argument("--serve-chunk", type=int, default=4096, help="server: poses per chunk")
+    ap.add_argument("--serve-active", type=int, default=8, help="server: requests admitted at once")
+    ap.add_argument("--serve-mix", default="c4", choices=["c4", "small"],
+                    help="request mix: c4 (N log-U[2k,64k], poses log-U[1k,64k]) or small "
+                         "(N log-U[2k,4k], poses log-U[1k,2k])")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--opt-outer", type=int, default=0,
                     help="rounds of contact-point optimisation (Alg. 2) before the verdicts; 0 = the plain method")
@@ -192,7 +198,8 @@ def realize_flops_per_set(w) -> float:
 
 
 def serve_bench(torch, lg, rate: float, seconds: float, seed: int = 0, alone_sample: int = 40,
-                n_requests: int = 0, batched: bool = True) -> dict:
+                n_requests: int = 0, batched: bool = True, slots: int = 0, chunk: int = 4096,
+                mix: str = "c4", active: int = 8) -> dict:
     """Serving stream: Poisson arrivals at ``rate`` req/s for ``seconds``
     (or exactly ``n_requests`` arrivals), on a server in batched or
     per-stream mode.
@@ -224,8 +231,9 @@ def serve_bench(torch, lg, rate: float, seconds: float, seed: int = 0, alone_sam
     reqs = []
     for r in range(n_req):
         obj, sdf = pool[0] if rng.uniform() < 0.5 else pool[1 + int(rng.integers(0, len(pool) - 1))]
-        n = int(np.exp(rng.uniform(np.log(2048), np.log(65536))))
-        P = int(np.exp(rng.uniform(np.log(1024), np.log(65536))))
+        n_hi, P_hi = (65536, 65536) if mix == "c4" else (4096, 2048)
+        n = int(np.exp(rng.uniform(np.log(2048), np.log(n_hi))))
+        P = int(np.exp(rng.uniform(np.log(1024), np.log(P_hi))))
         sel = np.sort(rng.choice(obj.n, size=n, replace=False))  # keeps the Morton order
         dof = 16 if rng.uniform() < 0.5 else 22
         sp = synth.SearchParams(draws=32, k=hands[dof].n_fingers, mu=0.5, m_edges=8, eps=1e-3, seed=seed,
@@ -238,7 +246,8 @@ def serve_bench(torch, lg, rate: float, seconds: float, seed: int = 0, alone_sam
         return srv.make_request(f, p, nm, po, sp, rid, ik=ik_, sdf=sdf_)
 
     mode = "batched" if batched else "streams"
-    srv = lg.Server(budget_bytes=48 << 30, max_active=8, chunk_poses=4096, batched=batched)
+    srv = lg.Server(budget_bytes=48 << 30, max_active=active, chunk_poses=chunk, batched=batched,
+                    batch_slots=slots)
     built = [make(srv, a) for _, a in reqs]
     print(f"serve {mode} {rate:g} req/s: {n_req} requests over {arrivals[-1]:.1f} s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
@@ -259,7 +268,8 @@ def serve_bench(torch, lg, rate: float, seconds: float, seed: int = 0, alone_sam
     st = srv.stats()
     srv.destroy()
     # a sample of the same requests, one at a time
-    srv = lg.Server(budget_bytes=48 << 30, max_active=8, chunk_poses=4096, batched=batched)
+    srv = lg.Server(budget_bytes=48 << 30, max_active=active, chunk_poses=chunk, batched=batched,
+                    batch_slots=slots)
     idx = np.linspace(0, n_req - 1, min(alone_sample, n_req)).astype(int)
     alone, alone_valid, same = [], 0, True
     for i in idx:
@@ -273,7 +283,7 @@ def serve_bench(torch, lg, rate: float, seconds: float, seed: int = 0, alone_sam
     for f in fields.values():
         f.release()
     alone = np.array(alone)
-    return {"mode": mode, "rate_rps": rate, "requests": n_req, "poses": int(sum(len(a[3]) for _, a in reqs)),
+    return {"mode": mode, "batch_slots": (slots or 4) if batched else None, "max_active": active, "rate_rps": rate, "requests": n_req, "poses": int(sum(len(a[3]) for _, a in reqs)),
             "span_s": span, "batches": int(st["batches"]),
             "chunks_per_batch": (st["batched_chunks"] / st["batches"]) if st["batches"] else None,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
@@ -283,7 +293,9 @@ def serve_bench(torch, lg, rate: float, seconds: float, seed: int = 0, alone_sam
             "alone_p99_ms": float(np.percentile(alone, 99) * 1e3),
             "alone_valid_grasps_per_s": alone_valid / float(alone.sum()),
             "alone_equals_mix": bool(same),
-            "mix": "sphere / superquadric 50/50, N log-U[2k,64k], poses log-U[1k,64k], "
+            "chunk_poses": chunk,
+            "mix": ("sphere / superquadric 50/50, N log-U[2k,64k], poses log-U[1k,64k], " if mix == "c4" else
+                    "sphere / superquadric 50/50, N log-U[2k,4k], poses log-U[1k,2k], ") +
                    "16/22-DOF hands 50/50, D=32, IK + SDF penetration"}
 
 
@@ -547,7 +559,8 @@ def main():
                 if mode not in ("batched", "streams"):
                     raise SystemExit(f"unknown serve mode {mode!r}")
                 r = serve_bench(torch, lg, rate, args.serve_seconds, args.seed, args.serve_alone,
-                                args.serve_requests, batched=(mode == "batched"))
+                                args.serve_requests, batched=(mode == "batched"), slots=args.serve_slots,
+                                chunk=args.serve_chunk, mix=args.serve_mix, active=args.serve_active)
                 print(json.dumps({"serving": r}), flush=True)
         return
     w = synth.workload(args.workload, seed=args.seed, with_sdf=(args.workload == "c3"))

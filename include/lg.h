@@ -416,9 +416,13 @@ lg_status lg_realize(const lg_field *field, const lg_sdf *sdf, const float *pts,
 /*    verdicts, accepted-set list, IK + penetration, counters.  Chunks of     */
 /*    uneven size share a launch (each owns the blocks its size needs); the   */
 /*    kernels with a size template (fingers, contacts, joints per finger)     */
-/*    take one launch per size class present.  Two batches are in flight at   */
-/*    most.  Requests with the contact-point optimisation (opt_outer > 0)     */
-/*    run on their own streams in either mode.                                */
+/*    take one launch per size class present.  Up to `batch_slots` batches   */
+/*    are in flight, one stream each; when several slots are free, the idle   */
+/*    chunks, in ascending size (poses x points), are cut into that many      */
+/*    batches of about equal work, so small chunks do not wait behind large   */
+/*    ones.  A request joins batches once its upload has finished.  Requests  */
+/*    with the contact-point optimisation (opt_outer > 0) run on their own    */
+/*    streams in either mode.                                                 */
 /* Host API, thread-safe; work runs on a server thread.                       */
 /* ------------------------------------------------------------------------ */
 typedef struct lg_server lg_server;
@@ -428,6 +432,7 @@ typedef struct {
     int32_t max_active;     /* requests in flight at once, 1..64 */
     int32_t chunk_poses;    /* poses per scheduling quantum, >= 1 */
     int32_t batched;        /* 1: batched launches over a descriptor table (see above) */
+    int32_t batch_slots;    /* batched mode: batches in flight at once, 1..8 (0: 4) */
 } lg_server_params;
 
 typedef struct {

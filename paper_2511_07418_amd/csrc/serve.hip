@@ -13,8 +13,9 @@
 //    (default priority) and its chunk launches its own kernels.  Batched
 //    mode: the next chunks of all idle requests are written into a
 //    descriptor table (one ChunkDesc each) and run as one launch per stage,
-//    each chunk owning the blocks its size needs; two batches can be in
-//    flight, on two streams, so a batch is assembled while the other runs;
+//    each chunk owning the blocks its size needs; `batch_slots` batches can
+//    be in flight, one stream each, so batches are assembled while others
+//    run; a request joins batches once its admission upload has finished;
 //  * determinism: RNG counters depend on (request_id, pose index within the
 //    request, draw) only, so results are identical alone and in any mix.
 #include <math.h>
@@ -218,7 +219,7 @@ struct Req {
 // holds kMaxBatch chunk descriptors and up to kMaxLaunch member lists.
 constexpr int kMaxBatch = 64;
 constexpr int kMaxLaunch = 48;
-constexpr int kBatchSlots = 2;
+constexpr int kMaxBatchSlots = 8;
 constexpr size_t kListBytes = align_up(2 * kMaxBatch) + align_up(4 * (kMaxBatch + 1));
 constexpr size_t kTableBytes = align_up(sizeof(ChunkDesc) * kMaxBatch) + kMaxLaunch * kListBytes;
 
@@ -240,7 +241,7 @@ struct lg_server {
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
     std::vector<int> free_slots;
-    lg::BatchSlot batch[lg::kBatchSlots];
+    std::vector<lg::BatchSlot> batch;
     int n_cu = 0;
     std::mutex mu;
     std::condition_variable cv;
@@ -469,10 +470,6 @@ static lg_status launch_batch(lg_server *S, BatchSlot &B)
         const int32_t P = (int32_t)std::min<int64_t>(S->p.chunk_poses, q->r.n_poses - q->next_pose);
         fill_desc(S, q, P, cd[j]);
         all[j] = j;
-        if (q->fresh) {  // the admission copies ran on the request's own stream
-            LG_HIP(hipStreamWaitEvent(B.s, q->ev, 0));
-            q->fresh = false;
-        }
         q->next_pose += P;
         q->in_flight = true;
     }
@@ -610,8 +607,8 @@ static void release(lg_server *S)
         if (B.ev) (void)hipEventDestroy(B.ev);
         if (B.dev) (void)hipFree(B.dev);
         if (B.host) (void)hipHostFree(B.host);
-        B = BatchSlot{};
     }
+    S->batch.clear();
     if (S->slab.base) (void)hipFree(S->slab.base);
     S->slab.base = nullptr;
 }
@@ -670,32 +667,60 @@ static void worker_loop(lg_server *S)
             S->st.peak_bytes = std::max<uint64_t>(S->st.peak_bytes, S->slab.used());
             progressed = true;
         }
-        // one chunk per idle active request, round-robin by admission order:
-        // on the request's own stream, or in one batch of all idle batched
-        // requests when a batch slot is free
-        BatchSlot *free_batch = nullptr;
-        for (BatchSlot &B : S->batch)
-            if (!B.busy && !free_batch) free_batch = &B;
+        // one chunk per idle active request: on the request's own stream, or
+        // in a batch (batched requests, when a batch slot is free)
+        std::vector<Req *> idle;
         for (Req *q : S->active) {
             if (q->in_flight || q->cancel || q->status != LG_OK || q->next_pose >= q->r.n_poses) continue;
             if (q->batched) {
-                if (free_batch && (int)free_batch->members.size() < kMaxBatch) free_batch->members.push_back(q);
+                // a request joins a batch once its admission copies are done, so
+                // that no batch waits for another request's upload
+                if (q->fresh) {
+                    if (hipEventQuery(q->ev) != hipSuccess) continue;
+                    q->fresh = false;
+                }
+                idle.push_back(q);
                 continue;
             }
             lg_status st = launch_chunk(S, q);
             if (st != LG_OK) q->status = st;
             progressed = true;
         }
-        if (free_batch && !free_batch->members.empty()) {
-            const lg_status st = launch_batch(S, *free_batch);
-            if (st != LG_OK)
-                for (Req *q : free_batch->members) q->status = st;
-            // the event ends whatever was enqueued, also after a failure
-            if (hipEventRecord(free_batch->ev, free_batch->s) != hipSuccess) (void)hipStreamSynchronize(free_batch->s);
-            free_batch->busy = true;
-            ++S->st.batches;
-            S->st.batched_chunks += (int64_t)free_batch->members.size();
-            progressed = true;
+        std::vector<BatchSlot *> free_slots;
+        for (BatchSlot &B : S->batch)
+            if (!B.busy) free_slots.push_back(&B);
+        if (!idle.empty() && !free_slots.empty()) {
+            // Idle chunks in ascending size (poses x points), cut into as many
+            // batches as there are free slots, of about equal size: small
+            // chunks share a batch instead of waiting behind large ones.
+            auto work = [&](const Req *q) {
+                return (double)std::min<int64_t>(S->p.chunk_poses, q->r.n_poses - q->next_pose) * q->r.n_points;
+            };
+            std::stable_sort(idle.begin(), idle.end(), [&](const Req *x, const Req *y) { return work(x) < work(y); });
+            double total = 0;
+            for (const Req *q : idle) total += work(q);
+            const size_t nb = std::min(free_slots.size(), idle.size());
+            size_t b = 0;
+            double acc = 0;
+            for (Req *q : idle) {
+                BatchSlot *B = free_slots[b];
+                B->members.push_back(q);
+                acc += work(q);
+                if (b + 1 < nb && acc >= total * (double)(b + 1) / (double)nb) ++b;
+            }
+            for (size_t i = 0; i < nb; ++i) {
+                BatchSlot *B = free_slots[i];
+                if (B->members.empty()) continue;
+                const lg_status st = launch_batch(S, *B);
+                if (st != LG_OK)
+                    for (Req *q : B->members) q->status = st;
+                // the event ends whatever was enqueued, also after a failure
+                if (hipEventRecord(B->ev, B->s) != hipSuccess) (void)hipStreamSynchronize(B->s);
+                B->busy = true;
+                ++S->st.batches;
+                S->st.batched_chunks += (int64_t)B->members.size();
+                progressed = true;
+            }
         }
         S->st.bytes_in_use = S->slab.used();
         if (!progressed) {
@@ -724,8 +749,8 @@ lg_status lg_serve_create(const lg_server_params *params, lg_server **out)
 {
     if (!params || !out) return fail(LG_EINVAL, "null params or out");
     if (params->max_active < 1 || params->max_active > kMaxBatch || params->chunk_poses < 1 ||
-        params->budget_bytes < kAlign)
-        return fail(LG_EINVAL, "need 1 <= max_active <= 64, chunk_poses >= 1, budget >= 256 B");
+        params->budget_bytes < kAlign || params->batch_slots < 0 || params->batch_slots > kMaxBatchSlots)
+        return fail(LG_EINVAL, "need 1 <= max_active <= 64, chunk_poses >= 1, budget >= 256 B, 0 <= batch_slots <= 8");
     auto S = std::make_unique<lg_server>();
     S->p = *params;
     S->t0 = std::chrono::steady_clock::now();
@@ -748,6 +773,7 @@ lg_status lg_serve_create(const lg_server_params *params, lg_server **out)
         }
         if (params->batched) {
             LG_HIP(hipDeviceGetAttribute(&S->n_cu, hipDeviceAttributeMultiprocessorCount, S->device));
+            S->batch.resize(params->batch_slots > 0 ? params->batch_slots : 4);
             for (BatchSlot &B : S->batch) {
                 LG_HIP(hipStreamCreateWithFlags(&B.s, hipStreamNonBlocking));
                 LG_HIP(hipEventCreateWithFlags(&B.ev, hipEventDisableTiming));

@@ -82,7 +82,7 @@ class Sdf(C.Structure):
 
 class ServerParams(C.Structure):
     _fields_ = [("budget_bytes", C.c_uint64), ("max_active", C.c_int32), ("chunk_poses", C.c_int32),
-                ("batched", C.c_int32)]
+                ("batched", C.c_int32), ("batch_slots", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -596,8 +596,10 @@ class Server:
     ``batched``: run the chunks of all idle requests as one launch per stage
     over a per-chunk descriptor table (else one stream per request)."""
 
-    def __init__(self, budget_bytes: int, max_active: int = 8, chunk_poses: int = 4096, batched: bool = True):
-        self.params = ServerParams(int(budget_bytes), int(max_active), int(chunk_poses), int(bool(batched)))
+    def __init__(self, budget_bytes: int, max_active: int = 8, chunk_poses: int = 4096, batched: bool = True,
+                 batch_slots: int = 0):
+        self.params = ServerParams(int(budget_bytes), int(max_active), int(chunk_poses), int(bool(batched)),
+                                   int(batch_slots))
         h = C.c_void_p()
         _check(_lib.lg_serve_create(C.byref(self.params), C.byref(h)), "lg_serve_create")
         self.handle = h
