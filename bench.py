@@ -318,6 +318,37 @@ def _prop_input(torch, obj, seed: int):
     return torch.from_numpy(x).cuda()
 
 
+def _coverage(torch, pipe, ids, obj, cell: float = 0.01) -> tuple:
+    """Spread of the valid grasps of one object: (fraction of the object's
+    occupied surface cells, edge ``cell``, holding a contact of some valid
+    grasp; number of distinct palm-pose cells: the palm origin in the object
+    frame on the same grid, times the palm's approach axis (+z) in one of 96
+    cube-map directions, 6 faces x 4 x 4)."""
+    p = torch.from_numpy(obj.pts).cuda()
+    c = torch.floor(p / cell).long() + (1 << 10)
+    key = (c[:, 0] << 22) | (c[:, 1] << 11) | c[:, 2]
+    occ, pt_cell = torch.unique(key, return_inverse=True)
+    if ids.numel() == 0:
+        return 0.0, 0
+    k = pipe.sbuf.set_pt.shape[-1]
+    sets = pipe.sbuf.set_pt.view(-1, k)[ids.long()].reshape(-1).long()
+    surf = torch.unique(pt_cell[sets[sets >= 0]]).numel() / occ.numel()
+    P = pipe.poses[(ids.long() // int(pipe.sp.draws))].view(-1, 3, 4).double()
+    R, t = P[:, :, :3], P[:, :, 3]
+    o = -(R.transpose(1, 2) @ t.unsqueeze(-1)).squeeze(-1)   # palm origin, object frame
+    z = R[:, 2, :]                                            # palm +z axis, object frame
+    a = z.abs().argmax(dim=1)
+    major = z.gather(1, a[:, None]).squeeze(1)
+    face = 2 * a + (major < 0).long()
+    uv = torch.stack([z[:, 1], z[:, 2], z[:, 0], z[:, 2], z[:, 0], z[:, 1]], 1).view(-1, 3, 2)
+    uv = uv[torch.arange(len(a), device=z.device), a] / major.abs()[:, None]
+    b = torch.clamp(((uv + 1.0) * 2.0).long(), 0, 3)
+    dirbin = face * 16 + b[:, 0] * 4 + b[:, 1]
+    oc = torch.floor(o / cell).long() + (1 << 10)
+    pk = (((oc[:, 0] << 22) | (oc[:, 1] << 11) | oc[:, 2]) * 96) + dirbin
+    return float(surf), int(torch.unique(pk).numel())
+
+
 def _diversity(torch, pipe, ids) -> int:
     """Distinct sorted point-index k-tuples among the valid grasps."""
     if ids.numel() == 0:
@@ -410,8 +441,8 @@ def proposer_bench(torch, lg, pool, n_train: int, n_eval: int, epochs: int, seed
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     # ---- evaluation on held-out objects ---------------------------------------------------
-    res = {"uniform": {"valid": 0, "diversity": 0, "s": 0.0, "per_obj": []},
-           "learned": {"valid": 0, "diversity": 0, "s": 0.0, "per_obj": []}}
+    res = {kind: {"valid": 0, "diversity": 0, "surface": 0.0, "pose_cells": 0, "s": 0.0, "per_obj": []}
+           for kind in ("uniform", "learned")}
     ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     held = []
     for i, (s_, obj, sdf) in enumerate(pool.imap(_c2_object, range(100000, 100000 + n_eval), chunksize=2)):
@@ -434,6 +465,9 @@ def proposer_bench(torch, lg, pool, n_train: int, n_eval: int, epochs: int, seed
             r = res[kind]
             r["valid"] += int(ids.numel())
             r["diversity"] += _diversity(torch, pipe, ids)
+            surf, cells = _coverage(torch, pipe, ids, obj)
+            r["surface"] += surf
+            r["pose_cells"] += cells
             r["s"] += ev[0].elapsed_time(ev[1]) * 1e-3
             r["per_obj"].append(int(ids.numel()))
     out = {"train_objects": n_train, "train_objects_with_valid": len(xs), "train_valid_grasps": n_valid_train,
@@ -443,6 +477,8 @@ def proposer_bench(torch, lg, pool, n_train: int, n_eval: int, epochs: int, seed
     for kind, r in res.items():
         out[kind] = {"valid_grasps": r["valid"], "valid_per_object": r["valid"] / n_eval,
                      "valid_grasps_per_s": r["valid"] / r["s"], "distinct_contact_sets": r["diversity"],
+                     "contact_surface_coverage": r["surface"] / n_eval,
+                     "palm_pose_cells_per_object": r["pose_cells"] / n_eval,
                      "seconds": r["s"]}
     pu, pl = np.array(res["uniform"]["per_obj"]), np.array(res["learned"]["per_obj"])
     out["objects_learned_ge_uniform"] = int((pl >= pu).sum())

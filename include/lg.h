@@ -420,7 +420,9 @@ lg_status lg_realize(const lg_field *field, const lg_sdf *sdf, const float *pts,
 /*    are in flight, one stream each; when several slots are free, the idle   */
 /*    chunks, in ascending size (poses x points), are cut into that many      */
 /*    batches of about equal work, so small chunks do not wait behind large   */
-/*    ones.  A request joins batches once its upload has finished.  Requests  */
+/*    ones.  A request joins batches once its upload has finished; one of    */
+/*    two chunks or more holds two copies of the chunk buffers, so two of its */
+/*    chunks can be in flight at once, in two batches.  Requests              */
 /*    with the contact-point optimisation (opt_outer > 0) run on their own    */
 /*    streams in either mode.                                                 */
 /* Host API, thread-safe; work runs on a server thread.                       */

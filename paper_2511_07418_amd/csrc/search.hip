@@ -705,11 +705,14 @@ k_grid_scan(uint32_t *__restrict__ cell_count, const GridDev *__restrict__ gd, u
     }
 }
 
+// the points of each cell, contiguous: (x, y, z, point index as bits)
 __global__ void k_grid_scatter(const float *__restrict__ pts, int N, const GridDev *__restrict__ gd,
-                               uint32_t *__restrict__ cursor, int32_t *__restrict__ cell_pts)
+                               uint32_t *__restrict__ cursor, float4 *__restrict__ cell_pts)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) cell_pts[atomicAdd(&cursor[point_cell(*gd, pts, N, i)], 1u)] = i;
+    if (i < N)
+        cell_pts[atomicAdd(&cursor[point_cell(*gd, pts, N, i)], 1u)] =
+            make_float4(pts[i], pts[N + i], pts[2 * N + i], __int_as_float(i));
 }
 
 __device__ inline bool dom_has(const uint32_t *dom, int i) { return (dom[i >> 5] >> (i & 31)) & 1u; }
@@ -724,7 +727,7 @@ __device__ inline bool dom_has(const uint32_t *dom, int i) { return (dom[i >> 5]
 // float: the shell and box tests keep 1e-6 m of slack.
 constexpr int kProjShellsInc = 8;
 __device__ int project_domain_inc(const GridDev &g, const uint32_t *__restrict__ cell_start,
-                                  const int32_t *__restrict__ cell_pts, const float *__restrict__ pts, int N,
+                                  const float4 *__restrict__ cell_pts, const float *__restrict__ pts, int N,
                                   const uint32_t *__restrict__ dom, double yx, double yy, double yz, int inc)
 {
     const double fx = (yx - g.lo[0]) * (double)g.inv_cell, fy = (yy - g.lo[1]) * (double)g.inv_cell,
@@ -737,8 +740,8 @@ __device__ int project_domain_inc(const GridDev &g, const uint32_t *__restrict__
         const double ex = (double)pts[inc] - yx, ey = (double)pts[N + inc] - yy, ez = (double)pts[2 * N + inc] - yz;
         best = ex * ex + ey * ey + ez * ez;
     }
-    auto consider = [&](int i) {
-        const double ex = (double)pts[i] - yx, ey = (double)pts[N + i] - yy, ez = (double)pts[2 * N + i] - yz;
+    auto consider_at = [&](int i, float px, float py, float pz) {
+        const double ex = (double)px - yx, ey = (double)py - yy, ez = (double)pz - yz;
         const double d2 = ex * ex + ey * ey + ez * ez;
         if (d2 < best || (d2 == best && i < bi)) {
             best = d2;
@@ -768,8 +771,9 @@ __device__ int project_domain_inc(const GridDev &g, const uint32_t *__restrict__
                     if (x >= 0 && x < g.dims[0] && box_d2(x, yv, z) <= lim * lim) {
                         const int cc = (z * g.dims[1] + yv) * g.dims[0] + x;
                         for (uint32_t q = cell_start[cc]; q < cell_start[cc + 1]; ++q) {
-                            const int i = cell_pts[q];
-                            if (dom_has(dom, i)) consider(i);
+                            const float4 v = cell_pts[q];
+                            const int i = __float_as_int(v.w);
+                            if (dom_has(dom, i)) consider_at(i, v.x, v.y, v.z);
                         }
                     }
                     if (R == 0) break;
@@ -784,7 +788,8 @@ __device__ int project_domain_inc(const GridDev &g, const uint32_t *__restrict__
         while (x) {
             const int b = __ffs(x) - 1;
             x &= x - 1u;
-            consider(w * 32 + b);
+            const int i = w * 32 + b;
+            consider_at(i, pts[i], pts[N + i], pts[2 * N + i]);
         }
     }
     return bi;
@@ -809,7 +814,7 @@ k_opt_project(const float *__restrict__ pts, const float *__restrict__ nrm, int 
               const int32_t *__restrict__ palm_pt, int F, int D, int k, int round, int n_inner, double sigma,
               uint32_t seed_lo, uint32_t seed_hi, uint32_t request_id, int64_t pose_offset,
               const GridDev *__restrict__ gdp, const uint32_t *__restrict__ cell_start,
-              const int32_t *__restrict__ cell_pts, const int32_t *__restrict__ set_pt, int32_t *__restrict__ cands)
+              const float4 *__restrict__ cell_pts, const int32_t *__restrict__ set_pt, int32_t *__restrict__ cands)
 {
     const GridDev g = *gdp;
     const int NW = (N + 31) >> 5;
@@ -1277,7 +1282,7 @@ extern "C" {
 // workspace: [set chunks: count, offset] [pose chunks: count, offset]
 //            [valid pose list P] [n_valid_poses] [pose_valid P bytes]
 //            and, for the contact-point optimisation, [grid params]
-//            [cell counts/cursor (kGridMax+1)^3] [cell starts +1] [cell points N]
+//            [cell counts/cursor (kGridMax+1)^3] [cell starts +1] [cell points N: xyz + index]
 //            [a round's candidates P D k n_inner]
 struct SearchWs {
     uint32_t *chunk_count, *chunk_off, *pchunk_count, *pchunk_off;
@@ -1285,7 +1290,7 @@ struct SearchWs {
     uint8_t *pose_valid;
     GridDev *grid;
     uint32_t *cell_count, *cell_start;
-    int32_t *cell_pts;
+    float4 *cell_pts;
     int32_t *cands;
     size_t bytes;
 };
@@ -1318,8 +1323,9 @@ static SearchWs search_ws(void *base, int64_t n_points, int64_t n_poses, int64_t
         off += (size_t)ncell * 4;
         w.cell_start = reinterpret_cast<uint32_t *>(b + off);
         off += (size_t)(ncell + 1) * 4;
-        w.cell_pts = reinterpret_cast<int32_t *>(b + off);
-        off += ((size_t)n_points * 4 + 255) & ~(size_t)255;
+        off = (off + 255) & ~(size_t)255;
+        w.cell_pts = reinterpret_cast<float4 *>(b + off);
+        off += ((size_t)n_points * 16 + 255) & ~(size_t)255;
         w.cands = reinterpret_cast<int32_t *>(b + off);
         off += (size_t)n_sets * k * n_inner * 4;
     }

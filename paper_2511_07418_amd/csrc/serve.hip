@@ -150,11 +150,24 @@ class Slab {
     uint64_t used_ = 0;
 };
 
-// Sizes of one request's device buffers (inputs + one chunk of work).
+// Sizes of one request's device buffers: its inputs and counters, then
+// `nbuf` copies of one chunk's working buffers (the offsets are those of copy
+// 0; copy j lies j * buf_bytes further).  Batched requests of two chunks or
+// more get two copies, so that two of their chunks can be in flight, in two
+// batches; the others get one.
 struct ReqLayout {
-    uint64_t pts, nrm, bounds, poses, sdf, dom_bits, dom_count, set_pt, set_link, verdict, tstar, acc, n_acc, ws;
-    uint64_t q, err, ang, depth, valid, counters, total;
+    uint64_t pts, nrm, bounds, poses, sdf, counters;
+    uint64_t dom_bits, dom_count, set_pt, set_link, verdict, tstar, acc, n_acc, ws, ws_bytes;
+    uint64_t q, err, ang, depth, valid;
+    uint64_t buf_bytes;
+    int nbuf;
+    uint64_t total;
 };
+
+static bool batched_request(const lg_server_params &sp, const lg_request &r)
+{
+    return sp.batched && r.search.opt_outer == 0;
+}
 
 static ReqLayout layout_of(const lg_server_params &sp, const lg_request &r)
 {
@@ -175,6 +188,8 @@ static ReqLayout layout_of(const lg_server_params &sp, const lg_request &r)
     L.poses = take(48 * (uint64_t)r.n_poses);
     const int64_t G = r.realize ? r.sdf_dims : 0;
     L.sdf = take(4 * (uint64_t)(G * G * G));
+    L.counters = take(3 * 8);
+    const uint64_t work0 = off;
     L.dom_bits = take(4 * (uint64_t)(chunk * F * NW));
     L.dom_count = take(4 * (uint64_t)(chunk * F));
     L.set_pt = take(4 * (uint64_t)(sets * k));
@@ -184,15 +199,17 @@ static ReqLayout layout_of(const lg_server_params &sp, const lg_request &r)
     L.acc = take(4 * (uint64_t)sets);
     L.n_acc = take(4);
     lg_search_params p = r.search;
-    L.ws = take(lg_search_workspace_bytes((int32_t)N, (int32_t)chunk, &p));
+    L.ws_bytes = lg_search_workspace_bytes((int32_t)N, (int32_t)chunk, &p);
+    L.ws = take(L.ws_bytes);
     const int64_t ra = r.realize ? sets : 0;
     L.q = take(4 * (uint64_t)(ra * J));
     L.err = take(4 * (uint64_t)(ra * k));
     L.ang = take(4 * (uint64_t)(ra * k));
     L.depth = take(4 * (uint64_t)ra);
     L.valid = take((uint64_t)ra);
-    L.counters = take(3 * 8);
-    L.total = off;
+    L.buf_bytes = off - work0;
+    L.nbuf = batched_request(sp, r) && r.n_poses > chunk ? 2 : 1;
+    L.total = work0 + L.nbuf * L.buf_bytes;
     return L;
 }
 
@@ -205,7 +222,9 @@ struct Req {
     int slot = -1;
     int32_t state = LG_REQ_QUEUED;
     int32_t status = LG_OK;
-    bool cancel = false, in_flight = false;
+    bool cancel = false;
+    int inflight = 0;      // chunks enqueued and not yet complete
+    uint32_t buf_busy = 0; // working-buffer copies held by chunks in flight (bit per copy)
     bool batched = false;  // chunks go through the batched launches
     bool fresh = false;    // admission copies not yet waited for by a batch
     int64_t next_pose = 0;
@@ -229,6 +248,7 @@ struct BatchSlot {
     char *dev = nullptr;   // device table
     char *host = nullptr;  // pinned staging copy
     std::vector<Req *> members;
+    std::vector<int> bufs;  // the working-buffer copy of each member's chunk
     bool busy = false;
 };
 
@@ -315,7 +335,7 @@ static lg_status launch_chunk(lg_server *S, Req *q)
     int32_t *n_acc = reinterpret_cast<int32_t *>(base + L.n_acc);
     st = lg_search(r.field, pts, nrm, r.n_points, poses, P, db, dc, &sp, set_pt, set_link,
                    reinterpret_cast<uint8_t *>(base + L.verdict), reinterpret_cast<double *>(base + L.tstar), acc,
-                   n_acc, base + L.ws, L.q - L.ws, s);
+                   n_acc, base + L.ws, L.ws_bytes, s);
     if (st != LG_OK) return st;
     uint8_t *valid = nullptr;
     if (r.realize) {
@@ -340,7 +360,7 @@ static lg_status launch_chunk(lg_server *S, Req *q)
     LG_HIP(hipGetLastError());
     LG_HIP(hipEventRecord(q->ev, s));
     q->next_pose = g0 + P;
-    q->in_flight = true;
+    q->inflight = 1;
     return LG_OK;
 }
 
@@ -382,12 +402,13 @@ struct TableWriter {
     }
 };
 
-// every argument of request q's next chunk of P poses
-static void fill_desc(const lg_server *S, const Req *q, int32_t P, ChunkDesc &c)
+// every argument of request q's next chunk of P poses, in working-buffer copy buf
+static void fill_desc(const lg_server *S, const Req *q, int32_t P, int buf, ChunkDesc &c)
 {
     const lg_request &r = q->r;
     const lg_field *f = r.field;
-    char *base = S->slab.base + q->off;
+    char *in = S->slab.base + q->off;                    // inputs and counters
+    char *base = in + (uint64_t)buf * q->L.buf_bytes;  // this chunk's working buffers
     const ReqLayout &L = q->L;
     const int64_t g0 = q->next_pose;
     memset(&c, 0, sizeof c);
@@ -395,10 +416,10 @@ static void fill_desc(const lg_server *S, const Req *q, int32_t P, ChunkDesc &c)
     c.merged = f->d_merged;
     c.bits = f->d_bits;
     c.wit = f->has_witness ? f->d_wit : nullptr;
-    c.pts = reinterpret_cast<const float *>(base + L.pts);
-    c.nrm = reinterpret_cast<const float *>(base + L.nrm);
-    c.poses = reinterpret_cast<const float *>(base + L.poses) + 12 * g0;
-    c.bounds = reinterpret_cast<const float4 *>(base + L.bounds);
+    c.pts = reinterpret_cast<const float *>(in + L.pts);
+    c.nrm = reinterpret_cast<const float *>(in + L.nrm);
+    c.poses = reinterpret_cast<const float *>(in + L.poses) + 12 * g0;
+    c.bounds = reinterpret_cast<const float4 *>(in + L.bounds);
     c.N = r.n_points;
     c.P = P;
     c.D = r.search.draws;
@@ -425,7 +446,7 @@ static void fill_desc(const lg_server *S, const Req *q, int32_t P, ChunkDesc &c)
     c.realize = r.realize ? 1 : 0;
     if (r.realize) {
         c.S = SdfDev{r.sdf_origin[0], r.sdf_origin[1], r.sdf_origin[2], r.sdf_h, 1.0f / r.sdf_h, r.sdf_dims,
-                     reinterpret_cast<const float *>(base + L.sdf)};
+                     reinterpret_cast<const float *>(in + L.sdf)};
         const lg_ik_params &p = r.ik;  // random joints of fingers without contact: keyed like the search
         c.ik = IkDev{p.iters, p.phase1, p.lambda, p.beta, p.tol_pos, p.tol_ang, p.margin, p.self_collision,
                      c.seed_lo, c.seed_hi, r.request_id, g0};
@@ -435,7 +456,7 @@ static void fill_desc(const lg_server *S, const Req *q, int32_t P, ChunkDesc &c)
         c.depth = reinterpret_cast<float *>(base + L.depth);
         c.valid = reinterpret_cast<uint8_t *>(base + L.valid);
     }
-    c.counters = reinterpret_cast<unsigned long long *>(base + L.counters);
+    c.counters = reinterpret_cast<unsigned long long *>(in + L.counters);
 }
 
 // members with the same bucket value, in member order
@@ -462,16 +483,20 @@ static std::vector<std::vector<int>> buckets(const std::vector<int> &who, Key ke
 static lg_status launch_batch(lg_server *S, BatchSlot &B)
 {
     const int n = (int)B.members.size();
+    B.bufs.assign(n, 0);
     TableWriter T{B.host, B.dev};
     ChunkDesc *cd = T.descs();
     std::vector<int> all(n);
     for (int j = 0; j < n; ++j) {
         Req *q = B.members[j];
         const int32_t P = (int32_t)std::min<int64_t>(S->p.chunk_poses, q->r.n_poses - q->next_pose);
-        fill_desc(S, q, P, cd[j]);
+        const int buf = __builtin_ctz(~q->buf_busy);  // a free working-buffer copy (inflight < nbuf)
+        fill_desc(S, q, P, buf, cd[j]);
+        B.bufs[j] = buf;
+        q->buf_busy |= 1u << buf;
         all[j] = j;
         q->next_pose += P;
-        q->in_flight = true;
+        ++q->inflight;
     }
     auto blocks = [&](const std::vector<int> &who, auto per) {
         std::vector<uint32_t> nb;
@@ -622,7 +647,10 @@ static void worker_loop(lg_server *S)
         // completions: batches, then requests
         for (BatchSlot &B : S->batch) {
             if (B.busy && hipEventQuery(B.ev) == hipSuccess) {
-                for (Req *q : B.members) q->in_flight = false;
+                for (size_t j = 0; j < B.members.size(); ++j) {
+                    --B.members[j]->inflight;
+                    B.members[j]->buf_busy &= ~(1u << B.bufs[j]);
+                }
                 B.members.clear();
                 B.busy = false;
                 progressed = true;
@@ -630,11 +658,11 @@ static void worker_loop(lg_server *S)
         }
         for (size_t i = 0; i < S->active.size();) {
             Req *q = S->active[i];
-            if (q->in_flight && !q->batched && hipEventQuery(q->ev) == hipSuccess) {
-                q->in_flight = false;
+            if (q->inflight && !q->batched && hipEventQuery(q->ev) == hipSuccess) {
+                q->inflight = 0;
                 progressed = true;
             }
-            if (!q->in_flight && (q->cancel || q->next_pose >= q->r.n_poses || q->status != LG_OK)) {
+            if (!q->inflight && (q->cancel || q->next_pose >= q->r.n_poses || q->status != LG_OK)) {
                 finish(S, q, q->status != LG_OK ? LG_REQ_FAILED : (q->cancel ? LG_REQ_CANCELLED : LG_REQ_DONE));
                 S->active.erase(S->active.begin() + i);
                 S->st.active = (int32_t)S->active.size();
@@ -655,7 +683,7 @@ static void worker_loop(lg_server *S)
             q->slot = S->free_slots.back();
             S->free_slots.pop_back();
             q->ev = S->events[q->slot];
-            q->batched = S->p.batched && q->r.search.opt_outer == 0;
+            q->batched = batched_request(S->p, q->r);
             q->state = LG_REQ_RUNNING;
             q->t_admit = S->now();
             lg_status st = admit(S, q);
@@ -671,8 +699,9 @@ static void worker_loop(lg_server *S)
         // in a batch (batched requests, when a batch slot is free)
         std::vector<Req *> idle;
         for (Req *q : S->active) {
-            if (q->in_flight || q->cancel || q->status != LG_OK || q->next_pose >= q->r.n_poses) continue;
+            if (q->cancel || q->status != LG_OK || q->next_pose >= q->r.n_poses) continue;
             if (q->batched) {
+                if (q->inflight >= q->L.nbuf) continue;
                 // a request joins a batch once its admission copies are done, so
                 // that no batch waits for another request's upload
                 if (q->fresh) {
@@ -682,6 +711,7 @@ static void worker_loop(lg_server *S)
                 idle.push_back(q);
                 continue;
             }
+            if (q->inflight) continue;
             lg_status st = launch_chunk(S, q);
             if (st != LG_OK) q->status = st;
             progressed = true;
