@@ -130,7 +130,12 @@ __device__ inline int nearest_bin_lut4(const uint32_t *lut, const float4 *c4, in
     const float s = (0.5f * kLutRes) * __builtin_amdgcn_rcpf(m);
     const int iu = min(max((int)fmaf(u, s, 0.5f * kLutRes), 0), kLutRes - 1);
     const int iv = min(max((int)fmaf(v, s, 0.5f * kLutRes), 0), kLutRes - 1);
-    const uint32_t e = lut[(face * kLutRes + iv) * kLutRes + iu];
+    // byte offset of the entry; the row by a 24-bit multiply (full rate; the
+    // compiler would otherwise pick the quarter-rate 32-bit multiply)
+    uint32_t row;
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(row) : "n"(4 * kLutRes), "v"((uint32_t)(face * kLutRes + iv)));
+    const uint32_t boff = row + ((uint32_t)iu << 2);
+    const uint32_t e = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(lut) + boff);
     float best = -3.0e38f;
     int bi = 0;
     if (e == 0xffffffffu) {  // more than four candidates: every bin

@@ -770,10 +770,19 @@ __device__ int project_domain_inc(const GridDev &g, const uint32_t *__restrict__
                     const double lim = sqrt(best) + 1e-6;
                     if (x >= 0 && x < g.dims[0] && box_d2(x, yv, z) <= lim * lim) {
                         const int cc = (z * g.dims[1] + yv) * g.dims[0] + x;
-                        for (uint32_t q = cell_start[cc]; q < cell_start[cc + 1]; ++q) {
+                        // the domain bit is read only for a point that would
+                        // improve on the best (rare once a near point is known)
+                        const uint32_t q1 = cell_start[cc + 1];
+#pragma unroll 4
+                        for (uint32_t q = cell_start[cc]; q < q1; ++q) {
                             const float4 v = cell_pts[q];
                             const int i = __float_as_int(v.w);
-                            if (dom_has(dom, i)) consider_at(i, v.x, v.y, v.z);
+                            const double ex = (double)v.x - yx, ey = (double)v.y - yy, ez = (double)v.z - yz;
+                            const double d2 = ex * ex + ey * ey + ez * ez;
+                            if ((d2 < best || (d2 == best && i < bi)) && dom_has(dom, i)) {
+                                best = d2;
+                                bi = i;
+                            }
                         }
                     }
                     if (R == 0) break;
