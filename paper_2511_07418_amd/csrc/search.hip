@@ -209,10 +209,25 @@ k_draw_batch(const ChunkDesc *__restrict__ d, const uint16_t *__restrict__ idx, 
 
 // ---- force-closure LP ---------------------------------------------------------
 // Duff et al. (2017) branchless orthonormal basis of unit n.
+__device__ inline double duff_a(double nz) { return -1.0 / (copysign(1.0, nz) + nz); }
+
+// the basis from a = duff_a(nz), computed once per normal by the LP
+__device__ inline void duff_basis_a(double nx, double ny, double nz, double a, double *x, double *y)
+{
+    const double sign = copysign(1.0, nz);
+    const double b = nx * ny * a;
+    x[0] = 1.0 + sign * nx * nx * a;
+    x[1] = sign * b;
+    x[2] = -sign * nx;
+    y[0] = b;
+    y[1] = sign + ny * ny * a;
+    y[2] = -ny;
+}
+
 __device__ inline void duff_basis(double nx, double ny, double nz, double *x, double *y)
 {
     const double sign = copysign(1.0, nz);
-    const double a = -1.0 / (sign + nz);
+    const double a = duff_a(nz);
     const double b = nx * ny * a;
     x[0] = 1.0 + sign * nx * nx * a;
     x[1] = sign * b;
@@ -249,6 +264,19 @@ __device__ inline double lp_lane(float (&cd)[KM * 6][256], int tid, int k, int m
 {
     const int n = k * m;
     const double inv_rho = 1.0 / rho;
+    // the reciprocal of each contact's tangent basis, once per LP (every
+    // pricing and column rebuilds the basis); in LDS up to 6 contacts, beyond
+    // that recomputed (the LDS would cost the 8-contact kernels occupancy)
+    constexpr bool kDa = KM <= 6;
+    __shared__ double da[kDa ? KM : 1][256];
+    if constexpr (kDa)
+        for (int i = 0; i < k; ++i) da[i][tid] = duff_a((double)cd[6 * i + 5][tid]);
+    auto basis_of = [&](int ci, double nx, double ny, double nz, double *x, double *y) {
+        if constexpr (kDa)
+            duff_basis_a(nx, ny, nz, da[ci][tid], x, y);
+        else
+            duff_basis(nx, ny, nz, x, y);
+    };
     // contact i's point and normal (each lane reads only its own column)
     auto contact = [&](int ci, double &px, double &py, double &pz, double &nx, double &ny, double &nz) {
         px = cd[6 * ci + 0][tid];
@@ -267,7 +295,7 @@ __device__ inline double lp_lane(float (&cd)[KM * 6][256], int tid, int k, int m
             double px, py, pz, nx, ny, nz;
             contact(ci, px, py, pz, nx, ny, nz);
             double x[3], y[3];
-            duff_basis(nx, ny, nz, x, y);
+            basis_of(ci, nx, ny, nz, x, y);
             const double c = cs.ce[e], s = cs.se[e];
             const double dx = -nx + mu * (c * x[0] + s * y[0]);
             const double dy = -ny + mu * (c * x[1] + s * y[1]);
@@ -402,7 +430,7 @@ __device__ inline double lp_lane(float (&cd)[KM * 6][256], int tid, int k, int m
             const double uy = y[1] + (y[5] * px - y[3] * pz) * inv_rho;
             const double uz = y[2] + (y[3] * py - y[4] * px) * inv_rho;
             double x[3], yy[3];
-            duff_basis(nx, ny, nz, x, yy);
+            basis_of(i, nx, ny, nz, x, yy);
             const double an = ux * nx + uy * ny + uz * nz;
             const double bx = ux * x[0] + uy * x[1] + uz * x[2];
             const double by = ux * yy[0] + uy * yy[1] + uz * yy[2];
