@@ -94,14 +94,32 @@ __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-// Candidate table of the normal bins over a cube map of directions: a
-// direction d is mapped to face (major axis, sign) and cell (iu, iv) of a
-// kLutRes x kLutRes grid over (d_b, d_c) / |d_a|.  A cell lists, in increasing
-// order, every bin whose dot product can come within kLutMargin of the best
-// one anywhere in the cell (checked on a dense sub-grid of the cell; the
-// margin exceeds the dot-product variation between sub-grid points), so the
-// argmax over the candidates equals the argmax over all bins.  Cells with
-// more than four candidates are marked for the full search (0xffffffff).
+// Candidate table of the normal bins over a cube map of directions, in the
+// GPU's own cube-map convention (the v_cube* instructions the query uses): a
+// direction d goes to face f = 0..5 (+x, -x, +y, -y, +z, -z; on ties z before
+// y before x) and face coordinates (s, t) in [-1, 1]^2, s = sc / |d_major|,
+// t = tc / |d_major|, with
+//   +x: d ~ (1, -t, -s)   -x: d ~ (-1, -t, s)   +y: d ~ (s, 1, t)
+//   -y: d ~ (s, -1, -t)   +z: d ~ (s, -t, 1)    -z: d ~ (-s, -t, -1),
+// and to cell (is, it) of a kLutRes x kLutRes grid over (s, t).  A cell lists,
+// in increasing order, every bin whose dot product can come within kLutMargin
+// of the best one anywhere in the closed cell (checked on a dense sub-grid of
+// the cell; the margin exceeds the dot-product variation between sub-grid
+// points), so the argmax over the candidates equals the argmax over all bins,
+// also for a direction on a cell or face boundary.  Cells with more than four
+// candidates are marked for the full search (0xffffffff).
+static void cube_direction(int face, double s, double t, double *d)
+{
+    switch (face) {
+    case 0: d[0] = 1.0; d[1] = -t; d[2] = -s; break;
+    case 1: d[0] = -1.0; d[1] = -t; d[2] = s; break;
+    case 2: d[0] = s; d[1] = 1.0; d[2] = t; break;
+    case 3: d[0] = s; d[1] = -1.0; d[2] = -t; break;
+    case 4: d[0] = s; d[1] = -t; d[2] = 1.0; break;
+    default: d[0] = -s; d[1] = -t; d[2] = -1.0; break;
+    }
+}
+
 static void build_bin_lut(const std::vector<float> &bc, int B, std::vector<uint32_t> &lut)
 {
     const int R = kLutRes, SUB = 9;
@@ -109,19 +127,15 @@ static void build_bin_lut(const std::vector<float> &bc, int B, std::vector<uint3
     const double sub_step = 2.0 / R / (SUB - 1);           // in face coordinates
     const double margin = 2.0 * sub_step + 1e-4;            // angular spacing <= coordinate spacing
     for (int face = 0; face < 6; ++face) {
-        const int a = face >> 1, bax = (a + 1) % 3, cax = (a + 2) % 3;
-        const double sg = (face & 1) ? -1.0 : 1.0;
-        for (int iv = 0; iv < R; ++iv)
-            for (int iu = 0; iu < R; ++iu) {
+        for (int it = 0; it < R; ++it)
+            for (int is = 0; is < R; ++is) {
                 std::vector<int> cand;
-                for (int sv = 0; sv < SUB; ++sv)
-                    for (int su = 0; su < SUB; ++su) {
-                        const double u = -1.0 + 2.0 * (iu + (double)su / (SUB - 1)) / R;
-                        const double v = -1.0 + 2.0 * (iv + (double)sv / (SUB - 1)) / R;
+                for (int st = 0; st < SUB; ++st)
+                    for (int ss = 0; ss < SUB; ++ss) {
+                        const double sv = -1.0 + 2.0 * (is + (double)ss / (SUB - 1)) / R;
+                        const double tv = -1.0 + 2.0 * (it + (double)st / (SUB - 1)) / R;
                         double d[3];
-                        d[a] = sg;
-                        d[bax] = u;
-                        d[cax] = v;
+                        cube_direction(face, sv, tv, d);
                         const double nd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
                         double best = -1e300, dots[kMaxBins];
                         for (int b = 0; b < B; ++b) {
@@ -137,7 +151,7 @@ static void build_bin_lut(const std::vector<float> &bc, int B, std::vector<uint3
                     // absent slots repeat the first candidate (the kernel evaluates all four)
                     uint32_t e = 0;
                     for (size_t i = 0; i < 4; ++i) e |= (uint32_t)cand[i < cand.size() ? i : 0] << (8 * i);
-                    lut[(face * R + iv) * R + iu] = e;
+                    lut[(face * R + it) * R + is] = e;
                 }
             }
     }

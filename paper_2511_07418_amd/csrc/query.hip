@@ -119,22 +119,19 @@ __device__ inline uint32_t block_skip(const float4 *__restrict__ bounds, const A
 // every bin.
 __device__ inline int nearest_bin_lut4(const uint32_t *lut, const float4 *c4, int B, float dx, float dy, float dz)
 {
-    const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
-    const bool xm = (ax >= ay) & (ax >= az);
-    const bool ym = !xm & (ay >= az);
-    const float m = xm ? ax : (ym ? ay : az);
-    const float u = xm ? dy : (ym ? dz : dx);
-    const float v = xm ? dz : (ym ? dx : dy);
-    const float dm = xm ? dx : (ym ? dy : dz);
-    const int face = (xm ? 0 : (ym ? 2 : 4)) + (dm < 0.f ? 1 : 0);
-    const float s = (0.5f * kLutRes) * __builtin_amdgcn_rcpf(m);
-    const int iu = min(max((int)fmaf(u, s, 0.5f * kLutRes), 0), kLutRes - 1);
-    const int iv = min(max((int)fmaf(v, s, 0.5f * kLutRes), 0), kLutRes - 1);
+    // face and face coordinates by the cube-map instructions (the table is
+    // built in their convention): ma = 2 x the major component, so
+    // (sc / |major| + 1) R / 2 = sc R / |ma| + R / 2
+    const int face = (int)__builtin_amdgcn_cubeid(dx, dy, dz);
+    const float sc = __builtin_amdgcn_cubesc(dx, dy, dz), tc = __builtin_amdgcn_cubetc(dx, dy, dz);
+    const float sf = (float)kLutRes * __builtin_amdgcn_rcpf(fabsf(__builtin_amdgcn_cubema(dx, dy, dz)));
+    const int is = min(max((int)fmaf(sc, sf, 0.5f * kLutRes), 0), kLutRes - 1);
+    const int it = min(max((int)fmaf(tc, sf, 0.5f * kLutRes), 0), kLutRes - 1);
     // byte offset of the entry; the row by a 24-bit multiply (full rate; the
     // compiler would otherwise pick the quarter-rate 32-bit multiply)
     uint32_t row;
-    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(row) : "n"(4 * kLutRes), "v"((uint32_t)(face * kLutRes + iv)));
-    const uint32_t boff = row + ((uint32_t)iu << 2);
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(row) : "n"(4 * kLutRes), "v"((uint32_t)(face * kLutRes + it)));
+    const uint32_t boff = row + ((uint32_t)is << 2);
     const uint32_t e = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(lut) + boff);
     float best = -3.0e38f;
     int bi = 0;
