@@ -154,7 +154,7 @@ class Slab {
 // `nbuf` copies of one chunk's working buffers (the offsets are those of copy
 // 0; copy j lies j * buf_bytes further).  Batched requests of two chunks or
 // more get two copies, so that two of their chunks can be in flight, in two
-// batches; the others get one.
+// batches, unless two copies exceed the server's budget; the others get one.
 struct ReqLayout {
     uint64_t pts, nrm, bounds, poses, sdf, counters;
     uint64_t dom_bits, dom_count, set_pt, set_link, verdict, tstar, acc, n_acc, ws, ws_bytes;
@@ -209,6 +209,7 @@ static ReqLayout layout_of(const lg_server_params &sp, const lg_request &r)
     L.valid = take((uint64_t)ra);
     L.buf_bytes = off - work0;
     L.nbuf = batched_request(sp, r) && r.n_poses > chunk ? 2 : 1;
+    if (work0 + L.nbuf * L.buf_bytes > sp.budget_bytes) L.nbuf = 1;  // one copy if two cannot fit
     L.total = work0 + L.nbuf * L.buf_bytes;
     return L;
 }

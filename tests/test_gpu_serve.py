@@ -240,3 +240,25 @@ def test_batched_equals_streams_on_uneven_mix(env):
             assert st["batches"] == 0
     assert results[True] == results[False]
     assert sum(r[0] for r in results[True]) > 0 and any(r[1] < r[0] for r in results[True])
+
+
+def test_batched_request_falls_back_to_one_buffer_copy(env):
+    """A batched request of several chunks holds two copies of the chunk
+    buffers, or one when two exceed the server's budget; either way its result
+    is the same."""
+    lg, w1, w2, f1, f2 = env
+    one = lg.Server(budget_bytes=1 << 30, max_active=2, chunk_poses=64, batched=False)
+    req, keep = one.make_request(f1, w1.obj.pts, w1.obj.nrm, w1.poses, w1.search, request_id=21)
+    one_bytes = one.request_bytes(req)
+    one.destroy()
+    big = lg.Server(budget_bytes=1 << 30, max_active=2, chunk_poses=64, batched=True)
+    two_bytes = big.request_bytes(req)
+    assert two_bytes > one_bytes
+    ref = big.wait(big.submit(req), 60.0)
+    big.destroy()
+    small = lg.Server(budget_bytes=one_bytes + 256, max_active=2, chunk_poses=64, batched=True)
+    assert small.request_bytes(req) == one_bytes
+    r = small.wait(small.submit(req), 60.0)
+    small.destroy()
+    assert ref["state"] == r["state"] == lg.LG_REQ_DONE
+    assert (r["n_acc"], r["n_valid"], r["acc_hash"]) == (ref["n_acc"], ref["n_valid"], ref["acc_hash"])
