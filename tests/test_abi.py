@@ -151,3 +151,17 @@ def test_morton_order_on_the_host(lglib):
     with pytest.raises(lglib.LgError):
         lglib.lg_morton_order(bad)
     assert L.lg_chunk_bounds(None, 10, None, None) == lglib.LG_EINVAL
+
+
+def test_server_parameters_checked_before_device_work(lglib):
+    """lg_serve_create refuses bad parameters (batch slots, active requests,
+    chunk size) before it allocates anything."""
+    L = lglib.lib()
+    h = C.c_void_p()
+    for p in (lglib.ServerParams(1 << 20, 4, 64, 1, 9),     # more than 8 batch slots
+              lglib.ServerParams(1 << 20, 4, 64, 1, -1),    # negative batch slots
+              lglib.ServerParams(1 << 20, 65, 64, 1, 0),    # more than 64 active requests
+              lglib.ServerParams(1 << 20, 4, 0, 0, 0)):     # empty chunks
+        assert L.lg_serve_create(C.byref(p), C.byref(h)) == lglib.LG_EINVAL
+        assert b"batch_slots" in L.lg_last_error() or b"max_active" in L.lg_last_error()
+        assert h.value is None
