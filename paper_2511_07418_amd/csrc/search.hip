@@ -629,7 +629,7 @@ k_verdict_batch(const ChunkDesc *__restrict__ d, const uint16_t *__restrict__ id
 // sort.  The search scans shells of cells at Chebyshev distance R = 0, 1, ...
 // around the candidate's cell; points in unscanned cells are at least R c away,
 // so once the best distance is below R c (less a rounding margin) it is exact
-// (project_domain_inc).  Distances are FP64, ties go to the lowest point index.
+// (project_domain_wave).  Distances are FP64, ties go to the lowest point index.
 constexpr int kGridMax = 64;
 constexpr uint32_t kPurposeOpt = 5u;
 constexpr double kOptTau = 1e-9;  // candidates within kOptTau of the best criterion value tie
@@ -747,34 +747,127 @@ __device__ inline bool dom_has(const uint32_t *dom, int i) { return (dom[i >> 5]
 
 // Nearest domain point to y given a domain point `inc` (the contact's current
 // point): FP64 distances, lowest index on ties, with inc as the incumbent.
-// Shell R is scanned only while R c can still beat the best distance, cells
-// whose box lies farther than the best are skipped, and no point beyond
-// |y - inc| needs a look: the scan ends by R = ceil(|y - inc| / c) + 1 (the
-// whole domain is scanned only past kProjShellsInc shells, for steps of many
-// cell edges).  The pruning tests run in float, in cell units, against
-// lim = (sqrt(best) + 1e-6 m) / c rounded up by a relative 1e-5: points are
-// binned in float, and the 1e-6 m of slack covers both that binning and the
-// float tests, so a pruned cell never holds a point that could win.  lim is
-// recomputed only when the best improves.  A cell's records are read four at
-// a time (the last record repeated past the end), so four loads are in
-// flight per lane; the domain bit is read only for a point that would improve
-// on the best (rare once a near point is known).
+// The 64 lanes of a wave project one candidate together (all arguments are
+// wave-uniform), so the lanes never wait on each other's scans.  Shells of
+// cells at Chebyshev distance R = 0, 1, ... around y's cell are scanned while
+// R - 1 cell edges can still beat the best distance (the scan ends by R =
+// ceil(|y - inc| / c) + 1; the whole domain is scanned only past
+// kProjShellsInc shells).  In one pass each lane takes one cell position of
+// the shell and keeps it if its box lies within the best distance; the kept
+// cells' points are then spread over the lanes, 64 points per step, in the
+// order of the lanes' running counts (a DPP scan).  A step's points that beat
+// the best are checked against the domain bits and the wave takes their
+// minimum (distance, then index) by DPP.  The box and shell tests run in
+// float, in cell units, against lim = (sqrt(best) + 1e-6 m) / c rounded up by
+// a relative 1e-5: points are binned in float, and the 1e-6 m of slack covers
+// both that binning and the float tests, so a skipped cell never holds a
+// point that could win.  The incumbent's distance and the centre cell's range
+// come in with the candidate (each lane reads them for its own candidate).
 constexpr int kProjShellsInc = 8;
-__device__ int project_domain_inc(const GridDev &g, const uint32_t *__restrict__ cell_start,
-                                  const float4 *__restrict__ cell_pts, const float *__restrict__ pts, int N,
-                                  const uint32_t *__restrict__ dom, double yx, double yy, double yz, int inc)
+
+__device__ inline double wave_bcast(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// DPP move of both halves of a double; lanes without a source keep v
+template <int C, int RM = 0xf>
+__device__ inline double dpp_d(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)(uint32_t)b, hi = (int)(b >> 32);
+    const int nlo = __builtin_amdgcn_update_dpp(lo, lo, C, RM, 0xf, false);
+    const int nhi = __builtin_amdgcn_update_dpp(hi, hi, C, RM, 0xf, false);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)nhi << 32) | (uint32_t)nlo));
+}
+
+// minimum over the wave, valid in lane 63: quad swaps, row rotations by 4
+// and 8, then rows 0+1 and 2+3 and the halves joined by the row broadcasts
+__device__ inline double wave_min63(double v)
+{
+    v = fmin(v, dpp_d<0xB1>(v));        // quad_perm [1, 0, 3, 2]
+    v = fmin(v, dpp_d<0x4E>(v));        // quad_perm [2, 3, 0, 1]
+    v = fmin(v, dpp_d<0x124>(v));       // row_ror:4
+    v = fmin(v, dpp_d<0x128>(v));       // row_ror:8
+    v = fmin(v, dpp_d<0x142, 0xA>(v));  // row_bcast:15 into rows 1 and 3
+    v = fmin(v, dpp_d<0x143, 0xC>(v));  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+// inclusive prefix sum over the lanes (row shifts by 1, 2, 4, 8, then the row
+// broadcasts); lanes without a source add 0
+__device__ inline uint32_t wave_scan_incl(uint32_t x)
+{
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
+
+// the minimum of (d2, i) over the lanes with `take` (lexicographic), folded
+// into (best, bi); every lane returns the same result
+__device__ inline void wave_lexmin(bool take, double d2, int i, double &best, int &bi)
+{
+    const unsigned long long m = __ballot(take);
+    if (!m) return;
+    double v;
+    int ib;
+    if (__popcll(m) == 1) {
+        const int l = __builtin_ctzll(m);
+        v = wave_bcast(d2, l);
+        ib = __builtin_amdgcn_readlane(i, l);
+    } else {
+        v = wave_bcast(wave_min63(take ? d2 : INFINITY), 63);
+        const unsigned long long t = __ballot(take && d2 == v);
+        ib = __builtin_amdgcn_readlane(i, __builtin_ctzll(t));
+        for (unsigned long long r = t & (t - 1); r; r &= r - 1)  // equal distances: the lowest index
+            ib = min(ib, __builtin_amdgcn_readlane(i, __builtin_ctzll(r)));
+    }
+    if (v < best || (v == best && ib < bi)) {
+        best = v;
+        bi = ib;
+    }
+}
+
+// position p of the shell at Chebyshev distance R >= 1 (side s = 2R + 1):
+// the two z faces (s^2 each), then a ring of 4(s - 1) cells per inner z slab
+__device__ inline void shell_pos(int R, int p, int &dx, int &dy, int &dz)
+{
+    const int s = 2 * R + 1, s2 = s * s;
+    if (p < 2 * s2) {
+        const bool hi = p >= s2;
+        dz = hi ? R : -R;
+        const int r = p - (hi ? s2 : 0), ry = r / s;
+        dy = ry - R;
+        dx = r - ry * s - R;
+    } else {
+        const int q = p - 2 * s2, ring = 4 * (s - 1), sl = q / ring, t = q - sl * ring, e = t / (s - 1),
+                  o = t - e * (s - 1);
+        dz = sl - R + 1;
+        dx = e == 0 ? o - R : (e == 1 ? R : (e == 2 ? R - o : -R));
+        dy = e == 0 ? -R : (e == 1 ? o - R : (e == 2 ? R : R - o));
+    }
+}
+
+// best: the incumbent's squared distance; [cq0, cq0 + ccnt): the records of
+// y's own cell (empty when y lies outside the grid)
+__device__ int project_domain_wave(const GridDev &g, const uint32_t *__restrict__ cell_start,
+                                   const float4 *__restrict__ cell_pts, const float *__restrict__ pts, int N,
+                                   const uint32_t *__restrict__ dom, double yx, double yy, double yz, int inc,
+                                   double best, uint32_t cq0, uint32_t ccnt, int lane)
 {
     const double fx = (yx - g.lo[0]) * (double)g.inv_cell, fy = (yy - g.lo[1]) * (double)g.inv_cell,
                  fz = (yz - g.lo[2]) * (double)g.inv_cell;
     const int cx = (int)floor(fx), cy = (int)floor(fy), cz = (int)floor(fz);
     // y inside its cell, in cell units
     const float rx = (float)(fx - (double)cx), ry = (float)(fy - (double)cy), rz = (float)(fz - (double)cz);
-    double best;
     int bi = inc;
-    {
-        const double ex = (double)pts[inc] - yx, ey = (double)pts[N + inc] - yy, ez = (double)pts[2 * N + inc] - yz;
-        best = ex * ex + ey * ey + ez * ez;
-    }
     float lim, lim2;
     auto set_lim = [&]() {
         lim = (float)((sqrt(best) + 1e-6) * (double)g.inv_cell) * 1.00001f;
@@ -785,77 +878,94 @@ __device__ int project_domain_inc(const GridDev &g, const uint32_t *__restrict__
     auto slab = [](int o, float r) { return o > 0 ? (float)o - r : (o < 0 ? (float)(-o - 1) + r : 0.0f); };
     for (int R = 0; R <= kProjShellsInc; ++R) {
         if (R > 0 && lim < (float)(R - 1)) return bi;  // shell R cannot hold a closer point
-        for (int dz = -R; dz <= R; ++dz) {
-            const int z = cz + dz;
-            const float sz = slab(dz, rz) * slab(dz, rz);
-            if (z < 0 || z >= g.dims[2] || sz > lim2) continue;
-            for (int dy = -R; dy <= R; ++dy) {
-                const int yv = cy + dy;
-                const float syz = sz + slab(dy, ry) * slab(dy, ry);
-                if (yv < 0 || yv >= g.dims[1] || syz > lim2) continue;
-                const bool edge = (dz == -R || dz == R || dy == -R || dy == R);
-                for (int dx = -R; dx <= R; dx += (edge ? 1 : 2 * R)) {
-                    const int x = cx + dx;
-                    if (x >= 0 && x < g.dims[0] && syz + slab(dx, rx) * slab(dx, rx) <= lim2) {
-                        const int cc = (z * g.dims[1] + yv) * g.dims[0] + x;
-                        const uint32_t q0 = cell_start[cc], q1 = cell_start[cc + 1];
-                        bool improved = false;
-                        for (uint32_t q = q0; q < q1; q += 4) {
-                            float4 v[4];
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) v[u] = cell_pts[min(q + (uint32_t)u, q1 - 1u)];
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const int i = __float_as_int(v[u].w);
-                                const double ex = (double)v[u].x - yx, ey = (double)v[u].y - yy,
-                                             ez = (double)v[u].z - yz;
-                                const double d2 = ex * ex + ey * ey + ez * ez;
-                                if ((d2 < best || (d2 == best && i < bi)) && dom_has(dom, i)) {
-                                    best = d2;
-                                    bi = i;
-                                    improved = true;
-                                }
-                            }
-                        }
-                        if (improved) set_lim();
-                    }
-                    if (R == 0) break;
+        const int s = 2 * R + 1, n_pos = R == 0 ? 1 : s * s * s - (s - 2) * (s - 2) * (s - 2);
+        for (int p0 = 0; p0 < n_pos; p0 += 64) {
+            // this lane's cell position: kept if inside the grid and within lim
+            uint32_t q0 = 0, cnt = 0;
+            if (R == 0) {
+                if (lane == 0) {
+                    q0 = cq0;
+                    cnt = ccnt;
                 }
+            } else if (p0 + lane < n_pos) {
+                int dx, dy, dz;
+                shell_pos(R, p0 + lane, dx, dy, dz);
+                const int x = cx + dx, yv = cy + dy, z = cz + dz;
+                const float bx = slab(dx, rx), by = slab(dy, ry), bz = slab(dz, rz);
+                if (x >= 0 && x < g.dims[0] && yv >= 0 && yv < g.dims[1] && z >= 0 && z < g.dims[2] &&
+                    bx * bx + by * by + bz * bz <= lim2) {
+                    const int cc = (z * g.dims[1] + yv) * g.dims[0] + x;
+                    q0 = cell_start[cc];
+                    cnt = cell_start[cc + 1] - q0;
+                }
+            }
+            // lane l's points are [ex, ex + cnt) of the pass's running count
+            const uint32_t incl = wave_scan_incl(cnt), ex = incl - cnt;
+            const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+            for (uint32_t b0 = 0; b0 < total; b0 += 64) {
+                const uint32_t f = b0 + (uint32_t)lane;
+                // the record of point f: the kept cells whose ranges meet this
+                // step, in lane order (the last one starting at or before f owns it)
+                uint32_t rec = 0;
+                for (unsigned long long km = __ballot(cnt > 0 && ex < b0 + 64u && incl > b0); km; km &= km - 1) {
+                    const int l = __builtin_ctzll(km);
+                    const uint32_t lex = (uint32_t)__builtin_amdgcn_readlane((int)ex, l);
+                    const uint32_t lq0 = (uint32_t)__builtin_amdgcn_readlane((int)q0, l);
+                    if (f >= lex) rec = lq0 + (f - lex);
+                }
+                bool take = false;
+                double d2 = INFINITY;
+                int i = INT_MAX;
+                if (f < total) {
+                    const float4 v = cell_pts[rec];
+                    i = __float_as_int(v.w);
+                    const double ex3 = (double)v.x - yx, ey3 = (double)v.y - yy, ez3 = (double)v.z - yz;
+                    d2 = ex3 * ex3 + ey3 * ey3 + ez3 * ez3;
+                    take = (d2 < best || (d2 == best && i < bi)) && dom_has(dom, i);
+                }
+                const double old = best;
+                wave_lexmin(take, d2, i, best, bi);
+                if (best != old) set_lim();
             }
         }
     }
     if (sqrt(best) < (double)kProjShellsInc * g.cell - 1e-6) return bi;
+    // beyond the shells: every domain point, words spread over the lanes
     const int NW = (N + 31) >> 5;
-    for (int w = 0; w < NW; ++w) {
+    double lb = INFINITY;
+    int li = INT_MAX;
+    for (int w = lane; w < NW; w += 64) {
         uint32_t x = dom[w];
         while (x) {
             const int b = __ffs(x) - 1;
             x &= x - 1u;
             const int i = w * 32 + b;
-            const double ex = (double)pts[i] - yx, ey = (double)pts[N + i] - yy, ez = (double)pts[2 * N + i] - yz;
-            const double d2 = ex * ex + ey * ey + ez * ez;
-            if (d2 < best || (d2 == best && i < bi)) {
-                best = d2;
-                bi = i;
+            const double ex3 = (double)pts[i] - yx, ey3 = (double)pts[N + i] - yy, ez3 = (double)pts[2 * N + i] - yz;
+            const double d2 = ex3 * ex3 + ey3 * ey3 + ez3 * ez3;
+            if (d2 < lb || (d2 == lb && i < li)) {
+                lb = d2;
+                li = i;
             }
         }
     }
+    wave_lexmin(li != INT_MAX, lb, li, best, bi);
     return bi;
 }
 
 
-// GS lanes per set (GS >= n_inner, a power of two): lane j evaluates candidate
-// j of every step; the group agrees on the pick by shuffles and one ballot.
-// Alg. 2, the candidates of one round (Sec. 5.4): thread per (set, contact
-// i, candidate j).  Contact i's candidates are drawn around its point at the
-// start of the round (contact i moves only at its own step), so a round's
-// projections are independent of its criterion evaluations and run here, at
-// full occupancy, before them: y = p_i + dx x_i + dy y_i with (dx, dy) =
-// sigma * Box-Muller of Philox block (g + pose_offset, d, 5 | step << 8,
-// request_id), step = (round k + i) n_inner + j, and cand = the nearest point
-// of contact i's domain (incumbent p_i).  cands[((t k + i) n_inner + j)], t =
-// the set's rank among the sets of valid poses; -1 for sets not drawn.
-__global__ void __launch_bounds__(256)
+// Alg. 2, the candidates of one round (Sec. 5.4): one candidate per
+// (set, contact i, candidate j).  Contact i's candidates are drawn around its
+// point at the start of the round (contact i moves only at its own step), so
+// a round's projections are independent of its criterion evaluations and run
+// here, before them: y = p_i + dx x_i + dy y_i with (dx, dy) = sigma *
+// Box-Muller of Philox block (g + pose_offset, d, 5 | step << 8, request_id),
+// step = (round k + i) n_inner + j, and cand = the nearest point of contact
+// i's domain (incumbent p_i).  cands[((t k + i) n_inner + j)], t = the set's
+// rank among the sets of valid poses; -1 for sets not drawn.  Each lane draws
+// one candidate; the wave then projects its 64 candidates one after another,
+// all lanes together (project_domain_wave).  Eight waves per SIMD (64 VGPRs;
+// the candidate set-up spills a few) hide more of the scans' load latency.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_opt_project(const float *__restrict__ pts, const float *__restrict__ nrm, int N,
               const int32_t *__restrict__ valid_poses, const int32_t *__restrict__ n_valid_poses,
               const uint32_t *__restrict__ dom_bits, const uint32_t *__restrict__ dom_count,
@@ -866,40 +976,75 @@ k_opt_project(const float *__restrict__ pts, const float *__restrict__ nrm, int 
 {
     const GridDev g = *gdp;
     const int NW = (N + 31) >> 5;
+    const int lane = threadIdx.x & 63;
     const int64_t per_set = (int64_t)k * n_inner;
     const int64_t n_total = (int64_t)(*n_valid_poses) * D * per_set;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n_total; u += stride) {
-        const int64_t t = u / per_set;
-        const int rem = (int)(u - t * per_set), i = rem / n_inner, j = rem - i * n_inner;
-        const int64_t pg = valid_poses[t / D];
-        const int d = (int)(t % D);
-        const int32_t *sp = set_pt + (pg * D + d) * k;
-        const uint32_t fm = choose_fingers(eligible_fingers(dom_count, pg, F), k, (uint32_t)(pose_offset + pg), d,
-                                           request_id, seed_lo, seed_hi);
-        const int pc = palm_pt ? palm_pt[pg] : -1;
-        bool drawn = fm != 0 && pc < N;
-        for (int q = 0; q < k; ++q) drawn &= sp[q] >= 0 && sp[q] < N;
-        if (!drawn) {
-            cands[u] = -1;
-            continue;
+    // the loop bound is uniform over the wave (u - lane is the wave's first candidate)
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u - lane < n_total; u += stride) {
+        bool live = false;
+        double yx = 0.0, yy = 0.0, yz = 0.0, best0 = 0.0;
+        int inc = 0;
+        int64_t dom_off = 0;
+        uint32_t cq0 = 0, ccnt = 0;  // the records of y's own cell
+        if (u < n_total) {
+            const int64_t t = u / per_set;
+            const int rem = (int)(u - t * per_set), i = rem / n_inner, j = rem - i * n_inner;
+            const int64_t pg = valid_poses[t / D];
+            const int d = (int)(t % D);
+            const int32_t *sp = set_pt + (pg * D + d) * k;
+            const uint32_t fm = choose_fingers(eligible_fingers(dom_count, pg, F), k, (uint32_t)(pose_offset + pg),
+                                               d, request_id, seed_lo, seed_hi);
+            const int pc = palm_pt ? palm_pt[pg] : -1;
+            bool drawn = fm != 0 && pc < N;
+            for (int q = 0; q < k; ++q) drawn &= sp[q] >= 0 && sp[q] < N;
+            if (!drawn) {
+                cands[u] = -1;
+            } else {
+                live = true;
+                inc = sp[i];
+                const double px = pts[inc], py = pts[N + inc], pz = pts[2 * N + inc];
+                double tx[3], ty[3];
+                duff_basis(nrm[inc], nrm[N + inc], nrm[2 * N + inc], tx, ty);
+                uint32_t w[4];
+                const uint32_t step = (uint32_t)((round * k + i) * n_inner + j);
+                philox4x32_10((uint32_t)(pose_offset + pg), (uint32_t)d, kPurposeOpt | (step << 8), request_id,
+                              seed_lo, seed_hi, w);
+                const double u1 = ((double)(w[0] >> 8) + 1.0) * (1.0 / 16777216.0);
+                const double u2 = (double)(w[1] >> 8) * (1.0 / 16777216.0);
+                const double rr = sqrt(-2.0 * log(u1));
+                const double dx = sigma * rr * cos(2.0 * M_PI * u2), dy = sigma * rr * sin(2.0 * M_PI * u2);
+                yx = px + dx * tx[0] + dy * ty[0];
+                yy = py + dx * tx[1] + dy * ty[1];
+                yz = pz + dx * tx[2] + dy * ty[2];
+                dom_off = (pg * F + select_in_word(fm, (uint32_t)i)) * NW;  // contact i's finger
+                {
+                    const double ex = px - yx, ey = py - yy, ez = pz - yz;
+                    best0 = ex * ex + ey * ey + ez * ez;
+                }
+                const int cx = (int)floor((yx - g.lo[0]) * (double)g.inv_cell),
+                          cy = (int)floor((yy - g.lo[1]) * (double)g.inv_cell),
+                          cz = (int)floor((yz - g.lo[2]) * (double)g.inv_cell);
+                if (cx >= 0 && cx < g.dims[0] && cy >= 0 && cy < g.dims[1] && cz >= 0 && cz < g.dims[2]) {
+                    const int cc = (cz * g.dims[1] + cy) * g.dims[0] + cx;
+                    cq0 = cell_start[cc];
+                    ccnt = cell_start[cc + 1] - cq0;
+                }
+            }
         }
-        const int idx = sp[i];
-        const double px = pts[idx], py = pts[N + idx], pz = pts[2 * N + idx];
-        double tx[3], ty[3];
-        duff_basis(nrm[idx], nrm[N + idx], nrm[2 * N + idx], tx, ty);
-        uint32_t w[4];
-        const uint32_t step = (uint32_t)((round * k + i) * n_inner + j);
-        philox4x32_10((uint32_t)(pose_offset + pg), (uint32_t)d, kPurposeOpt | (step << 8), request_id, seed_lo,
-                      seed_hi, w);
-        const double u1 = ((double)(w[0] >> 8) + 1.0) * (1.0 / 16777216.0);
-        const double u2 = (double)(w[1] >> 8) * (1.0 / 16777216.0);
-        const double rr = sqrt(-2.0 * log(u1));
-        const double dx = sigma * rr * cos(2.0 * M_PI * u2), dy = sigma * rr * sin(2.0 * M_PI * u2);
-        const int fi = select_in_word(fm, (uint32_t)i);  // finger of contact i
-        cands[u] = project_domain_inc(g, cell_start, cell_pts, pts, N, dom_bits + (pg * F + fi) * NW,
-                                      px + dx * tx[0] + dy * ty[0], py + dx * tx[1] + dy * ty[1],
-                                      pz + dx * tx[2] + dy * ty[2], idx);
+        int res = -1;
+        for (unsigned long long todo = __ballot(live); todo; todo &= todo - 1) {
+            const int c = __builtin_ctzll(todo);
+            const int64_t off = ((int64_t)__builtin_amdgcn_readlane((int)(dom_off >> 32), c) << 32) |
+                                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)dom_off, c);
+            const int r = project_domain_wave(
+                g, cell_start, cell_pts, pts, N, dom_bits + off, wave_bcast(yx, c), wave_bcast(yy, c),
+                wave_bcast(yz, c), __builtin_amdgcn_readlane(inc, c), wave_bcast(best0, c),
+                (uint32_t)__builtin_amdgcn_readlane((int)cq0, c), (uint32_t)__builtin_amdgcn_readlane((int)ccnt, c),
+                lane);
+            if (lane == c) res = r;
+        }
+        if (live) cands[u] = res;
     }
 }
 
