@@ -444,7 +444,7 @@ uint32_t verdict_blocks(int64_t n_sets, int n_cu);
 LpConst lp_const(int m);
 // the search workspace's lists of a chunk of P poses (no contact optimisation)
 void chunk_workspace(void *ws, int64_t n_points, int64_t n_poses, int64_t draws, ChunkDesc &c);
-lg_status verdict_batch(const BatchLaunch &b, int km, hipStream_t s);
+lg_status verdict_batch(const BatchLaunch &b, int km, bool m8, hipStream_t s);  // m8: every chunk has an 8-edge cone
 uint32_t realize_blocks(int64_t max_acc, int F, int n_cu);
 lg_status realize_batch(const BatchLaunch &b, int max_dof, hipStream_t s);
 

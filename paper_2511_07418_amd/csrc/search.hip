@@ -260,7 +260,9 @@ constexpr int kBlandAfter = 48;   // pivots priced by Dantzig's rule before Blan
 
 // t* of the set held in this lane's LDS column (cd[6 i + c][tid]); status
 // 0 = optimal, 1 = pivot cap, 2 = unbounded ratio test (not expected).
-template <int KM, bool WARM = false>
+// MC > 0: the cone has MC edges (m == MC), known at compile time, so the
+// pricing's edge loop is unrolled over constant edge directions.
+template <int KM, bool WARM = false, int MC = 0>
 __device__ inline double lp_lane(float (&cd)[KM * 6][256], int tid, int k, int m, double mu, double rho,
                                  int max_pivots, const LpConst &cs, int &status_out, int (*warm)[256] = nullptr)
 {
@@ -436,12 +438,25 @@ __device__ inline double lp_lane(float (&cd)[KM * 6][256], int tid, int k, int m
             const double an = ux * nx + uy * ny + uz * nz;
             const double bx = ux * x[0] + uy * x[1] + uz * x[2];
             const double by = ux * yy[0] + uy * yy[1] + uz * yy[2];
-            for (int ee = 0; ee < m; ++ee) {
-                const double d = -(-an + mu * (cs.ce[ee] * bx + cs.se[ee] * by)) - y[6];
-                if (d < best) {
-                    best = d;
-                    e = i * m + ee;
-                    if (bland) break;
+            if constexpr (MC > 0) {
+                bool done = false;
+#pragma unroll
+                for (int ee = 0; ee < MC; ++ee) {
+                    const double d = -(-an + mu * (cs.ce[ee] * bx + cs.se[ee] * by)) - y[6];
+                    if (!done && d < best) {
+                        best = d;
+                        e = i * MC + ee;
+                        done = bland;
+                    }
+                }
+            } else {
+                for (int ee = 0; ee < m; ++ee) {
+                    const double d = -(-an + mu * (cs.ce[ee] * bx + cs.se[ee] * by)) - y[6];
+                    if (d < best) {
+                        best = d;
+                        e = i * m + ee;
+                        if (bland) break;
+                    }
                 }
             }
         }
@@ -553,7 +568,7 @@ __device__ inline double lp_lane(float (&cd)[KM * 6][256], int tid, int k, int m
 
 // block bid of nb blocks (grid-stride); cd: contact data of each lane's set
 // in LDS, lane-contiguous: cd[6*i + c][tid]
-template <int KM>
+template <int KM, int MC = 0>
 __device__ __forceinline__ void verdict_sets(float (&cd)[KM * 6][256], int64_t bid, int64_t nb,
                                              const float *__restrict__ pts, const float *__restrict__ nrm, int N,
                                              const int32_t *__restrict__ set_pt, const int32_t *__restrict__ palm_pt,
@@ -591,13 +606,13 @@ __device__ __forceinline__ void verdict_sets(float (&cd)[KM * 6][256], int64_t b
             continue;
         }
         int status = 0;
-        const double ts = lp_lane<KM>(cd, tid, kc, m, mu, rho, max_pivots, cs, status);
+        const double ts = lp_lane<KM, false, MC>(cd, tid, kc, m, mu, rho, max_pivots, cs, status);
         verdict[sid] = (status == 0 && ts <= eps) ? 1 : 0;
         tstar[sid] = status == 0 ? ts : __builtin_nan("");
     }
 }
 
-template <int KM>
+template <int KM, int MC>
 __global__ void __launch_bounds__(256)
 k_verdict_lane(const float *__restrict__ pts, const float *__restrict__ nrm, int N, const int32_t *__restrict__ set_pt,
                const int32_t *__restrict__ palm_pt, const int32_t *__restrict__ valid_poses,
@@ -605,11 +620,11 @@ k_verdict_lane(const float *__restrict__ pts, const float *__restrict__ nrm, int
                int max_pivots, LpConst cs, uint8_t *__restrict__ verdict, double *__restrict__ tstar)
 {
     __shared__ float cd[KM * 6][256];
-    verdict_sets<KM>(cd, blockIdx.x, gridDim.x, pts, nrm, N, set_pt, palm_pt, valid_poses, n_valid_poses, D, k, m, mu,
-                     rho, eps, max_pivots, cs, verdict, tstar);
+    verdict_sets<KM, MC>(cd, blockIdx.x, gridDim.x, pts, nrm, N, set_pt, palm_pt, valid_poses, n_valid_poses, D, k, m,
+                         mu, rho, eps, max_pivots, cs, verdict, tstar);
 }
 
-template <int KM>
+template <int KM, int MC>
 __global__ void __launch_bounds__(256)
 k_verdict_batch(const ChunkDesc *__restrict__ d, const uint16_t *__restrict__ idx, const uint32_t *__restrict__ first,
                 int n)
@@ -617,7 +632,7 @@ k_verdict_batch(const ChunkDesc *__restrict__ d, const uint16_t *__restrict__ id
     __shared__ float cd[KM * 6][256];
     const int j = batch_member(first, n, blockIdx.x);
     const ChunkDesc &c = d[idx[j]];
-    verdict_sets<KM>(cd, blockIdx.x - first[j], first[j + 1] - first[j], c.pts, c.nrm, c.N, c.set_pt, nullptr,
+    verdict_sets<KM, MC>(cd, blockIdx.x - first[j], first[j + 1] - first[j], c.pts, c.nrm, c.N, c.set_pt, nullptr,
                      c.valid_poses, c.n_valid_poses, c.D, c.k, c.m, c.mu, c.rho, c.eps, c.max_pivots, c.cs, c.verdict,
                      c.tstar);
 }
@@ -1056,7 +1071,7 @@ k_opt_project(const float *__restrict__ pts, const float *__restrict__ nrm, int 
 // of it by one ballot; contact i moves there.  The set's points are written
 // back after the round; tstar (the last step's J) and, after the last round,
 // the verdict.
-template <int KM, int GS>
+template <int KM, int GS, int MC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, const int32_t *__restrict__ valid_poses,
            const int32_t *__restrict__ n_valid_poses, const uint32_t *__restrict__ dom_count,
@@ -1118,7 +1133,7 @@ k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, 
                 if (cand >= 0) {  // always, for a drawn set (its domains are non-empty)
                     load(i, cand);
                     int st = 0;
-                    Jc = lp_lane<KM, true>(cd, tid, kc, m, mu, rho, max_pivots, cs, st, wbs);
+                    Jc = lp_lane<KM, true, MC>(cd, tid, kc, m, mu, rho, max_pivots, cs, st, wbs);
                     if (st != 0) Jc = INFINITY;
                 }
             }
@@ -1616,14 +1631,17 @@ static lg_status search_impl(const lg_field *field, const float *pts, const floa
     LG_HIP(hipGetDevice(&dev));
     LG_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     const dim3 lgrid(verdict_blocks(n_sets, n_cu));
-#define LG_VERDICT(KM)                                                                                          \
-    hipLaunchKernelGGL(k_verdict_lane<KM>, lgrid, dim3(256), 0, s, pts, nrm, n_points, set_pt, palm,             \
+    // the common 8-edge cone gets kernels with the edge loop unrolled
+    const bool m8 = p->m_edges == 8;
+#define LG_VERDICT_M(KM, MC)                                                                                    \
+    hipLaunchKernelGGL((k_verdict_lane<KM, MC>), lgrid, dim3(256), 0, s, pts, nrm, n_points, set_pt, palm,       \
                        ws.valid_poses,                                                                          \
                        ws.n_valid_poses, p->draws, p->k, p->m_edges, (double)p->mu, (double)p->moment_scale,     \
                        (double)p->eps, p->max_pivots, cs, verdict, tstar)
+#define LG_VERDICT(KM) if (m8) LG_VERDICT_M(KM, 8); else LG_VERDICT_M(KM, 0)
     if (!opt) {
-        if (kk <= 3) LG_VERDICT(3); else if (kk <= 4) LG_VERDICT(4); else if (kk <= 5) LG_VERDICT(5);
-        else if (kk <= 6) LG_VERDICT(6); else LG_VERDICT(8);
+        if (kk <= 3) { LG_VERDICT(3); } else if (kk <= 4) { LG_VERDICT(4); } else if (kk <= 5) { LG_VERDICT(5); }
+        else if (kk <= 6) { LG_VERDICT(6); } else { LG_VERDICT(8); }
     } else {
         // cell grid of the object, then Alg. 2 on the drawn sets, then the links of the moved contacts
         const int64_t ncell = (int64_t)(kGridMax + 1) * (kGridMax + 1) * (kGridMax + 1);
@@ -1641,31 +1659,38 @@ static lg_status search_impl(const lg_field *field, const float *pts, const floa
             1, std::min<int64_t>((n_sets * gs + 255) / 256, (int64_t)n_cu * 8)));
         const dim3 pgrid((unsigned)std::max<int64_t>(
             1, std::min<int64_t>((n_sets * p->k * p->opt_inner + 255) / 256, (int64_t)n_cu * 32)));
-#define LG_OPT(KM, GS)                                                                                           \
-    hipLaunchKernelGGL((k_optimize<KM, GS>), ogrid, dim3(256), 0, s, pts, nrm, n_points, ws.valid_poses,           \
+#define LG_OPT_M(KM, GS, MC)                                                                                     \
+    hipLaunchKernelGGL((k_optimize<KM, GS, MC>), ogrid, dim3(256), 0, s, pts, nrm, n_points, ws.valid_poses,       \
                        ws.n_valid_poses, dom_count, palm, H.F, p->draws, p->k, p->m_edges, (double)p->mu,         \
                        (double)p->moment_scale, (double)p->eps, p->max_pivots, cs, p->opt_inner,                  \
                        r == p->opt_outer - 1, (uint32_t)p->seed, (uint32_t)(p->seed >> 32), p->request_id,        \
                        p->pose_offset, ws.cands, set_pt, verdict, tstar)
+#define LG_OPT(KM, GS) LG_OPT_M(KM, GS, 0)
 #define LG_OPT_K(GS)                                                                                             \
     if (kk <= 3) LG_OPT(3, GS); else if (kk <= 4) LG_OPT(4, GS); else if (kk <= 5) LG_OPT(5, GS);              \
     else if (kk <= 6) LG_OPT(6, GS); else LG_OPT(8, GS)
+#define LG_OPT_K8                                                                                                \
+    if (kk <= 3) LG_OPT_M(3, 8, 8); else if (kk <= 4) LG_OPT_M(4, 8, 8); else if (kk <= 5) LG_OPT_M(5, 8, 8);  \
+    else if (kk <= 6) LG_OPT_M(6, 8, 8); else LG_OPT_M(8, 8, 8)
         for (int r = 0; r < p->opt_outer; ++r) {
             hipLaunchKernelGGL(k_opt_project, pgrid, dim3(256), 0, s, pts, nrm, n_points, ws.valid_poses,
                                ws.n_valid_poses, dom_bits, dom_count, palm, H.F, p->draws, p->k, r, p->opt_inner,
                                (double)p->opt_sigma, (uint32_t)p->seed, (uint32_t)(p->seed >> 32), p->request_id,
                                p->pose_offset, ws.grid, ws.cell_start, ws.cell_pts, set_pt, ws.cands);
             if (gs == 1) { LG_OPT_K(1); } else if (gs == 2) { LG_OPT_K(2); } else if (gs == 4) { LG_OPT_K(4); }
-            else if (gs == 8) { LG_OPT_K(8); } else { LG_OPT_K(16); }
+            else if (gs == 8 && m8) { LG_OPT_K8; } else if (gs == 8) { LG_OPT_K(8); } else { LG_OPT_K(16); }
         }
+#undef LG_OPT_K8
 #undef LG_OPT_K
 #undef LG_OPT
+#undef LG_OPT_M
         LG_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_relink, lgrid, dim3(256), 0, s, H, field->d_bits, pts, nrm, n_points, poses,
                            ws.valid_poses, ws.n_valid_poses, dom_count, p->draws, p->k, (uint32_t)p->seed,
                            (uint32_t)(p->seed >> 32), p->request_id, p->pose_offset, set_pt, set_link);
     }
 #undef LG_VERDICT
+#undef LG_VERDICT_M
     LG_HIP(hipGetLastError());
     const int64_t n_chunks = (n_sets + kChunk - 1) / kChunk;
     uint32_t *chunk_count = ws.chunk_count;
@@ -1777,13 +1802,16 @@ lg_status lg_search_extend(const lg_field *field, const float *pts, const float 
     LG_HIP(hipGetDevice(&dev));
     LG_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     const dim3 lgrid((unsigned)std::max<int64_t>(1, std::min<int64_t>((n_sets + 255) / 256, (int64_t)n_cu * 8)));
-#define LG_VERDICT2(KM)                                                                                         \
-    hipLaunchKernelGGL(k_verdict_lane<KM>, lgrid, dim3(256), 0, s, pts, nrm, n_points, set_pt2, nullptr,          \
+    const bool m8 = p->m_edges == 8;
+#define LG_VERDICT2_M(KM, MC)                                                                                   \
+    hipLaunchKernelGGL((k_verdict_lane<KM, MC>), lgrid, dim3(256), 0, s, pts, nrm, n_points, set_pt2, nullptr,    \
                        ws.valid_poses, ws.n_valid_poses, p->draws, k2, p->m_edges, (double)p->mu,                \
                        (double)p->moment_scale, (double)p->eps, p->max_pivots, cs, verdict2, tstar2)
-    if (k2 <= 3) LG_VERDICT2(3); else if (k2 <= 4) LG_VERDICT2(4); else if (k2 <= 5) LG_VERDICT2(5);
-    else if (k2 <= 6) LG_VERDICT2(6); else LG_VERDICT2(8);
+#define LG_VERDICT2(KM) if (m8) LG_VERDICT2_M(KM, 8); else LG_VERDICT2_M(KM, 0)
+    if (k2 <= 3) { LG_VERDICT2(3); } else if (k2 <= 4) { LG_VERDICT2(4); } else if (k2 <= 5) { LG_VERDICT2(5); }
+    else if (k2 <= 6) { LG_VERDICT2(6); } else { LG_VERDICT2(8); }
 #undef LG_VERDICT2
+#undef LG_VERDICT2_M
     LG_HIP(hipGetLastError());
     const int64_t n_chunks = (n_sets + kChunk - 1) / kChunk;
     hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)n_chunks), dim3(kCompactThreads), 0, s, verdict2, n_sets,
@@ -1909,13 +1937,16 @@ lg_status lg::compact_scatter_batch(const BatchLaunch &b, bool poses, hipStream_
     return LG_OK;
 }
 
-lg_status lg::verdict_batch(const BatchLaunch &b, int km, hipStream_t s)
+lg_status lg::verdict_batch(const BatchLaunch &b, int km, bool m8, hipStream_t s)
 {
     if (b.n <= 0 || b.blocks == 0) return LG_OK;
-#define LG_VB(KM) hipLaunchKernelGGL(k_verdict_batch<KM>, dim3(b.blocks), dim3(256), 0, s, b.d, b.idx, b.first, b.n)
-    if (km <= 3) LG_VB(3); else if (km <= 4) LG_VB(4); else if (km <= 5) LG_VB(5); else if (km <= 6) LG_VB(6);
-    else LG_VB(8);
+#define LG_VB_M(KM, MC)                                                                                          \
+    hipLaunchKernelGGL((k_verdict_batch<KM, MC>), dim3(b.blocks), dim3(256), 0, s, b.d, b.idx, b.first, b.n)
+#define LG_VB(KM) if (m8) LG_VB_M(KM, 8); else LG_VB_M(KM, 0)
+    if (km <= 3) { LG_VB(3); } else if (km <= 4) { LG_VB(4); } else if (km <= 5) { LG_VB(5); }
+    else if (km <= 6) { LG_VB(6); } else { LG_VB(8); }
 #undef LG_VB
+#undef LG_VB_M
     LG_HIP(hipGetLastError());
     return LG_OK;
 }

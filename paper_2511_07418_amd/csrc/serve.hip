@@ -529,7 +529,8 @@ static lg_status launch_batch(lg_server *S, BatchSlot &B)
     if ((st = T.list(all, blocks(all, poses), ld)) != LG_OK) return st;
     if ((st = T.list(all, blocks(all, pose_chunks), pc)) != LG_OK) return st;
     if ((st = T.list(all, blocks(all, one), ps)) != LG_OK) return st;
-    for (auto &g : buckets(all, [&](int m) { return km_bucket(cd[m].k); })) {
+    // verdict launches by contact-count class and by whether the cone has 8 edges
+    for (auto &g : buckets(all, [&](int m) { return (km_bucket(cd[m].k) << 1) | (cd[m].m == 8 ? 1 : 0); })) {
         lv.push_back({BatchLaunch{}, g[0]});
         if ((st = T.list(g, blocks(g, lp_blocks), lv.back().b)) != LG_OK) return st;
     }
@@ -559,7 +560,7 @@ static lg_status launch_batch(lg_server *S, BatchSlot &B)
     if ((st = compact_scan_batch(ps, true, B.s)) != LG_OK) return st;
     if ((st = compact_scatter_batch(pc, true, B.s)) != LG_OK) return st;
     for (const Keyed &g : lv)
-        if ((st = verdict_batch(g.b, cd[g.rep].k, B.s)) != LG_OK) return st;
+        if ((st = verdict_batch(g.b, cd[g.rep].k, cd[g.rep].m == 8, B.s)) != LG_OK) return st;
     if ((st = compact_count_batch(sc, false, B.s)) != LG_OK) return st;
     if ((st = compact_scan_batch(ss, false, B.s)) != LG_OK) return st;
     if ((st = compact_scatter_batch(sc, false, B.s)) != LG_OK) return st;
