@@ -904,7 +904,14 @@ __device__ int project_domain_wave(const GridDev &g, const uint32_t *__restrict_
                 }
             } else if (p0 + lane < n_pos) {
                 int dx, dy, dz;
-                shell_pos(R, p0 + lane, dx, dy, dz);
+                if (R == 1) {  // the 26 neighbours: the 3 x 3 x 3 block less its centre (constant divisors)
+                    const int q = lane + (lane >= 13 ? 1 : 0);
+                    dx = q % 3 - 1;
+                    dy = (q / 3) % 3 - 1;
+                    dz = q / 9 - 1;
+                } else {
+                    shell_pos(R, p0 + lane, dx, dy, dz);
+                }
                 const int x = cx + dx, yv = cy + dy, z = cz + dz;
                 const float bx = slab(dx, rx), by = slab(dy, ry), bz = slab(dz, rz);
                 if (x >= 0 && x < g.dims[0] && yv >= 0 && yv < g.dims[1] && z >= 0 && z < g.dims[2] &&
