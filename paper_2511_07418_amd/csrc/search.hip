@@ -295,7 +295,8 @@ __device__ inline double lp_lane(float (&cd)[KM * 6][256], int tid, int k, int m
 #pragma unroll
         for (int r = 0; r < 7; ++r) a[r] = 0.0;
         if (j < n) {
-            const int ci = j / m, e = j - ci * m;
+            const int mm = MC > 0 ? MC : m;  // a constant divisor for the 8-edge kernels
+            const int ci = j / mm, e = j - ci * mm;
             double px, py, pz, nx, ny, nz;
             contact(ci, px, py, pz, nx, ny, nz);
             double x[3], y[3];
