@@ -222,7 +222,13 @@ typedef struct {
                                draws no sets.  Not supported by the server (must be NULL there). */
 } lg_search_params;
 
-/* Bytes of device workspace lg_search needs for n_points points and n_poses poses. */
+/* Bytes of device workspace lg_search asks for with n_points points and n_poses
+ * poses.  With opt_outer > 0 this includes per-candidate arrays that let the
+ * criteria of Alg. 2 gather their slow LPs into launches of their own; lg_search
+ * also accepts a workspace without them (down to the size with opt_outer = 0
+ * plus Alg. 2's cell grid and candidate ids) and then solves each step's LPs in
+ * one launch per round, with the same outputs.  A smaller workspace fails with
+ * LG_EINVAL. */
 size_t lg_search_workspace_bytes(int32_t n_points, int32_t n_poses, const lg_search_params *params);
 
 /*
@@ -270,8 +276,10 @@ lg_status lg_search(const lg_field *field, const float *pts, const float *nrm, i
  * as lg_search, minus workspace/workspace_bytes: the workspace is a static
  * device array of lg_search_noalloc_max_bytes() bytes (8 MiB) per GPU, held
  * until the process ends; its device address is looked up once per device on
- * the first call there.  Calls whose lg_search_workspace_bytes() exceeds that
- * size fail with LG_EINVAL before anything is enqueued.  No call allocates:
+ * the first call there.  The per-candidate arrays of Alg. 2's gathered slow
+ * LPs are used only when they fit; calls whose least workspace (see
+ * lg_search_workspace_bytes) exceeds that size fail with LG_EINVAL before
+ * anything is enqueued.  No call allocates:
  * no hipMalloc, hipFree or allocating library routine, and no memset node
  * (the cell counts of Alg. 2 are cleared by a kernel).  Every call on a GPU
  * shares that GPU's array, and each call rewrites what it reads from it:

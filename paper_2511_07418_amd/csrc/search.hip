@@ -1170,6 +1170,199 @@ k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, 
     }
 }
 
+// ---- Alg. 2 criteria with the slow LPs gathered into their own waves --------
+// k_optimize runs a contact step's candidate LPs side by side, so each wave
+// waits for the slowest of its 64 LPs at every step.  Most warm-started LPs
+// end within a pivot or two of the warm basis, but about a third need many
+// more.  With a workspace that holds a step's candidate results, each
+// contact step takes three launches instead: every candidate's LP stopped
+// after kOptEasyPivots simplex pivots (kOptColdPivots at a round's first
+// step, which has no warm basis) (k_opt_try); the LPs not finished by then
+// queued and solved again from the same start with the full pivot cap, in
+// waves of slow LPs only (k_opt_hard); then each set's pick (k_opt_pick).
+// A capped run is a prefix of the full run from the same start, so t*, the
+// final bases and the picks are those of k_optimize.  (Caps measured at c3:
+// 1, 2, 4, 8 warm pivots gave a search stage of 119, 117, 112, 110 ms; a cap
+// of 14 on the cold step took 2.5 ms off.)
+constexpr int kOptEasyPivots = 8;
+constexpr int kOptColdPivots = 14;
+
+struct OptSplit {
+    double *sJ;          // per set: criterion value of its last pick (INF before any)
+    int32_t *sB;         // per set: 7 basis column ids of its last finite pick (-1: none yet)
+    double *cJ;          // per candidate (set t, candidate j at t * n_inner + j): t*, INF if unsolved
+    int32_t *cB;         // per candidate: the 7 column ids of its final basis
+    int32_t *queue;      // candidates whose LP needs more than kOptEasyPivots pivots
+    uint32_t *n_queue;   // queue length, one counter per contact step
+};
+
+// Set t of the sets of poses with non-empty domains: its set id and whether it
+// was drawn (the drawn-set test of k_optimize); kc = contacts with the palm's.
+__device__ inline bool opt_set(int64_t t, const int32_t *__restrict__ valid_poses, const uint32_t *__restrict__ dom_count,
+                               const int32_t *__restrict__ palm_pt, const int32_t *__restrict__ set_pt, int N, int F,
+                               int D, int k, uint32_t seed_lo, uint32_t seed_hi, uint32_t request_id,
+                               int64_t pose_offset, int64_t &sid, int &pc)
+{
+    const int64_t pg = valid_poses[t / D];
+    const int d = (int)(t % D);
+    sid = pg * D + d;
+    const int32_t *sp = set_pt + sid * k;
+    const uint32_t fm = choose_fingers(eligible_fingers(dom_count, pg, F), k, (uint32_t)(pose_offset + pg), d,
+                                       request_id, seed_lo, seed_hi);
+    pc = palm_pt ? palm_pt[pg] : -1;
+    bool drawn = fm != 0 && pc < N;
+    for (int i = 0; i < k; ++i) drawn &= sp[i] >= 0 && sp[i] < N;
+    return drawn;
+}
+
+// LP of candidate j of set t at contact step i, from the set's current points
+// (its own column of cd), warm-started from the set's last pick's basis
+// (none at the round's first step); cap: the pivot cap of this run.
+template <int KM, int MC>
+__device__ inline double opt_cand_lp(float (&cd)[KM * 6][256], int (&wb)[7][256], int tid, int64_t t, int j, int i,
+                                     const float *__restrict__ pts, const float *__restrict__ nrm, int N,
+                                     const int32_t *__restrict__ valid_poses, const uint32_t *__restrict__ dom_count,
+                                     const int32_t *__restrict__ palm_pt, int F, int D, int k, int m, double mu,
+                                     double rho, int cap, const LpConst &cs, int n_inner, uint32_t seed_lo,
+                                     uint32_t seed_hi, uint32_t request_id, int64_t pose_offset,
+                                     const int32_t *__restrict__ cands, const int32_t *__restrict__ set_pt,
+                                     const OptSplit &os, int &st)
+{
+    st = 3;  // no LP (not a drawn set, or no candidate)
+    int64_t sid;
+    int pc;
+    if (!opt_set(t, valid_poses, dom_count, palm_pt, set_pt, N, F, D, k, seed_lo, seed_hi, request_id, pose_offset,
+                 sid, pc))
+        return INFINITY;
+    const int cand = cands[(t * k + i) * n_inner + j];
+    if (cand < 0) return INFINITY;
+    auto load = [&](int ci, int idx) {
+        cd[6 * ci + 0][tid] = pts[idx];
+        cd[6 * ci + 1][tid] = pts[N + idx];
+        cd[6 * ci + 2][tid] = pts[2 * N + idx];
+        cd[6 * ci + 3][tid] = nrm[idx];
+        cd[6 * ci + 4][tid] = nrm[N + idx];
+        cd[6 * ci + 5][tid] = nrm[2 * N + idx];
+    };
+    const int32_t *sp = set_pt + sid * k;
+    for (int c = 0; c < k; ++c) load(c, c == i ? cand : sp[c]);
+    if (pc >= 0) load(k, pc);
+#pragma unroll
+    for (int r = 0; r < 7; ++r) wb[r][tid] = i == 0 ? -1 : os.sB[t * 7 + r];
+    return lp_lane<KM, true, MC>(cd, tid, pc >= 0 ? k + 1 : k, m, mu, rho, cap, cs, st, wb);
+}
+
+template <int KM, int MC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_opt_try(const float *__restrict__ pts, const float *__restrict__ nrm, int N,
+          const int32_t *__restrict__ valid_poses, const int32_t *__restrict__ n_valid_poses,
+          const uint32_t *__restrict__ dom_count, const int32_t *__restrict__ palm_pt, int F, int D, int k, int m,
+          double mu, double rho, int max_pivots, LpConst cs, int n_inner, int i, uint32_t seed_lo, uint32_t seed_hi,
+          uint32_t request_id, int64_t pose_offset, const int32_t *__restrict__ cands,
+          const int32_t *__restrict__ set_pt, OptSplit os)
+{
+    __shared__ float cd[KM * 6][256];
+    __shared__ int wb[7][256];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int64_t n_cand = (int64_t)(*n_valid_poses) * D * n_inner;
+    const int cap = min(max_pivots, i == 0 ? kOptColdPivots : kOptEasyPivots);
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + tid; g < n_cand; g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = g / n_inner;
+        const int j = (int)(g - t * n_inner);
+        int st;
+        const double Jc = opt_cand_lp<KM, MC>(cd, wb, tid, t, j, i, pts, nrm, N, valid_poses, dom_count, palm_pt, F,
+                                              D, k, m, mu, rho, cap, cs, n_inner, seed_lo, seed_hi, request_id,
+                                              pose_offset, cands, set_pt, os, st);
+        const bool slow = st == 1 && cap < max_pivots;
+        if (!slow) {
+            os.cJ[g] = st == 0 ? Jc : INFINITY;
+#pragma unroll
+            for (int r = 0; r < 7; ++r) os.cB[g * 7 + r] = wb[r][tid];
+        }
+        // one queue reservation per wave
+        const unsigned long long sb = __ballot(slow);
+        if (sb) {
+            const int leader = __ffsll((long long)sb) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(os.n_queue + i, (uint32_t)__popcll(sb));
+            base = __shfl(base, leader, 64);
+            if (slow) os.queue[base + __popcll(sb & ((1ull << lane) - 1))] = (int32_t)g;
+        }
+    }
+}
+
+template <int KM, int MC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_opt_hard(const float *__restrict__ pts, const float *__restrict__ nrm, int N,
+           const int32_t *__restrict__ valid_poses, const uint32_t *__restrict__ dom_count,
+           const int32_t *__restrict__ palm_pt, int F, int D, int k, int m, double mu, double rho, int max_pivots,
+           LpConst cs, int n_inner, int i, uint32_t seed_lo, uint32_t seed_hi, uint32_t request_id,
+           int64_t pose_offset, const int32_t *__restrict__ cands, const int32_t *__restrict__ set_pt, OptSplit os)
+{
+    __shared__ float cd[KM * 6][256];
+    __shared__ int wb[7][256];
+    const int tid = threadIdx.x;
+    const int64_t n = os.n_queue[i];
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + tid; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = os.queue[q];
+        const int64_t t = g / n_inner;
+        const int j = (int)(g - t * n_inner);
+        int st;
+        const double Jc = opt_cand_lp<KM, MC>(cd, wb, tid, t, j, i, pts, nrm, N, valid_poses, dom_count, palm_pt, F,
+                                              D, k, m, mu, rho, max_pivots, cs, n_inner, seed_lo, seed_hi,
+                                              request_id, pose_offset, cands, set_pt, os, st);
+        os.cJ[g] = st == 0 ? Jc : INFINITY;
+#pragma unroll
+        for (int r = 0; r < 7; ++r) os.cB[g * 7 + r] = wb[r][tid];
+    }
+}
+
+// Each set's pick at contact step i: the lowest candidate within kOptTau of
+// the best t* (the first candidate when none is finite), its point into the
+// set, its basis the warm start of the next step when its t* is finite.
+__global__ void k_opt_pick(const int32_t *__restrict__ valid_poses, const int32_t *__restrict__ n_valid_poses,
+                           const uint32_t *__restrict__ dom_count, const int32_t *__restrict__ palm_pt, int N, int F,
+                           int D, int k, int n_inner, int i, bool last, double eps, uint32_t seed_lo,
+                           uint32_t seed_hi, uint32_t request_id, int64_t pose_offset,
+                           const int32_t *__restrict__ cands, int32_t *__restrict__ set_pt,
+                           uint8_t *__restrict__ verdict, double *__restrict__ tstar, OptSplit os)
+{
+    const int64_t n_work = (int64_t)(*n_valid_poses) * D;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_work;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int64_t sid;
+        int pc;
+        if (!opt_set(t, valid_poses, dom_count, palm_pt, set_pt, N, F, D, k, seed_lo, seed_hi, request_id,
+                     pose_offset, sid, pc)) {
+            verdict[sid] = 0;  // not a drawn set: no criterion
+            tstar[sid] = __builtin_nan("");
+            continue;
+        }
+        const double *cj = os.cJ + t * n_inner;
+        double mn = INFINITY;
+        for (int j = 0; j < n_inner; ++j) mn = fmin(mn, cj[j]);
+        int js = -1;
+        for (int j = n_inner - 1; j >= 0; --j)
+            if (cj[j] <= mn + kOptTau) js = j;
+        const int pick = js >= 0 ? cands[(t * k + i) * n_inner + js] : -1;
+        double J = i == 0 ? INFINITY : os.sJ[t];
+        if (i == 0) os.sB[t * 7] = -1;
+        if (pick >= 0) {
+            J = cj[js];
+            set_pt[sid * k + i] = pick;
+            if (!isinf(J)) {
+#pragma unroll
+                for (int r = 0; r < 7; ++r) os.sB[t * 7 + r] = os.cB[(t * n_inner + js) * 7 + r];
+            }
+        }
+        os.sJ[t] = J;
+        if (i == k - 1) {
+            tstar[sid] = isinf(J) ? __builtin_nan("") : J;
+            if (last) verdict[sid] = J <= eps ? 1 : 0;
+        }
+    }
+}
+
 // links of the (moved) contacts of every set of a pose with non-empty domains,
 // picked with the set's draw words exactly as k_draw does
 __global__ void k_relink(DevHand H, const uint32_t *__restrict__ bits, const float *__restrict__ pts,
@@ -1508,11 +1701,12 @@ struct SearchWs {
     uint32_t *cell_count, *cell_start;
     float4 *cell_pts;
     int32_t *cands;
+    OptSplit split;   // arrays of the gathered-slow-LP criteria (null when not laid out)
     size_t bytes;
 };
 
 static SearchWs search_ws(void *base, int64_t n_points, int64_t n_poses, int64_t draws, bool opt, int64_t k = 0,
-                          int64_t n_inner = 0)
+                          int64_t n_inner = 0, bool split = false)
 {
     const int64_t n_sets = n_poses * draws;
     const int64_t nc = (n_sets + kChunk - 1) / kChunk, npc = (n_poses + kChunk - 1) / kChunk;
@@ -1530,6 +1724,7 @@ static SearchWs search_ws(void *base, int64_t n_points, int64_t n_poses, int64_t
     w.cell_count = w.cell_start = nullptr;
     w.cell_pts = nullptr;
     w.cands = nullptr;
+    w.split = OptSplit{};
     if (opt) {
         const int64_t ncell = (int64_t)(kGridMax + 1) * (kGridMax + 1) * (kGridMax + 1);
         char *b = static_cast<char *>(base);
@@ -1544,16 +1739,81 @@ static SearchWs search_ws(void *base, int64_t n_points, int64_t n_poses, int64_t
         off += ((size_t)n_points * 16 + 255) & ~(size_t)255;
         w.cands = reinterpret_cast<int32_t *>(b + off);
         off += (size_t)n_sets * k * n_inner * 4;
+        if (split) {
+            const size_t nc_ = (size_t)n_sets * n_inner;
+            auto take = [&](size_t bytes) {
+                off = (off + 255) & ~(size_t)255;
+                char *q = b + off;
+                off += bytes;
+                return q;
+            };
+            w.split.sJ = reinterpret_cast<double *>(take((size_t)n_sets * 8));
+            w.split.sB = reinterpret_cast<int32_t *>(take((size_t)n_sets * 28));
+            w.split.cJ = reinterpret_cast<double *>(take(nc_ * 8));
+            w.split.cB = reinterpret_cast<int32_t *>(take(nc_ * 28));
+            w.split.queue = reinterpret_cast<int32_t *>(take(nc_ * 4));
+            w.split.n_queue = reinterpret_cast<uint32_t *>(take((size_t)std::max<int64_t>(k, 1) * 4));
+        }
     }
     w.bytes = off + 256;
     return w;
 }
 
-size_t lg_search_workspace_bytes(int32_t n_points, int32_t n_poses, const lg_search_params *p)
+// Alg. 2 criteria with the slow LPs gathered need candidate ids below 2^31.
+static bool split_fits(int64_t n_poses, int64_t draws, const lg_search_params *p)
+{
+    return p->opt_outer > 0 && n_poses * draws * p->opt_inner < 0x7fffffffLL;
+}
+
+// Workspace of the search: with split, the arrays of the gathered-slow-LP
+// criteria too (what lg_search_workspace_bytes asks for); without, the least
+// a search runs in (Alg. 2 then runs its criteria in one launch per round).
+static size_t search_ws_bytes(int32_t n_points, int32_t n_poses, const lg_search_params *p, bool split)
 {
     if (!p || n_poses <= 0 || p->draws <= 0) return 256;
     return search_ws(nullptr, std::max(n_points, 0), n_poses, p->draws, p->opt_outer > 0, p->k,
-                     p->opt_outer > 0 ? p->opt_inner : 0).bytes;
+                     p->opt_outer > 0 ? p->opt_inner : 0, split && split_fits(n_poses, p->draws, p)).bytes;
+}
+
+size_t lg_search_workspace_bytes(int32_t n_points, int32_t n_poses, const lg_search_params *p)
+{
+    return search_ws_bytes(n_points, n_poses, p, true);
+}
+
+// One round of Alg. 2 criteria with the slow LPs gathered: per contact step
+// the capped LPs of every candidate, the queued slow ones, the picks.
+static lg_status opt_split_round(const float *pts, const float *nrm, int n_points, const SearchWs &ws,
+                                 const uint32_t *dom_count, const int32_t *palm, int F, const lg_search_params *p,
+                                 int kk, bool m8, const LpConst &cs, dim3 sgrid, dim3 cgrid, bool last,
+                                 int32_t *set_pt, uint8_t *verdict, double *tstar, hipStream_t s)
+{
+    const uint32_t slo = (uint32_t)p->seed, shi = (uint32_t)(p->seed >> 32);
+    const double mu = p->mu, rho = p->moment_scale;
+    // queue counters cleared by a kernel, not a memset node (the stream may be captured)
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, ws.split.n_queue, (int64_t)p->k, 0u);
+    for (int i = 0; i < p->k; ++i) {
+#define LG_SPLIT_M(KM, MC)                                                                                       \
+    do {                                                                                                         \
+        hipLaunchKernelGGL((k_opt_try<KM, MC>), cgrid, dim3(256), 0, s, pts, nrm, n_points, ws.valid_poses,     \
+                           ws.n_valid_poses, dom_count, palm, F, p->draws, p->k, p->m_edges, mu, rho,           \
+                           p->max_pivots, cs, p->opt_inner, i, slo, shi, p->request_id, p->pose_offset,          \
+                           ws.cands, set_pt, ws.split);                                                          \
+        hipLaunchKernelGGL((k_opt_hard<KM, MC>), cgrid, dim3(256), 0, s, pts, nrm, n_points, ws.valid_poses,    \
+                           dom_count, palm, F, p->draws, p->k, p->m_edges, mu, rho, p->max_pivots, cs,           \
+                           p->opt_inner, i, slo, shi, p->request_id, p->pose_offset, ws.cands, set_pt,           \
+                           ws.split);                                                                            \
+    } while (0)
+#define LG_SPLIT(KM) if (m8) LG_SPLIT_M(KM, 8); else LG_SPLIT_M(KM, 0)
+        if (kk <= 3) { LG_SPLIT(3); } else if (kk <= 4) { LG_SPLIT(4); } else if (kk <= 5) { LG_SPLIT(5); }
+        else if (kk <= 6) { LG_SPLIT(6); } else { LG_SPLIT(8); }
+#undef LG_SPLIT
+#undef LG_SPLIT_M
+        hipLaunchKernelGGL(k_opt_pick, sgrid, dim3(256), 0, s, ws.valid_poses, ws.n_valid_poses, dom_count, palm,
+                           n_points, F, p->draws, p->k, p->opt_inner, i, last, (double)p->eps, slo, shi,
+                           p->request_id, p->pose_offset, ws.cands, set_pt, verdict, tstar, ws.split);
+    }
+    LG_HIP(hipGetLastError());
+    return LG_OK;
 }
 
 }  // extern "C"
@@ -1612,13 +1872,16 @@ static lg_status search_impl(const lg_field *field, const float *pts, const floa
     if (p->opt_outer < 0 || p->opt_outer > 64 || (p->opt_outer > 0 && (p->opt_inner < 1 || p->opt_inner > 16)) ||
         !(p->opt_sigma >= 0.0f) || (int64_t)p->opt_outer * p->k * p->opt_inner >= (1 << 24))
         return fail(LG_EINVAL, "need 0 <= opt_outer <= 64, 1 <= opt_inner <= 16, opt_sigma >= 0");
-    if (workspace_bytes < lg_search_workspace_bytes(n_points, n_poses, p)) return fail(LG_EINVAL, "workspace too small");
+    if (workspace_bytes < search_ws_bytes(n_points, n_poses, p, false)) return fail(LG_EINVAL, "workspace too small");
     const int NW = (n_points + 31) / 32, nsb = (NW + kSuper - 1) / kSuper;
     const size_t lds = (size_t)H.F * (nsb + 1) * sizeof(uint32_t);
     if (lds > 48 * 1024) return fail(LG_EUNSUPPORTED, "too many points for the draw rank structure");
     hipStream_t s = as_stream(stream);
     const bool opt = p->opt_outer > 0;
-    const SearchWs ws = search_ws(workspace, n_points, n_poses, p->draws, opt, p->k, opt ? p->opt_inner : 0);
+    // Alg. 2 criteria with the slow LPs gathered when the workspace holds their arrays
+    const bool split = opt && split_fits(n_poses, p->draws, p) &&
+                       workspace_bytes >= search_ws_bytes(n_points, n_poses, p, true);
+    const SearchWs ws = search_ws(workspace, n_points, n_poses, p->draws, opt, p->k, opt ? p->opt_inner : 0, split);
     hipLaunchKernelGGL(k_draw, dim3(n_poses), dim3(kDrawThreads), lds, s, H, field->d_bits, pts, nrm, n_points,
                        poses, dom_bits, dom_count, palm, p->draws, p->k, (uint32_t)p->seed, (uint32_t)(p->seed >> 32),
                        p->request_id, p->pose_offset, set_pt, set_link, ws.pose_valid, verdict, tstar);
@@ -1667,6 +1930,10 @@ static lg_status search_impl(const lg_field *field, const float *pts, const floa
             1, std::min<int64_t>((n_sets * gs + 255) / 256, (int64_t)n_cu * 8)));
         const dim3 pgrid((unsigned)std::max<int64_t>(
             1, std::min<int64_t>((n_sets * p->k * p->opt_inner + 255) / 256, (int64_t)n_cu * 32)));
+        // grid-stride grids of the gathered-slow-LP criteria (candidates; sets)
+        const dim3 cgrid((unsigned)std::max<int64_t>(
+            1, std::min<int64_t>((n_sets * p->opt_inner + 255) / 256, (int64_t)n_cu * 8)));
+        const dim3 sgrid((unsigned)std::max<int64_t>(1, std::min<int64_t>((n_sets + 255) / 256, (int64_t)n_cu * 8)));
 #define LG_OPT_M(KM, GS, MC)                                                                                     \
     hipLaunchKernelGGL((k_optimize<KM, GS, MC>), ogrid, dim3(256), 0, s, pts, nrm, n_points, ws.valid_poses,       \
                        ws.n_valid_poses, dom_count, palm, H.F, p->draws, p->k, p->m_edges, (double)p->mu,         \
@@ -1685,6 +1952,12 @@ static lg_status search_impl(const lg_field *field, const float *pts, const floa
                                ws.n_valid_poses, dom_bits, dom_count, palm, H.F, p->draws, p->k, r, p->opt_inner,
                                (double)p->opt_sigma, (uint32_t)p->seed, (uint32_t)(p->seed >> 32), p->request_id,
                                p->pose_offset, ws.grid, ws.cell_start, ws.cell_pts, set_pt, ws.cands);
+            if (split) {
+                const lg_status so = opt_split_round(pts, nrm, n_points, ws, dom_count, palm, H.F, p, kk, m8, cs,
+                                                     sgrid, cgrid, r == p->opt_outer - 1, set_pt, verdict, tstar, s);
+                if (so != LG_OK) return so;
+                continue;
+            }
             if (gs == 1) { LG_OPT_K(1); } else if (gs == 2) { LG_OPT_K(2); } else if (gs == 4) { LG_OPT_K(4); }
             else if (gs == 8 && m8) { LG_OPT_K8; } else if (gs == 8) { LG_OPT_K(8); } else { LG_OPT_K(16); }
         }
@@ -1879,7 +2152,7 @@ lg_status lg_search_noalloc(const lg_field *field, const float *pts, const float
                             double *tstar, int32_t *acc_list, int32_t *n_acc, void *stream)
 {
     if (!p) return fail(LG_EINVAL, "null params");
-    const size_t need = lg_search_workspace_bytes(n_points, n_poses, p);
+    const size_t need = search_ws_bytes(n_points, n_poses, p, false);  // the least a search runs in
     if (need > kStaticScratchBytes)
         return fail(LG_EINVAL, "search needs " + std::to_string(need) + " bytes of workspace, above the " +
                                    std::to_string(kStaticScratchBytes) + "-byte static scratch");

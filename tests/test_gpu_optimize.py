@@ -151,3 +151,70 @@ def test_invalid_optimisation_parameters(bad):
         lg.lg_search(field, soa(w.obj.pts), soa(w.obj.nrm), dev(w.poses), dev(Q["dom_bits"].view(np.int32)),
                      dev(Q["dom_count"].view(np.int32)), dataclasses.replace(w.search, **bad))
     assert ei.value.status == lg.LG_EINVAL
+
+
+def test_optimize_c3_full_shape_as_benchmarked():
+    """One round of Alg. 2 in the launch the benchmark times with --opt-outer 1:
+    C3 at full shape (65,536 poses x 64 draws of 5 contacts, 65,536 Morton-ordered
+    points) on the bounded query's domains, 8 candidates per contact, sigma 4 mm.
+    Sampled poses are recomputed by the oracle at their global pose index from
+    the domains the GPU's query gave them (stage-isolated: the query has its own
+    tests; the oracle's domains differ from them only in flagged bits), with the
+    bars of the reduced-shape tests: unflagged sets
+    on the oracle's points with t* within 1e-9 and its verdicts outside the
+    eps band; flagged sets on one of the oracle's admissible outcomes; links of
+    the final points outside the rounding bands; the accepted list exact."""
+    lg = lgmod()
+    w = synth.workload("c3", samples=4096, with_sdf=False)
+    order = lg.lg_morton_order(w.obj.pts)
+    w = dataclasses.replace(w, obj=dataclasses.replace(w.obj, pts=w.obj.pts[order], nrm=w.obj.nrm[order]))
+    sp0 = dataclasses.replace(w.search, opt_outer=1, opt_inner=8, opt_sigma=0.004)
+    ref = oracle.build_field(w.hand, w.field, flags=False)
+    field = lg.lg_field_import(w.hand, w.field, ref["bits"])
+    pts, nrm = soa(w.obj.pts), soa(w.obj.nrm)
+    poses = dev(w.poses)
+    db, dc = lg.lg_query_domains_bounded(field, pts, nrm, poses, lg.lg_chunk_bounds(pts))
+    bufs = lg.lg_search(field, pts, nrm, poses, db, dc, sp0)
+    torch.cuda.synchronize()
+    D, k = sp0.draws, sp0.k
+    ver_all = bufs.verdict.cpu().numpy().reshape(-1)
+    n_acc = int(bufs.n_acc.item())
+    assert n_acc > 0
+    assert (bufs.acc_list[:n_acc].cpu().numpy() == np.flatnonzero(ver_all)).all(), "compaction order"
+    drawn = np.flatnonzero((bufs.set_pt[:, :, 0].cpu().numpy() >= 0).any(-1))   # poses with drawn sets
+    sel = np.sort(np.random.default_rng(23).choice(drawn, size=16, replace=False))
+    checked = flagged = 0
+    for g in sel:
+        g = int(g)
+        Qg = {"dom_bits": np.ascontiguousarray(db[g:g + 1].cpu().numpy().view(np.uint32)),
+              "dom_count": np.ascontiguousarray(dc[g:g + 1].cpu().numpy().view(np.uint32))}
+        sp = dataclasses.replace(sp0, pose_offset=g)
+        d_spt, _ = oracle.draw(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses[g:g + 1],
+                               Qg["dom_bits"], Qg["dom_count"], sp)
+        O = oracle.optimize(w.obj.pts, w.obj.nrm, Qg["dom_bits"], d_spt, sp, w.hand.n_fingers,
+                            dom_count=Qg["dom_count"])
+        spt = bufs.set_pt[g:g + 1].cpu().numpy()
+        sln = bufs.set_link[g:g + 1].cpu().numpy().astype(np.int32)
+        tst = bufs.tstar[g:g + 1].cpu().numpy().reshape(-1)
+        ver = ver_all[g * D:(g + 1) * D]
+        valid = (d_spt >= 0).all(-1).reshape(-1)
+        flag = O["oflag"].astype(bool)
+        ok = valid & ~flag
+        checked += int(ok.sum())
+        flagged += int((valid & flag).sum())
+        same = (spt.reshape(-1, k) == O["set_pt"].reshape(-1, k)).all(-1)
+        assert same[ok].all(), (g, int((~same[ok]).sum()))
+        assert np.allclose(tst[ok], O["tstar"][ok], atol=1e-9, rtol=0), g
+        assert ((ver != O["verdict"]) & ok & ~O["vflag"].astype(bool)).sum() == 0, g
+        check_flagged_outcomes(w, sp, Qg, d_spt, np.flatnonzero(valid & flag), spt, tst, ver)
+        assert (spt.reshape(-1, k)[~valid] == -1).all() and np.isnan(tst[~valid]).all()
+        fin = O["set_pt"].reshape(-1, k).copy()
+        fl = np.flatnonzero(valid & flag)
+        fin[fl] = spt.reshape(-1, k)[fl]
+        o_sln, o_lf = oracle.relink(w.hand, w.field, ref["bits"], w.obj.pts, w.obj.nrm, w.poses[g:g + 1],
+                                    fin.reshape(spt.shape), sp, dom_count=Qg["dom_count"], link_flags=True)
+        mis = (sln.reshape(-1, k) != o_sln.reshape(-1, k))[valid]
+        assert (mis & (o_lf.reshape(-1, k)[valid] == 0)).sum() == 0, g
+    print(f"[alg2 c3] {checked} unflagged and {flagged} flagged sets checked", flush=True)
+    assert checked > 0
+    assert flagged <= 0.08 * max(1, checked + flagged)

@@ -1,13 +1,21 @@
 """lg_search_noalloc (the search on the library's static device scratch)
 against lg_search (the search on a caller workspace), through the C ABI.
 
-Both run the same kernels, so every output must be identical: drawn points
-and links, verdicts, t* (bit for bit, NaN where the set is invalid), the
-accepted list and its length.  Two calls in a row on the shared scratch, the
-second smaller than the first, for the plain search and for the search with
-contact-point optimisation (Alg. 2, whose cell grid lives in the scratch and
-is cleared by a kernel on every call).  A request above the scratch size is
-refused before anything is enqueued.
+The plain search runs the same kernels in both, so every output must be
+identical: drawn points and links, verdicts, t* (bit for bit, NaN where the
+set is invalid), the accepted list and its length.  With contact-point
+optimisation (Alg. 2) lg_search gathers the slow criterion LPs into launches
+of their own (per-candidate arrays in its workspace), while lg_search_noalloc
+does so only where those arrays fit the static scratch and otherwise solves a
+step's LPs in one launch: the same LPs from the same starting bases, compiled
+into different kernels, so the points, links, verdicts and accepted lists
+must still be identical and t* agrees within 1e-9 (the bar against the
+oracle), not bit for bit.  Two calls in a row on the shared scratch, the
+second smaller than the first (the first call of the Alg. 2 case exceeds the
+scratch with those arrays, the second fits), for the plain search and for the
+search with Alg. 2, whose cell grid lives in the scratch and is cleared by a
+kernel on every call.  A request above the scratch size is refused before
+anything is enqueued.
 """
 import dataclasses
 
@@ -39,13 +47,19 @@ def _outputs(b):
             "acc": b.acc_list[:n].cpu().numpy()}
 
 
-def _same(a, b):
+def _same(a, b, exact_tstar=True):
     for key in ("set_pt", "set_link", "verdict", "acc"):
         assert np.array_equal(a[key], b[key]), key
     assert a["n_acc"] == b["n_acc"]
     ta, tb = a["tstar"], b["tstar"]
     assert np.array_equal(np.isnan(ta), np.isnan(tb))
-    assert np.array_equal(ta.view(np.uint64)[~np.isnan(ta)], tb.view(np.uint64)[~np.isnan(tb)])
+    fa, fb = ta[~np.isnan(ta)], tb[~np.isnan(tb)]
+    if exact_tstar:
+        assert np.array_equal(fa.view(np.uint64), fb.view(np.uint64))
+    else:
+        dt = float(np.abs(fa - fb).max()) if fa.size else 0.0
+        print(f"[no_alloc] max |t* difference| {dt:.3e} over {fa.size} sets", flush=True)
+        assert dt <= 1e-9
 
 
 def _case(name, n_poses, n_points, opt):
@@ -83,7 +97,7 @@ def test_noalloc_equals_workspace_search_twice(name, sizes, opt):
     for n_poses, n_points in sizes:      # second call smaller: the scratch keeps the first call's contents
         print(f"[no_alloc] {name} P={n_poses} N={n_points} opt={opt}", flush=True)
         ref, got = _case(name, n_poses, n_points, opt)
-        _same(ref, got)
+        _same(ref, got, exact_tstar=not opt)
 
 
 def test_noalloc_refuses_above_the_scratch():
