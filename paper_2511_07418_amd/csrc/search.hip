@@ -1181,9 +1181,10 @@ k_optimize(const float *__restrict__ pts, const float *__restrict__ nrm, int N, 
 // queued and solved again from the same start with the full pivot cap, in
 // waves of slow LPs only (k_opt_hard); then each set's pick (k_opt_pick).
 // A capped run is a prefix of the full run from the same start, so t*, the
-// final bases and the picks are those of k_optimize.  (Caps measured at c3:
-// 1, 2, 4, 8 warm pivots gave a search stage of 119, 117, 112, 110 ms; a cap
-// of 14 on the cold step took 2.5 ms off.)
+// final bases and the picks are those of k_optimize.  (Caps measured at c3,
+// search stage: 1, 2, 4, 8, 12, 16 warm pivots 119, 117, 112, 110, 113,
+// 117 ms with the cold step uncapped; with 8 warm, 10, 14, 20 cold pivots
+// 108.6, 107.5, 109.7 ms.)
 constexpr int kOptEasyPivots = 8;
 constexpr int kOptColdPivots = 14;
 
