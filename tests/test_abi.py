@@ -100,6 +100,11 @@ def test_search_workspace_grows_with_the_optimisation(lglib):
     b0 = L.lg_search_workspace_bytes(2048, 256, C.byref(p0))
     b1 = L.lg_search_workspace_bytes(2048, 256, C.byref(p1))
     assert b1 >= b0 + 2048 * 4 and L.lg_search_workspace_bytes(2048, 0, C.byref(p1)) == 256
+    # with Alg. 2 the asked-for workspace holds, beyond the candidate ids
+    # (4 B per set, contact and candidate), the gathered-LP criteria arrays:
+    # 36 B per set (last pick's t* and basis) + 40 B per candidate (t*, basis, queue)
+    n_sets, k, n_in = 256 * w.search.draws, w.search.k, p1.opt_inner
+    assert b1 - b0 >= n_sets * k * n_in * 4 + n_sets * 36 + n_sets * n_in * 40
 
 
 def test_concave_filter_validation_without_device_work(lglib):
